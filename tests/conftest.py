@@ -1,0 +1,25 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (HIP device) and the built HIP library")
+    config.addinivalue_line("markers", "slow: oracle runs taking more than a few seconds")
+
+
+@pytest.fixture(scope="session")
+def sto3g():
+    import inputs
+    return inputs.load_basis("sto-3g")
+
+
+@pytest.fixture(scope="session")
+def b631gs():
+    import inputs
+    return inputs.load_basis("6-31g*")

@@ -1,0 +1,110 @@
+"""Pins of the oracle's J/K, SCF and gradient against invariants and brute force.
+
+* J and K against an einsum over the full ERI tensor (plain definition).
+* SCF: Tr(PS) = N_e, PSP = 2P, vanishing commutator, invariance of E under a
+  rigid rotation plus translation, independence of the converged E from the
+  starting guess.
+* Gradient: central finite differences of converged energies; zero net force
+  and zero torque; rotation covariance.
+"""
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from inputs.geometry import random_rotation
+
+
+def _rand_density(n, rng):
+    A = rng.standard_normal((n, n))
+    return 0.1 * (A + A.T)
+
+
+@pytest.mark.parametrize("case", ["h2o_sto3g", "w2"])
+def test_jk_against_full_tensor(case, sto3g, b631gs):
+    w = inputs.workload(case)
+    Z, x = w["instances"][0]
+    b = oracle.build_basis(sto3g if w["basis"] == "sto-3g" else b631gs, Z, x)
+    g = oracle.eri_tensor(b)
+    P = _rand_density(b["nbf"], np.random.default_rng(3))
+    Jr = np.einsum("ijkl,kl->ij", g, P)
+    Kr = np.einsum("ikjl,kl->ij", g, P)
+    J, K, nq = oracle.jk(b, P, tau=0.0)
+    assert np.abs(J - Jr).max() < 1e-12 and np.abs(K - Kr).max() < 1e-12
+    assert np.abs(J - J.T).max() < 1e-13 and np.abs(K - K.T).max() < 1e-13
+    ns = b["nsh"]
+    npair = ns * (ns + 1) // 2
+    assert nq == npair * (npair + 1) // 2
+    # screened build differs by less than the dropped bound
+    Js, Ks, nqs = oracle.jk(b, P, tau=1e-12)
+    assert nqs <= nq
+    assert np.abs(Js - Jr).max() < 1e-9 and np.abs(Ks - Kr).max() < 1e-9
+
+
+@pytest.fixture(scope="module")
+def h2o_scf(sto3g):
+    w = inputs.workload("h2o_sto3g")
+    Z, x = w["instances"][0]
+    b = oracle.build_basis(sto3g, Z, x)
+    return b, oracle.scf(b, w["e_tol"], w["comm_tol"])
+
+
+def test_scf_density_properties(h2o_scf):
+    b, r = h2o_scf
+    assert r["converged"]
+    P, S, F = r["P"], r["S"], r["F"]
+    assert np.trace(P @ S) == pytest.approx(10.0, abs=1e-10)
+    assert np.abs(P @ S @ P - 2 * P).max() < 1e-9
+    assert np.abs(F @ P @ S - S @ P @ F).max() < 1e-7
+    # energy expression against J/K at the same P
+    J, K, _ = oracle.jk(b, P, 0.0)
+    H = r["H"]
+    e = 0.5 * np.sum(P * (2 * H + J - 0.5 * K)) + oracle.nuclear_repulsion(b["Z"], b["xyz"])
+    assert e == pytest.approx(r["E"], abs=1e-11)
+
+
+def test_scf_rigid_motion_invariance(h2o_scf, sto3g):
+    b, r = h2o_scf
+    R = random_rotation(np.random.default_rng(11))
+    x2 = b["xyz"] @ R.T + np.array([0.7, -1.3, 2.1])
+    b2 = oracle.build_basis(sto3g, b["Z"], x2)
+    r2 = oracle.scf(b2, 1e-10, 1e-8)
+    assert r2["E"] == pytest.approx(r["E"], abs=1e-10)
+
+
+def test_scf_guess_independence(h2o_scf):
+    b, r = h2o_scf
+    rng = np.random.default_rng(5)
+    P0 = r["P"] + 0.05 * _rand_density(b["nbf"], rng)
+    r2 = oracle.scf(b, 1e-10, 1e-8, guess=P0)
+    assert r2["E"] == pytest.approx(r["E"], abs=1e-9)
+
+
+def test_gradient_finite_difference(b631gs):
+    Z, x = inputs.workload("h2o_sto3g")["instances"][0]
+    b = oracle.build_basis(b631gs, Z, x)
+    r = oracle.scf(b, 1e-12, 1e-10)
+    g = oracle.gradient(b, r["P"], r["F"])
+    h = 1e-4
+    for a, d in [(0, 0), (0, 2), (1, 1), (2, 0)]:
+        xp, xm = x.copy(), x.copy()
+        xp[a, d] += h
+        xm[a, d] -= h
+        ep = oracle.scf(oracle.build_basis(b631gs, Z, xp), 1e-12, 1e-10, guess=r["P"])["E"]
+        em = oracle.scf(oracle.build_basis(b631gs, Z, xm), 1e-12, 1e-10, guess=r["P"])["E"]
+        assert g[a, d] == pytest.approx((ep - em) / (2 * h), abs=1e-7)
+
+
+def test_gradient_net_force_torque_and_rotation(sto3g):
+    Z, x = inputs.water_cluster(2, 21)
+    b = oracle.build_basis(sto3g, Z, x)
+    r = oracle.scf(b, 1e-11, 1e-9)
+    g = oracle.gradient(b, r["P"], r["F"])
+    assert np.abs(g.sum(axis=0)).max() < 1e-10
+    assert np.abs(np.cross(x, g).sum(axis=0)).max() < 1e-8
+    R = random_rotation(np.random.default_rng(2))
+    b2 = oracle.build_basis(sto3g, Z, x @ R.T + 1.0)
+    r2 = oracle.scf(b2, 1e-11, 1e-9)
+    g2 = oracle.gradient(b2, r2["P"], r2["F"])
+    assert np.abs(g2 - g @ R.T).max() < 1e-8
