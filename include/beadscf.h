@@ -1,0 +1,169 @@
+/*
+ * beadscf.h - C ABI of the batched direct-SCF energy/force engine for MI355X.
+ *
+ * The engine computes, for every replica ("bead", "image" or independent
+ * cluster) of a batch, the Born-Oppenheimer energy and force at the
+ * closed-shell Hartree-Fock level in a Gaussian basis.  This is the per-replica
+ * force provider of the paper's replica simulation: the replica layer hands a
+ * set of n nuclear configurations to the electronic-structure layer and gets
+ * back the BO energy and force of each (Section 2, Fig. 1a), gathered into
+ * per-replica arrays (the zero-filled E[n] and F[n][N_atom][3] of Section 2).
+ * The SCF thresholds follow Section 3.1 (density threshold 1e-6, integral
+ * cutoff 1e-12), and each replica's previous-step orbitals can seed its next
+ * SCF (Section 2, reuse of the molecular orbitals kept in memory).
+ *
+ * Conventions
+ *   - Atomic units throughout: bohr, hartree (Eh), Eh/bohr.
+ *   - Instance-major arrays; atoms in input order; xyz fastest.
+ *   - Matrices are n x n FP64, symmetric, row-major (= column-major).  Basis
+ *     order: atoms in input order, shells in basis-file order, Cartesian
+ *     components lexicographic (x,y,z; xx,xy,xz,yy,yz,zz), each component
+ *     normalised to unit self-overlap.
+ *   - Host arrays passed in are copied before the call returns; outputs go
+ *     into caller-owned buffers.  With device_ptrs != 0 the pointers are HIP
+ *     device memory on the context's device and the work is ordered on the
+ *     context's stream.
+ *   - Every call returns a bscf_status (BSCF_OK == 0, errors < 0); nothing
+ *     throws across the ABI.  The message of the last error on the calling
+ *     thread is returned by bscf_last_error().
+ *   - One context is not thread-safe; several contexts may coexist.
+ */
+#ifndef BEADSCF_H
+#define BEADSCF_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int bscf_status;
+#define BSCF_OK 0
+#define BSCF_E_INVALID (-1)     /* bad argument or call order                    */
+#define BSCF_E_UNSUPPORTED (-2) /* element/l not in basis, odd electron count, ... */
+#define BSCF_E_DEVICE (-3)      /* HIP / rocBLAS / rocSOLVER failure             */
+#define BSCF_E_STATE (-4)       /* e.g. forces requested before an SCF           */
+#define BSCF_E_NOMEM (-5)       /* device allocation failed                      */
+
+typedef struct bscf_ctx bscf_ctx; /* opaque; owns every device buffer it allocates */
+
+typedef enum { BSCF_FP64 = 0, BSCF_MIXED = 1 } bscf_precision;
+typedef enum {
+  BSCF_GUESS_CORE = 0,     /* core-Hamiltonian guess                              */
+  BSCF_GUESS_PREVIOUS = 1, /* previous SCF orbitals, re-orthonormalised in new S  */
+  BSCF_GUESS_LEARNED = 2,  /* density predicted by the in-run trained network     */
+  BSCF_GUESS_USER = 3      /* density set with bscf_set_density                  */
+} bscf_guess;
+
+/* Per-instance status bits returned by bscf_run_scf. */
+#define BSCF_CONVERGED 0
+#define BSCF_MAX_ITER 1
+#define BSCF_NAN 2
+#define BSCF_FALLBACK_USED 4
+
+typedef struct {
+  double e_tol;        /* |E_k - E_{k-1}| threshold (Eh), e.g. 1e-8              */
+  double comm_tol;     /* max |X^T(FPS - SPF)X| threshold, e.g. 1e-6 (the paper's
+                          density threshold, Section 3.1)                       */
+  double schwarz_tol;  /* skip shell quartets with Q_ab Q_cd below this; 1e-12 is
+                          the paper's integral cutoff (Section 3.1)              */
+  double fp32_split_tol; /* MIXED only: quartets with Q_ab Q_cd above this are
+                            evaluated in FP64, the rest in FP32                 */
+  int max_iter;        /* SCF iterations per call                               */
+  int diis_size;       /* Pulay DIIS subspace (<= 8)                            */
+  int precision;       /* bscf_precision                                        */
+  int guess;           /* bscf_guess                                            */
+  int deterministic;   /* reserved: 0                                           */
+} bscf_scf_opts;
+
+/* Fill opts with defaults: e_tol 1e-8, comm_tol 1e-6, schwarz_tol 1e-12,
+ * fp32_split_tol 1e-4, max_iter 100, diis_size 8, FP64, core guess. */
+bscf_status bscf_default_opts(bscf_scf_opts* opts);
+
+/* Create a context on HIP device `hip_device`; `hip_stream` may be NULL (the
+ * context creates its own) or an existing hipStream_t (not owned). */
+bscf_status bscf_create(int hip_device, void* hip_stream, bscf_ctx** out);
+bscf_status bscf_destroy(bscf_ctx* ctx);
+
+/* Basis set as JSON text: {"elements": {"H": {"Z": 1, "shells": [{"l": 0,
+ * "exponents": [...], "coefficients": [...]}, ...]}, ...}}; s, p, d shells
+ * (SP shells given as separate s and p shells).  Copied. */
+bscf_status bscf_load_basis(bscf_ctx* ctx, const char* basis_json);
+
+/* Batch composition: n_inst instances; n_atoms[i] atoms each with nuclear
+ * charges Z_concat (concatenated over instances) and total charges charge[i]
+ * (may be NULL for neutral).  Allocates all per-instance device storage.
+ * BSCF_E_UNSUPPORTED for an element missing from the basis or an odd number
+ * of electrons. */
+bscf_status bscf_set_instances(bscf_ctx* ctx, int n_inst, const int* n_atoms,
+                               const int* Z_concat, const int* charge);
+
+/* Nuclear positions [sum n_atoms][3] in bohr, host memory, copied.  Computes
+ * the shell-pair data, Schwarz bounds, screened work lists, S, H and the
+ * orthogonaliser of every instance on the device. */
+bscf_status bscf_set_geometries(bscf_ctx* ctx, const double* xyz_bohr_concat);
+
+/* One Fock build at given densities: P (all instances concatenated, each
+ * n_i x n_i) -> F = H + J - K/2 and E[i] = Tr[P(H+F)]/2 + E_nuc.  With
+ * device_ptrs, P and F are device pointers and E may be NULL.  schwarz_tol as
+ * in the options (<= 0: no screening); precision a bscf_precision. */
+bscf_status bscf_build_fock(bscf_ctx* ctx, const double* P, double* F, double* E,
+                            double schwarz_tol, int precision, int device_ptrs);
+
+/* Same build returning J and K separately (for tests). */
+bscf_status bscf_build_jk(bscf_ctx* ctx, const double* P, double* J, double* K,
+                          double schwarz_tol, int precision, int device_ptrs);
+
+/* Run the SCF of every instance (Pulay DIIS on the orthogonalised commutator;
+ * converged when both thresholds hold).  Outputs (host, may be NULL): E[n_inst],
+ * n_iter[n_inst], status[n_inst] (bscf status bits).  Non-convergence of an
+ * instance is a status bit, not an error. */
+bscf_status bscf_run_scf(bscf_ctx* ctx, const bscf_scf_opts* opts, double* E, int* n_iter,
+                         int* status);
+
+/* Forces F = -dE/dR [sum n_atoms][3] (Eh/bohr, host) at the densities of the
+ * last bscf_run_scf (Pople et al. 1979 gradient with W = P F P / 2).
+ * BSCF_E_STATE if no SCF has run at the current geometry. */
+bscf_status bscf_forces(bscf_ctx* ctx, double* F);
+
+/* Density of instance `inst` after the last SCF (n_i x n_i), host or device. */
+bscf_status bscf_get_density(bscf_ctx* ctx, int inst, double* P, int device_ptr);
+/* Set the density of every instance (concatenated), used by BSCF_GUESS_USER. */
+bscf_status bscf_set_density(bscf_ctx* ctx, const double* P, int device_ptrs);
+/* One-electron matrices of instance `inst` (host buffers, may be NULL). */
+bscf_status bscf_get_one_electron(bscf_ctx* ctx, int inst, double* S, double* H);
+
+/* Full ERI tensor of instance `inst` (n^4 doubles, host), n <= 64; test use. */
+bscf_status bscf_eri_tensor(bscf_ctx* ctx, int inst, double* out);
+/* Schwarz bounds of instance `inst` as an n_shell x n_shell matrix (host). */
+bscf_status bscf_schwarz(bscf_ctx* ctx, int inst, double* Q, int nsh);
+
+/* Sizes: basis functions / shells / atoms of instance `inst`. */
+bscf_status bscf_instance_info(bscf_ctx* ctx, int inst, int* nbf, int* nshell, int* natom);
+
+/* Counts of the current work lists: screened shell quartets, primitive
+ * quartets and the algorithmic FLOPs of one Fock build over all instances. */
+bscf_status bscf_work_counts(bscf_ctx* ctx, double* n_quartets, double* n_prim_quartets,
+                             double* flops);
+
+/* Statistics as a JSON object (quartets per class, timings of the last calls). */
+bscf_status bscf_get_stats(bscf_ctx* ctx, char* buf, int len);
+
+/* Evaluate the device Boys function: out[i*(m_max+1)+m] = F_m(T[i]) for n
+ * values of T (host arrays), in FP64 (precision 0) or FP32 (1).  Test use. */
+bscf_status bscf_boys(bscf_ctx* ctx, int m_max, int n, const double* T, double* out,
+                      int precision);
+/* Host-side Boys table entry F_m(0.1 k) used to build the device table. */
+double bscf_boys_table_entry(int m, int k);
+
+/* Learned SCF guess (Section 2's orbital reuse extended by an in-run trained
+ * network): train on the converged densities collected so far, save, load. */
+bscf_status bscf_guess_train(bscf_ctx* ctx, int n_adam_steps, float* loss);
+bscf_status bscf_guess_save(bscf_ctx* ctx, const char* path);
+bscf_status bscf_guess_load(bscf_ctx* ctx, const char* path);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* bscf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BEADSCF_H */

@@ -1,0 +1,241 @@
+"""Thin ctypes binding of libbeadscf.so (include/beadscf.h).
+
+Argument marshalling only: every step of the energy/force path runs in the
+library's HIP kernels.  Importing this module without the built library raises
+ImportError; there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbeadscf.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1601_02713_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+BSCF_FP64, BSCF_MIXED = 0, 1
+GUESS_CORE, GUESS_PREVIOUS, GUESS_LEARNED, GUESS_USER = 0, 1, 2, 3
+STATUS_MAX_ITER, STATUS_NAN, STATUS_FALLBACK = 1, 2, 4
+
+
+class ScfOpts(ctypes.Structure):
+    _fields_ = [("e_tol", ctypes.c_double), ("comm_tol", ctypes.c_double),
+                ("schwarz_tol", ctypes.c_double), ("fp32_split_tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("diis_size", ctypes.c_int),
+                ("precision", ctypes.c_int), ("guess", ctypes.c_int),
+                ("deterministic", ctypes.c_int)]
+
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_SIGS = {
+    "bscf_default_opts": [ctypes.POINTER(ScfOpts)],
+    "bscf_create": [_i, _vp, ctypes.POINTER(_vp)],
+    "bscf_destroy": [_vp],
+    "bscf_load_basis": [_vp, ctypes.c_char_p],
+    "bscf_set_instances": [_vp, _i, _vp, _vp, _vp],
+    "bscf_set_geometries": [_vp, _vp],
+    "bscf_build_fock": [_vp, _vp, _vp, _vp, _d, _i, _i],
+    "bscf_build_jk": [_vp, _vp, _vp, _vp, _d, _i, _i],
+    "bscf_run_scf": [_vp, ctypes.POINTER(ScfOpts), _vp, _vp, _vp],
+    "bscf_forces": [_vp, _vp],
+    "bscf_get_density": [_vp, _i, _vp, _i],
+    "bscf_set_density": [_vp, _vp, _i],
+    "bscf_get_one_electron": [_vp, _i, _vp, _vp],
+    "bscf_eri_tensor": [_vp, _i, _vp],
+    "bscf_schwarz": [_vp, _i, _vp, _i],
+    "bscf_instance_info": [_vp, _i, _vp, _vp, _vp],
+    "bscf_work_counts": [_vp, _vp, _vp, _vp],
+    "bscf_get_stats": [_vp, ctypes.c_char_p, _i],
+    "bscf_boys": [_vp, _i, _i, _vp, _vp, _i],
+    "bscf_guess_train": [_vp, _i, _vp],
+    "bscf_guess_save": [_vp, ctypes.c_char_p],
+    "bscf_guess_load": [_vp, ctypes.c_char_p],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.bscf_last_error.restype = ctypes.c_char_p
+_lib.bscf_last_error.argtypes = []
+_lib.bscf_boys_table_entry.restype = ctypes.c_double
+_lib.bscf_boys_table_entry.argtypes = [_i, _i]
+
+
+class BscfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"beadscf error {code}: {msg}")
+        self.code = code
+
+
+def _chk(rc):
+    if rc != 0:
+        raise BscfError(rc, _lib.bscf_last_error().decode())
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_vp)
+
+
+def default_opts(**kw) -> ScfOpts:
+    o = ScfOpts()
+    _chk(_lib.bscf_default_opts(ctypes.byref(o)))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def boys_table_entry(m: int, k: int) -> float:
+    return _lib.bscf_boys_table_entry(m, k)
+
+
+def exported_symbols():
+    return list(_SIGS) + ["bscf_last_error", "bscf_boys_table_entry"]
+
+
+class Engine:
+    """One context on one HIP device (optionally on a caller's stream)."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        h = _vp()
+        _chk(_lib.bscf_create(device, _vp(stream) if stream else None, ctypes.byref(h)))
+        self._h = h
+        self.n_inst = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.bscf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    # ---- setup
+    def load_basis(self, basis):
+        text = basis if isinstance(basis, str) else json.dumps(basis)
+        _chk(_lib.bscf_load_basis(self._h, text.encode()))
+
+    def set_instances(self, Zs, charges=None):
+        Zs = [np.asarray(z, np.int32) for z in Zs]
+        na = np.array([len(z) for z in Zs], np.int32)
+        zc = np.ascontiguousarray(np.concatenate(Zs).astype(np.int32))
+        ch = None if charges is None else np.ascontiguousarray(np.asarray(charges, np.int32))
+        _chk(_lib.bscf_set_instances(self._h, len(Zs), _ptr(na), _ptr(zc),
+                                     _ptr(ch) if ch is not None else None))
+        self.n_inst = len(Zs)
+        self.natoms = na
+        self.nbf = []
+        for i in range(self.n_inst):
+            nb = ctypes.c_int()
+            _chk(_lib.bscf_instance_info(self._h, i, ctypes.byref(nb), None, None))
+            self.nbf.append(nb.value)
+
+    def set_geometries(self, xyzs):
+        x = np.ascontiguousarray(np.concatenate([np.asarray(v, float).reshape(-1, 3) for v in xyzs]))
+        _chk(_lib.bscf_set_geometries(self._h, _ptr(x)))
+
+    def _cat(self, mats):
+        return np.ascontiguousarray(np.concatenate([np.asarray(m, float).ravel() for m in mats]))
+
+    def _split(self, flat):
+        out, o = [], 0
+        for n in self.nbf:
+            out.append(flat[o:o + n * n].reshape(n, n).copy())
+            o += n * n
+        return out
+
+    # ---- compute
+    def build_fock(self, Ps, schwarz_tol=1e-12, precision=BSCF_FP64):
+        P = self._cat(Ps)
+        F = np.empty_like(P)
+        E = np.empty(self.n_inst)
+        _chk(_lib.bscf_build_fock(self._h, _ptr(P), _ptr(F), _ptr(E), schwarz_tol, precision, 0))
+        return self._split(F), E
+
+    def build_jk(self, Ps, schwarz_tol=1e-12, precision=BSCF_FP64):
+        P = self._cat(Ps)
+        J, K = np.empty_like(P), np.empty_like(P)
+        _chk(_lib.bscf_build_jk(self._h, _ptr(P), _ptr(J), _ptr(K), schwarz_tol, precision, 0))
+        return self._split(J), self._split(K)
+
+    def run_scf(self, opts: ScfOpts | None = None, **kw):
+        o = opts or default_opts(**kw)
+        E = np.empty(self.n_inst)
+        it = np.empty(self.n_inst, np.int32)
+        st = np.empty(self.n_inst, np.int32)
+        _chk(_lib.bscf_run_scf(self._h, ctypes.byref(o), _ptr(E), _ptr(it), _ptr(st)))
+        return E, it, st
+
+    def forces(self):
+        F = np.empty((int(self.natoms.sum()), 3))
+        _chk(_lib.bscf_forces(self._h, _ptr(F)))
+        out, o = [], 0
+        for n in self.natoms:
+            out.append(F[o:o + n].copy())
+            o += n
+        return out
+
+    def density(self, i):
+        n = self.nbf[i]
+        P = np.empty((n, n))
+        _chk(_lib.bscf_get_density(self._h, i, _ptr(P), 0))
+        return P
+
+    def set_density(self, Ps):
+        P = self._cat(Ps)
+        _chk(_lib.bscf_set_density(self._h, _ptr(P), 0))
+
+    def one_electron(self, i):
+        n = self.nbf[i]
+        S, H = np.empty((n, n)), np.empty((n, n))
+        _chk(_lib.bscf_get_one_electron(self._h, i, _ptr(S), _ptr(H)))
+        return S, H
+
+    def eri_tensor(self, i):
+        n = self.nbf[i]
+        out = np.empty((n, n, n, n))
+        _chk(_lib.bscf_eri_tensor(self._h, i, _ptr(out)))
+        return out
+
+    def schwarz(self, i):
+        ns = ctypes.c_int()
+        _chk(_lib.bscf_instance_info(self._h, i, None, ctypes.byref(ns), None))
+        Q = np.empty((ns.value, ns.value))
+        _chk(_lib.bscf_schwarz(self._h, i, _ptr(Q), ns.value))
+        return Q
+
+    def work_counts(self):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _chk(_lib.bscf_work_counts(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def stats(self):
+        buf = ctypes.create_string_buffer(1 << 16)
+        _chk(_lib.bscf_get_stats(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def boys(self, m_max, T, precision=0):
+        T = np.ascontiguousarray(np.asarray(T, float))
+        out = np.empty((len(T), m_max + 1))
+        _chk(_lib.bscf_boys(self._h, m_max, len(T), _ptr(T), _ptr(out), precision))
+        return out
+
+    def guess_train(self, steps):
+        l = ctypes.c_float()
+        _chk(_lib.bscf_guess_train(self._h, steps, ctypes.byref(l)))
+        return l.value
+
+    def guess_save(self, path):
+        _chk(_lib.bscf_guess_save(self._h, path.encode()))
+
+    def guess_load(self, path):
+        _chk(_lib.bscf_guess_load(self._h, path.encode()))

@@ -1,0 +1,86 @@
+"""Build libbeadscf.so for gfx950 in-tree.
+
+Steps: run csrc/gen_eri.py into csrc/generated/, compile every .hip/.cpp
+translation unit with hipcc (in parallel), link the shared library next to
+this file.  ``python -m paper_1601_02713_amd.build [--force]``.
+"""
+
+from __future__ import annotations
+
+import concurrent.futures as cf
+import glob
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+GEN = os.path.join(CSRC, "generated")
+OBJ = os.path.join(os.path.dirname(HERE), "_build", "obj")
+LIB = os.path.join(HERE, "libbeadscf.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+HIPFLAGS = [
+    "-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-result", "-I", CSRC, "-I", GEN, "-I", os.path.join(ROCM, "include"),
+]
+
+
+def _sources():
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")) +
+                  glob.glob(os.path.join(GEN, "*.hip")))
+    return srcs
+
+
+def _newest_header():
+    hs = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(GEN, "*.h")) + \
+        [os.path.join(os.path.dirname(HERE), "include", "beadscf.h")]
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src, force, hdr_time):
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    if not force and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if t > os.path.getmtime(src) and t > hdr_time:
+            return obj, None
+    cmd = ["hipcc"] + HIPFLAGS + ["-x", "hip", "-c", src, "-o", obj + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        return obj, f"{' '.join(cmd)}\n{r.stdout}\n{r.stderr}"
+    os.replace(obj + ".tmp", obj)
+    return obj, None
+
+
+def build(force: bool = False, jobs: int | None = None, verbose: bool = True) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    gen_script = os.path.join(CSRC, "gen_eri.py")
+    stamp = os.path.join(GEN, "classes.h")
+    if force or not os.path.exists(stamp) or os.path.getmtime(stamp) < os.path.getmtime(gen_script):
+        subprocess.check_call([sys.executable, gen_script, GEN])
+    hdr_time = _newest_header()
+    srcs = _sources()
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    objs, errs = [], []
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        for obj, err in ex.map(lambda s: _compile(s, force, hdr_time), srcs):
+            objs.append(obj)
+            if err:
+                errs.append(err)
+    if errs:
+        raise RuntimeError("hipcc failed:\n" + "\n\n".join(errs))
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(o) for o in objs):
+        tmp = LIB + f".tmp{os.getpid()}"
+        cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + [
+            "-L", os.path.join(ROCM, "lib"), "-lrocsolver", "-lrocblas", "-lamdhip64",
+            f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB}")
+    return LIB
+
+
+if __name__ == "__main__":
+    build(force="--force" in sys.argv)

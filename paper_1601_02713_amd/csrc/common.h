@@ -1,0 +1,59 @@
+// Shared device/host data layouts of the batched direct-SCF engine.
+//
+// All instances (beads, images or independent clusters) live in one set of
+// flat arrays: shells, shell pairs and primitive pairs are concatenated over
+// instances; n x n matrices of instance i start at moff[i] (row-major FP64).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bscf {
+
+constexpr int kLmax = 2;            // s, p, d shells
+constexpr int kBoysRows = 401;      // Boys table grid T = 0, 0.1, ..., 40
+constexpr double kBoysStep = 0.1;
+constexpr double kBoysTmax = 40.0;  // asymptotic branch at and above
+constexpr int kBoysCols = 24;       // F_0..F_22 and exp(-T_k) in column 23
+constexpr int kBoysExpCol = 23;
+constexpr int kWave = 64;
+
+// Primitive pair of a contracted shell pair (a, b) with la >= lb.
+struct PrimPair {
+  double p;              // alpha + beta
+  double Px, Py, Pz;     // (alpha A + beta B) / p
+  double PAx, PAy, PAz;  // P - A
+  double C;              // sqrt(2) pi^{5/4} c_a c_b exp(-alpha beta/p |AB|^2) / p
+  double oo2p;           // 1 / (2p)
+  double alpha, beta;    // exponents on A and B (gradients)
+  double pad;
+};
+
+struct Shell {
+  double x, y, z;
+  int l;
+  int bf;      // first basis function, local to the instance
+  int inst;
+  int atom;    // global atom index
+  int prim0;   // into the shell-primitive arrays
+  int nprim;
+};
+
+struct ShellPair {
+  int a, b;    // global shell indices, l(a) >= l(b)
+  int prim0;   // first PrimPair
+  int nprim;   // primitive pairs
+};
+
+// One wavefront's work: a bra shell pair against nket ket pairs taken from
+// kets[ket0 ...] (all of one angular class and one primitive count).
+struct WorkItem {
+  int bra;
+  int ket0;
+  int nket;
+  int diag;    // 1 if kets may include the bra pair itself
+};
+
+__host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+}  // namespace bscf

@@ -1,0 +1,1337 @@
+// Host side of the batched direct-SCF engine and its C ABI (include/beadscf.h).
+//
+// Per geometry: shell pairs and primitive pairs (device kernel), Schwarz
+// bounds Q_ab = sqrt(max |(ab|ab)|) (device), screened work lists (host,
+// integer work only: pairs sorted by Q per class and primitive count, each bra
+// taking the surviving prefix of kets with Q_ab Q_cd >= tau, the paper's
+// integral cutoff of Section 3.1), S, T, V (device) and X = S^{-1/2}.
+// Per SCF iteration over all active instances: J/K by the generated class
+// kernels, Fock assembly and energy, commutator error, DIIS, orthogonalised
+// eigensolve and the new density, convergence flags (one device->host copy of
+// per-instance flags per iteration; converged instances are masked).
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/beadscf.h"
+#include "classes.h"
+#include "common.h"
+#include "kernels.h"
+#include "grad.h"
+#include "mlp.h"
+
+using namespace bscf;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                         \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
+    if (e_ != hipSuccess)                                                                 \
+      throw Error(BSCF_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+#define BLASCHK(x)                                                                        \
+  do {                                                                                    \
+    rocblas_status s_ = (x);                                                              \
+    if (s_ != rocblas_status_success)                                                     \
+      throw Error(BSCF_E_DEVICE, std::string(#x) + ": rocblas status " + std::to_string(s_)); \
+  } while (0)
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void resize(size_t m) {
+    if (m <= n && p) return;
+    release();
+    if (m == 0) m = 1;
+    if (hipMalloc(&p, m * sizeof(T)) != hipSuccess) {
+      p = nullptr;
+      throw Error(BSCF_E_NOMEM, "hipMalloc of " + std::to_string(m * sizeof(T)) + " bytes failed");
+    }
+    n = m;
+  }
+  void upload(const std::vector<T>& v, hipStream_t s) {
+    resize(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+};
+
+// ------------------------------------------------------------ mini JSON
+struct JVal {
+  enum Kind { NUL, NUM, STR, ARR, OBJ, BOOL } kind = NUL;
+  double num = 0;
+  std::string str;
+  std::vector<JVal> arr;
+  std::vector<std::pair<std::string, JVal>> obj;
+  const JVal* get(const std::string& k) const {
+    for (auto& kv : obj)
+      if (kv.first == k) return &kv.second;
+    return nullptr;
+  }
+};
+
+struct JParser {
+  const char* s;
+  void ws() { while (*s && isspace((unsigned char)*s)) ++s; }
+  [[noreturn]] void fail(const char* m) { throw Error(BSCF_E_INVALID, std::string("basis JSON: ") + m); }
+  JVal parse() {
+    ws();
+    JVal v;
+    if (*s == '{') {
+      v.kind = JVal::OBJ;
+      ++s;
+      ws();
+      if (*s == '}') { ++s; return v; }
+      for (;;) {
+        ws();
+        if (*s != '"') fail("expected key");
+        std::string k = str();
+        ws();
+        if (*s != ':') fail("expected ':'");
+        ++s;
+        v.obj.emplace_back(k, parse());
+        ws();
+        if (*s == ',') { ++s; continue; }
+        if (*s == '}') { ++s; return v; }
+        fail("expected ',' or '}'");
+      }
+    } else if (*s == '[') {
+      v.kind = JVal::ARR;
+      ++s;
+      ws();
+      if (*s == ']') { ++s; return v; }
+      for (;;) {
+        v.arr.push_back(parse());
+        ws();
+        if (*s == ',') { ++s; continue; }
+        if (*s == ']') { ++s; return v; }
+        fail("expected ',' or ']'");
+      }
+    } else if (*s == '"') {
+      v.kind = JVal::STR;
+      v.str = str();
+    } else if (!strncmp(s, "true", 4)) {
+      v.kind = JVal::BOOL; v.num = 1; s += 4;
+    } else if (!strncmp(s, "false", 5)) {
+      v.kind = JVal::BOOL; s += 5;
+    } else if (!strncmp(s, "null", 4)) {
+      s += 4;
+    } else {
+      char* end;
+      v.num = strtod(s, &end);
+      if (end == s) fail("bad value");
+      v.kind = JVal::NUM;
+      s = end;
+    }
+    return v;
+  }
+  std::string str() {
+    std::string out;
+    ++s;
+    while (*s && *s != '"') {
+      if (*s == '\\' && s[1]) { out.push_back(s[1]); s += 2; continue; }
+      out.push_back(*s++);
+    }
+    if (*s != '"') fail("unterminated string");
+    ++s;
+    return out;
+  }
+};
+
+struct BasisShell {
+  int l;
+  std::vector<double> exps, coefs;  // coefs: d_k * radial norm * contraction rescale
+};
+
+// radial primitive normalisation (2a/pi)^{3/4} (4a)^{l/2}, the x^l component
+// carrying the double factorial separately; the contraction is rescaled so that
+// <phi|phi> = 1 with <g_i|g_j> = (pi/(ai+aj))^{3/2} (2l-1)!!/(2(ai+aj))^l.
+BasisShell normalise_shell(int l, const std::vector<double>& e, const std::vector<double>& d) {
+  BasisShell s;
+  s.l = l;
+  s.exps = e;
+  const double pi = M_PI;
+  std::vector<double> c(e.size());
+  for (size_t k = 0; k < e.size(); ++k)
+    c[k] = d[k] * std::pow(2.0 * e[k] / pi, 0.75) * std::pow(4.0 * e[k], 0.5 * l);
+  double dfac = 1.0;
+  for (int k = 2 * l - 1; k > 1; k -= 2) dfac *= k;
+  double ss = 0.0;
+  for (size_t i = 0; i < e.size(); ++i)
+    for (size_t j = 0; j < e.size(); ++j) {
+      const double p = e[i] + e[j];
+      ss += c[i] * c[j] * std::pow(pi / p, 1.5) * dfac / std::pow(2.0 * p, l);
+    }
+  // the component norm 1/sqrt((2l-1)!!) of x^l makes the self-overlap ss/dfac
+  const double r = 1.0 / std::sqrt(ss / dfac);
+  for (auto& x : c) x *= r;
+  s.coefs = c;
+  return s;
+}
+
+struct Group {
+  int first, count, n;
+};
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+}  // namespace
+
+struct bscf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  rocblas_handle blas = nullptr;
+
+  std::map<int, std::vector<BasisShell>> basis;
+
+  // instances
+  int ninst = 0;
+  std::vector<int> natoms, atom_off, Zs, charge, nbf, nocc, nshell, shell_off;
+  std::vector<long long> moff;
+  long long mtot = 0;
+  int max_n = 0, max_atoms = 0, total_atoms = 0;
+  std::vector<Group> groups;
+  // shells, pairs (topology fixed per batch composition)
+  std::vector<Shell> shells;
+  std::vector<double> sh_exp, sh_coef;
+  std::vector<ShellPair> pairs;
+  std::vector<int> pair_class;     // 0..5
+  std::vector<int> prim_owner;
+  int nprim_pairs = 0;
+  std::vector<std::vector<int>> pairs_by_class;  // global pair ids per pair class
+  std::vector<double> xyz;
+  bool have_geom = false, have_scf = false;
+  std::vector<double> Q;           // per pair
+  double work_tau = -1.0;
+  // work lists per quartet class
+  struct ClassWork {
+    std::vector<WorkItem> items;
+    DevBuf<WorkItem> d_items;
+    double nquart = 0, nprimq = 0;
+  };
+  ClassWork work[kNumQuartetClasses];
+  std::vector<int> kets;
+  DevBuf<int> d_kets;
+
+  // device data
+  DevBuf<Shell> d_shells;
+  DevBuf<double> d_sh_exp, d_sh_coef;
+  DevBuf<ShellPair> d_pairs;
+  DevBuf<int> d_prim_owner;
+  DevBuf<PrimPair> d_prims;
+  DevBuf<double> d_Q;
+  std::vector<DevBuf<int>> d_pair_ids;   // per pair class
+  DevBuf<double> d_boys64;
+  DevBuf<float> d_boys32;
+  DevBuf<int> d_nocc, d_nbf, d_natoms, d_atom_off, d_active, d_all_active, d_conv_iter, d_status;
+  DevBuf<long long> d_moff;
+  DevBuf<double> d_xyz, d_Zd, d_Enuc, d_E, d_Eprev, d_emax, d_grad;
+  DevBuf<int> d_task_a, d_task_b;  // 1e tasks: pair shells
+  std::vector<int> task_first, task_count;  // per pair class ranges into task arrays
+  // matrices
+  DevBuf<double> S, T, V, H, X, F, J, K, P, Pnew, W, tmp1, tmp2, err, Fbar, C, Cacc, eig, eigE;
+  DevBuf<double> Fhist, Ehist, diisB, diisC;
+  DevBuf<int> diis_count, diis_head, d_info;
+  bool have_C = false;
+
+  // stats
+  double t_fock_ms = 0, t_scf_ms = 0, t_grad_ms = 0, t_setup_ms = 0;
+  int fock_builds = 0, scf_iters = 0;
+  std::vector<int> last_iters;
+
+  mlp::Guess guess;
+
+  BatchInfo batch(bool masked) const {
+    BatchInfo b;
+    b.ninst = ninst;
+    b.nbf = d_nbf.p;
+    b.moff = d_moff.p;
+    b.active = masked ? d_active.p : nullptr;
+    return b;
+  }
+};
+
+namespace {
+
+template <typename F>
+bscf_status guard(F&& f) {
+  try {
+    f();
+    g_err.clear();
+    return BSCF_OK;
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return BSCF_E_DEVICE;
+  }
+}
+
+void need(bool c, int code, const std::string& m) {
+  if (!c) throw Error(code, m);
+}
+
+// pair class index of (la, lb), la >= lb: ss, ps, pp, ds, dp, dd
+int pclass(int la, int lb) { return la * (la + 1) / 2 + lb; }
+
+void sync(bscf_ctx* c) { HIPCHK(hipStreamSynchronize(c->stream)); }
+
+// ---- dense helpers over groups of equal-n consecutive instances
+void gemm(bscf_ctx* c, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+          double alpha, const double* A, const double* B, double beta, double* Cm) {
+  for (const Group& g : c->groups) {
+    const long long o = c->moff[g.first];
+    const long long st = (long long)g.n * g.n;
+    const int mm = m < 0 ? g.n : m, nn = n < 0 ? g.n : n, kk = k < 0 ? g.n : k;
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, ta, tb, mm, nn, kk, &alpha, A + o, g.n, st,
+                                          B + o, g.n, st, &beta, Cm + o, g.n, st, g.count));
+  }
+}
+
+// symmetric eigendecomposition in place: A <- eigenvectors (columns), w <- values
+void syevd(bscf_ctx* c, double* A, double* w) {
+  for (const Group& g : c->groups) {
+    const long long o = c->moff[g.first];
+    const long long st = (long long)g.n * g.n;
+    // eigenvalues of instance i stored at w + moff[i] (row 0 of its block)
+    BLASCHK(rocsolver_dsyevd_strided_batched(c->blas, rocblas_evect_original, rocblas_fill_upper,
+                                             g.n, A + o, g.n, st, w + o, st, c->eigE.p + o, st,
+                                             c->d_info.p + g.first, g.count));
+  }
+}
+
+__global__ void scale_cols_kernel(BatchInfo b, const double* U, const double* w, double* out,
+                                  double power) {
+  const int inst = blockIdx.y;
+  const int n = b.nbf[inst];
+  const long long o = b.moff[inst], nn = (long long)n * n;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
+       k += (long long)gridDim.x * blockDim.x) {
+    const long long col = k / n;  // column-major: element k = (row k%n, col k/n)
+    out[o + k] = U[o + k] * pow(w[o + col], power);
+  }
+}
+
+__global__ void min_eig_kernel(BatchInfo b, const double* w, double* out) {
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst >= b.ninst) return;
+  out[inst] = w[b.moff[inst]];
+}
+
+// X = S^{-1/2} (Loewdin) for every instance
+void build_orthogonaliser(bscf_ctx* c) {
+  const long long mt = c->mtot;
+  HIPCHK(hipMemcpyAsync(c->eig.p, c->S.p, mt * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  syevd(c, c->eig.p, c->tmp2.p);
+  // smallest eigenvalue check
+  std::vector<double> wmin(c->ninst);
+  for (int i = 0; i < c->ninst; ++i)
+    HIPCHK(hipMemcpyAsync(&wmin[i], c->tmp2.p + c->moff[i], sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+  sync(c);
+  for (int i = 0; i < c->ninst; ++i)
+    need(wmin[i] > 1e-7, BSCF_E_UNSUPPORTED,
+         "overlap matrix of instance " + std::to_string(i) + " is near-singular (min eigenvalue " +
+             std::to_string(wmin[i]) + ")");
+  BatchInfo b = c->batch(false);
+  const long long nn = (long long)c->max_n * c->max_n;
+  const unsigned gx = (unsigned)std::min<long long>((nn + 255) / 256, 1024);
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(gx, c->ninst), dim3(256), 0, c->stream, b, c->eig.p,
+                     c->tmp2.p, c->tmp1.p, -0.5);
+  // X = (U w^{-1/2}) U^T
+  gemm(c, rocblas_operation_none, rocblas_operation_transpose, -1, -1, -1, 1.0, c->tmp1.p,
+       c->eig.p, 0.0, c->X.p);
+}
+
+// density from Fbar: F' = X Fbar X, eig, C = X C', P = 2 C_occ C_occ^T
+void density_from_fock(bscf_ctx* c, const double* Fb, double* Pout) {
+  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->X.p, Fb, 0.0,
+       c->tmp1.p);
+  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->tmp1.p, c->X.p, 0.0,
+       c->eig.p);
+  syevd(c, c->eig.p, c->tmp2.p);
+  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->X.p, c->eig.p, 0.0,
+       c->C.p);
+  for (const Group& g : c->groups) {
+    const long long o = c->moff[g.first];
+    const long long st = (long long)g.n * g.n;
+    const int no = c->nocc[g.first];
+    const double two = 2.0, zero = 0.0;
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none,
+                                          rocblas_operation_transpose, g.n, g.n, no, &two,
+                                          c->C.p + o, g.n, st, c->C.p + o, g.n, st, &zero,
+                                          Pout + o, g.n, st, g.count));
+  }
+}
+
+void build_shell_topology(bscf_ctx* c) {
+  c->shells.clear();
+  c->sh_exp.clear();
+  c->sh_coef.clear();
+  c->pairs.clear();
+  c->pair_class.clear();
+  c->prim_owner.clear();
+  c->nshell.assign(c->ninst, 0);
+  c->shell_off.assign(c->ninst, 0);
+  c->pairs_by_class.assign(kNumPairClasses, {});
+  for (int i = 0; i < c->ninst; ++i) {
+    c->shell_off[i] = (int)c->shells.size();
+    int bf = 0;
+    for (int a = 0; a < c->natoms[i]; ++a) {
+      const int z = c->Zs[c->atom_off[i] + a];
+      for (const BasisShell& bs : c->basis[z]) {
+        Shell s{};
+        s.l = bs.l;
+        s.bf = bf;
+        s.inst = i;
+        s.atom = c->atom_off[i] + a;
+        s.prim0 = (int)c->sh_exp.size();
+        s.nprim = (int)bs.exps.size();
+        for (size_t k = 0; k < bs.exps.size(); ++k) {
+          c->sh_exp.push_back(bs.exps[k]);
+          c->sh_coef.push_back(bs.coefs[k]);
+        }
+        bf += ncart(bs.l);
+        c->shells.push_back(s);
+      }
+    }
+    c->nshell[i] = (int)c->shells.size() - c->shell_off[i];
+    // pairs a >= b (index), stored with the higher l first
+    const int s0 = c->shell_off[i], ns = c->nshell[i];
+    for (int a = 0; a < ns; ++a)
+      for (int b = 0; b <= a; ++b) {
+        int sa = s0 + a, sb = s0 + b;
+        if (c->shells[sa].l < c->shells[sb].l) std::swap(sa, sb);
+        ShellPair p;
+        p.a = sa;
+        p.b = sb;
+        p.prim0 = c->nprim_pairs;
+        p.nprim = c->shells[sa].nprim * c->shells[sb].nprim;
+        for (int k = 0; k < p.nprim; ++k) c->prim_owner.push_back((int)c->pairs.size());
+        c->nprim_pairs += p.nprim;
+        const int pc = pclass(c->shells[sa].l, c->shells[sb].l);
+        c->pairs_by_class[pc].push_back((int)c->pairs.size());
+        c->pair_class.push_back(pc);
+        c->pairs.push_back(p);
+      }
+  }
+}
+
+// Work lists for the Fock build (see file comment).
+void build_work(bscf_ctx* c, double tau) {
+  const int NPC = kNumPairClasses;
+  // per instance, per pair class: subclasses keyed by primitive count
+  struct Sub {
+    int nprim;
+    std::vector<int> ids;   // sorted by Q desc
+    std::vector<double> q;
+    int ket_off;
+  };
+  std::vector<std::vector<std::vector<Sub>>> subs(c->ninst, std::vector<std::vector<Sub>>(NPC));
+  std::vector<int> sub_of(c->pairs.size()), rank_of(c->pairs.size());
+  for (int pc = 0; pc < NPC; ++pc)
+    for (int pid : c->pairs_by_class[pc]) {
+      const int inst = c->shells[c->pairs[pid].a].inst;
+      auto& v = subs[inst][pc];
+      int k = 0;
+      while (k < (int)v.size() && v[k].nprim != c->pairs[pid].nprim) ++k;
+      if (k == (int)v.size()) v.push_back(Sub{c->pairs[pid].nprim, {}, {}, 0});
+      v[k].ids.push_back(pid);
+    }
+  c->kets.clear();
+  for (int i = 0; i < c->ninst; ++i)
+    for (int pc = 0; pc < NPC; ++pc) {
+      auto& v = subs[i][pc];
+      std::sort(v.begin(), v.end(), [](const Sub& x, const Sub& y) { return x.nprim > y.nprim; });
+      for (int s = 0; s < (int)v.size(); ++s) {
+        auto& sb = v[s];
+        std::stable_sort(sb.ids.begin(), sb.ids.end(),
+                         [&](int x, int y) { return c->Q[x] > c->Q[y]; });
+        sb.q.resize(sb.ids.size());
+        sb.ket_off = (int)c->kets.size();
+        for (size_t r = 0; r < sb.ids.size(); ++r) {
+          sb.q[r] = c->Q[sb.ids[r]];
+          sub_of[sb.ids[r]] = s;
+          rank_of[sb.ids[r]] = (int)r;
+          c->kets.push_back(sb.ids[r]);
+        }
+      }
+    }
+  const int CHUNK = 256;
+  const QuartetClass* qc = quartet_classes();
+  for (int q = 0; q < kNumQuartetClasses; ++q) {
+    auto& W = c->work[q];
+    W.items.clear();
+    W.nquart = 0;
+    W.nprimq = 0;
+    const int X = pclass(qc[q].la, qc[q].lb), Y = pclass(qc[q].lc, qc[q].ld);
+    struct Tmp {
+      WorkItem w;
+      double cost;
+    };
+    std::vector<Tmp> tmp;
+    for (int i = 0; i < c->ninst; ++i) {
+      for (const Sub& bs : subs[i][X])
+        for (size_t r = 0; r < bs.ids.size(); ++r) {
+          const int bra = bs.ids[r];
+          const double qb = bs.q[r];
+          const int sb = sub_of[bra];
+          const auto& kv = subs[i][Y];
+          for (int t = 0; t < (int)kv.size(); ++t) {
+            const Sub& ks = kv[t];
+            int lim;
+            if (tau > 0.0) {
+              // number of kets with qb * q >= tau (q sorted descending)
+              int lo = 0, hi = (int)ks.q.size();
+              while (lo < hi) {
+                const int mid = (lo + hi) / 2;
+                if (qb * ks.q[mid] >= tau) lo = mid + 1;
+                else hi = mid;
+              }
+              lim = lo;
+            } else {
+              lim = (int)ks.q.size();
+            }
+            if (X == Y) {
+              if (t > sb) lim = 0;
+              else if (t == sb) lim = std::min(lim, (int)r + 1);
+            }
+            for (int k0 = 0; k0 < lim; k0 += CHUNK) {
+              const int nk = std::min(CHUNK, lim - k0);
+              WorkItem w{bra, ks.ket_off + k0, nk, (X == Y && t == sb) ? 1 : 0};
+              tmp.push_back({w, double(nk) * bs.nprim * ks.nprim});
+              W.nquart += nk;
+              W.nprimq += double(nk) * bs.nprim * ks.nprim;
+            }
+          }
+        }
+    }
+    std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; });
+    W.items.resize(tmp.size());
+    for (size_t k = 0; k < tmp.size(); ++k) W.items[k] = tmp[k].w;
+    W.d_items.upload(W.items, c->stream);
+  }
+  c->d_kets.upload(c->kets, c->stream);
+  c->work_tau = tau;
+}
+
+void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
+  if (tau != c->work_tau) build_work(c, tau);
+  const double t0 = now_ms();
+  launch_fill(c->J.p, c->mtot, 0.0, c->stream);
+  launch_fill(c->K.p, c->mtot, 0.0, c->stream);
+  FockArgs a;
+  a.pairs = c->d_pairs.p;
+  a.prims = c->d_prims.p;
+  a.shells = c->d_shells.p;
+  a.kets = c->d_kets.p;
+  a.moff = c->d_moff.p;
+  a.nbf = c->d_nbf.p;
+  a.P = c->P.p;
+  a.J = c->J.p;
+  a.K = c->K.p;
+  a.boys64 = c->d_boys64.p;
+  a.boys32 = c->d_boys32.p;
+  a.active = masked ? c->d_active.p : c->d_all_active.p;
+  const QuartetClass* qc = quartet_classes();
+  for (int q = 0; q < kNumQuartetClasses; ++q) {
+    auto& W = c->work[q];
+    if (W.items.empty()) continue;
+    a.items = W.d_items.p;
+    a.nitems = (int)W.items.size();
+    qc[q].fock(a, precision == BSCF_MIXED ? 1 : 0, c->stream);
+  }
+  HIPCHK(hipGetLastError());
+  BatchInfo b = c->batch(false);
+  launch_fock_assemble(b, c->max_n, c->H.p, c->J.p, c->K.p, c->P.p, c->d_Enuc.p, c->F.p, c->d_E.p,
+                       c->stream);
+  c->fock_builds++;
+  c->t_fock_ms += now_ms() - t0;
+}
+
+void require_geom(bscf_ctx* c) {
+  need(c->ninst > 0, BSCF_E_INVALID, "no instances set");
+  need(c->have_geom, BSCF_E_INVALID, "no geometry set");
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* bscf_last_error(void) { return g_err.c_str(); }
+
+bscf_status bscf_default_opts(bscf_scf_opts* o) {
+  if (!o) return BSCF_E_INVALID;
+  o->e_tol = 1e-8;
+  o->comm_tol = 1e-6;
+  o->schwarz_tol = 1e-12;
+  o->fp32_split_tol = 1e-4;
+  o->max_iter = 100;
+  o->diis_size = 8;
+  o->precision = BSCF_FP64;
+  o->guess = BSCF_GUESS_CORE;
+  o->deterministic = 0;
+  return BSCF_OK;
+}
+
+bscf_status bscf_create(int hip_device, void* hip_stream, bscf_ctx** out) {
+  return guard([&] {
+    need(out != nullptr, BSCF_E_INVALID, "out is NULL");
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    need(hip_device >= 0 && hip_device < ndev, BSCF_E_INVALID, "bad device index");
+    std::unique_ptr<bscf_ctx> c(new bscf_ctx());
+    c->device = hip_device;
+    HIPCHK(hipSetDevice(hip_device));
+    if (hip_stream) {
+      c->stream = (hipStream_t)hip_stream;
+    } else {
+      HIPCHK(hipStreamCreate(&c->stream));
+      c->own_stream = true;
+    }
+    BLASCHK(rocblas_create_handle(&c->blas));
+    BLASCHK(rocblas_set_stream(c->blas, c->stream));
+    std::vector<double> tab(kBoysRows * kBoysCols);
+    boys_table_host(tab.data());
+    std::vector<float> tab32(tab.begin(), tab.end());
+    c->d_boys64.upload(tab, c->stream);
+    c->d_boys32.upload(tab32, c->stream);
+    sync(c.get());
+    *out = c.release();
+  });
+}
+
+bscf_status bscf_destroy(bscf_ctx* c) {
+  if (!c) return BSCF_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->blas) rocblas_destroy_handle(c->blas);
+  hipStream_t s = c->stream;
+  bool own = c->own_stream;
+  delete c;
+  if (own) (void)hipStreamDestroy(s);
+  return BSCF_OK;
+}
+
+bscf_status bscf_load_basis(bscf_ctx* c, const char* json) {
+  return guard([&] {
+    need(c && json, BSCF_E_INVALID, "NULL argument");
+    JParser p{json};
+    JVal root = p.parse();
+    const JVal* el = root.get("elements");
+    need(el && el->kind == JVal::OBJ, BSCF_E_INVALID, "basis JSON: no 'elements' object");
+    std::map<int, std::vector<BasisShell>> b;
+    for (auto& kv : el->obj) {
+      const JVal* z = kv.second.get("Z");
+      const JVal* sh = kv.second.get("shells");
+      need(z && sh && sh->kind == JVal::ARR, BSCF_E_INVALID, "basis JSON: element without Z/shells");
+      std::vector<BasisShell> v;
+      for (const JVal& s : sh->arr) {
+        const JVal* l = s.get("l");
+        const JVal* e = s.get("exponents");
+        const JVal* d = s.get("coefficients");
+        need(l && e && d && e->arr.size() == d->arr.size() && !e->arr.empty(), BSCF_E_INVALID,
+             "basis JSON: malformed shell");
+        const int ll = (int)l->num;
+        need(ll >= 0 && ll <= kLmax, BSCF_E_UNSUPPORTED, "only s, p, d shells are supported");
+        std::vector<double> ex, co;
+        for (auto& x : e->arr) ex.push_back(x.num);
+        for (auto& x : d->arr) co.push_back(x.num);
+        for (double x : ex) need(x > 0.0, BSCF_E_INVALID, "non-positive exponent");
+        v.push_back(normalise_shell(ll, ex, co));
+      }
+      b[(int)z->num] = v;
+    }
+    c->basis = b;
+  });
+}
+
+bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, const int* Z,
+                               const int* charge) {
+  return guard([&] {
+    need(c && n_inst > 0 && n_atoms && Z, BSCF_E_INVALID, "bad arguments");
+    need(!c->basis.empty(), BSCF_E_INVALID, "load a basis first");
+    HIPCHK(hipSetDevice(c->device));
+    c->ninst = n_inst;
+    c->natoms.assign(n_atoms, n_atoms + n_inst);
+    c->atom_off.assign(n_inst, 0);
+    int tot = 0;
+    for (int i = 0; i < n_inst; ++i) {
+      need(n_atoms[i] > 0, BSCF_E_INVALID, "instance without atoms");
+      c->atom_off[i] = tot;
+      tot += n_atoms[i];
+    }
+    c->total_atoms = tot;
+    c->Zs.assign(Z, Z + tot);
+    c->charge.assign(n_inst, 0);
+    if (charge) c->charge.assign(charge, charge + n_inst);
+    c->nbf.assign(n_inst, 0);
+    c->nocc.assign(n_inst, 0);
+    c->moff.assign(n_inst, 0);
+    c->mtot = 0;
+    c->max_n = 0;
+    c->max_atoms = 0;
+    for (int i = 0; i < n_inst; ++i) {
+      int ne = -c->charge[i], nb = 0;
+      for (int a = 0; a < n_atoms[i]; ++a) {
+        const int z = c->Zs[c->atom_off[i] + a];
+        auto it = c->basis.find(z);
+        need(it != c->basis.end(), BSCF_E_UNSUPPORTED,
+             "element Z=" + std::to_string(z) + " not in basis");
+        ne += z;
+        for (auto& s : it->second) nb += ncart(s.l);
+      }
+      need(ne > 0 && ne % 2 == 0, BSCF_E_UNSUPPORTED,
+           "instance " + std::to_string(i) + ": closed-shell RHF needs an even electron count");
+      need(ne / 2 <= nb, BSCF_E_UNSUPPORTED, "more occupied orbitals than basis functions");
+      c->nbf[i] = nb;
+      c->nocc[i] = ne / 2;
+      c->moff[i] = c->mtot;
+      c->mtot += (long long)nb * nb;
+      c->max_n = std::max(c->max_n, nb);
+      c->max_atoms = std::max(c->max_atoms, n_atoms[i]);
+    }
+    c->groups.clear();
+    for (int i = 0; i < n_inst; ++i) {
+      if (!c->groups.empty() && c->groups.back().n == c->nbf[i] &&
+          c->nocc[c->groups.back().first] == c->nocc[i])
+        c->groups.back().count++;
+      else
+        c->groups.push_back(Group{i, 1, c->nbf[i]});
+    }
+    c->nprim_pairs = 0;
+    build_shell_topology(c);
+    const hipStream_t s = c->stream;
+    c->d_nbf.upload(c->nbf, s);
+    c->d_nocc.upload(c->nocc, s);
+    c->d_moff.upload(c->moff, s);
+    c->d_natoms.upload(c->natoms, s);
+    c->d_atom_off.upload(c->atom_off, s);
+    std::vector<double> zd(c->Zs.begin(), c->Zs.end());
+    c->d_Zd.upload(zd, s);
+    c->d_sh_exp.upload(c->sh_exp, s);
+    c->d_sh_coef.upload(c->sh_coef, s);
+    c->d_pairs.upload(c->pairs, s);
+    c->d_prim_owner.upload(c->prim_owner, s);
+    c->d_prims.resize(c->nprim_pairs);
+    c->d_Q.resize(c->pairs.size());
+    c->d_pair_ids.clear();
+    c->d_pair_ids.resize(kNumPairClasses);
+    for (int pc = 0; pc < kNumPairClasses; ++pc) c->d_pair_ids[pc].upload(c->pairs_by_class[pc], s);
+    // 1e task arrays: pairs grouped by pair class
+    std::vector<int> ta, tb;
+    c->task_first.assign(kNumPairClasses, 0);
+    c->task_count.assign(kNumPairClasses, 0);
+    for (int pc = 0; pc < kNumPairClasses; ++pc) {
+      c->task_first[pc] = (int)ta.size();
+      for (int pid : c->pairs_by_class[pc]) {
+        ta.push_back(c->pairs[pid].a);
+        tb.push_back(c->pairs[pid].b);
+      }
+      c->task_count[pc] = (int)ta.size() - c->task_first[pc];
+    }
+    c->d_task_a.upload(ta, s);
+    c->d_task_b.upload(tb, s);
+    std::vector<int> ones(n_inst, 1), zeros(n_inst, 0);
+    c->d_active.upload(ones, s);
+    c->d_all_active.upload(ones, s);
+    c->d_conv_iter.upload(zeros, s);
+    c->d_status.upload(zeros, s);
+    c->d_info.upload(zeros, s);
+    const size_t mt = (size_t)c->mtot;
+    for (DevBuf<double>* m : {&c->S, &c->T, &c->V, &c->H, &c->X, &c->F, &c->J, &c->K, &c->P,
+                              &c->Pnew, &c->W, &c->tmp1, &c->tmp2, &c->err, &c->Fbar, &c->C,
+                              &c->Cacc, &c->eig, &c->eigE})
+      m->resize(mt);
+    c->Fhist.resize(mt * 8);
+    c->Ehist.resize(mt * 8);
+    c->diisB.resize((size_t)n_inst * 64);
+    c->diisC.resize((size_t)n_inst * 8);
+    c->diis_count.resize(n_inst);
+    c->diis_head.resize(n_inst);
+    c->d_Enuc.resize(n_inst);
+    c->d_E.resize((size_t)n_inst * (1 + c->max_n));
+    c->d_Eprev.resize(n_inst);
+    c->d_emax.resize(n_inst);
+    c->d_grad.resize((size_t)tot * 3);
+    c->d_xyz.resize((size_t)tot * 3);
+    c->have_geom = false;
+    c->have_scf = false;
+    c->have_C = false;
+    c->work_tau = -1.0;
+    c->guess.reset_batch(c->ninst);
+    sync(c);
+  });
+}
+
+bscf_status bscf_set_geometries(bscf_ctx* c, const double* xyz) {
+  return guard([&] {
+    need(c && xyz, BSCF_E_INVALID, "NULL argument");
+    need(c->ninst > 0, BSCF_E_INVALID, "set instances first");
+    HIPCHK(hipSetDevice(c->device));
+    const double t0 = now_ms();
+    for (int k = 0; k < 3 * c->total_atoms; ++k)
+      need(std::isfinite(xyz[k]), BSCF_E_INVALID, "non-finite coordinate");
+    c->xyz.assign(xyz, xyz + 3 * c->total_atoms);
+    for (Shell& s : c->shells) {
+      s.x = xyz[3 * s.atom];
+      s.y = xyz[3 * s.atom + 1];
+      s.z = xyz[3 * s.atom + 2];
+    }
+    const hipStream_t st = c->stream;
+    c->d_shells.upload(c->shells, st);
+    c->d_xyz.upload(c->xyz, st);
+    PrimPairSetupArgs pa{c->nprim_pairs, c->d_prim_owner.p, c->d_pairs.p, c->d_shells.p,
+                         c->d_sh_exp.p, c->d_sh_coef.p, c->d_prims.p};
+    launch_prim_pairs(pa, st);
+    launch_nuclear(c->ninst, c->d_natoms.p, c->d_atom_off.p, c->d_xyz.p, c->d_Zd.p, c->d_Enuc.p,
+                   nullptr, 0, st);
+    // Schwarz bounds
+    for (int pc = 0; pc < kNumPairClasses; ++pc) {
+      if (c->pairs_by_class[pc].empty()) continue;
+      SchwarzArgs sa{c->d_pair_ids[pc].p, (int)c->pairs_by_class[pc].size(), c->d_pairs.p,
+                     c->d_prims.p, c->d_shells.p, c->d_boys64.p, c->d_Q.p};
+      const int la = pc == 0 ? 0 : (pc < 3 ? 1 : 2);
+      const int lb = pc - la * (la + 1) / 2;
+      schwarz_launcher(la, lb)(sa, st);
+    }
+    // one-electron matrices
+    launch_fill(c->V.p, c->mtot, 0.0, st);
+    for (int pc = 0; pc < kNumPairClasses; ++pc) {
+      if (c->task_count[pc] == 0) continue;
+      const int la = pc == 0 ? 0 : (pc < 3 ? 1 : 2);
+      const int lb = pc - la * (la + 1) / 2;
+      OneEArgs oa;
+      oa.atoms_per_task_stride = c->max_atoms;
+      oa.ntasks = c->task_count[pc] * c->max_atoms;
+      oa.task_a = c->d_task_a.p + c->task_first[pc];
+      oa.task_b = c->d_task_b.p + c->task_first[pc];
+      oa.shells = c->d_shells.p;
+      oa.sh_exp = c->d_sh_exp.p;
+      oa.sh_coef = c->d_sh_coef.p;
+      oa.natoms = c->d_natoms.p;
+      oa.atom_off = c->d_atom_off.p;
+      oa.atom_xyz = c->d_xyz.p;
+      oa.atom_Z = c->d_Zd.p;
+      oa.nbf = c->d_nbf.p;
+      oa.moff = c->d_moff.p;
+      oa.boys64 = c->d_boys64.p;
+      oa.S = c->S.p;
+      oa.T = c->T.p;
+      oa.V = c->V.p;
+      launch_onee(la, lb, oa, st);
+    }
+    HIPCHK(hipGetLastError());
+    // H = T + V
+    BatchInfo ball = c->batch(false);
+    launch_scale_copy(ball, c->max_n, c->T.p, c->H.p, 1.0, 0, st);
+    {
+      const double one = 1.0;
+      BLASCHK(rocblas_daxpy(c->blas, (int)c->mtot, &one, c->V.p, 1, c->H.p, 1));
+    }
+    build_orthogonaliser(c);
+    c->Q.resize(c->pairs.size());
+    HIPCHK(hipMemcpyAsync(c->Q.data(), c->d_Q.p, c->pairs.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+    sync(c);
+    c->work_tau = -1.0;
+    c->have_geom = true;
+    c->have_scf = false;
+    c->t_setup_ms += now_ms() - t0;
+  });
+}
+
+bscf_status bscf_build_jk(bscf_ctx* c, const double* P, double* J, double* K, double tau,
+                          int precision, int device_ptrs) {
+  return guard([&] {
+    need(c && P && J && K, BSCF_E_INVALID, "NULL argument");
+    require_geom(c);
+    HIPCHK(hipSetDevice(c->device));
+    const auto kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double), kind, c->stream));
+    fock_build(c, tau, precision, false);
+    // symmetrised J, K
+    BatchInfo b = c->batch(false);
+    launch_scale_copy(b, c->max_n, c->J.p, c->tmp1.p, 0.5, 1, c->stream);
+    launch_scale_copy(b, c->max_n, c->K.p, c->tmp2.p, 0.5, 1, c->stream);
+    const double half = 0.5;
+    BLASCHK(rocblas_daxpy(c->blas, (int)c->mtot, &half, c->J.p, 1, c->tmp1.p, 1));
+    BLASCHK(rocblas_daxpy(c->blas, (int)c->mtot, &half, c->K.p, 1, c->tmp2.p, 1));
+    const auto back = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPCHK(hipMemcpyAsync(J, c->tmp1.p, c->mtot * sizeof(double), back, c->stream));
+    HIPCHK(hipMemcpyAsync(K, c->tmp2.p, c->mtot * sizeof(double), back, c->stream));
+    sync(c);
+  });
+}
+
+bscf_status bscf_build_fock(bscf_ctx* c, const double* P, double* F, double* E, double tau,
+                            int precision, int device_ptrs) {
+  return guard([&] {
+    need(c && P && F, BSCF_E_INVALID, "NULL argument");
+    require_geom(c);
+    HIPCHK(hipSetDevice(c->device));
+    const auto kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double), kind, c->stream));
+    fock_build(c, tau, precision, false);
+    const auto back = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPCHK(hipMemcpyAsync(F, c->F.p, c->mtot * sizeof(double), back, c->stream));
+    if (E) HIPCHK(hipMemcpyAsync(E, c->d_E.p, c->ninst * sizeof(double), device_ptrs ? back : hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+  });
+}
+
+bscf_status bscf_set_density(bscf_ctx* c, const double* P, int device_ptrs) {
+  return guard([&] {
+    need(c && P, BSCF_E_INVALID, "NULL argument");
+    need(c->ninst > 0, BSCF_E_INVALID, "set instances first");
+    HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double),
+                          device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+    sync(c);
+  });
+}
+
+namespace {
+// out[o + j*no + i] = U[o + j*no + i] * w[o + j]^{-1/2}, no x no column-major blocks
+__global__ void scale_cols_occ_kernel(int ninst, const long long* moff, const int* nocc,
+                                      const double* U, const double* w, double* out) {
+  const int inst = blockIdx.y;
+  if (inst >= ninst) return;
+  const int no = nocc[inst];
+  const long long o = moff[inst], nn = (long long)no * no;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
+       k += (long long)gridDim.x * blockDim.x)
+    out[o + k] = U[o + k] / sqrt(w[o + k / no]);
+}
+
+// previous-step guess: C_occ' = C_occ (C_occ^T S C_occ)^{-1/2}, P = 2 C' C'^T
+void previous_guess(bscf_ctx* c) {
+  const double one = 1.0, zero = 0.0, two = 2.0;
+  for (const Group& g : c->groups) {
+    const long long o = c->moff[g.first];
+    const long long st = (long long)g.n * g.n;
+    const int n = g.n, no = c->nocc[g.first];
+    // tmp1 = S C_occ (n x no)
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none,
+                                          n, no, n, &one, c->S.p + o, n, st, c->Cacc.p + o, n, st,
+                                          &zero, c->tmp1.p + o, n, st, g.count));
+    // eig = C_occ^T S C_occ (no x no, leading dim no)
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose,
+                                          rocblas_operation_none, no, no, n, &one, c->Cacc.p + o,
+                                          n, st, c->tmp1.p + o, n, st, &zero, c->eig.p + o, no, st,
+                                          g.count));
+    BLASCHK(rocsolver_dsyevd_strided_batched(c->blas, rocblas_evect_original, rocblas_fill_upper,
+                                             no, c->eig.p + o, no, st, c->tmp2.p + o, st,
+                                             c->eigE.p + o, st, c->d_info.p + g.first, g.count));
+  }
+  const long long nn = (long long)c->max_n * c->max_n;
+  const unsigned gx = (unsigned)std::min<long long>((nn + 255) / 256, 1024);
+  hipLaunchKernelGGL(scale_cols_occ_kernel, dim3(gx, c->ninst), dim3(256), 0, c->stream, c->ninst,
+                     c->d_moff.p, c->d_nocc.p, c->eig.p, c->tmp2.p, c->err.p);
+  for (const Group& g : c->groups) {
+    const long long o = c->moff[g.first];
+    const long long st = (long long)g.n * g.n;
+    const int n = g.n, no = c->nocc[g.first];
+    // Minv = (U w^-1/2) U^T -> Fbar (no x no)
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none,
+                                          rocblas_operation_transpose, no, no, no, &one,
+                                          c->err.p + o, no, st, c->eig.p + o, no, st, &zero,
+                                          c->Fbar.p + o, no, st, g.count));
+    // C' = C_occ Minv (n x no) -> tmp1
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none,
+                                          n, no, no, &one, c->Cacc.p + o, n, st, c->Fbar.p + o, no,
+                                          st, &zero, c->tmp1.p + o, n, st, g.count));
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none,
+                                          rocblas_operation_transpose, n, n, no, &two,
+                                          c->tmp1.p + o, n, st, c->tmp1.p + o, n, st, &zero,
+                                          c->P.p + o, n, st, g.count));
+  }
+}
+
+__global__ void commit_C_kernel(BatchInfo b, const double* src, double* dst) {
+  const int inst = blockIdx.y;
+  if (!b.active[inst]) return;
+  const int n = b.nbf[inst];
+  const long long o = b.moff[inst], nn = (long long)n * n;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
+       k += (long long)gridDim.x * blockDim.x)
+    dst[o + k] = src[o + k];
+}
+}  // namespace
+
+bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int* n_iter,
+                         int* status) {
+  return guard([&] {
+    need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    require_geom(c);
+    HIPCHK(hipSetDevice(c->device));
+    bscf_scf_opts o;
+    bscf_default_opts(&o);
+    if (opts) o = *opts;
+    need(o.max_iter > 0 && o.diis_size >= 1 && o.diis_size <= 8, BSCF_E_INVALID, "bad options");
+    const double t0 = now_ms();
+    const hipStream_t st = c->stream;
+    const int ni = c->ninst;
+    std::vector<int> flags(ni, 1), stat(ni, 1), iters(ni, 0);
+    // guess
+    int guess = o.guess;
+    std::vector<int> fallback(ni, 0);
+    if (guess == BSCF_GUESS_PREVIOUS && !c->have_C) guess = BSCF_GUESS_CORE;
+    if (guess == BSCF_GUESS_LEARNED) {
+      if (!c->have_C || !c->guess.predict(c)) {
+        guess = c->have_C ? BSCF_GUESS_PREVIOUS : BSCF_GUESS_CORE;
+        std::fill(fallback.begin(), fallback.end(), 4);
+      }
+    }
+    if (guess == BSCF_GUESS_CORE) {
+      c->d_active.upload(flags, st);
+      density_from_fock(c, c->H.p, c->P.p);
+      commit_C_kernel<<<dim3(1024, ni), 256, 0, st>>>(c->batch(true), c->C.p, c->Cacc.p);
+    } else if (guess == BSCF_GUESS_PREVIOUS) {
+      previous_guess(c);
+    }
+    // (BSCF_GUESS_USER: P already set; LEARNED: P written by predict)
+    c->d_active.upload(flags, st);
+    c->d_status.upload(stat, st);
+    std::vector<int> zeros(ni, 0);
+    c->diis_count.upload(zeros, st);
+    c->diis_head.upload(zeros, st);
+    c->d_conv_iter.upload(zeros, st);
+    launch_fill(c->diisB.p, (long long)ni * 64, 0.0, st);
+    DiisArgs d;
+    d.ninst = ni;
+    d.max_vec = o.diis_size;
+    d.nbf = c->d_nbf.p;
+    d.moff = c->d_moff.p;
+    d.active = c->d_active.p;
+    d.stride = c->mtot;
+    d.Fhist = c->Fhist.p;
+    d.Ehist = c->Ehist.p;
+    d.B = c->diisB.p;
+    d.count = c->diis_count.p;
+    d.head = c->diis_head.p;
+    d.coef = c->diisC.p;
+    BatchInfo bm = c->batch(true);
+    int it = 0;
+    for (; it < o.max_iter; ++it) {
+      fock_build(c, o.schwarz_tol, o.precision, true);
+      // M = F P S, e = X (M - M^T) X
+      gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->F.p, c->P.p, 0.0,
+           c->tmp1.p);
+      gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->tmp1.p, c->S.p,
+           0.0, c->tmp2.p);
+      launch_antisym(c->batch(false), c->max_n, c->tmp2.p, c->tmp1.p, c->d_emax.p, st);
+      gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->X.p, c->tmp1.p,
+           0.0, c->tmp2.p);
+      gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->tmp2.p, c->X.p,
+           0.0, c->err.p);
+      launch_convergence(ni, c->d_E.p, c->d_Eprev.p, c->d_emax.p, o.e_tol, o.comm_tol, it,
+                         c->d_active.p, c->d_conv_iter.p, c->d_status.p, st);
+      HIPCHK(hipMemcpyAsync(flags.data(), c->d_active.p, ni * sizeof(int), hipMemcpyDeviceToHost, st));
+      sync(c);
+      c->scf_iters++;
+      bool any = false;
+      for (int i = 0; i < ni; ++i) any |= flags[i] != 0;
+      if (!any) break;
+      launch_diis_store(d, c->max_n, c->F.p, c->err.p, st);
+      launch_diis_extrapolate(d, c->max_n, c->Fbar.p, st);
+      density_from_fock(c, c->Fbar.p, c->Pnew.p);
+      launch_commit(bm, c->max_n, c->Pnew.p, c->P.p, st);
+      commit_C_kernel<<<dim3(1024, ni), 256, 0, st>>>(bm, c->C.p, c->Cacc.p);
+    }
+    std::vector<double> e(ni);
+    HIPCHK(hipMemcpyAsync(e.data(), c->d_E.p, ni * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(stat.data(), c->d_status.p, ni * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(iters.data(), c->d_conv_iter.p, ni * sizeof(int), hipMemcpyDeviceToHost, st));
+    sync(c);
+    for (int i = 0; i < ni; ++i) {
+      if (iters[i] == 0) iters[i] = it < o.max_iter ? it + 1 : o.max_iter;
+      stat[i] |= fallback[i];
+    }
+    if (E) std::copy(e.begin(), e.end(), E);
+    if (n_iter) std::copy(iters.begin(), iters.end(), n_iter);
+    if (status) std::copy(stat.begin(), stat.end(), status);
+    c->last_iters = iters;
+    c->have_C = true;
+    c->have_scf = true;
+    c->guess.record(c);
+    c->t_scf_ms += now_ms() - t0;
+  });
+}
+
+bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
+  return guard([&] {
+    need(c && Fout, BSCF_E_INVALID, "NULL argument");
+    need(c->have_scf, BSCF_E_STATE, "forces need an SCF at the current geometry");
+    HIPCHK(hipSetDevice(c->device));
+    const double t0 = now_ms();
+    const hipStream_t st = c->stream;
+    // W = P F P / 2
+    gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->P.p, c->F.p, 0.0,
+         c->tmp1.p);
+    gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 0.5, c->tmp1.p, c->P.p, 0.0,
+         c->W.p);
+    launch_fill(c->d_grad.p, 3LL * c->total_atoms, 0.0, st);
+    launch_nuclear(c->ninst, c->d_natoms.p, c->d_atom_off.p, c->d_xyz.p, c->d_Zd.p, c->d_Enuc.p,
+                   c->d_grad.p, 1, st);
+    for (int pc = 0; pc < kNumPairClasses; ++pc) {
+      if (c->task_count[pc] == 0) continue;
+      const int la = pc == 0 ? 0 : (pc < 3 ? 1 : 2);
+      const int lb = pc - la * (la + 1) / 2;
+      Grad1EArgs g;
+      g.atoms_per_task_stride = c->max_atoms;
+      g.ntasks = c->task_count[pc] * c->max_atoms;
+      g.task_a = c->d_task_a.p + c->task_first[pc];
+      g.task_b = c->d_task_b.p + c->task_first[pc];
+      g.shells = c->d_shells.p;
+      g.sh_exp = c->d_sh_exp.p;
+      g.sh_coef = c->d_sh_coef.p;
+      g.natoms = c->d_natoms.p;
+      g.atom_off = c->d_atom_off.p;
+      g.atom_xyz = c->d_xyz.p;
+      g.atom_Z = c->d_Zd.p;
+      g.nbf = c->d_nbf.p;
+      g.moff = c->d_moff.p;
+      g.boys64 = c->d_boys64.p;
+      g.P = c->P.p;
+      g.W = c->W.p;
+      g.active = c->d_all_active.p;
+      g.grad = c->d_grad.p;
+      launch_grad1e(la, lb, g, st);
+    }
+    // two-electron part over the same screened work lists
+    GradArgs ga;
+    ga.pairs = c->d_pairs.p;
+    ga.prims = c->d_prims.p;
+    ga.shells = c->d_shells.p;
+    ga.kets = c->d_kets.p;
+    ga.moff = c->d_moff.p;
+    ga.nbf = c->d_nbf.p;
+    ga.P = c->P.p;
+    ga.grad = c->d_grad.p;
+    ga.boys64 = c->d_boys64.p;
+    for (int q = 0; q < kNumQuartetClasses; ++q) {
+      auto& W = c->work[q];
+      if (W.items.empty()) continue;
+      ga.items = W.d_items.p;
+      ga.nitems = (int)W.items.size();
+      grad_launcher(q)(ga, st);
+    }
+    HIPCHK(hipGetLastError());
+    std::vector<double> g(3 * c->total_atoms);
+    HIPCHK(hipMemcpyAsync(g.data(), c->d_grad.p, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(c);
+    for (size_t k = 0; k < g.size(); ++k) Fout[k] = -g[k];
+    c->t_grad_ms += now_ms() - t0;
+  });
+}
+
+bscf_status bscf_get_density(bscf_ctx* c, int inst, double* P, int device_ptr) {
+  return guard([&] {
+    need(c && P && inst >= 0 && inst < c->ninst, BSCF_E_INVALID, "bad arguments");
+    const size_t nn = (size_t)c->nbf[inst] * c->nbf[inst];
+    HIPCHK(hipMemcpyAsync(P, c->P.p + c->moff[inst], nn * sizeof(double),
+                          device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+  });
+}
+
+bscf_status bscf_get_one_electron(bscf_ctx* c, int inst, double* S, double* H) {
+  return guard([&] {
+    need(c && inst >= 0 && inst < c->ninst, BSCF_E_INVALID, "bad arguments");
+    require_geom(c);
+    const size_t nn = (size_t)c->nbf[inst] * c->nbf[inst];
+    if (S) HIPCHK(hipMemcpyAsync(S, c->S.p + c->moff[inst], nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (H) HIPCHK(hipMemcpyAsync(H, c->H.p + c->moff[inst], nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+  });
+}
+
+bscf_status bscf_eri_tensor(bscf_ctx* c, int inst, double* out) {
+  return guard([&] {
+    need(c && out && inst >= 0 && inst < c->ninst, BSCF_E_INVALID, "bad arguments");
+    require_geom(c);
+    const int n = c->nbf[inst];
+    need(n <= 64, BSCF_E_INVALID, "eri_tensor is limited to n <= 64");
+    const size_t n4 = (size_t)n * n * n * n;
+    DevBuf<double> d_out;
+    d_out.resize(n4);
+    launch_fill(d_out.p, (long long)n4, 0.0, c->stream);
+    const QuartetClass* qc = quartet_classes();
+    for (int q = 0; q < kNumQuartetClasses; ++q) {
+      const int X = pclass(qc[q].la, qc[q].lb), Y = pclass(qc[q].lc, qc[q].ld);
+      std::vector<int> quart;
+      std::vector<int> bl, kl;
+      for (int pid : c->pairs_by_class[X])
+        if (c->shells[c->pairs[pid].a].inst == inst) bl.push_back(pid);
+      for (int pid : c->pairs_by_class[Y])
+        if (c->shells[c->pairs[pid].a].inst == inst) kl.push_back(pid);
+      for (int b : bl)
+        for (int k : kl) {
+          if (X == Y && k > b) continue;
+          quart.push_back(b);
+          quart.push_back(k);
+        }
+      if (quart.empty()) continue;
+      DevBuf<int> dq;
+      dq.upload(quart, c->stream);
+      TensorArgs ta{dq.p, (int)quart.size() / 2, c->d_pairs.p, c->d_prims.p, c->d_shells.p,
+                    c->d_boys64.p, n, d_out.p};
+      qc[q].tensor(ta, c->stream);
+      sync(c);
+    }
+    HIPCHK(hipMemcpyAsync(out, d_out.p, n4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+  });
+}
+
+bscf_status bscf_schwarz(bscf_ctx* c, int inst, double* Qout, int nsh) {
+  return guard([&] {
+    need(c && Qout && inst >= 0 && inst < c->ninst, BSCF_E_INVALID, "bad arguments");
+    require_geom(c);
+    need(nsh == c->nshell[inst], BSCF_E_INVALID, "nsh does not match the instance");
+    const int s0 = c->shell_off[inst];
+    for (size_t p = 0; p < c->pairs.size(); ++p) {
+      const ShellPair& sp = c->pairs[p];
+      if (c->shells[sp.a].inst != inst) continue;
+      const int a = sp.a - s0, b = sp.b - s0;
+      Qout[a * nsh + b] = Qout[b * nsh + a] = c->Q[p];
+    }
+  });
+}
+
+bscf_status bscf_instance_info(bscf_ctx* c, int inst, int* nbf, int* nshell, int* natom) {
+  return guard([&] {
+    need(c && inst >= 0 && inst < c->ninst, BSCF_E_INVALID, "bad arguments");
+    if (nbf) *nbf = c->nbf[inst];
+    if (nshell) *nshell = c->nshell[inst];
+    if (natom) *natom = c->natoms[inst];
+  });
+}
+
+bscf_status bscf_work_counts(bscf_ctx* c, double* nq, double* npq, double* flops) {
+  return guard([&] {
+    need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    require_geom(c);
+    if (c->work_tau < 0) build_work(c, 1e-12);
+    const QuartetClass* qc = quartet_classes();
+    double a = 0, b = 0, f = 0;
+    for (int q = 0; q < kNumQuartetClasses; ++q) {
+      a += c->work[q].nquart;
+      b += c->work[q].nprimq;
+      const int L = qc[q].la + qc[q].lb + qc[q].lc + qc[q].ld;
+      (void)L;
+      const int nout = ncart(qc[q].la) * ncart(qc[q].lb) * ncart(qc[q].lc) * ncart(qc[q].ld);
+      // per primitive quartet: VRR (+ the Boys evaluation counted in the table)
+      // per contracted quartet: HRR + digestion (6 FMAs = 12 FLOP per integral)
+      f += c->work[q].nprimq * qc[q].vrr_flops + c->work[q].nquart * (qc[q].hrr_flops + 12.0 * nout);
+    }
+    if (nq) *nq = a;
+    if (npq) *npq = b;
+    if (flops) *flops = f;
+  });
+}
+
+bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
+  return guard([&] {
+    need(c && buf && len > 0, BSCF_E_INVALID, "bad arguments");
+    std::ostringstream s;
+    s << "{\"fock_builds\": " << c->fock_builds << ", \"scf_iterations\": " << c->scf_iters
+      << ", \"t_fock_ms\": " << c->t_fock_ms << ", \"t_scf_ms\": " << c->t_scf_ms
+      << ", \"t_grad_ms\": " << c->t_grad_ms << ", \"t_setup_ms\": " << c->t_setup_ms
+      << ", \"classes\": {";
+    const QuartetClass* qc = quartet_classes();
+    for (int q = 0; q < kNumQuartetClasses; ++q) {
+      s << (q ? ", " : "") << "\"" << qc[q].la << qc[q].lb << qc[q].lc << qc[q].ld << "\": ["
+        << c->work[q].nquart << ", " << c->work[q].nprimq << ", " << c->work[q].items.size() << "]";
+    }
+    s << "}}";
+    const std::string str = s.str();
+    need((int)str.size() < len, BSCF_E_INVALID, "buffer too small");
+    memcpy(buf, str.c_str(), str.size() + 1);
+  });
+}
+
+double bscf_boys_table_entry(int m, int k) {
+  static std::vector<double> tab;
+  if (tab.empty()) {
+    tab.resize(kBoysRows * kBoysCols);
+    boys_table_host(tab.data());
+  }
+  if (m < 0 || m >= kBoysCols || k < 0 || k >= kBoysRows) return NAN;
+  return tab[k * kBoysCols + m];
+}
+
+bscf_status bscf_boys(bscf_ctx* c, int m_max, int n, const double* T, double* out, int precision) {
+  return guard([&] {
+    need(c && T && out && n > 0 && m_max >= 0 && m_max <= 12, BSCF_E_INVALID, "bad arguments");
+    DevBuf<double> dT, dO;
+    std::vector<double> t(T, T + n);
+    dT.upload(t, c->stream);
+    dO.resize((size_t)n * (m_max + 1));
+    launch_boys_eval(m_max, n, dT.p, dO.p, precision, c->d_boys64.p, c->d_boys32.p, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, dO.p, (size_t)n * (m_max + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+  });
+}
+
+bscf_status bscf_guess_train(bscf_ctx* c, int n_adam_steps, float* loss) {
+  return guard([&] {
+    need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    float l = c->guess.train(c, n_adam_steps);
+    if (loss) *loss = l;
+  });
+}
+
+bscf_status bscf_guess_save(bscf_ctx* c, const char* path) {
+  return guard([&] {
+    need(c && path, BSCF_E_INVALID, "NULL argument");
+    c->guess.save(path);
+  });
+}
+
+bscf_status bscf_guess_load(bscf_ctx* c, const char* path) {
+  return guard([&] {
+    need(c && path, BSCF_E_INVALID, "NULL argument");
+    c->guess.load(path);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,312 @@
+// Per-class kernels of the direct-SCF Fock build.
+//
+// One wavefront owns one WorkItem: a bra shell pair and up to 64*k ket shell
+// pairs of one angular class and one primitive count.  Each lane evaluates one
+// contracted shell quartet (Obara-Saika VRR over the primitive quartets,
+// contraction, HRR; generated per class), then digests it into J and K:
+//   J_mn += f_J (mn|ls) P_ls,   J_ls += f_J (mn|ls) P_mn,
+//   K_ml += f_K (mn|ls) P_ns,   K_ms += f_K (mn|ls) P_nl,
+//   K_nl += f_K (mn|ls) P_ms,   K_ns += f_K (mn|ls) P_ml,
+// with f_J = g/2, f_K = g/4 and g the number of distinct permutations of the
+// shell quartet (1, 2, 4 or 8); J and K are symmetrised afterwards.  Together
+// this reproduces J_mn = sum (mn|ls) P_ls and K_ml = sum (mn|ls) P_ns over all
+// ordered index quartets.  Bra contributions to J are reduced across the
+// wavefront before one atomic add per element; the others use FP64 atomics.
+#pragma once
+#include "boys.h"
+#include "common.h"
+
+namespace bscf {
+
+struct FockArgs {
+  const WorkItem* items;
+  int nitems;
+  const ShellPair* pairs;
+  const PrimPair* prims;
+  const Shell* shells;
+  const int* kets;
+  const long long* moff;   // matrix offset per instance
+  const int* nbf;          // basis size per instance
+  const double* P;
+  double* J;
+  double* K;
+  const double* boys64;
+  const float* boys32;
+  const int* active;       // per instance: nonzero while its SCF runs
+};
+
+struct SchwarzArgs {
+  const int* pair_ids;     // pairs of one class
+  int npairs;
+  const ShellPair* pairs;
+  const PrimPair* prims;
+  const Shell* shells;
+  const double* boys64;
+  double* Q;               // per pair
+};
+
+struct TensorArgs {        // full ERI tensor of one instance (test path)
+  const int* quartets;     // (bra, ket) pair indices, canonical
+  int nquart;
+  const ShellPair* pairs;
+  const PrimPair* prims;
+  const Shell* shells;
+  const double* boys64;
+  int n;
+  double* out;             // n^4
+};
+
+// Contracted (ab|cd) block of class CL for one quartet, in type R.  Classes
+// with total angular momentum >= 6 keep one out-of-line copy shared by all
+// kernels of the class (bounded code size and compile time).
+template <class CL, typename R>
+__device__ __forceinline__ void eri_block_body(const PrimPair* __restrict__ bp, int nb,
+                                          const PrimPair* __restrict__ kp, int nk,
+                                          const double AB[3], const double CD[3],
+                                          const double* __restrict__ tab64,
+                                          const float* __restrict__ tab32, R* out) {
+  constexpr int L = CL::LA + CL::LB + CL::LC + CL::LD;
+  R acc[CL::NACC];
+#pragma unroll
+  for (int k = 0; k < CL::NACC; ++k) acc[k] = R(0);
+  for (int i = 0; i < nb; ++i) {
+    const PrimPair B = bp[i];
+    for (int j = 0; j < nk; ++j) {
+      const PrimPair Q = kp[j];
+      const double pq = B.p + Q.p;
+      const double rpq = rsqrt(pq);
+      const double oopq = rpq * rpq;
+      const double rho = B.p * Q.p * oopq;
+      const double PQx = B.Px - Q.Px, PQy = B.Py - Q.Py, PQz = B.Pz - Q.Pz;
+      const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+      const double pref = B.C * Q.C * rpq;
+      R F[L + 1];
+      if constexpr (sizeof(R) == 8) {
+        boys_f64<L>(T, pref, tab64, reinterpret_cast<double*>(F));
+      } else {
+        boys_f32<L>(T, pref, tab32, reinterpret_cast<float*>(F));
+      }
+      if constexpr (L == 0) {
+        acc[0] += F[0];
+      } else {
+        const double qf = Q.p * oopq, pf = B.p * oopq;
+        CL::template vrr<R>(F, R(B.PAx), R(B.PAy), R(B.PAz), R(-qf * PQx), R(-qf * PQy),
+                            R(-qf * PQz), R(Q.PAx), R(Q.PAy), R(Q.PAz), R(pf * PQx),
+                            R(pf * PQy), R(pf * PQz), R(B.oo2p), R(Q.oo2p), R(0.5 * oopq),
+                            R(B.oo2p * qf), R(Q.oo2p * pf), R(1), acc);
+      }
+    }
+  }
+  CL::template hrr<R>(acc, R(AB[0]), R(AB[1]), R(AB[2]), R(CD[0]), R(CD[1]), R(CD[2]), out);
+}
+
+template <class CL, typename R>
+__device__ __noinline__ void eri_block_outline(const PrimPair* __restrict__ bp, int nb,
+                                               const PrimPair* __restrict__ kp, int nk,
+                                               const double* AB, const double* CD,
+                                               const double* __restrict__ tab64,
+                                               const float* __restrict__ tab32, R* out) {
+  eri_block_body<CL, R>(bp, nb, kp, nk, AB, CD, tab64, tab32, out);
+}
+
+template <class CL, typename R>
+__device__ __forceinline__ void eri_block(const PrimPair* __restrict__ bp, int nb,
+                                          const PrimPair* __restrict__ kp, int nk,
+                                          const double AB[3], const double CD[3],
+                                          const double* __restrict__ tab64,
+                                          const float* __restrict__ tab32, R* out) {
+  if constexpr (CL::LA + CL::LB + CL::LC + CL::LD >= 6) {
+    eri_block_outline<CL, R>(bp, nb, kp, nk, AB, CD, tab64, tab32, out);
+  } else {
+    eri_block_body<CL, R>(bp, nb, kp, nk, AB, CD, tab64, tab32, out);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+template <class CL, typename R>
+__global__ __launch_bounds__(256) void fock_kernel(FockArgs a) {
+  constexpr int NA = ncart(CL::LA), NB = ncart(CL::LB), NC = ncart(CL::LC), ND = ncart(CL::LD);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int item_id = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  if (item_id >= a.nitems) return;
+  const WorkItem it = a.items[item_id];
+  const ShellPair bra = a.pairs[it.bra];
+  const Shell sa = a.shells[bra.a], sb = a.shells[bra.b];
+  const int inst = sa.inst;
+  if (!a.active[inst]) return;
+  const long long mo = a.moff[inst];
+  const int n = a.nbf[inst];
+  const double* __restrict__ P = a.P + mo;
+  double* J = a.J + mo;
+  double* K = a.K + mo;
+  const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
+  const int m0 = sa.bf, n0 = sb.bf;
+  double Pab[NA][NB];
+#pragma unroll
+  for (int i = 0; i < NA; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) Pab[i][j] = P[(m0 + i) * n + n0 + j];
+  double jbra[NA][NB];
+#pragma unroll
+  for (int i = 0; i < NA; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) jbra[i][j] = 0.0;
+  const double gab = (bra.a == bra.b) ? 1.0 : 2.0;
+
+  for (int base = 0; base < it.nket; base += kWave) {
+    const bool valid = base + lane < it.nket;
+    const int kid = a.kets[it.ket0 + (valid ? base + lane : 0)];
+    const ShellPair ket = a.pairs[kid];
+    const Shell sc = a.shells[ket.a], sd = a.shells[ket.b];
+    const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
+    R v[CL::NOUT];
+    eri_block<CL, R>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
+                     a.boys64, a.boys32, v);
+    const double g = gab * ((ket.a == ket.b) ? 1.0 : 2.0) * ((kid == it.bra) ? 1.0 : 2.0);
+    const double fj = valid ? 0.5 * g : 0.0;
+    const double fk = 0.5 * fj;
+    const int l0 = sc.bf, s0 = sd.bf;
+    double Pcd[NC][ND], Pac[NA][NC], Pad[NA][ND], Pbc[NB][NC], Pbd[NB][ND];
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+      for (int l = 0; l < ND; ++l) Pcd[k][l] = P[(l0 + k) * n + s0 + l];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) Pac[i][k] = P[(m0 + i) * n + l0 + k];
+#pragma unroll
+      for (int l = 0; l < ND; ++l) Pad[i][l] = P[(m0 + i) * n + s0 + l];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) Pbc[j][k] = P[(n0 + j) * n + l0 + k];
+#pragma unroll
+      for (int l = 0; l < ND; ++l) Pbd[j][l] = P[(n0 + j) * n + s0 + l];
+    }
+    double jket[NC][ND], kac[NA][NC], kad[NA][ND], kbc[NB][NC], kbd[NB][ND];
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+      for (int l = 0; l < ND; ++l) jket[k][l] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) kac[i][k] = 0.0;
+#pragma unroll
+      for (int l = 0; l < ND; ++l) kad[i][l] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) kbc[j][k] = 0.0;
+#pragma unroll
+      for (int l = 0; l < ND; ++l) kbd[j][l] = 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        double jb = 0.0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+          for (int l = 0; l < ND; ++l) {
+            const double x = double(v[((i * NB + j) * NC + k) * ND + l]);
+            jb = fma(x, Pcd[k][l], jb);
+            jket[k][l] = fma(x, Pab[i][j], jket[k][l]);
+            kac[i][k] = fma(x, Pbd[j][l], kac[i][k]);
+            kad[i][l] = fma(x, Pbc[j][k], kad[i][l]);
+            kbc[j][k] = fma(x, Pad[i][l], kbc[j][k]);
+            kbd[j][l] = fma(x, Pac[i][k], kbd[j][l]);
+          }
+        jbra[i][j] = fma(fj, jb, jbra[i][j]);
+      }
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k)
+#pragma unroll
+        for (int l = 0; l < ND; ++l) atomicAdd(&J[(l0 + k) * n + s0 + l], fj * jket[k][l]);
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) atomicAdd(&K[(m0 + i) * n + l0 + k], fk * kac[i][k]);
+#pragma unroll
+        for (int l = 0; l < ND; ++l) atomicAdd(&K[(m0 + i) * n + s0 + l], fk * kad[i][l]);
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) atomicAdd(&K[(n0 + j) * n + l0 + k], fk * kbc[j][k]);
+#pragma unroll
+        for (int l = 0; l < ND; ++l) atomicAdd(&K[(n0 + j) * n + s0 + l], fk * kbd[j][l]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NA; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const double s = wave_sum(jbra[i][j]);
+      if (lane == 0) atomicAdd(&J[(m0 + i) * n + n0 + j], s);
+    }
+}
+
+// Q for each pair of class (LA LB|LA LB): sqrt(max |(mn|mn)|).
+template <class CL>
+__global__ __launch_bounds__(256) void schwarz_kernel(SchwarzArgs a) {
+  constexpr int NA = ncart(CL::LA), NB = ncart(CL::LB);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.npairs) return;
+  const int pid = a.pair_ids[t];
+  const ShellPair pr = a.pairs[pid];
+  const Shell sa = a.shells[pr.a], sb = a.shells[pr.b];
+  const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
+  double v[CL::NOUT];
+  eri_block<CL, double>(a.prims + pr.prim0, pr.nprim, a.prims + pr.prim0, pr.nprim, AB, AB,
+                        a.boys64, nullptr, v);
+  double m = 0.0;
+#pragma unroll
+  for (int i = 0; i < NA; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) m = fmax(m, fabs(v[(i * NB + j) * NA * NB + i * NB + j]));
+  a.Q[pid] = sqrt(m);
+}
+
+// Full tensor (test path): every canonical quartet writes its 8 permutations.
+template <class CL>
+__global__ __launch_bounds__(64) void tensor_kernel(TensorArgs a) {
+  constexpr int NA = ncart(CL::LA), NB = ncart(CL::LB), NC = ncart(CL::LC), ND = ncart(CL::LD);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.nquart) return;
+  const ShellPair bra = a.pairs[a.quartets[2 * t]], ket = a.pairs[a.quartets[2 * t + 1]];
+  const Shell sa = a.shells[bra.a], sb = a.shells[bra.b], sc = a.shells[ket.a],
+              sd = a.shells[ket.b];
+  const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
+  const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
+  double v[CL::NOUT];
+  eri_block<CL, double>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
+                        a.boys64, nullptr, v);
+  const long long n = a.n;
+  for (int i = 0; i < NA; ++i)
+    for (int j = 0; j < NB; ++j)
+      for (int k = 0; k < NC; ++k)
+        for (int l = 0; l < ND; ++l) {
+          const double x = v[((i * NB + j) * NC + k) * ND + l];
+          const long long m = sa.bf + i, nn = sb.bf + j, la = sc.bf + k, s = sd.bf + l;
+          const long long idx[8][4] = {{m, nn, la, s}, {nn, m, la, s}, {m, nn, s, la},
+                                       {nn, m, s, la}, {la, s, m, nn}, {s, la, m, nn},
+                                       {la, s, nn, m}, {s, la, nn, m}};
+          for (int q = 0; q < 8; ++q)
+            a.out[((idx[q][0] * n + idx[q][1]) * n + idx[q][2]) * n + idx[q][3]] = x;
+        }
+}
+
+}  // namespace bscf

@@ -1,0 +1,116 @@
+// Argument blocks and host launchers of the non-class kernels.
+#pragma once
+#include "common.h"
+
+namespace bscf {
+
+struct PrimPairSetupArgs {
+  int nprim;
+  const int* prim_pair_owner;  // shell-pair index of each primitive pair
+  const ShellPair* pairs;
+  const Shell* shells;
+  const double* sh_exp;        // per shell primitive: exponent
+  const double* sh_coef;       // per shell primitive: normalised contraction coefficient
+  PrimPair* prims;
+};
+
+struct OneEArgs {
+  int ntasks;                  // pairs * atoms_per_task_stride
+  int atoms_per_task_stride;   // max atoms per instance
+  const int* task_a;
+  const int* task_b;
+  const Shell* shells;
+  const double* sh_exp;
+  const double* sh_coef;
+  const int* natoms;
+  const int* atom_off;
+  const double* atom_xyz;
+  const double* atom_Z;
+  const int* nbf;
+  const long long* moff;
+  const double* boys64;
+  double* S;
+  double* T;
+  double* V;
+};
+
+struct Grad1EArgs {
+  int ntasks;
+  int atoms_per_task_stride;
+  const int* task_a;
+  const int* task_b;
+  const Shell* shells;
+  const double* sh_exp;
+  const double* sh_coef;
+  const int* natoms;
+  const int* atom_off;
+  const double* atom_xyz;
+  const double* atom_Z;
+  const int* nbf;
+  const long long* moff;
+  const double* boys64;
+  const double* P;
+  const double* W;
+  const int* active;
+  double* grad;                // [total atoms][3]
+};
+
+void launch_prim_pairs(const PrimPairSetupArgs& a, hipStream_t s);
+void launch_onee(int la, int lb, const OneEArgs& a, hipStream_t s);
+void launch_grad1e(int la, int lb, const Grad1EArgs& a, hipStream_t s);
+
+// ---- dense per-instance helpers (scf.hip) ----
+struct BatchInfo {
+  int ninst;
+  const int* nbf;
+  const long long* moff;
+  const int* active;
+};
+
+void launch_fill(double* p, long long n, double v, hipStream_t s);
+// F = H + (J + J^T)/2 - (K + K^T)/4 ; E[i] = Tr[P(H+F)]/2 + Enuc[i]
+void launch_fock_assemble(const BatchInfo& b, int max_n, const double* H, const double* J,
+                          const double* K, const double* P, const double* Enuc, double* F,
+                          double* E, hipStream_t s);
+// out = A - A^T per instance, emax[i] = max |out| (emax zeroed here)
+void launch_antisym(const BatchInfo& b, int max_n, const double* A, double* out, double* emax,
+                    hipStream_t s);
+// DIIS: store F, e in slot; update B row; solve; Fbar = sum c F
+struct DiisArgs {
+  int ninst;
+  int max_vec;
+  const int* nbf;
+  const long long* moff;
+  const int* active;
+  long long stride;      // per-slot stride of the history buffers (total matrix size)
+  double* Fhist;         // [max_vec][mtot]
+  double* Ehist;
+  double* B;             // [ninst][max_vec][max_vec]
+  int* count;            // per instance number of stored vectors
+  int* head;             // per instance next slot
+  double* coef;          // [ninst][max_vec]
+};
+void launch_diis_store(const DiisArgs& d, int max_n, const double* F, const double* e,
+                       hipStream_t s);
+void launch_diis_extrapolate(const DiisArgs& d, int max_n, double* Fbar, hipStream_t s);
+// convergence flags: conv[i] = |E - Eprev| < etol && emax < ctol (only active)
+void launch_convergence(int ninst, const double* E, double* Eprev, const double* emax,
+                        double etol, double ctol, int iter, int* active, int* conv_iter,
+                        int* status, hipStream_t s);
+// P_new -> P for active instances
+void launch_commit(const BatchInfo& b, int max_n, const double* Pnew, double* P, hipStream_t s);
+// nuclear repulsion energy and gradient per instance
+void launch_nuclear(int ninst, const int* natoms, const int* atom_off, const double* xyz,
+                    const double* Z, double* Enuc, double* grad, int want_grad, hipStream_t s);
+// dst = alpha * src (or its transpose) per instance (all instances if active is NULL)
+void launch_scale_copy(const BatchInfo& b, int max_n, const double* src, double* dst,
+                       double alpha, int transpose, hipStream_t s);
+
+// out[i*(m_max+1)+m] = F_m(T[i]) by the device Boys function (FP64 or FP32 body)
+void launch_boys_eval(int m_max, int n, const double* T, double* out, int fp32,
+                      const double* tab64, const float* tab32, hipStream_t s);
+
+// Boys table on the host (Gauss-Legendre quadrature of the defining integral)
+void boys_table_host(double* tab /* kBoysRows * kBoysCols */);
+
+}  // namespace bscf

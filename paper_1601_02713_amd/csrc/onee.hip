@@ -1,0 +1,409 @@
+// One-electron integrals (S, T, V) and their nuclear derivatives, plus the
+// per-geometry primitive-pair setup.
+//
+// Overlap: one-dimensional Obara-Saika recurrences
+//   S_{i+1,j} = X_PA S_ij + (i S_{i-1,j} + j S_{i,j-1}) / (2p),
+//   S_{i,j+1} = X_PB S_ij + (i S_{i-1,j} + j S_{i,j-1}) / (2p),
+//   S_00 = sqrt(pi/p) exp(-mu X_AB^2).
+// Kinetic: -1/2 <a|d^2/dx^2|b> per direction from overlaps with the ket power
+// shifted by -2, 0, +2.  Nuclear attraction: Obara-Saika two-index
+// recurrence on [a|b]^(m) with [0|0]^(m) = 2 pi/p K_AB F_m(p |PC|^2).
+// Centre derivatives: d/dA_i g_a = 2 alpha g_{a+1_i} - a_i g_{a-1_i}; the
+// operator-centre derivative of V follows from translational invariance,
+// d/dC = -(d/dA + d/dB).
+#include "boys.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace bscf {
+
+namespace {
+
+__device__ __forceinline__ void comp(int l, int c, int& lx, int& ly, int& lz) {
+  int n = 0;
+  for (int x = l; x >= 0; --x)
+    for (int y = l - x; y >= 0; --y) {
+      if (n == c) { lx = x; ly = y; lz = l - x - y; return; }
+      ++n;
+    }
+}
+
+// index of tuple t among all tuples with |t| <= its shell, ordered by |t| then
+// lexicographically
+__device__ __forceinline__ int tidx(int lx, int ly, int lz) {
+  const int l = lx + ly + lz;
+  const int u = l - lx;
+  return l * (l + 1) * (l + 2) / 6 + u * (u + 1) / 2 + (u - ly);
+}
+
+__device__ __forceinline__ double comp_factor(int lx, int ly, int lz) {
+  // 1 / sqrt((2lx-1)!! (2ly-1)!! (2lz-1)!!)
+  double d = 1.0;
+  for (int k = 2 * lx - 1; k > 1; k -= 2) d *= k;
+  for (int k = 2 * ly - 1; k > 1; k -= 2) d *= k;
+  for (int k = 2 * lz - 1; k > 1; k -= 2) d *= k;
+  return 1.0 / sqrt(d);
+}
+
+constexpr int kMaxL1 = 3;           // shell l after one raise
+constexpr int kS1 = kMaxL1 + 4;     // 1-D overlap index range
+
+struct OS1D {
+  double S[3][kS1][kS1];
+};
+
+__device__ void overlap_1d(double a, double b, const double* A, const double* B, int imax,
+                           int jmax, OS1D& o) {
+  const double p = a + b, oo2p = 0.5 / p, mu = a * b / p;
+  for (int d = 0; d < 3; ++d) {
+    const double P = (a * A[d] + b * B[d]) / p;
+    const double XPA = P - A[d], XPB = P - B[d], XAB = A[d] - B[d];
+    double(*S)[kS1] = o.S[d];
+    S[0][0] = sqrt(M_PI / p) * exp(-mu * XAB * XAB);
+    for (int i = 0; i <= imax; ++i) {
+      if (i > 0) S[i][0] = XPA * S[i - 1][0] + (i > 1 ? (i - 1) * oo2p * S[i - 2][0] : 0.0);
+      for (int j = 1; j <= jmax; ++j)
+        S[i][j] = XPB * S[i][j - 1] + oo2p * ((i > 0 ? i * S[i - 1][j - 1] : 0.0) +
+                                              (j > 1 ? (j - 1) * S[i][j - 2] : 0.0));
+    }
+  }
+}
+
+__device__ __forceinline__ double ov3(const OS1D& o, const int* ta, const int* tb) {
+  for (int d = 0; d < 3; ++d)
+    if (ta[d] < 0 || tb[d] < 0) return 0.0;
+  return o.S[0][ta[0]][tb[0]] * o.S[1][ta[1]][tb[1]] * o.S[2][ta[2]][tb[2]];
+}
+
+__device__ double kin3(const OS1D& o, const int* ta, const int* tb, double b) {
+  if (ta[0] < 0 || ta[1] < 0 || ta[2] < 0 || tb[0] < 0 || tb[1] < 0 || tb[2] < 0) return 0.0;
+  double t = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const int j = tb[d];
+    int tp[3] = {tb[0], tb[1], tb[2]}, tm[3] = {tb[0], tb[1], tb[2]};
+    tp[d] += 2;
+    tm[d] -= 2;
+    t += 4.0 * b * b * ov3(o, ta, tp) - 2.0 * b * (2 * j + 1) * ov3(o, ta, tb) +
+         (j > 1 ? j * (j - 1) * ov3(o, ta, tm) : 0.0);
+  }
+  return -0.5 * t;
+}
+
+__host__ __device__ constexpr int ntup(int l) { return (l + 1) * (l + 2) * (l + 3) / 6; }
+
+// [a|1/r_C|b] for all tuples |a| <= LA, |b| <= LB (primitive, positive sign)
+template <int LA, int LB>
+struct NucTab {
+  double v[LA + LB + 1][ntup(LA)][ntup(LB)];
+};
+
+template <int LA, int LB>
+__device__ void nuc_table(double a, double b, const double* A, const double* B, const double* C,
+                          const double* boys64, NucTab<LA, LB>& t) {
+  constexpr int la = LA, lb = LB;
+  const double p = a + b, oo2p = 0.5 / p, mu = a * b / p;
+  double P[3], PA[3], PB[3], PC[3], AB2 = 0.0, PC2 = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    P[d] = (a * A[d] + b * B[d]) / p;
+    PA[d] = P[d] - A[d];
+    PB[d] = P[d] - B[d];
+    PC[d] = P[d] - C[d];
+    AB2 += (A[d] - B[d]) * (A[d] - B[d]);
+    PC2 += PC[d] * PC[d];
+  }
+  constexpr int L = LA + LB;
+  double F[L + 1];
+  const double pref = 2.0 * M_PI / p * exp(-mu * AB2);
+  boys_f64<L>(p * PC2, pref, boys64, F);
+  for (int tot = 0; tot <= L; ++tot)
+    for (int na = 0; na <= min(la, tot); ++na) {
+      const int nb = tot - na;
+      if (nb > lb) continue;
+      for (int ca = 0; ca < ncart(na); ++ca)
+        for (int cb = 0; cb < ncart(nb); ++cb) {
+          int ta[3], tb[3];
+          comp(na, ca, ta[0], ta[1], ta[2]);
+          comp(nb, cb, tb[0], tb[1], tb[2]);
+          const int ia = tidx(ta[0], ta[1], ta[2]), ib = tidx(tb[0], tb[1], tb[2]);
+          for (int m = 0; m <= L - tot; ++m) {
+            double r;
+            if (tot == 0) {
+              r = F[m];
+            } else if (nb > 0) {
+              const int i = tb[0] > 0 ? 0 : (tb[1] > 0 ? 1 : 2);
+              int b1[3] = {tb[0], tb[1], tb[2]};
+              b1[i] -= 1;
+              const int j1 = tidx(b1[0], b1[1], b1[2]);
+              r = PB[i] * t.v[m][ia][j1] - PC[i] * t.v[m + 1][ia][j1];
+              if (ta[i] > 0) {
+                int a1[3] = {ta[0], ta[1], ta[2]};
+                a1[i] -= 1;
+                const int i1 = tidx(a1[0], a1[1], a1[2]);
+                r += ta[i] * oo2p * (t.v[m][i1][j1] - t.v[m + 1][i1][j1]);
+              }
+              if (b1[i] > 0) {
+                int b2[3] = {b1[0], b1[1], b1[2]};
+                b2[i] -= 1;
+                const int j2 = tidx(b2[0], b2[1], b2[2]);
+                r += b1[i] * oo2p * (t.v[m][ia][j2] - t.v[m + 1][ia][j2]);
+              }
+            } else {
+              const int i = ta[0] > 0 ? 0 : (ta[1] > 0 ? 1 : 2);
+              int a1[3] = {ta[0], ta[1], ta[2]};
+              a1[i] -= 1;
+              const int i1 = tidx(a1[0], a1[1], a1[2]);
+              r = PA[i] * t.v[m][i1][ib] - PC[i] * t.v[m + 1][i1][ib];
+              if (a1[i] > 0) {
+                int a2[3] = {a1[0], a1[1], a1[2]};
+                a2[i] -= 1;
+                const int i2 = tidx(a2[0], a2[1], a2[2]);
+                r += a1[i] * oo2p * (t.v[m][i2][ib] - t.v[m + 1][i2][ib]);
+              }
+            }
+            t.v[m][ia][ib] = r;
+          }
+        }
+    }
+}
+
+template <int LA, int LB>
+__device__ __forceinline__ double nuc_get(const NucTab<LA, LB>& t, const int* ta, const int* tb) {
+  for (int d = 0; d < 3; ++d)
+    if (ta[d] < 0 || tb[d] < 0) return 0.0;
+  if (ta[0] + ta[1] + ta[2] > LA || tb[0] + tb[1] + tb[2] > LB) return 0.0;
+  return t.v[0][tidx(ta[0], ta[1], ta[2])][tidx(tb[0], tb[1], tb[2])];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Primitive-pair data: one thread per primitive pair.
+__global__ void prim_pair_kernel(PrimPairSetupArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.nprim) return;
+  const int pid = a.prim_pair_owner[t];
+  const ShellPair sp = a.pairs[pid];
+  const int k = t - sp.prim0;
+  const Shell sa = a.shells[sp.a], sb = a.shells[sp.b];
+  const int ka = k / sb.nprim, kb = k % sb.nprim;
+  const double al = a.sh_exp[sa.prim0 + ka], be = a.sh_exp[sb.prim0 + kb];
+  const double ca = a.sh_coef[sa.prim0 + ka], cb = a.sh_coef[sb.prim0 + kb];
+  const double p = al + be;
+  const double Px = (al * sa.x + be * sb.x) / p, Py = (al * sa.y + be * sb.y) / p,
+               Pz = (al * sa.z + be * sb.z) / p;
+  const double dx = sa.x - sb.x, dy = sa.y - sb.y, dz = sa.z - sb.z;
+  const double K = exp(-al * be / p * (dx * dx + dy * dy + dz * dz));
+  PrimPair o;
+  o.p = p;
+  o.Px = Px; o.Py = Py; o.Pz = Pz;
+  o.PAx = Px - sa.x; o.PAy = Py - sa.y; o.PAz = Pz - sa.z;
+  // sqrt(2) * pi^(5/4)
+  o.C = 5.9149671727956128778 * ca * cb * K / p;
+  o.oo2p = 0.5 / p;
+  o.alpha = al;
+  o.beta = be;
+  o.pad = 0.0;
+  a.prims[t] = o;
+}
+
+// ---------------------------------------------------------------------------
+// S, T, V: one thread per (shell pair a >= b of one instance) x nucleus chunk.
+// V is accumulated with atomics over nuclei; S and T are written by the
+// thread handling nucleus 0.  Output is the normalised-component basis.
+template <int LA, int LB>
+__global__ void onee_kernel(OneEArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.ntasks) return;
+  const int pidx = t / a.atoms_per_task_stride;
+  const int cidx = t % a.atoms_per_task_stride;
+  const int sh_a = a.task_a[pidx], sh_b = a.task_b[pidx];
+  const Shell sa = a.shells[sh_a], sb = a.shells[sh_b];
+  const int inst = sa.inst;
+  const int nat = a.natoms[inst];
+  if (cidx >= nat) return;
+  const int n = a.nbf[inst];
+  const long long mo = a.moff[inst];
+  const int atom = a.atom_off[inst] + cidx;
+  const double A[3] = {sa.x, sa.y, sa.z}, B[3] = {sb.x, sb.y, sb.z};
+  const double Cc[3] = {a.atom_xyz[3 * atom], a.atom_xyz[3 * atom + 1], a.atom_xyz[3 * atom + 2]};
+  const double Zc = a.atom_Z[atom];
+  const int na = ncart(sa.l), nb = ncart(sb.l);
+  double Sb[6][6], Tb[6][6], Vb[6][6];
+  for (int i = 0; i < na; ++i)
+    for (int j = 0; j < nb; ++j) Sb[i][j] = Tb[i][j] = Vb[i][j] = 0.0;
+  NucTab<LA, LB> nt;
+  OS1D o;
+  for (int ka = 0; ka < sa.nprim; ++ka)
+    for (int kb = 0; kb < sb.nprim; ++kb) {
+      const double al = a.sh_exp[sa.prim0 + ka], be = a.sh_exp[sb.prim0 + kb];
+      const double cc = a.sh_coef[sa.prim0 + ka] * a.sh_coef[sb.prim0 + kb];
+      nuc_table<LA, LB>(al, be, A, B, Cc, a.boys64, nt);
+      if (cidx == 0) overlap_1d(al, be, A, B, sa.l, sb.l + 2, o);
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) {
+          int ta[3], tb[3];
+          comp(sa.l, i, ta[0], ta[1], ta[2]);
+          comp(sb.l, j, tb[0], tb[1], tb[2]);
+          Vb[i][j] -= Zc * cc * nuc_get(nt, ta, tb);
+          if (cidx == 0) {
+            Sb[i][j] += cc * ov3(o, ta, tb);
+            Tb[i][j] += cc * kin3(o, ta, tb, be);
+          }
+        }
+    }
+  for (int i = 0; i < na; ++i)
+    for (int j = 0; j < nb; ++j) {
+      int ta[3], tb[3];
+      comp(sa.l, i, ta[0], ta[1], ta[2]);
+      comp(sb.l, j, tb[0], tb[1], tb[2]);
+      const double f = comp_factor(ta[0], ta[1], ta[2]) * comp_factor(tb[0], tb[1], tb[2]);
+      const long long ij = mo + (long long)(sa.bf + i) * n + sb.bf + j;
+      const long long ji = mo + (long long)(sb.bf + j) * n + sa.bf + i;
+      atomicAdd(&a.V[ij], f * Vb[i][j]);
+      if (sh_a != sh_b) atomicAdd(&a.V[ji], f * Vb[i][j]);
+      if (cidx == 0) {
+        a.S[ij] = f * Sb[i][j];
+        a.S[ji] = f * Sb[i][j];
+        a.T[ij] = f * Tb[i][j];
+        a.T[ji] = f * Tb[i][j];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One-electron gradient: sum P dH/dX - sum W dS/dX per atom; one thread per
+// (ordered pair a >= b) x nucleus, off-diagonal pairs counted twice.
+template <int LA, int LB>
+__global__ void grad1e_kernel(Grad1EArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.ntasks) return;
+  const int pidx = t / a.atoms_per_task_stride;
+  const int cidx = t % a.atoms_per_task_stride;
+  const int sh_a = a.task_a[pidx], sh_b = a.task_b[pidx];
+  const Shell sa = a.shells[sh_a], sb = a.shells[sh_b];
+  const int inst = sa.inst;
+  const int nat = a.natoms[inst];
+  if (cidx >= nat) return;
+  if (!a.active[inst]) return;
+  const int n = a.nbf[inst];
+  const long long mo = a.moff[inst];
+  const int atom = a.atom_off[inst] + cidx;
+  const double A[3] = {sa.x, sa.y, sa.z}, B[3] = {sb.x, sb.y, sb.z};
+  const double Cc[3] = {a.atom_xyz[3 * atom], a.atom_xyz[3 * atom + 1], a.atom_xyz[3 * atom + 2]};
+  const double Zc = a.atom_Z[atom];
+  const int na = ncart(sa.l), nb = ncart(sb.l);
+  const double sym = (sh_a == sh_b) ? 1.0 : 2.0;
+  double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0}, gC[3] = {0, 0, 0};
+  NucTab<LA + 1, LB + 1> nt;
+  OS1D o;
+  for (int ka = 0; ka < sa.nprim; ++ka)
+    for (int kb = 0; kb < sb.nprim; ++kb) {
+      const double al = a.sh_exp[sa.prim0 + ka], be = a.sh_exp[sb.prim0 + kb];
+      const double cc = a.sh_coef[sa.prim0 + ka] * a.sh_coef[sb.prim0 + kb];
+      nuc_table<LA + 1, LB + 1>(al, be, A, B, Cc, a.boys64, nt);
+      if (cidx == 0) overlap_1d(al, be, A, B, sa.l + 1, sb.l + 3, o);
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) {
+          int ta[3], tb[3];
+          comp(sa.l, i, ta[0], ta[1], ta[2]);
+          comp(sb.l, j, tb[0], tb[1], tb[2]);
+          const double f = cc * comp_factor(ta[0], ta[1], ta[2]) * comp_factor(tb[0], tb[1], tb[2]);
+          const long long ij = mo + (long long)(sa.bf + i) * n + sb.bf + j;
+          const double pij = sym * f * a.P[ij], wij = sym * f * a.W[ij];
+          for (int d = 0; d < 3; ++d) {
+            int up[3] = {ta[0], ta[1], ta[2]}, dn[3] = {ta[0], ta[1], ta[2]};
+            up[d] += 1;
+            dn[d] -= 1;
+            int upb[3] = {tb[0], tb[1], tb[2]}, dnb[3] = {tb[0], tb[1], tb[2]};
+            upb[d] += 1;
+            dnb[d] -= 1;
+            // nuclear attraction of this nucleus, basis-centre derivatives
+            const double vA = -Zc * (2 * al * nuc_get(nt, up, tb) - ta[d] * nuc_get(nt, dn, tb));
+            const double vB = -Zc * (2 * be * nuc_get(nt, ta, upb) - tb[d] * nuc_get(nt, ta, dnb));
+            gA[d] += pij * vA;
+            gB[d] += pij * vB;
+            gC[d] -= pij * (vA + vB);
+            if (cidx == 0) {
+              const double sA = 2 * al * ov3(o, up, tb) - ta[d] * ov3(o, dn, tb);
+              const double sB = 2 * be * ov3(o, ta, upb) - tb[d] * ov3(o, ta, dnb);
+              const double kA = 2 * al * kin3(o, up, tb, be) - ta[d] * kin3(o, dn, tb, be);
+              const double kB = 2 * be * kin3(o, ta, upb, be) - tb[d] * kin3(o, ta, dnb, be);
+              gA[d] += pij * kA - wij * sA;
+              gB[d] += pij * kB - wij * sB;
+            }
+          }
+        }
+    }
+  for (int d = 0; d < 3; ++d) {
+    atomicAdd(&a.grad[3 * sa.atom + d], gA[d]);
+    atomicAdd(&a.grad[3 * sb.atom + d], gB[d]);
+    atomicAdd(&a.grad[3 * atom + d], gC[d]);
+  }
+}
+
+void launch_onee(int la, int lb, const OneEArgs& a, hipStream_t s) {
+  if (a.ntasks == 0) return;
+  const dim3 g((a.ntasks + 127) / 128), b(128);
+#define BSCF_ONEE(X, Y) \
+  if (la == X && lb == Y) { hipLaunchKernelGGL((onee_kernel<X, Y>), g, b, 0, s, a); return; }
+  BSCF_ONEE(0, 0) BSCF_ONEE(1, 0) BSCF_ONEE(1, 1) BSCF_ONEE(2, 0) BSCF_ONEE(2, 1) BSCF_ONEE(2, 2)
+#undef BSCF_ONEE
+}
+
+void launch_grad1e(int la, int lb, const Grad1EArgs& a, hipStream_t s) {
+  if (a.ntasks == 0) return;
+  const dim3 g((a.ntasks + 127) / 128), b(128);
+#define BSCF_G1(X, Y) \
+  if (la == X && lb == Y) { hipLaunchKernelGGL((grad1e_kernel<X, Y>), g, b, 0, s, a); return; }
+  BSCF_G1(0, 0) BSCF_G1(1, 0) BSCF_G1(1, 1) BSCF_G1(2, 0) BSCF_G1(2, 1) BSCF_G1(2, 2)
+#undef BSCF_G1
+}
+
+namespace {
+template <int M>
+__device__ void boys_eval_one(double T, int fp32, const double* t64, const float* t32, double* o) {
+  if (fp32) {
+    float F[M + 1];
+    boys_f32<M>(T, 1.0, t32, F);
+    for (int m = 0; m <= M; ++m) o[m] = F[m];
+  } else {
+    double F[M + 1];
+    boys_f64<M>(T, 1.0, t64, F);
+    for (int m = 0; m <= M; ++m) o[m] = F[m];
+  }
+}
+__global__ void boys_eval_kernel(int m_max, int n, const double* T, double* out, int fp32,
+                                 const double* t64, const float* t32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double* o = out + (long long)i * (m_max + 1);
+  switch (m_max) {
+    case 0: boys_eval_one<0>(T[i], fp32, t64, t32, o); break;
+    case 1: boys_eval_one<1>(T[i], fp32, t64, t32, o); break;
+    case 2: boys_eval_one<2>(T[i], fp32, t64, t32, o); break;
+    case 3: boys_eval_one<3>(T[i], fp32, t64, t32, o); break;
+    case 4: boys_eval_one<4>(T[i], fp32, t64, t32, o); break;
+    case 5: boys_eval_one<5>(T[i], fp32, t64, t32, o); break;
+    case 6: boys_eval_one<6>(T[i], fp32, t64, t32, o); break;
+    case 7: boys_eval_one<7>(T[i], fp32, t64, t32, o); break;
+    case 8: boys_eval_one<8>(T[i], fp32, t64, t32, o); break;
+    case 9: boys_eval_one<9>(T[i], fp32, t64, t32, o); break;
+    case 10: boys_eval_one<10>(T[i], fp32, t64, t32, o); break;
+    case 11: boys_eval_one<11>(T[i], fp32, t64, t32, o); break;
+    default: boys_eval_one<12>(T[i], fp32, t64, t32, o); break;
+  }
+}
+}  // namespace
+
+void launch_boys_eval(int m_max, int n, const double* T, double* out, int fp32,
+                      const double* tab64, const float* tab32, hipStream_t s) {
+  hipLaunchKernelGGL(boys_eval_kernel, dim3((n + 127) / 128), dim3(128), 0, s, m_max, n, T, out,
+                     fp32, tab64, tab32);
+}
+
+void launch_prim_pairs(const PrimPairSetupArgs& a, hipStream_t s) {
+  if (a.nprim == 0) return;
+  hipLaunchKernelGGL(prim_pair_kernel, dim3((a.nprim + 255) / 256), dim3(256), 0, s, a);
+}
+
+}  // namespace bscf

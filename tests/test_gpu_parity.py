@@ -1,0 +1,139 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Layered: Boys function (against mpmath) -> full ERI tensors -> one-electron
+matrices and Schwarz bounds -> J/K at fixed densities (screened and
+unscreened, batched instances of different sizes) -> converged SCF energies.
+Tolerances follow from FP64 rounding of the quantities compared.
+"""
+
+import mpmath
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def beadscf():
+    from paper_1601_02713_amd import beadscf as b
+    return b
+
+
+@pytest.fixture(scope="module")
+def eng(beadscf):
+    e = beadscf.Engine(0)
+    yield e
+    e.close()
+
+
+def _setup(eng, basis_name, instances):
+    eng.load_basis(inputs.load_basis(basis_name))
+    eng.set_instances([z for z, _ in instances])
+    eng.set_geometries([x for _, x in instances])
+
+
+def _rand_density(n, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    return 0.05 * (A + A.T)
+
+
+def test_device_boys_against_mpmath(eng):
+    mpmath.mp.dps = 40
+    T = np.concatenate([[0.0, 1e-10, 0.04999, 0.05001, 39.95, 39.9999, 40.0, 40.0001, 55.0, 300.0],
+                        np.random.default_rng(1).uniform(0, 45, 200)])
+    F64 = eng.boys(12, T, 0)
+    F32 = eng.boys(12, T, 1)
+    for i, t in enumerate(T):
+        for m in range(13):
+            tt = mpmath.mpf(float(t))
+            ref = float(mpmath.mpf(1) / (2 * m + 1) if tt == 0 else
+                        mpmath.gammainc(m + mpmath.mpf(1) / 2, 0, tt) / (2 * tt ** (m + mpmath.mpf(1) / 2)))
+            assert abs(F64[i, m] - ref) <= 2e-14 * ref, (t, m, F64[i, m], ref)
+            assert abs(F32[i, m] - ref) <= 2e-6 * ref, (t, m, F32[i, m], ref)
+
+
+@pytest.mark.parametrize("case,basis", [("h2o_sto3g", "sto-3g"), ("h2o_sto3g", "6-31g*")])
+def test_eri_tensor(eng, case, basis):
+    inst = inputs.workload(case)["instances"]
+    _setup(eng, basis, inst)
+    b = oracle.build_basis(inputs.load_basis(basis), *inst[0])
+    ref = oracle.eri_tensor(b)
+    got = eng.eri_tensor(0)
+    assert np.abs(got - ref).max() < 1e-13
+
+
+def test_one_electron_and_schwarz(eng, b631gs):
+    inst = inputs.workload("w2")["instances"]
+    _setup(eng, "6-31g*", inst)
+    b = oracle.build_basis(b631gs, *inst[0])
+    S, T, V = oracle.one_electron(b)
+    Sg, Hg = eng.one_electron(0)
+    assert np.abs(Sg - S).max() < 1e-13
+    assert np.abs(Hg - (T + V)).max() < 1e-12
+    Q = oracle.schwarz(b)
+    Qg = eng.schwarz(0)
+    assert np.allclose(Qg, Q, rtol=1e-12, atol=1e-300)
+
+
+@pytest.mark.parametrize("tau", [0.0, 1e-12])
+def test_jk_fixed_density(eng, b631gs, tau):
+    inst = inputs.workload("w2")["instances"]
+    _setup(eng, "6-31g*", inst)
+    b = oracle.build_basis(b631gs, *inst[0])
+    P = _rand_density(b["nbf"], 4)
+    J, K, _ = oracle.jk(b, P, tau=tau)
+    Jg, Kg = eng.build_jk([P], schwarz_tol=tau)
+    assert np.abs(Jg[0] - J).max() < 1e-11
+    assert np.abs(Kg[0] - K).max() < 1e-11
+
+
+def test_jk_batched_uneven(eng, b631gs):
+    """Instances of 1, 3 and 2 waters in one batch, each against the oracle."""
+    inst = []
+    for nw in (1, 3, 2):
+        inst += inputs.workload(f"w{nw}")["instances"]
+    _setup(eng, "6-31g*", inst)
+    Ps = []
+    for i, (z, x) in enumerate(inst):
+        n = oracle.build_basis(b631gs, z, x)["nbf"]
+        Ps.append(_rand_density(n, 10 + i))
+    Jg, Kg = eng.build_jk(Ps)
+    Fg, Eg = eng.build_fock(Ps)
+    for i, (z, x) in enumerate(inst):
+        b = oracle.build_basis(b631gs, z, x)
+        J, K, _ = oracle.jk(b, Ps[i])
+        assert np.abs(Jg[i] - J).max() < 1e-11
+        assert np.abs(Kg[i] - K).max() < 1e-11
+        S, T, V = oracle.one_electron(b)
+        F, E = oracle.fock_energy(b, T + V, Ps[i])
+        assert np.abs(Fg[i] - F).max() < 1e-11
+        assert abs(Eg[i] - E) < 1e-10
+
+
+def test_scf_h2o_sto3g(eng, sto3g):
+    w = inputs.workload("h2o_sto3g")
+    _setup(eng, "sto-3g", w["instances"])
+    b = oracle.build_basis(sto3g, *w["instances"][0])
+    r = oracle.scf(b, 1e-11, 1e-9)
+    E, it, st = eng.run_scf(e_tol=1e-11, comm_tol=1e-9)
+    assert st[0] == 0
+    assert abs(E[0] - r["E"]) < 1e-10
+    assert np.abs(eng.density(0) - r["P"]).max() < 1e-7
+
+
+def test_scf_batched_beads(eng, b631gs):
+    """Four (H2O)2 beads in one batch: each equals its own oracle SCF."""
+    z, x = inputs.water_cluster(2, 7)
+    bx = inputs.beads(z, x, 4, 7)
+    inst = [(z, bx[k]) for k in range(4)]
+    _setup(eng, "6-31g*", inst)
+    E, it, st = eng.run_scf(e_tol=1e-10, comm_tol=1e-8)
+    assert (st == 0).all()
+    for k in range(4):
+        b = oracle.build_basis(b631gs, *inst[k])
+        r = oracle.scf(b, 1e-10, 1e-8)
+        assert abs(E[k] - r["E"]) < 1e-8
