@@ -144,7 +144,17 @@ bscf_status bscf_instance_info(bscf_ctx* ctx, int inst, int* nbf, int* nshell, i
 bscf_status bscf_work_counts(bscf_ctx* ctx, double* n_quartets, double* n_prim_quartets,
                              double* flops);
 
-/* Statistics as a JSON object (quartets per class, timings of the last calls). */
+/* Kernel profiling: with on != 0 every Fock-build class kernel is bracketed by
+ * HIP events on the context's stream; per-class times appear in the stats. */
+bscf_status bscf_set_profiling(bscf_ctx* ctx, int on);
+/* Zero the accumulated counters and timers reported by bscf_get_stats. */
+bscf_status bscf_reset_stats(bscf_ctx* ctx);
+
+/* Statistics as a JSON object: per quartet class the screened quartet and
+ * primitive-quartet counts of the current work lists, the counts and
+ * algorithmic FLOPs evaluated since the last reset (active instances only) and
+ * the measured kernel time; totals of Fock builds, SCF iterations and phase
+ * timers (ms). */
 bscf_status bscf_get_stats(bscf_ctx* ctx, char* buf, int len);
 
 /* Evaluate the device Boys function: out[i*(m_max+1)+m] = F_m(T[i]) for n

@@ -56,6 +56,8 @@ _SIGS = {
     "bscf_instance_info": [_vp, _i, _vp, _vp, _vp],
     "bscf_work_counts": [_vp, _vp, _vp, _vp],
     "bscf_get_stats": [_vp, ctypes.c_char_p, _i],
+    "bscf_set_profiling": [_vp, _i],
+    "bscf_reset_stats": [_vp],
     "bscf_boys": [_vp, _i, _i, _vp, _vp, _i],
     "bscf_guess_train": [_vp, _i, _vp],
     "bscf_guess_save": [_vp, ctypes.c_char_p],
@@ -217,6 +219,12 @@ class Engine:
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _chk(_lib.bscf_work_counts(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
+
+    def set_profiling(self, on=True):
+        _chk(_lib.bscf_set_profiling(self._h, 1 if on else 0))
+
+    def reset_stats(self):
+        _chk(_lib.bscf_reset_stats(self._h))
 
     def stats(self):
         buf = ctypes.create_string_buffer(1 << 16)

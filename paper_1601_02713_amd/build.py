@@ -10,6 +10,7 @@ from __future__ import annotations
 import concurrent.futures as cf
 import glob
 import os
+import re
 import subprocess
 import sys
 
@@ -33,17 +34,31 @@ def _sources():
     return srcs
 
 
-def _newest_header():
-    hs = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(GEN, "*.h")) + \
-        [os.path.join(os.path.dirname(HERE), "include", "beadscf.h")]
-    return max(os.path.getmtime(h) for h in hs)
+_INC = re.compile(r'^\s*#\s*include\s*"([^"]+)"', re.M)
 
 
-def _compile(src, force, hdr_time):
+def _deps_mtime(path, seen=None):
+    """Newest mtime of a file and of every quoted include it pulls in."""
+    seen = set() if seen is None else seen
+    if path in seen or not os.path.exists(path):
+        return 0.0
+    seen.add(path)
+    t = os.path.getmtime(path)
+    with open(path, errors="replace") as f:
+        text = f.read()
+    for inc in _INC.findall(text):
+        for d in (os.path.dirname(path), CSRC, GEN):
+            cand = os.path.normpath(os.path.join(d, inc))
+            if os.path.exists(cand):
+                t = max(t, _deps_mtime(cand, seen))
+                break
+    return t
+
+
+def _compile(src, force, hdr_time=None):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
     if not force and os.path.exists(obj):
-        t = os.path.getmtime(obj)
-        if t > os.path.getmtime(src) and t > hdr_time:
+        if os.path.getmtime(obj) > _deps_mtime(src):
             return obj, None
     cmd = ["hipcc"] + HIPFLAGS + ["-x", "hip", "-c", src, "-o", obj + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -59,12 +74,11 @@ def build(force: bool = False, jobs: int | None = None, verbose: bool = True) ->
     stamp = os.path.join(GEN, "classes.h")
     if force or not os.path.exists(stamp) or os.path.getmtime(stamp) < os.path.getmtime(gen_script):
         subprocess.check_call([sys.executable, gen_script, GEN])
-    hdr_time = _newest_header()
     srcs = _sources()
     jobs = jobs or min(16, os.cpu_count() or 4)
     objs, errs = [], []
     with cf.ThreadPoolExecutor(jobs) as ex:
-        for obj, err in ex.map(lambda s: _compile(s, force, hdr_time), srcs):
+        for obj, err in ex.map(lambda s: _compile(s, force), srcs):
             objs.append(obj)
             if err:
                 errs.append(err)

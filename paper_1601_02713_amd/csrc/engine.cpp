@@ -243,6 +243,11 @@ struct bscf_ctx {
     std::vector<WorkItem> items;
     DevBuf<WorkItem> d_items;
     double nquart = 0, nprimq = 0;
+    std::vector<double> inst_quart, inst_primq;  // per instance
+    // evaluated so far (active instances only) and measured kernel time
+    double done_quart = 0, done_primq = 0, kernel_ms = 0;
+    long launches = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
   };
   ClassWork work[kNumQuartetClasses];
   std::vector<int> kets;
@@ -268,6 +273,8 @@ struct bscf_ctx {
   DevBuf<double> Fhist, Ehist, diisB, diisC;
   DevBuf<int> diis_count, diis_head, d_info;
   bool have_C = false;
+  std::vector<int> h_active;   // host copy of the active flags
+  bool profiling = false;
 
   // stats
   double t_fock_ms = 0, t_scf_ms = 0, t_grad_ms = 0, t_setup_ms = 0;
@@ -501,6 +508,8 @@ void build_work(bscf_ctx* c, double tau) {
     W.nquart = 0;
     W.nprimq = 0;
     const int X = pclass(qc[q].la, qc[q].lb), Y = pclass(qc[q].lc, qc[q].ld);
+    W.inst_quart.assign(c->ninst, 0.0);
+    W.inst_primq.assign(c->ninst, 0.0);
     struct Tmp {
       WorkItem w;
       double cost;
@@ -538,6 +547,8 @@ void build_work(bscf_ctx* c, double tau) {
               tmp.push_back({w, double(nk) * bs.nprim * ks.nprim});
               W.nquart += nk;
               W.nprimq += double(nk) * bs.nprim * ks.nprim;
+              W.inst_quart[i] += nk;
+              W.inst_primq[i] += double(nk) * bs.nprim * ks.nprim;
             }
           }
         }
@@ -575,9 +586,33 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
     if (W.items.empty()) continue;
     a.items = W.d_items.p;
     a.nitems = (int)W.items.size();
+    if (c->profiling) {
+      if (!W.ev0) {
+        HIPCHK(hipEventCreate(&W.ev0));
+        HIPCHK(hipEventCreate(&W.ev1));
+      }
+      HIPCHK(hipEventRecord(W.ev0, c->stream));
+    }
     qc[q].fock(a, precision == BSCF_MIXED ? 1 : 0, c->stream);
+    if (c->profiling) HIPCHK(hipEventRecord(W.ev1, c->stream));
+    for (int i = 0; i < c->ninst; ++i)
+      if (!masked || c->h_active[i]) {
+        W.done_quart += W.inst_quart[i];
+        W.done_primq += W.inst_primq[i];
+      }
+    W.launches++;
   }
   HIPCHK(hipGetLastError());
+  if (c->profiling) {
+    sync(c);
+    for (int q = 0; q < kNumQuartetClasses; ++q) {
+      auto& W = c->work[q];
+      if (W.items.empty()) continue;
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, W.ev0, W.ev1));
+      W.kernel_ms += ms;
+    }
+  }
   BatchInfo b = c->batch(false);
   launch_fock_assemble(b, c->max_n, c->H.p, c->J.p, c->K.p, c->P.p, c->d_Enuc.p, c->F.p, c->d_E.p,
                        c->stream);
@@ -642,6 +677,10 @@ bscf_status bscf_destroy(bscf_ctx* c) {
   if (!c) return BSCF_OK;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  for (auto& W : c->work) {
+    if (W.ev0) (void)hipEventDestroy(W.ev0);
+    if (W.ev1) (void)hipEventDestroy(W.ev1);
+  }
   if (c->blas) rocblas_destroy_handle(c->blas);
   hipStream_t s = c->stream;
   bool own = c->own_stream;
@@ -1009,6 +1048,7 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     const hipStream_t st = c->stream;
     const int ni = c->ninst;
     std::vector<int> flags(ni, 1), stat(ni, 1), iters(ni, 0);
+    c->h_active.assign(ni, 1);
     // guess
     int guess = o.guess;
     std::vector<int> fallback(ni, 0);
@@ -1066,6 +1106,7 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
       HIPCHK(hipMemcpyAsync(flags.data(), c->d_active.p, ni * sizeof(int), hipMemcpyDeviceToHost, st));
       sync(c);
       c->scf_iters++;
+      c->h_active = flags;
       bool any = false;
       for (int i = 0; i < ni; ++i) any |= flags[i] != 0;
       if (!any) break;
@@ -1258,13 +1299,34 @@ bscf_status bscf_work_counts(bscf_ctx* c, double* nq, double* npq, double* flops
       const int L = qc[q].la + qc[q].lb + qc[q].lc + qc[q].ld;
       (void)L;
       const int nout = ncart(qc[q].la) * ncart(qc[q].lb) * ncart(qc[q].lc) * ncart(qc[q].ld);
-      // per primitive quartet: VRR (+ the Boys evaluation counted in the table)
+      // per primitive quartet: VRR plus setup and Boys (60 + 4L FLOP);
       // per contracted quartet: HRR + digestion (6 FMAs = 12 FLOP per integral)
-      f += c->work[q].nprimq * qc[q].vrr_flops + c->work[q].nquart * (qc[q].hrr_flops + 12.0 * nout);
+      const double boys = 60.0 + 4.0 * (qc[q].la + qc[q].lb + qc[q].lc + qc[q].ld);
+      f += c->work[q].nprimq * (qc[q].vrr_flops + boys) +
+           c->work[q].nquart * (qc[q].hrr_flops + 12.0 * nout);
     }
     if (nq) *nq = a;
     if (npq) *npq = b;
     if (flops) *flops = f;
+  });
+}
+
+bscf_status bscf_set_profiling(bscf_ctx* c, int on) {
+  return guard([&] {
+    need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    c->profiling = on != 0;
+  });
+}
+
+bscf_status bscf_reset_stats(bscf_ctx* c) {
+  return guard([&] {
+    need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    for (auto& W : c->work) {
+      W.done_quart = W.done_primq = W.kernel_ms = 0;
+      W.launches = 0;
+    }
+    c->t_fock_ms = c->t_scf_ms = c->t_grad_ms = c->t_setup_ms = 0;
+    c->fock_builds = c->scf_iters = 0;
   });
 }
 
@@ -1278,8 +1340,16 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
       << ", \"classes\": {";
     const QuartetClass* qc = quartet_classes();
     for (int q = 0; q < kNumQuartetClasses; ++q) {
-      s << (q ? ", " : "") << "\"" << qc[q].la << qc[q].lb << qc[q].lc << qc[q].ld << "\": ["
-        << c->work[q].nquart << ", " << c->work[q].nprimq << ", " << c->work[q].items.size() << "]";
+      const auto& W = c->work[q];
+      const double nout = ncart(qc[q].la) * ncart(qc[q].lb) * ncart(qc[q].lc) * ncart(qc[q].ld);
+      const double boys = 60.0 + 4.0 * (qc[q].la + qc[q].lb + qc[q].lc + qc[q].ld);
+      const double flops = W.done_primq * (qc[q].vrr_flops + boys) +
+                           W.done_quart * (qc[q].hrr_flops + 12.0 * nout);
+      s << (q ? ", " : "") << "\"" << qc[q].la << qc[q].lb << qc[q].lc << qc[q].ld
+        << "\": {\"quartets\": " << W.nquart << ", \"prim_quartets\": " << W.nprimq
+        << ", \"items\": " << W.items.size() << ", \"done_quartets\": " << W.done_quart
+        << ", \"done_prim_quartets\": " << W.done_primq << ", \"done_flops\": " << flops
+        << ", \"kernel_ms\": " << W.kernel_ms << ", \"launches\": " << W.launches << "}";
     }
     s << "}}";
     const std::string str = s.str();

@@ -41,6 +41,16 @@ import sys
 LMAX = 2  # s, p, d
 
 
+def write_if_changed(path, text):
+    """Write only when the content differs (keeps mtimes for incremental builds)."""
+    if os.path.exists(path):
+        with open(path) as f:
+            if f.read() == text:
+                return
+    with open(path, "w") as f:
+        f.write(text)
+
+
 def cart(l):
     return [(x, y, l - x - y) for x in range(l, -1, -1) for y in range(l - x, -1, -1)]
 
@@ -168,8 +178,8 @@ def gen_vrr(emin, emax, fmin, fmax):
     return fn, nacc, flops, "\n".join(code)
 
 
-def gen_hrr(la, lb, lc, ld):
-    """(ab|cd) from contracted [e0|f0], e in [la, la+lb], f in [lc, lc+ld]."""
+def hrr_core(la, lb, lc, ld, src_name="acc", prefix="h", norm=True):
+    """Straight-line HRR lines and the output expression of each (a,b,c,d)."""
     E = shells_range(la, la + lb)
     Fs = shells_range(lc, lc + ld)
     eidx = {e: k for k, e in enumerate(E)}
@@ -180,9 +190,8 @@ def gen_hrr(la, lb, lc, ld):
     names = {}
 
     def src(e, f):
-        return f"acc[{eidx[e] * nf + fidx[f]}]"
+        return f"{src_name}[{eidx[e] * nf + fidx[f]}]"
 
-    # bra HRR: X(a,b; f)
     def bra(a, b, f):
         nonlocal flops
         key = ("B", a, b, f)
@@ -195,7 +204,7 @@ def gen_hrr(la, lb, lc, ld):
         b1 = sub(b, i)
         x = bra(add(a, i), b1, f)
         y = bra(a, b1, f)
-        nm = f"h{len(lines)}"
+        nm = f"{prefix}{len(lines)}"
         lines.append(f"const R {nm} = fma(AB{'xyz'[i]}, {y}, {x});")
         flops += 2
         names[key] = nm
@@ -212,7 +221,7 @@ def gen_hrr(la, lb, lc, ld):
         d1 = sub(d, i)
         x = ket(a, b, add(c, i), d1)
         y = ket(a, b, c, d1)
-        nm = f"h{len(lines)}"
+        nm = f"{prefix}{len(lines)}"
         lines.append(f"const R {nm} = fma(CD{'xyz'[i]}, {y}, {x});")
         flops += 2
         names[key] = nm
@@ -223,20 +232,152 @@ def gen_hrr(la, lb, lc, ld):
         for b in cart(lb):
             for c in cart(lc):
                 for d in cart(ld):
-                    f = comp_norm(a) * comp_norm(b) * comp_norm(c) * comp_norm(d)
                     v = ket(a, b, c, d)
-                    if abs(f - 1.0) > 1e-15:
-                        v = f"R({f!r}) * {v}"
-                        flops += 1
-                    outs.append(v)
+                    if norm:
+                        f = comp_norm(a) * comp_norm(b) * comp_norm(c) * comp_norm(d)
+                        if abs(f - 1.0) > 1e-15:
+                            v = f"R({f!r}) * {v}"
+                            flops += 1
+                    outs.append(((a, b, c, d), v))
+    return lines, outs, flops, len(E) * nf
+
+
+def gen_hrr(la, lb, lc, ld):
+    """(ab|cd) from contracted [e0|f0], e in [la, la+lb], f in [lc, lc+ld]."""
+    lines, outs, flops, nacc = hrr_core(la, lb, lc, ld)
+    nf = len(shells_range(lc, lc + ld))
     fn = f"hrr_{la}_{lb}_{lc}_{ld}"
     code = [
-        f"// (ab|cd) block [{ncart(la)}][{ncart(lb)}][{ncart(lc)}][{ncart(ld)}] from {len(E)}x{nf} contracted [e0|f0]: {flops} flops",
+        f"// (ab|cd) block [{ncart(la)}][{ncart(lb)}][{ncart(lc)}][{ncart(ld)}] from {nacc // nf}x{nf} contracted [e0|f0]: {flops} flops",
         "template <typename R>",
         f"__device__ __forceinline__ void {fn}(const R* __restrict__ acc, const R ABx, const R ABy, const R ABz,",
         "    const R CDx, const R CDy, const R CDz, R* __restrict__ out) {",
-    ] + ["  " + ln for ln in lines] + [f"  out[{k}] = {o};" for k, o in enumerate(outs)] + ["}", ""]
-    return fn, len(E) * nf, flops, "\n".join(code)
+    ] + ["  " + ln for ln in lines] + [f"  out[{k}] = {o[1]};" for k, o in enumerate(outs)] + ["}", ""]
+    return fn, nacc, flops, "\n".join(code)
+
+
+def gen_grad(la, lb, lc, ld):
+    """Gradient pieces of class (la lb|lc ld).
+
+    VRR accumulates, per primitive quartet with weights w:
+      RA = 2 alpha [e0|f0], e in [la+1, la+lb+1]   -> (a+1_i b|cd)
+      RB = 2 beta  [e0|f0], e in [la, la+lb+1]     -> (a b+1_i|cd)
+      RC = 2 gamma [e0|f0], f in [lc+1, lc+ld+1]   -> (ab|c+1_i d)
+      LA, LB, LC = [e0|f0] on the lowered ranges   -> (a-1_i b|cd), ...
+    and the contraction forms, with G the density factor per (a,b,c,d),
+      gX_i = sum G (2 exp (x+1_i ..) - x_i (x-1_i ..))   for X = A, B, C.
+    """
+    sets = [("RA", "wa", la + 1, la + lb + 1, lc, lc + ld),
+            ("RB", "wb", la, la + lb + 1, lc, lc + ld),
+            ("RC", "wc", la, la + lb, lc + 1, lc + ld + 1)]
+    if la > 0:
+        sets.append(("LA", None, la - 1, la - 1 + lb, lc, lc + ld))
+    if lb > 0:
+        sets.append(("LB", None, la, la + lb - 1, lc, lc + ld))
+    if lc > 0:
+        sets.append(("LC", None, la, la + lb, lc - 1, lc - 1 + ld))
+    v = VRR(0, 0, 0, 0)
+    acc_lines = []
+    sizes = {}
+    flops = 0
+    for nm, w, e0, e1, f0, f1 in sets:
+        tg = [(e, f) for e in shells_range(e0, e1) for f in shells_range(f0, f1)]
+        sizes[nm] = len(tg)
+        for k, (e, f) in enumerate(tg):
+            t = v.name(e, f, 0)
+            acc_lines.append(f"  {nm}[{k}] = fma({w or 'one'}, {t}, {nm}[{k}]);")
+            flops += 2
+    flops += v.flops
+    tag = f"{la}{lb}{lc}{ld}"
+    params = ", ".join(f"R* __restrict__ {s[0]}" for s in sets)
+    vrr_code = [
+        f"// gradient VRR of class ({tag}): {flops} flops per primitive quartet",
+        "template <typename R>",
+        f"__device__ __forceinline__ void gvrr_{tag}(const R* __restrict__ F, const R PAx, const R PAy, const R PAz,",
+        "    const R WPx, const R WPy, const R WPz, const R QCx, const R QCy, const R QCz,",
+        "    const R WQx, const R WQy, const R WQz, const R oo2p, const R oo2q, const R oo2pq,",
+        f"    const R rho_p2, const R rho_q2, const R wa, const R wb, const R wc, {params}) {{",
+        "  const R one = R(1);",
+    ] + ["  " + ln for ln in v.lines] + acc_lines + ["}", ""]
+    # contraction
+    ca, cb, cc, cd = cart(la), cart(lb), cart(lc), cart(ld)
+    gidx = {}
+    k = 0
+    for a in ca:
+        for b in cb:
+            for c in cc:
+                for d in cd:
+                    gidx[(a, b, c, d)] = k
+                    k += 1
+    nrm = {key: comp_norm(key[0]) * comp_norm(key[1]) * comp_norm(key[2]) * comp_norm(key[3])
+           for key in gidx}
+    body = []
+    cflops = 0
+    hr = [("RA", 0, +1, (la + 1, lb, lc, ld)), ("RB", 1, +1, (la, lb + 1, lc, ld)),
+          ("RC", 2, +1, (la, lb, lc + 1, ld))]
+    if la > 0:
+        hr.append(("LA", 0, -1, (la - 1, lb, lc, ld)))
+    if lb > 0:
+        hr.append(("LB", 1, -1, (la, lb - 1, lc, ld)))
+    if lc > 0:
+        hr.append(("LC", 2, -1, (la, lb, lc - 1, ld)))
+    for nm, cen, sgn, cls in hr:
+        lines, outs, fl, _ = hrr_core(*cls, src_name=nm, prefix=f"{nm.lower()}_", norm=False)
+        body += ["  " + ln for ln in lines]
+        cflops += fl
+        for comp, expr in outs:
+            for i in range(3):
+                t = list(comp)
+                u = list(t[cen])
+                if sgn > 0:
+                    if u[i] == 0:
+                        continue
+                    u[i] -= 1
+                    coef = 1.0
+                else:
+                    u[i] += 1
+                    coef = -float(u[i])
+                t[cen] = tuple(u)
+                key = tuple(t)
+                if key not in gidx:
+                    continue
+                c = coef * nrm[key]
+                body.append(f"  g[{3 * cen + i}] = fma({c!r} * G[{gidx[key]}], double({expr}), g[{3 * cen + i}]);")
+                cflops += 3
+    prim = la + lb + lc + ld >= 6
+    if prim:
+        # fused per-primitive form: sets assigned (weighted), contracted at once
+        fused = [
+            f"// fused gradient of class ({tag}) for one primitive quartet",
+            "template <typename R>",
+            f"__device__ __forceinline__ void gprim_{tag}(const R* __restrict__ F, const R PAx, const R PAy, const R PAz,",
+            "    const R WPx, const R WPy, const R WPz, const R QCx, const R QCy, const R QCz,",
+            "    const R WQx, const R WQy, const R WQz, const R oo2p, const R oo2q, const R oo2pq,",
+            "    const R rho_p2, const R rho_q2, const R wa, const R wb, const R wc,",
+            "    const R ABx, const R ABy, const R ABz, const R CDx, const R CDy, const R CDz,",
+            "    const double* __restrict__ G, double* __restrict__ g) {",
+            "  const R one = R(1);",
+        ] + ["  " + ln for ln in v.lines]
+        for nm, w, e0, e1, f0, f1 in sets:
+            fused.append(f"  R {nm}[{sizes[nm]}];")
+        fused += [ln.replace(" = fma(", " = (").replace(f", {ln.split('[')[0].strip()}[", "; //[")
+                  for ln in []]
+        k_lines = []
+        for ln in acc_lines:
+            # "  RA[k] = fma(w, t, RA[k]);" -> "  RA[k] = w * t;"
+            lhs, rhs = ln.split(" = fma(")
+            w, t, _ = rhs.split(", ")
+            k_lines.append(f"{lhs} = {w} * {t};")
+        fused += k_lines + body + ["}", ""]
+    con_code = [
+        f"// gradient contraction of class ({tag}): {cflops} flops per quartet",
+        "template <typename R>",
+        f"__device__ __forceinline__ void gcon_{tag}({', '.join('const R* __restrict__ ' + s[0] for s in sets)},",
+        "    const R ABx, const R ABy, const R ABz, const R CDx, const R CDy, const R CDz,",
+        "    const double* __restrict__ G, double* __restrict__ g) {",
+    ] + body + ["}", ""]
+    code = vrr_code + con_code if not prim else fused
+    return sets, sizes, flops, cflops, "\n".join(code)
 
 
 def pair_classes():
@@ -284,8 +425,7 @@ def main(outdir):
         hdr = [f"// generated by gen_eri.py: class ({la}{lb}|{lc}{ld})", "#pragma once",
                "#include <hip/hip_runtime.h>", "namespace bscf {", "", code_v, code_h, struct,
                "}  // namespace bscf", ""]
-        with open(os.path.join(outdir, f"eri_{tag}.h"), "w") as f:
-            f.write("\n".join(hdr))
+        write_if_changed(os.path.join(outdir, f"eri_{tag}.h"), "\n".join(hdr))
         tu = [f"// generated by gen_eri.py: kernels of class ({la}{lb}|{lc}{ld})",
               '#include "fock_kernel.h"', f'#include "eri_{tag}.h"', "namespace bscf {",
               f"void launch_fock_{tag}(const FockArgs& a, int fp32, hipStream_t s) {{",
@@ -305,12 +445,69 @@ def main(outdir):
                    f"  hipLaunchKernelGGL((schwarz_kernel<Cls{tag}>), dim3((a.npairs + 255) / 256), dim3(256), 0, s, a);",
                    "}"]
         tu += ["}  // namespace bscf", ""]
-        with open(os.path.join(outdir, f"fock_{tag}.hip"), "w") as f:
-            f.write("\n".join(tu))
+        write_if_changed(os.path.join(outdir, f"fock_{tag}.hip"), "\n".join(tu))
         table[tag] = dict(vrr_flops_per_prim=fl_v, hrr_flops=fl_h, nacc=nacc, ncart=nout)
+    # gradient classes
+    for (la, lb, lc, ld) in classes:
+        tag = f"{la}{lb}{lc}{ld}"
+        sets, sizes, gfl, cfl, code = gen_grad(la, lb, lc, ld)
+        names = [s[0] for s in sets]
+        allsets = ["RA", "RB", "RC", "LA", "LB", "LC"]
+        prim = la + lb + lc + ld >= 6
+        szs = ", ".join(f"N{s} = {sizes.get(s, 1)}" for s in allsets)
+        arg = ", ".join(s for s in names)
+        if not prim:
+            wrap = f"""struct ClsG{tag} {{
+  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld};
+  static constexpr bool PRIM = false;
+  static constexpr int {szs};
+  template <typename R>
+  __device__ static __forceinline__ void vrr(const R* F, R PAx, R PAy, R PAz, R WPx, R WPy, R WPz,
+      R QCx, R QCy, R QCz, R WQx, R WQy, R WQz, R oo2p, R oo2q, R oo2pq, R rho_p2, R rho_q2,
+      R wa, R wb, R wc, R* RA, R* RB, R* RC, R* LA, R* LB, R* LC) {{
+    gvrr_{tag}<R>(F, PAx, PAy, PAz, WPx, WPy, WPz, QCx, QCy, QCz, WQx, WQy, WQz, oo2p, oo2q,
+                  oo2pq, rho_p2, rho_q2, wa, wb, wc, {arg});
+  }}
+  template <typename R>
+  __device__ static __forceinline__ void con(const R* RA, const R* RB, const R* RC, const R* LA,
+      const R* LB, const R* LC, R ABx, R ABy, R ABz, R CDx, R CDy, R CDz, const double* G,
+      double* g) {{
+    gcon_{tag}<R>({arg}, ABx, ABy, ABz, CDx, CDy, CDz, G, g);
+  }}
+}};
+"""
+        else:
+            wrap = f"""struct ClsG{tag} {{
+  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld};
+  static constexpr bool PRIM = true;
+  static constexpr int {szs};
+  template <typename R>
+  __device__ static __forceinline__ void prim(const R* F, R PAx, R PAy, R PAz, R WPx, R WPy,
+      R WPz, R QCx, R QCy, R QCz, R WQx, R WQy, R WQz, R oo2p, R oo2q, R oo2pq, R rho_p2,
+      R rho_q2, R wa, R wb, R wc, R ABx, R ABy, R ABz, R CDx, R CDy, R CDz, const double* G,
+      double* g) {{
+    gprim_{tag}<R>(F, PAx, PAy, PAz, WPx, WPy, WPz, QCx, QCy, QCz, WQx, WQy, WQz, oo2p, oo2q,
+                   oo2pq, rho_p2, rho_q2, wa, wb, wc, ABx, ABy, ABz, CDx, CDy, CDz, G, g);
+  }}
+}};
+"""
+        hdr = [f"// generated by gen_eri.py: gradient of class ({la}{lb}|{lc}{ld})", "#pragma once",
+               "#include <hip/hip_runtime.h>", "namespace bscf {", "", code, wrap,
+               "}  // namespace bscf", ""]
+        write_if_changed(os.path.join(outdir, f"grad_{tag}.h"), "\n".join(hdr))
+        tu = [f"// generated by gen_eri.py: gradient kernel of class ({la}{lb}|{lc}{ld})",
+              '#include "grad_kernel.h"', f'#include "grad_{tag}.h"', "namespace bscf {",
+              f"void launch_grad_{tag}(const GradArgs& a, hipStream_t s) {{",
+              "  const int blocks = (a.nitems + 3) / 4;",
+              "  if (blocks == 0) return;",
+              f"  hipLaunchKernelGGL((grad_kernel<ClsG{tag}>), dim3(blocks), dim3(256), 0, s, a);",
+              "}", "}  // namespace bscf", ""]
+        write_if_changed(os.path.join(outdir, f"grad_{tag}.hip"), "\n".join(tu))
+        table[tag]["grad_vrr_flops_per_prim"] = gfl
+        table[tag]["grad_contract_flops"] = cfl
     # registry
     reg = ["// generated by gen_eri.py: launcher registry", "#pragma once",
-           '#include "fock_kernel.h"', "namespace bscf {"]
+           '#include "fock_kernel.h"', '#include "grad.h"', "namespace bscf {"]
     for (la, lb, lc, ld) in classes:
         tag = f"{la}{lb}{lc}{ld}"
         reg.append(f"void launch_fock_{tag}(const FockArgs&, int, hipStream_t);")
@@ -327,15 +524,20 @@ def main(outdir):
         reg.append(f"    {{{la}, {lb}, {lc}, {ld}, launch_fock_{tag}, launch_tensor_{tag}, "
                    f"{table[tag]['vrr_flops_per_prim']}.0, {table[tag]['hrr_flops']}.0}},")
     reg += ["  };", "  return t;", "}"]
+    for (la, lb, lc, ld) in classes:
+        reg.append(f"void launch_grad_{la}{lb}{lc}{ld}(const GradArgs&, hipStream_t);")
+    reg.append("inline GradLauncher grad_launcher(int q) {")
+    reg.append("  static const GradLauncher t[] = {" + ", ".join(
+        f"launch_grad_{c[0]}{c[1]}{c[2]}{c[3]}" for c in classes) + "};")
+    reg.append("  return t[q];")
+    reg.append("}")
     reg.append(f"constexpr int kNumPairClasses = {len(pair_classes())};")
     reg.append("inline void (*schwarz_launcher(int la, int lb))(const SchwarzArgs&, hipStream_t) {")
     for (la, lb) in pair_classes():
         reg.append(f"  if (la == {la} && lb == {lb}) return launch_schwarz_{la}{lb};")
     reg += ["  return nullptr;", "}", "}  // namespace bscf", ""]
-    with open(os.path.join(outdir, "classes.h"), "w") as f:
-        f.write("\n".join(reg))
-    with open(os.path.join(outdir, "eri_flops.json"), "w") as f:
-        json.dump(table, f, indent=1)
+    write_if_changed(os.path.join(outdir, "classes.h"), "\n".join(reg))
+    write_if_changed(os.path.join(outdir, "eri_flops.json"), json.dumps(table, indent=1))
     return [f"{c[0]}{c[1]}{c[2]}{c[3]}" for c in classes]
 
 

@@ -19,6 +19,6 @@ struct GradArgs {
 };
 
 using GradLauncher = void (*)(const GradArgs&, hipStream_t);
-GradLauncher grad_launcher(int quartet_class);
+// grad_launcher(q) is defined in the generated classes.h
 
 }  // namespace bscf

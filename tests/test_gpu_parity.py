@@ -137,3 +137,32 @@ def test_scf_batched_beads(eng, b631gs):
         b = oracle.build_basis(b631gs, *inst[k])
         r = oracle.scf(b, 1e-10, 1e-8)
         assert abs(E[k] - r["E"]) < 1e-8
+
+
+@pytest.mark.parametrize("basis", ["sto-3g", "6-31g*"])
+def test_forces_single_water(eng, basis):
+    w = inputs.workload("h2o_sto3g")
+    _setup(eng, basis, w["instances"])
+    b = oracle.build_basis(inputs.load_basis(basis), *w["instances"][0])
+    r = oracle.scf(b, 1e-11, 1e-9)
+    g = oracle.gradient(b, r["P"], r["F"])
+    E, it, st = eng.run_scf(e_tol=1e-11, comm_tol=1e-9)
+    F = eng.forces()[0]
+    assert abs(E[0] - r["E"]) < 1e-9
+    assert np.abs(F + g).max() < 1e-8
+    assert np.abs(F.sum(axis=0)).max() < 1e-9
+
+
+def test_forces_batched_beads(eng, b631gs):
+    z, x = inputs.water_cluster(2, 9)
+    bx = inputs.beads(z, x, 2, 9)
+    inst = [(z, bx[k]) for k in range(2)]
+    _setup(eng, "6-31g*", inst)
+    E, it, st = eng.run_scf(e_tol=1e-11, comm_tol=1e-9)
+    F = eng.forces()
+    for k in range(2):
+        b = oracle.build_basis(b631gs, *inst[k])
+        r = oracle.scf(b, 1e-11, 1e-9)
+        g = oracle.gradient(b, r["P"], r["F"])
+        assert abs(E[k] - r["E"]) < 1e-9
+        assert np.abs(F[k] + g).max() < 1e-8
