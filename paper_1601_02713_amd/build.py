@@ -60,10 +60,17 @@ def _compile(src, force, hdr_time=None):
     if not force and os.path.exists(obj):
         if os.path.getmtime(obj) > _deps_mtime(src):
             return obj, None
-    cmd = ["hipcc"] + HIPFLAGS + ["-x", "hip", "-c", src, "-o", obj + ".tmp"]
+    cmd = ["hipcc"] + HIPFLAGS + ["-Rpass-analysis=kernel-resource-usage", "-x", "hip", "-c", src,
+                                  "-o", obj + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         return obj, f"{' '.join(cmd)}\n{r.stdout}\n{r.stderr}"
+    # per-kernel resource usage (VGPRs, scratch bytes per lane) for inspection
+    with open(obj + ".resources.txt", "w") as f:
+        for ln in r.stderr.splitlines():
+            if "remark:" in ln and any(k in ln for k in ("Function Name", "VGPRs:", "AGPRs:",
+                                                          "ScratchSize", "Occupancy", "LDS Size")):
+                f.write(ln.split("remark:", 1)[1].replace(" [-Rpass-analysis=kernel-resource-usage]", "") + "\n")
     os.replace(obj + ".tmp", obj)
     return obj, None
 

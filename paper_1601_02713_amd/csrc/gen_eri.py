@@ -266,6 +266,9 @@ def gen_grad(la, lb, lc, ld):
       LA, LB, LC = [e0|f0] on the lowered ranges   -> (a-1_i b|cd), ...
     and the contraction forms, with G the density factor per (a,b,c,d),
       gX_i = sum G (2 exp (x+1_i ..) - x_i (x-1_i ..))   for X = A, B, C.
+    Classes with la+lb+lc+ld >= 6 contract every primitive quartet at once
+    (no contracted accumulators) in three per-centre passes, each evaluating
+    only the recurrence nodes its own sets need.
     """
     sets = [("RA", "wa", la + 1, la + lb + 1, lc, lc + ld),
             ("RB", "wb", la, la + lb + 1, lc, lc + ld),
@@ -276,30 +279,13 @@ def gen_grad(la, lb, lc, ld):
         sets.append(("LB", None, la, la + lb - 1, lc, lc + ld))
     if lc > 0:
         sets.append(("LC", None, la, la + lb, lc - 1, lc - 1 + ld))
-    v = VRR(0, 0, 0, 0)
-    acc_lines = []
-    sizes = {}
-    flops = 0
-    for nm, w, e0, e1, f0, f1 in sets:
-        tg = [(e, f) for e in shells_range(e0, e1) for f in shells_range(f0, f1)]
-        sizes[nm] = len(tg)
-        for k, (e, f) in enumerate(tg):
-            t = v.name(e, f, 0)
-            acc_lines.append(f"  {nm}[{k}] = fma({w or 'one'}, {t}, {nm}[{k}]);")
-            flops += 2
-    flops += v.flops
     tag = f"{la}{lb}{lc}{ld}"
-    params = ", ".join(f"R* __restrict__ {s[0]}" for s in sets)
-    vrr_code = [
-        f"// gradient VRR of class ({tag}): {flops} flops per primitive quartet",
-        "template <typename R>",
-        f"__device__ __forceinline__ void gvrr_{tag}(const R* __restrict__ F, const R PAx, const R PAy, const R PAz,",
-        "    const R WPx, const R WPy, const R WPz, const R QCx, const R QCy, const R QCz,",
-        "    const R WQx, const R WQy, const R WQz, const R oo2p, const R oo2q, const R oo2pq,",
-        f"    const R rho_p2, const R rho_q2, const R wa, const R wb, const R wc, {params}) {{",
-        "  const R one = R(1);",
-    ] + ["  " + ln for ln in v.lines] + acc_lines + ["}", ""]
-    # contraction
+    sizes = {}
+    targets = {}
+    for nm, w, e0, e1, f0, f1 in sets:
+        targets[nm] = [(e, f) for e in shells_range(e0, e1) for f in shells_range(f0, f1)]
+        sizes[nm] = len(targets[nm])
+    # contraction lines per set
     ca, cb, cc, cd = cart(la), cart(lb), cart(lc), cart(ld)
     gidx = {}
     k = 0
@@ -311,19 +297,15 @@ def gen_grad(la, lb, lc, ld):
                     k += 1
     nrm = {key: comp_norm(key[0]) * comp_norm(key[1]) * comp_norm(key[2]) * comp_norm(key[3])
            for key in gidx}
-    body = []
+    hr = {"RA": (0, +1, (la + 1, lb, lc, ld)), "RB": (1, +1, (la, lb + 1, lc, ld)),
+          "RC": (2, +1, (la, lb, lc + 1, ld)), "LA": (0, -1, (la - 1, lb, lc, ld)),
+          "LB": (1, -1, (la, lb - 1, lc, ld)), "LC": (2, -1, (la, lb, lc - 1, ld))}
+    con = {}
     cflops = 0
-    hr = [("RA", 0, +1, (la + 1, lb, lc, ld)), ("RB", 1, +1, (la, lb + 1, lc, ld)),
-          ("RC", 2, +1, (la, lb, lc + 1, ld))]
-    if la > 0:
-        hr.append(("LA", 0, -1, (la - 1, lb, lc, ld)))
-    if lb > 0:
-        hr.append(("LB", 1, -1, (la, lb - 1, lc, ld)))
-    if lc > 0:
-        hr.append(("LC", 2, -1, (la, lb, lc - 1, ld)))
-    for nm, cen, sgn, cls in hr:
+    for nm, *_ in sets:
+        cen, sgn, cls = hr[nm]
         lines, outs, fl, _ = hrr_core(*cls, src_name=nm, prefix=f"{nm.lower()}_", norm=False)
-        body += ["  " + ln for ln in lines]
+        body = ["  " + ln for ln in lines]
         cflops += fl
         for comp, expr in outs:
             for i in range(3):
@@ -344,39 +326,66 @@ def gen_grad(la, lb, lc, ld):
                 c = coef * nrm[key]
                 body.append(f"  g[{3 * cen + i}] = fma({c!r} * G[{gidx[key]}], double({expr}), g[{3 * cen + i}]);")
                 cflops += 3
+        con[nm] = body
+    sig = ["template <typename R>",
+           "__device__ {inl} void {fn}(const R* __restrict__ F, const R PAx, const R PAy, const R PAz,",
+           "    const R WPx, const R WPy, const R WPz, const R QCx, const R QCy, const R QCz,",
+           "    const R WQx, const R WQy, const R WQz, const R oo2p, const R oo2q, const R oo2pq,",
+           "    const R rho_p2, const R rho_q2, const R wa, const R wb, const R wc{extra}) {{"]
     prim = la + lb + lc + ld >= 6
-    if prim:
-        # fused per-primitive form: sets assigned (weighted), contracted at once
-        fused = [
-            f"// fused gradient of class ({tag}) for one primitive quartet",
-            "template <typename R>",
-            f"__device__ __forceinline__ void gprim_{tag}(const R* __restrict__ F, const R PAx, const R PAy, const R PAz,",
-            "    const R WPx, const R WPy, const R WPz, const R QCx, const R QCy, const R QCz,",
-            "    const R WQx, const R WQy, const R WQz, const R oo2p, const R oo2q, const R oo2pq,",
-            "    const R rho_p2, const R rho_q2, const R wa, const R wb, const R wc,",
-            "    const R ABx, const R ABy, const R ABz, const R CDx, const R CDy, const R CDz,",
-            "    const double* __restrict__ G, double* __restrict__ g) {",
-            "  const R one = R(1);",
-        ] + ["  " + ln for ln in v.lines]
-        for nm, w, e0, e1, f0, f1 in sets:
-            fused.append(f"  R {nm}[{sizes[nm]}];")
-        fused += [ln.replace(" = fma(", " = (").replace(f", {ln.split('[')[0].strip()}[", "; //[")
-                  for ln in []]
-        k_lines = []
-        for ln in acc_lines:
-            # "  RA[k] = fma(w, t, RA[k]);" -> "  RA[k] = w * t;"
-            lhs, rhs = ln.split(" = fma(")
-            w, t, _ = rhs.split(", ")
-            k_lines.append(f"{lhs} = {w} * {t};")
-        fused += k_lines + body + ["}", ""]
-    con_code = [
-        f"// gradient contraction of class ({tag}): {cflops} flops per quartet",
-        "template <typename R>",
-        f"__device__ __forceinline__ void gcon_{tag}({', '.join('const R* __restrict__ ' + s[0] for s in sets)},",
-        "    const R ABx, const R ABy, const R ABz, const R CDx, const R CDy, const R CDz,",
-        "    const double* __restrict__ G, double* __restrict__ g) {",
-    ] + body + ["}", ""]
-    code = vrr_code + con_code if not prim else fused
+    flops = 0
+    if not prim:
+        v = VRR(0, 0, 0, 0)
+        acc_lines = []
+        for nm, w, *_ in sets:
+            for kk, (e, f) in enumerate(targets[nm]):
+                t = v.name(e, f, 0)
+                acc_lines.append(f"  {nm}[{kk}] = fma({w or 'one'}, {t}, {nm}[{kk}]);")
+                flops += 2
+        flops += v.flops
+        params = "".join(f", R* __restrict__ {s[0]}" for s in sets)
+        code = [f"// gradient VRR of class ({tag}): {flops} flops per primitive quartet"]
+        code += [s.format(inl="__forceinline__", fn=f"gvrr_{tag}", extra=params) for s in sig]
+        code += ["  const R one = R(1);"] + ["  " + ln for ln in v.lines] + acc_lines + ["}", ""]
+        code += [f"// gradient contraction of class ({tag}): {cflops} flops per quartet",
+                 "template <typename R>",
+                 f"__device__ __forceinline__ void gcon_{tag}({', '.join('const R* __restrict__ ' + s[0] for s in sets)},",
+                 "    const R ABx, const R ABy, const R ABz, const R CDx, const R CDy, const R CDz,",
+                 "    const double* __restrict__ G, double* __restrict__ g) {"]
+        for nm, *_ in sets:
+            code += con[nm]
+        code += ["}", ""]
+        return sets, sizes, flops, cflops, "\n".join(code)
+    code = []
+    extra = (", const R ABx, const R ABy, const R ABz, const R CDx, const R CDy, const R CDz,"
+             "\n    const double* __restrict__ G, double* __restrict__ g")
+    for X in "ABC":
+        grp = [s for s in sets if s[0][1] == X]
+        v = VRR(0, 0, 0, 0)
+        asg = []
+        for nm, w, *_ in grp:
+            asg.append(f"  R {nm}[{sizes[nm]}];")
+            for kk, (e, f) in enumerate(targets[nm]):
+                t = v.name(e, f, 0)
+                asg.append(f"  {nm}[{kk}] = {w or 'one'} * {t};")
+        flops += v.flops
+        code += [f"// gradient of class ({tag}), centre {X}, one primitive quartet"]
+        code += [s.format(inl="__noinline__", fn=f"gprim{X}_{tag}", extra=extra) for s in sig]
+        code += ["  const R one = R(1);"] + ["  " + ln for ln in v.lines] + asg
+        for nm, *_ in grp:
+            code += con[nm]
+        code += ["}", ""]
+    code += ["template <typename R>",
+             f"__device__ __forceinline__ void gprim_{tag}(const R* __restrict__ F, const R PAx, const R PAy, const R PAz,",
+             "    const R WPx, const R WPy, const R WPz, const R QCx, const R QCy, const R QCz,",
+             "    const R WQx, const R WQy, const R WQz, const R oo2p, const R oo2q, const R oo2pq,",
+             "    const R rho_p2, const R rho_q2, const R wa, const R wb, const R wc,",
+             "    const R ABx, const R ABy, const R ABz, const R CDx, const R CDy, const R CDz,",
+             "    const double* __restrict__ G, double* __restrict__ g) {"]
+    for X in "ABC":
+        code.append(f"  gprim{X}_{tag}<R>(F, PAx, PAy, PAz, WPx, WPy, WPz, QCx, QCy, QCz, WQx, WQy, WQz,"
+                    " oo2p, oo2q, oo2pq, rho_p2, rho_q2, wa, wb, wc, ABx, ABy, ABz, CDx, CDy, CDz, G, g);")
+    code += ["}", ""]
     return sets, sizes, flops, cflops, "\n".join(code)
 
 
