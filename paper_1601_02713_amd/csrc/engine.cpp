@@ -613,7 +613,7 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
       W.kernel_ms += ms;
     }
   }
-  BatchInfo b = c->batch(false);
+  BatchInfo b = c->batch(masked);
   launch_fock_assemble(b, c->max_n, c->H.p, c->J.p, c->K.p, c->P.p, c->d_Enuc.p, c->F.p, c->d_E.p,
                        c->stream);
   c->fock_builds++;

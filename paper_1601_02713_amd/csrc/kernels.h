@@ -68,7 +68,8 @@ struct BatchInfo {
 };
 
 void launch_fill(double* p, long long n, double v, hipStream_t s);
-// F = H + (J + J^T)/2 - (K + K^T)/4 ; E[i] = Tr[P(H+F)]/2 + Enuc[i]
+// F = H + (J + J^T)/2 - (K + K^T)/4 ; E[i] = Tr[P(H+F)]/2 + Enuc[i]; instances
+// masked out by b.active (when non-NULL) keep their F and E
 void launch_fock_assemble(const BatchInfo& b, int max_n, const double* H, const double* J,
                           const double* K, const double* P, const double* Enuc, double* F,
                           double* E, hipStream_t s);

@@ -42,7 +42,8 @@ __global__ void fock_assemble_kernel(BatchInfo b, const double* H, const double*
   __shared__ double sh[8];
   const int inst = blockIdx.y, i = blockIdx.x;
   const int n = b.nbf[inst];
-  if (i >= n) return;
+  // a converged (masked) instance keeps the F and E of its last build
+  if (i >= n || (b.active && !b.active[inst])) return;
   const long long o = b.moff[inst];
   double e = 0.0;
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
@@ -55,10 +56,11 @@ __global__ void fock_assemble_kernel(BatchInfo b, const double* H, const double*
   if (threadIdx.x == 0) rowE[(long long)inst * gridDim.x + i] = 0.5 * e;
 }
 
-__global__ void energy_sum_kernel(int ninst, int max_n, const int* nbf, const double* rowE,
-                                  const double* Enuc, double* E) {
+__global__ void energy_sum_kernel(int ninst, int max_n, const int* nbf, const int* active,
+                                  const double* rowE, const double* Enuc, double* E) {
   __shared__ double sh[8];
   const int inst = blockIdx.x;
+  if (active && !active[inst]) return;
   const int n = nbf[inst];
   double e = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) e += rowE[(long long)inst * max_n + i];
@@ -291,7 +293,7 @@ void launch_fock_assemble(const BatchInfo& b, int max_n, const double* H, const 
   hipLaunchKernelGGL(fock_assemble_kernel, dim3(max_n, b.ninst), dim3(256), 0, s, b, H, J, K, P,
                      F, rowE);
   hipLaunchKernelGGL(energy_sum_kernel, dim3(b.ninst), dim3(256), 0, s, b.ninst, max_n, b.nbf,
-                     rowE, Enuc, E);
+                     b.active, rowE, Enuc, E);
 }
 
 void launch_antisym(const BatchInfo& b, int max_n, const double* A, double* out, double* emax,

@@ -166,3 +166,19 @@ def test_forces_batched_beads(eng, b631gs):
         g = oracle.gradient(b, r["P"], r["F"])
         assert abs(E[k] - r["E"]) < 1e-9
         assert np.abs(F[k] + g).max() < 1e-8
+
+
+def test_scf_staggered_convergence(eng, b631gs):
+    """Instances that converge at different iterations keep the energy and
+    Fock matrix of their own last build while the others iterate on."""
+    inst = inputs.workload("w1")["instances"] + inputs.workload("w3")["instances"]
+    z, x = inputs.water_cluster(2, 9)
+    inst += [(z, b) for b in inputs.beads(z, x, 2, 9)]
+    _setup(eng, "6-31g*", inst)
+    E, it, st = eng.run_scf(e_tol=1e-11, comm_tol=1e-9)
+    assert len(set(it.tolist())) > 1, it
+    for k, (zz, xx) in enumerate(inst):
+        b = oracle.build_basis(b631gs, zz, xx)
+        r = oracle.scf(b, 1e-11, 1e-9)
+        assert st[k] == 0
+        assert abs(E[k] - r["E"]) < 1e-9, (k, it, E[k], r["E"])
