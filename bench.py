@@ -35,7 +35,7 @@ def cpu_baseline(w, seconds: float):
     from oracle import rhf
     basis = inputs.load_basis(w["basis"])
     nq_total, t_total, beads = 0, 0.0, 0
-    for z, x in w["instances"]:
+    for z, x in list(w["instances"]) * 8:
         b = oracle.build_basis(basis, z, x)
         Q = oracle.schwarz(b)
         S, T, V = oracle.one_electron(b)
@@ -109,6 +109,11 @@ def main():
     k_ms = sum(c["kernel_ms"] for c in cls.values())
     k_fl = sum(c["done_flops"] for c in cls.values())
     dom = max(cls, key=lambda k: cls[k]["kernel_ms"])
+    fock_gpu_ms = st_json["t_fock_gpu_ms"]
+    per_class = {k: {"quartets_per_build": v["quartets"], "prim_quartets_per_build": v["prim_quartets"],
+                     "ms_per_launch": v["kernel_ms"] / max(v["launches"], 1),
+                     "tflops": (v["done_flops"] / (v["kernel_ms"] * 1e-3) / 1e12) if v["kernel_ms"] else None}
+                 for k, v in cls.items() if v["launches"]}
     d = cls[dom]
     ach = d["done_flops"] / (d["kernel_ms"] * 1e-3) / 1e12 if d["kernel_ms"] > 0 else 0.0
     n_inst = len(xs)
@@ -131,9 +136,11 @@ def main():
         "bead_scf_steps_per_s": iters / wall,
         "bead_energy_force_per_s": n_inst * args.steps / wall,
         "scf_iterations_per_bead": iters / (n_inst * args.steps),
-        "fock_kernels_quartets_per_s": done_q / (k_ms * 1e-3) if k_ms else None,
-        "fock_kernels_tflops": k_fl / (k_ms * 1e-3) / 1e12 if k_ms else None,
-        "fock_kernel_ms_per_step": k_ms / args.steps,
+        "fock_build_ms": fock_gpu_ms / max(st_json["fock_builds"], 1),
+        "fock_builds_per_step": st_json["fock_builds"] / args.steps,
+        "fock_quartets_per_s": done_q / (fock_gpu_ms * 1e-3) if fock_gpu_ms else None,
+        "fock_tflops": k_fl / (fock_gpu_ms * 1e-3) / 1e12 if fock_gpu_ms else None,
+        "fock_frac_fp64_peak": (k_fl / (fock_gpu_ms * 1e-3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS) if fock_gpu_ms else None,
         "phase_ms_per_step": {k: st_json[k] / args.steps for k in
                               ("t_setup_ms", "t_scf_ms", "t_grad_ms", "t_fock_ms")},
         "roofline": {"bound": "alu", "kernel": f"fock_kernel<Cls{dom}, double>",
@@ -142,6 +149,7 @@ def main():
                      "launches": d["launches"],
                      "avg_launch_ms": d["kernel_ms"] / max(d["launches"], 1)},
         "energies_first_bead": float(E[0]),
+        "classes": per_class,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -45,14 +45,49 @@ struct ShellPair {
   int nprim;   // primitive pairs
 };
 
-// One wavefront's work: a bra shell pair against nket ket pairs taken from
-// kets[ket0 ...] (all of one angular class and one primitive count).
-struct WorkItem {
+// A row of the screened work list: bra shell pair `bra` against the nket ket
+// pairs kets[ket0 ...] (one angular class, one primitive count, Schwarz
+// prefix).  Rows of one instance and one (bra, ket) primitive-count pair are
+// consecutive.
+struct WorkRow {
   int bra;
   int ket0;
   int nket;
-  int diag;    // 1 if kets may include the bra pair itself
+  int pad;
 };
+
+// One wavefront's work: `count` (<= 64) consecutive quartets starting at
+// quartet `off` of row `row`, all of one instance and one contraction pair.
+struct WorkItem {
+  int row;
+  int off;
+  int count;
+  int pad;
+};
+
+// Quartet of lane `lane` of item `it`; returns false (and a valid dummy
+// quartet) for lanes beyond it.count.  `single_row` is true when the whole
+// item lies in one row (uniform bra across the wavefront).
+__device__ __forceinline__ bool lane_quartet(const WorkItem& it, const WorkRow* __restrict__ rows,
+                                             const int* __restrict__ kets, int lane, int& bra,
+                                             int& ket, bool& single_row) {
+  const WorkRow r0 = rows[it.row];
+  single_row = r0.nket - it.off >= it.count;
+  if (lane >= it.count) {
+    bra = r0.bra;
+    ket = kets[r0.ket0 + it.off];
+    return false;
+  }
+  int r = it.row, k = it.off + lane, nk = r0.nket;
+  while (k >= nk) {
+    k -= nk;
+    ++r;
+    nk = rows[r].nket;
+  }
+  bra = rows[r].bra;
+  ket = kets[rows[r].ket0 + k];
+  return true;
+}
 
 __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 

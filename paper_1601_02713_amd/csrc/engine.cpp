@@ -215,6 +215,11 @@ struct bscf_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  static constexpr int kAux = 4;   // streams for concurrent class kernels
+  hipStream_t aux[kAux] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
+  hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;   // whole Fock build (profiling)
+  double t_fock_gpu_ms = 0;
   rocblas_handle blas = nullptr;
 
   std::map<int, std::vector<BasisShell>> basis;
@@ -241,7 +246,9 @@ struct bscf_ctx {
   // work lists per quartet class
   struct ClassWork {
     std::vector<WorkItem> items;
+    std::vector<WorkRow> rows;
     DevBuf<WorkItem> d_items;
+    DevBuf<WorkRow> d_rows;
     double nquart = 0, nprimq = 0;
     std::vector<double> inst_quart, inst_primq;  // per instance
     // evaluated so far (active instances only) and measured kernel time
@@ -500,11 +507,11 @@ void build_work(bscf_ctx* c, double tau) {
         }
       }
     }
-  const int CHUNK = 256;
   const QuartetClass* qc = quartet_classes();
   for (int q = 0; q < kNumQuartetClasses; ++q) {
     auto& W = c->work[q];
     W.items.clear();
+    W.rows.clear();
     W.nquart = 0;
     W.nprimq = 0;
     const int X = pclass(qc[q].la, qc[q].lb), Y = pclass(qc[q].lc, qc[q].ld);
@@ -516,6 +523,8 @@ void build_work(bscf_ctx* c, double tau) {
     };
     std::vector<Tmp> tmp;
     for (int i = 0; i < c->ninst; ++i) {
+      // rows of this instance grouped by (bra, ket) primitive counts
+      std::vector<std::pair<std::pair<int, int>, std::vector<WorkRow>>> groups;
       for (const Sub& bs : subs[i][X])
         for (size_t r = 0; r < bs.ids.size(); ++r) {
           const int bra = bs.ids[r];
@@ -541,22 +550,46 @@ void build_work(bscf_ctx* c, double tau) {
               if (t > sb) lim = 0;
               else if (t == sb) lim = std::min(lim, (int)r + 1);
             }
-            for (int k0 = 0; k0 < lim; k0 += CHUNK) {
-              const int nk = std::min(CHUNK, lim - k0);
-              WorkItem w{bra, ks.ket_off + k0, nk, (X == Y && t == sb) ? 1 : 0};
-              tmp.push_back({w, double(nk) * bs.nprim * ks.nprim});
-              W.nquart += nk;
-              W.nprimq += double(nk) * bs.nprim * ks.nprim;
-              W.inst_quart[i] += nk;
-              W.inst_primq[i] += double(nk) * bs.nprim * ks.nprim;
-            }
+            if (lim == 0) continue;
+            const std::pair<int, int> key(bs.nprim, ks.nprim);
+            size_t g = 0;
+            while (g < groups.size() && groups[g].first != key) ++g;
+            if (g == groups.size()) groups.push_back({key, {}});
+            groups[g].second.push_back(WorkRow{bra, ks.ket_off, lim, 0});
+            W.nquart += lim;
+            W.nprimq += double(lim) * bs.nprim * ks.nprim;
+            W.inst_quart[i] += lim;
+            W.inst_primq[i] += double(lim) * bs.nprim * ks.nprim;
           }
         }
+      // tile every group with items of up to 64 quartets (one per lane)
+      for (auto& gr : groups) {
+        const int r0 = (int)W.rows.size();
+        W.rows.insert(W.rows.end(), gr.second.begin(), gr.second.end());
+        const int r1 = (int)W.rows.size();
+        const double cost = double(gr.first.first) * gr.first.second;
+        int r = r0, off = 0;
+        while (r < r1) {
+          WorkItem w{r, off, 0, 0};
+          while (w.count < kWave && r < r1) {
+            const int t = std::min(W.rows[r].nket - off, kWave - w.count);
+            w.count += t;
+            off += t;
+            if (off == W.rows[r].nket) {
+              ++r;
+              off = 0;
+            }
+          }
+          tmp.push_back({w, cost});
+        }
+      }
     }
+    // most expensive contraction groups first
     std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; });
     W.items.resize(tmp.size());
     for (size_t k = 0; k < tmp.size(); ++k) W.items[k] = tmp[k].w;
     W.d_items.upload(W.items, c->stream);
+    W.d_rows.upload(W.rows, c->stream);
   }
   c->d_kets.upload(c->kets, c->stream);
   c->work_tau = tau;
@@ -581,20 +614,36 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
   a.boys32 = c->d_boys32.p;
   a.active = masked ? c->d_active.p : c->d_all_active.p;
   const QuartetClass* qc = quartet_classes();
-  for (int q = 0; q < kNumQuartetClasses; ++q) {
+  // class kernels run concurrently on the auxiliary streams (J and K are
+  // accumulated with atomics, so their order does not matter); heavy classes
+  // are issued first because they are latency-bound
+  if (c->profiling) {
+    if (!c->ev_b0) {
+      HIPCHK(hipEventCreate(&c->ev_b0));
+      HIPCHK(hipEventCreate(&c->ev_b1));
+    }
+    HIPCHK(hipEventRecord(c->ev_b0, c->stream));
+  }
+  HIPCHK(hipEventRecord(c->ev_fork, c->stream));
+  for (int k = 0; k < bscf_ctx::kAux; ++k) HIPCHK(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
+  int slot = 0;
+  for (int qq = kNumQuartetClasses - 1; qq >= 0; --qq) {
+    const int q = qq;
     auto& W = c->work[q];
     if (W.items.empty()) continue;
+    const hipStream_t s = c->aux[slot++ % bscf_ctx::kAux];
     a.items = W.d_items.p;
+    a.rows = W.d_rows.p;
     a.nitems = (int)W.items.size();
     if (c->profiling) {
       if (!W.ev0) {
         HIPCHK(hipEventCreate(&W.ev0));
         HIPCHK(hipEventCreate(&W.ev1));
       }
-      HIPCHK(hipEventRecord(W.ev0, c->stream));
+      HIPCHK(hipEventRecord(W.ev0, s));
     }
-    qc[q].fock(a, precision == BSCF_MIXED ? 1 : 0, c->stream);
-    if (c->profiling) HIPCHK(hipEventRecord(W.ev1, c->stream));
+    qc[q].fock(a, precision == BSCF_MIXED ? 1 : 0, s);
+    if (c->profiling) HIPCHK(hipEventRecord(W.ev1, s));
     for (int i = 0; i < c->ninst; ++i)
       if (!masked || c->h_active[i]) {
         W.done_quart += W.inst_quart[i];
@@ -602,9 +651,17 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
       }
     W.launches++;
   }
+  for (int k = 0; k < bscf_ctx::kAux; ++k) {
+    HIPCHK(hipEventRecord(c->ev_join[k], c->aux[k]));
+    HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join[k], 0));
+  }
   HIPCHK(hipGetLastError());
   if (c->profiling) {
+    HIPCHK(hipEventRecord(c->ev_b1, c->stream));
     sync(c);
+    float bms = 0.f;
+    HIPCHK(hipEventElapsedTime(&bms, c->ev_b0, c->ev_b1));
+    c->t_fock_gpu_ms += bms;
     for (int q = 0; q < kNumQuartetClasses; ++q) {
       auto& W = c->work[q];
       if (W.items.empty()) continue;
@@ -661,6 +718,11 @@ bscf_status bscf_create(int hip_device, void* hip_stream, bscf_ctx** out) {
       HIPCHK(hipStreamCreate(&c->stream));
       c->own_stream = true;
     }
+    for (int k = 0; k < bscf_ctx::kAux; ++k) {
+      HIPCHK(hipStreamCreate(&c->aux[k]));
+      HIPCHK(hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     BLASCHK(rocblas_create_handle(&c->blas));
     BLASCHK(rocblas_set_stream(c->blas, c->stream));
     std::vector<double> tab(kBoysRows * kBoysCols);
@@ -682,6 +744,14 @@ bscf_status bscf_destroy(bscf_ctx* c) {
     if (W.ev1) (void)hipEventDestroy(W.ev1);
   }
   if (c->blas) rocblas_destroy_handle(c->blas);
+  for (int k = 0; k < bscf_ctx::kAux; ++k) {
+    if (c->aux[k]) (void)hipStreamSynchronize(c->aux[k]);
+    if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
+    if (c->aux[k]) (void)hipStreamDestroy(c->aux[k]);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_b0) (void)hipEventDestroy(c->ev_b0);
+  if (c->ev_b1) (void)hipEventDestroy(c->ev_b1);
   hipStream_t s = c->stream;
   bool own = c->own_stream;
   delete c;
@@ -1187,12 +1257,20 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
     ga.P = c->P.p;
     ga.grad = c->d_grad.p;
     ga.boys64 = c->d_boys64.p;
-    for (int q = 0; q < kNumQuartetClasses; ++q) {
+    HIPCHK(hipEventRecord(c->ev_fork, st));
+    for (int k = 0; k < bscf_ctx::kAux; ++k) HIPCHK(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
+    int slot = 0;
+    for (int q = kNumQuartetClasses - 1; q >= 0; --q) {
       auto& W = c->work[q];
       if (W.items.empty()) continue;
       ga.items = W.d_items.p;
+      ga.rows = W.d_rows.p;
       ga.nitems = (int)W.items.size();
-      grad_launcher(q)(ga, st);
+      grad_launcher(q)(ga, c->aux[slot++ % bscf_ctx::kAux]);
+    }
+    for (int k = 0; k < bscf_ctx::kAux; ++k) {
+      HIPCHK(hipEventRecord(c->ev_join[k], c->aux[k]));
+      HIPCHK(hipStreamWaitEvent(st, c->ev_join[k], 0));
     }
     HIPCHK(hipGetLastError());
     std::vector<double> g(3 * c->total_atoms);
@@ -1325,7 +1403,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
       W.done_quart = W.done_primq = W.kernel_ms = 0;
       W.launches = 0;
     }
-    c->t_fock_ms = c->t_scf_ms = c->t_grad_ms = c->t_setup_ms = 0;
+    c->t_fock_ms = c->t_scf_ms = c->t_grad_ms = c->t_setup_ms = c->t_fock_gpu_ms = 0;
     c->fock_builds = c->scf_iters = 0;
   });
 }
@@ -1337,6 +1415,7 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
     s << "{\"fock_builds\": " << c->fock_builds << ", \"scf_iterations\": " << c->scf_iters
       << ", \"t_fock_ms\": " << c->t_fock_ms << ", \"t_scf_ms\": " << c->t_scf_ms
       << ", \"t_grad_ms\": " << c->t_grad_ms << ", \"t_setup_ms\": " << c->t_setup_ms
+      << ", \"t_fock_gpu_ms\": " << c->t_fock_gpu_ms
       << ", \"classes\": {";
     const QuartetClass* qc = quartet_classes();
     for (int q = 0; q < kNumQuartetClasses; ++q) {

@@ -21,6 +21,7 @@ namespace bscf {
 struct FockArgs {
   const WorkItem* items;
   int nitems;
+  const WorkRow* rows;
   const ShellPair* pairs;
   const PrimPair* prims;
   const Shell* shells;
@@ -69,10 +70,12 @@ __device__ __forceinline__ void eri_block_body(const PrimPair* __restrict__ bp, 
   R acc[CL::NACC];
 #pragma unroll
   for (int k = 0; k < CL::NACC; ++k) acc[k] = R(0);
-  for (int i = 0; i < nb; ++i) {
-    const PrimPair B = bp[i];
-    for (int j = 0; j < nk; ++j) {
-      const PrimPair Q = kp[j];
+  // ket primitives (one set per lane) outermost: each is loaded once; the
+  // bra primitives are shared by the lanes of a wavefront and stay cached
+  for (int j = 0; j < nk; ++j) {
+    const PrimPair Q = kp[j];
+    for (int i = 0; i < nb; ++i) {
+      const PrimPair B = bp[i];
       const double pq = B.p + Q.p;
       const double rpq = rsqrt(pq);
       const double oopq = rpq * rpq;
@@ -136,9 +139,12 @@ __global__ __launch_bounds__(256) void fock_kernel(FockArgs a) {
   const int item_id = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
   if (item_id >= a.nitems) return;
   const WorkItem it = a.items[item_id];
-  const ShellPair bra = a.pairs[it.bra];
+  int bid, kid;
+  bool single;
+  const bool valid = lane_quartet(it, a.rows, a.kets, lane, bid, kid, single);
+  const ShellPair bra = a.pairs[bid];
   const Shell sa = a.shells[bra.a], sb = a.shells[bra.b];
-  const int inst = sa.inst;
+  const int inst = sa.inst;               // one instance per item
   if (!a.active[inst]) return;
   const long long mo = a.moff[inst];
   const int n = a.nbf[inst];
@@ -152,111 +158,109 @@ __global__ __launch_bounds__(256) void fock_kernel(FockArgs a) {
   for (int i = 0; i < NA; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) Pab[i][j] = P[(m0 + i) * n + n0 + j];
-  double jbra[NA][NB];
+  const ShellPair ket = a.pairs[kid];
+  const Shell sc = a.shells[ket.a], sd = a.shells[ket.b];
+  const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
+  R v[CL::NOUT];
+  eri_block<CL, R>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
+                   a.boys64, a.boys32, v);
+  const double g = ((bra.a == bra.b) ? 1.0 : 2.0) * ((ket.a == ket.b) ? 1.0 : 2.0) *
+                   ((kid == bid) ? 1.0 : 2.0);
+  const double fj = valid ? 0.5 * g : 0.0;
+  const double fk = 0.5 * fj;
+  const int l0 = sc.bf, s0 = sd.bf;
+  double Pcd[NC][ND], Pac[NA][NC], Pad[NA][ND], Pbc[NB][NC], Pbd[NB][ND];
 #pragma unroll
-  for (int i = 0; i < NA; ++i)
+  for (int k = 0; k < NC; ++k)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) jbra[i][j] = 0.0;
-  const double gab = (bra.a == bra.b) ? 1.0 : 2.0;
-
-  for (int base = 0; base < it.nket; base += kWave) {
-    const bool valid = base + lane < it.nket;
-    const int kid = a.kets[it.ket0 + (valid ? base + lane : 0)];
-    const ShellPair ket = a.pairs[kid];
-    const Shell sc = a.shells[ket.a], sd = a.shells[ket.b];
-    const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
-    R v[CL::NOUT];
-    eri_block<CL, R>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
-                     a.boys64, a.boys32, v);
-    const double g = gab * ((ket.a == ket.b) ? 1.0 : 2.0) * ((kid == it.bra) ? 1.0 : 2.0);
-    const double fj = valid ? 0.5 * g : 0.0;
-    const double fk = 0.5 * fj;
-    const int l0 = sc.bf, s0 = sd.bf;
-    double Pcd[NC][ND], Pac[NA][NC], Pad[NA][ND], Pbc[NB][NC], Pbd[NB][ND];
+    for (int l = 0; l < ND; ++l) Pcd[k][l] = P[(l0 + k) * n + s0 + l];
 #pragma unroll
-    for (int k = 0; k < NC; ++k)
+  for (int i = 0; i < NA; ++i) {
 #pragma unroll
-      for (int l = 0; l < ND; ++l) Pcd[k][l] = P[(l0 + k) * n + s0 + l];
+    for (int k = 0; k < NC; ++k) Pac[i][k] = P[(m0 + i) * n + l0 + k];
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
+    for (int l = 0; l < ND; ++l) Pad[i][l] = P[(m0 + i) * n + s0 + l];
+  }
 #pragma unroll
-      for (int k = 0; k < NC; ++k) Pac[i][k] = P[(m0 + i) * n + l0 + k];
+  for (int j = 0; j < NB; ++j) {
 #pragma unroll
-      for (int l = 0; l < ND; ++l) Pad[i][l] = P[(m0 + i) * n + s0 + l];
-    }
+    for (int k = 0; k < NC; ++k) Pbc[j][k] = P[(n0 + j) * n + l0 + k];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
+    for (int l = 0; l < ND; ++l) Pbd[j][l] = P[(n0 + j) * n + s0 + l];
+  }
+  double jbra[NA][NB], jket[NC][ND], kac[NA][NC], kad[NA][ND], kbc[NB][NC], kbd[NB][ND];
 #pragma unroll
-      for (int k = 0; k < NC; ++k) Pbc[j][k] = P[(n0 + j) * n + l0 + k];
+  for (int k = 0; k < NC; ++k)
 #pragma unroll
-      for (int l = 0; l < ND; ++l) Pbd[j][l] = P[(n0 + j) * n + s0 + l];
-    }
-    double jket[NC][ND], kac[NA][NC], kad[NA][ND], kbc[NB][NC], kbd[NB][ND];
+    for (int l = 0; l < ND; ++l) jket[k][l] = 0.0;
 #pragma unroll
-    for (int k = 0; k < NC; ++k)
+  for (int i = 0; i < NA; ++i) {
 #pragma unroll
-      for (int l = 0; l < ND; ++l) jket[k][l] = 0.0;
+    for (int k = 0; k < NC; ++k) kac[i][k] = 0.0;
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
+    for (int l = 0; l < ND; ++l) kad[i][l] = 0.0;
+  }
 #pragma unroll
-      for (int k = 0; k < NC; ++k) kac[i][k] = 0.0;
+  for (int j = 0; j < NB; ++j) {
 #pragma unroll
-      for (int l = 0; l < ND; ++l) kad[i][l] = 0.0;
-    }
+    for (int k = 0; k < NC; ++k) kbc[j][k] = 0.0;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-#pragma unroll
-      for (int k = 0; k < NC; ++k) kbc[j][k] = 0.0;
-#pragma unroll
-      for (int l = 0; l < ND; ++l) kbd[j][l] = 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < NA; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        double jb = 0.0;
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-#pragma unroll
-          for (int l = 0; l < ND; ++l) {
-            const double x = double(v[((i * NB + j) * NC + k) * ND + l]);
-            jb = fma(x, Pcd[k][l], jb);
-            jket[k][l] = fma(x, Pab[i][j], jket[k][l]);
-            kac[i][k] = fma(x, Pbd[j][l], kac[i][k]);
-            kad[i][l] = fma(x, Pbc[j][k], kad[i][l]);
-            kbc[j][k] = fma(x, Pad[i][l], kbc[j][k]);
-            kbd[j][l] = fma(x, Pac[i][k], kbd[j][l]);
-          }
-        jbra[i][j] = fma(fj, jb, jbra[i][j]);
-      }
-    if (valid) {
-#pragma unroll
-      for (int k = 0; k < NC; ++k)
-#pragma unroll
-        for (int l = 0; l < ND; ++l) atomicAdd(&J[(l0 + k) * n + s0 + l], fj * jket[k][l]);
-#pragma unroll
-      for (int i = 0; i < NA; ++i) {
-#pragma unroll
-        for (int k = 0; k < NC; ++k) atomicAdd(&K[(m0 + i) * n + l0 + k], fk * kac[i][k]);
-#pragma unroll
-        for (int l = 0; l < ND; ++l) atomicAdd(&K[(m0 + i) * n + s0 + l], fk * kad[i][l]);
-      }
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-#pragma unroll
-        for (int k = 0; k < NC; ++k) atomicAdd(&K[(n0 + j) * n + l0 + k], fk * kbc[j][k]);
-#pragma unroll
-        for (int l = 0; l < ND; ++l) atomicAdd(&K[(n0 + j) * n + s0 + l], fk * kbd[j][l]);
-      }
-    }
+    for (int l = 0; l < ND; ++l) kbd[j][l] = 0.0;
   }
 #pragma unroll
   for (int i = 0; i < NA; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const double s = wave_sum(jbra[i][j]);
-      if (lane == 0) atomicAdd(&J[(m0 + i) * n + n0 + j], s);
+      double jb = 0.0;
+#pragma unroll
+      for (int k = 0; k < NC; ++k)
+#pragma unroll
+        for (int l = 0; l < ND; ++l) {
+          const double x = double(v[((i * NB + j) * NC + k) * ND + l]);
+          jb = fma(x, Pcd[k][l], jb);
+          jket[k][l] = fma(x, Pab[i][j], jket[k][l]);
+          kac[i][k] = fma(x, Pbd[j][l], kac[i][k]);
+          kad[i][l] = fma(x, Pbc[j][k], kad[i][l]);
+          kbc[j][k] = fma(x, Pad[i][l], kbc[j][k]);
+          kbd[j][l] = fma(x, Pac[i][k], kbd[j][l]);
+        }
+      jbra[i][j] = fj * jb;
     }
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+      for (int l = 0; l < ND; ++l) atomicAdd(&J[(l0 + k) * n + s0 + l], fj * jket[k][l]);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) atomicAdd(&K[(m0 + i) * n + l0 + k], fk * kac[i][k]);
+#pragma unroll
+      for (int l = 0; l < ND; ++l) atomicAdd(&K[(m0 + i) * n + s0 + l], fk * kad[i][l]);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) atomicAdd(&K[(n0 + j) * n + l0 + k], fk * kbc[j][k]);
+#pragma unroll
+      for (int l = 0; l < ND; ++l) atomicAdd(&K[(n0 + j) * n + s0 + l], fk * kbd[j][l]);
+    }
+  }
+  if (single) {
+    // one bra pair for the whole wavefront: reduce its J block first
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const double s = wave_sum(jbra[i][j]);
+        if (lane == 0) atomicAdd(&J[(m0 + i) * n + n0 + j], s);
+      }
+  } else if (valid) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) atomicAdd(&J[(m0 + i) * n + n0 + j], jbra[i][j]);
+  }
 }
 
 // Q for each pair of class (LA LB|LA LB): sqrt(max |(mn|mn)|).

@@ -7,6 +7,7 @@ namespace bscf {
 struct GradArgs {
   const WorkItem* items;
   int nitems;
+  const WorkRow* rows;
   const ShellPair* pairs;
   const PrimPair* prims;
   const Shell* shells;

@@ -40,10 +40,10 @@ __device__ __forceinline__ void grad_block_body(const PrimPair* __restrict__ bp,
     for (int k = 0; k < CG::NLB; ++k) LB[k] = 0;
 #pragma unroll
     for (int k = 0; k < CG::NLC; ++k) LC[k] = 0;
-    for (int i = 0; i < nb; ++i) {
-      const PrimPair B = bp[i];
-      for (int j = 0; j < nk; ++j) {
-        const PrimPair Q = kp[j];
+    for (int j = 0; j < nk; ++j) {
+      const PrimPair Q = kp[j];
+      for (int i = 0; i < nb; ++i) {
+        const PrimPair B = bp[i];
         const double pq = B.p + Q.p;
         const double rpq = rsqrt(pq);
         const double oopq = rpq * rpq;
@@ -61,10 +61,10 @@ __device__ __forceinline__ void grad_block_body(const PrimPair* __restrict__ bp,
     }
     CG::template con<R>(RA, RB, RC, LA, LB, LC, AB[0], AB[1], AB[2], CD[0], CD[1], CD[2], G, g9);
   } else {
-    for (int i = 0; i < nb; ++i) {
-      const PrimPair B = bp[i];
-      for (int j = 0; j < nk; ++j) {
-        const PrimPair Q = kp[j];
+    for (int j = 0; j < nk; ++j) {
+      const PrimPair Q = kp[j];
+      for (int i = 0; i < nb; ++i) {
+        const PrimPair B = bp[i];
         const double pq = B.p + Q.p;
         const double rpq = rsqrt(pq);
         const double oopq = rpq * rpq;
@@ -107,7 +107,10 @@ __global__ __launch_bounds__(256) void grad_kernel(GradArgs a) {
   const int item_id = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
   if (item_id >= a.nitems) return;
   const WorkItem it = a.items[item_id];
-  const ShellPair bra = a.pairs[it.bra];
+  int bid, kid;
+  bool single;
+  const bool valid = lane_quartet(it, a.rows, a.kets, lane, bid, kid, single);
+  const ShellPair bra = a.pairs[bid];
   const Shell sa = a.shells[bra.a], sb = a.shells[bra.b];
   const int inst = sa.inst;
   const long long mo = a.moff[inst];
@@ -115,65 +118,58 @@ __global__ __launch_bounds__(256) void grad_kernel(GradArgs a) {
   const double* __restrict__ P = a.P + mo;
   const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
   const int m0 = sa.bf, n0 = sb.bf;
-  double Pab[NA][NB];
+  const ShellPair ket = a.pairs[kid];
+  const Shell sc = a.shells[ket.a], sd = a.shells[ket.b];
+  const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
+  const double deg = ((bra.a == bra.b) ? 1.0 : 2.0) * ((ket.a == ket.b) ? 1.0 : 2.0) *
+                     ((kid == bid) ? 1.0 : 2.0);
+  const double fac = valid ? 0.5 * deg : 0.0;
+  const int l0 = sc.bf, s0 = sd.bf;
+  double G[NOUT];
 #pragma unroll
   for (int i = 0; i < NA; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) Pab[i][j] = P[(m0 + i) * n + n0 + j];
-  const double gab = (bra.a == bra.b) ? 1.0 : 2.0;
-  double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
-
-  for (int base = 0; base < it.nket; base += kWave) {
-    const bool valid = base + lane < it.nket;
-    const int kid = a.kets[it.ket0 + (valid ? base + lane : 0)];
-    const ShellPair ket = a.pairs[kid];
-    const Shell sc = a.shells[ket.a], sd = a.shells[ket.b];
-    const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
-    const double deg = gab * ((ket.a == ket.b) ? 1.0 : 2.0) * ((kid == it.bra) ? 1.0 : 2.0);
-    const double fac = valid ? 0.5 * deg : 0.0;
-    const int l0 = sc.bf, s0 = sd.bf;
-    double G[NOUT];
+    for (int j = 0; j < NB; ++j) {
+      const double pab = P[(m0 + i) * n + n0 + j];
 #pragma unroll
-    for (int i = 0; i < NA; ++i)
+      for (int k = 0; k < NC; ++k)
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-#pragma unroll
-          for (int l = 0; l < ND; ++l) {
-            const double pcd = P[(l0 + k) * n + s0 + l];
-            const double pac = P[(m0 + i) * n + l0 + k], pbd = P[(n0 + j) * n + s0 + l];
-            const double pad = P[(m0 + i) * n + s0 + l], pbc = P[(n0 + j) * n + l0 + k];
-            G[((i * NB + j) * NC + k) * ND + l] =
-                fac * (Pab[i][j] * pcd - 0.25 * (pac * pbd + pad * pbc));
-          }
-    double g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if constexpr (CG::LA + CG::LB + CG::LC + CG::LD >= 5) {
-      grad_block_outline<CG>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB,
-                             CD, a.boys64, G, g9);
-    } else {
-      grad_block_body<CG>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
-                          a.boys64, G, g9);
+        for (int l = 0; l < ND; ++l) {
+          const double pcd = P[(l0 + k) * n + s0 + l];
+          const double pac = P[(m0 + i) * n + l0 + k], pbd = P[(n0 + j) * n + s0 + l];
+          const double pad = P[(m0 + i) * n + s0 + l], pbc = P[(n0 + j) * n + l0 + k];
+          G[((i * NB + j) * NC + k) * ND + l] = fac * (pab * pcd - 0.25 * (pac * pbd + pad * pbc));
+        }
     }
+  double g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if constexpr (CG::LA + CG::LB + CG::LC + CG::LD >= 5) {
+    grad_block_outline<CG>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB,
+                           CD, a.boys64, G, g9);
+  } else {
+    grad_block_body<CG>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
+                        a.boys64, G, g9);
+  }
+  if (valid) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      gA[d] += g9[d];
-      gB[d] += g9[3 + d];
-    }
-    if (valid) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        atomicAdd(&a.grad[3 * sc.atom + d], g9[6 + d]);
-        atomicAdd(&a.grad[3 * sd.atom + d], -(g9[d] + g9[3 + d] + g9[6 + d]));
-      }
+      atomicAdd(&a.grad[3 * sc.atom + d], g9[6 + d]);
+      atomicAdd(&a.grad[3 * sd.atom + d], -(g9[d] + g9[3 + d] + g9[6 + d]));
     }
   }
+  if (single) {
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const double x = gwave_sum(gA[d]), y = gwave_sum(gB[d]);
-    if (lane == 0) {
-      atomicAdd(&a.grad[3 * sa.atom + d], x);
-      atomicAdd(&a.grad[3 * sb.atom + d], y);
+    for (int d = 0; d < 3; ++d) {
+      const double x = gwave_sum(g9[d]), y = gwave_sum(g9[3 + d]);
+      if (lane == 0) {
+        atomicAdd(&a.grad[3 * sa.atom + d], x);
+        atomicAdd(&a.grad[3 * sb.atom + d], y);
+      }
+    }
+  } else if (valid) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      atomicAdd(&a.grad[3 * sa.atom + d], g9[d]);
+      atomicAdd(&a.grad[3 * sb.atom + d], g9[3 + d]);
     }
   }
 }
