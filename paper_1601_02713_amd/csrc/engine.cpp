@@ -219,6 +219,11 @@ struct bscf_ctx {
   hipStream_t aux[kAux] = {};
   hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
   hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;   // whole Fock build (profiling)
+  // per-lane private (scratch) bytes of every class kernel: [class][fp64, fp32, grad].
+  // The runtime reserves scratch per hardware queue for full occupancy, so
+  // kernels that use scratch all go to aux[0]; only scratch-free kernels
+  // overlap on the other streams.
+  int private_bytes[kNumQuartetClasses][3] = {};
   double t_fock_gpu_ms = 0;
   rocblas_handle blas = nullptr;
 
@@ -627,11 +632,14 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
   HIPCHK(hipEventRecord(c->ev_fork, c->stream));
   for (int k = 0; k < bscf_ctx::kAux; ++k) HIPCHK(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
   int slot = 0;
+  const int pcol = precision == BSCF_MIXED ? 1 : 0;
   for (int qq = kNumQuartetClasses - 1; qq >= 0; --qq) {
     const int q = qq;
     auto& W = c->work[q];
     if (W.items.empty()) continue;
-    const hipStream_t s = c->aux[slot++ % bscf_ctx::kAux];
+    const hipStream_t s = c->private_bytes[q][pcol] != 0
+                              ? c->aux[0]
+                              : c->aux[1 + slot++ % (bscf_ctx::kAux - 1)];
     a.items = W.d_items.p;
     a.rows = W.d_rows.p;
     a.nitems = (int)W.items.size();
@@ -723,6 +731,16 @@ bscf_status bscf_create(int hip_device, void* hip_stream, bscf_ctx** out) {
       HIPCHK(hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming));
     }
     HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    {
+      const QuartetClass* qc = quartet_classes();
+      for (int q = 0; q < kNumQuartetClasses; ++q) {
+        c->private_bytes[q][0] = qc[q].fock_private_bytes(0);
+        c->private_bytes[q][1] = qc[q].fock_private_bytes(1);
+        c->private_bytes[q][2] = qc[q].grad_private_bytes();
+        for (int k = 0; k < 3; ++k)
+          need(c->private_bytes[q][k] >= 0, BSCF_E_DEVICE, "hipFuncGetAttributes failed");
+      }
+    }
     BLASCHK(rocblas_create_handle(&c->blas));
     BLASCHK(rocblas_set_stream(c->blas, c->stream));
     std::vector<double> tab(kBoysRows * kBoysCols);
@@ -1266,7 +1284,10 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
       ga.items = W.d_items.p;
       ga.rows = W.d_rows.p;
       ga.nitems = (int)W.items.size();
-      grad_launcher(q)(ga, c->aux[slot++ % bscf_ctx::kAux]);
+      const hipStream_t s = c->private_bytes[q][2] != 0
+                                ? c->aux[0]
+                                : c->aux[1 + slot++ % (bscf_ctx::kAux - 1)];
+      grad_launcher(q)(ga, s);
     }
     for (int k = 0; k < bscf_ctx::kAux; ++k) {
       HIPCHK(hipEventRecord(c->ev_join[k], c->aux[k]));
@@ -1428,7 +1449,9 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
         << "\": {\"quartets\": " << W.nquart << ", \"prim_quartets\": " << W.nprimq
         << ", \"items\": " << W.items.size() << ", \"done_quartets\": " << W.done_quart
         << ", \"done_prim_quartets\": " << W.done_primq << ", \"done_flops\": " << flops
-        << ", \"kernel_ms\": " << W.kernel_ms << ", \"launches\": " << W.launches << "}";
+        << ", \"kernel_ms\": " << W.kernel_ms << ", \"launches\": " << W.launches
+        << ", \"private_bytes\": [" << c->private_bytes[q][0] << ", " << c->private_bytes[q][1]
+        << ", " << c->private_bytes[q][2] << "]}";
     }
     s << "}}";
     const std::string str = s.str();

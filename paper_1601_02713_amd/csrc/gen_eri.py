@@ -444,6 +444,13 @@ def main(outdir):
                if la + lb + lc + ld < 7 else "  (void)fp32;  // rare heavy class: FP64 in every precision mode\n ") +
               f" hipLaunchKernelGGL((fock_kernel<Cls{tag}, double>), dim3(blocks), dim3(256), 0, s, a);",
               "}",
+              f"int fock_private_bytes_{tag}(int fp32) {{",
+              "  hipFuncAttributes at{};",
+              (f"  if (fp32) {{ if (hipFuncGetAttributes(&at, reinterpret_cast<const void*>(&fock_kernel<Cls{tag}, float>)) != hipSuccess) return -1; }}\n  else"
+               if la + lb + lc + ld < 7 else "  (void)fp32;\n "),
+              f" if (hipFuncGetAttributes(&at, reinterpret_cast<const void*>(&fock_kernel<Cls{tag}, double>)) != hipSuccess) return -1;",
+              "  return (int)at.localSizeBytes;",
+              "}",
               f"void launch_tensor_{tag}(const TensorArgs& a, hipStream_t s) {{",
               "  if (a.nquart == 0) return;",
               f"  hipLaunchKernelGGL((tensor_kernel<Cls{tag}>), dim3((a.nquart + 63) / 64), dim3(64), 0, s, a);",
@@ -510,6 +517,11 @@ def main(outdir):
               "  const int blocks = (a.nitems + 3) / 4;",
               "  if (blocks == 0) return;",
               f"  hipLaunchKernelGGL((grad_kernel<ClsG{tag}>), dim3(blocks), dim3(256), 0, s, a);",
+              "}",
+              f"int grad_private_bytes_{tag}() {{",
+              "  hipFuncAttributes at{};",
+              f"  if (hipFuncGetAttributes(&at, reinterpret_cast<const void*>(&grad_kernel<ClsG{tag}>)) != hipSuccess) return -1;",
+              "  return (int)at.localSizeBytes;",
               "}", "}  // namespace bscf", ""]
         write_if_changed(os.path.join(outdir, f"grad_{tag}.hip"), "\n".join(tu))
         table[tag]["grad_vrr_flops_per_prim"] = gfl
@@ -520,18 +532,22 @@ def main(outdir):
     for (la, lb, lc, ld) in classes:
         tag = f"{la}{lb}{lc}{ld}"
         reg.append(f"void launch_fock_{tag}(const FockArgs&, int, hipStream_t);")
+        reg.append(f"int fock_private_bytes_{tag}(int);")
+        reg.append(f"int grad_private_bytes_{tag}();")
         reg.append(f"void launch_tensor_{tag}(const TensorArgs&, hipStream_t);")
     for (la, lb) in pair_classes():
         reg.append(f"void launch_schwarz_{la}{lb}(const SchwarzArgs&, hipStream_t);")
     reg.append(f"constexpr int kNumQuartetClasses = {len(classes)};")
     reg.append("struct QuartetClass { int la, lb, lc, ld; void (*fock)(const FockArgs&, int, hipStream_t);")
-    reg.append("  void (*tensor)(const TensorArgs&, hipStream_t); double vrr_flops, hrr_flops; };")
+    reg.append("  void (*tensor)(const TensorArgs&, hipStream_t); double vrr_flops, hrr_flops;")
+    reg.append("  int (*fock_private_bytes)(int); int (*grad_private_bytes)(); };")
     reg.append("inline const QuartetClass* quartet_classes() {")
     reg.append("  static const QuartetClass t[] = {")
     for (la, lb, lc, ld) in classes:
         tag = f"{la}{lb}{lc}{ld}"
         reg.append(f"    {{{la}, {lb}, {lc}, {ld}, launch_fock_{tag}, launch_tensor_{tag}, "
-                   f"{table[tag]['vrr_flops_per_prim']}.0, {table[tag]['hrr_flops']}.0}},")
+                   f"{table[tag]['vrr_flops_per_prim']}.0, {table[tag]['hrr_flops']}.0, "
+                   f"fock_private_bytes_{tag}, grad_private_bytes_{tag}}},")
     reg += ["  };", "  return t;", "}"]
     for (la, lb, lc, ld) in classes:
         reg.append(f"void launch_grad_{la}{lb}{lc}{ld}(const GradArgs&, hipStream_t);")
