@@ -220,9 +220,10 @@ struct bscf_ctx {
   hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
   hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;   // whole Fock build (profiling)
   // per-lane private (scratch) bytes of every class kernel: [class][fp64, fp32, grad].
-  // The runtime reserves scratch per hardware queue for full occupancy, so
-  // kernels that use scratch all go to aux[0]; only scratch-free kernels
-  // overlap on the other streams.
+  // The runtime reserves (and keeps) scratch per hardware queue for full
+  // occupancy, so every kernel that uses scratch (class kernels, one-electron
+  // and Schwarz kernels) runs on the context's own stream; only scratch-free
+  // class kernels overlap on the auxiliary streams.
   int private_bytes[kNumQuartetClasses][3] = {};
   double t_fock_gpu_ms = 0;
   rocblas_handle blas = nullptr;
@@ -637,9 +638,8 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
     const int q = qq;
     auto& W = c->work[q];
     if (W.items.empty()) continue;
-    const hipStream_t s = c->private_bytes[q][pcol] != 0
-                              ? c->aux[0]
-                              : c->aux[1 + slot++ % (bscf_ctx::kAux - 1)];
+    const hipStream_t s = c->private_bytes[q][pcol] != 0 ? c->stream
+                                                          : c->aux[slot++ % bscf_ctx::kAux];
     a.items = W.d_items.p;
     a.rows = W.d_rows.p;
     a.nitems = (int)W.items.size();
@@ -1284,9 +1284,7 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
       ga.items = W.d_items.p;
       ga.rows = W.d_rows.p;
       ga.nitems = (int)W.items.size();
-      const hipStream_t s = c->private_bytes[q][2] != 0
-                                ? c->aux[0]
-                                : c->aux[1 + slot++ % (bscf_ctx::kAux - 1)];
+      const hipStream_t s = c->private_bytes[q][2] != 0 ? st : c->aux[slot++ % bscf_ctx::kAux];
       grad_launcher(q)(ga, s);
     }
     for (int k = 0; k < bscf_ctx::kAux; ++k) {
