@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -219,12 +220,23 @@ struct bscf_ctx {
   hipStream_t aux[kAux] = {};
   hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
   hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;   // whole Fock build (profiling)
+  // Kernel variant per class: 0 = one quartet per lane, 1 = one quartet per
+  // wavefront (cooperative); [precision mode][class] for the Fock build and
+  // [class] for the gradient.  Chosen by timing both on the current work
+  // lists (autotune) unless BSCF_VARIANT=lane|coop forces one.
+  int fock_variant[2][kNumQuartetClasses] = {};
+  int grad_variant[kNumQuartetClasses] = {};
+  bool fock_tuned[2] = {false, false};
+  bool grad_tuned = false;
+  float tune_ms[2][kNumQuartetClasses][2] = {};
+  float tune_grad_ms[kNumQuartetClasses][2] = {};
   // per-lane private (scratch) bytes of every class kernel: [class][fp64, fp32, grad].
   // The runtime reserves (and keeps) scratch per hardware queue for full
   // occupancy, so every kernel that uses scratch (class kernels, one-electron
   // and Schwarz kernels) runs on the context's own stream; only scratch-free
   // class kernels overlap on the auxiliary streams.
   int private_bytes[kNumQuartetClasses][3] = {};
+  int coop_bytes[kNumQuartetClasses][2] = {};   // cooperative fock, gradient
   double t_fock_gpu_ms = 0;
   rocblas_handle blas = nullptr;
 
@@ -601,8 +613,57 @@ void build_work(bscf_ctx* c, double tau) {
   c->work_tau = tau;
 }
 
+// Time the lane and cooperative kernels of every class that has both on the
+// current work lists (second of two runs each, into throwaway J and K) and keep
+// the faster; BSCF_VARIANT=lane|coop forces a choice.
+void autotune_fock(bscf_ctx* c, int pcol) {
+  const char* env = getenv("BSCF_VARIANT");
+  const QuartetClass* qc = quartet_classes();
+  FockArgs a;
+  a.pairs = c->d_pairs.p;
+  a.prims = c->d_prims.p;
+  a.shells = c->d_shells.p;
+  a.kets = c->d_kets.p;
+  a.moff = c->d_moff.p;
+  a.nbf = c->d_nbf.p;
+  a.P = c->P.p;
+  a.J = c->tmp1.p;
+  a.K = c->tmp2.p;
+  a.boys64 = c->d_boys64.p;
+  a.boys32 = c->d_boys32.p;
+  a.active = c->d_all_active.p;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (int q = 0; q < kNumQuartetClasses; ++q) {
+    auto& W = c->work[q];
+    if (!qc[q].fock || W.items.empty()) continue;
+    if (env && !strcmp(env, "lane")) { c->fock_variant[pcol][q] = 0; continue; }
+    if (env && !strcmp(env, "coop")) { c->fock_variant[pcol][q] = 1; continue; }
+    a.items = W.d_items.p;
+    a.rows = W.d_rows.p;
+    a.nitems = (int)W.items.size();
+    for (int v = 0; v < 2; ++v) {
+      for (int rep = 0; rep < 2; ++rep) {
+        HIPCHK(hipEventRecord(e0, c->stream));
+        if (v) qc[q].coop_fock(a, c->stream);
+        else qc[q].fock(a, pcol, c->stream);
+        HIPCHK(hipEventRecord(e1, c->stream));
+      }
+      HIPCHK(hipEventSynchronize(e1));
+      HIPCHK(hipEventElapsedTime(&c->tune_ms[pcol][q][v], e0, e1));
+    }
+    c->fock_variant[pcol][q] = c->tune_ms[pcol][q][1] < c->tune_ms[pcol][q][0] ? 1 : 0;
+  }
+  HIPCHK(hipGetLastError());
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->fock_tuned[pcol] = true;
+}
+
 void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
   if (tau != c->work_tau) build_work(c, tau);
+  if (!c->fock_tuned[precision == BSCF_MIXED ? 1 : 0]) autotune_fock(c, precision == BSCF_MIXED ? 1 : 0);
   const double t0 = now_ms();
   launch_fill(c->J.p, c->mtot, 0.0, c->stream);
   launch_fill(c->K.p, c->mtot, 0.0, c->stream);
@@ -638,8 +699,9 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
     const int q = qq;
     auto& W = c->work[q];
     if (W.items.empty()) continue;
-    const hipStream_t s = c->private_bytes[q][pcol] != 0 ? c->stream
-                                                          : c->aux[slot++ % bscf_ctx::kAux];
+    const int var = c->fock_variant[pcol][q];
+    const int pbytes = var ? c->coop_bytes[q][0] : c->private_bytes[q][pcol];
+    const hipStream_t s = pbytes != 0 ? c->stream : c->aux[slot++ % bscf_ctx::kAux];
     a.items = W.d_items.p;
     a.rows = W.d_rows.p;
     a.nitems = (int)W.items.size();
@@ -650,7 +712,8 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
       }
       HIPCHK(hipEventRecord(W.ev0, s));
     }
-    qc[q].fock(a, precision == BSCF_MIXED ? 1 : 0, s);
+    if (var) qc[q].coop_fock(a, s);
+    else qc[q].fock(a, pcol, s);
     if (c->profiling) HIPCHK(hipEventRecord(W.ev1, s));
     for (int i = 0; i < c->ninst; ++i)
       if (!masked || c->h_active[i]) {
@@ -734,11 +797,17 @@ bscf_status bscf_create(int hip_device, void* hip_stream, bscf_ctx** out) {
     {
       const QuartetClass* qc = quartet_classes();
       for (int q = 0; q < kNumQuartetClasses; ++q) {
-        c->private_bytes[q][0] = qc[q].fock_private_bytes(0);
-        c->private_bytes[q][1] = qc[q].fock_private_bytes(1);
-        c->private_bytes[q][2] = qc[q].grad_private_bytes();
+        c->private_bytes[q][0] = qc[q].fock ? qc[q].fock_private_bytes(0) : 0;
+        c->private_bytes[q][1] = qc[q].fock ? qc[q].fock_private_bytes(1) : 0;
+        c->private_bytes[q][2] = qc[q].grad ? qc[q].grad_private_bytes() : 0;
+        c->coop_bytes[q][0] = qc[q].coop_private_bytes(0);
+        c->coop_bytes[q][1] = qc[q].coop_private_bytes(1);
         for (int k = 0; k < 3; ++k)
           need(c->private_bytes[q][k] >= 0, BSCF_E_DEVICE, "hipFuncGetAttributes failed");
+        for (int k = 0; k < 2; ++k)
+          need(c->coop_bytes[q][k] >= 0, BSCF_E_DEVICE, "hipFuncGetAttributes failed");
+        c->fock_variant[0][q] = c->fock_variant[1][q] = qc[q].fock ? 0 : 1;
+        c->grad_variant[q] = qc[q].grad ? 0 : 1;
       }
     }
     BLASCHK(rocblas_create_handle(&c->blas));
@@ -923,6 +992,7 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->have_scf = false;
     c->have_C = false;
     c->work_tau = -1.0;
+    c->fock_tuned[0] = c->fock_tuned[1] = c->grad_tuned = false;
     c->guess.reset_batch(c->ninst);
     sync(c);
   });
@@ -1266,6 +1336,7 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
     }
     // two-electron part over the same screened work lists
     GradArgs ga;
+    ga.rows = nullptr;
     ga.pairs = c->d_pairs.p;
     ga.prims = c->d_prims.p;
     ga.shells = c->d_shells.p;
@@ -1275,6 +1346,37 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
     ga.P = c->P.p;
     ga.grad = c->d_grad.p;
     ga.boys64 = c->d_boys64.p;
+    const QuartetClass* qc = quartet_classes();
+    if (!c->grad_tuned) {
+      // time both gradient variants where both exist (into a throwaway buffer)
+      const char* env = getenv("BSCF_VARIANT");
+      GradArgs gt = ga;
+      gt.grad = c->tmp1.p;
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      for (int q = 0; q < kNumQuartetClasses; ++q) {
+        auto& W = c->work[q];
+        if (!qc[q].grad || W.items.empty()) continue;
+        if (env && !strcmp(env, "lane")) { c->grad_variant[q] = 0; continue; }
+        if (env && !strcmp(env, "coop")) { c->grad_variant[q] = 1; continue; }
+        gt.items = W.d_items.p;
+        gt.rows = W.d_rows.p;
+        gt.nitems = (int)W.items.size();
+        for (int v = 0; v < 2; ++v) {
+          HIPCHK(hipEventRecord(e0, st));
+          if (v) qc[q].coop_grad(gt, st);
+          else qc[q].grad(gt, st);
+          HIPCHK(hipEventRecord(e1, st));
+          HIPCHK(hipEventSynchronize(e1));
+          HIPCHK(hipEventElapsedTime(&c->tune_grad_ms[q][v], e0, e1));
+        }
+        c->grad_variant[q] = c->tune_grad_ms[q][1] < c->tune_grad_ms[q][0] ? 1 : 0;
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      c->grad_tuned = true;
+    }
     HIPCHK(hipEventRecord(c->ev_fork, st));
     for (int k = 0; k < bscf_ctx::kAux; ++k) HIPCHK(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
     int slot = 0;
@@ -1284,8 +1386,11 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
       ga.items = W.d_items.p;
       ga.rows = W.d_rows.p;
       ga.nitems = (int)W.items.size();
-      const hipStream_t s = c->private_bytes[q][2] != 0 ? st : c->aux[slot++ % bscf_ctx::kAux];
-      grad_launcher(q)(ga, s);
+      const int var = c->grad_variant[q];
+      const int pbytes = var ? c->coop_bytes[q][1] : c->private_bytes[q][2];
+      const hipStream_t s = pbytes != 0 ? st : c->aux[slot++ % bscf_ctx::kAux];
+      if (var) qc[q].coop_grad(ga, s);
+      else qc[q].grad(ga, s);
     }
     for (int k = 0; k < bscf_ctx::kAux; ++k) {
       HIPCHK(hipEventRecord(c->ev_join[k], c->aux[k]));
@@ -1449,7 +1554,10 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
         << ", \"done_prim_quartets\": " << W.done_primq << ", \"done_flops\": " << flops
         << ", \"kernel_ms\": " << W.kernel_ms << ", \"launches\": " << W.launches
         << ", \"private_bytes\": [" << c->private_bytes[q][0] << ", " << c->private_bytes[q][1]
-        << ", " << c->private_bytes[q][2] << "]}";
+        << ", " << c->private_bytes[q][2] << "], \"variant\": [" << c->fock_variant[0][q] << ", "
+        << c->fock_variant[1][q] << ", " << c->grad_variant[q] << "], \"tune_ms\": ["
+        << c->tune_ms[0][q][0] << ", " << c->tune_ms[0][q][1] << ", " << c->tune_grad_ms[q][0]
+        << ", " << c->tune_grad_ms[q][1] << "]}";
     }
     s << "}}";
     const std::string str = s.str();

@@ -36,6 +36,7 @@ from __future__ import annotations
 import itertools
 import json
 import os
+import re
 import sys
 
 LMAX = 2  # s, p, d
@@ -402,19 +403,93 @@ def quartet_classes():
     return out
 
 
+LANE_E_MAX = 5   # one-lane-per-quartet Fock kernels up to this total L
+LANE_G_MAX = 4   # one-lane-per-quartet gradient kernels up to this total L
+
+
+def coop_tu(la, lb, lc, ld):
+    """Cooperative kernels of one class: node tables, traits, launchers."""
+    import gen_coop
+    tag = f"{la}{lb}{lc}{ld}"
+    pe = gen_coop.energy_program(la, lb, lc, ld)
+    pg = gen_coop.grad_program(la, lb, lc, ld)
+
+    def traits(name, p, prefix, grad):
+        acc = [f"  __device__ static const {t}* {f}() {{ return {prefix}_{f}; }}"
+               for t, f in [("int", "vrr_lstart"), ("unsigned short", "vrr_dst"), ("int", "vrr_t0"),
+                            ("unsigned short", "vrr_src"), ("unsigned char", "vrr_sel"),
+                            ("double", "vrr_mult"), ("int", "hrr_lstart"), ("unsigned short", "hrr_dst"),
+                            ("int", "hrr_t0"), ("unsigned short", "hrr_src"), ("unsigned char", "hrr_sel"),
+                            ("double", "hrr_mult"), ("unsigned short", "acc_slot"),
+                            ("unsigned short", "tgt_slot"), ("unsigned char", "tgt_w")]]
+        if grad:
+            acc += [f"  __device__ static const {t}* {f}() {{ return {prefix}_{f}; }}"
+                    for t, f in [("int", "con_lstart"), ("unsigned short", "con_slot"),
+                                 ("unsigned char", "con_g"), ("unsigned short", "con_G"),
+                                 ("double", "con_c")]]
+            extra = f", NCLEV = {len(p['con_lstart']) - 1}"
+        else:
+            acc += [f"  __device__ static const {t}* {f}() {{ return {prefix}_{f}; }}"
+                    for t, f in [("unsigned short", "out_slot"), ("double", "norm")]]
+            extra = ""
+        return "\n".join([
+            f"struct {name} {{",
+            f"  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld}, L = {p['L']};",
+            f"  static constexpr int NSLOT = {p['nslot']}, NACC = {p['nacc']}, NOUT = {p['nout']}, "
+            f"FSLOT = {p['fslot']};",
+            f"  static constexpr int NVLEV = {len(p['vrr'][0]) - 1}, NHLEV = {len(p['hrr'][0]) - 1}{extra};",
+        ] + acc + ["};", ""])
+
+    lines = [f"// generated by gen_eri.py / gen_coop.py: cooperative kernels of class ({la}{lb}|{lc}{ld})",
+             '#include "coop_kernel.h"', "namespace bscf {", "namespace {",
+             gen_coop.emit_tables(f"cE{tag}", pe), gen_coop.emit_tables(f"cG{tag}", pg, grad=True),
+             traits(f"CoopE{tag}", pe, f"cE{tag}", False), traits(f"CoopG{tag}", pg, f"cG{tag}", True),
+             "}  // namespace",
+             f"void launch_coop_fock_{tag}(const FockArgs& a, hipStream_t s) {{",
+             "  if (a.nitems == 0) return;",
+             f"  hipLaunchKernelGGL((coop_fock_kernel<CoopE{tag}>), dim3(a.nitems * 64), dim3(64), 0, s, a);",
+             "}",
+             f"void launch_coop_grad_{tag}(const GradArgs& a, hipStream_t s) {{",
+             "  if (a.nitems == 0) return;",
+             f"  hipLaunchKernelGGL((coop_grad_kernel<CoopG{tag}>), dim3(a.nitems * 64), dim3(64), 0, s, a);",
+             "}",
+             f"void launch_coop_tensor_{tag}(const TensorArgs& a, hipStream_t s) {{",
+             "  if (a.nquart == 0) return;",
+             f"  hipLaunchKernelGGL((coop_tensor_kernel<CoopE{tag}>), dim3(a.nquart), dim3(64), 0, s, a);",
+             "}",
+             f"int coop_private_bytes_{tag}(int which) {{",
+             "  hipFuncAttributes at{};",
+             f"  const void* f = which ? reinterpret_cast<const void*>(&coop_grad_kernel<CoopG{tag}>)",
+             f"                        : reinterpret_cast<const void*>(&coop_fock_kernel<CoopE{tag}>);",
+             "  if (hipFuncGetAttributes(&at, f) != hipSuccess) return -1;",
+             "  return (int)at.localSizeBytes;",
+             "}"]
+    if (la, lb) == (lc, ld):
+        lines += [f"void launch_coop_schwarz_{la}{lb}(const SchwarzArgs& a, hipStream_t s) {{",
+                  "  if (a.npairs == 0) return;",
+                  f"  hipLaunchKernelGGL((coop_schwarz_kernel<CoopE{tag}>), dim3(a.npairs), dim3(64), 0, s, a);",
+                  "}"]
+    lines += ["}  // namespace bscf", ""]
+    return "\n".join(lines), pe, pg
+
+
 def main(outdir):
-    """Write eri_<tag>.h, fock_<tag>.hip per class, classes.h and eri_flops.json."""
+    """Write the per-class headers and translation units, classes.h and
+    eri_flops.json."""
     os.makedirs(outdir, exist_ok=True)
     table = {}
     classes = quartet_classes()
     for (la, lb, lc, ld) in classes:
         tag = f"{la}{lb}{lc}{ld}"
+        L = la + lb + lc + ld
         ev = (la, la + lb, lc, lc + ld)
         fn_v, nacc, fl_v, code_v = gen_vrr(*ev)
         fn_h, nacc_h, fl_h, code_h = gen_hrr(la, lb, lc, ld)
         assert nacc == nacc_h
         nout = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
-        struct = f"""struct Cls{tag} {{
+        table[tag] = dict(vrr_flops_per_prim=fl_v, hrr_flops=fl_h, nacc=nacc, ncart=nout)
+        if L <= LANE_E_MAX:
+            struct = f"""struct Cls{tag} {{
   static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld};
   static constexpr int NACC = {nacc}, NOUT = {nout};
   template <typename R>
@@ -431,49 +506,52 @@ def main(outdir):
   }}
 }};
 """
-        hdr = [f"// generated by gen_eri.py: class ({la}{lb}|{lc}{ld})", "#pragma once",
-               "#include <hip/hip_runtime.h>", "namespace bscf {", "", code_v, code_h, struct,
-               "}  // namespace bscf", ""]
-        write_if_changed(os.path.join(outdir, f"eri_{tag}.h"), "\n".join(hdr))
-        tu = [f"// generated by gen_eri.py: kernels of class ({la}{lb}|{lc}{ld})",
-              '#include "fock_kernel.h"', f'#include "eri_{tag}.h"', "namespace bscf {",
-              f"void launch_fock_{tag}(const FockArgs& a, int fp32, hipStream_t s) {{",
-              "  const int blocks = (a.nitems + 3) / 4;",
-              "  if (blocks == 0) return;",
-              (f"  if (fp32) hipLaunchKernelGGL((fock_kernel<Cls{tag}, float>), dim3(blocks), dim3(256), 0, s, a);\n  else"
-               if la + lb + lc + ld < 7 else "  (void)fp32;  // rare heavy class: FP64 in every precision mode\n ") +
-              f" hipLaunchKernelGGL((fock_kernel<Cls{tag}, double>), dim3(blocks), dim3(256), 0, s, a);",
-              "}",
-              f"int fock_private_bytes_{tag}(int fp32) {{",
-              "  hipFuncAttributes at{};",
-              (f"  if (fp32) {{ if (hipFuncGetAttributes(&at, reinterpret_cast<const void*>(&fock_kernel<Cls{tag}, float>)) != hipSuccess) return -1; }}\n  else"
-               if la + lb + lc + ld < 7 else "  (void)fp32;\n "),
-              f" if (hipFuncGetAttributes(&at, reinterpret_cast<const void*>(&fock_kernel<Cls{tag}, double>)) != hipSuccess) return -1;",
-              "  return (int)at.localSizeBytes;",
-              "}",
-              f"void launch_tensor_{tag}(const TensorArgs& a, hipStream_t s) {{",
-              "  if (a.nquart == 0) return;",
-              f"  hipLaunchKernelGGL((tensor_kernel<Cls{tag}>), dim3((a.nquart + 63) / 64), dim3(64), 0, s, a);",
-              "}"]
-        if (la, lb) == (lc, ld):
-            tu += [f"void launch_schwarz_{la}{lb}(const SchwarzArgs& a, hipStream_t s) {{",
-                   "  if (a.npairs == 0) return;",
-                   f"  hipLaunchKernelGGL((schwarz_kernel<Cls{tag}>), dim3((a.npairs + 255) / 256), dim3(256), 0, s, a);",
-                   "}"]
-        tu += ["}  // namespace bscf", ""]
-        write_if_changed(os.path.join(outdir, f"fock_{tag}.hip"), "\n".join(tu))
-        table[tag] = dict(vrr_flops_per_prim=fl_v, hrr_flops=fl_h, nacc=nacc, ncart=nout)
-    # gradient classes
+            hdr = [f"// generated by gen_eri.py: class ({la}{lb}|{lc}{ld})", "#pragma once",
+                   "#include <hip/hip_runtime.h>", "namespace bscf {", "", code_v, code_h, struct,
+                   "}  // namespace bscf", ""]
+            write_if_changed(os.path.join(outdir, f"eri_{tag}.h"), "\n".join(hdr))
+            tu = [f"// generated by gen_eri.py: kernels of class ({la}{lb}|{lc}{ld})",
+                  '#include "fock_kernel.h"', f'#include "eri_{tag}.h"', "namespace bscf {",
+                  f"void launch_fock_{tag}(const FockArgs& a, int fp32, hipStream_t s) {{",
+                  "  const int blocks = (a.nitems + 3) / 4;",
+                  "  if (blocks == 0) return;",
+                  f"  if (fp32) hipLaunchKernelGGL((fock_kernel<Cls{tag}, float>), dim3(blocks), dim3(256), 0, s, a);",
+                  f"  else hipLaunchKernelGGL((fock_kernel<Cls{tag}, double>), dim3(blocks), dim3(256), 0, s, a);",
+                  "}",
+                  f"int fock_private_bytes_{tag}(int fp32) {{",
+                  "  hipFuncAttributes at{};",
+                  f"  const void* f = fp32 ? reinterpret_cast<const void*>(&fock_kernel<Cls{tag}, float>)",
+                  f"                       : reinterpret_cast<const void*>(&fock_kernel<Cls{tag}, double>);",
+                  "  if (hipFuncGetAttributes(&at, f) != hipSuccess) return -1;",
+                  "  return (int)at.localSizeBytes;",
+                  "}",
+                  f"void launch_tensor_{tag}(const TensorArgs& a, hipStream_t s) {{",
+                  "  if (a.nquart == 0) return;",
+                  f"  hipLaunchKernelGGL((tensor_kernel<Cls{tag}>), dim3((a.nquart + 63) / 64), dim3(64), 0, s, a);",
+                  "}"]
+            if (la, lb) == (lc, ld):
+                tu += [f"void launch_schwarz_{la}{lb}(const SchwarzArgs& a, hipStream_t s) {{",
+                       "  if (a.npairs == 0) return;",
+                       f"  hipLaunchKernelGGL((schwarz_kernel<Cls{tag}>), dim3((a.npairs + 255) / 256), dim3(256), 0, s, a);",
+                       "}"]
+            tu += ["}  // namespace bscf", ""]
+            write_if_changed(os.path.join(outdir, f"fock_{tag}.hip"), "\n".join(tu))
+        ctu, pe, pg = coop_tu(la, lb, lc, ld)
+        write_if_changed(os.path.join(outdir, f"coop_{tag}.hip"), ctu)
+        table[tag]["coop_lds_bytes"] = [8 * pe["nslot"], 8 * (pg["nslot"] + nout)]
+    # gradient classes (lane form)
     for (la, lb, lc, ld) in classes:
         tag = f"{la}{lb}{lc}{ld}"
         sets, sizes, gfl, cfl, code = gen_grad(la, lb, lc, ld)
+        table[tag]["grad_vrr_flops_per_prim"] = gfl
+        table[tag]["grad_contract_flops"] = cfl
+        if la + lb + lc + ld > LANE_G_MAX:
+            continue
         names = [s[0] for s in sets]
         allsets = ["RA", "RB", "RC", "LA", "LB", "LC"]
-        prim = la + lb + lc + ld >= 6
         szs = ", ".join(f"N{s} = {sizes.get(s, 1)}" for s in allsets)
         arg = ", ".join(s for s in names)
-        if not prim:
-            wrap = f"""struct ClsG{tag} {{
+        wrap = f"""struct ClsG{tag} {{
   static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld};
   static constexpr bool PRIM = false;
   static constexpr int {szs};
@@ -489,21 +567,6 @@ def main(outdir):
       const R* LB, const R* LC, R ABx, R ABy, R ABz, R CDx, R CDy, R CDz, const double* G,
       double* g) {{
     gcon_{tag}<R>({arg}, ABx, ABy, ABz, CDx, CDy, CDz, G, g);
-  }}
-}};
-"""
-        else:
-            wrap = f"""struct ClsG{tag} {{
-  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld};
-  static constexpr bool PRIM = true;
-  static constexpr int {szs};
-  template <typename R>
-  __device__ static __forceinline__ void prim(const R* F, R PAx, R PAy, R PAz, R WPx, R WPy,
-      R WPz, R QCx, R QCy, R QCz, R WQx, R WQy, R WQz, R oo2p, R oo2q, R oo2pq, R rho_p2,
-      R rho_q2, R wa, R wb, R wc, R ABx, R ABy, R ABz, R CDx, R CDy, R CDz, const double* G,
-      double* g) {{
-    gprim_{tag}<R>(F, PAx, PAy, PAz, WPx, WPy, WPz, QCx, QCy, QCz, WQx, WQy, WQz, oo2p, oo2q,
-                   oo2pq, rho_p2, rho_q2, wa, wb, wc, ABx, ABy, ABz, CDx, CDy, CDz, G, g);
   }}
 }};
 """
@@ -524,42 +587,70 @@ def main(outdir):
               "  return (int)at.localSizeBytes;",
               "}", "}  // namespace bscf", ""]
         write_if_changed(os.path.join(outdir, f"grad_{tag}.hip"), "\n".join(tu))
-        table[tag]["grad_vrr_flops_per_prim"] = gfl
-        table[tag]["grad_contract_flops"] = cfl
+    # drop translation units of an earlier configuration
+    for fn in os.listdir(outdir):
+        m = re.match(r"(fock|grad|eri)_(\d{4})\.(hip|h)$", fn)
+        if not m:
+            continue
+        Lx = sum(int(ch) for ch in m.group(2))
+        lim = LANE_G_MAX if m.group(1) == "grad" else LANE_E_MAX
+        if Lx > lim:
+            os.remove(os.path.join(outdir, fn))
     # registry
     reg = ["// generated by gen_eri.py: launcher registry", "#pragma once",
            '#include "fock_kernel.h"', '#include "grad.h"', "namespace bscf {"]
     for (la, lb, lc, ld) in classes:
         tag = f"{la}{lb}{lc}{ld}"
-        reg.append(f"void launch_fock_{tag}(const FockArgs&, int, hipStream_t);")
-        reg.append(f"int fock_private_bytes_{tag}(int);")
-        reg.append(f"int grad_private_bytes_{tag}();")
-        reg.append(f"void launch_tensor_{tag}(const TensorArgs&, hipStream_t);")
+        L = la + lb + lc + ld
+        if L <= LANE_E_MAX:
+            reg.append(f"void launch_fock_{tag}(const FockArgs&, int, hipStream_t);")
+            reg.append(f"int fock_private_bytes_{tag}(int);")
+            reg.append(f"void launch_tensor_{tag}(const TensorArgs&, hipStream_t);")
+        if L <= LANE_G_MAX:
+            reg.append(f"void launch_grad_{tag}(const GradArgs&, hipStream_t);")
+            reg.append(f"int grad_private_bytes_{tag}();")
+        reg.append(f"void launch_coop_fock_{tag}(const FockArgs&, hipStream_t);")
+        reg.append(f"void launch_coop_grad_{tag}(const GradArgs&, hipStream_t);")
+        reg.append(f"void launch_coop_tensor_{tag}(const TensorArgs&, hipStream_t);")
+        reg.append(f"int coop_private_bytes_{tag}(int);")
     for (la, lb) in pair_classes():
-        reg.append(f"void launch_schwarz_{la}{lb}(const SchwarzArgs&, hipStream_t);")
+        if 2 * (la + lb) <= LANE_E_MAX:
+            reg.append(f"void launch_schwarz_{la}{lb}(const SchwarzArgs&, hipStream_t);")
+        else:
+            reg.append(f"void launch_coop_schwarz_{la}{lb}(const SchwarzArgs&, hipStream_t);")
     reg.append(f"constexpr int kNumQuartetClasses = {len(classes)};")
-    reg.append("struct QuartetClass { int la, lb, lc, ld; void (*fock)(const FockArgs&, int, hipStream_t);")
-    reg.append("  void (*tensor)(const TensorArgs&, hipStream_t); double vrr_flops, hrr_flops;")
-    reg.append("  int (*fock_private_bytes)(int); int (*grad_private_bytes)(); };")
-    reg.append("inline const QuartetClass* quartet_classes() {")
-    reg.append("  static const QuartetClass t[] = {")
+    reg += ["// lane: one quartet per lane (nullptr where not generated); coop: one per wavefront",
+            "struct QuartetClass {",
+            "  int la, lb, lc, ld;",
+            "  void (*fock)(const FockArgs&, int, hipStream_t);",
+            "  void (*coop_fock)(const FockArgs&, hipStream_t);",
+            "  void (*grad)(const GradArgs&, hipStream_t);",
+            "  void (*coop_grad)(const GradArgs&, hipStream_t);",
+            "  void (*tensor)(const TensorArgs&, hipStream_t);",
+            "  double vrr_flops, hrr_flops, grad_vrr_flops, grad_con_flops;",
+            "  int (*fock_private_bytes)(int);",
+            "  int (*grad_private_bytes)();",
+            "  int (*coop_private_bytes)(int);",
+            "};",
+            "inline const QuartetClass* quartet_classes() {",
+            "  static const QuartetClass t[] = {"]
     for (la, lb, lc, ld) in classes:
         tag = f"{la}{lb}{lc}{ld}"
-        reg.append(f"    {{{la}, {lb}, {lc}, {ld}, launch_fock_{tag}, launch_tensor_{tag}, "
-                   f"{table[tag]['vrr_flops_per_prim']}.0, {table[tag]['hrr_flops']}.0, "
-                   f"fock_private_bytes_{tag}, grad_private_bytes_{tag}}},")
+        L = la + lb + lc + ld
+        le, lg = L <= LANE_E_MAX, L <= LANE_G_MAX
+        t = table[tag]
+        reg.append(f"    {{{la}, {lb}, {lc}, {ld}, {f'launch_fock_{tag}' if le else 'nullptr'}, "
+                   f"launch_coop_fock_{tag}, {f'launch_grad_{tag}' if lg else 'nullptr'}, "
+                   f"launch_coop_grad_{tag}, {f'launch_tensor_{tag}' if le else f'launch_coop_tensor_{tag}'}, "
+                   f"{t['vrr_flops_per_prim']}.0, {t['hrr_flops']}.0, {t['grad_vrr_flops_per_prim']}.0, "
+                   f"{t['grad_contract_flops']}.0, {f'fock_private_bytes_{tag}' if le else 'nullptr'}, "
+                   f"{f'grad_private_bytes_{tag}' if lg else 'nullptr'}, coop_private_bytes_{tag}}},")
     reg += ["  };", "  return t;", "}"]
-    for (la, lb, lc, ld) in classes:
-        reg.append(f"void launch_grad_{la}{lb}{lc}{ld}(const GradArgs&, hipStream_t);")
-    reg.append("inline GradLauncher grad_launcher(int q) {")
-    reg.append("  static const GradLauncher t[] = {" + ", ".join(
-        f"launch_grad_{c[0]}{c[1]}{c[2]}{c[3]}" for c in classes) + "};")
-    reg.append("  return t[q];")
-    reg.append("}")
     reg.append(f"constexpr int kNumPairClasses = {len(pair_classes())};")
     reg.append("inline void (*schwarz_launcher(int la, int lb))(const SchwarzArgs&, hipStream_t) {")
     for (la, lb) in pair_classes():
-        reg.append(f"  if (la == {la} && lb == {lb}) return launch_schwarz_{la}{lb};")
+        fn = f"launch_schwarz_{la}{lb}" if 2 * (la + lb) <= LANE_E_MAX else f"launch_coop_schwarz_{la}{lb}"
+        reg.append(f"  if (la == {la} && lb == {lb}) return {fn};")
     reg += ["  return nullptr;", "}", "}  // namespace bscf", ""]
     write_if_changed(os.path.join(outdir, "classes.h"), "\n".join(reg))
     write_if_changed(os.path.join(outdir, "eri_flops.json"), json.dumps(table, indent=1))

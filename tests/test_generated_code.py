@@ -160,3 +160,81 @@ def test_generated_gradient_class(tag):
     # applies the component norms itself, with unit radial coefficients here
     ref = np.array([np.sum(G * der[cen, dd].ravel()) for cen in range(3) for dd in range(3)])
     assert np.abs(got - ref).max() <= 1e-11 * max(1.0, np.abs(ref).max()), (got, ref)
+
+
+# ------------------------------------------------ cooperative node programs
+import gen_coop  # noqa: E402
+
+
+def _contracted_oracle(shells, deriv=False):
+    """Oracle block for shells [(l, [alphas], [coefs], centre)] with the given
+    raw contraction coefficients (no renormalisation)."""
+    l, atom, nprim, pofs, bf, exps, coefs = [], [], [], [], [], [], []
+    nbf = 0
+    for k, (ll, al, co, X) in enumerate(shells):
+        l.append(ll); atom.append(k); nprim.append(len(al)); pofs.append(len(exps)); bf.append(nbf)
+        exps += list(al)
+        coefs += list(co)
+        nbf += (ll + 1) * (ll + 2) // 2
+    i32 = lambda v: np.array(v, np.int32)
+    b = dict(l=i32(l), atom=i32(atom), nprim=i32(nprim), pofs=i32(pofs), bf=i32(bf),
+             exps=np.array(exps), coefs=np.array(coefs), nbf=nbf, nsh=4,
+             xyz=np.array([s[3] for s in shells]), Z=i32([1] * 4))
+    return oracle.eri_quartet(b, 0, 1, 2, 3, deriv=deriv)
+
+
+def _program_inputs(shells, Lmax):
+    """Per-primitive-quartet Boys values and the 27 scalars of gen_coop."""
+    Fs, scs = [], []
+    (la, aa, ca, A), (lb, ab, cb, B), (lc, ac, cc, C), (ld, ad, cd, D) = shells
+    for ia, a in enumerate(aa):
+        for ib, b in enumerate(ab):
+            for ic, c in enumerate(ac):
+                for id_, d in enumerate(ad):
+                    sh = [(la, a, A), (lb, b, B), (lc, c, C), (ld, d, D)]
+                    env, pref, T, _ = _prim_inputs(sh)
+                    pref *= ca[ia] * cb[ib] * cc[ic] * cd[id_]
+                    Fs.append(list(_boys(Lmax, T) * pref))
+                    sc = [0.0] * gen_coop.NSEL
+                    for nm, k in gen_coop.SEL.items():
+                        sc[k] = 1.0 if nm == "one" else env[nm]
+                    scs.append(sc)
+    return Fs, scs
+
+
+def _rand_contracted(ls, nprim):
+    out = []
+    for l, k in zip(ls, nprim):
+        out.append((l, list(RNG.uniform(0.3, 2.5, k)), list(RNG.uniform(0.2, 1.0, k)),
+                    RNG.uniform(-1.0, 1.0, 3)))
+    return out
+
+
+@pytest.mark.parametrize("tag,nprim", [("0000", (3, 2, 1, 2)), ("1010", (2, 1, 2, 1)),
+                                       ("2121", (2, 1, 1, 2)), ("2211", (1, 2, 2, 1)),
+                                       ("2220", (1, 1, 1, 2)), ("2222", (1, 1, 1, 1))])
+def test_cooperative_energy_program(tag, nprim):
+    la, lb, lc, ld = map(int, tag)
+    prog = gen_coop.energy_program(la, lb, lc, ld)
+    sh = _rand_contracted([la, lb, lc, ld], nprim)
+    Fs, scs = _program_inputs(sh, la + lb + lc + ld)
+    got = np.array(gen_coop.interpret(prog, Fs, scs, scs[0]))
+    ref = _contracted_oracle(sh).ravel()
+    assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("tag,nprim", [("0000", (2, 2, 1, 2)), ("1000", (2, 1, 2, 1)),
+                                       ("2010", (1, 2, 2, 1)), ("1111", (2, 2, 2, 2)),
+                                       ("2111", (1, 2, 2, 1)), ("2121", (2, 1, 1, 2)),
+                                       ("2222", (1, 1, 1, 1))])
+def test_cooperative_gradient_program(tag, nprim):
+    la, lb, lc, ld = map(int, tag)
+    prog = gen_coop.grad_program(la, lb, lc, ld)
+    sh = _rand_contracted([la, lb, lc, ld], nprim)
+    Fs, scs = _program_inputs(sh, la + lb + lc + ld + 1)
+    nout = gen_eri.ncart(la) * gen_eri.ncart(lb) * gen_eri.ncart(lc) * gen_eri.ncart(ld)
+    G = RNG.standard_normal(nout)
+    got = np.array(gen_coop.interpret(prog, Fs, scs, scs[0], grad_G=list(G)))
+    _, der = _contracted_oracle(sh, deriv=True)
+    ref = np.array([np.sum(G * der[cen, dd].ravel()) for cen in range(3) for dd in range(3)])
+    assert np.abs(got - ref).max() <= 1e-11 * max(1.0, np.abs(ref).max()), (got, ref)

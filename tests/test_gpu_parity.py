@@ -182,3 +182,37 @@ def test_scf_staggered_convergence(eng, b631gs):
         r = oracle.scf(b, 1e-11, 1e-9)
         assert st[k] == 0
         assert abs(E[k] - r["E"]) < 1e-9, (k, it, E[k], r["E"])
+
+
+@pytest.mark.parametrize("variant", ["lane", "coop"])
+def test_jk_and_forces_each_kernel_variant(beadscf, b631gs, variant, monkeypatch):
+    """Both kernel forms of every class (one quartet per lane, one per
+    wavefront) against the oracle: J/K at a fixed density for a 3-water
+    cluster, and forces of a 2-water cluster."""
+    monkeypatch.setenv("BSCF_VARIANT", variant)
+    e = beadscf.Engine(0)
+    try:
+        inst = inputs.workload("w3")["instances"]
+        _setup(e, "6-31g*", inst)
+        b = oracle.build_basis(b631gs, *inst[0])
+        P = _rand_density(b["nbf"], 21)
+        J, K, _ = oracle.jk(b, P)
+        Jg, Kg = e.build_jk([P])
+        assert np.abs(Jg[0] - J).max() < 1e-11
+        assert np.abs(Kg[0] - K).max() < 1e-11
+        st = e.stats()["classes"]
+        for tag, v in st.items():
+            if v["items"]:
+                lane_exists = sum(map(int, tag)) <= 5
+                assert v["variant"][0] == (1 if variant == "coop" or not lane_exists else 0), tag
+        z, x = inputs.water_cluster(2, 13)
+        _setup(e, "6-31g*", [(z, x)])
+        E, it, status = e.run_scf(e_tol=1e-11, comm_tol=1e-9)
+        F = e.forces()[0]
+        bb = oracle.build_basis(b631gs, z, x)
+        r = oracle.scf(bb, 1e-11, 1e-9)
+        g = oracle.gradient(bb, r["P"], r["F"])
+        assert abs(E[0] - r["E"]) < 1e-9
+        assert np.abs(F + g).max() < 1e-8
+    finally:
+        e.close()
