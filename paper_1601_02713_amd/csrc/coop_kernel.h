@@ -112,6 +112,21 @@ __device__ __forceinline__ void coop_primitives(const PrimPair* __restrict__ bp,
   __syncthreads();
 }
 
+// Row and column basis functions of element t of the six digestion blocks,
+// listed as J_ab, J_cd, K_ac, K_ad, K_bc, K_bd (row-major each).
+template <int NA, int NB, int NC, int ND>
+__device__ __forceinline__ int2 block_rc(int t, int m0, int n0, int l0, int s0) {
+  constexpr int OCD = NA * NB, OAC = OCD + NC * ND, OAD = OAC + NA * NC, OBC = OAD + NA * ND,
+                OBD = OBC + NB * NC;
+  if (t < OCD) return make_int2(m0 + t / NB, n0 + t % NB);
+  if (t < OAC) { t -= OCD; return make_int2(l0 + t / ND, s0 + t % ND); }
+  if (t < OAD) { t -= OAC; return make_int2(m0 + t / NC, l0 + t % NC); }
+  if (t < OBC) { t -= OAD; return make_int2(m0 + t / ND, s0 + t % ND); }
+  if (t < OBD) { t -= OBC; return make_int2(n0 + t / NC, l0 + t % NC); }
+  t -= OBD;
+  return make_int2(n0 + t / ND, s0 + t % ND);
+}
+
 // Quartet of block b of a cooperative launch (one quartet per block).
 __device__ __forceinline__ bool coop_quartet(const WorkItem* items, const WorkRow* rows,
                                              const int* kets, int b, int& bid, int& kid) {
@@ -141,26 +156,82 @@ __global__ __launch_bounds__(64) void coop_fock_kernel(FockArgs a) {
                CP::hrr_mult(), sc, slots);
     __syncthreads();
   }
-  // digestion: one integral per lane at a time, FP64 atomics into J and K
-  constexpr int NB = ncart(CP::LB), NC = ncart(CP::LC), ND = ncart(CP::LD);
+  // digestion: the six density blocks go to LDS, then each lane contracts one
+  // element of one of the six J/K blocks and adds it with one atomic; lanes
+  // follow the column index, so an atomic instruction covers few segments
+  constexpr int NA = ncart(CP::LA), NB = ncart(CP::LB), NC = ncart(CP::LC), ND = ncart(CP::LD);
+  constexpr int OCD = NA * NB, OAC = OCD + NC * ND, OAD = OAC + NA * NC, OBC = OAD + NA * ND,
+                OBD = OBC + NB * NC, NPB = OBD + NB * ND;
+  __shared__ double pb[NPB];
   const long long mo = a.moff[inst];
   const int n = a.nbf[inst];
   const double* __restrict__ P = a.P + mo;
   double* J = a.J + mo;
   double* K = a.K + mo;
+  const int m0 = sa.bf, n0 = sb.bf, l0 = sc_.bf, s0 = sd.bf;
+  for (int t = threadIdx.x; t < NPB; t += kWave) {
+    const int2 rc = block_rc<NA, NB, NC, ND>(t, m0, n0, l0, s0);
+    pb[t] = P[rc.x * n + rc.y];
+  }
+  for (int e = threadIdx.x; e < CP::NOUT; e += kWave) slots[CP::out_slot()[e]] *= CP::norm()[e];
+  __syncthreads();
   const double g = ((bra.a == bra.b) ? 1.0 : 2.0) * ((ket.a == ket.b) ? 1.0 : 2.0) *
                    ((kid == bid) ? 1.0 : 2.0);
   const double fj = 0.5 * g, fk = 0.25 * g;
-  for (int e = threadIdx.x; e < CP::NOUT; e += kWave) {
-    const int l = e % ND, k = (e / ND) % NC, j = (e / (ND * NC)) % NB, i = e / (ND * NC * NB);
-    const int mu = sa.bf + i, nu = sb.bf + j, la = sc_.bf + k, si = sd.bf + l;
-    const double x = slots[CP::out_slot()[e]] * CP::norm()[e];
-    atomicAdd(&J[mu * n + nu], fj * x * P[la * n + si]);
-    atomicAdd(&J[la * n + si], fj * x * P[mu * n + nu]);
-    atomicAdd(&K[mu * n + la], fk * x * P[nu * n + si]);
-    atomicAdd(&K[mu * n + si], fk * x * P[nu * n + la]);
-    atomicAdd(&K[nu * n + la], fk * x * P[mu * n + si]);
-    atomicAdd(&K[nu * n + si], fk * x * P[mu * n + la]);
+  const unsigned short* os = CP::out_slot();
+  for (int t = threadIdx.x; t < NPB; t += kWave) {
+    double acc = 0.0, f;
+    if (t < OCD) {          // J_ab = sum_cd (ab|cd) P_cd
+      const int i = t / NB, j = t % NB;
+      #pragma unroll 1
+      for (int k = 0; k < NC; ++k)
+        #pragma unroll 1
+        for (int l = 0; l < ND; ++l)
+          acc = fma(slots[os[((i * NB + j) * NC + k) * ND + l]], pb[OCD + k * ND + l], acc);
+      f = fj;
+    } else if (t < OAC) {   // J_cd = sum_ab (ab|cd) P_ab
+      const int k = (t - OCD) / ND, l = (t - OCD) % ND;
+      #pragma unroll 1
+      for (int i = 0; i < NA; ++i)
+        #pragma unroll 1
+        for (int j = 0; j < NB; ++j)
+          acc = fma(slots[os[((i * NB + j) * NC + k) * ND + l]], pb[i * NB + j], acc);
+      f = fj;
+    } else if (t < OAD) {   // K_ac = sum_bd (ab|cd) P_bd
+      const int i = (t - OAC) / NC, k = (t - OAC) % NC;
+      #pragma unroll 1
+      for (int j = 0; j < NB; ++j)
+        #pragma unroll 1
+        for (int l = 0; l < ND; ++l)
+          acc = fma(slots[os[((i * NB + j) * NC + k) * ND + l]], pb[OBD + j * ND + l], acc);
+      f = fk;
+    } else if (t < OBC) {   // K_ad = sum_bc (ab|cd) P_bc
+      const int i = (t - OAD) / ND, l = (t - OAD) % ND;
+      #pragma unroll 1
+      for (int j = 0; j < NB; ++j)
+        #pragma unroll 1
+        for (int k = 0; k < NC; ++k)
+          acc = fma(slots[os[((i * NB + j) * NC + k) * ND + l]], pb[OBC + j * NC + k], acc);
+      f = fk;
+    } else if (t < OBD) {   // K_bc = sum_ad (ab|cd) P_ad
+      const int j = (t - OBC) / NC, k = (t - OBC) % NC;
+      #pragma unroll 1
+      for (int i = 0; i < NA; ++i)
+        #pragma unroll 1
+        for (int l = 0; l < ND; ++l)
+          acc = fma(slots[os[((i * NB + j) * NC + k) * ND + l]], pb[OAD + i * ND + l], acc);
+      f = fk;
+    } else {                // K_bd = sum_ac (ab|cd) P_ac
+      const int j = (t - OBD) / ND, l = (t - OBD) % ND;
+      #pragma unroll 1
+      for (int i = 0; i < NA; ++i)
+        #pragma unroll 1
+        for (int k = 0; k < NC; ++k)
+          acc = fma(slots[os[((i * NB + j) * NC + k) * ND + l]], pb[OAC + i * NC + k], acc);
+      f = fk;
+    }
+    const int2 rc = block_rc<NA, NB, NC, ND>(t, m0, n0, l0, s0);
+    atomicAdd(t < OAC ? &J[rc.x * n + rc.y] : &K[rc.x * n + rc.y], f * acc);
   }
 }
 

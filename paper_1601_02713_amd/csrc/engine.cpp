@@ -37,6 +37,10 @@ using namespace bscf;
 
 namespace {
 
+// quartets per lane-kernel unit: the K rows of its bra are flushed once per
+// unit, so longer units amortise the flush, shorter ones spread the work
+constexpr int kUnitQuartets = 256;
+
 thread_local std::string g_err;
 
 struct Error : std::runtime_error {
@@ -263,10 +267,14 @@ struct bscf_ctx {
   double work_tau = -1.0;
   // work lists per quartet class
   struct ClassWork {
-    std::vector<WorkItem> items;
-    std::vector<WorkRow> rows;
-    DevBuf<WorkItem> d_items;
-    DevBuf<WorkRow> d_rows;
+    // 64-quartet items over rows grouped by primitive counts (cooperative
+    // kernels, gradient) and per-bra units over rows grouped by bra (lane
+    // Fock kernels)
+    std::vector<WorkItem> items, units;
+    std::vector<WorkRow> rows, urows;
+    DevBuf<WorkItem> d_items, d_units;
+    DevBuf<WorkRow> d_rows, d_urows;
+    bool lds_ok = true;   // the lane kernel's LDS rows fit one workgroup
     double nquart = 0, nprimq = 0;
     std::vector<double> inst_quart, inst_primq;  // per instance
     // evaluated so far (active instances only) and measured kernel time
@@ -277,6 +285,10 @@ struct bscf_ctx {
   ClassWork work[kNumQuartetClasses];
   std::vector<int> kets;
   DevBuf<int> d_kets;
+  // ket-list-position buffers: P gathered per ket pair and ket-side J
+  DevBuf<double> d_Pk, d_Jk;
+  int max_ncd = 0;
+  size_t max_lds_bytes = 65536;
 
   // device data
   DevBuf<Shell> d_shells;
@@ -539,7 +551,9 @@ void build_work(bscf_ctx* c, double tau) {
       WorkItem w;
       double cost;
     };
-    std::vector<Tmp> tmp;
+    std::vector<Tmp> tmp, utmp;
+    W.units.clear();
+    W.urows.clear();
     for (int i = 0; i < c->ninst; ++i) {
       // rows of this instance grouped by (bra, ket) primitive counts
       std::vector<std::pair<std::pair<int, int>, std::vector<WorkRow>>> groups;
@@ -549,6 +563,8 @@ void build_work(bscf_ctx* c, double tau) {
           const double qb = bs.q[r];
           const int sb = sub_of[bra];
           const auto& kv = subs[i][Y];
+          const int ur0 = (int)W.urows.size();
+          std::vector<int> ur_nprim;
           for (int t = 0; t < (int)kv.size(); ++t) {
             const Sub& ks = kv[t];
             int lim;
@@ -574,10 +590,31 @@ void build_work(bscf_ctx* c, double tau) {
             while (g < groups.size() && groups[g].first != key) ++g;
             if (g == groups.size()) groups.push_back({key, {}});
             groups[g].second.push_back(WorkRow{bra, ks.ket_off, lim, 0});
+            W.urows.push_back(WorkRow{bra, ks.ket_off, lim, 0});
+            ur_nprim.push_back(ks.nprim);
             W.nquart += lim;
             W.nprimq += double(lim) * bs.nprim * ks.nprim;
             W.inst_quart[i] += lim;
             W.inst_primq[i] += double(lim) * bs.nprim * ks.nprim;
+          }
+          // units of this bra: up to kUnitQuartets consecutive quartets over
+          // its rows (all ket primitive counts)
+          const int ur1 = (int)W.urows.size();
+          int rr = ur0, off = 0;
+          while (rr < ur1) {
+            WorkItem u{rr, off, 0, 0};
+            double cost = 0.0;
+            while (u.count < kUnitQuartets && rr < ur1) {
+              const int t = std::min(W.urows[rr].nket - off, kUnitQuartets - u.count);
+              u.count += t;
+              cost += double(t) * bs.nprim * ur_nprim[rr - ur0];
+              off += t;
+              if (off == W.urows[rr].nket) {
+                ++rr;
+                off = 0;
+              }
+            }
+            utmp.push_back({u, cost});
           }
         }
       // tile every group with items of up to 64 quartets (one per lane)
@@ -608,41 +645,98 @@ void build_work(bscf_ctx* c, double tau) {
     for (size_t k = 0; k < tmp.size(); ++k) W.items[k] = tmp[k].w;
     W.d_items.upload(W.items, c->stream);
     W.d_rows.upload(W.rows, c->stream);
+    std::stable_sort(utmp.begin(), utmp.end(), [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; });
+    W.units.resize(utmp.size());
+    for (size_t k = 0; k < utmp.size(); ++k) W.units[k] = utmp[k].w;
+    W.d_units.upload(W.units, c->stream);
+    W.d_urows.upload(W.urows, c->stream);
+    W.lds_ok = sizeof(double) * (size_t)unit_lds_doubles(qc[q].la, qc[q].lb, c->max_n) <=
+               c->max_lds_bytes;
   }
   c->d_kets.upload(c->kets, c->stream);
+  // ket-position buffers; Jk is kept zero between builds by jk_finalize
+  c->max_ncd = 0;
+  for (int pid : c->kets) {
+    const ShellPair& pr = c->pairs[pid];
+    c->max_ncd = std::max(c->max_ncd, ncart(c->shells[pr.a].l) * ncart(c->shells[pr.b].l));
+  }
+  const size_t nkb = (size_t)c->max_ncd * c->kets.size();
+  c->d_Pk.resize(nkb);
+  c->d_Jk.resize(nkb);
+  HIPCHK(hipMemsetAsync(c->d_Jk.p, 0, sizeof(double) * c->d_Jk.n, c->stream));
   c->work_tau = tau;
 }
 
-// Time the lane and cooperative kernels of every class that has both on the
-// current work lists (second of two runs each, into throwaway J and K) and keep
-// the faster; BSCF_VARIANT=lane|coop forces a choice.
-void autotune_fock(bscf_ctx* c, int pcol) {
-  const char* env = getenv("BSCF_VARIANT");
-  const QuartetClass* qc = quartet_classes();
+FockArgs fock_args(bscf_ctx* c, double* J, double* K, const int* active) {
   FockArgs a;
+  a.items = nullptr;
+  a.nitems = 0;
+  a.rows = nullptr;
+  a.units = nullptr;
+  a.nunits = 0;
+  a.urows = nullptr;
   a.pairs = c->d_pairs.p;
   a.prims = c->d_prims.p;
   a.shells = c->d_shells.p;
   a.kets = c->d_kets.p;
   a.moff = c->d_moff.p;
   a.nbf = c->d_nbf.p;
+  a.nmax = c->max_n;
+  a.nk_total = (int)c->kets.size();
   a.P = c->P.p;
-  a.J = c->tmp1.p;
-  a.K = c->tmp2.p;
+  a.Pk = c->d_Pk.p;
+  a.J = J;
+  a.Jk = c->d_Jk.p;
+  a.K = K;
   a.boys64 = c->d_boys64.p;
   a.boys32 = c->d_boys32.p;
-  a.active = c->d_all_active.p;
+  a.active = active;
+  return a;
+}
+
+void set_class(FockArgs& a, const bscf_ctx::ClassWork& W) {
+  a.items = W.d_items.p;
+  a.nitems = (int)W.items.size();
+  a.rows = W.d_rows.p;
+  a.units = W.d_units.p;
+  a.nunits = (int)W.units.size();
+  a.urows = W.d_urows.p;
+}
+
+KetPosArgs ketpos_args(bscf_ctx* c) {
+  KetPosArgs k;
+  k.nk_total = (int)c->kets.size();
+  k.kets = c->d_kets.p;
+  k.pairs = c->d_pairs.p;
+  k.shells = c->d_shells.p;
+  k.moff = c->d_moff.p;
+  k.nbf = c->d_nbf.p;
+  return k;
+}
+
+// Time the lane and cooperative kernels of every class that has both on the
+// current work lists (second of two runs each, into throwaway J and K) and keep
+// the faster; BSCF_VARIANT=lane|coop forces a choice.  A class whose lane
+// kernel needs more LDS than one workgroup may hold runs cooperatively.
+void autotune_fock(bscf_ctx* c, int pcol) {
+  const char* env = getenv("BSCF_VARIANT");
+  const QuartetClass* qc = quartet_classes();
+  FockArgs a = fock_args(c, c->tmp1.p, c->tmp2.p, c->d_all_active.p);
+  const KetPosArgs kp = ketpos_args(c);
+  launch_gather_pk(kp, c->max_ncd, c->P.p, c->d_Pk.p, c->stream);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   for (int q = 0; q < kNumQuartetClasses; ++q) {
     auto& W = c->work[q];
-    if (!qc[q].fock || W.items.empty()) continue;
+    if (!qc[q].fock || !W.lds_ok) {
+      c->fock_variant[pcol][q] = 1;
+      continue;
+    }
+    if (W.items.empty()) continue;
     if (env && !strcmp(env, "lane")) { c->fock_variant[pcol][q] = 0; continue; }
     if (env && !strcmp(env, "coop")) { c->fock_variant[pcol][q] = 1; continue; }
-    a.items = W.d_items.p;
-    a.rows = W.d_rows.p;
-    a.nitems = (int)W.items.size();
+    set_class(a, W);
     for (int v = 0; v < 2; ++v) {
       for (int rep = 0; rep < 2; ++rep) {
         HIPCHK(hipEventRecord(e0, c->stream));
@@ -655,6 +749,8 @@ void autotune_fock(bscf_ctx* c, int pcol) {
     }
     c->fock_variant[pcol][q] = c->tune_ms[pcol][q][1] < c->tune_ms[pcol][q][0] ? 1 : 0;
   }
+  // the lane runs left ket-side sums in Jk: fold them into the throwaway J
+  launch_jk_finalize(kp, c->max_ncd, c->d_Jk.p, c->tmp1.p, c->stream);
   HIPCHK(hipGetLastError());
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -667,23 +763,14 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
   const double t0 = now_ms();
   launch_fill(c->J.p, c->mtot, 0.0, c->stream);
   launch_fill(c->K.p, c->mtot, 0.0, c->stream);
-  FockArgs a;
-  a.pairs = c->d_pairs.p;
-  a.prims = c->d_prims.p;
-  a.shells = c->d_shells.p;
-  a.kets = c->d_kets.p;
-  a.moff = c->d_moff.p;
-  a.nbf = c->d_nbf.p;
-  a.P = c->P.p;
-  a.J = c->J.p;
-  a.K = c->K.p;
-  a.boys64 = c->d_boys64.p;
-  a.boys32 = c->d_boys32.p;
-  a.active = masked ? c->d_active.p : c->d_all_active.p;
+  FockArgs a = fock_args(c, c->J.p, c->K.p, masked ? c->d_active.p : c->d_all_active.p);
+  const KetPosArgs kp = ketpos_args(c);
   const QuartetClass* qc = quartet_classes();
   // class kernels run concurrently on the auxiliary streams (J and K are
   // accumulated with atomics, so their order does not matter); heavy classes
-  // are issued first because they are latency-bound
+  // are issued first because they are latency-bound.  Kernels that need
+  // private scratch stay on the context stream: the runtime reserves scratch
+  // per hardware queue for full occupancy.
   if (c->profiling) {
     if (!c->ev_b0) {
       HIPCHK(hipEventCreate(&c->ev_b0));
@@ -691,20 +778,18 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
     }
     HIPCHK(hipEventRecord(c->ev_b0, c->stream));
   }
+  launch_gather_pk(kp, c->max_ncd, c->P.p, c->d_Pk.p, c->stream);
   HIPCHK(hipEventRecord(c->ev_fork, c->stream));
   for (int k = 0; k < bscf_ctx::kAux; ++k) HIPCHK(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
   int slot = 0;
   const int pcol = precision == BSCF_MIXED ? 1 : 0;
-  for (int qq = kNumQuartetClasses - 1; qq >= 0; --qq) {
-    const int q = qq;
+  for (int q = kNumQuartetClasses - 1; q >= 0; --q) {
     auto& W = c->work[q];
     if (W.items.empty()) continue;
     const int var = c->fock_variant[pcol][q];
     const int pbytes = var ? c->coop_bytes[q][0] : c->private_bytes[q][pcol];
     const hipStream_t s = pbytes != 0 ? c->stream : c->aux[slot++ % bscf_ctx::kAux];
-    a.items = W.d_items.p;
-    a.rows = W.d_rows.p;
-    a.nitems = (int)W.items.size();
+    set_class(a, W);
     if (c->profiling) {
       if (!W.ev0) {
         HIPCHK(hipEventCreate(&W.ev0));
@@ -726,6 +811,7 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
     HIPCHK(hipEventRecord(c->ev_join[k], c->aux[k]));
     HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join[k], 0));
   }
+  launch_jk_finalize(kp, c->max_ncd, c->d_Jk.p, c->J.p, c->stream);
   HIPCHK(hipGetLastError());
   if (c->profiling) {
     HIPCHK(hipEventRecord(c->ev_b1, c->stream));
@@ -794,6 +880,11 @@ bscf_status bscf_create(int hip_device, void* hip_stream, bscf_ctx** out) {
       HIPCHK(hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming));
     }
     HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    {
+      int lds = 0;
+      HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device));
+      c->max_lds_bytes = (size_t)lds;
+    }
     {
       const QuartetClass* qc = quartet_classes();
       for (int q = 0; q < kNumQuartetClasses; ++q) {

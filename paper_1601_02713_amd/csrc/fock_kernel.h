@@ -1,17 +1,30 @@
 // Per-class kernels of the direct-SCF Fock build.
 //
-// One wavefront owns one WorkItem: a bra shell pair and up to 64*k ket shell
-// pairs of one angular class and one primitive count.  Each lane evaluates one
-// contracted shell quartet (Obara-Saika VRR over the primitive quartets,
-// contraction, HRR; generated per class), then digests it into J and K:
+// Every shell quartet (ab|cd) is digested into J and K as
 //   J_mn += f_J (mn|ls) P_ls,   J_ls += f_J (mn|ls) P_mn,
 //   K_ml += f_K (mn|ls) P_ns,   K_ms += f_K (mn|ls) P_nl,
 //   K_nl += f_K (mn|ls) P_ms,   K_ns += f_K (mn|ls) P_ml,
 // with f_J = g/2, f_K = g/4 and g the number of distinct permutations of the
 // shell quartet (1, 2, 4 or 8); J and K are symmetrised afterwards.  Together
 // this reproduces J_mn = sum (mn|ls) P_ls and K_ml = sum (mn|ls) P_ns over all
-// ordered index quartets.  Bra contributions to J are reduced across the
-// wavefront before one atomic add per element; the others use FP64 atomics.
+// ordered index quartets.  All K contributions land in the rows of the bra
+// shells a and b.
+//
+// Lane kernels: one wavefront owns one FockUnit, a bra shell pair and up to a
+// few hundred of its ket pairs (consecutive ket-list positions, possibly over
+// several primitive-count rows).  Each lane evaluates one contracted quartet
+// per pass (Obara-Saika VRR over the primitive quartets, contraction, HRR;
+// generated per class).  FP64 atomics into global memory are issued per 64-byte
+// segment, so scattered per-lane atomics run at about an eighth of the rate of
+// row-contiguous ones; the digestion is therefore arranged so that no lane
+// scatters into J or K:
+//   * the K rows of shells a and b are accumulated in LDS (LDS atomics) for
+//     the whole unit and flushed once with row-contiguous global atomics;
+//   * the ket-side J block of each lane goes to Jk, indexed by ket-list
+//     position and stored component-major (adjacent lanes write adjacent
+//     doubles), and is folded into J after all classes (jk_finalize);
+//   * the ket-side density P_cd is read from Pk, gathered the same way;
+//   * the bra-side J block is reduced across the wavefront at the end.
 #pragma once
 #include "boys.h"
 #include "common.h"
@@ -19,17 +32,24 @@
 namespace bscf {
 
 struct FockArgs {
-  const WorkItem* items;
+  const WorkItem* items;   // 64-quartet items (cooperative kernels)
   int nitems;
   const WorkRow* rows;
+  const WorkItem* units;   // per-bra units (lane kernels)
+  int nunits;
+  const WorkRow* urows;
   const ShellPair* pairs;
   const PrimPair* prims;
   const Shell* shells;
   const int* kets;
   const long long* moff;   // matrix offset per instance
   const int* nbf;          // basis size per instance
+  int nmax;                // largest basis size (row length of the LDS accumulators)
+  int nk_total;            // number of ket-list positions (stride of Pk and Jk)
   const double* P;
+  const double* Pk;        // Pk[e * nk_total + pos] = P_cd component e of the pair at pos
   double* J;
+  double* Jk;              // ket-side J, same layout as Pk; cleared by jk_finalize
   double* K;
   const double* boys64;
   const float* boys32;
@@ -132,135 +152,151 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// LDS footprint of the unit kernel of a class: K accumulators and P rows of the
+// bra shells, (NA + NB) rows of nmax doubles each.
+__host__ __device__ constexpr int unit_lds_doubles(int la, int lb, int nmax) {
+  return 2 * (ncart(la) + ncart(lb)) * nmax;
+}
+
 template <class CL, typename R>
-__global__ __launch_bounds__(256) void fock_kernel(FockArgs a) {
+__global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
   constexpr int NA = ncart(CL::LA), NB = ncart(CL::LB), NC = ncart(CL::LC), ND = ncart(CL::LD);
-  const int lane = threadIdx.x & (kWave - 1);
-  const int item_id = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-  if (item_id >= a.nitems) return;
-  const WorkItem it = a.items[item_id];
-  int bid, kid;
-  bool single;
-  const bool valid = lane_quartet(it, a.rows, a.kets, lane, bid, kid, single);
+  constexpr int NR = NA + NB;
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x;
+  const WorkItem u = a.units[blockIdx.x];
+  const int bid = a.urows[u.row].bra;
   const ShellPair bra = a.pairs[bid];
   const Shell sa = a.shells[bra.a], sb = a.shells[bra.b];
-  const int inst = sa.inst;               // one instance per item
+  const int inst = sa.inst;
   if (!a.active[inst]) return;
   const long long mo = a.moff[inst];
   const int n = a.nbf[inst];
-  const double* __restrict__ P = a.P + mo;
-  double* J = a.J + mo;
-  double* K = a.K + mo;
-  const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
   const int m0 = sa.bf, n0 = sb.bf;
-  double Pab[NA][NB];
-#pragma unroll
-  for (int i = 0; i < NA; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) Pab[i][j] = P[(m0 + i) * n + n0 + j];
-  const ShellPair ket = a.pairs[kid];
-  const Shell sc = a.shells[ket.a], sd = a.shells[ket.b];
-  const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
-  R v[CL::NOUT];
-  eri_block<CL, R>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
-                   a.boys64, a.boys32, v);
-  const double g = ((bra.a == bra.b) ? 1.0 : 2.0) * ((ket.a == ket.b) ? 1.0 : 2.0) *
-                   ((kid == bid) ? 1.0 : 2.0);
-  const double fj = valid ? 0.5 * g : 0.0;
-  const double fk = 0.5 * fj;
-  const int l0 = sc.bf, s0 = sd.bf;
-  double Pcd[NC][ND], Pac[NA][NC], Pad[NA][ND], Pbc[NB][NC], Pbd[NB][ND];
-#pragma unroll
-  for (int k = 0; k < NC; ++k)
-#pragma unroll
-    for (int l = 0; l < ND; ++l) Pcd[k][l] = P[(l0 + k) * n + s0 + l];
-#pragma unroll
-  for (int i = 0; i < NA; ++i) {
-#pragma unroll
-    for (int k = 0; k < NC; ++k) Pac[i][k] = P[(m0 + i) * n + l0 + k];
-#pragma unroll
-    for (int l = 0; l < ND; ++l) Pad[i][l] = P[(m0 + i) * n + s0 + l];
+  double* Kacc = lds;           // row r: K row of bf m0 + r (r < NA) or n0 + r - NA
+  double* Prow = lds + NR * n;  // the same rows of P
+  for (int t = lane; t < NR * n; t += kWave) {
+    const int r = t / n, col = t - r * n;
+    const int bf = r < NA ? m0 + r : n0 + (r - NA);
+    Kacc[t] = 0.0;
+    Prow[t] = a.P[mo + (long long)bf * n + col];
   }
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-#pragma unroll
-    for (int k = 0; k < NC; ++k) Pbc[j][k] = P[(n0 + j) * n + l0 + k];
-#pragma unroll
-    for (int l = 0; l < ND; ++l) Pbd[j][l] = P[(n0 + j) * n + s0 + l];
-  }
-  double jbra[NA][NB], jket[NC][ND], kac[NA][NC], kad[NA][ND], kbc[NB][NC], kbd[NB][ND];
-#pragma unroll
-  for (int k = 0; k < NC; ++k)
-#pragma unroll
-    for (int l = 0; l < ND; ++l) jket[k][l] = 0.0;
-#pragma unroll
-  for (int i = 0; i < NA; ++i) {
-#pragma unroll
-    for (int k = 0; k < NC; ++k) kac[i][k] = 0.0;
-#pragma unroll
-    for (int l = 0; l < ND; ++l) kad[i][l] = 0.0;
-  }
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-#pragma unroll
-    for (int k = 0; k < NC; ++k) kbc[j][k] = 0.0;
-#pragma unroll
-    for (int l = 0; l < ND; ++l) kbd[j][l] = 0.0;
-  }
+  __syncthreads();
+  double Pab[NA][NB], jab[NA][NB];
 #pragma unroll
   for (int i = 0; i < NA; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      double jb = 0.0;
-#pragma unroll
-      for (int k = 0; k < NC; ++k)
-#pragma unroll
-        for (int l = 0; l < ND; ++l) {
-          const double x = double(v[((i * NB + j) * NC + k) * ND + l]);
-          jb = fma(x, Pcd[k][l], jb);
-          jket[k][l] = fma(x, Pab[i][j], jket[k][l]);
-          kac[i][k] = fma(x, Pbd[j][l], kac[i][k]);
-          kad[i][l] = fma(x, Pbc[j][k], kad[i][l]);
-          kbc[j][k] = fma(x, Pad[i][l], kbc[j][k]);
-          kbd[j][l] = fma(x, Pac[i][k], kbd[j][l]);
-        }
-      jbra[i][j] = fj * jb;
+      Pab[i][j] = Prow[i * n + n0 + j];
+      jab[i][j] = 0.0;
     }
-  if (valid) {
+  const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
+  for (int c0 = 0; c0 < u.count; c0 += kWave) {
+    const int t = c0 + lane;
+    const bool valid = t < u.count;
+    int rr = u.row, k0 = u.off + (valid ? t : 0);
+    int nk = a.urows[rr].nket;
+    while (k0 >= nk) {
+      k0 -= nk;
+      ++rr;
+      nk = a.urows[rr].nket;
+    }
+    const int pos = a.urows[rr].ket0 + k0;
+    const int kid = a.kets[pos];
+    const ShellPair ket = a.pairs[kid];
+    const Shell sc = a.shells[ket.a], sd = a.shells[ket.b];
+    const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
+    R v[CL::NOUT];
+    eri_block<CL, R>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
+                     a.boys64, a.boys32, v);
+    const double g = ((bra.a == bra.b) ? 1.0 : 2.0) * ((ket.a == ket.b) ? 1.0 : 2.0) *
+                     ((kid == bid) ? 1.0 : 2.0);
+    const double fj = valid ? 0.5 * g : 0.0;
+    const double fk = 0.5 * fj;
+    const int l0 = sc.bf, s0 = sd.bf;
+    double Pcd[NC][ND];
 #pragma unroll
     for (int k = 0; k < NC; ++k)
 #pragma unroll
-      for (int l = 0; l < ND; ++l) atomicAdd(&J[(l0 + k) * n + s0 + l], fj * jket[k][l]);
+      for (int l = 0; l < ND; ++l) Pcd[k][l] = a.Pk[(long long)(k * ND + l) * a.nk_total + pos];
+    double jket[NC][ND], kac[NA][NC], kad[NA][ND], kbc[NB][NC], kbd[NB][ND];
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+      for (int l = 0; l < ND; ++l) jket[k][l] = 0.0;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
 #pragma unroll
-      for (int k = 0; k < NC; ++k) atomicAdd(&K[(m0 + i) * n + l0 + k], fk * kac[i][k]);
+      for (int k = 0; k < NC; ++k) kac[i][k] = 0.0;
 #pragma unroll
-      for (int l = 0; l < ND; ++l) atomicAdd(&K[(m0 + i) * n + s0 + l], fk * kad[i][l]);
+      for (int l = 0; l < ND; ++l) kad[i][l] = 0.0;
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
 #pragma unroll
-      for (int k = 0; k < NC; ++k) atomicAdd(&K[(n0 + j) * n + l0 + k], fk * kbc[j][k]);
+      for (int k = 0; k < NC; ++k) kbc[j][k] = 0.0;
 #pragma unroll
-      for (int l = 0; l < ND; ++l) atomicAdd(&K[(n0 + j) * n + s0 + l], fk * kbd[j][l]);
+      for (int l = 0; l < ND; ++l) kbd[j][l] = 0.0;
     }
-  }
-  if (single) {
-    // one bra pair for the whole wavefront: reduce its J block first
 #pragma unroll
     for (int i = 0; i < NA; ++i)
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        const double s = wave_sum(jbra[i][j]);
-        if (lane == 0) atomicAdd(&J[(m0 + i) * n + n0 + j], s);
+        double jb = 0.0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+          for (int l = 0; l < ND; ++l) {
+            const double x = double(v[((i * NB + j) * NC + k) * ND + l]);
+            jb = fma(x, Pcd[k][l], jb);
+            jket[k][l] = fma(x, Pab[i][j], jket[k][l]);
+            kac[i][k] = fma(x, Prow[(NA + j) * n + s0 + l], kac[i][k]);
+            kad[i][l] = fma(x, Prow[(NA + j) * n + l0 + k], kad[i][l]);
+            kbc[j][k] = fma(x, Prow[i * n + s0 + l], kbc[j][k]);
+            kbd[j][l] = fma(x, Prow[i * n + l0 + k], kbd[j][l]);
+          }
+        jab[i][j] = fma(fj, jb, jab[i][j]);
       }
-  } else if (valid) {
+    if (valid) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i)
+      for (int k = 0; k < NC; ++k)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) atomicAdd(&J[(m0 + i) * n + n0 + j], jbra[i][j]);
+        for (int l = 0; l < ND; ++l)
+          atomicAdd(&a.Jk[(long long)(k * ND + l) * a.nk_total + pos], fj * jket[k][l]);
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) atomicAdd(&Kacc[i * n + l0 + k], fk * kac[i][k]);
+#pragma unroll
+        for (int l = 0; l < ND; ++l) atomicAdd(&Kacc[i * n + s0 + l], fk * kad[i][l]);
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) atomicAdd(&Kacc[(NA + j) * n + l0 + k], fk * kbc[j][k]);
+#pragma unroll
+        for (int l = 0; l < ND; ++l) atomicAdd(&Kacc[(NA + j) * n + s0 + l], fk * kbd[j][l]);
+      }
+    }
   }
+  __syncthreads();
+  double* K = a.K + mo;
+  for (int t = lane; t < NR * n; t += kWave) {
+    const double x = Kacc[t];
+    if (x != 0.0) {
+      const int r = t / n, col = t - r * n;
+      const int bf = r < NA ? m0 + r : n0 + (r - NA);
+      atomicAdd(&K[(long long)bf * n + col], x);
+    }
+  }
+  double* J = a.J + mo;
+#pragma unroll
+  for (int i = 0; i < NA; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const double x = wave_sum(jab[i][j]);
+      if (lane == 0) atomicAdd(&J[(m0 + i) * n + n0 + j], x);
+    }
 }
 
 // Q for each pair of class (LA LB|LA LB): sqrt(max |(mn|mn)|).

@@ -201,6 +201,7 @@ def energy_program(la, lb, lc, ld):
     outs = hrr_graph(gh, la, lb, lc, ld, lambda e, f: ("A", e, f), "A")
     lv_h, slot_h, top_h = schedule(gh, list(amap), amap, set(outs), nacc)
     out_slot = [slot_h[k] for k in outs]
+    assert len(set(out_slot)) == len(out_slot)   # outputs are scaled in place
     norms = [comp_norm(a) * comp_norm(b) * comp_norm(c) * comp_norm(d)
              for a in cart(la) for b in cart(lb) for c in cart(lc) for d in cart(ld)]
     vrr = encode([[(k, gv.nodes[k]) for k in lv] for lv in lv_v], slot_v)

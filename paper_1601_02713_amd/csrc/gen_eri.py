@@ -513,15 +513,15 @@ def main(outdir):
             tu = [f"// generated by gen_eri.py: kernels of class ({la}{lb}|{lc}{ld})",
                   '#include "fock_kernel.h"', f'#include "eri_{tag}.h"', "namespace bscf {",
                   f"void launch_fock_{tag}(const FockArgs& a, int fp32, hipStream_t s) {{",
-                  "  const int blocks = (a.nitems + 3) / 4;",
-                  "  if (blocks == 0) return;",
-                  f"  if (fp32) hipLaunchKernelGGL((fock_kernel<Cls{tag}, float>), dim3(blocks), dim3(256), 0, s, a);",
-                  f"  else hipLaunchKernelGGL((fock_kernel<Cls{tag}, double>), dim3(blocks), dim3(256), 0, s, a);",
+                  "  if (a.nunits == 0) return;",
+                  f"  const size_t lds = sizeof(double) * unit_lds_doubles({la}, {lb}, a.nmax);",
+                  f"  if (fp32) hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, float>), dim3(a.nunits), dim3(64), lds, s, a);",
+                  f"  else hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, double>), dim3(a.nunits), dim3(64), lds, s, a);",
                   "}",
                   f"int fock_private_bytes_{tag}(int fp32) {{",
                   "  hipFuncAttributes at{};",
-                  f"  const void* f = fp32 ? reinterpret_cast<const void*>(&fock_kernel<Cls{tag}, float>)",
-                  f"                       : reinterpret_cast<const void*>(&fock_kernel<Cls{tag}, double>);",
+                  f"  const void* f = fp32 ? reinterpret_cast<const void*>(&fock_unit_kernel<Cls{tag}, float>)",
+                  f"                       : reinterpret_cast<const void*>(&fock_unit_kernel<Cls{tag}, double>);",
                   "  if (hipFuncGetAttributes(&at, f) != hipSuccess) return -1;",
                   "  return (int)at.localSizeBytes;",
                   "}",

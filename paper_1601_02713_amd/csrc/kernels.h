@@ -59,6 +59,25 @@ void launch_prim_pairs(const PrimPairSetupArgs& a, hipStream_t s);
 void launch_onee(int la, int lb, const OneEArgs& a, hipStream_t s);
 void launch_grad1e(int la, int lb, const Grad1EArgs& a, hipStream_t s);
 
+// ---- ket-list-position buffers of the Fock build (jk.hip) ----
+// Position pos of the ket list holds shell pair kets[pos] = (c, d); its
+// component e = k * ncart(l_d) + l is stored at [e * nk_total + pos], so the
+// lanes of a wavefront that take consecutive positions touch consecutive
+// doubles.
+struct KetPosArgs {
+  int nk_total;
+  const int* kets;
+  const ShellPair* pairs;
+  const Shell* shells;
+  const long long* moff;
+  const int* nbf;
+};
+// Pk[e * nk_total + pos] = P(c_k, d_l)
+void launch_gather_pk(const KetPosArgs& a, int max_ncd, const double* P, double* Pk,
+                      hipStream_t s);
+// J(c_k, d_l) += Jk[e * nk_total + pos], then Jk = 0 (ready for the next build)
+void launch_jk_finalize(const KetPosArgs& a, int max_ncd, double* Jk, double* J, hipStream_t s);
+
 // ---- dense per-instance helpers (scf.hip) ----
 struct BatchInfo {
   int ninst;
