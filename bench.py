@@ -112,7 +112,10 @@ def main():
     fock_gpu_ms = st_json["t_fock_gpu_ms"]
     per_class = {k: {"quartets_per_build": v["quartets"], "prim_quartets_per_build": v["prim_quartets"],
                      "ms_per_launch": v["kernel_ms"] / max(v["launches"], 1),
-                     "tflops": (v["done_flops"] / (v["kernel_ms"] * 1e-3) / 1e12) if v["kernel_ms"] else None}
+                     "tflops": (v["done_flops"] / (v["kernel_ms"] * 1e-3) / 1e12) if v["kernel_ms"] else None,
+                     "kernel": "lane" if v["variant"][0 if prec == beadscf.BSCF_FP64 else 1] == 0 else "coop",
+                     "grad_ms_per_launch": v["grad_ms"] / max(v["grad_launches"], 1),
+                     "grad_kernel": "lane" if v["variant"][2] == 0 else "coop"}
                  for k, v in cls.items() if v["launches"]}
     d = cls[dom]
     ach = d["done_flops"] / (d["kernel_ms"] * 1e-3) / 1e12 if d["kernel_ms"] > 0 else 0.0
@@ -142,8 +145,10 @@ def main():
         "fock_tflops": k_fl / (fock_gpu_ms * 1e-3) / 1e12 if fock_gpu_ms else None,
         "fock_frac_fp64_peak": (k_fl / (fock_gpu_ms * 1e-3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS) if fock_gpu_ms else None,
         "phase_ms_per_step": {k: st_json[k] / args.steps for k in
-                              ("t_setup_ms", "t_scf_ms", "t_grad_ms", "t_fock_ms")},
-        "roofline": {"bound": "alu", "kernel": f"fock_kernel<Cls{dom}, double>",
+                              ("t_setup_ms", "t_scf_ms", "t_grad_ms", "t_fock_ms", "t_work_ms")},
+        "roofline": {"bound": "alu",
+                     "kernel": (f"fock_unit_kernel<Cls{dom}, double>" if per_class[dom]["kernel"] == "lane"
+                                else f"coop_fock_kernel<CoopE{dom}>"),
                      "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
                      "launches": d["launches"],

@@ -1,13 +1,17 @@
-// Cooperative kernels: one wavefront (a 64-thread block) per shell quartet.
+// Cooperative kernels: one block of CP::NT threads (one to eight wavefronts)
+// per shell quartet.
 //
 // The recurrence graph of the quartet (Obara-Saika VRR per primitive quartet,
 // accumulation into contracted targets, Head-Gordon-Pople HRR, and for the
 // gradient the contraction with the density factor) is evaluated level by
 // level out of LDS from generated node tables (gen_coop.py): every node is
 // dst = sum_t mult_t * scalar[sel_t] * slot[src_t], and the nodes of a level
-// are spread over the 64 lanes.  This keeps the state of high angular momentum
-// classes in LDS instead of spilling it to scratch, and spreads one quartet's
-// latency over a whole wavefront.
+// are spread over the threads of the block.  A node is one 64-bit word (first
+// term, destination slot, term count) and a term one 32-bit word (source slot,
+// scalar selector, integer multiplier + 8), so each term costs one table load.
+// This keeps the state of high angular momentum classes in LDS instead of
+// spilling it to scratch; classes whose LDS footprint admits few blocks per CU
+// get more threads per quartet.
 #pragma once
 #include "boys.h"
 #include "common.h"
@@ -23,18 +27,24 @@ enum : int {
   kSelWb = 25, kSelWc = 26, kNumSel = 27
 };
 
-// Evaluate one level range [n0, n1) of a node table.
-__device__ __forceinline__ void coop_level(int n0, int n1, const unsigned short* __restrict__ dst,
-                                           const int* __restrict__ t0,
-                                           const unsigned short* __restrict__ src,
-                                           const unsigned char* __restrict__ sel,
-                                           const double* __restrict__ mult, const double* sc,
-                                           double* slots) {
-  for (int nd = n0 + (int)threadIdx.x; nd < n1; nd += kWave) {
+// Evaluate one level range [n0, n1) of a packed node table.
+template <int NT>
+__device__ __forceinline__ void coop_level(int n0, int n1,
+                                           const unsigned long long* __restrict__ node,
+                                           const unsigned int* __restrict__ term,
+                                           const double* sc, double* slots) {
+  for (int nd = n0 + (int)threadIdx.x; nd < n1; nd += NT) {
+    const unsigned long long w = node[nd];
+    const int t0 = (int)(w & 0xFFFFFFFFull);
+    const int dst = (int)((w >> 32) & 0xFFFFull);
+    const int t1 = t0 + (int)((w >> 48) & 0xFFull);
     double v = 0.0;
-    const int e = t0[nd + 1];
-    for (int t = t0[nd]; t < e; ++t) v = fma(mult[t] * sc[sel[t]], slots[src[t]], v);
-    slots[dst[nd]] = v;
+    for (int t = t0; t < t1; ++t) {
+      const unsigned int u = term[t];
+      const double m = (double)((int)(u >> 24) - 8);
+      v = fma(m * sc[(u >> 16) & 0xFFu], slots[u & 0xFFFFu], v);
+    }
+    slots[dst] = v;
   }
 }
 
@@ -47,9 +57,9 @@ __device__ __forceinline__ void coop_primitives(const PrimPair* __restrict__ bp,
                                                 const double AB[3], const double CD[3],
                                                 const double* __restrict__ tab64, double* sc,
                                                 double* slots) {
-  constexpr int L = CP::L;
+  constexpr int L = CP::L, NT = CP::NT;
   const int tid = threadIdx.x;
-  for (int t = tid; t < CP::NACC; t += kWave) slots[CP::acc_slot()[t]] = 0.0;
+  for (int t = tid; t < CP::NACC; t += NT) slots[CP::acc_slot()[t]] = 0.0;
   if (tid == 0) {
     sc[kSelOne] = 1.0;
     sc[kSelAB] = AB[0];
@@ -100,16 +110,25 @@ __device__ __forceinline__ void coop_primitives(const PrimPair* __restrict__ bp,
       __syncthreads();
       const int* ls = CP::vrr_lstart();
       for (int lv = 0; lv < CP::NVLEV; ++lv) {
-        coop_level(ls[lv], ls[lv + 1], CP::vrr_dst(), CP::vrr_t0(), CP::vrr_src(), CP::vrr_sel(),
-                   CP::vrr_mult(), sc, slots);
+        coop_level<NT>(ls[lv], ls[lv + 1], CP::vrr_node(), CP::vrr_term(), sc, slots);
         __syncthreads();
       }
-      for (int t = tid; t < CP::NACC; t += kWave)
+      for (int t = tid; t < CP::NACC; t += NT)
         slots[CP::acc_slot()[t]] = fma(sc[CP::tgt_w()[t]], slots[CP::tgt_slot()[t]],
                                        slots[CP::acc_slot()[t]]);
     }
   }
   __syncthreads();
+}
+
+// HRR levels of a quartet (Fock, Schwarz and tensor kernels).
+template <class CP>
+__device__ __forceinline__ void coop_hrr(const double* sc, double* slots) {
+  const int* hs = CP::hrr_lstart();
+  for (int lv = 0; lv < CP::NHLEV; ++lv) {
+    coop_level<CP::NT>(hs[lv], hs[lv + 1], CP::hrr_node(), CP::hrr_term(), sc, slots);
+    __syncthreads();
+  }
 }
 
 // Row and column basis functions of element t of the six digestion blocks,
@@ -136,7 +155,8 @@ __device__ __forceinline__ bool coop_quartet(const WorkItem* items, const WorkRo
 }
 
 template <class CP>
-__global__ __launch_bounds__(64) void coop_fock_kernel(FockArgs a) {
+__global__ __launch_bounds__(CP::NT) void coop_fock_kernel(FockArgs a) {
+  constexpr int NT = CP::NT;
   __shared__ double slots[CP::NSLOT];
   __shared__ double sc[kNumSel];
   int bid, kid;
@@ -150,12 +170,7 @@ __global__ __launch_bounds__(64) void coop_fock_kernel(FockArgs a) {
   const double CD[3] = {sc_.x - sd.x, sc_.y - sd.y, sc_.z - sd.z};
   coop_primitives<CP>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
                       a.boys64, sc, slots);
-  const int* hs = CP::hrr_lstart();
-  for (int lv = 0; lv < CP::NHLEV; ++lv) {
-    coop_level(hs[lv], hs[lv + 1], CP::hrr_dst(), CP::hrr_t0(), CP::hrr_src(), CP::hrr_sel(),
-               CP::hrr_mult(), sc, slots);
-    __syncthreads();
-  }
+  coop_hrr<CP>(sc, slots);
   // digestion: the six density blocks go to LDS, then each lane contracts one
   // element of one of the six J/K blocks and adds it with one atomic; lanes
   // follow the column index, so an atomic instruction covers few segments
@@ -169,17 +184,17 @@ __global__ __launch_bounds__(64) void coop_fock_kernel(FockArgs a) {
   double* J = a.J + mo;
   double* K = a.K + mo;
   const int m0 = sa.bf, n0 = sb.bf, l0 = sc_.bf, s0 = sd.bf;
-  for (int t = threadIdx.x; t < NPB; t += kWave) {
+  for (int t = threadIdx.x; t < NPB; t += NT) {
     const int2 rc = block_rc<NA, NB, NC, ND>(t, m0, n0, l0, s0);
     pb[t] = P[rc.x * n + rc.y];
   }
-  for (int e = threadIdx.x; e < CP::NOUT; e += kWave) slots[CP::out_slot()[e]] *= CP::norm()[e];
+  for (int e = threadIdx.x; e < CP::NOUT; e += NT) slots[CP::out_slot()[e]] *= CP::norm()[e];
   __syncthreads();
   const double g = ((bra.a == bra.b) ? 1.0 : 2.0) * ((ket.a == ket.b) ? 1.0 : 2.0) *
                    ((kid == bid) ? 1.0 : 2.0);
   const double fj = 0.5 * g, fk = 0.25 * g;
   const unsigned short* os = CP::out_slot();
-  for (int t = threadIdx.x; t < NPB; t += kWave) {
+  for (int t = threadIdx.x; t < NPB; t += NT) {
     double acc = 0.0, f;
     if (t < OCD) {          // J_ab = sum_cd (ab|cd) P_cd
       const int i = t / NB, j = t % NB;
@@ -236,12 +251,15 @@ __global__ __launch_bounds__(64) void coop_fock_kernel(FockArgs a) {
 }
 
 template <class CP>
-__global__ __launch_bounds__(64) void coop_grad_kernel(GradArgs a) {
+__global__ __launch_bounds__(CP::NT) void coop_grad_kernel(GradArgs a) {
+  constexpr int NT = CP::NT, NW = NT / kWave;
   constexpr int NA = ncart(CP::LA), NB = ncart(CP::LB), NC = ncart(CP::LC), ND = ncart(CP::LD);
   constexpr int NOUT = NA * NB * NC * ND;
   __shared__ double slots[CP::NSLOT];
   __shared__ double G[NOUT];
   __shared__ double sc[kNumSel];
+  __shared__ double ctab[CP::NCTAB];
+  __shared__ double red[NW][9];
   int bid, kid;
   if (!coop_quartet(a.items, a.rows, a.kets, blockIdx.x, bid, kid)) return;
   const ShellPair bra = a.pairs[bid], ket = a.pairs[kid];
@@ -253,13 +271,14 @@ __global__ __launch_bounds__(64) void coop_grad_kernel(GradArgs a) {
   const double* __restrict__ P = a.P + mo;
   const double deg = ((bra.a == bra.b) ? 1.0 : 2.0) * ((ket.a == ket.b) ? 1.0 : 2.0) *
                      ((kid == bid) ? 1.0 : 2.0);
-  for (int e = threadIdx.x; e < NOUT; e += kWave) {
+  for (int e = threadIdx.x; e < NOUT; e += NT) {
     const int l = e % ND, k = (e / ND) % NC, j = (e / (ND * NC)) % NB, i = e / (ND * NC * NB);
     const int mu = sa.bf + i, nu = sb.bf + j, la = sc_.bf + k, si = sd.bf + l;
     G[e] = 0.5 * deg *
            (P[mu * n + nu] * P[la * n + si] -
             0.25 * (P[mu * n + la] * P[nu * n + si] + P[mu * n + si] * P[nu * n + la]));
   }
+  for (int t = threadIdx.x; t < CP::NCTAB; t += NT) ctab[t] = CP::con_ctab()[t];
   const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
   const double CD[3] = {sc_.x - sd.x, sc_.y - sd.y, sc_.z - sd.z};
   coop_primitives<CP>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
@@ -269,32 +288,45 @@ __global__ __launch_bounds__(64) void coop_grad_kernel(GradArgs a) {
   for (int k = 0; k < 9; ++k) g[k] = 0.0;
   const int* hs = CP::hrr_lstart();
   const int* cs = CP::con_lstart();
+  const unsigned long long* cw = CP::con_word();
   constexpr int NLOOP = CP::NHLEV + 1 > CP::NCLEV ? CP::NHLEV + 1 : CP::NCLEV;
   for (int lv = 0; lv < NLOOP; ++lv) {
     if (lv > 0 && lv <= CP::NHLEV) {
-      coop_level(hs[lv - 1], hs[lv], CP::hrr_dst(), CP::hrr_t0(), CP::hrr_src(), CP::hrr_sel(),
-                 CP::hrr_mult(), sc, slots);
+      coop_level<NT>(hs[lv - 1], hs[lv], CP::hrr_node(), CP::hrr_term(), sc, slots);
       __syncthreads();
     }
     if (lv < CP::NCLEV)
-      for (int c = cs[lv] + (int)threadIdx.x; c < cs[lv + 1]; c += kWave) {
-      const double v = CP::con_c()[c] * G[CP::con_G()[c]] * slots[CP::con_slot()[c]];
-      const int gk = CP::con_g()[c];
+      for (int c = cs[lv] + (int)threadIdx.x; c < cs[lv + 1]; c += NT) {
+        const unsigned long long w = cw[c];
+        const double v = ctab[(w >> 40) & 0xFFull] * G[(w >> 16) & 0xFFFFull] *
+                         slots[w & 0xFFFFull];
+        const int gk = (int)((w >> 32) & 0xFFull);
 #pragma unroll
-      for (int k = 0; k < 9; ++k) g[k] += (gk == k) ? v : 0.0;
-    }
+        for (int k = 0; k < 9; ++k) g[k] += (gk == k) ? v : 0.0;
+      }
     __syncthreads();
   }
+  // block reduction: across the wavefront, then across wavefronts
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
 #pragma unroll
-  for (int k = 0; k < 9; ++k)
+  for (int k = 0; k < 9; ++k) {
     for (int o = 32; o > 0; o >>= 1) g[k] += __shfl_xor(g[k], o, kWave);
+    if (lane == 0) red[wv][k] = g[k];
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    double t[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      t[k] = 0.0;
+      for (int w = 0; w < NW; ++w) t[k] += red[w][k];
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      atomicAdd(&a.grad[3 * sa.atom + d], g[d]);
-      atomicAdd(&a.grad[3 * sb.atom + d], g[3 + d]);
-      atomicAdd(&a.grad[3 * sc_.atom + d], g[6 + d]);
-      atomicAdd(&a.grad[3 * sd.atom + d], -(g[d] + g[3 + d] + g[6 + d]));
+      atomicAdd(&a.grad[3 * sa.atom + d], t[d]);
+      atomicAdd(&a.grad[3 * sb.atom + d], t[3 + d]);
+      atomicAdd(&a.grad[3 * sc_.atom + d], t[6 + d]);
+      atomicAdd(&a.grad[3 * sd.atom + d], -(t[d] + t[3 + d] + t[6 + d]));
     }
   }
 }
@@ -305,35 +337,37 @@ namespace bscf {
 
 // Schwarz bound of one pair per block: sqrt(max |(mn|mn)|) over the pair.
 template <class CP>
-__global__ __launch_bounds__(64) void coop_schwarz_kernel(SchwarzArgs a) {
+__global__ __launch_bounds__(CP::NT) void coop_schwarz_kernel(SchwarzArgs a) {
+  constexpr int NT = CP::NT, NW = NT / kWave;
   __shared__ double slots[CP::NSLOT];
   __shared__ double sc[kNumSel];
+  __shared__ double red[NW];
   const int pid = a.pair_ids[blockIdx.x];
   const ShellPair pr = a.pairs[pid];
   const Shell sa = a.shells[pr.a], sb = a.shells[pr.b];
   const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
   coop_primitives<CP>(a.prims + pr.prim0, pr.nprim, a.prims + pr.prim0, pr.nprim, AB, AB,
                       a.boys64, sc, slots);
-  const int* hs = CP::hrr_lstart();
-  for (int lv = 0; lv < CP::NHLEV; ++lv) {
-    coop_level(hs[lv], hs[lv + 1], CP::hrr_dst(), CP::hrr_t0(), CP::hrr_src(), CP::hrr_sel(),
-               CP::hrr_mult(), sc, slots);
-    __syncthreads();
-  }
+  coop_hrr<CP>(sc, slots);
   constexpr int NAB = ncart(CP::LA) * ncart(CP::LB);
   double m = 0.0;
-  for (int d = threadIdx.x; d < NAB; d += kWave) {
+  for (int d = threadIdx.x; d < NAB; d += NT) {
     const int e = d * NAB + d;
     m = fmax(m, fabs(slots[CP::out_slot()[e]] * CP::norm()[e]));
   }
   for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, kWave));
-  if (threadIdx.x == 0) a.Q[pid] = sqrt(m);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < NW; ++w) m = fmax(m, red[w]);
+    a.Q[pid] = sqrt(m);
+  }
 }
 
 // Full tensor of one instance (test path): every canonical quartet writes its
 // eight index permutations.
 template <class CP>
-__global__ __launch_bounds__(64) void coop_tensor_kernel(TensorArgs a) {
+__global__ __launch_bounds__(CP::NT) void coop_tensor_kernel(TensorArgs a) {
   __shared__ double slots[CP::NSLOT];
   __shared__ double sc[kNumSel];
   const ShellPair bra = a.pairs[a.quartets[2 * blockIdx.x]];
@@ -344,15 +378,10 @@ __global__ __launch_bounds__(64) void coop_tensor_kernel(TensorArgs a) {
   const double CD[3] = {sc_.x - sd.x, sc_.y - sd.y, sc_.z - sd.z};
   coop_primitives<CP>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
                       a.boys64, sc, slots);
-  const int* hs = CP::hrr_lstart();
-  for (int lv = 0; lv < CP::NHLEV; ++lv) {
-    coop_level(hs[lv], hs[lv + 1], CP::hrr_dst(), CP::hrr_t0(), CP::hrr_src(), CP::hrr_sel(),
-               CP::hrr_mult(), sc, slots);
-    __syncthreads();
-  }
+  coop_hrr<CP>(sc, slots);
   constexpr int NB = ncart(CP::LB), NC = ncart(CP::LC), ND = ncart(CP::LD);
   const long long n = a.n;
-  for (int e = threadIdx.x; e < CP::NOUT; e += kWave) {
+  for (int e = threadIdx.x; e < CP::NOUT; e += CP::NT) {
     const int l = e % ND, k = (e / ND) % NC, j = (e / (ND * NC)) % NB, i = e / (ND * NC * NB);
     const double x = slots[CP::out_slot()[e]] * CP::norm()[e];
     const long long m = sa.bf + i, nn = sb.bf + j, la = sc_.bf + k, s = sd.bf + l;

@@ -223,7 +223,14 @@ struct bscf_ctx {
   static constexpr int kAux = 4;   // streams for concurrent class kernels
   hipStream_t aux[kAux] = {};
   hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
-  hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;   // whole Fock build (profiling)
+  // profiling: event pairs recorded around launches and read back only when
+  // the statistics are requested, so the timed work is not synchronised
+  struct ProfRec {
+    hipEvent_t e0, e1;
+    int q, kind;   // class index; kind: 0 Fock class kernel, 1 gradient class kernel, 2 whole build
+  };
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_free;
   // Kernel variant per class: 0 = one quartet per lane, 1 = one quartet per
   // wavefront (cooperative); [precision mode][class] for the Fock build and
   // [class] for the gradient.  Chosen by timing both on the current work
@@ -241,7 +248,7 @@ struct bscf_ctx {
   // class kernels overlap on the auxiliary streams.
   int private_bytes[kNumQuartetClasses][3] = {};
   int coop_bytes[kNumQuartetClasses][2] = {};   // cooperative fock, gradient
-  double t_fock_gpu_ms = 0;
+  double t_fock_gpu_ms = 0, t_work_ms = 0;
   rocblas_handle blas = nullptr;
 
   std::map<int, std::vector<BasisShell>> basis;
@@ -278,9 +285,8 @@ struct bscf_ctx {
     double nquart = 0, nprimq = 0;
     std::vector<double> inst_quart, inst_primq;  // per instance
     // evaluated so far (active instances only) and measured kernel time
-    double done_quart = 0, done_primq = 0, kernel_ms = 0;
-    long launches = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double done_quart = 0, done_primq = 0, kernel_ms = 0, grad_ms = 0;
+    long launches = 0, grad_launches = 0;
   };
   ClassWork work[kNumQuartetClasses];
   std::vector<int> kets;
@@ -667,6 +673,41 @@ void build_work(bscf_ctx* c, double tau) {
   c->work_tau = tau;
 }
 
+// Start a profiled interval on stream s (returns its index) / end it.
+int prof_begin(bscf_ctx* c, int q, int kind, hipStream_t s) {
+  bscf_ctx::ProfRec r{nullptr, nullptr, q, kind};
+  for (hipEvent_t* e : {&r.e0, &r.e1}) {
+    if (c->prof_free.empty()) {
+      HIPCHK(hipEventCreate(e));
+    } else {
+      *e = c->prof_free.back();
+      c->prof_free.pop_back();
+    }
+  }
+  HIPCHK(hipEventRecord(r.e0, s));
+  c->prof_pending.push_back(r);
+  return (int)c->prof_pending.size() - 1;
+}
+
+void prof_end(bscf_ctx* c, int idx, hipStream_t s) {
+  HIPCHK(hipEventRecord(c->prof_pending[idx].e1, s));
+}
+
+// Read back every pending interval into the statistics.
+void prof_collect(bscf_ctx* c) {
+  for (auto& r : c->prof_pending) {
+    HIPCHK(hipEventSynchronize(r.e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, r.e0, r.e1));
+    if (r.kind == 0) c->work[r.q].kernel_ms += ms;
+    else if (r.kind == 1) c->work[r.q].grad_ms += ms;
+    else c->t_fock_gpu_ms += ms;
+    c->prof_free.push_back(r.e0);
+    c->prof_free.push_back(r.e1);
+  }
+  c->prof_pending.clear();
+}
+
 FockArgs fock_args(bscf_ctx* c, double* J, double* K, const int* active) {
   FockArgs a;
   a.items = nullptr;
@@ -758,7 +799,11 @@ void autotune_fock(bscf_ctx* c, int pcol) {
 }
 
 void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
-  if (tau != c->work_tau) build_work(c, tau);
+  if (tau != c->work_tau) {
+    const double tw = now_ms();
+    build_work(c, tau);
+    c->t_work_ms += now_ms() - tw;
+  }
   if (!c->fock_tuned[precision == BSCF_MIXED ? 1 : 0]) autotune_fock(c, precision == BSCF_MIXED ? 1 : 0);
   const double t0 = now_ms();
   launch_fill(c->J.p, c->mtot, 0.0, c->stream);
@@ -771,13 +816,7 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
   // are issued first because they are latency-bound.  Kernels that need
   // private scratch stay on the context stream: the runtime reserves scratch
   // per hardware queue for full occupancy.
-  if (c->profiling) {
-    if (!c->ev_b0) {
-      HIPCHK(hipEventCreate(&c->ev_b0));
-      HIPCHK(hipEventCreate(&c->ev_b1));
-    }
-    HIPCHK(hipEventRecord(c->ev_b0, c->stream));
-  }
+  const int pbuild = c->profiling ? prof_begin(c, 0, 2, c->stream) : -1;
   launch_gather_pk(kp, c->max_ncd, c->P.p, c->d_Pk.p, c->stream);
   HIPCHK(hipEventRecord(c->ev_fork, c->stream));
   for (int k = 0; k < bscf_ctx::kAux; ++k) HIPCHK(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
@@ -790,16 +829,10 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
     const int pbytes = var ? c->coop_bytes[q][0] : c->private_bytes[q][pcol];
     const hipStream_t s = pbytes != 0 ? c->stream : c->aux[slot++ % bscf_ctx::kAux];
     set_class(a, W);
-    if (c->profiling) {
-      if (!W.ev0) {
-        HIPCHK(hipEventCreate(&W.ev0));
-        HIPCHK(hipEventCreate(&W.ev1));
-      }
-      HIPCHK(hipEventRecord(W.ev0, s));
-    }
+    const int pk = c->profiling ? prof_begin(c, q, 0, s) : -1;
     if (var) qc[q].coop_fock(a, s);
     else qc[q].fock(a, pcol, s);
-    if (c->profiling) HIPCHK(hipEventRecord(W.ev1, s));
+    if (pk >= 0) prof_end(c, pk, s);
     for (int i = 0; i < c->ninst; ++i)
       if (!masked || c->h_active[i]) {
         W.done_quart += W.inst_quart[i];
@@ -813,20 +846,8 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
   }
   launch_jk_finalize(kp, c->max_ncd, c->d_Jk.p, c->J.p, c->stream);
   HIPCHK(hipGetLastError());
-  if (c->profiling) {
-    HIPCHK(hipEventRecord(c->ev_b1, c->stream));
-    sync(c);
-    float bms = 0.f;
-    HIPCHK(hipEventElapsedTime(&bms, c->ev_b0, c->ev_b1));
-    c->t_fock_gpu_ms += bms;
-    for (int q = 0; q < kNumQuartetClasses; ++q) {
-      auto& W = c->work[q];
-      if (W.items.empty()) continue;
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, W.ev0, W.ev1));
-      W.kernel_ms += ms;
-    }
-  }
+  if (pbuild >= 0) prof_end(c, pbuild, c->stream);
+  if (c->prof_pending.size() > 8192) prof_collect(c);
   BatchInfo b = c->batch(masked);
   launch_fock_assemble(b, c->max_n, c->H.p, c->J.p, c->K.p, c->P.p, c->d_Enuc.p, c->F.p, c->d_E.p,
                        c->stream);
@@ -917,10 +938,11 @@ bscf_status bscf_destroy(bscf_ctx* c) {
   if (!c) return BSCF_OK;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  for (auto& W : c->work) {
-    if (W.ev0) (void)hipEventDestroy(W.ev0);
-    if (W.ev1) (void)hipEventDestroy(W.ev1);
+  for (auto& r : c->prof_pending) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
   }
+  for (hipEvent_t e : c->prof_free) (void)hipEventDestroy(e);
   if (c->blas) rocblas_destroy_handle(c->blas);
   for (int k = 0; k < bscf_ctx::kAux; ++k) {
     if (c->aux[k]) (void)hipStreamSynchronize(c->aux[k]);
@@ -928,8 +950,6 @@ bscf_status bscf_destroy(bscf_ctx* c) {
     if (c->aux[k]) (void)hipStreamDestroy(c->aux[k]);
   }
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-  if (c->ev_b0) (void)hipEventDestroy(c->ev_b0);
-  if (c->ev_b1) (void)hipEventDestroy(c->ev_b1);
   hipStream_t s = c->stream;
   bool own = c->own_stream;
   delete c;
@@ -1427,16 +1447,35 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
     }
     // two-electron part over the same screened work lists
     GradArgs ga;
+    ga.items = nullptr;
+    ga.nitems = 0;
     ga.rows = nullptr;
+    ga.units = nullptr;
+    ga.nunits = 0;
+    ga.urows = nullptr;
     ga.pairs = c->d_pairs.p;
     ga.prims = c->d_prims.p;
     ga.shells = c->d_shells.p;
     ga.kets = c->d_kets.p;
     ga.moff = c->d_moff.p;
     ga.nbf = c->d_nbf.p;
+    ga.atom_off = c->d_atom_off.p;
+    ga.nmax = c->max_n;
+    ga.max_atoms = c->max_atoms;
+    ga.nk_total = (int)c->kets.size();
     ga.P = c->P.p;
+    ga.Pk = c->d_Pk.p;
     ga.grad = c->d_grad.p;
     ga.boys64 = c->d_boys64.p;
+    launch_gather_pk(ketpos_args(c), c->max_ncd, c->P.p, c->d_Pk.p, st);
+    auto set_gclass = [](GradArgs& g, const bscf_ctx::ClassWork& W) {
+      g.items = W.d_items.p;
+      g.nitems = (int)W.items.size();
+      g.rows = W.d_rows.p;
+      g.units = W.d_units.p;
+      g.nunits = (int)W.units.size();
+      g.urows = W.d_urows.p;
+    };
     const QuartetClass* qc = quartet_classes();
     if (!c->grad_tuned) {
       // time both gradient variants where both exist (into a throwaway buffer)
@@ -1448,12 +1487,16 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
       HIPCHK(hipEventCreate(&e1));
       for (int q = 0; q < kNumQuartetClasses; ++q) {
         auto& W = c->work[q];
-        if (!qc[q].grad || W.items.empty()) continue;
+        const bool lds_ok = sizeof(double) * (size_t)grad_unit_lds_doubles(
+                                qc[q].la, qc[q].lb, c->max_n, c->max_atoms) <= c->max_lds_bytes;
+        if (!qc[q].grad || !lds_ok) {
+          c->grad_variant[q] = 1;
+          continue;
+        }
+        if (W.items.empty()) continue;
         if (env && !strcmp(env, "lane")) { c->grad_variant[q] = 0; continue; }
         if (env && !strcmp(env, "coop")) { c->grad_variant[q] = 1; continue; }
-        gt.items = W.d_items.p;
-        gt.rows = W.d_rows.p;
-        gt.nitems = (int)W.items.size();
+        set_gclass(gt, W);
         for (int v = 0; v < 2; ++v) {
           HIPCHK(hipEventRecord(e0, st));
           if (v) qc[q].coop_grad(gt, st);
@@ -1474,14 +1517,15 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
     for (int q = kNumQuartetClasses - 1; q >= 0; --q) {
       auto& W = c->work[q];
       if (W.items.empty()) continue;
-      ga.items = W.d_items.p;
-      ga.rows = W.d_rows.p;
-      ga.nitems = (int)W.items.size();
+      set_gclass(ga, W);
       const int var = c->grad_variant[q];
       const int pbytes = var ? c->coop_bytes[q][1] : c->private_bytes[q][2];
       const hipStream_t s = pbytes != 0 ? st : c->aux[slot++ % bscf_ctx::kAux];
+      const int pk = c->profiling ? prof_begin(c, q, 1, s) : -1;
       if (var) qc[q].coop_grad(ga, s);
       else qc[q].grad(ga, s);
+      if (pk >= 0) prof_end(c, pk, s);
+      W.grad_launches++;
     }
     for (int k = 0; k < bscf_ctx::kAux; ++k) {
       HIPCHK(hipEventRecord(c->ev_join[k], c->aux[k]));
@@ -1614,11 +1658,12 @@ bscf_status bscf_set_profiling(bscf_ctx* c, int on) {
 bscf_status bscf_reset_stats(bscf_ctx* c) {
   return guard([&] {
     need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    prof_collect(c);
     for (auto& W : c->work) {
-      W.done_quart = W.done_primq = W.kernel_ms = 0;
-      W.launches = 0;
+      W.done_quart = W.done_primq = W.kernel_ms = W.grad_ms = 0;
+      W.launches = W.grad_launches = 0;
     }
-    c->t_fock_ms = c->t_scf_ms = c->t_grad_ms = c->t_setup_ms = c->t_fock_gpu_ms = 0;
+    c->t_fock_ms = c->t_scf_ms = c->t_grad_ms = c->t_setup_ms = c->t_fock_gpu_ms = c->t_work_ms = 0;
     c->fock_builds = c->scf_iters = 0;
   });
 }
@@ -1626,11 +1671,12 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
 bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
   return guard([&] {
     need(c && buf && len > 0, BSCF_E_INVALID, "bad arguments");
+    prof_collect(c);
     std::ostringstream s;
     s << "{\"fock_builds\": " << c->fock_builds << ", \"scf_iterations\": " << c->scf_iters
       << ", \"t_fock_ms\": " << c->t_fock_ms << ", \"t_scf_ms\": " << c->t_scf_ms
       << ", \"t_grad_ms\": " << c->t_grad_ms << ", \"t_setup_ms\": " << c->t_setup_ms
-      << ", \"t_fock_gpu_ms\": " << c->t_fock_gpu_ms
+      << ", \"t_fock_gpu_ms\": " << c->t_fock_gpu_ms << ", \"t_work_ms\": " << c->t_work_ms
       << ", \"classes\": {";
     const QuartetClass* qc = quartet_classes();
     for (int q = 0; q < kNumQuartetClasses; ++q) {
@@ -1644,6 +1690,7 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
         << ", \"items\": " << W.items.size() << ", \"done_quartets\": " << W.done_quart
         << ", \"done_prim_quartets\": " << W.done_primq << ", \"done_flops\": " << flops
         << ", \"kernel_ms\": " << W.kernel_ms << ", \"launches\": " << W.launches
+        << ", \"grad_ms\": " << W.grad_ms << ", \"grad_launches\": " << W.grad_launches
         << ", \"private_bytes\": [" << c->private_bytes[q][0] << ", " << c->private_bytes[q][1]
         << ", " << c->private_bytes[q][2] << "], \"variant\": [" << c->fock_variant[0][q] << ", "
         << c->fock_variant[1][q] << ", " << c->grad_variant[q] << "], \"tune_ms\": ["

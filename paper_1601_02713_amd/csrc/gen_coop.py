@@ -206,7 +206,7 @@ def energy_program(la, lb, lc, ld):
              for a in cart(la) for b in cart(lb) for c in cart(lc) for d in cart(ld)]
     vrr = encode([[(k, gv.nodes[k]) for k in lv] for lv in lv_v], slot_v)
     hrr = encode([[(k, gh.nodes[k]) for k in lv] for lv in lv_h], slot_h)
-    return dict(L=L, nslot=max(top_h, top_v), vrr=vrr, hrr=hrr, acc_slot=acc_slot,
+    return dict(L=L, lsh=(la, lb, lc, ld), nslot=max(top_h, top_v), vrr=vrr, hrr=hrr, acc_slot=acc_slot,
                 tgt_slot=tgt_slot, tgt_w=[0] * nacc, out_slot=out_slot, norms=norms,
                 nacc=nacc, nout=len(outs), fslot=nacc)
 
@@ -310,23 +310,105 @@ def grad_program(la, lb, lc, ld):
     for lst in con_by:
         flat += lst
         con_lstart.append(len(flat))
-    return dict(L=L, nslot=max(top_h, top_v), vrr=vrr, hrr=hrr, acc_slot=acc_slot,
+    return dict(L=L, lsh=(la, lb, lc, ld), nslot=max(top_h, top_v), vrr=vrr, hrr=hrr, acc_slot=acc_slot,
                 tgt_slot=tgt_slot, tgt_w=tw, nacc=nacc, nout=n, fslot=nacc,
                 con_lstart=con_lstart, con_slot=[slot_h[c[0]] for c in flat],
                 con_g=[c[1] for c in flat], con_G=[c[2] for c in flat], con_c=[c[3] for c in flat])
 
 
+def pack_phase(ph):
+    """Pack one phase for the device: a 64-bit word per node (first term,
+    destination slot, term count) and a 32-bit word per term (source slot,
+    scalar selector, multiplier + 8).  Multipliers are small integers."""
+    ls, dst, t0, src, sel, mult = ph
+    nodes, terms = [], []
+    for i, d in enumerate(dst):
+        cnt = t0[i + 1] - t0[i]
+        assert 0 <= d < 1 << 16 and 0 <= cnt < 1 << 8 and 0 <= t0[i] < 1 << 32
+        nodes.append(t0[i] | (d << 32) | (cnt << 48))
+    for x, se, m in zip(src, sel, mult):
+        assert m == int(m) and -8 <= m < 248 and 0 <= x < 1 << 16 and 0 <= se < 1 << 8
+        terms.append(x | (se << 16) | ((int(m) + 8) << 24))
+    return list(ls), nodes, terms
+
+
+def unpack_phase(ls, nodes, terms):
+    """Inverse of pack_phase (the decoding the kernels do)."""
+    dst = [(w >> 32) & 0xFFFF for w in nodes]
+    t0 = [w & 0xFFFFFFFF for w in nodes]
+    t0.append(t0[-1] + ((nodes[-1] >> 48) & 0xFF) if nodes else 0)
+    src = [u & 0xFFFF for u in terms]
+    sel = [(u >> 16) & 0xFF for u in terms]
+    mult = [float(((u >> 24) & 0xFF) - 8) for u in terms]
+    return list(ls), dst, t0, src, sel, mult
+
+
+def pack_con(prog):
+    """Gradient contraction entries as 64-bit words (slot, G index, gradient
+    component, coefficient index) plus the table of distinct coefficients."""
+    ctab = sorted(set(prog["con_c"]))
+    assert len(ctab) < 256
+    words = []
+    for sl, gk, G, c in zip(prog["con_slot"], prog["con_g"], prog["con_G"], prog["con_c"]):
+        assert 0 <= sl < 1 << 16 and 0 <= G < 1 << 16 and 0 <= gk < 9
+        words.append(sl | (G << 16) | (gk << 32) | (ctab.index(c) << 40))
+    return words, ctab
+
+
+def unpack_con(words, ctab):
+    return dict(con_slot=[w & 0xFFFF for w in words], con_G=[(w >> 16) & 0xFFFF for w in words],
+                con_g=[(w >> 32) & 0xFF for w in words], con_c=[ctab[(w >> 40) & 0xFF] for w in words])
+
+
+def packed(prog):
+    """The program with every table replaced by its decoded packed form."""
+    q = dict(prog)
+    for ph in ("vrr", "hrr"):
+        q[ph] = unpack_phase(*pack_phase(prog[ph]))
+    if "con_c" in prog:
+        q.update(unpack_con(*pack_con(prog)))
+    return q
+
+
+def lds_doubles(prog, grad):
+    """LDS of the cooperative kernels, in doubles (slots, scalars, and the
+    density factors (gradient) or the digestion blocks (Fock))."""
+    la, lb, lc, ld = prog["lsh"]
+    na, nb, nc, nd = (ncart(x) for x in (la, lb, lc, ld))
+    extra = na * nb * nc * nd + 16 + 9 * 8 if grad else (na * nb + nc * nd + (na + nb) * (nc + nd))
+    return prog["nslot"] + NSEL + extra
+
+
+def threads_per_block(prog, grad, lds_per_cu=160 * 1024):
+    """Threads that share one quartet: enough for about eight wavefronts per
+    CU once LDS limits the resident blocks, at most the program's typical
+    level width (rounded to wavefronts) and 512."""
+    per_cu = max(1, lds_per_cu // (8 * lds_doubles(prog, grad)))
+    nt = 64 * -(-8 // per_cu)
+    widths = []
+    for ph in ("vrr", "hrr"):
+        ls = prog[ph][0]
+        widths += [ls[i + 1] - ls[i] for i in range(len(ls) - 1)]
+    widths.sort()
+    med = widths[len(widths) // 2] if widths else 64
+    return max(64, min(nt, 512, (med // 64) * 64))
+
+
 def emit_tables(name, prog, grad=False):
-    """C++ constant tables of one program (namespace-scope __constant__)."""
+    """C++ constant tables of one program (namespace-scope __device__)."""
     def arr(t, nm, v):
-        body = ", ".join(repr(float(x)) if t == "double" else str(int(x)) for x in v) or "0"
-        return f"__device__ const {t} {name}_{nm}[{max(len(v), 1)}] = {{{body}}};"
+        if t == "double":
+            body = ", ".join(repr(float(x)) for x in v)
+        elif t == "unsigned long long":
+            body = ", ".join(f"{int(x)}ull" for x in v)
+        else:
+            body = ", ".join(str(int(x)) for x in v)
+        return f"__device__ const {t} {name}_{nm}[{max(len(v), 1)}] = {{{body or '0'}}};"
     out = [f"// cooperative tables: {prog['nslot']} LDS slots, L = {prog['L']}"]
     for ph in ("vrr", "hrr"):
-        ls, dst, t0, src, sel, mult = prog[ph]
-        out += [arr("int", f"{ph}_lstart", ls), arr("unsigned short", f"{ph}_dst", dst),
-                arr("int", f"{ph}_t0", t0), arr("unsigned short", f"{ph}_src", src),
-                arr("unsigned char", f"{ph}_sel", sel), arr("double", f"{ph}_mult", mult)]
+        ls, nodes, terms = pack_phase(prog[ph])
+        out += [arr("int", f"{ph}_lstart", ls), arr("unsigned long long", f"{ph}_node", nodes),
+                arr("unsigned int", f"{ph}_term", terms)]
     out += [arr("unsigned short", "acc_slot", prog["acc_slot"]),
             arr("unsigned short", "tgt_slot", prog["tgt_slot"]),
             arr("unsigned char", "tgt_w", prog["tgt_w"])]
@@ -334,11 +416,10 @@ def emit_tables(name, prog, grad=False):
         out += [arr("unsigned short", "out_slot", prog["out_slot"]),
                 arr("double", "norm", prog["norms"])]
     else:
+        words, ctab = pack_con(prog)
         out += [arr("int", "con_lstart", prog["con_lstart"]),
-                arr("unsigned short", "con_slot", prog["con_slot"]),
-                arr("unsigned char", "con_g", prog["con_g"]),
-                arr("unsigned short", "con_G", prog["con_G"]),
-                arr("double", "con_c", prog["con_c"])]
+                arr("unsigned long long", "con_word", words),
+                arr("double", "con_ctab", ctab)]
     return "\n".join(out)
 
 

@@ -416,18 +416,16 @@ def coop_tu(la, lb, lc, ld):
 
     def traits(name, p, prefix, grad):
         acc = [f"  __device__ static const {t}* {f}() {{ return {prefix}_{f}; }}"
-               for t, f in [("int", "vrr_lstart"), ("unsigned short", "vrr_dst"), ("int", "vrr_t0"),
-                            ("unsigned short", "vrr_src"), ("unsigned char", "vrr_sel"),
-                            ("double", "vrr_mult"), ("int", "hrr_lstart"), ("unsigned short", "hrr_dst"),
-                            ("int", "hrr_t0"), ("unsigned short", "hrr_src"), ("unsigned char", "hrr_sel"),
-                            ("double", "hrr_mult"), ("unsigned short", "acc_slot"),
-                            ("unsigned short", "tgt_slot"), ("unsigned char", "tgt_w")]]
+               for t, f in [("int", "vrr_lstart"), ("unsigned long long", "vrr_node"),
+                            ("unsigned int", "vrr_term"), ("int", "hrr_lstart"),
+                            ("unsigned long long", "hrr_node"), ("unsigned int", "hrr_term"),
+                            ("unsigned short", "acc_slot"), ("unsigned short", "tgt_slot"),
+                            ("unsigned char", "tgt_w")]]
         if grad:
             acc += [f"  __device__ static const {t}* {f}() {{ return {prefix}_{f}; }}"
-                    for t, f in [("int", "con_lstart"), ("unsigned short", "con_slot"),
-                                 ("unsigned char", "con_g"), ("unsigned short", "con_G"),
-                                 ("double", "con_c")]]
-            extra = f", NCLEV = {len(p['con_lstart']) - 1}"
+                    for t, f in [("int", "con_lstart"), ("unsigned long long", "con_word"),
+                                 ("double", "con_ctab")]]
+            extra = f", NCLEV = {len(p['con_lstart']) - 1}, NCTAB = {len(set(p['con_c']))}"
         else:
             acc += [f"  __device__ static const {t}* {f}() {{ return {prefix}_{f}; }}"
                     for t, f in [("unsigned short", "out_slot"), ("double", "norm")]]
@@ -438,6 +436,7 @@ def coop_tu(la, lb, lc, ld):
             f"  static constexpr int NSLOT = {p['nslot']}, NACC = {p['nacc']}, NOUT = {p['nout']}, "
             f"FSLOT = {p['fslot']};",
             f"  static constexpr int NVLEV = {len(p['vrr'][0]) - 1}, NHLEV = {len(p['hrr'][0]) - 1}{extra};",
+            f"  static constexpr int NT = {gen_coop.threads_per_block(p, grad)};   // threads per quartet",
         ] + acc + ["};", ""])
 
     lines = [f"// generated by gen_eri.py / gen_coop.py: cooperative kernels of class ({la}{lb}|{lc}{ld})",
@@ -447,15 +446,15 @@ def coop_tu(la, lb, lc, ld):
              "}  // namespace",
              f"void launch_coop_fock_{tag}(const FockArgs& a, hipStream_t s) {{",
              "  if (a.nitems == 0) return;",
-             f"  hipLaunchKernelGGL((coop_fock_kernel<CoopE{tag}>), dim3(a.nitems * 64), dim3(64), 0, s, a);",
+             f"  hipLaunchKernelGGL((coop_fock_kernel<CoopE{tag}>), dim3(a.nitems * 64), dim3(CoopE{tag}::NT), 0, s, a);",
              "}",
              f"void launch_coop_grad_{tag}(const GradArgs& a, hipStream_t s) {{",
              "  if (a.nitems == 0) return;",
-             f"  hipLaunchKernelGGL((coop_grad_kernel<CoopG{tag}>), dim3(a.nitems * 64), dim3(64), 0, s, a);",
+             f"  hipLaunchKernelGGL((coop_grad_kernel<CoopG{tag}>), dim3(a.nitems * 64), dim3(CoopG{tag}::NT), 0, s, a);",
              "}",
              f"void launch_coop_tensor_{tag}(const TensorArgs& a, hipStream_t s) {{",
              "  if (a.nquart == 0) return;",
-             f"  hipLaunchKernelGGL((coop_tensor_kernel<CoopE{tag}>), dim3(a.nquart), dim3(64), 0, s, a);",
+             f"  hipLaunchKernelGGL((coop_tensor_kernel<CoopE{tag}>), dim3(a.nquart), dim3(CoopE{tag}::NT), 0, s, a);",
              "}",
              f"int coop_private_bytes_{tag}(int which) {{",
              "  hipFuncAttributes at{};",
@@ -467,7 +466,7 @@ def coop_tu(la, lb, lc, ld):
     if (la, lb) == (lc, ld):
         lines += [f"void launch_coop_schwarz_{la}{lb}(const SchwarzArgs& a, hipStream_t s) {{",
                   "  if (a.npairs == 0) return;",
-                  f"  hipLaunchKernelGGL((coop_schwarz_kernel<CoopE{tag}>), dim3(a.npairs), dim3(64), 0, s, a);",
+                  f"  hipLaunchKernelGGL((coop_schwarz_kernel<CoopE{tag}>), dim3(a.npairs), dim3(CoopE{tag}::NT), 0, s, a);",
                   "}"]
     lines += ["}  // namespace bscf", ""]
     return "\n".join(lines), pe, pg
@@ -577,13 +576,13 @@ def main(outdir):
         tu = [f"// generated by gen_eri.py: gradient kernel of class ({la}{lb}|{lc}{ld})",
               '#include "grad_kernel.h"', f'#include "grad_{tag}.h"', "namespace bscf {",
               f"void launch_grad_{tag}(const GradArgs& a, hipStream_t s) {{",
-              "  const int blocks = (a.nitems + 3) / 4;",
-              "  if (blocks == 0) return;",
-              f"  hipLaunchKernelGGL((grad_kernel<ClsG{tag}>), dim3(blocks), dim3(256), 0, s, a);",
+              "  if (a.nunits == 0) return;",
+              f"  const size_t lds = sizeof(double) * grad_unit_lds_doubles({la}, {lb}, a.nmax, a.max_atoms);",
+              f"  hipLaunchKernelGGL((grad_unit_kernel<ClsG{tag}>), dim3(a.nunits), dim3(64), lds, s, a);",
               "}",
               f"int grad_private_bytes_{tag}() {{",
               "  hipFuncAttributes at{};",
-              f"  if (hipFuncGetAttributes(&at, reinterpret_cast<const void*>(&grad_kernel<ClsG{tag}>)) != hipSuccess) return -1;",
+              f"  if (hipFuncGetAttributes(&at, reinterpret_cast<const void*>(&grad_unit_kernel<ClsG{tag}>)) != hipSuccess) return -1;",
               "  return (int)at.localSizeBytes;",
               "}", "}  // namespace bscf", ""]
         write_if_changed(os.path.join(outdir, f"grad_{tag}.hip"), "\n".join(tu))

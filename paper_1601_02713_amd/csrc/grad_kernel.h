@@ -99,77 +99,109 @@ __device__ __forceinline__ T gwave_sum(T v) {
   return v;
 }
 
+// One wavefront per FockUnit (a bra pair and up to a few hundred kets; see
+// fock_kernel.h).  The density factor of each quartet is built from the bra
+// shells' P rows (LDS) and the ket block of Pk; dE/dR of the bra atoms is
+// reduced across the wavefront once per unit, that of the ket atoms is
+// accumulated per atom in LDS and flushed with contiguous atomics.
 template <class CG>
-__global__ __launch_bounds__(256) void grad_kernel(GradArgs a) {
+__global__ __launch_bounds__(64) void grad_unit_kernel(GradArgs a) {
   constexpr int NA = ncart(CG::LA), NB = ncart(CG::LB), NC = ncart(CG::LC), ND = ncart(CG::LD);
+  constexpr int NR = NA + NB;
   constexpr int NOUT = NA * NB * NC * ND;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int item_id = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-  if (item_id >= a.nitems) return;
-  const WorkItem it = a.items[item_id];
-  int bid, kid;
-  bool single;
-  const bool valid = lane_quartet(it, a.rows, a.kets, lane, bid, kid, single);
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x;
+  const WorkItem u = a.units[blockIdx.x];
+  const int bid = a.urows[u.row].bra;
   const ShellPair bra = a.pairs[bid];
   const Shell sa = a.shells[bra.a], sb = a.shells[bra.b];
   const int inst = sa.inst;
   const long long mo = a.moff[inst];
   const int n = a.nbf[inst];
-  const double* __restrict__ P = a.P + mo;
-  const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
   const int m0 = sa.bf, n0 = sb.bf;
-  const ShellPair ket = a.pairs[kid];
-  const Shell sc = a.shells[ket.a], sd = a.shells[ket.b];
-  const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
-  const double deg = ((bra.a == bra.b) ? 1.0 : 2.0) * ((ket.a == ket.b) ? 1.0 : 2.0) *
-                     ((kid == bid) ? 1.0 : 2.0);
-  const double fac = valid ? 0.5 * deg : 0.0;
-  const int l0 = sc.bf, s0 = sd.bf;
-  double G[NOUT];
-#pragma unroll
-  for (int i = 0; i < NA; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const double pab = P[(m0 + i) * n + n0 + j];
-#pragma unroll
-      for (int k = 0; k < NC; ++k)
-#pragma unroll
-        for (int l = 0; l < ND; ++l) {
-          const double pcd = P[(l0 + k) * n + s0 + l];
-          const double pac = P[(m0 + i) * n + l0 + k], pbd = P[(n0 + j) * n + s0 + l];
-          const double pad = P[(m0 + i) * n + s0 + l], pbc = P[(n0 + j) * n + l0 + k];
-          G[((i * NB + j) * NC + k) * ND + l] = fac * (pab * pcd - 0.25 * (pac * pbd + pad * pbc));
-        }
-    }
-  double g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  if constexpr (CG::LA + CG::LB + CG::LC + CG::LD >= 5) {
-    grad_block_outline<CG>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB,
-                           CD, a.boys64, G, g9);
-  } else {
-    grad_block_body<CG>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
-                        a.boys64, G, g9);
+  const int a0 = a.atom_off[inst];
+  double* Prow = lds;                 // P rows of bf m0 + r (r < NA) and n0 + r - NA
+  double* Gat = lds + NR * n;         // dE/dR per atom of the instance
+  const int nat3 = 3 * a.max_atoms;
+  for (int t = lane; t < NR * n; t += kWave) {
+    const int r = t / n, col = t - r * n;
+    const int bf = r < NA ? m0 + r : n0 + (r - NA);
+    Prow[t] = a.P[mo + (long long)bf * n + col];
   }
-  if (valid) {
+  for (int t = lane; t < nat3; t += kWave) Gat[t] = 0.0;
+  __syncthreads();
+  const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
+  double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
+  for (int c0 = 0; c0 < u.count; c0 += kWave) {
+    const int t = c0 + lane;
+    const bool valid = t < u.count;
+    int rr = u.row, k0 = u.off + (valid ? t : 0);
+    int nk = a.urows[rr].nket;
+    while (k0 >= nk) {
+      k0 -= nk;
+      ++rr;
+      nk = a.urows[rr].nket;
+    }
+    const int pos = a.urows[rr].ket0 + k0;
+    const int kid = a.kets[pos];
+    const ShellPair ket = a.pairs[kid];
+    const Shell sc = a.shells[ket.a], sd = a.shells[ket.b];
+    const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
+    const double deg = ((bra.a == bra.b) ? 1.0 : 2.0) * ((ket.a == ket.b) ? 1.0 : 2.0) *
+                       ((kid == bid) ? 1.0 : 2.0);
+    const double fac = valid ? 0.5 * deg : 0.0;
+    const int l0 = sc.bf, s0 = sd.bf;
+    double G[NOUT];
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+      for (int l = 0; l < ND; ++l) {
+        const double pcd = a.Pk[(long long)(k * ND + l) * a.nk_total + pos];
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            const double pab = Prow[i * n + n0 + j];
+            const double pac = Prow[i * n + l0 + k], pbd = Prow[(NA + j) * n + s0 + l];
+            const double pad = Prow[i * n + s0 + l], pbc = Prow[(NA + j) * n + l0 + k];
+            G[((i * NB + j) * NC + k) * ND + l] =
+                fac * (pab * pcd - 0.25 * (pac * pbd + pad * pbc));
+          }
+      }
+    double g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if constexpr (CG::LA + CG::LB + CG::LC + CG::LD >= 5) {
+      grad_block_outline<CG>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB,
+                             CD, a.boys64, G, g9);
+    } else {
+      grad_block_body<CG>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
+                          a.boys64, G, g9);
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      atomicAdd(&a.grad[3 * sc.atom + d], g9[6 + d]);
-      atomicAdd(&a.grad[3 * sd.atom + d], -(g9[d] + g9[3 + d] + g9[6 + d]));
+      gA[d] += g9[d];
+      gB[d] += g9[3 + d];
     }
-  }
-  if (single) {
+    if (valid) {
+      const int ac = sc.atom - a0, ad = sd.atom - a0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double x = gwave_sum(g9[d]), y = gwave_sum(g9[3 + d]);
-      if (lane == 0) {
-        atomicAdd(&a.grad[3 * sa.atom + d], x);
-        atomicAdd(&a.grad[3 * sb.atom + d], y);
+      for (int d = 0; d < 3; ++d) {
+        atomicAdd(&Gat[3 * ac + d], g9[6 + d]);
+        atomicAdd(&Gat[3 * ad + d], -(g9[d] + g9[3 + d] + g9[6 + d]));
       }
     }
-  } else if (valid) {
+  }
+  __syncthreads();
+  double* grad = a.grad + 3LL * a0;
+  for (int t = lane; t < nat3; t += kWave) {
+    const double x = Gat[t];
+    if (x != 0.0) atomicAdd(&grad[t], x);
+  }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      atomicAdd(&a.grad[3 * sa.atom + d], g9[d]);
-      atomicAdd(&a.grad[3 * sb.atom + d], g9[3 + d]);
+  for (int d = 0; d < 3; ++d) {
+    const double x = gwave_sum(gA[d]), y = gwave_sum(gB[d]);
+    if (lane == 0) {
+      atomicAdd(&a.grad[3 * sa.atom + d], x);
+      atomicAdd(&a.grad[3 * sb.atom + d], y);
     }
   }
 }

@@ -215,7 +215,8 @@ def _rand_contracted(ls, nprim):
                                        ("2220", (1, 1, 1, 2)), ("2222", (1, 1, 1, 1))])
 def test_cooperative_energy_program(tag, nprim):
     la, lb, lc, ld = map(int, tag)
-    prog = gen_coop.energy_program(la, lb, lc, ld)
+    # the tables as the kernels decode them (packed node/term words)
+    prog = gen_coop.packed(gen_coop.energy_program(la, lb, lc, ld))
     sh = _rand_contracted([la, lb, lc, ld], nprim)
     Fs, scs = _program_inputs(sh, la + lb + lc + ld)
     got = np.array(gen_coop.interpret(prog, Fs, scs, scs[0]))
@@ -229,7 +230,7 @@ def test_cooperative_energy_program(tag, nprim):
                                        ("2222", (1, 1, 1, 1))])
 def test_cooperative_gradient_program(tag, nprim):
     la, lb, lc, ld = map(int, tag)
-    prog = gen_coop.grad_program(la, lb, lc, ld)
+    prog = gen_coop.packed(gen_coop.grad_program(la, lb, lc, ld))
     sh = _rand_contracted([la, lb, lc, ld], nprim)
     Fs, scs = _program_inputs(sh, la + lb + lc + ld + 1)
     nout = gen_eri.ncart(la) * gen_eri.ncart(lb) * gen_eri.ncart(lc) * gen_eri.ncart(ld)
@@ -238,3 +239,18 @@ def test_cooperative_gradient_program(tag, nprim):
     _, der = _contracted_oracle(sh, deriv=True)
     ref = np.array([np.sum(G * der[cen, dd].ravel()) for cen in range(3) for dd in range(3)])
     assert np.abs(got - ref).max() <= 1e-11 * max(1.0, np.abs(ref).max()), (got, ref)
+
+
+@pytest.mark.parametrize("tag", ["0000", "2110", "2222"])
+def test_cooperative_tables_pack_losslessly(tag):
+    """Packed node/term/contraction words decode to the generated tables."""
+    la, lb, lc, ld = map(int, tag)
+    for prog in (gen_coop.energy_program(la, lb, lc, ld), gen_coop.grad_program(la, lb, lc, ld)):
+        q = gen_coop.packed(prog)
+        for ph in ("vrr", "hrr"):
+            assert [list(x) for x in q[ph]] == [list(x) for x in prog[ph]]
+        for k in ("con_slot", "con_G", "con_g", "con_c"):
+            if k in prog:
+                assert list(q[k]) == list(prog[k])
+        nt = gen_coop.threads_per_block(prog, "con_c" in prog)
+        assert nt % 64 == 0 and 64 <= nt <= 512
