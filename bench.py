@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="w8_beads")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--split", type=float, default=1e-4,
+                    help="mixed precision: quartets with Q_ab Q_cd below this run in FP32")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -83,7 +85,8 @@ def main():
     eng.set_instances(Zs)
     prec = beadscf.BSCF_MIXED if args.precision == "mixed" else beadscf.BSCF_FP64
     opts = beadscf.default_opts(e_tol=w["e_tol"], comm_tol=w["comm_tol"], schwarz_tol=1e-12,
-                                precision=prec, guess=beadscf.GUESS_CORE, max_iter=60)
+                                precision=prec, guess=beadscf.GUESS_CORE, max_iter=60,
+                                fp32_split_tol=args.split)
 
     def step():
         eng.set_geometries(xs)
@@ -156,6 +159,21 @@ def main():
         "energies_first_bead": float(E[0]),
         "classes": per_class,
     }
+    if prec == beadscf.BSCF_MIXED:
+        # accuracy of the timed (mixed) result against the FP64 path, bead by bead
+        fp32 = sum(c["done_quartets_fp32"] for c in cls.values())
+        o64 = beadscf.default_opts(e_tol=w["e_tol"], comm_tol=w["comm_tol"], schwarz_tol=1e-12,
+                                   precision=beadscf.BSCF_FP64, guess=beadscf.GUESS_CORE,
+                                   max_iter=60)
+        E64, _, _ = eng.run_scf(o64)
+        F64 = eng.forces()
+        dE = np.abs(np.asarray(E) - E64)
+        dF = np.array([np.abs(a - b).max() for a, b in zip(F, F64)])
+        out["mixed_precision"] = {
+            "fp32_split_tol": args.split, "fp32_quartet_share": fp32 / max(done_q, 1),
+            "max_abs_dE_vs_fp64_Eh": float(dE.max()), "max_abs_dF_vs_fp64_Eh_per_bohr": float(dF.max()),
+            "per_bead_abs_dE_Eh": [float(v) for v in dE],
+            "per_bead_max_abs_dF_Eh_per_bohr": [float(v) for v in dF]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -14,6 +14,8 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <atomic>
+#include <exception>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -24,6 +26,7 @@
 #include <sstream>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/beadscf.h"
@@ -40,6 +43,14 @@ namespace {
 // quartets per lane-kernel unit: the K rows of its bra are flushed once per
 // unit, so longer units amortise the flush, shorter ones spread the work
 constexpr int kUnitQuartets = 256;
+
+// The HIP runtime backs a kernel's private segment with scratch reserved per
+// hardware queue for full occupancy (bytes per lane x 64 lanes x 32 waves x
+// 256 CUs) and keeps the reservation while the process lives; several
+// contexts in one process reach several queues.  Lane kernels that spill more
+// than this many bytes per lane are never launched (their class runs
+// cooperatively), which bounds every queue's reservation to about 1 GiB.
+constexpr int kMaxLaneScratch = 2048;
 
 thread_local std::string g_err;
 
@@ -271,16 +282,28 @@ struct bscf_ctx {
   std::vector<double> xyz;
   bool have_geom = false, have_scf = false;
   std::vector<double> Q;           // per pair
-  double work_tau = -1.0;
+  double work_tau = -1.0, work_split = -1.0;
+  double split_tol = 1e-4;   // FP32 split of MIXED builds (from the last SCF options)
   // work lists per quartet class
   struct ClassWork {
     // 64-quartet items over rows grouped by primitive counts (cooperative
     // kernels, gradient) and per-bra units over rows grouped by bra (lane
     // Fock kernels)
-    std::vector<WorkItem> items, units;
-    std::vector<WorkRow> rows, urows;
-    DevBuf<WorkItem> d_items, d_units;
-    DevBuf<WorkRow> d_rows, d_urows;
+    std::vector<WorkItem> items;
+    std::vector<WorkRow> rows;
+    DevBuf<WorkItem> d_items;
+    DevBuf<WorkRow> d_rows;
+    // unit lists: kUnitsAll every screened quartet; kUnits64 / kUnits32 the
+    // quartets with Q_ab Q_cd at or above / below the FP32 split of MIXED mode
+    struct UnitList {
+      std::vector<WorkItem> units;
+      std::vector<WorkRow> rows;
+      DevBuf<WorkItem> d_units;
+      DevBuf<WorkRow> d_rows;
+    } ul[3];
+    double nquart32 = 0;                 // quartets of the FP32 list
+    std::vector<double> inst_quart32;    // per instance
+    double done_quart32 = 0;
     bool lds_ok = true;   // the lane kernel's LDS rows fit one workgroup
     double nquart = 0, nprimq = 0;
     std::vector<double> inst_quart, inst_primq;  // per instance
@@ -504,7 +527,7 @@ void build_shell_topology(bscf_ctx* c) {
 }
 
 // Work lists for the Fock build (see file comment).
-void build_work(bscf_ctx* c, double tau) {
+void build_work(bscf_ctx* c, double tau, double split) {
   const int NPC = kNumPairClasses;
   // per instance, per pair class: subclasses keyed by primitive count
   struct Sub {
@@ -544,7 +567,8 @@ void build_work(bscf_ctx* c, double tau) {
       }
     }
   const QuartetClass* qc = quartet_classes();
-  for (int q = 0; q < kNumQuartetClasses; ++q) {
+  // classes are independent: build their lists on host threads
+  auto build_class = [&](int q) {
     auto& W = c->work[q];
     W.items.clear();
     W.rows.clear();
@@ -557,9 +581,45 @@ void build_work(bscf_ctx* c, double tau) {
       WorkItem w;
       double cost;
     };
-    std::vector<Tmp> tmp, utmp;
-    W.units.clear();
-    W.urows.clear();
+    std::vector<Tmp> tmp, utmp[3];
+    for (auto& L : W.ul) {
+      L.units.clear();
+      L.rows.clear();
+    }
+    W.nquart32 = 0;
+    W.inst_quart32.assign(c->ninst, 0.0);
+    // count of kets of a Q-descending list with qb * q >= thr
+    auto prefix = [](const std::vector<double>& q, double qb, double thr) {
+      int lo = 0, hi = (int)q.size();
+      while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (qb * q[mid] >= thr) lo = mid + 1;
+        else hi = mid;
+      }
+      return lo;
+    };
+    // units of one bra over its rows [r0, r1) of list k: up to kUnitQuartets
+    // consecutive quartets across its rows (all ket primitive counts)
+    auto add_units = [&](int k, int r0, const std::vector<int>& kn, int bnprim) {
+      auto& L = W.ul[k];
+      const int r1 = (int)L.rows.size();
+      int rr = r0, off = 0;
+      while (rr < r1) {
+        WorkItem u{rr, off, 0, 0};
+        double cost = 0.0;
+        while (u.count < kUnitQuartets && rr < r1) {
+          const int t = std::min(L.rows[rr].nket - off, kUnitQuartets - u.count);
+          u.count += t;
+          cost += double(t) * bnprim * kn[rr - r0];
+          off += t;
+          if (off == L.rows[rr].nket) {
+            ++rr;
+            off = 0;
+          }
+        }
+        utmp[k].push_back({u, cost});
+      }
+    };
     for (int i = 0; i < c->ninst; ++i) {
       // rows of this instance grouped by (bra, ket) primitive counts
       std::vector<std::pair<std::pair<int, int>, std::vector<WorkRow>>> groups;
@@ -569,59 +629,41 @@ void build_work(bscf_ctx* c, double tau) {
           const double qb = bs.q[r];
           const int sb = sub_of[bra];
           const auto& kv = subs[i][Y];
-          const int ur0 = (int)W.urows.size();
-          std::vector<int> ur_nprim;
+          int ur0[3];
+          std::vector<int> ur_nprim[3];
+          for (int k = 0; k < 3; ++k) ur0[k] = (int)W.ul[k].rows.size();
           for (int t = 0; t < (int)kv.size(); ++t) {
             const Sub& ks = kv[t];
-            int lim;
-            if (tau > 0.0) {
-              // number of kets with qb * q >= tau (q sorted descending)
-              int lo = 0, hi = (int)ks.q.size();
-              while (lo < hi) {
-                const int mid = (lo + hi) / 2;
-                if (qb * ks.q[mid] >= tau) lo = mid + 1;
-                else hi = mid;
-              }
-              lim = lo;
-            } else {
-              lim = (int)ks.q.size();
-            }
+            int lim = tau > 0.0 ? prefix(ks.q, qb, tau) : (int)ks.q.size();
             if (X == Y) {
               if (t > sb) lim = 0;
               else if (t == sb) lim = std::min(lim, (int)r + 1);
             }
             if (lim == 0) continue;
+            const int n64 = std::min(lim, prefix(ks.q, qb, split));
             const std::pair<int, int> key(bs.nprim, ks.nprim);
             size_t g = 0;
             while (g < groups.size() && groups[g].first != key) ++g;
             if (g == groups.size()) groups.push_back({key, {}});
             groups[g].second.push_back(WorkRow{bra, ks.ket_off, lim, 0});
-            W.urows.push_back(WorkRow{bra, ks.ket_off, lim, 0});
-            ur_nprim.push_back(ks.nprim);
+            W.ul[0].rows.push_back(WorkRow{bra, ks.ket_off, lim, 0});
+            ur_nprim[0].push_back(ks.nprim);
+            if (n64 > 0) {
+              W.ul[1].rows.push_back(WorkRow{bra, ks.ket_off, n64, 0});
+              ur_nprim[1].push_back(ks.nprim);
+            }
+            if (lim > n64) {
+              W.ul[2].rows.push_back(WorkRow{bra, ks.ket_off + n64, lim - n64, 0});
+              ur_nprim[2].push_back(ks.nprim);
+            }
+            W.nquart32 += lim - n64;
+            W.inst_quart32[i] += lim - n64;
             W.nquart += lim;
             W.nprimq += double(lim) * bs.nprim * ks.nprim;
             W.inst_quart[i] += lim;
             W.inst_primq[i] += double(lim) * bs.nprim * ks.nprim;
           }
-          // units of this bra: up to kUnitQuartets consecutive quartets over
-          // its rows (all ket primitive counts)
-          const int ur1 = (int)W.urows.size();
-          int rr = ur0, off = 0;
-          while (rr < ur1) {
-            WorkItem u{rr, off, 0, 0};
-            double cost = 0.0;
-            while (u.count < kUnitQuartets && rr < ur1) {
-              const int t = std::min(W.urows[rr].nket - off, kUnitQuartets - u.count);
-              u.count += t;
-              cost += double(t) * bs.nprim * ur_nprim[rr - ur0];
-              off += t;
-              if (off == W.urows[rr].nket) {
-                ++rr;
-                off = 0;
-              }
-            }
-            utmp.push_back({u, cost});
-          }
+          for (int k = 0; k < 3; ++k) add_units(k, ur0[k], ur_nprim[k], bs.nprim);
         }
       // tile every group with items of up to 64 quartets (one per lane)
       for (auto& gr : groups) {
@@ -649,15 +691,43 @@ void build_work(bscf_ctx* c, double tau) {
     std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; });
     W.items.resize(tmp.size());
     for (size_t k = 0; k < tmp.size(); ++k) W.items[k] = tmp[k].w;
-    W.d_items.upload(W.items, c->stream);
-    W.d_rows.upload(W.rows, c->stream);
-    std::stable_sort(utmp.begin(), utmp.end(), [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; });
-    W.units.resize(utmp.size());
-    for (size_t k = 0; k < utmp.size(); ++k) W.units[k] = utmp[k].w;
-    W.d_units.upload(W.units, c->stream);
-    W.d_urows.upload(W.urows, c->stream);
+    for (int k = 0; k < 3; ++k) {
+      auto& ut = utmp[k];
+      std::stable_sort(ut.begin(), ut.end(), [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; });
+      W.ul[k].units.resize(ut.size());
+      for (size_t j = 0; j < ut.size(); ++j) W.ul[k].units[j] = ut[j].w;
+    }
     W.lds_ok = sizeof(double) * (size_t)unit_lds_doubles(qc[q].la, qc[q].lb, c->max_n) <=
                c->max_lds_bytes;
+  };
+  {
+    std::atomic<int> next{0};
+    std::vector<std::exception_ptr> err(kNumQuartetClasses);
+    auto worker = [&] {
+      for (int q; (q = next++) < kNumQuartetClasses;) {
+        try {
+          build_class(q);
+        } catch (...) {
+          err[q] = std::current_exception();
+        }
+      }
+    };
+    const int nth = std::max(1, std::min<int>(8, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nth; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto& th : pool) th.join();
+    for (auto& e : err)
+      if (e) std::rethrow_exception(e);
+  }
+  for (int q = 0; q < kNumQuartetClasses; ++q) {
+    auto& W = c->work[q];
+    W.d_items.upload(W.items, c->stream);
+    W.d_rows.upload(W.rows, c->stream);
+    for (auto& L : W.ul) {
+      L.d_units.upload(L.units, c->stream);
+      L.d_rows.upload(L.rows, c->stream);
+    }
   }
   c->d_kets.upload(c->kets, c->stream);
   // ket-position buffers; Jk is kept zero between builds by jk_finalize
@@ -671,6 +741,7 @@ void build_work(bscf_ctx* c, double tau) {
   c->d_Jk.resize(nkb);
   HIPCHK(hipMemsetAsync(c->d_Jk.p, 0, sizeof(double) * c->d_Jk.n, c->stream));
   c->work_tau = tau;
+  c->work_split = split;
 }
 
 // Start a profiled interval on stream s (returns its index) / end it.
@@ -735,13 +806,35 @@ FockArgs fock_args(bscf_ctx* c, double* J, double* K, const int* active) {
   return a;
 }
 
-void set_class(FockArgs& a, const bscf_ctx::ClassWork& W) {
+// Point a at the 64-quartet items of class W and at its unit list k.
+void set_class(FockArgs& a, const bscf_ctx::ClassWork& W, int k) {
   a.items = W.d_items.p;
   a.nitems = (int)W.items.size();
   a.rows = W.d_rows.p;
-  a.units = W.d_units.p;
-  a.nunits = (int)W.units.size();
-  a.urows = W.d_urows.p;
+  a.units = W.ul[k].d_units.p;
+  a.nunits = (int)W.ul[k].units.size();
+  a.urows = W.ul[k].d_rows.p;
+}
+
+// Lane-kernel launches of class q: every quartet in FP64, or in MIXED mode
+// the quartets above the split in FP64 and the rest in FP32.
+template <class Launch>
+void lane_launches(bscf_ctx* c, FockArgs& a, int q, int precision, Launch&& launch) {
+  const QuartetClass* qc = quartet_classes();
+  const auto& W = c->work[q];
+  if (precision != BSCF_MIXED) {
+    set_class(a, W, 0);
+    launch(0, [&](hipStream_t s) { qc[q].fock(a, 0, s); });
+  } else {
+    if (!W.ul[1].units.empty()) {
+      set_class(a, W, 1);
+      launch(0, [&](hipStream_t s) { qc[q].fock(a, 0, s); });
+    }
+    if (!W.ul[2].units.empty()) {
+      set_class(a, W, 2);
+      launch(1, [&](hipStream_t s) { qc[q].fock(a, 1, s); });
+    }
+  }
 }
 
 KetPosArgs ketpos_args(bscf_ctx* c) {
@@ -770,19 +863,21 @@ void autotune_fock(bscf_ctx* c, int pcol) {
   HIPCHK(hipEventCreate(&e1));
   for (int q = 0; q < kNumQuartetClasses; ++q) {
     auto& W = c->work[q];
-    if (!qc[q].fock || !W.lds_ok) {
+    if (!qc[q].fock || !W.lds_ok || c->private_bytes[q][0] > kMaxLaneScratch ||
+        (pcol && c->private_bytes[q][1] > kMaxLaneScratch)) {
       c->fock_variant[pcol][q] = 1;
       continue;
     }
     if (W.items.empty()) continue;
     if (env && !strcmp(env, "lane")) { c->fock_variant[pcol][q] = 0; continue; }
     if (env && !strcmp(env, "coop")) { c->fock_variant[pcol][q] = 1; continue; }
-    set_class(a, W);
+    set_class(a, W, 0);
     for (int v = 0; v < 2; ++v) {
       for (int rep = 0; rep < 2; ++rep) {
         HIPCHK(hipEventRecord(e0, c->stream));
         if (v) qc[q].coop_fock(a, c->stream);
-        else qc[q].fock(a, pcol, c->stream);
+        else lane_launches(c, a, q, pcol ? BSCF_MIXED : BSCF_FP64,
+                           [&](int, auto&& run) { run(c->stream); });
         HIPCHK(hipEventRecord(e1, c->stream));
       }
       HIPCHK(hipEventSynchronize(e1));
@@ -799,9 +894,9 @@ void autotune_fock(bscf_ctx* c, int pcol) {
 }
 
 void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
-  if (tau != c->work_tau) {
+  if (tau != c->work_tau || (precision == BSCF_MIXED && c->split_tol != c->work_split)) {
     const double tw = now_ms();
-    build_work(c, tau);
+    build_work(c, tau, c->split_tol);
     c->t_work_ms += now_ms() - tw;
   }
   if (!c->fock_tuned[precision == BSCF_MIXED ? 1 : 0]) autotune_fock(c, precision == BSCF_MIXED ? 1 : 0);
@@ -825,18 +920,26 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
   for (int q = kNumQuartetClasses - 1; q >= 0; --q) {
     auto& W = c->work[q];
     if (W.items.empty()) continue;
-    const int var = c->fock_variant[pcol][q];
-    const int pbytes = var ? c->coop_bytes[q][0] : c->private_bytes[q][pcol];
-    const hipStream_t s = pbytes != 0 ? c->stream : c->aux[slot++ % bscf_ctx::kAux];
-    set_class(a, W);
-    const int pk = c->profiling ? prof_begin(c, q, 0, s) : -1;
-    if (var) qc[q].coop_fock(a, s);
-    else qc[q].fock(a, pcol, s);
-    if (pk >= 0) prof_end(c, pk, s);
+    // one launch: kernels with private scratch go to the context stream
+    auto launch = [&](int pbytes, auto&& run) {
+      const hipStream_t s = pbytes != 0 ? c->stream : c->aux[slot++ % bscf_ctx::kAux];
+      const int pk = c->profiling ? prof_begin(c, q, 0, s) : -1;
+      run(s);
+      if (pk >= 0) prof_end(c, pk, s);
+    };
+    if (c->fock_variant[pcol][q]) {
+      set_class(a, W, 0);
+      launch(c->coop_bytes[q][0], [&](hipStream_t s) { qc[q].coop_fock(a, s); });
+    } else {
+      lane_launches(c, a, q, precision, [&](int fp32, auto&& run) {
+        launch(c->private_bytes[q][fp32], run);
+      });
+    }
     for (int i = 0; i < c->ninst; ++i)
       if (!masked || c->h_active[i]) {
         W.done_quart += W.inst_quart[i];
         W.done_primq += W.inst_primq[i];
+        if (precision == BSCF_MIXED && !c->fock_variant[pcol][q]) W.done_quart32 += W.inst_quart32[i];
       }
     W.launches++;
   }
@@ -918,8 +1021,9 @@ bscf_status bscf_create(int hip_device, void* hip_stream, bscf_ctx** out) {
           need(c->private_bytes[q][k] >= 0, BSCF_E_DEVICE, "hipFuncGetAttributes failed");
         for (int k = 0; k < 2; ++k)
           need(c->coop_bytes[q][k] >= 0, BSCF_E_DEVICE, "hipFuncGetAttributes failed");
-        c->fock_variant[0][q] = c->fock_variant[1][q] = qc[q].fock ? 0 : 1;
-        c->grad_variant[q] = qc[q].grad ? 0 : 1;
+        c->fock_variant[0][q] = qc[q].fock && c->private_bytes[q][0] <= kMaxLaneScratch ? 0 : 1;
+        c->fock_variant[1][q] = qc[q].fock && c->private_bytes[q][1] <= kMaxLaneScratch ? 0 : 1;
+        c->grad_variant[q] = qc[q].grad && c->private_bytes[q][2] <= kMaxLaneScratch ? 0 : 1;
       }
     }
     BLASCHK(rocblas_create_handle(&c->blas));
@@ -1313,6 +1417,8 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     bscf_default_opts(&o);
     if (opts) o = *opts;
     need(o.max_iter > 0 && o.diis_size >= 1 && o.diis_size <= 8, BSCF_E_INVALID, "bad options");
+    need(o.fp32_split_tol > 0.0, BSCF_E_INVALID, "fp32_split_tol must be positive");
+    c->split_tol = o.fp32_split_tol;
     const double t0 = now_ms();
     const hipStream_t st = c->stream;
     const int ni = c->ninst;
@@ -1472,9 +1578,9 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
       g.items = W.d_items.p;
       g.nitems = (int)W.items.size();
       g.rows = W.d_rows.p;
-      g.units = W.d_units.p;
-      g.nunits = (int)W.units.size();
-      g.urows = W.d_urows.p;
+      g.units = W.ul[0].d_units.p;
+      g.nunits = (int)W.ul[0].units.size();
+      g.urows = W.ul[0].d_rows.p;
     };
     const QuartetClass* qc = quartet_classes();
     if (!c->grad_tuned) {
@@ -1489,7 +1595,7 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
         auto& W = c->work[q];
         const bool lds_ok = sizeof(double) * (size_t)grad_unit_lds_doubles(
                                 qc[q].la, qc[q].lb, c->max_n, c->max_atoms) <= c->max_lds_bytes;
-        if (!qc[q].grad || !lds_ok) {
+        if (!qc[q].grad || !lds_ok || c->private_bytes[q][2] > kMaxLaneScratch) {
           c->grad_variant[q] = 1;
           continue;
         }
@@ -1627,7 +1733,7 @@ bscf_status bscf_work_counts(bscf_ctx* c, double* nq, double* npq, double* flops
   return guard([&] {
     need(c != nullptr, BSCF_E_INVALID, "NULL context");
     require_geom(c);
-    if (c->work_tau < 0) build_work(c, 1e-12);
+    if (c->work_tau < 0) build_work(c, 1e-12, c->split_tol);
     const QuartetClass* qc = quartet_classes();
     double a = 0, b = 0, f = 0;
     for (int q = 0; q < kNumQuartetClasses; ++q) {
@@ -1660,7 +1766,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
     need(c != nullptr, BSCF_E_INVALID, "NULL context");
     prof_collect(c);
     for (auto& W : c->work) {
-      W.done_quart = W.done_primq = W.kernel_ms = W.grad_ms = 0;
+      W.done_quart = W.done_primq = W.kernel_ms = W.grad_ms = W.done_quart32 = 0;
       W.launches = W.grad_launches = 0;
     }
     c->t_fock_ms = c->t_scf_ms = c->t_grad_ms = c->t_setup_ms = c->t_fock_gpu_ms = c->t_work_ms = 0;
@@ -1687,6 +1793,7 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
                            W.done_quart * (qc[q].hrr_flops + 12.0 * nout);
       s << (q ? ", " : "") << "\"" << qc[q].la << qc[q].lb << qc[q].lc << qc[q].ld
         << "\": {\"quartets\": " << W.nquart << ", \"prim_quartets\": " << W.nprimq
+        << ", \"quartets_fp32_list\": " << W.nquart32 << ", \"done_quartets_fp32\": " << W.done_quart32
         << ", \"items\": " << W.items.size() << ", \"done_quartets\": " << W.done_quart
         << ", \"done_prim_quartets\": " << W.done_primq << ", \"done_flops\": " << flops
         << ", \"kernel_ms\": " << W.kernel_ms << ", \"launches\": " << W.launches

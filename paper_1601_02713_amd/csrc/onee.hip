@@ -47,35 +47,30 @@ __device__ __forceinline__ double comp_factor(int lx, int ly, int lz) {
 
 constexpr int kMaxL1 = 3;           // shell l after one raise
 constexpr int kS1 = kMaxL1 + 4;     // 1-D overlap index range
+constexpr int kTeam = 64;           // threads per one-electron task
 
-struct OS1D {
-  double S[3][kS1][kS1];
-};
-
-__device__ void overlap_1d(double a, double b, const double* A, const double* B, int imax,
-                           int jmax, OS1D& o) {
+// 1-D overlap tables S[d][i][j], one direction per thread (threads 0..2).
+__device__ void overlap_1d_dir(double a, double b, double Ad, double Bd, int imax, int jmax,
+                               double (*S)[kS1]) {
   const double p = a + b, oo2p = 0.5 / p, mu = a * b / p;
-  for (int d = 0; d < 3; ++d) {
-    const double P = (a * A[d] + b * B[d]) / p;
-    const double XPA = P - A[d], XPB = P - B[d], XAB = A[d] - B[d];
-    double(*S)[kS1] = o.S[d];
-    S[0][0] = sqrt(M_PI / p) * exp(-mu * XAB * XAB);
-    for (int i = 0; i <= imax; ++i) {
-      if (i > 0) S[i][0] = XPA * S[i - 1][0] + (i > 1 ? (i - 1) * oo2p * S[i - 2][0] : 0.0);
-      for (int j = 1; j <= jmax; ++j)
-        S[i][j] = XPB * S[i][j - 1] + oo2p * ((i > 0 ? i * S[i - 1][j - 1] : 0.0) +
-                                              (j > 1 ? (j - 1) * S[i][j - 2] : 0.0));
-    }
+  const double P = (a * Ad + b * Bd) / p;
+  const double XPA = P - Ad, XPB = P - Bd, XAB = Ad - Bd;
+  S[0][0] = sqrt(M_PI / p) * exp(-mu * XAB * XAB);
+  for (int i = 0; i <= imax; ++i) {
+    if (i > 0) S[i][0] = XPA * S[i - 1][0] + (i > 1 ? (i - 1) * oo2p * S[i - 2][0] : 0.0);
+    for (int j = 1; j <= jmax; ++j)
+      S[i][j] = XPB * S[i][j - 1] + oo2p * ((i > 0 ? i * S[i - 1][j - 1] : 0.0) +
+                                            (j > 1 ? (j - 1) * S[i][j - 2] : 0.0));
   }
 }
 
-__device__ __forceinline__ double ov3(const OS1D& o, const int* ta, const int* tb) {
+__device__ __forceinline__ double ov3(const double (*S)[kS1][kS1], const int* ta, const int* tb) {
   for (int d = 0; d < 3; ++d)
     if (ta[d] < 0 || tb[d] < 0) return 0.0;
-  return o.S[0][ta[0]][tb[0]] * o.S[1][ta[1]][tb[1]] * o.S[2][ta[2]][tb[2]];
+  return S[0][ta[0]][tb[0]] * S[1][ta[1]][tb[1]] * S[2][ta[2]][tb[2]];
 }
 
-__device__ double kin3(const OS1D& o, const int* ta, const int* tb, double b) {
+__device__ double kin3(const double (*S)[kS1][kS1], const int* ta, const int* tb, double b) {
   if (ta[0] < 0 || ta[1] < 0 || ta[2] < 0 || tb[0] < 0 || tb[1] < 0 || tb[2] < 0) return 0.0;
   double t = 0.0;
   for (int d = 0; d < 3; ++d) {
@@ -83,94 +78,119 @@ __device__ double kin3(const OS1D& o, const int* ta, const int* tb, double b) {
     int tp[3] = {tb[0], tb[1], tb[2]}, tm[3] = {tb[0], tb[1], tb[2]};
     tp[d] += 2;
     tm[d] -= 2;
-    t += 4.0 * b * b * ov3(o, ta, tp) - 2.0 * b * (2 * j + 1) * ov3(o, ta, tb) +
-         (j > 1 ? j * (j - 1) * ov3(o, ta, tm) : 0.0);
+    t += 4.0 * b * b * ov3(S, ta, tp) - 2.0 * b * (2 * j + 1) * ov3(S, ta, tb) +
+         (j > 1 ? j * (j - 1) * ov3(S, ta, tm) : 0.0);
   }
   return -0.5 * t;
 }
 
 __host__ __device__ constexpr int ntup(int l) { return (l + 1) * (l + 2) * (l + 3) / 6; }
 
-// [a|1/r_C|b] for all tuples |a| <= LA, |b| <= LB (primitive, positive sign)
-template <int LA, int LB>
+// [a|1/r_C|b]^(m) for all tuples |a| <= TA, |b| <= TB (primitive, positive
+// sign), in LDS: v[m][tidx(a)][tidx(b)].
+template <int TA, int TB>
 struct NucTab {
-  double v[LA + LB + 1][ntup(LA)][ntup(LB)];
+  double v[TA + TB + 1][ntup(TA)][ntup(TB)];
+  double PA[3], PB[3], PC[3], oo2p;
 };
 
-template <int LA, int LB>
-__device__ void nuc_table(double a, double b, const double* A, const double* B, const double* C,
-                          const double* boys64, NucTab<LA, LB>& t) {
-  constexpr int la = LA, lb = LB;
-  const double p = a + b, oo2p = 0.5 / p, mu = a * b / p;
-  double P[3], PA[3], PB[3], PC[3], AB2 = 0.0, PC2 = 0.0;
-  for (int d = 0; d < 3; ++d) {
-    P[d] = (a * A[d] + b * B[d]) / p;
-    PA[d] = P[d] - A[d];
-    PB[d] = P[d] - B[d];
-    PC[d] = P[d] - C[d];
-    AB2 += (A[d] - B[d]) * (A[d] - B[d]);
-    PC2 += PC[d] * PC[d];
-  }
-  constexpr int L = LA + LB;
-  double F[L + 1];
-  const double pref = 2.0 * M_PI / p * exp(-mu * AB2);
-  boys_f64<L>(p * PC2, pref, boys64, F);
-  for (int tot = 0; tot <= L; ++tot)
-    for (int na = 0; na <= min(la, tot); ++na) {
-      const int nb = tot - na;
-      if (nb > lb) continue;
-      for (int ca = 0; ca < ncart(na); ++ca)
-        for (int cb = 0; cb < ncart(nb); ++cb) {
-          int ta[3], tb[3];
-          comp(na, ca, ta[0], ta[1], ta[2]);
-          comp(nb, cb, tb[0], tb[1], tb[2]);
-          const int ia = tidx(ta[0], ta[1], ta[2]), ib = tidx(tb[0], tb[1], tb[2]);
-          for (int m = 0; m <= L - tot; ++m) {
-            double r;
-            if (tot == 0) {
-              r = F[m];
-            } else if (nb > 0) {
-              const int i = tb[0] > 0 ? 0 : (tb[1] > 0 ? 1 : 2);
-              int b1[3] = {tb[0], tb[1], tb[2]};
-              b1[i] -= 1;
-              const int j1 = tidx(b1[0], b1[1], b1[2]);
-              r = PB[i] * t.v[m][ia][j1] - PC[i] * t.v[m + 1][ia][j1];
-              if (ta[i] > 0) {
-                int a1[3] = {ta[0], ta[1], ta[2]};
-                a1[i] -= 1;
-                const int i1 = tidx(a1[0], a1[1], a1[2]);
-                r += ta[i] * oo2p * (t.v[m][i1][j1] - t.v[m + 1][i1][j1]);
-              }
-              if (b1[i] > 0) {
-                int b2[3] = {b1[0], b1[1], b1[2]};
-                b2[i] -= 1;
-                const int j2 = tidx(b2[0], b2[1], b2[2]);
-                r += b1[i] * oo2p * (t.v[m][ia][j2] - t.v[m + 1][ia][j2]);
-              }
-            } else {
-              const int i = ta[0] > 0 ? 0 : (ta[1] > 0 ? 1 : 2);
-              int a1[3] = {ta[0], ta[1], ta[2]};
-              a1[i] -= 1;
-              const int i1 = tidx(a1[0], a1[1], a1[2]);
-              r = PA[i] * t.v[m][i1][ib] - PC[i] * t.v[m + 1][i1][ib];
-              if (a1[i] > 0) {
-                int a2[3] = {a1[0], a1[1], a1[2]};
-                a2[i] -= 1;
-                const int i2 = tidx(a2[0], a2[1], a2[2]);
-                r += a1[i] * oo2p * (t.v[m][i2][ib] - t.v[m + 1][i2][ib]);
-              }
-            }
-            t.v[m][ia][ib] = r;
-          }
-        }
+// Entry k of recursion level tot (na + nb = tot, m <= L - tot), ordered by na,
+// then the a and b components, then m.
+template <int TA, int TB>
+__device__ __forceinline__ bool nuc_entry(int tot, int k, int& na, int& nb, int& ca, int& cb,
+                                          int& m) {
+  constexpr int L = TA + TB;
+  const int nm = L - tot + 1;
+  for (na = (tot > TB ? tot - TB : 0); na <= (tot < TA ? tot : TA); ++na) {
+    nb = tot - na;
+    const int cnt = ncart(na) * ncart(nb) * nm;
+    if (k < cnt) {
+      m = k % nm;
+      k /= nm;
+      cb = k % ncart(nb);
+      ca = k / ncart(nb);
+      return true;
     }
+    k -= cnt;
+  }
+  return false;
 }
 
-template <int LA, int LB>
-__device__ __forceinline__ double nuc_get(const NucTab<LA, LB>& t, const int* ta, const int* tb) {
+// Fill the table cooperatively: thread 0 sets the Boys values and scalars,
+// then each level of total angular momentum is spread over the team.
+template <int TA, int TB>
+__device__ void nuc_table(double a, double b, const double* A, const double* B, const double* C,
+                          const double* boys64, NucTab<TA, TB>& t) {
+  constexpr int L = TA + TB;
+  if (threadIdx.x == 0) {
+    const double p = a + b, mu = a * b / p;
+    double AB2 = 0.0, PC2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double P = (a * A[d] + b * B[d]) / p;
+      t.PA[d] = P - A[d];
+      t.PB[d] = P - B[d];
+      t.PC[d] = P - C[d];
+      AB2 += (A[d] - B[d]) * (A[d] - B[d]);
+      PC2 += t.PC[d] * t.PC[d];
+    }
+    t.oo2p = 0.5 / p;
+    double F[L + 1];
+    boys_f64<L>(p * PC2, 2.0 * M_PI / p * exp(-mu * AB2), boys64, F);
+    for (int m = 0; m <= L; ++m) t.v[m][0][0] = F[m];
+  }
+  __syncthreads();
+  const double oo2p = t.oo2p;
+  for (int tot = 1; tot <= L; ++tot) {
+    for (int k = threadIdx.x;; k += kTeam) {
+      int na, nb, ca, cb, m;
+      if (!nuc_entry<TA, TB>(tot, k, na, nb, ca, cb, m)) break;
+      int ta[3], tb[3];
+      comp(na, ca, ta[0], ta[1], ta[2]);
+      comp(nb, cb, tb[0], tb[1], tb[2]);
+      const int ia = tidx(ta[0], ta[1], ta[2]), ib = tidx(tb[0], tb[1], tb[2]);
+      double r;
+      if (nb > 0) {
+        const int i = tb[0] > 0 ? 0 : (tb[1] > 0 ? 1 : 2);
+        int b1[3] = {tb[0], tb[1], tb[2]};
+        b1[i] -= 1;
+        const int j1 = tidx(b1[0], b1[1], b1[2]);
+        r = t.PB[i] * t.v[m][ia][j1] - t.PC[i] * t.v[m + 1][ia][j1];
+        if (ta[i] > 0) {
+          int a1[3] = {ta[0], ta[1], ta[2]};
+          a1[i] -= 1;
+          const int i1 = tidx(a1[0], a1[1], a1[2]);
+          r += ta[i] * oo2p * (t.v[m][i1][j1] - t.v[m + 1][i1][j1]);
+        }
+        if (b1[i] > 0) {
+          int b2[3] = {b1[0], b1[1], b1[2]};
+          b2[i] -= 1;
+          const int j2 = tidx(b2[0], b2[1], b2[2]);
+          r += b1[i] * oo2p * (t.v[m][ia][j2] - t.v[m + 1][ia][j2]);
+        }
+      } else {
+        const int i = ta[0] > 0 ? 0 : (ta[1] > 0 ? 1 : 2);
+        int a1[3] = {ta[0], ta[1], ta[2]};
+        a1[i] -= 1;
+        const int i1 = tidx(a1[0], a1[1], a1[2]);
+        r = t.PA[i] * t.v[m][i1][ib] - t.PC[i] * t.v[m + 1][i1][ib];
+        if (a1[i] > 0) {
+          int a2[3] = {a1[0], a1[1], a1[2]};
+          a2[i] -= 1;
+          const int i2 = tidx(a2[0], a2[1], a2[2]);
+          r += a1[i] * oo2p * (t.v[m][i2][ib] - t.v[m + 1][i2][ib]);
+        }
+      }
+      t.v[m][ia][ib] = r;
+    }
+    __syncthreads();
+  }
+}
+
+template <int TA, int TB>
+__device__ __forceinline__ double nuc_get(const NucTab<TA, TB>& t, const int* ta, const int* tb) {
   for (int d = 0; d < 3; ++d)
     if (ta[d] < 0 || tb[d] < 0) return 0.0;
-  if (ta[0] + ta[1] + ta[2] > LA || tb[0] + tb[1] + tb[2] > LB) return 0.0;
+  if (ta[0] + ta[1] + ta[2] > TA || tb[0] + tb[1] + tb[2] > TB) return 0.0;
   return t.v[0][tidx(ta[0], ta[1], ta[2])][tidx(tb[0], tb[1], tb[2])];
 }
 
@@ -207,83 +227,81 @@ __global__ void prim_pair_kernel(PrimPairSetupArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// S, T, V: one thread per (shell pair a >= b of one instance) x nucleus chunk.
-// V is accumulated with atomics over nuclei; S and T are written by the
-// thread handling nucleus 0.  Output is the normalised-component basis.
+// S, T, V: one 64-thread block per (shell pair a >= b of one instance) x
+// nucleus; the recursion tables live in LDS and each thread owns component
+// pairs of the shell block.  V is accumulated with atomics over nuclei; S and
+// T are written by the block of nucleus 0.  Output is the normalised-component
+// basis.
 template <int LA, int LB>
-__global__ void onee_kernel(OneEArgs a) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.ntasks) return;
-  const int pidx = t / a.atoms_per_task_stride;
-  const int cidx = t % a.atoms_per_task_stride;
+__global__ __launch_bounds__(kTeam) void onee_kernel(OneEArgs a) {
+  __shared__ NucTab<LA, LB> nt;
+  __shared__ double S1[3][kS1][kS1];
+  const int pidx = blockIdx.x / a.atoms_per_task_stride;
+  const int cidx = blockIdx.x % a.atoms_per_task_stride;
   const int sh_a = a.task_a[pidx], sh_b = a.task_b[pidx];
   const Shell sa = a.shells[sh_a], sb = a.shells[sh_b];
   const int inst = sa.inst;
-  const int nat = a.natoms[inst];
-  if (cidx >= nat) return;
+  if (cidx >= a.natoms[inst]) return;
   const int n = a.nbf[inst];
   const long long mo = a.moff[inst];
   const int atom = a.atom_off[inst] + cidx;
   const double A[3] = {sa.x, sa.y, sa.z}, B[3] = {sb.x, sb.y, sb.z};
   const double Cc[3] = {a.atom_xyz[3 * atom], a.atom_xyz[3 * atom + 1], a.atom_xyz[3 * atom + 2]};
   const double Zc = a.atom_Z[atom];
-  const int na = ncart(sa.l), nb = ncart(sb.l);
-  double Sb[6][6], Tb[6][6], Vb[6][6];
-  for (int i = 0; i < na; ++i)
-    for (int j = 0; j < nb; ++j) Sb[i][j] = Tb[i][j] = Vb[i][j] = 0.0;
-  NucTab<LA, LB> nt;
-  OS1D o;
+  constexpr int NA = ncart(LA), NB = ncart(LB);
+  const int e = threadIdx.x;   // component pair of this thread (NA * NB <= 36 < kTeam)
+  const int i = e / NB, j = e % NB;
+  int ta[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
+  if (e < NA * NB) {
+    comp(LA, i, ta[0], ta[1], ta[2]);
+    comp(LB, j, tb[0], tb[1], tb[2]);
+  }
+  double Sv = 0.0, Tv = 0.0, Vv = 0.0;
   for (int ka = 0; ka < sa.nprim; ++ka)
     for (int kb = 0; kb < sb.nprim; ++kb) {
       const double al = a.sh_exp[sa.prim0 + ka], be = a.sh_exp[sb.prim0 + kb];
       const double cc = a.sh_coef[sa.prim0 + ka] * a.sh_coef[sb.prim0 + kb];
-      nuc_table<LA, LB>(al, be, A, B, Cc, a.boys64, nt);
-      if (cidx == 0) overlap_1d(al, be, A, B, sa.l, sb.l + 2, o);
-      for (int i = 0; i < na; ++i)
-        for (int j = 0; j < nb; ++j) {
-          int ta[3], tb[3];
-          comp(sa.l, i, ta[0], ta[1], ta[2]);
-          comp(sb.l, j, tb[0], tb[1], tb[2]);
-          Vb[i][j] -= Zc * cc * nuc_get(nt, ta, tb);
-          if (cidx == 0) {
-            Sb[i][j] += cc * ov3(o, ta, tb);
-            Tb[i][j] += cc * kin3(o, ta, tb, be);
-          }
+      __syncthreads();   // previous primitive's tables read
+      if (cidx == 0 && threadIdx.x < 3)
+        overlap_1d_dir(al, be, A[threadIdx.x], B[threadIdx.x], LA, LB + 2, S1[threadIdx.x]);
+      nuc_table<LA, LB>(al, be, A, B, Cc, a.boys64, nt);   // ends with a barrier
+      if (e < NA * NB) {
+        Vv -= Zc * cc * nuc_get(nt, ta, tb);
+        if (cidx == 0) {
+          Sv += cc * ov3(S1, ta, tb);
+          Tv += cc * kin3(S1, ta, tb, be);
         }
-    }
-  for (int i = 0; i < na; ++i)
-    for (int j = 0; j < nb; ++j) {
-      int ta[3], tb[3];
-      comp(sa.l, i, ta[0], ta[1], ta[2]);
-      comp(sb.l, j, tb[0], tb[1], tb[2]);
-      const double f = comp_factor(ta[0], ta[1], ta[2]) * comp_factor(tb[0], tb[1], tb[2]);
-      const long long ij = mo + (long long)(sa.bf + i) * n + sb.bf + j;
-      const long long ji = mo + (long long)(sb.bf + j) * n + sa.bf + i;
-      atomicAdd(&a.V[ij], f * Vb[i][j]);
-      if (sh_a != sh_b) atomicAdd(&a.V[ji], f * Vb[i][j]);
-      if (cidx == 0) {
-        a.S[ij] = f * Sb[i][j];
-        a.S[ji] = f * Sb[i][j];
-        a.T[ij] = f * Tb[i][j];
-        a.T[ji] = f * Tb[i][j];
       }
     }
+  if (e < NA * NB) {
+    const double f = comp_factor(ta[0], ta[1], ta[2]) * comp_factor(tb[0], tb[1], tb[2]);
+    const long long ij = mo + (long long)(sa.bf + i) * n + sb.bf + j;
+    const long long ji = mo + (long long)(sb.bf + j) * n + sa.bf + i;
+    atomicAdd(&a.V[ij], f * Vv);
+    if (sh_a != sh_b) atomicAdd(&a.V[ji], f * Vv);
+    if (cidx == 0) {
+      a.S[ij] = f * Sv;
+      a.S[ji] = f * Sv;
+      a.T[ij] = f * Tv;
+      a.T[ji] = f * Tv;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
-// One-electron gradient: sum P dH/dX - sum W dS/dX per atom; one thread per
-// (ordered pair a >= b) x nucleus, off-diagonal pairs counted twice.
+// One-electron gradient: sum P dH/dX - sum W dS/dX per atom; one 64-thread
+// block per (pair a >= b) x nucleus, off-diagonal pairs counted twice, tables
+// in LDS, component pairs over the threads, a wavefront reduction at the end.
 template <int LA, int LB>
-__global__ void grad1e_kernel(Grad1EArgs a) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.ntasks) return;
-  const int pidx = t / a.atoms_per_task_stride;
-  const int cidx = t % a.atoms_per_task_stride;
+__global__ __launch_bounds__(kTeam) void grad1e_kernel(Grad1EArgs a) {
+  __shared__ NucTab<LA + 1, LB + 1> nt;
+  __shared__ double S1[3][kS1][kS1];
+  const int pidx = blockIdx.x / a.atoms_per_task_stride;
+  const int cidx = blockIdx.x % a.atoms_per_task_stride;
   const int sh_a = a.task_a[pidx], sh_b = a.task_b[pidx];
   const Shell sa = a.shells[sh_a], sb = a.shells[sh_b];
   const int inst = sa.inst;
-  const int nat = a.natoms[inst];
-  if (cidx >= nat) return;
+  if (cidx >= a.natoms[inst]) return;
   if (!a.active[inst]) return;
   const int n = a.nbf[inst];
   const long long mo = a.moff[inst];
@@ -291,59 +309,67 @@ __global__ void grad1e_kernel(Grad1EArgs a) {
   const double A[3] = {sa.x, sa.y, sa.z}, B[3] = {sb.x, sb.y, sb.z};
   const double Cc[3] = {a.atom_xyz[3 * atom], a.atom_xyz[3 * atom + 1], a.atom_xyz[3 * atom + 2]};
   const double Zc = a.atom_Z[atom];
-  const int na = ncart(sa.l), nb = ncart(sb.l);
+  constexpr int NA = ncart(LA), NB = ncart(LB);
   const double sym = (sh_a == sh_b) ? 1.0 : 2.0;
-  double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0}, gC[3] = {0, 0, 0};
-  NucTab<LA + 1, LB + 1> nt;
-  OS1D o;
+  const int e = threadIdx.x;
+  const bool own = e < NA * NB;
+  int ta[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
+  double pij = 0.0, wij = 0.0;
+  if (own) {
+    comp(LA, e / NB, ta[0], ta[1], ta[2]);
+    comp(LB, e % NB, tb[0], tb[1], tb[2]);
+    const double f = comp_factor(ta[0], ta[1], ta[2]) * comp_factor(tb[0], tb[1], tb[2]);
+    const long long ij = mo + (long long)(sa.bf + e / NB) * n + sb.bf + e % NB;
+    pij = sym * f * a.P[ij];
+    wij = sym * f * a.W[ij];
+  }
+  double g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // A, B, C
   for (int ka = 0; ka < sa.nprim; ++ka)
     for (int kb = 0; kb < sb.nprim; ++kb) {
       const double al = a.sh_exp[sa.prim0 + ka], be = a.sh_exp[sb.prim0 + kb];
       const double cc = a.sh_coef[sa.prim0 + ka] * a.sh_coef[sb.prim0 + kb];
+      __syncthreads();
+      if (cidx == 0 && threadIdx.x < 3)
+        overlap_1d_dir(al, be, A[threadIdx.x], B[threadIdx.x], LA + 1, LB + 3, S1[threadIdx.x]);
       nuc_table<LA + 1, LB + 1>(al, be, A, B, Cc, a.boys64, nt);
-      if (cidx == 0) overlap_1d(al, be, A, B, sa.l + 1, sb.l + 3, o);
-      for (int i = 0; i < na; ++i)
-        for (int j = 0; j < nb; ++j) {
-          int ta[3], tb[3];
-          comp(sa.l, i, ta[0], ta[1], ta[2]);
-          comp(sb.l, j, tb[0], tb[1], tb[2]);
-          const double f = cc * comp_factor(ta[0], ta[1], ta[2]) * comp_factor(tb[0], tb[1], tb[2]);
-          const long long ij = mo + (long long)(sa.bf + i) * n + sb.bf + j;
-          const double pij = sym * f * a.P[ij], wij = sym * f * a.W[ij];
-          for (int d = 0; d < 3; ++d) {
-            int up[3] = {ta[0], ta[1], ta[2]}, dn[3] = {ta[0], ta[1], ta[2]};
-            up[d] += 1;
-            dn[d] -= 1;
-            int upb[3] = {tb[0], tb[1], tb[2]}, dnb[3] = {tb[0], tb[1], tb[2]};
-            upb[d] += 1;
-            dnb[d] -= 1;
-            // nuclear attraction of this nucleus, basis-centre derivatives
-            const double vA = -Zc * (2 * al * nuc_get(nt, up, tb) - ta[d] * nuc_get(nt, dn, tb));
-            const double vB = -Zc * (2 * be * nuc_get(nt, ta, upb) - tb[d] * nuc_get(nt, ta, dnb));
-            gA[d] += pij * vA;
-            gB[d] += pij * vB;
-            gC[d] -= pij * (vA + vB);
-            if (cidx == 0) {
-              const double sA = 2 * al * ov3(o, up, tb) - ta[d] * ov3(o, dn, tb);
-              const double sB = 2 * be * ov3(o, ta, upb) - tb[d] * ov3(o, ta, dnb);
-              const double kA = 2 * al * kin3(o, up, tb, be) - ta[d] * kin3(o, dn, tb, be);
-              const double kB = 2 * be * kin3(o, ta, upb, be) - tb[d] * kin3(o, ta, dnb, be);
-              gA[d] += pij * kA - wij * sA;
-              gB[d] += pij * kB - wij * sB;
-            }
-          }
+      if (!own) continue;
+      for (int d = 0; d < 3; ++d) {
+        int up[3] = {ta[0], ta[1], ta[2]}, dn[3] = {ta[0], ta[1], ta[2]};
+        up[d] += 1;
+        dn[d] -= 1;
+        int upb[3] = {tb[0], tb[1], tb[2]}, dnb[3] = {tb[0], tb[1], tb[2]};
+        upb[d] += 1;
+        dnb[d] -= 1;
+        // nuclear attraction of this nucleus, basis-centre derivatives
+        const double vA = -Zc * (2 * al * nuc_get(nt, up, tb) - ta[d] * nuc_get(nt, dn, tb));
+        const double vB = -Zc * (2 * be * nuc_get(nt, ta, upb) - tb[d] * nuc_get(nt, ta, dnb));
+        g[d] += cc * pij * vA;
+        g[3 + d] += cc * pij * vB;
+        g[6 + d] -= cc * pij * (vA + vB);
+        if (cidx == 0) {
+          const double sA = 2 * al * ov3(S1, up, tb) - ta[d] * ov3(S1, dn, tb);
+          const double sB = 2 * be * ov3(S1, ta, upb) - tb[d] * ov3(S1, ta, dnb);
+          const double kA = 2 * al * kin3(S1, up, tb, be) - ta[d] * kin3(S1, dn, tb, be);
+          const double kB = 2 * be * kin3(S1, ta, upb, be) - tb[d] * kin3(S1, ta, dnb, be);
+          g[d] += cc * (pij * kA - wij * sA);
+          g[3 + d] += cc * (pij * kB - wij * sB);
         }
+      }
     }
-  for (int d = 0; d < 3; ++d) {
-    atomicAdd(&a.grad[3 * sa.atom + d], gA[d]);
-    atomicAdd(&a.grad[3 * sb.atom + d], gB[d]);
-    atomicAdd(&a.grad[3 * atom + d], gC[d]);
-  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    for (int o = 32; o > 0; o >>= 1) g[k] += __shfl_xor(g[k], o, kTeam);
+  if (threadIdx.x == 0)
+    for (int d = 0; d < 3; ++d) {
+      atomicAdd(&a.grad[3 * sa.atom + d], g[d]);
+      atomicAdd(&a.grad[3 * sb.atom + d], g[3 + d]);
+      atomicAdd(&a.grad[3 * atom + d], g[6 + d]);
+    }
 }
 
 void launch_onee(int la, int lb, const OneEArgs& a, hipStream_t s) {
   if (a.ntasks == 0) return;
-  const dim3 g((a.ntasks + 127) / 128), b(128);
+  const dim3 g(a.ntasks), b(kTeam);
 #define BSCF_ONEE(X, Y) \
   if (la == X && lb == Y) { hipLaunchKernelGGL((onee_kernel<X, Y>), g, b, 0, s, a); return; }
   BSCF_ONEE(0, 0) BSCF_ONEE(1, 0) BSCF_ONEE(1, 1) BSCF_ONEE(2, 0) BSCF_ONEE(2, 1) BSCF_ONEE(2, 2)
@@ -352,7 +378,7 @@ void launch_onee(int la, int lb, const OneEArgs& a, hipStream_t s) {
 
 void launch_grad1e(int la, int lb, const Grad1EArgs& a, hipStream_t s) {
   if (a.ntasks == 0) return;
-  const dim3 g((a.ntasks + 127) / 128), b(128);
+  const dim3 g(a.ntasks), b(kTeam);
 #define BSCF_G1(X, Y) \
   if (la == X && lb == Y) { hipLaunchKernelGGL((grad1e_kernel<X, Y>), g, b, 0, s, a); return; }
   BSCF_G1(0, 0) BSCF_G1(1, 0) BSCF_G1(1, 1) BSCF_G1(2, 0) BSCF_G1(2, 1) BSCF_G1(2, 2)

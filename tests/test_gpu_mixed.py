@@ -1,0 +1,105 @@
+"""Mixed precision on the GPU: shell quartets whose Schwarz product lies below
+the split are evaluated in FP32 (FP32 VRR/HRR, FP32 Boys body), the rest in
+FP64, with J/K accumulation, the SCF algebra, the energy sums and the forces in
+FP64.  The bar: energies within 1e-6 Eh and forces within 1e-5 Eh/bohr of the
+FP64 oracle; the split is checked at both ends (all FP64 reproduces the FP64
+path, all FP32 still converges).
+"""
+
+import json
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+E_TOL_MIXED = 1e-6     # Eh
+F_TOL_MIXED = 1e-5     # Eh/bohr
+
+
+@pytest.fixture(scope="module")
+def beadscf():
+    from paper_1601_02713_amd import beadscf as b
+    return b
+
+
+@pytest.fixture(scope="module")
+def eng(beadscf):
+    e = beadscf.Engine(0)
+    yield e
+    e.close()
+
+
+def _setup(eng, basis_name, instances):
+    eng.load_basis(inputs.load_basis(basis_name))
+    eng.set_instances([z for z, _ in instances])
+    eng.set_geometries([x for _, x in instances])
+
+
+def _fp32_fraction(stats):
+    cls = stats["classes"].values()
+    return sum(c["done_quartets_fp32"] for c in cls) / max(sum(c["done_quartets"] for c in cls), 1)
+
+
+def test_mixed_energy_and_forces_against_oracle(eng, beadscf, b631gs):
+    """Two (H2O)2 beads, default split 1e-4: oracle FP64 energies and forces."""
+    z, x = inputs.water_cluster(2, 11)
+    bx = inputs.beads(z, x, 2, 11)
+    inst = [(z, bx[k]) for k in range(2)]
+    _setup(eng, "6-31g*", inst)
+    eng.reset_stats()
+    E, it, st = eng.run_scf(e_tol=1e-10, comm_tol=1e-8, precision=beadscf.BSCF_MIXED)
+    frac = _fp32_fraction(eng.stats())
+    F = eng.forces()
+    assert (st == 0).all()
+    assert frac > 0.0, frac          # the FP32 path is exercised (its share grows with size)
+    for k in range(2):
+        b = oracle.build_basis(b631gs, *inst[k])
+        r = oracle.scf(b, 1e-10, 1e-8)
+        g = oracle.gradient(b, r["P"], r["F"])
+        print(f"bead {k}: |dE| {abs(E[k] - r['E']):.2e} Eh, max|dF| {np.abs(F[k] + g).max():.2e} "
+              f"Eh/bohr, FP32 share {frac:.3f}")
+        assert abs(E[k] - r["E"]) < E_TOL_MIXED
+        assert np.abs(F[k] + g).max() < F_TOL_MIXED
+
+
+def test_mixed_matches_fp64_path_on_bead_batch(eng, beadscf):
+    """(H2O)8, 6-31G*, 4 beads: mixed against the FP64 GPU path bead by bead
+    (the FP64 path itself is held to the oracle by the parity tests)."""
+    w = inputs.workload("w8_beads", n_beads=4)
+    _setup(eng, w["basis"], w["instances"])
+    E64, _, st64 = eng.run_scf(e_tol=1e-9, comm_tol=1e-7)
+    F64 = eng.forces()
+    Em, _, stm = eng.run_scf(e_tol=1e-9, comm_tol=1e-7, precision=beadscf.BSCF_MIXED)
+    Fm = eng.forces()
+    assert (st64 == 0).all() and (stm == 0).all()
+    dE = np.abs(Em - E64)
+    dF = np.array([np.abs(a - b).max() for a, b in zip(Fm, F64)])
+    print(json.dumps({"max_dE": float(dE.max()), "max_dF": float(dF.max())}))
+    assert dE.max() < E_TOL_MIXED
+    assert dF.max() < F_TOL_MIXED
+
+
+def test_split_extremes(eng, beadscf):
+    """A split below every Schwarz product puts everything in FP64 and
+    reproduces the FP64 path; a split above all of them puts every lane-kernel
+    quartet in FP32."""
+    z, x = inputs.water_cluster(2, 5)
+    _setup(eng, "6-31g*", [(z, x)])
+    E64, _, _ = eng.run_scf(e_tol=1e-10, comm_tol=1e-8)
+    eng.reset_stats()
+    Eall64, _, _ = eng.run_scf(e_tol=1e-10, comm_tol=1e-8, precision=beadscf.BSCF_MIXED,
+                               fp32_split_tol=1e-300)
+    assert _fp32_fraction(eng.stats()) == 0.0
+    assert abs(Eall64[0] - E64[0]) < 1e-10
+    eng.reset_stats()
+    Eall32, _, st = eng.run_scf(e_tol=1e-10, comm_tol=1e-8, precision=beadscf.BSCF_MIXED,
+                                fp32_split_tol=1e300)
+    assert st[0] == 0
+    assert _fp32_fraction(eng.stats()) > 0.5
+    assert abs(Eall32[0] - E64[0]) < 1e-4
+    with pytest.raises(beadscf.BscfError):
+        eng.run_scf(precision=beadscf.BSCF_MIXED, fp32_split_tol=0.0)
