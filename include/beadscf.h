@@ -164,11 +164,49 @@ bscf_status bscf_boys(bscf_ctx* ctx, int m_max, int n, const double* T, double* 
 /* Host-side Boys table entry F_m(0.1 k) used to build the device table. */
 double bscf_boys_table_entry(int m, int k);
 
-/* Learned SCF guess (Section 2's orbital reuse extended by an in-run trained
- * network): train on the converged densities collected so far, save, load. */
+/* Learned SCF guess.  The paper reuses each replica's previous-step orbitals
+ * as the next step's starting point (Section 2); the learned guess corrects
+ * that previous-step density with a network over atom pairs (inputs: the
+ * pair's element types, geometry and displacement, its block of the
+ * previous-step guess and of the previous step's residual; output: the
+ * residual block, converged minus previous-step density), trained in-run.
+ * Every converged SCF that started from the previous-step or learned guess
+ * records its residual rows; run_scf with BSCF_GUESS_LEARNED applies the
+ * network once it has been trained, and otherwise (no model, no previous
+ * step, or a non-finite or oversized prediction) keeps the previous-step
+ * guess and sets BSCF_FALLBACK_USED.  The converged result does not depend on
+ * the guess beyond the SCF tolerance.
+ *
+ * Network: din -> 256 -> 256 -> dout, ReLU, FP32, plus a residual connection
+ * (the last dout inputs are added to the output; dout <= din); loss = masked
+ * mean squared error; Adam (beta 0.9 / 0.999, eps 1e-8).  Flat parameter
+ * order: W1 (din x 256, row-major), b1, W2 (256 x 256), b2, W3 (256 x dout),
+ * b3. */
+
+/* n_adam_steps full-batch Adam steps (learning rate 1e-3) on the last four
+ * recorded steps; *loss = loss before the last step (negative: no data). */
 bscf_status bscf_guess_train(bscf_ctx* ctx, int n_adam_steps, float* loss);
+/* Model, residual scale and Adam state to / from a binary file. */
 bscf_status bscf_guess_save(bscf_ctx* ctx, const char* path);
 bscf_status bscf_guess_load(bscf_ctx* ctx, const char* path);
+/* Fix the network to din inputs and dout outputs with seeded initial weights
+ * (in-run use sizes it from the batch by itself). */
+bscf_status bscf_guess_configure(bscf_ctx* ctx, int din, int dout, unsigned seed);
+/* Current input and output widths and parameter count (0 when unconfigured). */
+bscf_status bscf_guess_param_count(bscf_ctx* ctx, int* din, int* dout, long* n);
+/* Copy the flat parameter vector in / out (host, n floats); setting resets
+ * the Adam moments.  BSCF_E_INVALID if n differs from the parameter count. */
+bscf_status bscf_guess_set_params(bscf_ctx* ctx, const float* params, long n);
+bscf_status bscf_guess_get_params(bscf_ctx* ctx, float* params, long n);
+/* Evaluate the network on rows x din host inputs X into Y (rows x dout, may
+ * be NULL); with targets T and mask (rows x dout, both or neither) also the
+ * loss and the flat gradient (grad: parameter count floats, may be NULL). */
+bscf_status bscf_guess_eval(bscf_ctx* ctx, int rows, const float* X, const float* T,
+                            const float* mask, float* Y, float* grad, float* loss);
+/* steps full-batch Adam steps with learning rate lr on the given rows, from
+ * the current moments; *loss = loss before the last step. */
+bscf_status bscf_guess_fit(bscf_ctx* ctx, int rows, const float* X, const float* T,
+                           const float* mask, int steps, float lr, float* loss);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* bscf_last_error(void);

@@ -62,6 +62,12 @@ _SIGS = {
     "bscf_guess_train": [_vp, _i, _vp],
     "bscf_guess_save": [_vp, ctypes.c_char_p],
     "bscf_guess_load": [_vp, ctypes.c_char_p],
+    "bscf_guess_configure": [_vp, _i, _i, ctypes.c_uint],
+    "bscf_guess_param_count": [_vp, _vp, _vp, _vp],
+    "bscf_guess_set_params": [_vp, _vp, ctypes.c_long],
+    "bscf_guess_get_params": [_vp, _vp, ctypes.c_long],
+    "bscf_guess_eval": [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp],
+    "bscf_guess_fit": [_vp, _i, _vp, _vp, _vp, _i, ctypes.c_float, _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -247,3 +253,47 @@ class Engine:
 
     def guess_load(self, path):
         _chk(_lib.bscf_guess_load(self._h, path.encode()))
+
+    def guess_configure(self, din, dout, seed=2000):
+        _chk(_lib.bscf_guess_configure(self._h, din, dout, seed))
+
+    def guess_dims(self):
+        di, do, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_long()
+        _chk(_lib.bscf_guess_param_count(self._h, ctypes.byref(di), ctypes.byref(do), ctypes.byref(n)))
+        return di.value, do.value, n.value
+
+    def guess_params(self):
+        n = self.guess_dims()[2]
+        p = np.empty(n, np.float32)
+        _chk(_lib.bscf_guess_get_params(self._h, _ptr(p), n))
+        return p
+
+    def guess_set_params(self, p):
+        p = np.ascontiguousarray(np.asarray(p, np.float32))
+        _chk(_lib.bscf_guess_set_params(self._h, _ptr(p), p.size))
+
+    def guess_eval(self, X, T=None, mask=None):
+        """(Y, gradient, loss) of the network on host rows; gradient and loss
+        are None without targets."""
+        X = np.ascontiguousarray(np.asarray(X, np.float32))
+        _, dout, n = self.guess_dims()
+        Y = np.empty((X.shape[0], dout), np.float32)
+        if T is None:
+            _chk(_lib.bscf_guess_eval(self._h, X.shape[0], _ptr(X), None, None, _ptr(Y), None, None))
+            return Y, None, None
+        T = np.ascontiguousarray(np.asarray(T, np.float32))
+        M = np.ascontiguousarray(np.asarray(mask, np.float32))
+        g = np.empty(n, np.float32)
+        l = ctypes.c_float()
+        _chk(_lib.bscf_guess_eval(self._h, X.shape[0], _ptr(X), _ptr(T), _ptr(M), _ptr(Y), _ptr(g),
+                                  ctypes.byref(l)))
+        return Y, g, l.value
+
+    def guess_fit(self, X, T, mask, steps, lr=1e-3):
+        X = np.ascontiguousarray(np.asarray(X, np.float32))
+        T = np.ascontiguousarray(np.asarray(T, np.float32))
+        M = np.ascontiguousarray(np.asarray(mask, np.float32))
+        l = ctypes.c_float()
+        _chk(_lib.bscf_guess_fit(self._h, X.shape[0], _ptr(X), _ptr(T), _ptr(M), steps, lr,
+                                 ctypes.byref(l)))
+        return l.value

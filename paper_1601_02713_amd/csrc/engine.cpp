@@ -280,6 +280,7 @@ struct bscf_ctx {
   int nprim_pairs = 0;
   std::vector<std::vector<int>> pairs_by_class;  // global pair ids per pair class
   std::vector<double> xyz;
+  std::vector<int> atom_bf0, atom_nbf;   // per global atom: first basis function, count
   bool have_geom = false, have_scf = false;
   std::vector<double> Q;           // per pair
   double work_tau = -1.0, work_split = -1.0;
@@ -483,6 +484,8 @@ void build_shell_topology(bscf_ctx* c) {
   c->nshell.assign(c->ninst, 0);
   c->shell_off.assign(c->ninst, 0);
   c->pairs_by_class.assign(kNumPairClasses, {});
+  c->atom_bf0.assign(c->total_atoms, 0);
+  c->atom_nbf.assign(c->total_atoms, 0);
   for (int i = 0; i < c->ninst; ++i) {
     c->shell_off[i] = (int)c->shells.size();
     int bf = 0;
@@ -500,6 +503,8 @@ void build_shell_topology(bscf_ctx* c) {
           c->sh_exp.push_back(bs.exps[k]);
           c->sh_coef.push_back(bs.coefs[k]);
         }
+        if (c->atom_nbf[s.atom] == 0) c->atom_bf0[s.atom] = bf;
+        c->atom_nbf[s.atom] += ncart(bs.l);
         bf += ncart(bs.l);
         c->shells.push_back(s);
       }
@@ -1396,6 +1401,24 @@ void previous_guess(bscf_ctx* c) {
   }
 }
 
+mlp::Batch guess_batch(bscf_ctx* c) {
+  mlp::Batch b;
+  b.ninst = c->ninst;
+  b.moff = c->moff.data();
+  b.nbf = c->nbf.data();
+  b.natoms = c->natoms.data();
+  b.atom_off = c->atom_off.data();
+  b.Z = c->Zs.data();
+  b.xyz = c->xyz.data();
+  b.atom_bf0 = c->atom_bf0.data();
+  b.atom_nbf = c->atom_nbf.data();
+  b.total_atoms = c->total_atoms;
+  b.mtot = (size_t)c->mtot;
+  b.P = c->P.p;
+  b.stream = c->stream;
+  return b;
+}
+
 __global__ void commit_C_kernel(BatchInfo b, const double* src, double* dst) {
   const int inst = blockIdx.y;
   if (!b.active[inst]) return;
@@ -1427,21 +1450,26 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     // guess
     int guess = o.guess;
     std::vector<int> fallback(ni, 0);
-    if (guess == BSCF_GUESS_PREVIOUS && !c->have_C) guess = BSCF_GUESS_CORE;
-    if (guess == BSCF_GUESS_LEARNED) {
-      if (!c->have_C || !c->guess.predict(c)) {
-        guess = c->have_C ? BSCF_GUESS_PREVIOUS : BSCF_GUESS_CORE;
-        std::fill(fallback.begin(), fallback.end(), 4);
-      }
+    const mlp::Batch gb = guess_batch(c);
+    // the learned guess corrects the previous-step guess; without previous
+    // orbitals both fall back to the core guess
+    if ((guess == BSCF_GUESS_PREVIOUS || guess == BSCF_GUESS_LEARNED) && !c->have_C) {
+      if (guess == BSCF_GUESS_LEARNED) std::fill(fallback.begin(), fallback.end(), BSCF_FALLBACK_USED);
+      guess = BSCF_GUESS_CORE;
     }
     if (guess == BSCF_GUESS_CORE) {
       c->d_active.upload(flags, st);
       density_from_fock(c, c->H.p, c->P.p);
       commit_C_kernel<<<dim3(1024, ni), 256, 0, st>>>(c->batch(true), c->C.p, c->Cacc.p);
-    } else if (guess == BSCF_GUESS_PREVIOUS) {
+      c->guess.begin_step(gb, false);
+    } else if (guess == BSCF_GUESS_PREVIOUS || guess == BSCF_GUESS_LEARNED) {
       previous_guess(c);
+      c->guess.begin_step(gb, true);
+      if (guess == BSCF_GUESS_LEARNED && !c->guess.predict(gb))
+        std::fill(fallback.begin(), fallback.end(), BSCF_FALLBACK_USED);
+    } else {
+      c->guess.begin_step(gb, false);   // BSCF_GUESS_USER: P already set
     }
-    // (BSCF_GUESS_USER: P already set; LEARNED: P written by predict)
     c->d_active.upload(flags, st);
     c->d_status.upload(stat, st);
     std::vector<int> zeros(ni, 0);
@@ -1506,7 +1534,7 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     c->last_iters = iters;
     c->have_C = true;
     c->have_scf = true;
-    c->guess.record(c);
+    c->guess.record(guess_batch(c));
     c->t_scf_ms += now_ms() - t0;
   });
 }
@@ -1838,7 +1866,66 @@ bscf_status bscf_boys(bscf_ctx* c, int m_max, int n, const double* T, double* ou
 bscf_status bscf_guess_train(bscf_ctx* c, int n_adam_steps, float* loss) {
   return guard([&] {
     need(c != nullptr, BSCF_E_INVALID, "NULL context");
-    float l = c->guess.train(c, n_adam_steps);
+    need(n_adam_steps >= 0, BSCF_E_INVALID, "negative step count");
+    HIPCHK(hipSetDevice(c->device));
+    const float l = c->guess.train(n_adam_steps, c->stream);
+    if (loss) *loss = l;
+  });
+}
+
+bscf_status bscf_guess_configure(bscf_ctx* c, int din, int dout, unsigned seed) {
+  return guard([&] {
+    need(c != nullptr && din > 0 && dout > 0, BSCF_E_INVALID, "bad arguments");
+    HIPCHK(hipSetDevice(c->device));
+    c->guess.configure(din, dout, seed);
+  });
+}
+
+bscf_status bscf_guess_param_count(bscf_ctx* c, int* din, int* dout, long* n) {
+  return guard([&] {
+    need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    if (din) *din = c->guess.din();
+    if (dout) *dout = c->guess.dout();
+    if (n) *n = c->guess.din() ? c->guess.nparams() : 0;
+  });
+}
+
+bscf_status bscf_guess_set_params(bscf_ctx* c, const float* params, long n) {
+  return guard([&] {
+    need(c && params, BSCF_E_INVALID, "NULL argument");
+    need(c->guess.din() > 0, BSCF_E_STATE, "network not configured");
+    HIPCHK(hipSetDevice(c->device));
+    c->guess.set_params(params, n, c->stream);
+  });
+}
+
+bscf_status bscf_guess_get_params(bscf_ctx* c, float* params, long n) {
+  return guard([&] {
+    need(c && params, BSCF_E_INVALID, "NULL argument");
+    need(c->guess.din() > 0, BSCF_E_STATE, "network not configured");
+    HIPCHK(hipSetDevice(c->device));
+    c->guess.get_params(params, n, c->stream);
+  });
+}
+
+bscf_status bscf_guess_eval(bscf_ctx* c, int rows, const float* X, const float* T, const float* mask,
+                            float* Y, float* grad, float* loss) {
+  return guard([&] {
+    need(c && X && rows > 0, BSCF_E_INVALID, "bad arguments");
+    need((T == nullptr) == (mask == nullptr), BSCF_E_INVALID, "targets and mask go together");
+    need(c->guess.din() > 0, BSCF_E_STATE, "network not configured");
+    HIPCHK(hipSetDevice(c->device));
+    c->guess.eval_rows(rows, X, T, mask, Y, grad, loss, c->stream);
+  });
+}
+
+bscf_status bscf_guess_fit(bscf_ctx* c, int rows, const float* X, const float* T, const float* mask,
+                           int steps, float lr, float* loss) {
+  return guard([&] {
+    need(c && X && T && mask && rows > 0 && steps > 0 && lr > 0.f, BSCF_E_INVALID, "bad arguments");
+    need(c->guess.din() > 0, BSCF_E_STATE, "network not configured");
+    HIPCHK(hipSetDevice(c->device));
+    const float l = c->guess.fit_rows(rows, X, T, mask, steps, lr, c->stream);
     if (loss) *loss = l;
   });
 }
