@@ -56,6 +56,63 @@ def cpu_baseline(w, seconds: float):
                        f"{w['label']} beads, {t_total:.1f} s on the host")
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter profile
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None
+    when there is none or the kernel's sources changed since it was taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "fock_unit_0000_w8_16beads_hbm.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for src in rec["source_files"]:
+        with open(os.path.join(here, src), "rb") as f:
+            h.update(f.read())
+    return rec["hbm_bytes_per_dispatch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
+def guess_study(w, n_steps, dt_fs=0.25, temperature=300.0):
+    """Ring-polymer MD on the workload's beads: the previous-step guess run
+    integrates n_steps; the learned-guess run replays the same geometries,
+    trains after every step from step 1 and predicts from step 3."""
+    import numpy as np
+    import inputs
+    from paper_1601_02713_amd import beadscf, md
+    z = w["instances"][0][0]
+    xb = np.array([x for _, x in w["instances"]])
+    v = inputs.maxwell_boltzmann(z, len(xb), temperature, 4)
+    opts = beadscf.default_opts(e_tol=w["e_tol"], comm_tol=w["comm_tol"], max_iter=60)
+    basis = inputs.load_basis(w["basis"])
+    e1, e2 = beadscf.Engine(0), beadscf.Engine(0)
+    try:
+        poly = md.RingPolymer(z, xb.copy(), v, temperature)
+        ref, traj = md.run(e1, poly, n_steps, dt_fs, guess="previous", opts=opts, basis=basis)
+        lrn, _ = md.run(e2, poly, n_steps, dt_fs, guess="learned", opts=opts, geometries=traj,
+                        train_from=1, train_steps=30, predict_from=3, basis=basis)
+    finally:
+        e1.close()
+        e2.close()
+    k0 = 3
+    it_ref = np.array([r.iterations for r in ref[k0:]], float)
+    it_lrn = np.array([r.iterations for r in lrn[k0:]], float)
+    dE = max(float(np.abs(a.energies - b.energies).max()) for a, b in zip(ref, lrn))
+    return {
+        "workload": w["label"], "md_steps": n_steps, "dt_fs": dt_fs, "compared_steps": f"{k0}..{n_steps - 1}",
+        "scf_iterations_per_bead_previous_guess": float(it_ref.mean()),
+        "scf_iterations_per_bead_learned_guess": float(it_lrn.mean()),
+        "ms_per_step_previous_guess": float(np.mean([r.scf_ms + r.force_ms for r in ref[k0:]])),
+        "ms_per_step_learned_guess_excl_training": float(np.mean([r.scf_ms + r.force_ms for r in lrn[k0:]])),
+        "training_ms_per_step": float(np.mean([r.train_ms for r in lrn[k0:]])),
+        "fallbacks": int(sum(int(((r.status & beadscf.STATUS_FALLBACK) != 0).sum()) for r in lrn[k0:])),
+        "max_abs_dE_learned_vs_previous_Eh": dE,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,7 +124,20 @@ def main():
                     help="mixed precision: quartets with Q_ab Q_cd below this run in FP32")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--guess-steps", type=int, default=8,
+                    help="MD steps of the learned-guess study (0 skips it)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES between two device buffers (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "layout is a design note, not part of this build", file=sys.stderr)
@@ -122,6 +192,8 @@ def main():
                  for k, v in cls.items() if v["launches"]}
     d = cls[dom]
     ach = d["done_flops"] / (d["kernel_ms"] * 1e-3) / 1e12 if d["kernel_ms"] > 0 else 0.0
+    dom_kernel = (f"fock_unit_kernel<Cls{dom}, double>" if per_class[dom]["kernel"] == "lane"
+                  else f"coop_fock_kernel<CoopE{dom}>")
     n_inst = len(xs)
     out = {
         "metric": "screened shell-quartets/s",
@@ -150,10 +222,10 @@ def main():
         "phase_ms_per_step": {k: st_json[k] / args.steps for k in
                               ("t_setup_ms", "t_scf_ms", "t_grad_ms", "t_fock_ms", "t_work_ms")},
         "roofline": {"bound": "alu",
-                     "kernel": (f"fock_unit_kernel<Cls{dom}, double>" if per_class[dom]["kernel"] == "lane"
-                                else f"coop_fock_kernel<CoopE{dom}>"),
+                     "kernel": dom_kernel,
                      "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+                     "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "traffic": measured_traffic(dom_kernel),
+                     "traffic_unit": "bytes per launch",
                      "launches": d["launches"],
                      "avg_launch_ms": d["kernel_ms"] / max(d["launches"], 1)},
         "energies_first_bead": float(E[0]),
@@ -174,6 +246,9 @@ def main():
             "max_abs_dE_vs_fp64_Eh": float(dE.max()), "max_abs_dF_vs_fp64_Eh_per_bohr": float(dF.max()),
             "per_bead_abs_dE_Eh": [float(v) for v in dE],
             "per_bead_max_abs_dF_Eh_per_bohr": [float(v) for v in dF]}
+    if args.guess_steps > 0:
+        eng.close()
+        out["learned_guess"] = guess_study(w, args.guess_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -26,20 +26,25 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // is B (K x N, ldb) or, with TB, the transpose of B stored N x K.  A block of
 // four wavefronts computes a 64 x 64 tile from 16-deep LDS stages; each
 // wavefront owns 32 x 32 as 2 x 2 MFMA 16x16x4 (FP32) tiles.
+// With gridDim.z > 1 the K range is split into chunks of kchunk (a multiple
+// of 16) and every block adds its partial tile to C with atomics (C zeroed
+// beforehand, no bias or ReLU).
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(int M, int N, int K, const float* __restrict__ A,
                                                        int lda, const float* __restrict__ B, int ldb,
                                                        float* __restrict__ C, int ldc,
-                                                       const float* __restrict__ bias, int relu) {
+                                                       const float* __restrict__ bias, int relu,
+                                                       int kchunk) {
   __shared__ float As[16][64 + 4];
   __shared__ float Bs[16][64 + 4];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
   v4f acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
     for (int e = tid; e < 1024; e += 256) {
       int mm, kk;
       if (TA) {
@@ -51,7 +56,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(int M, int N, int K, cons
       }
       const int gm = m0 + mm, gk = k0 + kk;
       float x = 0.f;
-      if (gm < M && gk < K) x = TA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk];
+      if (gm < M && gk < kend) x = TA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk];
       As[kk][mm] = x;
     }
     for (int e = tid; e < 1024; e += 256) {
@@ -65,7 +70,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(int M, int N, int K, cons
       }
       const int gn = n0 + nn, gk = k0 + kk;
       float x = 0.f;
-      if (gn < N && gk < K) x = TB ? B[(long)gn * ldb + gk] : B[(long)gk * ldb + gn];
+      if (gn < N && gk < kend) x = TB ? B[(long)gn * ldb + gk] : B[(long)gk * ldb + gn];
       Bs[kk][nn] = x;
     }
     __syncthreads();
@@ -95,24 +100,44 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(int M, int N, int K, cons
         const int gn = n0 + wn + 16 * j + (lane & 15);
         if (gm < M && gn < N) {
           float x = acc[i][j][r];
-          if (bias) x += bias[gn];
-          if (relu) x = fmaxf(x, 0.f);
-          C[(long)gm * ldc + gn] = x;
+          if (gridDim.z > 1) {
+            atomicAdd(&C[(long)gm * ldc + gn], x);
+          } else {
+            if (bias) x += bias[gn];
+            if (relu) x = fmaxf(x, 0.f);
+            C[(long)gm * ldc + gn] = x;
+          }
         }
       }
 }
 
 void gemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb,
           float* C, int ldc, const float* bias, bool relu, hipStream_t s) {
-  const dim3 g((N + 63) / 64, (M + 63) / 64), b(256);
+  const int tiles = ((N + 63) / 64) * ((M + 63) / 64);
+  // few output tiles over a long reduction (weight gradients): split K so
+  // that about 512 blocks share it
+  int split = 1, kchunk = K;
+  if (!bias && !relu && tiles < 256 && K >= 1024) {
+    split = std::min((512 + tiles - 1) / tiles, K / 256);
+    kchunk = ((K + split - 1) / split + 15) / 16 * 16;
+    split = (K + kchunk - 1) / kchunk;
+    if (ldc == N) {
+      chk(hipMemsetAsync(C, 0, sizeof(float) * (size_t)M * N, s), "gemm zero");
+    } else {
+      for (int r = 0; r < M; ++r)
+        chk(hipMemsetAsync(C + (long)r * ldc, 0, sizeof(float) * N, s), "gemm zero");
+    }
+  }
+  const dim3 g((N + 63) / 64, (M + 63) / 64, split), b(256);
+  const int rl = relu ? 1 : 0;
   if (!ta && !tb)
-    hipLaunchKernelGGL((gemm_f32_kernel<false, false>), g, b, 0, s, M, N, K, A, lda, B, ldb, C, ldc, bias, relu ? 1 : 0);
+    hipLaunchKernelGGL((gemm_f32_kernel<false, false>), g, b, 0, s, M, N, K, A, lda, B, ldb, C, ldc, bias, rl, kchunk);
   else if (ta && !tb)
-    hipLaunchKernelGGL((gemm_f32_kernel<true, false>), g, b, 0, s, M, N, K, A, lda, B, ldb, C, ldc, bias, relu ? 1 : 0);
+    hipLaunchKernelGGL((gemm_f32_kernel<true, false>), g, b, 0, s, M, N, K, A, lda, B, ldb, C, ldc, bias, rl, kchunk);
   else if (!ta && tb)
-    hipLaunchKernelGGL((gemm_f32_kernel<false, true>), g, b, 0, s, M, N, K, A, lda, B, ldb, C, ldc, bias, relu ? 1 : 0);
+    hipLaunchKernelGGL((gemm_f32_kernel<false, true>), g, b, 0, s, M, N, K, A, lda, B, ldb, C, ldc, bias, rl, kchunk);
   else
-    hipLaunchKernelGGL((gemm_f32_kernel<true, true>), g, b, 0, s, M, N, K, A, lda, B, ldb, C, ldc, bias, relu ? 1 : 0);
+    hipLaunchKernelGGL((gemm_f32_kernel<true, true>), g, b, 0, s, M, N, K, A, lda, B, ldb, C, ldc, bias, rl, kchunk);
 }
 
 // dY = 2 M (Y - T) / cnt; acc += sum M (Y - T)^2
@@ -147,13 +172,22 @@ __global__ void relu_back_kernel(long n, const float* H, float* dH) {
     if (!(H[k] > 0.f)) dH[k] = 0.f;
 }
 
-// out[j] = sum_i A[i][j] (rows x cols, row-major)
+// out[j] += sum_i A[i][j] over the rows of this block's chunk (rows x cols,
+// row-major; out zeroed beforehand)
+constexpr int kColChunk = 256;
 __global__ void colsum_kernel(int rows, int cols, const float* A, float* out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= cols) return;
+  const int i0 = blockIdx.y * kColChunk, i1 = min(rows, i0 + kColChunk);
   float s = 0.f;
-  for (int i = 0; i < rows; ++i) s += A[(long)i * cols + j];
-  out[j] = s;
+  for (int i = i0; i < i1; ++i) s += A[(long)i * cols + j];
+  atomicAdd(&out[j], s);
+}
+
+void colsum(int rows, int cols, const float* A, float* out, hipStream_t s) {
+  chk(hipMemsetAsync(out, 0, sizeof(float) * cols, s), "colsum zero");
+  hipLaunchKernelGGL(colsum_kernel, dim3((cols + 255) / 256, (rows + kColChunk - 1) / kColChunk),
+                     dim3(256), 0, s, rows, cols, A, out);
 }
 
 __global__ void adam_kernel(long n, float* th, const float* g, float* m, float* v, float lr, float b1,
@@ -377,15 +411,15 @@ float Guess::backward(int rows, const float* X, const float* T, const float* M, 
   hipLaunchKernelGGL(loss_grad_kernel, grid1d(ny), dim3(256), 0, s, ny, y_.p, T, M,
                      (float)(1.0 / cnt), dy_.p, lossacc_.p);
   gemm(true, false, kHidden, dout_, rows, h2_.p, kHidden, dy_.p, dout_, gW3, dout_, nullptr, false, s);
-  hipLaunchKernelGGL(colsum_kernel, dim3((dout_ + 255) / 256), dim3(256), 0, s, rows, dout_, dy_.p, gb3);
+  colsum(rows, dout_, dy_.p, gb3, s);
   gemm(false, true, rows, kHidden, dout_, dy_.p, dout_, W3, dout_, dh2_.p, kHidden, nullptr, false, s);
   hipLaunchKernelGGL(relu_back_kernel, grid1d(nh), dim3(256), 0, s, nh, h2_.p, dh2_.p);
   gemm(true, false, kHidden, kHidden, rows, h1_.p, kHidden, dh2_.p, kHidden, gW2, kHidden, nullptr, false, s);
-  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, rows, kHidden, dh2_.p, gb2);
+  colsum(rows, kHidden, dh2_.p, gb2, s);
   gemm(false, true, rows, kHidden, kHidden, dh2_.p, kHidden, W2, kHidden, dh1_.p, kHidden, nullptr, false, s);
   hipLaunchKernelGGL(relu_back_kernel, grid1d(nh), dim3(256), 0, s, nh, h1_.p, dh1_.p);
   gemm(true, false, din_, kHidden, rows, X, din_, dh1_.p, kHidden, gW1, kHidden, nullptr, false, s);
-  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, rows, kHidden, dh1_.p, gb1);
+  colsum(rows, kHidden, dh1_.p, gb1, s);
   chk(hipGetLastError(), "backward launch");
   double l = 0.0;
   chk(hipMemcpyAsync(&l, lossacc_.p, sizeof(double), hipMemcpyDeviceToHost, s), "loss");

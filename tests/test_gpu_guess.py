@@ -50,9 +50,10 @@ def _theta(rng, din, dout):
     return mlp.flatten([W1, b1, W2, b2, W3, b3]).astype(np.float32)
 
 
-@pytest.mark.parametrize("rows,din,dout", [(150, 37, 9), (64, 64, 64), (1, 70, 5)])
+@pytest.mark.parametrize("rows,din,dout", [(150, 37, 9), (64, 64, 64), (1, 70, 5), (3000, 40, 12)])
 def test_network_forward_and_gradient_against_oracle(eng, rows, din, dout):
-    """Ragged and exact tile shapes: outputs, loss and every parameter
+    """Ragged and exact tile shapes, and a long reduction (weight gradients
+    over 3000 rows take the split-K path): outputs, loss and every parameter
     gradient within 1e-4 of the FP64 oracle (relative to each block's size)."""
     rng = np.random.default_rng([2000, rows, din])
     eng.guess_configure(din, dout)
