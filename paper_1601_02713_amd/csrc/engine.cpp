@@ -317,6 +317,13 @@ struct bscf_ctx {
   DevBuf<int> d_kets;
   // ket-list-position buffers: P gathered per ket pair and ket-side J
   DevBuf<double> d_Pk, d_Jk;
+  // ket primitive pairs copied into ket-list order: within a block of
+  // positions sharing a primitive count, primitive j of every position is
+  // adjacent to that of the next position (coalesced lane loads)
+  DevBuf<PrimPair> d_kprims;
+  DevBuf<int> d_kmap;          // source primitive pair of each kprims record
+  DevBuf<int2> d_kpos;         // per position: first record, stride
+  int max_prims = 1;
   int max_ncd = 0;
   size_t max_lds_bytes = 65536;
 
@@ -571,6 +578,27 @@ void build_work(bscf_ctx* c, double tau, double split) {
         }
       }
     }
+  {
+    std::vector<int2> kpos(c->kets.size());
+    std::vector<int> kmap;
+    c->max_prims = 1;
+    for (int i = 0; i < c->ninst; ++i)
+      for (int pc = 0; pc < NPC; ++pc)
+        for (const Sub& sb : subs[i][pc]) {
+          const int ns = (int)sb.ids.size(), kp0 = (int)kmap.size();
+          kmap.resize(kp0 + (size_t)ns * sb.nprim);
+          for (int r = 0; r < ns; ++r) {
+            const ShellPair& pr = c->pairs[sb.ids[r]];
+            kpos[sb.ket_off + r] = make_int2(kp0 + r, ns);
+            for (int j = 0; j < pr.nprim; ++j) kmap[kp0 + (size_t)j * ns + r] = pr.prim0 + j;
+          }
+          c->max_prims = std::max(c->max_prims, sb.nprim);
+        }
+    c->d_kpos.upload(kpos, c->stream);
+    c->d_kmap.upload(kmap, c->stream);
+    c->d_kprims.resize(kmap.size());
+    launch_gather_prims((int)kmap.size(), c->d_kmap.p, c->d_prims.p, c->d_kprims.p, c->stream);
+  }
   const QuartetClass* qc = quartet_classes();
   // classes are independent: build their lists on host threads
   auto build_class = [&](int q) {
@@ -702,8 +730,8 @@ void build_work(bscf_ctx* c, double tau, double split) {
       W.ul[k].units.resize(ut.size());
       for (size_t j = 0; j < ut.size(); ++j) W.ul[k].units[j] = ut[j].w;
     }
-    W.lds_ok = sizeof(double) * (size_t)unit_lds_doubles(qc[q].la, qc[q].lb, c->max_n) <=
-               c->max_lds_bytes;
+    W.lds_ok = sizeof(double) * (size_t)unit_lds_doubles(qc[q].la, qc[q].lb, c->max_n,
+                                                          c->max_prims) <= c->max_lds_bytes;
   };
   {
     std::atomic<int> next{0};
@@ -796,6 +824,9 @@ FockArgs fock_args(bscf_ctx* c, double* J, double* K, const int* active) {
   a.prims = c->d_prims.p;
   a.shells = c->d_shells.p;
   a.kets = c->d_kets.p;
+  a.kprims = c->d_kprims.p;
+  a.kpos = c->d_kpos.p;
+  a.max_prims = c->max_prims;
   a.moff = c->d_moff.p;
   a.nbf = c->d_nbf.p;
   a.nmax = c->max_n;
@@ -1591,6 +1622,9 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
     ga.prims = c->d_prims.p;
     ga.shells = c->d_shells.p;
     ga.kets = c->d_kets.p;
+    ga.kprims = c->d_kprims.p;
+    ga.kpos = c->d_kpos.p;
+    ga.max_prims = c->max_prims;
     ga.moff = c->d_moff.p;
     ga.nbf = c->d_nbf.p;
     ga.atom_off = c->d_atom_off.p;
@@ -1622,7 +1656,8 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
       for (int q = 0; q < kNumQuartetClasses; ++q) {
         auto& W = c->work[q];
         const bool lds_ok = sizeof(double) * (size_t)grad_unit_lds_doubles(
-                                qc[q].la, qc[q].lb, c->max_n, c->max_atoms) <= c->max_lds_bytes;
+                                qc[q].la, qc[q].lb, c->max_n, c->max_atoms, c->max_prims) <=
+                            c->max_lds_bytes;
         if (!qc[q].grad || !lds_ok || c->private_bytes[q][2] > kMaxLaneScratch) {
           c->grad_variant[q] = 1;
           continue;

@@ -42,6 +42,9 @@ struct FockArgs {
   const PrimPair* prims;
   const Shell* shells;
   const int* kets;
+  const PrimPair* kprims;  // ket primitive pairs in ket-list order (see kpos)
+  const int2* kpos;        // per ket position: first record in kprims, stride between primitives
+  int max_prims;           // largest primitive count of a shell pair
   const long long* moff;   // matrix offset per instance
   const int* nbf;          // basis size per instance
   int nmax;                // largest basis size (row length of the LDS accumulators)
@@ -82,7 +85,7 @@ struct TensorArgs {        // full ERI tensor of one instance (test path)
 // kernels of the class (bounded code size and compile time).
 template <class CL, typename R>
 __device__ __forceinline__ void eri_block_body(const PrimPair* __restrict__ bp, int nb,
-                                          const PrimPair* __restrict__ kp, int nk,
+                                          const PrimPair* __restrict__ kp, int nk, int ks,
                                           const double AB[3], const double CD[3],
                                           const double* __restrict__ tab64,
                                           const float* __restrict__ tab32, R* out) {
@@ -93,7 +96,7 @@ __device__ __forceinline__ void eri_block_body(const PrimPair* __restrict__ bp, 
   // ket primitives (one set per lane) outermost: each is loaded once; the
   // bra primitives are shared by the lanes of a wavefront and stay cached
   for (int j = 0; j < nk; ++j) {
-    const PrimPair Q = kp[j];
+    const PrimPair Q = kp[j * ks];
     for (int i = 0; i < nb; ++i) {
       const PrimPair B = bp[i];
       const double pq = B.p + Q.p;
@@ -125,23 +128,24 @@ __device__ __forceinline__ void eri_block_body(const PrimPair* __restrict__ bp, 
 
 template <class CL, typename R>
 __device__ __noinline__ void eri_block_outline(const PrimPair* __restrict__ bp, int nb,
-                                               const PrimPair* __restrict__ kp, int nk,
+                                               const PrimPair* __restrict__ kp, int nk, int ks,
                                                const double* AB, const double* CD,
                                                const double* __restrict__ tab64,
                                                const float* __restrict__ tab32, R* out) {
-  eri_block_body<CL, R>(bp, nb, kp, nk, AB, CD, tab64, tab32, out);
+  eri_block_body<CL, R>(bp, nb, kp, nk, ks, AB, CD, tab64, tab32, out);
 }
 
+// ket primitive j of the quartet is kp[j * ks]
 template <class CL, typename R>
 __device__ __forceinline__ void eri_block(const PrimPair* __restrict__ bp, int nb,
-                                          const PrimPair* __restrict__ kp, int nk,
+                                          const PrimPair* __restrict__ kp, int nk, int ks,
                                           const double AB[3], const double CD[3],
                                           const double* __restrict__ tab64,
                                           const float* __restrict__ tab32, R* out) {
   if constexpr (CL::LA + CL::LB + CL::LC + CL::LD >= 6) {
-    eri_block_outline<CL, R>(bp, nb, kp, nk, AB, CD, tab64, tab32, out);
+    eri_block_outline<CL, R>(bp, nb, kp, nk, ks, AB, CD, tab64, tab32, out);
   } else {
-    eri_block_body<CL, R>(bp, nb, kp, nk, AB, CD, tab64, tab32, out);
+    eri_block_body<CL, R>(bp, nb, kp, nk, ks, AB, CD, tab64, tab32, out);
   }
 }
 
@@ -153,9 +157,10 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 // LDS footprint of the unit kernel of a class: K accumulators and P rows of the
-// bra shells, (NA + NB) rows of nmax doubles each.
-__host__ __device__ constexpr int unit_lds_doubles(int la, int lb, int nmax) {
-  return 2 * (ncart(la) + ncart(lb)) * nmax;
+// bra shells, (NA + NB) rows of nmax doubles each, and the bra's primitive
+// pairs (at most max_prims records of 12 doubles).
+__host__ __device__ constexpr int unit_lds_doubles(int la, int lb, int nmax, int max_prims) {
+  return 2 * (ncart(la) + ncart(lb)) * nmax + 12 * max_prims;
 }
 
 template <class CL, typename R>
@@ -175,11 +180,17 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
   const int m0 = sa.bf, n0 = sb.bf;
   double* Kacc = lds;           // row r: K row of bf m0 + r (r < NA) or n0 + r - NA
   double* Prow = lds + NR * n;  // the same rows of P
+  PrimPair* Bp = reinterpret_cast<PrimPair*>(lds + 2 * NR * a.nmax);   // the bra's primitives
   for (int t = lane; t < NR * n; t += kWave) {
     const int r = t / n, col = t - r * n;
     const int bf = r < NA ? m0 + r : n0 + (r - NA);
     Kacc[t] = 0.0;
     Prow[t] = a.P[mo + (long long)bf * n + col];
+  }
+  {
+    const double* src = reinterpret_cast<const double*>(a.prims + bra.prim0);
+    double* dst = reinterpret_cast<double*>(Bp);
+    for (int t = lane; t < 12 * bra.nprim; t += kWave) dst[t] = src[t];
   }
   __syncthreads();
   double Pab[NA][NB], jab[NA][NB];
@@ -206,9 +217,10 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
     const ShellPair ket = a.pairs[kid];
     const Shell sc = a.shells[ket.a], sd = a.shells[ket.b];
     const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
+    const int2 kp = a.kpos[pos];
     R v[CL::NOUT];
-    eri_block<CL, R>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
-                     a.boys64, a.boys32, v);
+    eri_block<CL, R>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64, a.boys32,
+                     v);
     const double g = ((bra.a == bra.b) ? 1.0 : 2.0) * ((ket.a == ket.b) ? 1.0 : 2.0) *
                      ((kid == bid) ? 1.0 : 2.0);
     const double fj = valid ? 0.5 * g : 0.0;
@@ -310,7 +322,7 @@ __global__ __launch_bounds__(256) void schwarz_kernel(SchwarzArgs a) {
   const Shell sa = a.shells[pr.a], sb = a.shells[pr.b];
   const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
   double v[CL::NOUT];
-  eri_block<CL, double>(a.prims + pr.prim0, pr.nprim, a.prims + pr.prim0, pr.nprim, AB, AB,
+  eri_block<CL, double>(a.prims + pr.prim0, pr.nprim, a.prims + pr.prim0, pr.nprim, 1, AB, AB,
                         a.boys64, nullptr, v);
   double m = 0.0;
 #pragma unroll
@@ -332,7 +344,7 @@ __global__ __launch_bounds__(64) void tensor_kernel(TensorArgs a) {
   const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
   const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
   double v[CL::NOUT];
-  eri_block<CL, double>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
+  eri_block<CL, double>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, 1, AB, CD,
                         a.boys64, nullptr, v);
   const long long n = a.n;
   for (int i = 0; i < NA; ++i)

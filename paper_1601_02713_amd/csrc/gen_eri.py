@@ -513,7 +513,7 @@ def main(outdir):
                   '#include "fock_kernel.h"', f'#include "eri_{tag}.h"', "namespace bscf {",
                   f"void launch_fock_{tag}(const FockArgs& a, int fp32, hipStream_t s) {{",
                   "  if (a.nunits == 0) return;",
-                  f"  const size_t lds = sizeof(double) * unit_lds_doubles({la}, {lb}, a.nmax);",
+                  f"  const size_t lds = sizeof(double) * unit_lds_doubles({la}, {lb}, a.nmax, a.max_prims);",
                   f"  if (fp32) hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, float>), dim3(a.nunits), dim3(64), lds, s, a);",
                   f"  else hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, double>), dim3(a.nunits), dim3(64), lds, s, a);",
                   "}",
@@ -577,7 +577,7 @@ def main(outdir):
               '#include "grad_kernel.h"', f'#include "grad_{tag}.h"', "namespace bscf {",
               f"void launch_grad_{tag}(const GradArgs& a, hipStream_t s) {{",
               "  if (a.nunits == 0) return;",
-              f"  const size_t lds = sizeof(double) * grad_unit_lds_doubles({la}, {lb}, a.nmax, a.max_atoms);",
+              f"  const size_t lds = sizeof(double) * grad_unit_lds_doubles({la}, {lb}, a.nmax, a.max_atoms, a.max_prims);",
               f"  hipLaunchKernelGGL((grad_unit_kernel<ClsG{tag}>), dim3(a.nunits), dim3(64), lds, s, a);",
               "}",
               f"int grad_private_bytes_{tag}() {{",

@@ -15,6 +15,9 @@ struct GradArgs {
   const PrimPair* prims;
   const Shell* shells;
   const int* kets;
+  const PrimPair* kprims;  // ket primitive pairs in ket-list order (see FockArgs)
+  const int2* kpos;
+  int max_prims;
   const long long* moff;
   const int* nbf;
   const int* atom_off;     // first global atom of each instance
@@ -27,10 +30,12 @@ struct GradArgs {
   const double* boys64;
 };
 
-// LDS footprint of the gradient unit kernel: P rows of the bra shells and one
-// dE/dR accumulator triple per atom of the instance.
-__host__ __device__ constexpr int grad_unit_lds_doubles(int la, int lb, int nmax, int max_atoms) {
-  return (ncart(la) + ncart(lb)) * nmax + 3 * max_atoms;
+// LDS footprint of the gradient unit kernel: P rows of the bra shells, one
+// dE/dR accumulator triple per atom of the instance and the bra's primitive
+// pairs.
+__host__ __device__ constexpr int grad_unit_lds_doubles(int la, int lb, int nmax, int max_atoms,
+                                                        int max_prims) {
+  return (ncart(la) + ncart(lb)) * nmax + 3 * max_atoms + 12 * max_prims;
 }
 
 using GradLauncher = void (*)(const GradArgs&, hipStream_t);

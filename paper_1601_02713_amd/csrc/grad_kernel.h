@@ -20,7 +20,7 @@ namespace bscf {
 
 template <class CG>
 __device__ __forceinline__ void grad_block_body(const PrimPair* __restrict__ bp, int nb,
-                                                const PrimPair* __restrict__ kp, int nk,
+                                                const PrimPair* __restrict__ kp, int nk, int ks,
                                                 const double* AB, const double* CD,
                                                 const double* __restrict__ tab64,
                                                 const double* __restrict__ G, double* g9) {
@@ -41,7 +41,7 @@ __device__ __forceinline__ void grad_block_body(const PrimPair* __restrict__ bp,
 #pragma unroll
     for (int k = 0; k < CG::NLC; ++k) LC[k] = 0;
     for (int j = 0; j < nk; ++j) {
-      const PrimPair Q = kp[j];
+      const PrimPair Q = kp[j * ks];
       for (int i = 0; i < nb; ++i) {
         const PrimPair B = bp[i];
         const double pq = B.p + Q.p;
@@ -62,7 +62,7 @@ __device__ __forceinline__ void grad_block_body(const PrimPair* __restrict__ bp,
     CG::template con<R>(RA, RB, RC, LA, LB, LC, AB[0], AB[1], AB[2], CD[0], CD[1], CD[2], G, g9);
   } else {
     for (int j = 0; j < nk; ++j) {
-      const PrimPair Q = kp[j];
+      const PrimPair Q = kp[j * ks];
       for (int i = 0; i < nb; ++i) {
         const PrimPair B = bp[i];
         const double pq = B.p + Q.p;
@@ -85,11 +85,11 @@ __device__ __forceinline__ void grad_block_body(const PrimPair* __restrict__ bp,
 
 template <class CG>
 __device__ __noinline__ void grad_block_outline(const PrimPair* __restrict__ bp, int nb,
-                                                const PrimPair* __restrict__ kp, int nk,
+                                                const PrimPair* __restrict__ kp, int nk, int ks,
                                                 const double* AB, const double* CD,
                                                 const double* __restrict__ tab64,
                                                 const double* __restrict__ G, double* g9) {
-  grad_block_body<CG>(bp, nb, kp, nk, AB, CD, tab64, G, g9);
+  grad_block_body<CG>(bp, nb, kp, nk, ks, AB, CD, tab64, G, g9);
 }
 
 template <typename T>
@@ -121,8 +121,14 @@ __global__ __launch_bounds__(64) void grad_unit_kernel(GradArgs a) {
   const int m0 = sa.bf, n0 = sb.bf;
   const int a0 = a.atom_off[inst];
   double* Prow = lds;                 // P rows of bf m0 + r (r < NA) and n0 + r - NA
-  double* Gat = lds + NR * n;         // dE/dR per atom of the instance
+  double* Gat = lds + NR * a.nmax;    // dE/dR per atom of the instance
   const int nat3 = 3 * a.max_atoms;
+  PrimPair* Bp = reinterpret_cast<PrimPair*>(Gat + nat3);   // the bra's primitives
+  {
+    const double* src = reinterpret_cast<const double*>(a.prims + bra.prim0);
+    double* dst = reinterpret_cast<double*>(Bp);
+    for (int t = lane; t < 12 * bra.nprim; t += kWave) dst[t] = src[t];
+  }
   for (int t = lane; t < NR * n; t += kWave) {
     const int r = t / n, col = t - r * n;
     const int bf = r < NA ? m0 + r : n0 + (r - NA);
@@ -169,12 +175,13 @@ __global__ __launch_bounds__(64) void grad_unit_kernel(GradArgs a) {
           }
       }
     double g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int2 kp = a.kpos[pos];
     if constexpr (CG::LA + CG::LB + CG::LC + CG::LD >= 5) {
-      grad_block_outline<CG>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB,
-                             CD, a.boys64, G, g9);
+      grad_block_outline<CG>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64,
+                             G, g9);
     } else {
-      grad_block_body<CG>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,
-                          a.boys64, G, g9);
+      grad_block_body<CG>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64, G,
+                          g9);
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {

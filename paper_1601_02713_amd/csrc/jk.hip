@@ -45,7 +45,19 @@ __global__ __launch_bounds__(256) void jk_finalize_kernel(KetPosArgs a, int max_
   Jk[t] = 0.0;
 }
 
+__global__ __launch_bounds__(256) void gather_prims_kernel(int n, const int* __restrict__ map,
+                                                           const PrimPair* __restrict__ src,
+                                                           PrimPair* __restrict__ dst) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) dst[t] = src[map[t]];
+}
+
 }  // namespace
+
+void launch_gather_prims(int n, const int* map, const PrimPair* src, PrimPair* dst, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(gather_prims_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, map, src, dst);
+}
 
 void launch_gather_pk(const KetPosArgs& a, int max_ncd, const double* P, double* Pk,
                       hipStream_t s) {

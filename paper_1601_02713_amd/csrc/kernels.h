@@ -72,6 +72,8 @@ struct KetPosArgs {
   const long long* moff;
   const int* nbf;
 };
+// dst[t] = src[map[t]] for the n primitive-pair records of the ket order
+void launch_gather_prims(int n, const int* map, const PrimPair* src, PrimPair* dst, hipStream_t s);
 // Pk[e * nk_total + pos] = P(c_k, d_l)
 void launch_gather_pk(const KetPosArgs& a, int max_ncd, const double* P, double* Pk,
                       hipStream_t s);
