@@ -188,7 +188,9 @@ def main():
                      "tflops": (v["done_flops"] / (v["kernel_ms"] * 1e-3) / 1e12) if v["kernel_ms"] else None,
                      "kernel": "lane" if v["variant"][0 if prec == beadscf.BSCF_FP64 else 1] == 0 else "coop",
                      "grad_ms_per_launch": v["grad_ms"] / max(v["grad_launches"], 1),
-                     "grad_kernel": "lane" if v["variant"][2] == 0 else "coop"}
+                     "grad_kernel": "lane" if v["variant"][2] == 0 else "coop",
+                     "isolated_ms": {"lane": v["tune_ms"][0], "coop": v["tune_ms"][1],
+                                     "grad_lane": v["tune_ms"][2], "grad_coop": v["tune_ms"][3]}}
                  for k, v in cls.items() if v["launches"]}
     d = cls[dom]
     ach = d["done_flops"] / (d["kernel_ms"] * 1e-3) / 1e12 if d["kernel_ms"] > 0 else 0.0
@@ -221,6 +223,9 @@ def main():
         "fock_frac_fp64_peak": (k_fl / (fock_gpu_ms * 1e-3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS) if fock_gpu_ms else None,
         "phase_ms_per_step": {k: st_json[k] / args.steps for k in
                               ("t_setup_ms", "t_scf_ms", "t_grad_ms", "t_fock_ms", "t_work_ms")},
+        "density": {"method": "sp2", "calls_per_step": st_json["sp2_calls"] / args.steps,
+                    "projection_steps_per_call": st_json["sp2_steps"] / max(st_json["sp2_calls"], 1),
+                    "fallbacks": st_json["sp2_fallbacks"]},
         "roofline": {"bound": "alu",
                      "kernel": dom_kernel,
                      "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",

@@ -52,6 +52,11 @@ typedef enum {
   BSCF_GUESS_LEARNED = 2,  /* density predicted by the in-run trained network     */
   BSCF_GUESS_USER = 3      /* density set with bscf_set_density                  */
 } bscf_guess;
+typedef enum {
+  BSCF_DENSITY_SP2 = 0, /* second-order spectral projection of X^T F X (GEMMs only);
+                           a replica without a HOMO-LUMO gap falls back to EIG   */
+  BSCF_DENSITY_EIG = 1  /* eigendecomposition of X^T F X with aufbau occupation   */
+} bscf_density;
 
 /* Per-instance status bits returned by bscf_run_scf. */
 #define BSCF_CONVERGED 0
@@ -72,10 +77,13 @@ typedef struct {
   int precision;       /* bscf_precision                                        */
   int guess;           /* bscf_guess                                            */
   int deterministic;   /* reserved: 0                                           */
+  int density;         /* bscf_density: how each iteration's density is formed;
+                          both give the projector on the lowest N/2 levels of
+                          the extrapolated Fock matrix (Section 2, SCF step)   */
 } bscf_scf_opts;
 
 /* Fill opts with defaults: e_tol 1e-8, comm_tol 1e-6, schwarz_tol 1e-12,
- * fp32_split_tol 1e-4, max_iter 100, diis_size 8, FP64, core guess. */
+ * fp32_split_tol 1e-4, max_iter 100, diis_size 8, FP64, core guess, SP2. */
 bscf_status bscf_default_opts(bscf_scf_opts* opts);
 
 /* Create a context on HIP device `hip_device`; `hip_stream` may be NULL (the

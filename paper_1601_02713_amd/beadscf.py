@@ -23,6 +23,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 BSCF_FP64, BSCF_MIXED = 0, 1
 GUESS_CORE, GUESS_PREVIOUS, GUESS_LEARNED, GUESS_USER = 0, 1, 2, 3
+DENSITY_SP2, DENSITY_EIG = 0, 1
 STATUS_MAX_ITER, STATUS_NAN, STATUS_FALLBACK = 1, 2, 4
 
 
@@ -31,7 +32,7 @@ class ScfOpts(ctypes.Structure):
                 ("schwarz_tol", ctypes.c_double), ("fp32_split_tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("diis_size", ctypes.c_int),
                 ("precision", ctypes.c_int), ("guess", ctypes.c_int),
-                ("deterministic", ctypes.c_int)]
+                ("deterministic", ctypes.c_int), ("density", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p

@@ -52,6 +52,13 @@ constexpr int kUnitQuartets = 256;
 // cooperatively), which bounds every queue's reservation to about 1 GiB.
 constexpr int kMaxLaneScratch = 2048;
 
+// SP2 purification: at most this many projection steps per density, and the
+// idempotency error Tr X - Tr X^2 = sum_k l_k (1 - l_k) below which a replica's
+// projector counts as converged (two more steps then square the residual
+// occupation error away).
+constexpr int kSp2MaxSteps = 100;
+constexpr double kSp2Tol = 1e-11;
+
 thread_local std::string g_err;
 
 struct Error : std::runtime_error {
@@ -346,6 +353,13 @@ struct bscf_ctx {
   DevBuf<double> S, T, V, H, X, F, J, K, P, Pnew, W, tmp1, tmp2, err, Fbar, C, Cacc, eig, eigE;
   DevBuf<double> Fhist, Ehist, diisB, diisC;
   DevBuf<int> diis_count, diis_head, d_info;
+  // SP2 purification: per-step (Tr X, Tr X^2) of every instance, Gershgorin
+  // bounds, and the orbital-commit mask; sp2_pred is the step count the last
+  // call needed (the next call runs that many before its first check)
+  DevBuf<double> d_sp2, d_sp2b;
+  DevBuf<int> d_omask;
+  int sp2_pred = 24;
+  long long sp2_calls = 0, sp2_steps = 0, sp2_fallbacks = 0;
   bool have_C = false;
   std::vector<int> h_active;   // host copy of the active flags
   bool profiling = false;
@@ -460,15 +474,24 @@ void build_orthogonaliser(bscf_ctx* c) {
        c->eig.p, 0.0, c->X.p);
 }
 
-// density from Fbar: F' = X Fbar X, eig, C = X C', P = 2 C_occ C_occ^T
-void density_from_fock(bscf_ctx* c, const double* Fb, double* Pout) {
+// orthonormal-basis Fock matrix F' = X Fb X into eig
+void ortho_fock(bscf_ctx* c, const double* Fb) {
   gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->X.p, Fb, 0.0,
        c->tmp1.p);
   gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->tmp1.p, c->X.p, 0.0,
        c->eig.p);
+}
+
+// orbitals of Fb: eig <- eigenvectors of F' = X Fb X, C = X C'
+void orbitals_from_fock(bscf_ctx* c, const double* Fb) {
+  ortho_fock(c, Fb);
   syevd(c, c->eig.p, c->tmp2.p);
   gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->X.p, c->eig.p, 0.0,
        c->C.p);
+}
+
+// P = 2 C_occ C_occ^T from the orbitals in C
+void density_from_orbitals(bscf_ctx* c, double* Pout) {
   for (const Group& g : c->groups) {
     const long long o = c->moff[g.first];
     const long long st = (long long)g.n * g.n;
@@ -479,6 +502,77 @@ void density_from_fock(bscf_ctx* c, const double* Fb, double* Pout) {
                                           c->C.p + o, g.n, st, c->C.p + o, g.n, st, &zero,
                                           Pout + o, g.n, st, g.count));
   }
+}
+
+// SP2 on F' (in eig, overwritten by the projector Xp) for the instances with
+// act[i] set (the device mask b.active matches); then P = 2 X Xp X.  False when
+// some of them has not converged after kSp2MaxSteps steps (no gap).
+bool density_sp2(bscf_ctx* c, const BatchInfo& b, const std::vector<int>& act, double* Pout) {
+  const hipStream_t st = c->stream;
+  const int ni = c->ninst;
+  const long long sstride = 2LL * ni;
+  double* stats = c->d_sp2.p;
+  launch_fill(stats, (kSp2MaxSteps + 1) * sstride, 0.0, st);
+  launch_sp2_bounds(b, c->max_n, c->eig.p, c->d_sp2b.p, st);
+  launch_sp2_step(b, c->max_n, 0, c->eig.p, c->d_sp2b.p, c->d_nocc.p, nullptr, c->eig.p, nullptr,
+                  stats, st);
+  int k = 0;
+  auto step = [&] {
+    gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->eig.p, c->eig.p,
+         0.0, c->tmp1.p);
+    launch_sp2_step(b, c->max_n, 1, nullptr, nullptr, c->d_nocc.p, c->tmp1.p, c->eig.p,
+                    stats + k * sstride, stats + (k + 1) * sstride, st);
+    ++k;
+  };
+  int target = std::min(std::max(c->sp2_pred, 1), kSp2MaxSteps);
+  std::vector<double> h;
+  for (;;) {
+    while (k < target) step();
+    h.resize((size_t)(k + 1) * sstride);
+    HIPCHK(hipMemcpyAsync(h.data(), stats, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(c);
+    // first converged step of every replica taking part
+    int kc = 0;
+    bool all = true;
+    for (int i = 0; i < ni && all; ++i) {
+      if (!act[i]) continue;
+      int j = 0;
+      for (; j <= k; ++j) {
+        const double tr = h[(size_t)j * sstride + 2 * i], t2 = h[(size_t)j * sstride + 2 * i + 1];
+        if (tr - t2 < kSp2Tol && std::fabs(tr - c->nocc[i]) < 1e-6) break;
+      }
+      if (j > k) all = false;
+      else kc = std::max(kc, j);
+    }
+    if (all) {
+      c->sp2_pred = kc + 2;
+      while (k < std::min(kc + 2, kSp2MaxSteps)) step();   // stats rows stay within the buffer
+      break;
+    }
+    if (k >= kSp2MaxSteps) return false;
+    target = std::min(k + 4, kSp2MaxSteps);
+  }
+  c->sp2_calls++;
+  c->sp2_steps += k;
+  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->X.p, c->eig.p, 0.0,
+       c->tmp1.p);
+  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 2.0, c->tmp1.p, c->X.p, 0.0,
+       Pout);
+  return true;
+}
+
+// density of the extrapolated Fock matrix Fb for the replicas with act[i]
+// (device mask of b): SP2 by default, the eigenvector route on request or when
+// SP2 finds no gap
+void density_from_fock(bscf_ctx* c, const double* Fb, const BatchInfo& b,
+                       const std::vector<int>& act, int method, double* Pout) {
+  if (method == BSCF_DENSITY_SP2) {
+    ortho_fock(c, Fb);
+    if (density_sp2(c, b, act, Pout)) return;
+    c->sp2_fallbacks++;
+  }
+  orbitals_from_fock(c, Fb);
+  density_from_orbitals(c, Pout);
 }
 
 void build_shell_topology(bscf_ctx* c) {
@@ -1017,6 +1111,7 @@ bscf_status bscf_default_opts(bscf_scf_opts* o) {
   o->precision = BSCF_FP64;
   o->guess = BSCF_GUESS_CORE;
   o->deterministic = 0;
+  o->density = BSCF_DENSITY_SP2;
   return BSCF_OK;
 }
 
@@ -1230,13 +1325,16 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->Fhist.resize(mt * 8);
     c->Ehist.resize(mt * 8);
     c->diisB.resize((size_t)n_inst * 64);
+    c->d_sp2.resize((size_t)(kSp2MaxSteps + 1) * 2 * n_inst);
+    c->d_sp2b.resize((size_t)2 * n_inst * c->max_n);
+    c->d_omask.resize(n_inst);
     c->diisC.resize((size_t)n_inst * 8);
     c->diis_count.resize(n_inst);
     c->diis_head.resize(n_inst);
     c->d_Enuc.resize(n_inst);
     c->d_E.resize((size_t)n_inst * (1 + c->max_n));
     c->d_Eprev.resize(n_inst);
-    c->d_emax.resize(n_inst);
+    c->d_emax.resize((size_t)n_inst * (1 + (size_t)((c->max_n + 31) / 32) * ((c->max_n + 31) / 32)));
     c->d_grad.resize((size_t)tot * 3);
     c->d_xyz.resize((size_t)tot * 3);
     c->have_geom = false;
@@ -1287,8 +1385,7 @@ bscf_status bscf_set_geometries(bscf_ctx* c, const double* xyz) {
       const int la = pc == 0 ? 0 : (pc < 3 ? 1 : 2);
       const int lb = pc - la * (la + 1) / 2;
       OneEArgs oa;
-      oa.atoms_per_task_stride = c->max_atoms;
-      oa.ntasks = c->task_count[pc] * c->max_atoms;
+      oa.ntasks = c->task_count[pc];
       oa.task_a = c->d_task_a.p + c->task_first[pc];
       oa.task_b = c->d_task_b.p + c->task_first[pc];
       oa.shells = c->d_shells.p;
@@ -1472,11 +1569,13 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     if (opts) o = *opts;
     need(o.max_iter > 0 && o.diis_size >= 1 && o.diis_size <= 8, BSCF_E_INVALID, "bad options");
     need(o.fp32_split_tol > 0.0, BSCF_E_INVALID, "fp32_split_tol must be positive");
+    need(o.density == BSCF_DENSITY_SP2 || o.density == BSCF_DENSITY_EIG, BSCF_E_INVALID,
+         "density must be BSCF_DENSITY_SP2 or BSCF_DENSITY_EIG");
     c->split_tol = o.fp32_split_tol;
     const double t0 = now_ms();
     const hipStream_t st = c->stream;
     const int ni = c->ninst;
-    std::vector<int> flags(ni, 1), stat(ni, 1), iters(ni, 0);
+    std::vector<int> flags(ni, 1), stat(ni, 1), iters(ni, 0), updates(ni, 0);
     c->h_active.assign(ni, 1);
     // guess
     int guess = o.guess;
@@ -1490,8 +1589,7 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     }
     if (guess == BSCF_GUESS_CORE) {
       c->d_active.upload(flags, st);
-      density_from_fock(c, c->H.p, c->P.p);
-      commit_C_kernel<<<dim3(1024, ni), 256, 0, st>>>(c->batch(true), c->C.p, c->Cacc.p);
+      density_from_fock(c, c->H.p, c->batch(true), flags, o.density, c->P.p);
       c->guess.begin_step(gb, false);
     } else if (guess == BSCF_GUESS_PREVIOUS || guess == BSCF_GUESS_LEARNED) {
       previous_guess(c);
@@ -1535,7 +1633,8 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
            0.0, c->tmp2.p);
       gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->tmp2.p, c->X.p,
            0.0, c->err.p);
-      launch_convergence(ni, c->d_E.p, c->d_Eprev.p, c->d_emax.p, o.e_tol, o.comm_tol, it,
+      launch_convergence(ni, c->max_n, c->d_nbf.p, c->d_E.p, c->d_Eprev.p, c->d_emax.p, o.e_tol,
+                         o.comm_tol, it,
                          c->d_active.p, c->d_conv_iter.p, c->d_status.p, st);
       HIPCHK(hipMemcpyAsync(flags.data(), c->d_active.p, ni * sizeof(int), hipMemcpyDeviceToHost, st));
       sync(c);
@@ -1546,9 +1645,25 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
       if (!any) break;
       launch_diis_store(d, c->max_n, c->F.p, c->err.p, st);
       launch_diis_extrapolate(d, c->max_n, c->Fbar.p, st);
-      density_from_fock(c, c->Fbar.p, c->Pnew.p);
+      density_from_fock(c, c->Fbar.p, bm, flags, o.density, c->Pnew.p);
       launch_commit(bm, c->max_n, c->Pnew.p, c->P.p, st);
-      commit_C_kernel<<<dim3(1024, ni), 256, 0, st>>>(bm, c->C.p, c->Cacc.p);
+      for (int i = 0; i < ni; ++i) updates[i] += flags[i] != 0;
+    }
+    // orbitals for the next call's previous-step guess, once per call: those
+    // of the Fock matrix each replica's final density came from (DIIS leaves a
+    // finished replica's Fbar alone); a replica without a density update here
+    // keeps its stored orbitals
+    {
+      std::vector<int> mask(ni);
+      bool anyu = false;
+      for (int i = 0; i < ni; ++i) anyu |= (mask[i] = updates[i] > 0) != 0;
+      if (anyu) {
+        c->d_omask.upload(mask, st);
+        orbitals_from_fock(c, c->Fbar.p);
+        BatchInfo bo = c->batch(false);
+        bo.active = c->d_omask.p;
+        commit_C_kernel<<<dim3(1024, ni), 256, 0, st>>>(bo, c->C.p, c->Cacc.p);
+      }
     }
     std::vector<double> e(ni);
     HIPCHK(hipMemcpyAsync(e.data(), c->d_E.p, ni * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1590,8 +1705,7 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
       const int la = pc == 0 ? 0 : (pc < 3 ? 1 : 2);
       const int lb = pc - la * (la + 1) / 2;
       Grad1EArgs g;
-      g.atoms_per_task_stride = c->max_atoms;
-      g.ntasks = c->task_count[pc] * c->max_atoms;
+      g.ntasks = c->task_count[pc];
       g.task_a = c->d_task_a.p + c->task_first[pc];
       g.task_b = c->d_task_b.p + c->task_first[pc];
       g.shells = c->d_shells.p;
@@ -1834,6 +1948,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
     }
     c->t_fock_ms = c->t_scf_ms = c->t_grad_ms = c->t_setup_ms = c->t_fock_gpu_ms = c->t_work_ms = 0;
     c->fock_builds = c->scf_iters = 0;
+    c->sp2_calls = c->sp2_steps = c->sp2_fallbacks = 0;
   });
 }
 
@@ -1846,6 +1961,8 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
       << ", \"t_fock_ms\": " << c->t_fock_ms << ", \"t_scf_ms\": " << c->t_scf_ms
       << ", \"t_grad_ms\": " << c->t_grad_ms << ", \"t_setup_ms\": " << c->t_setup_ms
       << ", \"t_fock_gpu_ms\": " << c->t_fock_gpu_ms << ", \"t_work_ms\": " << c->t_work_ms
+      << ", \"sp2_calls\": " << c->sp2_calls << ", \"sp2_steps\": " << c->sp2_steps
+      << ", \"sp2_fallbacks\": " << c->sp2_fallbacks
       << ", \"classes\": {";
     const QuartetClass* qc = quartet_classes();
     for (int q = 0; q < kNumQuartetClasses; ++q) {

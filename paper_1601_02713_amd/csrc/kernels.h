@@ -15,8 +15,7 @@ struct PrimPairSetupArgs {
 };
 
 struct OneEArgs {
-  int ntasks;                  // pairs * atoms_per_task_stride
-  int atoms_per_task_stride;   // max atoms per instance
+  int ntasks;                  // shell pairs a >= b of this class (one block each)
   const int* task_a;
   const int* task_b;
   const Shell* shells;
@@ -35,8 +34,7 @@ struct OneEArgs {
 };
 
 struct Grad1EArgs {
-  int ntasks;
-  int atoms_per_task_stride;
+  int ntasks;                  // shell pairs a >= b of this class (one block each)
   const int* task_a;
   const int* task_b;
   const Shell* shells;
@@ -94,7 +92,9 @@ void launch_fill(double* p, long long n, double v, hipStream_t s);
 void launch_fock_assemble(const BatchInfo& b, int max_n, const double* H, const double* J,
                           const double* K, const double* P, const double* Enuc, double* F,
                           double* E, hipStream_t s);
-// out = A - A^T per instance, emax[i] = max |out| (emax zeroed here)
+// out = A - A^T per instance; the largest |out| of every 32 x 32 tile goes to
+// the scratch after the first ninst entries of emax (room for
+// ninst * ceil(max_n/32)^2 doubles), reduced into emax[i] by launch_convergence
 void launch_antisym(const BatchInfo& b, int max_n, const double* A, double* out, double* emax,
                     hipStream_t s);
 // DIIS: store F, e in slot; update B row; solve; Fbar = sum c F
@@ -115,10 +115,23 @@ struct DiisArgs {
 void launch_diis_store(const DiisArgs& d, int max_n, const double* F, const double* e,
                        hipStream_t s);
 void launch_diis_extrapolate(const DiisArgs& d, int max_n, double* Fbar, hipStream_t s);
-// convergence flags: conv[i] = |E - Eprev| < etol && emax < ctol (only active)
-void launch_convergence(int ninst, const double* E, double* Eprev, const double* emax,
-                        double etol, double ctol, int iter, int* active, int* conv_iter,
-                        int* status, hipStream_t s);
+// convergence flags: emax[i] = max |A - A^T| from launch_antisym's tile
+// maxima; conv[i] = |E - Eprev| < etol && emax < ctol (only active)
+void launch_convergence(int ninst, int max_n, const int* nbf, const double* E, double* Eprev,
+                        double* emax, double etol, double ctol, int iter, int* active,
+                        int* conv_iter, int* status, hipStream_t s);
+// SP2 purification (scf.hip): Gershgorin intervals of the rows of each
+// instance's F' (bounds[inst][row] = (lo, hi), room for ninst * max_n pairs),
+// then one projection step: mode 0 sets X = (hi I - F')/(hi - lo) over their
+// union; mode 1 replaces X by Y = X^2 or by 2X - Y, as the trace rule on
+// st_in (Tr X, Tr X^2 of the previous X) decides.  Tr X and Tr X^2 of the new
+// X are added into st_out, which must start at zero.  Instances masked out by
+// b.active are skipped.
+void launch_sp2_bounds(const BatchInfo& b, int max_n, const double* F, double* bounds,
+                       hipStream_t s);
+void launch_sp2_step(const BatchInfo& b, int max_n, int mode, const double* F,
+                     const double* bounds, const int* nocc, const double* Y, double* X,
+                     const double* st_in, double* st_out, hipStream_t s);
 // P_new -> P for active instances
 void launch_commit(const BatchInfo& b, int max_n, const double* Pnew, double* P, hipStream_t s);
 // nuclear repulsion energy and gradient per instance

@@ -47,7 +47,13 @@ __device__ __forceinline__ double comp_factor(int lx, int ly, int lz) {
 
 constexpr int kMaxL1 = 3;           // shell l after one raise
 constexpr int kS1 = kMaxL1 + 4;     // 1-D overlap index range
-constexpr int kTeam = 64;           // threads per one-electron task
+constexpr int kTeam = 64;           // threads per block (one wavefront)
+
+// A block handles one shell pair and all nuclei.  Its wavefront splits into
+// NS sub-teams of TS = kTeam / NS threads; sub-team s takes nuclei s, s + NS,
+// s + 2 NS, ... and fills its own nuclear-attraction table.  Larger tables
+// (total angular momentum L of the recursion) get larger sub-teams.
+__host__ __device__ constexpr int sub_teams(int L) { return L <= 2 ? 32 : (L == 3 ? 16 : (L <= 5 ? 4 : 2)); }
 
 // 1-D overlap tables S[d][i][j], one direction per thread (threads 0..2).
 __device__ void overlap_1d_dir(double a, double b, double Ad, double Bd, int imax, int jmax,
@@ -116,13 +122,15 @@ __device__ __forceinline__ bool nuc_entry(int tot, int k, int& na, int& nb, int&
   return false;
 }
 
-// Fill the table cooperatively: thread 0 sets the Boys values and scalars,
-// then each level of total angular momentum is spread over the team.
-template <int TA, int TB>
+// Fill one sub-team's table (lt: thread index within the sub-team of TS):
+// its first thread sets the Boys values and scalars, then each level of total
+// angular momentum is spread over the sub-team.  Every thread of the block
+// calls this together (the level barriers are block-wide).
+template <int TA, int TB, int TS>
 __device__ void nuc_table(double a, double b, const double* A, const double* B, const double* C,
-                          const double* boys64, NucTab<TA, TB>& t) {
+                          const double* boys64, int lt, NucTab<TA, TB>& t) {
   constexpr int L = TA + TB;
-  if (threadIdx.x == 0) {
+  if (lt == 0) {
     const double p = a + b, mu = a * b / p;
     double AB2 = 0.0, PC2 = 0.0;
     for (int d = 0; d < 3; ++d) {
@@ -141,7 +149,7 @@ __device__ void nuc_table(double a, double b, const double* A, const double* B, 
   __syncthreads();
   const double oo2p = t.oo2p;
   for (int tot = 1; tot <= L; ++tot) {
-    for (int k = threadIdx.x;; k += kTeam) {
+    for (int k = lt;; k += TS) {
       int na, nb, ca, cb, m;
       if (!nuc_entry<TA, TB>(tot, k, na, nb, ca, cb, m)) break;
       int ta[3], tb[3];
@@ -227,143 +235,198 @@ __global__ void prim_pair_kernel(PrimPairSetupArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// S, T, V: one 64-thread block per (shell pair a >= b of one instance) x
-// nucleus; the recursion tables live in LDS and each thread owns component
-// pairs of the shell block.  V is accumulated with atomics over nuclei; S and
-// T are written by the block of nucleus 0.  Output is the normalised-component
-// basis.
+// S, T, V: one 64-thread block per shell pair a >= b of one instance.  The
+// nuclei are taken in groups of NS, one per sub-team; within a sub-team the
+// threads own component pairs of the shell block (strided by TS).  S and T
+// come from sub-team 0 in the first group; the sub-teams' V partial sums meet
+// in LDS at the end, so every element is written once, without atomics.
+// Output is the normalised-component basis.
 template <int LA, int LB>
 __global__ __launch_bounds__(kTeam) void onee_kernel(OneEArgs a) {
-  __shared__ NucTab<LA, LB> nt;
+  constexpr int NS = sub_teams(LA + LB), TS = kTeam / NS;
+  constexpr int NA = ncart(LA), NB = ncart(LB), NE = (NA * NB + TS - 1) / TS;
+  __shared__ NucTab<LA, LB> nt[NS];
   __shared__ double S1[3][kS1][kS1];
-  const int pidx = blockIdx.x / a.atoms_per_task_stride;
-  const int cidx = blockIdx.x % a.atoms_per_task_stride;
-  const int sh_a = a.task_a[pidx], sh_b = a.task_b[pidx];
+  __shared__ double red[NS][NA * NB];
+  const int sh_a = a.task_a[blockIdx.x], sh_b = a.task_b[blockIdx.x];
   const Shell sa = a.shells[sh_a], sb = a.shells[sh_b];
   const int inst = sa.inst;
-  if (cidx >= a.natoms[inst]) return;
-  const int n = a.nbf[inst];
+  const int n = a.nbf[inst], natoms = a.natoms[inst];
   const long long mo = a.moff[inst];
-  const int atom = a.atom_off[inst] + cidx;
   const double A[3] = {sa.x, sa.y, sa.z}, B[3] = {sb.x, sb.y, sb.z};
-  const double Cc[3] = {a.atom_xyz[3 * atom], a.atom_xyz[3 * atom + 1], a.atom_xyz[3 * atom + 2]};
-  const double Zc = a.atom_Z[atom];
-  constexpr int NA = ncart(LA), NB = ncart(LB);
-  const int e = threadIdx.x;   // component pair of this thread (NA * NB <= 36 < kTeam)
-  const int i = e / NB, j = e % NB;
-  int ta[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
-  if (e < NA * NB) {
-    comp(LA, i, ta[0], ta[1], ta[2]);
-    comp(LB, j, tb[0], tb[1], tb[2]);
+  const int s = threadIdx.x / TS, lt = threadIdx.x % TS;
+  int ta[NE][3], tb[NE][3];
+  bool own[NE];
+  double Sv[NE], Tv[NE], Vv[NE];
+#pragma unroll
+  for (int q = 0; q < NE; ++q) {
+    const int e = lt + q * TS;
+    own[q] = e < NA * NB;
+    ta[q][0] = ta[q][1] = ta[q][2] = tb[q][0] = tb[q][1] = tb[q][2] = 0;
+    if (own[q]) {
+      comp(LA, e / NB, ta[q][0], ta[q][1], ta[q][2]);
+      comp(LB, e % NB, tb[q][0], tb[q][1], tb[q][2]);
+    }
+    Sv[q] = Tv[q] = Vv[q] = 0.0;
   }
-  double Sv = 0.0, Tv = 0.0, Vv = 0.0;
-  for (int ka = 0; ka < sa.nprim; ++ka)
-    for (int kb = 0; kb < sb.nprim; ++kb) {
-      const double al = a.sh_exp[sa.prim0 + ka], be = a.sh_exp[sb.prim0 + kb];
-      const double cc = a.sh_coef[sa.prim0 + ka] * a.sh_coef[sb.prim0 + kb];
-      __syncthreads();   // previous primitive's tables read
-      if (cidx == 0 && threadIdx.x < 3)
-        overlap_1d_dir(al, be, A[threadIdx.x], B[threadIdx.x], LA, LB + 2, S1[threadIdx.x]);
-      nuc_table<LA, LB>(al, be, A, B, Cc, a.boys64, nt);   // ends with a barrier
-      if (e < NA * NB) {
-        Vv -= Zc * cc * nuc_get(nt, ta, tb);
-        if (cidx == 0) {
-          Sv += cc * ov3(S1, ta, tb);
-          Tv += cc * kin3(S1, ta, tb, be);
+  for (int c0 = 0; c0 < natoms; c0 += NS) {
+    const int cidx = c0 + s;
+    const bool live = cidx < natoms;   // idle sub-teams run the barriers with Z = 0
+    const int atom = a.atom_off[inst] + (live ? cidx : 0);
+    const double Cc[3] = {a.atom_xyz[3 * atom], a.atom_xyz[3 * atom + 1], a.atom_xyz[3 * atom + 2]};
+    const double Zc = live ? a.atom_Z[atom] : 0.0;
+    const bool st = c0 == 0 && s == 0;
+    for (int ka = 0; ka < sa.nprim; ++ka)
+      for (int kb = 0; kb < sb.nprim; ++kb) {
+        const double al = a.sh_exp[sa.prim0 + ka], be = a.sh_exp[sb.prim0 + kb];
+        const double cc = a.sh_coef[sa.prim0 + ka] * a.sh_coef[sb.prim0 + kb];
+        __syncthreads();   // previous primitive's tables read
+        if (c0 == 0 && threadIdx.x < 3)
+          overlap_1d_dir(al, be, A[threadIdx.x], B[threadIdx.x], LA, LB + 2, S1[threadIdx.x]);
+        nuc_table<LA, LB, TS>(al, be, A, B, Cc, a.boys64, lt, nt[s]);   // ends with a barrier
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          if (!own[q]) continue;
+          Vv[q] -= Zc * cc * nuc_get(nt[s], ta[q], tb[q]);
+          if (st) {
+            Sv[q] += cc * ov3(S1, ta[q], tb[q]);
+            Tv[q] += cc * kin3(S1, ta[q], tb[q], be);
+          }
         }
       }
-    }
-  if (e < NA * NB) {
-    const double f = comp_factor(ta[0], ta[1], ta[2]) * comp_factor(tb[0], tb[1], tb[2]);
-    const long long ij = mo + (long long)(sa.bf + i) * n + sb.bf + j;
-    const long long ji = mo + (long long)(sb.bf + j) * n + sa.bf + i;
-    atomicAdd(&a.V[ij], f * Vv);
-    if (sh_a != sh_b) atomicAdd(&a.V[ji], f * Vv);
-    if (cidx == 0) {
-      a.S[ij] = f * Sv;
-      a.S[ji] = f * Sv;
-      a.T[ij] = f * Tv;
-      a.T[ji] = f * Tv;
+  }
+#pragma unroll
+  for (int q = 0; q < NE; ++q)
+    if (own[q]) red[s][lt + q * TS] = Vv[q];
+  __syncthreads();
+  for (int e = threadIdx.x; e < NA * NB; e += kTeam) {
+    double v = 0.0;
+    for (int k = 0; k < NS; ++k) v += red[k][e];
+    int xa[3], xb[3];
+    comp(LA, e / NB, xa[0], xa[1], xa[2]);
+    comp(LB, e % NB, xb[0], xb[1], xb[2]);
+    const double f = comp_factor(xa[0], xa[1], xa[2]) * comp_factor(xb[0], xb[1], xb[2]);
+    const long long ij = mo + (long long)(sa.bf + e / NB) * n + sb.bf + e % NB;
+    const long long ji = mo + (long long)(sb.bf + e % NB) * n + sa.bf + e / NB;
+    a.V[ij] = f * v;
+    if (sh_a != sh_b) a.V[ji] = f * v;   // a diagonal block's elements each have their own thread
+  }
+  if (s == 0) {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      if (!own[q]) continue;
+      const int e = lt + q * TS;
+      const double f = comp_factor(ta[q][0], ta[q][1], ta[q][2]) * comp_factor(tb[q][0], tb[q][1], tb[q][2]);
+      const long long ij = mo + (long long)(sa.bf + e / NB) * n + sb.bf + e % NB;
+      const long long ji = mo + (long long)(sb.bf + e % NB) * n + sa.bf + e / NB;
+      a.S[ij] = f * Sv[q];
+      a.T[ij] = f * Tv[q];
+      if (sh_a != sh_b) {
+        a.S[ji] = f * Sv[q];
+        a.T[ji] = f * Tv[q];
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // One-electron gradient: sum P dH/dX - sum W dS/dX per atom; one 64-thread
-// block per (pair a >= b) x nucleus, off-diagonal pairs counted twice, tables
-// in LDS, component pairs over the threads, a wavefront reduction at the end.
+// block per shell pair a >= b (off-diagonal pairs counted twice) with the
+// nuclei in sub-team groups as above.  A sub-team reduces its operator-centre
+// terms over its threads after each nucleus; the basis-centre terms are
+// reduced over the wavefront once at the end.
 template <int LA, int LB>
 __global__ __launch_bounds__(kTeam) void grad1e_kernel(Grad1EArgs a) {
-  __shared__ NucTab<LA + 1, LB + 1> nt;
+  constexpr int NS = sub_teams(LA + LB + 2), TS = kTeam / NS;
+  constexpr int NA = ncart(LA), NB = ncart(LB), NE = (NA * NB + TS - 1) / TS;
+  __shared__ NucTab<LA + 1, LB + 1> nt[NS];
   __shared__ double S1[3][kS1][kS1];
-  const int pidx = blockIdx.x / a.atoms_per_task_stride;
-  const int cidx = blockIdx.x % a.atoms_per_task_stride;
-  const int sh_a = a.task_a[pidx], sh_b = a.task_b[pidx];
+  const int sh_a = a.task_a[blockIdx.x], sh_b = a.task_b[blockIdx.x];
   const Shell sa = a.shells[sh_a], sb = a.shells[sh_b];
   const int inst = sa.inst;
-  if (cidx >= a.natoms[inst]) return;
   if (!a.active[inst]) return;
-  const int n = a.nbf[inst];
+  const int n = a.nbf[inst], natoms = a.natoms[inst];
   const long long mo = a.moff[inst];
-  const int atom = a.atom_off[inst] + cidx;
   const double A[3] = {sa.x, sa.y, sa.z}, B[3] = {sb.x, sb.y, sb.z};
-  const double Cc[3] = {a.atom_xyz[3 * atom], a.atom_xyz[3 * atom + 1], a.atom_xyz[3 * atom + 2]};
-  const double Zc = a.atom_Z[atom];
-  constexpr int NA = ncart(LA), NB = ncart(LB);
   const double sym = (sh_a == sh_b) ? 1.0 : 2.0;
-  const int e = threadIdx.x;
-  const bool own = e < NA * NB;
-  int ta[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
-  double pij = 0.0, wij = 0.0;
-  if (own) {
-    comp(LA, e / NB, ta[0], ta[1], ta[2]);
-    comp(LB, e % NB, tb[0], tb[1], tb[2]);
-    const double f = comp_factor(ta[0], ta[1], ta[2]) * comp_factor(tb[0], tb[1], tb[2]);
-    const long long ij = mo + (long long)(sa.bf + e / NB) * n + sb.bf + e % NB;
-    pij = sym * f * a.P[ij];
-    wij = sym * f * a.W[ij];
+  const int s = threadIdx.x / TS, lt = threadIdx.x % TS;
+  int ta[NE][3], tb[NE][3];
+  bool own[NE];
+  double pij[NE], wij[NE];
+#pragma unroll
+  for (int q = 0; q < NE; ++q) {
+    const int e = lt + q * TS;
+    own[q] = e < NA * NB;
+    ta[q][0] = ta[q][1] = ta[q][2] = tb[q][0] = tb[q][1] = tb[q][2] = 0;
+    pij[q] = wij[q] = 0.0;
+    if (own[q]) {
+      comp(LA, e / NB, ta[q][0], ta[q][1], ta[q][2]);
+      comp(LB, e % NB, tb[q][0], tb[q][1], tb[q][2]);
+      const double f = comp_factor(ta[q][0], ta[q][1], ta[q][2]) * comp_factor(tb[q][0], tb[q][1], tb[q][2]);
+      const long long ij = mo + (long long)(sa.bf + e / NB) * n + sb.bf + e % NB;
+      pij[q] = sym * f * a.P[ij];
+      wij[q] = sym * f * a.W[ij];
+    }
   }
-  double g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // A, B, C
-  for (int ka = 0; ka < sa.nprim; ++ka)
-    for (int kb = 0; kb < sb.nprim; ++kb) {
-      const double al = a.sh_exp[sa.prim0 + ka], be = a.sh_exp[sb.prim0 + kb];
-      const double cc = a.sh_coef[sa.prim0 + ka] * a.sh_coef[sb.prim0 + kb];
-      __syncthreads();
-      if (cidx == 0 && threadIdx.x < 3)
-        overlap_1d_dir(al, be, A[threadIdx.x], B[threadIdx.x], LA + 1, LB + 3, S1[threadIdx.x]);
-      nuc_table<LA + 1, LB + 1>(al, be, A, B, Cc, a.boys64, nt);
-      if (!own) continue;
-      for (int d = 0; d < 3; ++d) {
-        int up[3] = {ta[0], ta[1], ta[2]}, dn[3] = {ta[0], ta[1], ta[2]};
-        up[d] += 1;
-        dn[d] -= 1;
-        int upb[3] = {tb[0], tb[1], tb[2]}, dnb[3] = {tb[0], tb[1], tb[2]};
-        upb[d] += 1;
-        dnb[d] -= 1;
-        // nuclear attraction of this nucleus, basis-centre derivatives
-        const double vA = -Zc * (2 * al * nuc_get(nt, up, tb) - ta[d] * nuc_get(nt, dn, tb));
-        const double vB = -Zc * (2 * be * nuc_get(nt, ta, upb) - tb[d] * nuc_get(nt, ta, dnb));
-        g[d] += cc * pij * vA;
-        g[3 + d] += cc * pij * vB;
-        g[6 + d] -= cc * pij * (vA + vB);
-        if (cidx == 0) {
-          const double sA = 2 * al * ov3(S1, up, tb) - ta[d] * ov3(S1, dn, tb);
-          const double sB = 2 * be * ov3(S1, ta, upb) - tb[d] * ov3(S1, ta, dnb);
-          const double kA = 2 * al * kin3(S1, up, tb, be) - ta[d] * kin3(S1, dn, tb, be);
-          const double kB = 2 * be * kin3(S1, ta, upb, be) - tb[d] * kin3(S1, ta, dnb, be);
-          g[d] += cc * (pij * kA - wij * sA);
-          g[3 + d] += cc * (pij * kB - wij * sB);
+  double gab[6] = {0, 0, 0, 0, 0, 0};   // A, B
+  for (int c0 = 0; c0 < natoms; c0 += NS) {
+    const int cidx = c0 + s;
+    const bool live = cidx < natoms;   // idle sub-teams run the barriers with Z = 0
+    const int atom = a.atom_off[inst] + (live ? cidx : 0);
+    const double Cc[3] = {a.atom_xyz[3 * atom], a.atom_xyz[3 * atom + 1], a.atom_xyz[3 * atom + 2]};
+    const double Zc = live ? a.atom_Z[atom] : 0.0;
+    const bool st = c0 == 0 && s == 0;
+    double gc[3] = {0, 0, 0};
+    for (int ka = 0; ka < sa.nprim; ++ka)
+      for (int kb = 0; kb < sb.nprim; ++kb) {
+        const double al = a.sh_exp[sa.prim0 + ka], be = a.sh_exp[sb.prim0 + kb];
+        const double cc = a.sh_coef[sa.prim0 + ka] * a.sh_coef[sb.prim0 + kb];
+        __syncthreads();
+        if (c0 == 0 && threadIdx.x < 3)
+          overlap_1d_dir(al, be, A[threadIdx.x], B[threadIdx.x], LA + 1, LB + 3, S1[threadIdx.x]);
+        nuc_table<LA + 1, LB + 1, TS>(al, be, A, B, Cc, a.boys64, lt, nt[s]);
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          if (!own[q]) continue;
+          for (int d = 0; d < 3; ++d) {
+            int up[3] = {ta[q][0], ta[q][1], ta[q][2]}, dn[3] = {ta[q][0], ta[q][1], ta[q][2]};
+            up[d] += 1;
+            dn[d] -= 1;
+            int upb[3] = {tb[q][0], tb[q][1], tb[q][2]}, dnb[3] = {tb[q][0], tb[q][1], tb[q][2]};
+            upb[d] += 1;
+            dnb[d] -= 1;
+            // nuclear attraction of this nucleus, basis-centre derivatives
+            const double vA = -Zc * (2 * al * nuc_get(nt[s], up, tb[q]) - ta[q][d] * nuc_get(nt[s], dn, tb[q]));
+            const double vB = -Zc * (2 * be * nuc_get(nt[s], ta[q], upb) - tb[q][d] * nuc_get(nt[s], ta[q], dnb));
+            gab[d] += cc * pij[q] * vA;
+            gab[3 + d] += cc * pij[q] * vB;
+            gc[d] -= cc * pij[q] * (vA + vB);
+            if (st) {
+              const double sA = 2 * al * ov3(S1, up, tb[q]) - ta[q][d] * ov3(S1, dn, tb[q]);
+              const double sB = 2 * be * ov3(S1, ta[q], upb) - tb[q][d] * ov3(S1, ta[q], dnb);
+              const double kA = 2 * al * kin3(S1, up, tb[q], be) - ta[q][d] * kin3(S1, dn, tb[q], be);
+              const double kB = 2 * be * kin3(S1, ta[q], upb, be) - tb[q][d] * kin3(S1, ta[q], dnb, be);
+              gab[d] += cc * (pij[q] * kA - wij[q] * sA);
+              gab[3 + d] += cc * (pij[q] * kB - wij[q] * sB);
+            }
+          }
         }
       }
-    }
+    // operator-centre terms of this sub-team's nucleus (lanes of a sub-team
+    // are contiguous and aligned, so the xor butterfly stays inside it)
 #pragma unroll
-  for (int k = 0; k < 9; ++k)
-    for (int o = 32; o > 0; o >>= 1) g[k] += __shfl_xor(g[k], o, kTeam);
+    for (int d = 0; d < 3; ++d)
+      for (int o = TS / 2; o > 0; o >>= 1) gc[d] += __shfl_xor(gc[d], o, kTeam);
+    if (live && lt == 0)
+      for (int d = 0; d < 3; ++d) atomicAdd(&a.grad[3 * atom + d], gc[d]);
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    for (int o = 32; o > 0; o >>= 1) gab[k] += __shfl_xor(gab[k], o, kTeam);
   if (threadIdx.x == 0)
     for (int d = 0; d < 3; ++d) {
-      atomicAdd(&a.grad[3 * sa.atom + d], g[d]);
-      atomicAdd(&a.grad[3 * sb.atom + d], g[3 + d]);
-      atomicAdd(&a.grad[3 * atom + d], g[6 + d]);
+      atomicAdd(&a.grad[3 * sa.atom + d], gab[d]);
+      atomicAdd(&a.grad[3 * sb.atom + d], gab[3 + d]);
     }
 }
 

@@ -7,6 +7,15 @@
 // The J and K accumulated by the class kernels are symmetrised here.
 // Pulay DIIS (Pulay 1980/1982): B_ij = <e_i, e_j>, minimise |sum c_i e_i| with
 // sum c_i = 1, Fbar = sum c_i F_i.
+// Density from the orthonormal-basis Fock matrix F' by second-order spectral
+// projection (SP2, the trace-correcting purification of Niklasson, Phys. Rev.
+// B 66, 155115 (2002)): X_0 = (hi I - F') / (hi - lo) over Gershgorin bounds
+// [lo, hi] maps the spectrum into [0, 1] with the lowest levels of F' on top;
+// each step replaces X by X^2 or 2X - X^2, whichever brings Tr of the result
+// closer to the number of occupied orbitals, which drives the occupied levels
+// to 1 and the rest to 0 while keeping their order, so X converges to the
+// projector on the occupied subspace that diagonalisation with aufbau
+// occupation gives.
 #include <algorithm>
 #include <cmath>
 
@@ -68,24 +77,45 @@ __global__ void energy_sum_kernel(int ninst, int max_n, const int* nbf, const in
   if (threadIdx.x == 0) E[inst] = e + Enuc[inst];
 }
 
-__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
-  atomicMax(reinterpret_cast<unsigned long long*>(addr), __double_as_longlong(v));
+constexpr int kTile = 32;
+__host__ __device__ inline int ntiles_1d(int n) { return (n + kTile - 1) / kTile; }
+
+// max that keeps a NaN (so a diverged replica is caught by the finiteness test)
+__device__ __forceinline__ double nan_max(double a, double b) {
+  return (a != a || b != b) ? NAN : fmax(a, b);
 }
 
-// e = A - A^T written to A's antisymmetric copy out; emax over active instances
-__global__ void antisym_kernel(BatchInfo b, const double* A, double* out, double* emax) {
-  const int inst = blockIdx.y, i = blockIdx.x;
+// out = A - A^T by 32 x 32 tiles staged in LDS (both reads coalesced); the
+// largest |out| of each tile goes to tmax[inst][bi][bj] (tile grid of max_n)
+__global__ void antisym_kernel(BatchInfo b, int max_n, const double* A, double* out,
+                               double* tmax) {
+  __shared__ double t1[kTile][kTile + 1], t2[kTile][kTile + 1];
+  __shared__ double wm[4];
+  const int inst = blockIdx.z;
   const int n = b.nbf[inst];
-  if (i >= n) return;
+  const int nt = ntiles_1d(n), ntm = ntiles_1d(max_n);
+  const int bi = blockIdx.x, bj = blockIdx.y;
+  if (bi >= nt || bj >= nt) return;
   const long long o = b.moff[inst];
-  double m = 0.0;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const double v = A[o + (long long)i * n + j] - A[o + (long long)j * n + i];
-    out[o + (long long)i * n + j] = v;
-    m = fmax(m, fabs(v));
+  const int i0 = bi * kTile, j0 = bj * kTile, c = threadIdx.x;
+  for (int r = threadIdx.y; r < kTile; r += blockDim.y) {
+    t1[r][c] = (i0 + r < n && j0 + c < n) ? A[o + (long long)(i0 + r) * n + j0 + c] : 0.0;
+    t2[r][c] = (j0 + r < n && i0 + c < n) ? A[o + (long long)(j0 + r) * n + i0 + c] : 0.0;
   }
-  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(&emax[inst], m);
+  __syncthreads();
+  double m = 0.0;
+  for (int r = threadIdx.y; r < kTile; r += blockDim.y)
+    if (i0 + r < n && j0 + c < n) {
+      const double v = t1[r][c] - t2[c][r];   // A[i][j] - A[j][i]
+      out[o + (long long)(i0 + r) * n + j0 + c] = v;
+      m = nan_max(m, fabs(v));
+    }
+  for (int off = 32; off > 0; off >>= 1) m = nan_max(m, __shfl_xor(m, off, 64));
+  const int tid = threadIdx.y * kTile + threadIdx.x;
+  if ((tid & 63) == 0) wm[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0)
+    tmax[((long long)inst * ntm + bi) * ntm + bj] = nan_max(nan_max(wm[0], wm[1]), nan_max(wm[2], wm[3]));
 }
 
 // DIIS: copy F, e into the slot head[inst]
@@ -100,9 +130,18 @@ __global__ void diis_copy_kernel(DiisArgs d, const double* F, const double* e) {
     d.Fhist[slot * d.stride + o + k] = F[o + k];
     d.Ehist[slot * d.stride + o + k] = e[o + k];
   }
+  // the slot's row and column of B are summed afresh by diis_dot_kernel
+  if (blockIdx.x == 0 && threadIdx.x < d.max_vec) {
+    double* B = d.B + (long long)inst * d.max_vec * d.max_vec;
+    B[slot * d.max_vec + threadIdx.x] = 0.0;
+    B[threadIdx.x * d.max_vec + slot] = 0.0;
+  }
 }
 
-// B[inst][slot][j] = <e_slot, e_j> for stored j (grid: (max_vec, ninst))
+// B[inst][slot][j] = <e_slot, e_j> for stored j; grid (max_vec, ninst,
+// kDotSplit): each block sums one slice of the elements into B (zeroed by
+// diis_copy_kernel)
+constexpr int kDotSplit = 8;
 __global__ void diis_dot_kernel(DiisArgs d) {
   __shared__ double sh[8];
   const int inst = blockIdx.y, j = blockIdx.x;
@@ -116,14 +155,16 @@ __global__ void diis_dot_kernel(DiisArgs d) {
   if (!used) return;
   const int n = d.nbf[inst];
   const long long o = d.moff[inst], nn = (long long)n * n;
+  const long long per = (nn + kDotSplit - 1) / kDotSplit;
+  const long long k0 = blockIdx.z * per, k1 = min(nn, k0 + per);
   double s = 0.0;
-  for (long long k = threadIdx.x; k < nn; k += blockDim.x)
+  for (long long k = k0 + threadIdx.x; k < k1; k += blockDim.x)
     s += d.Ehist[slot * d.stride + o + k] * d.Ehist[j * d.stride + o + k];
   s = block_sum(s, sh);
   if (threadIdx.x == 0) {
     double* B = d.B + (long long)inst * d.max_vec * d.max_vec;
-    B[slot * d.max_vec + j] = s;
-    B[j * d.max_vec + slot] = s;
+    atomicAdd(&B[slot * d.max_vec + j], s);
+    if (j != slot) atomicAdd(&B[j * d.max_vec + slot], s);
   }
 }
 
@@ -135,57 +176,85 @@ __global__ void diis_advance_kernel(DiisArgs d) {
 }
 
 // Solve the DIIS system per instance; drop the oldest vector while the
-// elimination meets a pivot below 1e-14 of the largest |B| entry.
-__global__ void diis_solve_kernel(DiisArgs d) {
-  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
-  if (inst >= d.ninst || !d.active[inst]) return;
+// elimination meets a pivot below 1e-14 of the largest |B| entry.  One
+// wavefront per instance: lane r holds row r of the bordered system
+//   [B  -1] [c     ]   [ 0]
+//   [-1  0] [lambda] = [-1]
+// in registers (columns 0..8, right-hand side in column 9); Gauss-Jordan
+// elimination with partial pivoting, rows exchanged by lane shuffles.
+__global__ __launch_bounds__(64) void diis_solve_kernel(DiisArgs d) {
+  constexpr int kMaxM = 9;   // max_vec + 1
+  const int inst = blockIdx.x;
+  if (!d.active[inst]) return;
+  const int lane = threadIdx.x;
   const int mv = d.max_vec;
   const double* B = d.B + (long long)inst * mv * mv;
-  double* c = d.coef + (long long)inst * mv;
-  for (int k = 0; k < mv; ++k) c[k] = 0.0;
+  double* cf = d.coef + (long long)inst * mv;
   const int cnt = d.count[inst];
   const int newest = (d.head[inst] - 1 + mv) % mv;
-  int use = cnt;
-  while (use >= 2) {
-    int slots[8];
-    for (int k = 0; k < use; ++k) slots[k] = (newest - k + mv) % mv;
+  for (int use = cnt; use >= 2; --use) {
     const int m = use + 1;
-    double A[9][10];
+    double a[kMaxM + 1];
     double bmax = 0.0;
-    for (int r = 0; r < use; ++r)
-      for (int q = 0; q < use; ++q) {
-        A[r][q] = B[slots[r] * mv + slots[q]];
-        bmax = fmax(bmax, fabs(A[r][q]));
-      }
-    for (int r = 0; r < use; ++r) {
-      A[r][use] = -1.0;
-      A[use][r] = -1.0;
-      A[r][m] = 0.0;
+    const int sr = lane < mv ? (newest - lane + mv) % mv : 0;   // slot of this lane's row
+#pragma unroll
+    for (int q = 0; q <= kMaxM; ++q) a[q] = 0.0;
+    if (lane < use) {
+#pragma unroll
+      for (int q = 0; q < kMaxM; ++q)
+        if (q < use) {
+          a[q] = B[sr * mv + (newest - q + mv) % mv];
+          bmax = fmax(bmax, fabs(a[q]));
+        }
+#pragma unroll
+      for (int q = 0; q < kMaxM; ++q)
+        if (q == use) a[q] = -1.0;
+    } else if (lane == use) {
+#pragma unroll
+      for (int q = 0; q < kMaxM; ++q)
+        if (q < use) a[q] = -1.0;
+      a[kMaxM] = -1.0;
     }
-    A[use][use] = 0.0;
-    A[use][m] = -1.0;
+    for (int off = 32; off > 0; off >>= 1) bmax = fmax(bmax, __shfl_xor(bmax, off, 64));
     bool ok = true;
-    for (int col = 0; col < m && ok; ++col) {
-      int piv = col;
-      for (int r = col + 1; r < m; ++r)
-        if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
-      const double pv = A[piv][col];
-      if (!(fabs(pv) > 1e-14 * fmax(bmax, 1e-300))) { ok = false; break; }
-      if (piv != col)
-        for (int q = 0; q <= m; ++q) { const double t = A[col][q]; A[col][q] = A[piv][q]; A[piv][q] = t; }
-      for (int r = 0; r < m; ++r) {
-        if (r == col) continue;
-        const double f = A[r][col] / pv;
-        for (int q = col; q <= m; ++q) A[r][q] -= f * A[col][q];
+#pragma unroll
+    for (int col = 0; col < kMaxM; ++col) {
+      if (col >= m || !ok) continue;
+      // pivot: the first row in [col, m) of largest |a[col]|
+      const bool cand = lane >= col && lane < m;
+      double v = cand ? fabs(a[col]) : -1.0;
+      double vmax = v;
+      for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off, 64));
+      const unsigned long long hit = __ballot(cand && v == vmax);
+      const int piv = __ffsll((long long)hit) - 1;
+      const double pv = __shfl(a[col], piv, 64);
+      if (!(fabs(pv) > 1e-14 * fmax(bmax, 1e-300))) { ok = false; continue; }
+      const int partner = lane == col ? piv : (lane == piv ? col : lane);
+#pragma unroll
+      for (int q = 0; q <= kMaxM; ++q) a[q] = __shfl(a[q], partner, 64);
+      double prow[kMaxM + 1];
+#pragma unroll
+      for (int q = 0; q <= kMaxM; ++q) prow[q] = __shfl(a[q], col, 64);
+      if (lane != col && lane < m) {
+        const double f = a[col] / pv;
+#pragma unroll
+        for (int q = 0; q <= kMaxM; ++q)
+          if (q >= col) a[q] -= f * prow[q];
       }
     }
     if (ok) {
-      for (int k = 0; k < use; ++k) c[slots[k]] = A[k][m] / A[k][k];
+      double dg = 1.0;
+#pragma unroll
+      for (int q = 0; q < kMaxM; ++q)
+        if (q == lane) dg = a[q];
+      const double mine = a[kMaxM] / dg;   // coefficient of row lane's slot
+      const int k = lane < mv ? (newest - lane + mv) % mv : 0;   // row holding slot `lane`
+      const double v = __shfl(mine, k, 64);
+      if (lane < mv) cf[lane] = k < use ? v : 0.0;
       return;
     }
-    --use;  // drop the oldest
   }
-  c[newest] = 1.0;
+  if (lane < mv) cf[lane] = lane == newest ? 1.0 : 0.0;
 }
 
 __global__ void diis_combine_kernel(DiisArgs d, double* Fbar) {
@@ -203,19 +272,28 @@ __global__ void diis_combine_kernel(DiisArgs d, double* Fbar) {
   }
 }
 
-__global__ void convergence_kernel(int ninst, const double* E, double* Eprev, const double* emax,
-                                   double etol, double ctol, int iter, int* active,
-                                   int* conv_iter, int* status) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ninst || !active[i]) return;
+__global__ __launch_bounds__(64) void convergence_kernel(int ninst, int max_n, const int* nbf,
+                                                        const double* E, double* Eprev,
+                                                        const double* tmax, double* emax,
+                                                        double etol, double ctol, int iter,
+                                                        int* active, int* conv_iter, int* status) {
+  const int i = blockIdx.x;
+  if (!active[i]) return;
+  const int nt = ntiles_1d(nbf[i]), ntm = ntiles_1d(max_n);
+  double em = 0.0;
+  for (int t = threadIdx.x; t < nt * nt; t += 64)
+    em = nan_max(em, tmax[((long long)i * ntm + t / nt) * ntm + t % nt]);
+  for (int off = 32; off > 0; off >>= 1) em = nan_max(em, __shfl_xor(em, off, 64));
+  if (threadIdx.x != 0) return;
+  emax[i] = em;
   const double e = E[i];
-  if (!isfinite(e) || !isfinite(emax[i])) {
+  if (!isfinite(e) || !isfinite(em)) {
     active[i] = 0;
     status[i] |= 2;
     conv_iter[i] = iter + 1;
     return;
   }
-  if (iter > 0 && fabs(e - Eprev[i]) < etol && emax[i] < ctol) {
+  if (iter > 0 && fabs(e - Eprev[i]) < etol && em < ctol) {
     active[i] = 0;
     status[i] &= ~1;
     conv_iter[i] = iter + 1;
@@ -275,6 +353,86 @@ __global__ void nuclear_kernel(int ninst, const int* natoms, const int* atom_off
   Enuc[inst] = e;
 }
 
+// Gershgorin intervals of the rows of each instance's symmetric F': one
+// wavefront per row (read as its column, contiguous), rowb[inst][r] = (lo, hi)
+__global__ void sp2_bounds_kernel(BatchInfo b, int max_n, const double* F, double* rowb) {
+  const int inst = blockIdx.y;
+  if (b.active && !b.active[inst]) return;
+  const int n = b.nbf[inst];
+  const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (r >= n) return;   // whole wavefront; no barrier follows
+  const long long o = b.moff[inst];
+  double off = 0.0;
+  for (int j = lane; j < n; j += 64)
+    if (j != r) off += fabs(F[o + (long long)r * n + j]);
+  for (int k = 32; k > 0; k >>= 1) off += __shfl_xor(off, k, 64);
+  if (lane == 0) {
+    const double d = F[o + (long long)r * n + r];
+    rowb[((long long)inst * max_n + r) * 2] = d - off;
+    rowb[((long long)inst * max_n + r) * 2 + 1] = d + off;
+  }
+}
+
+// mode 0: X = (hi I - F') / (hi - lo); mode 1: X <- X^2 or 2X - X^2 (Y = X^2)
+// by the trace rule on the previous X's statistics st_in.  Both accumulate the
+// trace and the squared Frobenius norm (= Tr X^2 for symmetric X) of the new X
+// into st_out (zeroed by the caller).  X may alias F in mode 0.
+__global__ void sp2_step_kernel(BatchInfo b, int max_n, int mode, const double* F, const double* bounds,
+                                const int* nocc, const double* Y, double* X, const double* st_in,
+                                double* st_out) {
+  __shared__ double sh[16];
+  const int inst = blockIdx.y;
+  if (b.active && !b.active[inst]) return;
+  const int n = b.nbf[inst], nn = n * n;
+  const long long o = b.moff[inst];
+  double hi = 0.0, w = 1.0;
+  bool square = false;
+  if (mode == 0) {
+    // spectral interval: union of the rows' Gershgorin intervals
+    __shared__ double slo[4], shi[4];
+    double lo = INFINITY;
+    hi = -INFINITY;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+      lo = fmin(lo, bounds[((long long)inst * max_n + r) * 2]);
+      hi = fmax(hi, bounds[((long long)inst * max_n + r) * 2 + 1]);
+    }
+    for (int k = 32; k > 0; k >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, k, 64));
+      hi = fmax(hi, __shfl_xor(hi, k, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      slo[threadIdx.x >> 6] = lo;
+      shi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      lo = fmin(lo, slo[k]);
+      hi = fmax(hi, shi[k]);
+    }
+    w = hi - lo;
+    if (!(w > 0.0)) w = 1.0;   // F' = c I: X_0 = 0, which the trace check rejects
+  } else {
+    const double tr = st_in[2 * inst], t2 = st_in[2 * inst + 1], N = nocc[inst];
+    square = fabs(t2 - N) < fabs(2.0 * tr - t2 - N);
+  }
+  double ts = 0.0, fs = 0.0;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
+    const bool diag = (k % n) == (k / n);
+    double x;
+    if (mode == 0) x = ((diag ? hi : 0.0) - F[o + k]) / w;
+    else x = square ? Y[o + k] : 2.0 * X[o + k] - Y[o + k];
+    X[o + k] = x;
+    fs += x * x;
+    if (diag) ts += x;
+  }
+  ts = block_sum(ts, sh);
+  fs = block_sum(fs, sh);
+  if (threadIdx.x == 0) {
+    atomicAdd(&st_out[2 * inst], ts);
+    atomicAdd(&st_out[2 * inst + 1], fs);
+  }
+}
+
 }  // namespace
 
 void launch_fill(double* p, long long n, double v, hipStream_t s) {
@@ -298,8 +456,9 @@ void launch_fock_assemble(const BatchInfo& b, int max_n, const double* H, const 
 
 void launch_antisym(const BatchInfo& b, int max_n, const double* A, double* out, double* emax,
                     hipStream_t s) {
-  launch_fill(emax, b.ninst, 0.0, s);
-  hipLaunchKernelGGL(antisym_kernel, dim3(max_n, b.ninst), dim3(256), 0, s, b, A, out, emax);
+  const int nt = ntiles_1d(max_n);
+  hipLaunchKernelGGL(antisym_kernel, dim3(nt, nt, b.ninst), dim3(kTile, 8), 0, s, b, max_n, A, out,
+                     emax + b.ninst);
 }
 
 void launch_diis_store(const DiisArgs& d, int max_n, const double* F, const double* e,
@@ -307,28 +466,44 @@ void launch_diis_store(const DiisArgs& d, int max_n, const double* F, const doub
   const long long nn = (long long)max_n * max_n;
   const unsigned gx = (unsigned)std::min<long long>((nn + 255) / 256, 1024);
   hipLaunchKernelGGL(diis_copy_kernel, dim3(gx, d.ninst), dim3(256), 0, s, d, F, e);
-  hipLaunchKernelGGL(diis_dot_kernel, dim3(d.max_vec, d.ninst), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(diis_dot_kernel, dim3(d.max_vec, d.ninst, kDotSplit), dim3(256), 0, s, d);
   hipLaunchKernelGGL(diis_advance_kernel, dim3((d.ninst + 63) / 64), dim3(64), 0, s, d);
 }
 
 void launch_diis_extrapolate(const DiisArgs& d, int max_n, double* Fbar, hipStream_t s) {
-  hipLaunchKernelGGL(diis_solve_kernel, dim3((d.ninst + 63) / 64), dim3(64), 0, s, d);
+  hipLaunchKernelGGL(diis_solve_kernel, dim3(d.ninst), dim3(64), 0, s, d);
   const long long nn = (long long)max_n * max_n;
   const unsigned gx = (unsigned)std::min<long long>((nn + 255) / 256, 1024);
   hipLaunchKernelGGL(diis_combine_kernel, dim3(gx, d.ninst), dim3(256), 0, s, d, Fbar);
 }
 
-void launch_convergence(int ninst, const double* E, double* Eprev, const double* emax,
-                        double etol, double ctol, int iter, int* active, int* conv_iter,
-                        int* status, hipStream_t s) {
-  hipLaunchKernelGGL(convergence_kernel, dim3((ninst + 63) / 64), dim3(64), 0, s, ninst, E,
-                     Eprev, emax, etol, ctol, iter, active, conv_iter, status);
+void launch_convergence(int ninst, int max_n, const int* nbf, const double* E, double* Eprev,
+                        double* emax, double etol, double ctol, int iter, int* active,
+                        int* conv_iter, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(convergence_kernel, dim3(ninst), dim3(64), 0, s, ninst, max_n, nbf, E, Eprev,
+                     emax + ninst, emax, etol, ctol, iter, active, conv_iter, status);
 }
 
 void launch_commit(const BatchInfo& b, int max_n, const double* Pnew, double* P, hipStream_t s) {
   const long long nn = (long long)max_n * max_n;
   const unsigned gx = (unsigned)std::min<long long>((nn + 255) / 256, 1024);
   hipLaunchKernelGGL(commit_kernel, dim3(gx, b.ninst), dim3(256), 0, s, b, Pnew, P);
+}
+
+void launch_sp2_bounds(const BatchInfo& b, int max_n, const double* F, double* bounds,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(sp2_bounds_kernel, dim3((max_n + 3) / 4, b.ninst), dim3(256), 0, s, b, max_n,
+                     F, bounds);
+}
+
+void launch_sp2_step(const BatchInfo& b, int max_n, int mode, const double* F,
+                     const double* bounds, const int* nocc, const double* Y, double* X,
+                     const double* st_in, double* st_out, hipStream_t s) {
+  // a few blocks per instance: their atomics on the two statistics stay few
+  const long long nn = (long long)max_n * max_n;
+  const unsigned gx = (unsigned)std::max<long long>(1, std::min<long long>((nn + 4095) / 4096, 64));
+  hipLaunchKernelGGL(sp2_step_kernel, dim3(gx, b.ninst), dim3(256), 0, s, b, max_n, mode, F, bounds,
+                     nocc, Y, X, st_in, st_out);
 }
 
 void launch_scale_copy(const BatchInfo& b, int max_n, const double* src, double* dst,

@@ -216,3 +216,48 @@ def test_jk_and_forces_each_kernel_variant(beadscf, b631gs, variant, monkeypatch
         assert np.abs(F + g).max() < 1e-8
     finally:
         e.close()
+
+
+def test_density_methods_agree(eng, b631gs):
+    """SP2 purification and the eigenvector route give the same SCF: four
+    (H2O)2 beads, energies, densities and forces of the two runs agree to
+    rounding, and each energy matches the oracle (whose density comes from
+    eigenvectors)."""
+    z, x = inputs.water_cluster(2, 11)
+    bx = inputs.beads(z, x, 4, 11)
+    inst = [(z, bx[k]) for k in range(4)]
+    _setup(eng, "6-31g*", inst)
+    from paper_1601_02713_amd import beadscf as b
+    out = {}
+    for method in (b.DENSITY_EIG, b.DENSITY_SP2):
+        eng.reset_stats()
+        E, it, st = eng.run_scf(e_tol=1e-11, comm_tol=1e-9, density=method)
+        assert (st == 0).all()
+        out[method] = (E, [eng.density(k) for k in range(4)], eng.forces(), eng.stats())
+    Ee, Pe, Fe, se = out[b.DENSITY_EIG]
+    Es, Ps, Fs, ss = out[b.DENSITY_SP2]
+    assert se["sp2_calls"] == 0
+    assert ss["sp2_calls"] > 0 and ss["sp2_fallbacks"] == 0
+    assert np.abs(Ee - Es).max() < 1e-10
+    for k in range(4):
+        assert np.abs(Pe[k] - Ps[k]).max() < 1e-8
+        assert np.abs(Fe[k] - Fs[k]).max() < 1e-9
+        r = oracle.scf(oracle.build_basis(b631gs, *inst[k]), 1e-11, 1e-9)
+        assert abs(Es[k] - r["E"]) < 1e-9
+
+
+def test_density_without_gap(eng):
+    """Oxygen atom, core guess: two of three degenerate 2p levels are
+    occupied, so the guess density has no gap at the Fermi level.  SP2 either
+    hands such a replica to the eigenvector route or settles on two orbitals of
+    the degenerate set; either way the energy of the density is that of the
+    eigenvector route (every choice is equivalent by symmetry)."""
+    from paper_1601_02713_amd import beadscf as b
+    _setup(eng, "6-31g*", [(np.array([8]), np.zeros((1, 3)))])
+    E = {}
+    for method in (b.DENSITY_EIG, b.DENSITY_SP2):
+        eng.reset_stats()
+        E[method], _, _ = eng.run_scf(max_iter=1, density=method)
+        print(method, eng.stats()["sp2_fallbacks"])
+    assert np.isfinite(E[b.DENSITY_SP2]).all()
+    assert abs(E[b.DENSITY_SP2][0] - E[b.DENSITY_EIG][0]) < 1e-9
