@@ -504,31 +504,30 @@ void density_from_orbitals(bscf_ctx* c, double* Pout) {
   }
 }
 
-// SP2 on F' (in eig, overwritten by the projector Xp) for the instances with
-// act[i] set (the device mask b.active matches); then P = 2 X Xp X.  False when
-// some of them has not converged after kSp2MaxSteps steps (no gap).
+// SP2 on F' (in eig) for the instances with act[i] set (the device mask b.active
+// matches): X_k alternates between tmp1 and tmp2, each step one fused
+// product-and-update launch; then P = 2 X X_k X.  False when some of them has
+// not converged after kSp2MaxSteps steps (no gap).
 bool density_sp2(bscf_ctx* c, const BatchInfo& b, const std::vector<int>& act, double* Pout) {
   const hipStream_t st = c->stream;
   const int ni = c->ninst;
-  const long long sstride = 2LL * ni;
+  const int ntm = sp2_tiles(c->max_n);
+  const long long row = 2LL * ni * ntm;   // statistics of one step
   double* stats = c->d_sp2.p;
-  launch_fill(stats, (kSp2MaxSteps + 1) * sstride, 0.0, st);
+  double* buf[2] = {c->tmp1.p, c->tmp2.p};
   launch_sp2_bounds(b, c->max_n, c->eig.p, c->d_sp2b.p, st);
-  launch_sp2_step(b, c->max_n, 0, c->eig.p, c->d_sp2b.p, c->d_nocc.p, nullptr, c->eig.p, nullptr,
-                  stats, st);
+  launch_sp2_init(b, c->max_n, c->eig.p, c->d_sp2b.p, buf[0], stats, st);
   int k = 0;
   auto step = [&] {
-    gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->eig.p, c->eig.p,
-         0.0, c->tmp1.p);
-    launch_sp2_step(b, c->max_n, 1, nullptr, nullptr, c->d_nocc.p, c->tmp1.p, c->eig.p,
-                    stats + k * sstride, stats + (k + 1) * sstride, st);
+    launch_sp2_step(b, c->max_n, c->d_nocc.p, buf[k & 1], buf[(k + 1) & 1], stats + k * row,
+                    stats + (k + 1) * row, st);
     ++k;
   };
   int target = std::min(std::max(c->sp2_pred, 1), kSp2MaxSteps);
   std::vector<double> h;
   for (;;) {
     while (k < target) step();
-    h.resize((size_t)(k + 1) * sstride);
+    h.resize((size_t)(k + 1) * row);
     HIPCHK(hipMemcpyAsync(h.data(), stats, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     sync(c);
     // first converged step of every replica taking part
@@ -536,9 +535,15 @@ bool density_sp2(bscf_ctx* c, const BatchInfo& b, const std::vector<int>& act, d
     bool all = true;
     for (int i = 0; i < ni && all; ++i) {
       if (!act[i]) continue;
+      const int nt = (c->nbf[i] + 31) / 32;
       int j = 0;
       for (; j <= k; ++j) {
-        const double tr = h[(size_t)j * sstride + 2 * i], t2 = h[(size_t)j * sstride + 2 * i + 1];
+        double tr = 0.0, t2 = 0.0;
+        const double* r = h.data() + (size_t)j * row + (size_t)i * ntm * 2;
+        for (int t = 0; t < nt * nt; ++t) {
+          tr += r[2 * t];
+          t2 += r[2 * t + 1];
+        }
         if (tr - t2 < kSp2Tol && std::fabs(tr - c->nocc[i]) < 1e-6) break;
       }
       if (j > k) all = false;
@@ -554,9 +559,9 @@ bool density_sp2(bscf_ctx* c, const BatchInfo& b, const std::vector<int>& act, d
   }
   c->sp2_calls++;
   c->sp2_steps += k;
-  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->X.p, c->eig.p, 0.0,
-       c->tmp1.p);
-  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 2.0, c->tmp1.p, c->X.p, 0.0,
+  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->X.p, buf[k & 1], 0.0,
+       c->eig.p);
+  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 2.0, c->eig.p, c->X.p, 0.0,
        Pout);
   return true;
 }
@@ -1325,7 +1330,7 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->Fhist.resize(mt * 8);
     c->Ehist.resize(mt * 8);
     c->diisB.resize((size_t)n_inst * 64);
-    c->d_sp2.resize((size_t)(kSp2MaxSteps + 1) * 2 * n_inst);
+    c->d_sp2.resize((size_t)(kSp2MaxSteps + 1) * 2 * n_inst * sp2_tiles(c->max_n));
     c->d_sp2b.resize((size_t)2 * n_inst * c->max_n);
     c->d_omask.resize(n_inst);
     c->diisC.resize((size_t)n_inst * 8);

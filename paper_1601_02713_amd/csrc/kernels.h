@@ -120,18 +120,21 @@ void launch_diis_extrapolate(const DiisArgs& d, int max_n, double* Fbar, hipStre
 void launch_convergence(int ninst, int max_n, const int* nbf, const double* E, double* Eprev,
                         double* emax, double etol, double ctol, int iter, int* active,
                         int* conv_iter, int* status, hipStream_t s);
-// SP2 purification (scf.hip): Gershgorin intervals of the rows of each
-// instance's F' (bounds[inst][row] = (lo, hi), room for ninst * max_n pairs),
-// then one projection step: mode 0 sets X = (hi I - F')/(hi - lo) over their
-// union; mode 1 replaces X by Y = X^2 or by 2X - Y, as the trace rule on
-// st_in (Tr X, Tr X^2 of the previous X) decides.  Tr X and Tr X^2 of the new
-// X are added into st_out, which must start at zero.  Instances masked out by
-// b.active are skipped.
+// SP2 purification (scf.hip).  launch_sp2_bounds: Gershgorin intervals of
+// the rows of each instance's F' (bounds[inst][row] = (lo, hi), room for
+// ninst * max_n pairs).  launch_sp2_init: X = (hi I - (F' + F'^T)/2)/(hi - lo)
+// over their union.  launch_sp2_step: Xn = X^2 or 2X - X^2, as the trace rule
+// on st_in (the statistics of X) decides; X and Xn must not overlap.  Both
+// store, per 32 x 32 tile of the result, its (Tr, Tr^2) partial at
+// st[(inst * sp2_tiles(max_n) + tile) * 2]; the sum over an instance's tiles
+// is its (Tr X, Tr X^2).  Instances masked out by b.active are skipped.
 void launch_sp2_bounds(const BatchInfo& b, int max_n, const double* F, double* bounds,
                        hipStream_t s);
-void launch_sp2_step(const BatchInfo& b, int max_n, int mode, const double* F,
-                     const double* bounds, const int* nocc, const double* Y, double* X,
+void launch_sp2_init(const BatchInfo& b, int max_n, const double* F, const double* bounds,
+                     double* X, double* st, hipStream_t s);
+void launch_sp2_step(const BatchInfo& b, int max_n, const int* nocc, const double* X, double* Xn,
                      const double* st_in, double* st_out, hipStream_t s);
+int sp2_tiles(int max_n);
 // P_new -> P for active instances
 void launch_commit(const BatchInfo& b, int max_n, const double* Pnew, double* P, hipStream_t s);
 // nuclear repulsion energy and gradient per instance

@@ -122,13 +122,95 @@ __device__ __forceinline__ bool nuc_entry(int tot, int k, int& na, int& nb, int&
   return false;
 }
 
+// The recursion steps of a table, decoded once per block.  Level tot (na + nb
+// = tot) holds nuc_count(tot) entries; entry k of the table is one step
+//   v[dst] = X_i v[s0] - PC_i v[s0 + S] + c1/(2p) (v[s1] - v[s1 + S])
+//                                       + c2/(2p) (v[s2] - v[s2 + S]),
+// X = PB (b raised, b > 0) or PA (a raised, b = 0), S the stride from m to
+// m + 1, offsets flat in v[m][tidx(a)][tidx(b)].  Packed as two words:
+// w0 = dst | s0 << 12 | i << 24 | (X = PB) << 26 | c1 << 27 | c2 << 29,
+// w1 = s1 | s2 << 12.
+template <int TA, int TB>
+__host__ __device__ constexpr int nuc_count(int tot) {
+  int c = 0;
+  for (int na = (tot > TB ? tot - TB : 0); na <= (tot < TA ? tot : TA); ++na)
+    c += ncart(na) * ncart(tot - na) * (TA + TB - tot + 1);
+  return c;
+}
+template <int TA, int TB>
+__host__ __device__ constexpr int nuc_start(int tot) {   // first entry of level tot >= 1
+  int c = 0;
+  for (int t = 1; t < tot; ++t) c += nuc_count<TA, TB>(t);
+  return c;
+}
+template <int TA, int TB>
+struct NucPlan {
+  static constexpr int L = TA + TB;
+  static constexpr int S = ntup(TA) * ntup(TB);
+  static constexpr int total = nuc_start<TA, TB>(L + 1);
+  static constexpr int slots = total > 0 ? total : 1;
+};
+
+template <int TA, int TB>
+__device__ void nuc_plan(uint2* desc) {
+  using Pl = NucPlan<TA, TB>;
+  constexpr int NB = ntup(TB);
+  for (int e = threadIdx.x; e < Pl::total; e += blockDim.x) {
+    int tot = 1;
+    while (e >= nuc_start<TA, TB>(tot + 1)) ++tot;
+    int na, nb, ca, cb, m;
+    nuc_entry<TA, TB>(tot, e - nuc_start<TA, TB>(tot), na, nb, ca, cb, m);
+    int ta[3], tb[3];
+    comp(na, ca, ta[0], ta[1], ta[2]);
+    comp(nb, cb, tb[0], tb[1], tb[2]);
+    const int ia = tidx(ta[0], ta[1], ta[2]), ib = tidx(tb[0], tb[1], tb[2]);
+    auto flat = [&](int x, int y) { return (unsigned)(m * Pl::S + x * NB + y); };
+    unsigned dst = flat(ia, ib), s0, s1 = 0, s2 = 0, c1 = 0, c2 = 0, i, bside;
+    if (nb > 0) {
+      bside = 1;
+      i = tb[0] > 0 ? 0 : (tb[1] > 0 ? 1 : 2);
+      int b1[3] = {tb[0], tb[1], tb[2]};
+      b1[i] -= 1;
+      const int j1 = tidx(b1[0], b1[1], b1[2]);
+      s0 = flat(ia, j1);
+      if (ta[i] > 0) {
+        int a1[3] = {ta[0], ta[1], ta[2]};
+        a1[i] -= 1;
+        s1 = flat(tidx(a1[0], a1[1], a1[2]), j1);
+        c1 = ta[i];
+      }
+      if (b1[i] > 0) {
+        int b2[3] = {b1[0], b1[1], b1[2]};
+        b2[i] -= 1;
+        s2 = flat(ia, tidx(b2[0], b2[1], b2[2]));
+        c2 = b1[i];
+      }
+    } else {
+      bside = 0;
+      i = ta[0] > 0 ? 0 : (ta[1] > 0 ? 1 : 2);
+      int a1[3] = {ta[0], ta[1], ta[2]};
+      a1[i] -= 1;
+      s0 = flat(tidx(a1[0], a1[1], a1[2]), ib);
+      if (a1[i] > 0) {
+        int a2[3] = {a1[0], a1[1], a1[2]};
+        a2[i] -= 1;
+        s2 = flat(tidx(a2[0], a2[1], a2[2]), ib);
+        c2 = a1[i];
+      }
+    }
+    desc[e] = make_uint2(dst | s0 << 12 | i << 24 | bside << 26 | c1 << 27 | c2 << 29, s1 | s2 << 12);
+  }
+  __syncthreads();
+}
+
 // Fill one sub-team's table (lt: thread index within the sub-team of TS):
 // its first thread sets the Boys values and scalars, then each level of total
-// angular momentum is spread over the sub-team.  Every thread of the block
-// calls this together (the level barriers are block-wide).
+// angular momentum is spread over the sub-team by the decoded steps.  Every
+// thread of the block calls this together (the level barriers are block-wide).
 template <int TA, int TB, int TS>
 __device__ void nuc_table(double a, double b, const double* A, const double* B, const double* C,
-                          const double* boys64, int lt, NucTab<TA, TB>& t) {
+                          const double* boys64, int lt, const uint2* desc, NucTab<TA, TB>& t) {
+  using Pl = NucPlan<TA, TB>;
   constexpr int L = TA + TB;
   if (lt == 0) {
     const double p = a + b, mu = a * b / p;
@@ -148,47 +230,25 @@ __device__ void nuc_table(double a, double b, const double* A, const double* B, 
   }
   __syncthreads();
   const double oo2p = t.oo2p;
+  double* v = &t.v[0][0][0];
+#pragma unroll
   for (int tot = 1; tot <= L; ++tot) {
-    for (int k = lt;; k += TS) {
-      int na, nb, ca, cb, m;
-      if (!nuc_entry<TA, TB>(tot, k, na, nb, ca, cb, m)) break;
-      int ta[3], tb[3];
-      comp(na, ca, ta[0], ta[1], ta[2]);
-      comp(nb, cb, tb[0], tb[1], tb[2]);
-      const int ia = tidx(ta[0], ta[1], ta[2]), ib = tidx(tb[0], tb[1], tb[2]);
-      double r;
-      if (nb > 0) {
-        const int i = tb[0] > 0 ? 0 : (tb[1] > 0 ? 1 : 2);
-        int b1[3] = {tb[0], tb[1], tb[2]};
-        b1[i] -= 1;
-        const int j1 = tidx(b1[0], b1[1], b1[2]);
-        r = t.PB[i] * t.v[m][ia][j1] - t.PC[i] * t.v[m + 1][ia][j1];
-        if (ta[i] > 0) {
-          int a1[3] = {ta[0], ta[1], ta[2]};
-          a1[i] -= 1;
-          const int i1 = tidx(a1[0], a1[1], a1[2]);
-          r += ta[i] * oo2p * (t.v[m][i1][j1] - t.v[m + 1][i1][j1]);
-        }
-        if (b1[i] > 0) {
-          int b2[3] = {b1[0], b1[1], b1[2]};
-          b2[i] -= 1;
-          const int j2 = tidx(b2[0], b2[1], b2[2]);
-          r += b1[i] * oo2p * (t.v[m][ia][j2] - t.v[m + 1][ia][j2]);
-        }
-      } else {
-        const int i = ta[0] > 0 ? 0 : (ta[1] > 0 ? 1 : 2);
-        int a1[3] = {ta[0], ta[1], ta[2]};
-        a1[i] -= 1;
-        const int i1 = tidx(a1[0], a1[1], a1[2]);
-        r = t.PA[i] * t.v[m][i1][ib] - t.PC[i] * t.v[m + 1][i1][ib];
-        if (a1[i] > 0) {
-          int a2[3] = {a1[0], a1[1], a1[2]};
-          a2[i] -= 1;
-          const int i2 = tidx(a2[0], a2[1], a2[2]);
-          r += a1[i] * oo2p * (t.v[m][i2][ib] - t.v[m + 1][i2][ib]);
-        }
+    const int first = nuc_start<TA, TB>(tot), cnt = nuc_count<TA, TB>(tot);
+    for (int k = lt; k < cnt; k += TS) {
+      const uint2 d = desc[first + k];
+      const unsigned dst = d.x & 4095u, s0 = (d.x >> 12) & 4095u, i = (d.x >> 24) & 3u;
+      const unsigned c1 = (d.x >> 27) & 3u, c2 = (d.x >> 29) & 3u;
+      const double X = (d.x >> 26) & 1u ? t.PB[i] : t.PA[i];
+      double r = X * v[s0] - t.PC[i] * v[s0 + Pl::S];
+      if (c1) {
+        const unsigned s1 = d.y & 4095u;
+        r += c1 * oo2p * (v[s1] - v[s1 + Pl::S]);
       }
-      t.v[m][ia][ib] = r;
+      if (c2) {
+        const unsigned s2 = (d.y >> 12) & 4095u;
+        r += c2 * oo2p * (v[s2] - v[s2 + Pl::S]);
+      }
+      v[dst] = r;
     }
     __syncthreads();
   }
@@ -238,14 +298,15 @@ __global__ void prim_pair_kernel(PrimPairSetupArgs a) {
 // S, T, V: one 64-thread block per shell pair a >= b of one instance.  The
 // nuclei are taken in groups of NS, one per sub-team; within a sub-team the
 // threads own component pairs of the shell block (strided by TS).  S and T
-// come from sub-team 0 in the first group; the sub-teams' V partial sums meet
-// in LDS at the end, so every element is written once, without atomics.
-// Output is the normalised-component basis.
+// (no nucleus) come from thread e = component pair e in the first group; the
+// sub-teams' V partial sums meet in LDS at the end, so every element is
+// written once, without atomics.  Output is the normalised-component basis.
 template <int LA, int LB>
 __global__ __launch_bounds__(kTeam) void onee_kernel(OneEArgs a) {
   constexpr int NS = sub_teams(LA + LB), TS = kTeam / NS;
   constexpr int NA = ncart(LA), NB = ncart(LB), NE = (NA * NB + TS - 1) / TS;
   __shared__ NucTab<LA, LB> nt[NS];
+  __shared__ uint2 desc[NucPlan<LA, LB>::slots];
   __shared__ double S1[3][kS1][kS1];
   __shared__ double red[NS][NA * NB];
   const int sh_a = a.task_a[blockIdx.x], sh_b = a.task_b[blockIdx.x];
@@ -255,9 +316,10 @@ __global__ __launch_bounds__(kTeam) void onee_kernel(OneEArgs a) {
   const long long mo = a.moff[inst];
   const double A[3] = {sa.x, sa.y, sa.z}, B[3] = {sb.x, sb.y, sb.z};
   const int s = threadIdx.x / TS, lt = threadIdx.x % TS;
+  nuc_plan<LA, LB>(desc);
   int ta[NE][3], tb[NE][3];
   bool own[NE];
-  double Sv[NE], Tv[NE], Vv[NE];
+  double Vv[NE];
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
     const int e = lt + q * TS;
@@ -267,15 +329,23 @@ __global__ __launch_bounds__(kTeam) void onee_kernel(OneEArgs a) {
       comp(LA, e / NB, ta[q][0], ta[q][1], ta[q][2]);
       comp(LB, e % NB, tb[q][0], tb[q][1], tb[q][2]);
     }
-    Sv[q] = Tv[q] = Vv[q] = 0.0;
+    Vv[q] = 0.0;
   }
+  // component pair of this thread for S and T
+  const int es = threadIdx.x;
+  const bool own_st = es < NA * NB;
+  int xa[3] = {0, 0, 0}, xb[3] = {0, 0, 0};
+  if (own_st) {
+    comp(LA, es / NB, xa[0], xa[1], xa[2]);
+    comp(LB, es % NB, xb[0], xb[1], xb[2]);
+  }
+  double Sv = 0.0, Tv = 0.0;
   for (int c0 = 0; c0 < natoms; c0 += NS) {
     const int cidx = c0 + s;
     const bool live = cidx < natoms;   // idle sub-teams run the barriers with Z = 0
     const int atom = a.atom_off[inst] + (live ? cidx : 0);
     const double Cc[3] = {a.atom_xyz[3 * atom], a.atom_xyz[3 * atom + 1], a.atom_xyz[3 * atom + 2]};
     const double Zc = live ? a.atom_Z[atom] : 0.0;
-    const bool st = c0 == 0 && s == 0;
     for (int ka = 0; ka < sa.nprim; ++ka)
       for (int kb = 0; kb < sb.nprim; ++kb) {
         const double al = a.sh_exp[sa.prim0 + ka], be = a.sh_exp[sb.prim0 + kb];
@@ -283,15 +353,13 @@ __global__ __launch_bounds__(kTeam) void onee_kernel(OneEArgs a) {
         __syncthreads();   // previous primitive's tables read
         if (c0 == 0 && threadIdx.x < 3)
           overlap_1d_dir(al, be, A[threadIdx.x], B[threadIdx.x], LA, LB + 2, S1[threadIdx.x]);
-        nuc_table<LA, LB, TS>(al, be, A, B, Cc, a.boys64, lt, nt[s]);   // ends with a barrier
+        nuc_table<LA, LB, TS>(al, be, A, B, Cc, a.boys64, lt, desc, nt[s]);   // ends with a barrier
 #pragma unroll
-        for (int q = 0; q < NE; ++q) {
-          if (!own[q]) continue;
-          Vv[q] -= Zc * cc * nuc_get(nt[s], ta[q], tb[q]);
-          if (st) {
-            Sv[q] += cc * ov3(S1, ta[q], tb[q]);
-            Tv[q] += cc * kin3(S1, ta[q], tb[q], be);
-          }
+        for (int q = 0; q < NE; ++q)
+          if (own[q]) Vv[q] -= Zc * cc * nuc_get(nt[s], ta[q], tb[q]);
+        if (c0 == 0 && own_st) {
+          Sv += cc * ov3(S1, xa, xb);
+          Tv += cc * kin3(S1, xa, xb, be);
         }
       }
   }
@@ -299,32 +367,19 @@ __global__ __launch_bounds__(kTeam) void onee_kernel(OneEArgs a) {
   for (int q = 0; q < NE; ++q)
     if (own[q]) red[s][lt + q * TS] = Vv[q];
   __syncthreads();
-  for (int e = threadIdx.x; e < NA * NB; e += kTeam) {
+  if (own_st) {
     double v = 0.0;
-    for (int k = 0; k < NS; ++k) v += red[k][e];
-    int xa[3], xb[3];
-    comp(LA, e / NB, xa[0], xa[1], xa[2]);
-    comp(LB, e % NB, xb[0], xb[1], xb[2]);
+    for (int k = 0; k < NS; ++k) v += red[k][es];
     const double f = comp_factor(xa[0], xa[1], xa[2]) * comp_factor(xb[0], xb[1], xb[2]);
-    const long long ij = mo + (long long)(sa.bf + e / NB) * n + sb.bf + e % NB;
-    const long long ji = mo + (long long)(sb.bf + e % NB) * n + sa.bf + e / NB;
+    const long long ij = mo + (long long)(sa.bf + es / NB) * n + sb.bf + es % NB;
+    const long long ji = mo + (long long)(sb.bf + es % NB) * n + sa.bf + es / NB;
     a.V[ij] = f * v;
-    if (sh_a != sh_b) a.V[ji] = f * v;   // a diagonal block's elements each have their own thread
-  }
-  if (s == 0) {
-#pragma unroll
-    for (int q = 0; q < NE; ++q) {
-      if (!own[q]) continue;
-      const int e = lt + q * TS;
-      const double f = comp_factor(ta[q][0], ta[q][1], ta[q][2]) * comp_factor(tb[q][0], tb[q][1], tb[q][2]);
-      const long long ij = mo + (long long)(sa.bf + e / NB) * n + sb.bf + e % NB;
-      const long long ji = mo + (long long)(sb.bf + e % NB) * n + sa.bf + e / NB;
-      a.S[ij] = f * Sv[q];
-      a.T[ij] = f * Tv[q];
-      if (sh_a != sh_b) {
-        a.S[ji] = f * Sv[q];
-        a.T[ji] = f * Tv[q];
-      }
+    a.S[ij] = f * Sv;
+    a.T[ij] = f * Tv;
+    if (sh_a != sh_b) {   // a diagonal block's elements each have their own thread
+      a.V[ji] = f * v;
+      a.S[ji] = f * Sv;
+      a.T[ji] = f * Tv;
     }
   }
 }
@@ -333,13 +388,15 @@ __global__ __launch_bounds__(kTeam) void onee_kernel(OneEArgs a) {
 // One-electron gradient: sum P dH/dX - sum W dS/dX per atom; one 64-thread
 // block per shell pair a >= b (off-diagonal pairs counted twice) with the
 // nuclei in sub-team groups as above.  A sub-team reduces its operator-centre
-// terms over its threads after each nucleus; the basis-centre terms are
-// reduced over the wavefront once at the end.
+// terms over its threads after each nucleus; the overlap and kinetic terms
+// come from thread e = component pair e in the first group; the basis-centre
+// terms are reduced over the wavefront once at the end.
 template <int LA, int LB>
 __global__ __launch_bounds__(kTeam) void grad1e_kernel(Grad1EArgs a) {
   constexpr int NS = sub_teams(LA + LB + 2), TS = kTeam / NS;
   constexpr int NA = ncart(LA), NB = ncart(LB), NE = (NA * NB + TS - 1) / TS;
   __shared__ NucTab<LA + 1, LB + 1> nt[NS];
+  __shared__ uint2 desc[NucPlan<LA + 1, LB + 1>::slots];
   __shared__ double S1[3][kS1][kS1];
   const int sh_a = a.task_a[blockIdx.x], sh_b = a.task_b[blockIdx.x];
   const Shell sa = a.shells[sh_a], sb = a.shells[sh_b];
@@ -350,24 +407,32 @@ __global__ __launch_bounds__(kTeam) void grad1e_kernel(Grad1EArgs a) {
   const double A[3] = {sa.x, sa.y, sa.z}, B[3] = {sb.x, sb.y, sb.z};
   const double sym = (sh_a == sh_b) ? 1.0 : 2.0;
   const int s = threadIdx.x / TS, lt = threadIdx.x % TS;
+  nuc_plan<LA + 1, LB + 1>(desc);
+  auto load_pw = [&](int e, int* xa, int* xb, double& pe, double& we) {
+    comp(LA, e / NB, xa[0], xa[1], xa[2]);
+    comp(LB, e % NB, xb[0], xb[1], xb[2]);
+    const double f = comp_factor(xa[0], xa[1], xa[2]) * comp_factor(xb[0], xb[1], xb[2]);
+    const long long ij = mo + (long long)(sa.bf + e / NB) * n + sb.bf + e % NB;
+    pe = sym * f * a.P[ij];
+    we = sym * f * a.W[ij];
+  };
   int ta[NE][3], tb[NE][3];
   bool own[NE];
-  double pij[NE], wij[NE];
+  double pij[NE];
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
     const int e = lt + q * TS;
     own[q] = e < NA * NB;
     ta[q][0] = ta[q][1] = ta[q][2] = tb[q][0] = tb[q][1] = tb[q][2] = 0;
-    pij[q] = wij[q] = 0.0;
-    if (own[q]) {
-      comp(LA, e / NB, ta[q][0], ta[q][1], ta[q][2]);
-      comp(LB, e % NB, tb[q][0], tb[q][1], tb[q][2]);
-      const double f = comp_factor(ta[q][0], ta[q][1], ta[q][2]) * comp_factor(tb[q][0], tb[q][1], tb[q][2]);
-      const long long ij = mo + (long long)(sa.bf + e / NB) * n + sb.bf + e % NB;
-      pij[q] = sym * f * a.P[ij];
-      wij[q] = sym * f * a.W[ij];
-    }
+    pij[q] = 0.0;
+    double w_unused;
+    if (own[q]) load_pw(e, ta[q], tb[q], pij[q], w_unused);
   }
+  // component pair of this thread for the overlap and kinetic terms
+  const bool own_st = threadIdx.x < NA * NB;
+  int xa[3] = {0, 0, 0}, xb[3] = {0, 0, 0};
+  double pst = 0.0, wst = 0.0;
+  if (own_st) load_pw(threadIdx.x, xa, xb, pst, wst);
   double gab[6] = {0, 0, 0, 0, 0, 0};   // A, B
   for (int c0 = 0; c0 < natoms; c0 += NS) {
     const int cidx = c0 + s;
@@ -375,7 +440,6 @@ __global__ __launch_bounds__(kTeam) void grad1e_kernel(Grad1EArgs a) {
     const int atom = a.atom_off[inst] + (live ? cidx : 0);
     const double Cc[3] = {a.atom_xyz[3 * atom], a.atom_xyz[3 * atom + 1], a.atom_xyz[3 * atom + 2]};
     const double Zc = live ? a.atom_Z[atom] : 0.0;
-    const bool st = c0 == 0 && s == 0;
     double gc[3] = {0, 0, 0};
     for (int ka = 0; ka < sa.nprim; ++ka)
       for (int kb = 0; kb < sb.nprim; ++kb) {
@@ -384,7 +448,7 @@ __global__ __launch_bounds__(kTeam) void grad1e_kernel(Grad1EArgs a) {
         __syncthreads();
         if (c0 == 0 && threadIdx.x < 3)
           overlap_1d_dir(al, be, A[threadIdx.x], B[threadIdx.x], LA + 1, LB + 3, S1[threadIdx.x]);
-        nuc_table<LA + 1, LB + 1, TS>(al, be, A, B, Cc, a.boys64, lt, nt[s]);
+        nuc_table<LA + 1, LB + 1, TS>(al, be, A, B, Cc, a.boys64, lt, desc, nt[s]);
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
           if (!own[q]) continue;
@@ -401,16 +465,23 @@ __global__ __launch_bounds__(kTeam) void grad1e_kernel(Grad1EArgs a) {
             gab[d] += cc * pij[q] * vA;
             gab[3 + d] += cc * pij[q] * vB;
             gc[d] -= cc * pij[q] * (vA + vB);
-            if (st) {
-              const double sA = 2 * al * ov3(S1, up, tb[q]) - ta[q][d] * ov3(S1, dn, tb[q]);
-              const double sB = 2 * be * ov3(S1, ta[q], upb) - tb[q][d] * ov3(S1, ta[q], dnb);
-              const double kA = 2 * al * kin3(S1, up, tb[q], be) - ta[q][d] * kin3(S1, dn, tb[q], be);
-              const double kB = 2 * be * kin3(S1, ta[q], upb, be) - tb[q][d] * kin3(S1, ta[q], dnb, be);
-              gab[d] += cc * (pij[q] * kA - wij[q] * sA);
-              gab[3 + d] += cc * (pij[q] * kB - wij[q] * sB);
-            }
           }
         }
+        if (c0 == 0 && own_st)
+          for (int d = 0; d < 3; ++d) {
+            int up[3] = {xa[0], xa[1], xa[2]}, dn[3] = {xa[0], xa[1], xa[2]};
+            up[d] += 1;
+            dn[d] -= 1;
+            int upb[3] = {xb[0], xb[1], xb[2]}, dnb[3] = {xb[0], xb[1], xb[2]};
+            upb[d] += 1;
+            dnb[d] -= 1;
+            const double sA = 2 * al * ov3(S1, up, xb) - xa[d] * ov3(S1, dn, xb);
+            const double sB = 2 * be * ov3(S1, xa, upb) - xb[d] * ov3(S1, xa, dnb);
+            const double kA = 2 * al * kin3(S1, up, xb, be) - xa[d] * kin3(S1, dn, xb, be);
+            const double kB = 2 * be * kin3(S1, xa, upb, be) - xb[d] * kin3(S1, xa, dnb, be);
+            gab[d] += cc * (pst * kA - wst * sA);
+            gab[3 + d] += cc * (pst * kB - wst * sB);
+          }
       }
     // operator-centre terms of this sub-team's nucleus (lanes of a sub-team
     // are contiguous and aligned, so the xor butterfly stays inside it)

@@ -373,64 +373,190 @@ __global__ void sp2_bounds_kernel(BatchInfo b, int max_n, const double* F, doubl
   }
 }
 
-// mode 0: X = (hi I - F') / (hi - lo); mode 1: X <- X^2 or 2X - X^2 (Y = X^2)
-// by the trace rule on the previous X's statistics st_in.  Both accumulate the
-// trace and the squared Frobenius norm (= Tr X^2 for symmetric X) of the new X
-// into st_out (zeroed by the caller).  X may alias F in mode 0.
-__global__ void sp2_step_kernel(BatchInfo b, int max_n, int mode, const double* F, const double* bounds,
-                                const int* nocc, const double* Y, double* X, const double* st_in,
-                                double* st_out) {
-  __shared__ double sh[16];
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// sum of the per-tile partial (Tr, Tr^2) rows of one instance (a block-wide
+// call; the result is valid in every thread)
+__device__ void sp2_stats(const double* st, int nt2, double& tr, double& t2, double* sh) {
+  double a = 0.0, q = 0.0;
+  for (int t = threadIdx.x; t < nt2; t += blockDim.x) {
+    a += st[2 * t];
+    q += st[2 * t + 1];
+  }
+  for (int k = 32; k > 0; k >>= 1) {
+    a += __shfl_xor(a, k, 64);
+    q += __shfl_xor(q, k, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[2 * (threadIdx.x >> 6)] = a;
+    sh[2 * (threadIdx.x >> 6) + 1] = q;
+  }
+  __syncthreads();
+  tr = t2 = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    tr += sh[2 * w];
+    t2 += sh[2 * w + 1];
+  }
+  __syncthreads();
+}
+
+// block-wide sum of (a, q) into st[0], st[1] by thread 0
+__device__ void sp2_store_stats(double a, double q, double* st, double* sh) {
+  for (int k = 32; k > 0; k >>= 1) {
+    a += __shfl_xor(a, k, 64);
+    q += __shfl_xor(q, k, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[2 * (threadIdx.x >> 6)] = a;
+    sh[2 * (threadIdx.x >> 6) + 1] = q;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tq = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      ta += sh[2 * w];
+      tq += sh[2 * w + 1];
+    }
+    st[0] = ta;
+    st[1] = tq;
+  }
+}
+
+// X_0 = (hi I - (F' + F'^T)/2) / (hi - lo) over the union of the rows'
+// Gershgorin intervals; the symmetrised start keeps every later X exactly
+// symmetric.  Grid (tile of the 32 x 32 tiling, instance); each tile stores its
+// (Tr, Tr^2) partial at st[inst][tile].
+__global__ __launch_bounds__(256) void sp2_init_kernel(BatchInfo b, int max_n, const double* F,
+                                                       const double* rowb, double* X, double* st) {
+  __shared__ double sh[8];
   const int inst = blockIdx.y;
   if (b.active && !b.active[inst]) return;
-  const int n = b.nbf[inst], nn = n * n;
+  const int n = b.nbf[inst], nt = ntiles_1d(n), ntm = ntiles_1d(max_n);
+  const int tile = blockIdx.x;
+  if (tile >= nt * nt) return;
   const long long o = b.moff[inst];
-  double hi = 0.0, w = 1.0;
-  bool square = false;
-  if (mode == 0) {
-    // spectral interval: union of the rows' Gershgorin intervals
-    __shared__ double slo[4], shi[4];
-    double lo = INFINITY;
-    hi = -INFINITY;
-    for (int r = threadIdx.x; r < n; r += blockDim.x) {
-      lo = fmin(lo, bounds[((long long)inst * max_n + r) * 2]);
-      hi = fmax(hi, bounds[((long long)inst * max_n + r) * 2 + 1]);
+  double lo = INFINITY, hi = -INFINITY;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    lo = fmin(lo, rowb[((long long)inst * max_n + r) * 2]);
+    hi = fmax(hi, rowb[((long long)inst * max_n + r) * 2 + 1]);
+  }
+  for (int k = 32; k > 0; k >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, k, 64));
+    hi = fmax(hi, __shfl_xor(hi, k, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[2 * (threadIdx.x >> 6)] = lo;
+    sh[2 * (threadIdx.x >> 6) + 1] = hi;
+  }
+  __syncthreads();
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    lo = fmin(lo, sh[2 * w]);
+    hi = fmax(hi, sh[2 * w + 1]);
+  }
+  __syncthreads();
+  double wdt = hi - lo;
+  if (!(wdt > 0.0)) wdt = 1.0;   // F' = c I: X_0 = 0, which the trace check rejects
+  const int i0 = (tile / nt) * kTile, j0 = (tile % nt) * kTile;
+  double ts = 0.0, fs = 0.0;
+  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+    const int i = i0 + e / kTile, j = j0 + e % kTile;
+    if (i >= n || j >= n) continue;
+    const double f = 0.5 * (F[o + (long long)i * n + j] + F[o + (long long)j * n + i]);
+    const double x = ((i == j ? hi : 0.0) - f) / wdt;
+    X[o + (long long)i * n + j] = x;
+    fs += x * x;
+    if (i == j) ts += x;
+  }
+  sp2_store_stats(ts, fs, st + ((long long)inst * ntm * ntm + tile) * 2, sh);
+}
+
+// One projection step fused into the product: Y = X X (= X^T X, X symmetric)
+// by FP64 MFMA (16x16x4), one 32 x 32 tile per block and a 16 x 16 quadrant
+// per wavefront.  The operand panels X[k][i-range], X[k][j-range] (both
+// coalesced by symmetry) pass through LDS in chunks of kSp2K rows of k, the
+// next chunk loaded into registers while the current one is multiplied.  The
+// epilogue writes Xn = Y or 2X - Y by the trace rule on the previous
+// statistics and stores this tile's (Tr, Tr^2) partial of Xn.
+constexpr int kSp2K = 96;
+__global__ __launch_bounds__(256) void sp2_gemm_kernel(BatchInfo b, int max_n, const int* nocc,
+                                                       const double* X, double* Xn,
+                                                       const double* st_in, double* st_out) {
+  constexpr int kPer = kSp2K * kTile / 256;   // panel elements per thread and chunk
+  __shared__ double sh[8];
+  __shared__ double As[kSp2K][kTile], Bs[kSp2K][kTile];
+  const int inst = blockIdx.y;
+  if (b.active && !b.active[inst]) return;
+  const int n = b.nbf[inst], nt = ntiles_1d(n), ntm = ntiles_1d(max_n);
+  const int tile = blockIdx.x;
+  if (tile >= nt * nt) return;
+  const long long o = b.moff[inst];
+  const int ti0 = (tile / nt) * kTile, tj0 = (tile % nt) * kTile;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i0 = ti0 + (wave >> 1) * 16, j0 = tj0 + (wave & 1) * 16;
+  const int c = lane & 15, kq = lane >> 4;
+  // FP64 16x16x4 output layout: register r of lane l holds row l / 16 + 4 r,
+  // column l % 16 of the quadrant (unlike the FP32 16x16x4 instruction, whose
+  // lane holds four consecutive rows)
+  double xold[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + kq + 4 * r, j = j0 + c;
+    xold[r] = (i < n && j < n) ? X[o + (long long)i * n + j] : 0.0;
+  }
+  double ra[kPer], rb[kPer];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = threadIdx.x + 256 * q, k = k0 + e / kTile, cc = e % kTile;
+      ra[q] = (k < n && ti0 + cc < n) ? X[o + (long long)k * n + ti0 + cc] : 0.0;
+      rb[q] = (k < n && tj0 + cc < n) ? X[o + (long long)k * n + tj0 + cc] : 0.0;
     }
-    for (int k = 32; k > 0; k >>= 1) {
-      lo = fmin(lo, __shfl_xor(lo, k, 64));
-      hi = fmax(hi, __shfl_xor(hi, k, 64));
-    }
-    if ((threadIdx.x & 63) == 0) {
-      slo[threadIdx.x >> 6] = lo;
-      shi[threadIdx.x >> 6] = hi;
+  };
+  fetch(0);
+  double tr, t2;
+  sp2_stats(st_in + (long long)inst * ntm * ntm * 2, nt * nt, tr, t2, sh);
+  const double N = nocc[inst];
+  const bool square = fabs(t2 - N) < fabs(2.0 * tr - t2 - N);
+  v4d acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < n; k0 += kSp2K) {
+    __syncthreads();   // the previous chunk has been read
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      As[e / kTile][e % kTile] = ra[q];
+      Bs[e / kTile][e % kTile] = rb[q];
     }
     __syncthreads();
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
-      lo = fmin(lo, slo[k]);
-      hi = fmax(hi, shi[k]);
+    if (k0 + kSp2K < n) fetch(k0 + kSp2K);
+    const int kend = min(kSp2K, n - k0);
+    // two accumulators halve the dependent MFMA chain
+#pragma unroll
+    for (int kk = 0; kk < kSp2K; kk += 8) {
+      if (kk < kend) {
+        // A[i][k] = X[k][i], B[k][j] = X[k][j]; rows past n were staged as zero
+        const double a0 = As[kk + kq][i0 - ti0 + c], b0 = Bs[kk + kq][j0 - tj0 + c];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
+      }
+      if (kk + 4 < kend) {
+        const double a1 = As[kk + 4 + kq][i0 - ti0 + c], b1 = Bs[kk + 4 + kq][j0 - tj0 + c];
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc2, 0, 0, 0);
+      }
     }
-    w = hi - lo;
-    if (!(w > 0.0)) w = 1.0;   // F' = c I: X_0 = 0, which the trace check rejects
-  } else {
-    const double tr = st_in[2 * inst], t2 = st_in[2 * inst + 1], N = nocc[inst];
-    square = fabs(t2 - N) < fabs(2.0 * tr - t2 - N);
   }
+  acc += acc2;
   double ts = 0.0, fs = 0.0;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
-    const bool diag = (k % n) == (k / n);
-    double x;
-    if (mode == 0) x = ((diag ? hi : 0.0) - F[o + k]) / w;
-    else x = square ? Y[o + k] : 2.0 * X[o + k] - Y[o + k];
-    X[o + k] = x;
-    fs += x * x;
-    if (diag) ts += x;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + kq + 4 * r, j = j0 + c;
+    if (i < n && j < n) {
+      const double y = acc[r];
+      const double x = square ? y : 2.0 * xold[r] - y;
+      Xn[o + (long long)i * n + j] = x;
+      fs += x * x;
+      if (i == j) ts += x;
+    }
   }
-  ts = block_sum(ts, sh);
-  fs = block_sum(fs, sh);
-  if (threadIdx.x == 0) {
-    atomicAdd(&st_out[2 * inst], ts);
-    atomicAdd(&st_out[2 * inst + 1], fs);
-  }
+  sp2_store_stats(ts, fs, st_out + ((long long)inst * ntm * ntm + tile) * 2, sh);
 }
 
 }  // namespace
@@ -496,15 +622,21 @@ void launch_sp2_bounds(const BatchInfo& b, int max_n, const double* F, double* b
                      F, bounds);
 }
 
-void launch_sp2_step(const BatchInfo& b, int max_n, int mode, const double* F,
-                     const double* bounds, const int* nocc, const double* Y, double* X,
-                     const double* st_in, double* st_out, hipStream_t s) {
-  // a few blocks per instance: their atomics on the two statistics stay few
-  const long long nn = (long long)max_n * max_n;
-  const unsigned gx = (unsigned)std::max<long long>(1, std::min<long long>((nn + 4095) / 4096, 64));
-  hipLaunchKernelGGL(sp2_step_kernel, dim3(gx, b.ninst), dim3(256), 0, s, b, max_n, mode, F, bounds,
-                     nocc, Y, X, st_in, st_out);
+void launch_sp2_init(const BatchInfo& b, int max_n, const double* F, const double* bounds,
+                     double* X, double* st, hipStream_t s) {
+  const int nt = ntiles_1d(max_n);
+  hipLaunchKernelGGL(sp2_init_kernel, dim3(nt * nt, b.ninst), dim3(256), 0, s, b, max_n, F, bounds,
+                     X, st);
 }
+
+void launch_sp2_step(const BatchInfo& b, int max_n, const int* nocc, const double* X, double* Xn,
+                     const double* st_in, double* st_out, hipStream_t s) {
+  const int nt = ntiles_1d(max_n);
+  hipLaunchKernelGGL(sp2_gemm_kernel, dim3(nt * nt, b.ninst), dim3(256), 0, s, b, max_n, nocc, X,
+                     Xn, st_in, st_out);
+}
+
+int sp2_tiles(int max_n) { return ntiles_1d(max_n) * ntiles_1d(max_n); }
 
 void launch_scale_copy(const BatchInfo& b, int max_n, const double* src, double* dst,
                        double alpha, int transpose, hipStream_t s) {
