@@ -356,6 +356,28 @@ def gen_grad(la, lb, lc, ld):
         for nm, *_ in sets:
             code += con[nm]
         code += ["}", ""]
+        # per-centre forms: the sets of one centre, with only the recurrence
+        # nodes they need (used by classes whose six sets do not fit the lane's
+        # registers; three passes over the primitives, one per centre)
+        for X in "ABC":
+            grp = [st for st in sets if st[0][1] == X]
+            vx = VRR(0, 0, 0, 0)
+            acc_x = []
+            for nm, w, *_ in grp:
+                for kk, (e, f) in enumerate(targets[nm]):
+                    acc_x.append(f"  {nm}[{kk}] = fma({w or 'one'}, {vx.name(e, f, 0)}, {nm}[{kk}]);")
+            px = "".join(f", R* __restrict__ {st[0]}" for st in grp)
+            code += [f"// gradient VRR of class ({tag}), centre {X}"]
+            code += [ln.format(inl="__forceinline__", fn=f"gvrr{X}_{tag}", extra=px) for ln in sig]
+            code += ["  const R one = R(1);"] + ["  " + ln for ln in vx.lines] + acc_x + ["}", ""]
+            code += [f"// gradient contraction of class ({tag}), centre {X}",
+                     "template <typename R>",
+                     f"__device__ __forceinline__ void gcon{X}_{tag}({', '.join('const R* __restrict__ ' + st[0] for st in grp)},",
+                     "    const R ABx, const R ABy, const R ABz, const R CDx, const R CDy, const R CDz,",
+                     "    const double* __restrict__ G, double* __restrict__ g) {"]
+            for nm, *_ in grp:
+                code += con[nm]
+            code += ["}", ""]
         return sets, sizes, flops, cflops, "\n".join(code)
     code = []
     extra = (", const R ABx, const R ABy, const R ABz, const R CDx, const R CDy, const R CDz,"
@@ -405,6 +427,7 @@ def quartet_classes():
 
 LANE_E_MAX = 5   # one-lane-per-quartet Fock kernels up to this total L
 LANE_G_MAX = 4   # one-lane-per-quartet gradient kernels up to this total L
+SPLIT_GRAD_ACC = 120   # lane gradient classes with more accumulators run one pass per centre
 
 
 def coop_tu(la, lb, lc, ld):
@@ -550,10 +573,34 @@ def main(outdir):
         allsets = ["RA", "RB", "RC", "LA", "LB", "LC"]
         szs = ", ".join(f"N{s} = {sizes.get(s, 1)}" for s in allsets)
         arg = ", ".join(s for s in names)
+        split = sum(sizes.values()) > SPLIT_GRAD_ACC
+        def cargs(X):   # the per-centre functions' set arguments: S1 = raised, S2 = lowered
+            return "S1" + (", S2" if f"L{X}" in names else "")
+        vx = "\n".join(
+            f"    {'if' if k == 0 else 'else if'} constexpr (X == {k}) gvrr{X}_{tag}<R>(F, PAx, PAy, PAz, WPx, WPy, WPz, QCx, QCy, QCz, WQx, WQy, WQz, oo2p, oo2q, oo2pq, rho_p2, rho_q2, wa, wb, wc, {cargs(X)});"
+            for k, X in enumerate("ABC"))
+        cx = "\n".join(
+            f"    {'if' if k == 0 else 'else if'} constexpr (X == {k}) gcon{X}_{tag}<R>({cargs(X)}, ABx, ABy, ABz, CDx, CDy, CDz, G, g);"
+            for k, X in enumerate("ABC"))
         wrap = f"""struct ClsG{tag} {{
   static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld};
   static constexpr bool PRIM = false;
+  static constexpr bool SPLIT = {'true' if split else 'false'};   // one pass per centre
   static constexpr int {szs};
+  // centre X (0 = A, 1 = B, 2 = C): S1 = its raised set, S2 = its lowered set (if any)
+  template <int X, typename R>
+  __device__ static __forceinline__ void vrrx(const R* F, R PAx, R PAy, R PAz, R WPx, R WPy, R WPz,
+      R QCx, R QCy, R QCz, R WQx, R WQy, R WQz, R oo2p, R oo2q, R oo2pq, R rho_p2, R rho_q2,
+      R wa, R wb, R wc, R* S1, R* S2) {{
+    (void)S2;
+{vx}
+  }}
+  template <int X, typename R>
+  __device__ static __forceinline__ void conx(const R* S1, const R* S2, R ABx, R ABy, R ABz,
+      R CDx, R CDy, R CDz, const double* G, double* g) {{
+    (void)S2;
+{cx}
+  }}
   template <typename R>
   __device__ static __forceinline__ void vrr(const R* F, R PAx, R PAy, R PAz, R WPx, R WPy, R WPz,
       R QCx, R QCy, R QCz, R WQx, R WQy, R WQz, R oo2p, R oo2q, R oo2pq, R rho_p2, R rho_q2,

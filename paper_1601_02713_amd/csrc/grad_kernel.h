@@ -18,15 +18,65 @@
 
 namespace bscf {
 
-template <class CG>
-__device__ __forceinline__ void grad_block_body(const PrimPair* __restrict__ bp, int nb,
+// One centre's pass of a class whose six contracted sets do not fit a lane's
+// registers at once: the primitive loop again, accumulating only the raised
+// and lowered sets of centre X (0 = A, 1 = B, 2 = C), then their contraction.
+template <class CG, int X, class GF>
+__device__ __forceinline__ void grad_centre_pass(const PrimPair* __restrict__ bp, int nb,
+                                                 const PrimPair* __restrict__ kp, int nk, int ks,
+                                                 const double* AB, const double* CD,
+                                                 const double* __restrict__ tab64,
+                                                 const GF& gfill, double* g9) {
+  constexpr int L = CG::LA + CG::LB + CG::LC + CG::LD + 1;
+  constexpr int N1 = X == 0 ? CG::NRA : (X == 1 ? CG::NRB : CG::NRC);
+  constexpr int N2 = X == 0 ? CG::NLA : (X == 1 ? CG::NLB : CG::NLC);
+  using R = double;
+  R S1[N1], S2[N2];
+#pragma unroll
+  for (int k = 0; k < N1; ++k) S1[k] = 0;
+#pragma unroll
+  for (int k = 0; k < N2; ++k) S2[k] = 0;
+  for (int j = 0; j < nk; ++j) {
+    const PrimPair Q = kp[j * ks];
+    for (int i = 0; i < nb; ++i) {
+      const PrimPair B = bp[i];
+      const double pq = B.p + Q.p;
+      const double rpq = rsqrt(pq);
+      const double oopq = rpq * rpq;
+      const double rho = B.p * Q.p * oopq;
+      const double PQx = B.Px - Q.Px, PQy = B.Py - Q.Py, PQz = B.Pz - Q.Pz;
+      const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+      R F[L + 1];
+      boys_f64<L>(T, B.C * Q.C * rpq, tab64, F);
+      const double qf = Q.p * oopq, pf = B.p * oopq;
+      CG::template vrrx<X, R>(F, B.PAx, B.PAy, B.PAz, -qf * PQx, -qf * PQy, -qf * PQz, Q.PAx,
+                              Q.PAy, Q.PAz, pf * PQx, pf * PQy, pf * PQz, B.oo2p, Q.oo2p,
+                              0.5 * oopq, B.oo2p * qf, Q.oo2p * pf, 2.0 * B.alpha, 2.0 * B.beta,
+                              2.0 * Q.alpha, S1, S2);
+    }
+  }
+  double G[ncart(CG::LA) * ncart(CG::LB) * ncart(CG::LC) * ncart(CG::LD)];
+  gfill(G);
+  CG::template conx<X, R>(S1, S2, AB[0], AB[1], AB[2], CD[0], CD[1], CD[2], G, g9);
+}
+
+// Contracted-set forms (lane kernels): gfill(G) writes the quartet's density
+// factors, called right before each contraction so that they are not live
+// across the primitive loop.
+template <class CG, class GF>
+__device__ __forceinline__ void grad_block_lane(const PrimPair* __restrict__ bp, int nb,
                                                 const PrimPair* __restrict__ kp, int nk, int ks,
                                                 const double* AB, const double* CD,
                                                 const double* __restrict__ tab64,
-                                                const double* __restrict__ G, double* g9) {
+                                                const GF& gfill, double* g9) {
   constexpr int L = CG::LA + CG::LB + CG::LC + CG::LD + 1;
   using R = double;
-  if constexpr (!CG::PRIM) {
+  static_assert(!CG::PRIM, "lane gradient classes contract their sets");
+  if constexpr (CG::SPLIT) {
+    grad_centre_pass<CG, 0>(bp, nb, kp, nk, ks, AB, CD, tab64, gfill, g9);
+    grad_centre_pass<CG, 1>(bp, nb, kp, nk, ks, AB, CD, tab64, gfill, g9);
+    grad_centre_pass<CG, 2>(bp, nb, kp, nk, ks, AB, CD, tab64, gfill, g9);
+  } else {
     R RA[CG::NRA], RB[CG::NRB], RC[CG::NRC], LA[CG::NLA], LB[CG::NLB], LC[CG::NLC];
 #pragma unroll
     for (int k = 0; k < CG::NRA; ++k) RA[k] = 0;
@@ -59,7 +109,25 @@ __device__ __forceinline__ void grad_block_body(const PrimPair* __restrict__ bp,
                             2.0 * Q.alpha, RA, RB, RC, LA, LB, LC);
       }
     }
+    double G[ncart(CG::LA) * ncart(CG::LB) * ncart(CG::LC) * ncart(CG::LD)];
+    gfill(G);
     CG::template con<R>(RA, RB, RC, LA, LB, LC, AB[0], AB[1], AB[2], CD[0], CD[1], CD[2], G, g9);
+  }
+}
+
+template <class CG>
+__device__ __forceinline__ void grad_block_body(const PrimPair* __restrict__ bp, int nb,
+                                                const PrimPair* __restrict__ kp, int nk, int ks,
+                                                const double* AB, const double* CD,
+                                                const double* __restrict__ tab64,
+                                                const double* __restrict__ G, double* g9) {
+  constexpr int L = CG::LA + CG::LB + CG::LC + CG::LD + 1;
+  using R = double;
+  if constexpr (!CG::PRIM) {
+    grad_block_lane<CG>(bp, nb, kp, nk, ks, AB, CD, tab64, [&](double* Gd) {
+      for (int k = 0; k < ncart(CG::LA) * ncart(CG::LB) * ncart(CG::LC) * ncart(CG::LD); ++k)
+        Gd[k] = G[k];
+    }, g9);
   } else {
     for (int j = 0; j < nk; ++j) {
       const PrimPair Q = kp[j * ks];
@@ -157,31 +225,35 @@ __global__ __launch_bounds__(64) void grad_unit_kernel(GradArgs a) {
                        ((kid == bid) ? 1.0 : 2.0);
     const double fac = valid ? 0.5 * deg : 0.0;
     const int l0 = sc.bf, s0 = sd.bf;
-    double G[NOUT];
+    // density factors of the quartet (Coulomb and exchange terms)
+    auto gfill = [&](double* G) {
 #pragma unroll
-    for (int k = 0; k < NC; ++k)
+      for (int k = 0; k < NC; ++k)
 #pragma unroll
-      for (int l = 0; l < ND; ++l) {
-        const double pcd = a.Pk[(long long)(k * ND + l) * a.nk_total + pos];
+        for (int l = 0; l < ND; ++l) {
+          const double pcd = a.Pk[(long long)(k * ND + l) * a.nk_total + pos];
 #pragma unroll
-        for (int i = 0; i < NA; ++i)
+          for (int i = 0; i < NA; ++i)
 #pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            const double pab = Prow[i * n + n0 + j];
-            const double pac = Prow[i * n + l0 + k], pbd = Prow[(NA + j) * n + s0 + l];
-            const double pad = Prow[i * n + s0 + l], pbc = Prow[(NA + j) * n + l0 + k];
-            G[((i * NB + j) * NC + k) * ND + l] =
-                fac * (pab * pcd - 0.25 * (pac * pbd + pad * pbc));
-          }
-      }
+            for (int j = 0; j < NB; ++j) {
+              const double pab = Prow[i * n + n0 + j];
+              const double pac = Prow[i * n + l0 + k], pbd = Prow[(NA + j) * n + s0 + l];
+              const double pad = Prow[i * n + s0 + l], pbc = Prow[(NA + j) * n + l0 + k];
+              G[((i * NB + j) * NC + k) * ND + l] =
+                  fac * (pab * pcd - 0.25 * (pac * pbd + pad * pbc));
+            }
+        }
+    };
     double g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int2 kp = a.kpos[pos];
     if constexpr (CG::LA + CG::LB + CG::LC + CG::LD >= 5) {
+      double G[NOUT];
+      gfill(G);
       grad_block_outline<CG>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64,
                              G, g9);
     } else {
-      grad_block_body<CG>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64, G,
-                          g9);
+      grad_block_lane<CG>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64,
+                          gfill, g9);
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
