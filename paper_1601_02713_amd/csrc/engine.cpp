@@ -26,6 +26,7 @@
 #include <sstream>
 #include <stdexcept>
 #include <string>
+#include <future>
 #include <thread>
 #include <vector>
 
@@ -290,7 +291,14 @@ struct bscf_ctx {
   std::vector<int> atom_bf0, atom_nbf;   // per global atom: first basis function, count
   bool have_geom = false, have_scf = false;
   std::vector<double> Q;           // per pair
-  double work_tau = -1.0, work_split = -1.0;
+  double work_tau = -1.0, work_split = -1.0;   // parameters of the lists on the device
+  // host lists made by build_work_host (possibly on a worker thread started by
+  // bscf_set_geometries) and not yet uploaded: their parameters, ket-order
+  // primitive map and positions
+  double host_tau = -1.0, host_split = -1.0;
+  std::future<void> work_job;
+  std::vector<int2> h_kpos;
+  std::vector<int> h_kmap;
   double split_tol = 1e-4;   // FP32 split of MIXED builds (from the last SCF options)
   // work lists per quartet class
   struct ClassWork {
@@ -638,7 +646,9 @@ void build_shell_topology(bscf_ctx* c) {
 }
 
 // Work lists for the Fock build (see file comment).
-void build_work(bscf_ctx* c, double tau, double split) {
+// Host part of the work lists (no HIP calls, no device buffers): it may run
+// on a worker thread while the context's stream computes something else.
+void build_work_host(bscf_ctx* c, double tau, double split) {
   const int NPC = kNumPairClasses;
   // per instance, per pair class: subclasses keyed by primitive count
   struct Sub {
@@ -693,10 +703,8 @@ void build_work(bscf_ctx* c, double tau, double split) {
           }
           c->max_prims = std::max(c->max_prims, sb.nprim);
         }
-    c->d_kpos.upload(kpos, c->stream);
-    c->d_kmap.upload(kmap, c->stream);
-    c->d_kprims.resize(kmap.size());
-    launch_gather_prims((int)kmap.size(), c->d_kmap.p, c->d_prims.p, c->d_kprims.p, c->stream);
+    c->h_kpos.swap(kpos);
+    c->h_kmap.swap(kmap);
   }
   const QuartetClass* qc = quartet_classes();
   // classes are independent: build their lists on host threads
@@ -852,6 +860,22 @@ void build_work(bscf_ctx* c, double tau, double split) {
     for (auto& e : err)
       if (e) std::rethrow_exception(e);
   }
+  c->max_ncd = 0;
+  for (int pid : c->kets) {
+    const ShellPair& pr = c->pairs[pid];
+    c->max_ncd = std::max(c->max_ncd, ncart(c->shells[pr.a].l) * ncart(c->shells[pr.b].l));
+  }
+  c->host_tau = tau;
+  c->host_split = split;
+}
+
+// Device part: uploads, the ket-order primitive copy and the ket-position
+// buffers of the lists that build_work_host made.
+void build_work_device(bscf_ctx* c) {
+  c->d_kpos.upload(c->h_kpos, c->stream);
+  c->d_kmap.upload(c->h_kmap, c->stream);
+  c->d_kprims.resize(c->h_kmap.size());
+  launch_gather_prims((int)c->h_kmap.size(), c->d_kmap.p, c->d_prims.p, c->d_kprims.p, c->stream);
   for (int q = 0; q < kNumQuartetClasses; ++q) {
     auto& W = c->work[q];
     W.d_items.upload(W.items, c->stream);
@@ -863,17 +887,34 @@ void build_work(bscf_ctx* c, double tau, double split) {
   }
   c->d_kets.upload(c->kets, c->stream);
   // ket-position buffers; Jk is kept zero between builds by jk_finalize
-  c->max_ncd = 0;
-  for (int pid : c->kets) {
-    const ShellPair& pr = c->pairs[pid];
-    c->max_ncd = std::max(c->max_ncd, ncart(c->shells[pr.a].l) * ncart(c->shells[pr.b].l));
-  }
   const size_t nkb = (size_t)c->max_ncd * c->kets.size();
   c->d_Pk.resize(nkb);
   c->d_Jk.resize(nkb);
   HIPCHK(hipMemsetAsync(c->d_Jk.p, 0, sizeof(double) * c->d_Jk.n, c->stream));
-  c->work_tau = tau;
-  c->work_split = split;
+  c->work_tau = c->host_tau;
+  c->work_split = c->host_split;
+}
+
+// Wait for a work-list build started on a worker thread (rethrowing its
+// error); every entry point that reads or replaces the lists calls this first.
+void join_work(bscf_ctx* c) {
+  if (c->work_job.valid()) {
+    const double t0 = now_ms();
+    c->work_job.get();
+    c->t_work_ms += now_ms() - t0;
+  }
+}
+
+// Lists for (tau, split) on the device: finish the worker's build when it was
+// made for these parameters, else build them here.
+void ensure_work(bscf_ctx* c, double tau, double split, bool split_matters) {
+  join_work(c);
+  if (c->work_tau == tau && (!split_matters || c->work_split == split)) return;
+  const double t0 = now_ms();
+  if (!(c->host_tau == tau && (!split_matters || c->host_split == split)))
+    build_work_host(c, tau, split);
+  build_work_device(c);
+  c->t_work_ms += now_ms() - t0;
 }
 
 // Start a profiled interval on stream s (returns its index) / end it.
@@ -1029,11 +1070,7 @@ void autotune_fock(bscf_ctx* c, int pcol) {
 }
 
 void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
-  if (tau != c->work_tau || (precision == BSCF_MIXED && c->split_tol != c->work_split)) {
-    const double tw = now_ms();
-    build_work(c, tau, c->split_tol);
-    c->t_work_ms += now_ms() - tw;
-  }
+  ensure_work(c, tau, c->split_tol, precision == BSCF_MIXED);
   if (!c->fock_tuned[precision == BSCF_MIXED ? 1 : 0]) autotune_fock(c, precision == BSCF_MIXED ? 1 : 0);
   const double t0 = now_ms();
   launch_fill(c->J.p, c->mtot, 0.0, c->stream);
@@ -1176,6 +1213,12 @@ bscf_status bscf_create(int hip_device, void* hip_stream, bscf_ctx** out) {
 
 bscf_status bscf_destroy(bscf_ctx* c) {
   if (!c) return BSCF_OK;
+  if (c->work_job.valid()) {
+    try {
+      c->work_job.get();
+    } catch (...) {
+    }
+  }
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   for (auto& r : c->prof_pending) {
@@ -1200,6 +1243,7 @@ bscf_status bscf_destroy(bscf_ctx* c) {
 bscf_status bscf_load_basis(bscf_ctx* c, const char* json) {
   return guard([&] {
     need(c && json, BSCF_E_INVALID, "NULL argument");
+    join_work(c);
     JParser p{json};
     JVal root = p.parse();
     const JVal* el = root.get("elements");
@@ -1236,6 +1280,7 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     need(c && n_inst > 0 && n_atoms && Z, BSCF_E_INVALID, "bad arguments");
     need(!c->basis.empty(), BSCF_E_INVALID, "load a basis first");
     HIPCHK(hipSetDevice(c->device));
+    join_work(c);
     c->ninst = n_inst;
     c->natoms.assign(n_atoms, n_atoms + n_inst);
     c->atom_off.assign(n_inst, 0);
@@ -1345,7 +1390,7 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->have_geom = false;
     c->have_scf = false;
     c->have_C = false;
-    c->work_tau = -1.0;
+    c->work_tau = c->host_tau = -1.0;
     c->fock_tuned[0] = c->fock_tuned[1] = c->grad_tuned = false;
     c->guess.reset_batch(c->ninst);
     sync(c);
@@ -1357,6 +1402,8 @@ bscf_status bscf_set_geometries(bscf_ctx* c, const double* xyz) {
     need(c && xyz, BSCF_E_INVALID, "NULL argument");
     need(c->ninst > 0, BSCF_E_INVALID, "set instances first");
     HIPCHK(hipSetDevice(c->device));
+    join_work(c);
+    c->work_tau = c->host_tau = -1.0;
     const double t0 = now_ms();
     for (int k = 0; k < 3 * c->total_atoms; ++k)
       need(std::isfinite(xyz[k]), BSCF_E_INVALID, "non-finite coordinate");
@@ -1416,12 +1463,16 @@ bscf_status bscf_set_geometries(bscf_ctx* c, const double* xyz) {
       const double one = 1.0;
       BLASCHK(rocblas_daxpy(c->blas, (int)c->mtot, &one, c->V.p, 1, c->H.p, 1));
     }
-    build_orthogonaliser(c);
+    // Schwarz bounds to the host; the screened work lists are then built on a
+    // worker thread while the stream computes the orthogonaliser (and the
+    // caller's SCF its guess); the first Fock build joins it
     c->Q.resize(c->pairs.size());
     HIPCHK(hipMemcpyAsync(c->Q.data(), c->d_Q.p, c->pairs.size() * sizeof(double),
                           hipMemcpyDeviceToHost, st));
     sync(c);
-    c->work_tau = -1.0;
+    const double split = c->split_tol;
+    c->work_job = std::async(std::launch::async, [c, split] { build_work_host(c, 1e-12, split); });
+    build_orthogonaliser(c);
     c->have_geom = true;
     c->have_scf = false;
     c->t_setup_ms += now_ms() - t0;
@@ -1915,7 +1966,8 @@ bscf_status bscf_work_counts(bscf_ctx* c, double* nq, double* npq, double* flops
   return guard([&] {
     need(c != nullptr, BSCF_E_INVALID, "NULL context");
     require_geom(c);
-    if (c->work_tau < 0) build_work(c, 1e-12, c->split_tol);
+    join_work(c);
+    if (c->work_tau < 0) ensure_work(c, 1e-12, c->split_tol, false);
     const QuartetClass* qc = quartet_classes();
     double a = 0, b = 0, f = 0;
     for (int q = 0; q < kNumQuartetClasses; ++q) {
@@ -1946,6 +1998,7 @@ bscf_status bscf_set_profiling(bscf_ctx* c, int on) {
 bscf_status bscf_reset_stats(bscf_ctx* c) {
   return guard([&] {
     need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    join_work(c);
     prof_collect(c);
     for (auto& W : c->work) {
       W.done_quart = W.done_primq = W.kernel_ms = W.grad_ms = W.done_quart32 = 0;
@@ -1960,6 +2013,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
 bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
   return guard([&] {
     need(c && buf && len > 0, BSCF_E_INVALID, "bad arguments");
+    join_work(c);
     prof_collect(c);
     std::ostringstream s;
     s << "{\"fock_builds\": " << c->fock_builds << ", \"scf_iterations\": " << c->scf_iters
