@@ -227,7 +227,8 @@ def main():
         "fock_tflops": k_fl / (fock_gpu_ms * 1e-3) / 1e12 if fock_gpu_ms else None,
         "fock_frac_fp64_peak": (k_fl / (fock_gpu_ms * 1e-3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS) if fock_gpu_ms else None,
         "phase_ms_per_step": {k: st_json[k] / args.steps for k in
-                              ("t_setup_ms", "t_scf_ms", "t_grad_ms", "t_fock_ms", "t_work_ms")},
+                              ("t_setup_ms", "t_scf_ms", "t_grad_ms", "t_fock_ms", "t_work_ms",
+                               "t_work_host_ms")},
         "density": {"method": "sp2", "calls_per_step": st_json["sp2_calls"] / args.steps,
                     "projection_steps_per_call": st_json["sp2_steps"] / max(st_json["sp2_calls"], 1),
                     "fallbacks": st_json["sp2_fallbacks"]},

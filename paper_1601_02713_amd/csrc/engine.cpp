@@ -268,6 +268,8 @@ struct bscf_ctx {
   int private_bytes[kNumQuartetClasses][3] = {};
   int coop_bytes[kNumQuartetClasses][2] = {};   // cooperative fock, gradient
   double t_fock_gpu_ms = 0, t_work_ms = 0;
+  double t_work_host_ms = 0;   // host part of the work lists, wherever it ran
+  double t_work_phase_ms[3] = {0, 0, 0};   // its ket lists, parts, merges
   rocblas_handle blas = nullptr;
 
   std::map<int, std::vector<BasisShell>> basis;
@@ -649,7 +651,30 @@ void build_shell_topology(bscf_ctx* c) {
 // Host part of the work lists (no HIP calls, no device buffers): it may run
 // on a worker thread while the context's stream computes something else.
 void build_work_host(bscf_ctx* c, double tau, double split) {
+  const double t_start = now_ms();
   const int NPC = kNumPairClasses;
+  // host threads over ntasks independent tasks (errors rethrown here)
+  auto run_tasks = [&](int ntasks, auto&& task) {
+    std::atomic<int> next{0};
+    std::vector<std::exception_ptr> err(ntasks);
+    auto worker = [&] {
+      for (int t; (t = next++) < ntasks;) {
+        try {
+          task(t);
+        } catch (...) {
+          err[t] = std::current_exception();
+        }
+      }
+    };
+    const int nth = std::max(1, std::min<int>(8, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nth; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto& th : pool) th.join();
+    for (auto& e : err)
+      if (e) std::rethrow_exception(e);
+  };
+
   // per instance, per pair class: subclasses keyed by primitive count
   struct Sub {
     int nprim;
@@ -668,19 +693,27 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
       if (k == (int)v.size()) v.push_back(Sub{c->pairs[pid].nprim, {}, {}, 0});
       v[k].ids.push_back(pid);
     }
+  // every subclass's kets in descending Schwarz bound (instances in parallel)
+  run_tasks(c->ninst, [&](int i) {
+    for (int pc = 0; pc < NPC; ++pc) {
+      auto& v = subs[i][pc];
+      std::sort(v.begin(), v.end(), [](const Sub& x, const Sub& y) { return x.nprim > y.nprim; });
+      for (auto& sb : v) {
+        std::stable_sort(sb.ids.begin(), sb.ids.end(),
+                         [&](int x, int y) { return c->Q[x] > c->Q[y]; });
+        sb.q.resize(sb.ids.size());
+        for (size_t r = 0; r < sb.ids.size(); ++r) sb.q[r] = c->Q[sb.ids[r]];
+      }
+    }
+  });
   c->kets.clear();
   for (int i = 0; i < c->ninst; ++i)
     for (int pc = 0; pc < NPC; ++pc) {
       auto& v = subs[i][pc];
-      std::sort(v.begin(), v.end(), [](const Sub& x, const Sub& y) { return x.nprim > y.nprim; });
       for (int s = 0; s < (int)v.size(); ++s) {
         auto& sb = v[s];
-        std::stable_sort(sb.ids.begin(), sb.ids.end(),
-                         [&](int x, int y) { return c->Q[x] > c->Q[y]; });
-        sb.q.resize(sb.ids.size());
         sb.ket_off = (int)c->kets.size();
         for (size_t r = 0; r < sb.ids.size(); ++r) {
-          sb.q[r] = c->Q[sb.ids[r]];
           sub_of[sb.ids[r]] = s;
           rank_of[sb.ids[r]] = (int)r;
           c->kets.push_back(sb.ids[r]);
@@ -707,159 +740,204 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
     c->h_kmap.swap(kmap);
   }
   const QuartetClass* qc = quartet_classes();
-  // classes are independent: build their lists on host threads
-  auto build_class = [&](int q) {
-    auto& W = c->work[q];
-    W.items.clear();
-    W.rows.clear();
-    W.nquart = 0;
-    W.nprimq = 0;
-    const int X = pclass(qc[q].la, qc[q].lb), Y = pclass(qc[q].lc, qc[q].ld);
-    W.inst_quart.assign(c->ninst, 0.0);
-    W.inst_primq.assign(c->ninst, 0.0);
-    struct Tmp {
-      WorkItem w;
-      double cost;
-    };
-    std::vector<Tmp> tmp, utmp[3];
-    for (auto& L : W.ul) {
-      L.units.clear();
-      L.rows.clear();
+  struct Tmp {
+    WorkItem w;
+    double cost;
+  };
+  // The lists of one (class, instance), row indices local to the part; the
+  // class's lists are the parts in instance order.
+  struct Part {
+    std::vector<WorkRow> rows;     // item rows (grouped by primitive counts)
+    std::vector<Tmp> tmp;          // 64-quartet items over them
+    std::vector<WorkRow> urows[3];
+    std::vector<Tmp> utmp[3];      // per-bra units of the three unit lists
+    double nquart = 0, nprimq = 0, nquart32 = 0;
+  };
+  const int ni = c->ninst;
+  std::vector<Part> parts((size_t)kNumQuartetClasses * ni);
+  // count of kets of a Q-descending list with qb * q >= thr
+  auto prefix = [](const std::vector<double>& q, double qb, double thr) {
+    int lo = 0, hi = (int)q.size();
+    while (lo < hi) {
+      const int mid = (lo + hi) / 2;
+      if (qb * q[mid] >= thr) lo = mid + 1;
+      else hi = mid;
     }
-    W.nquart32 = 0;
-    W.inst_quart32.assign(c->ninst, 0.0);
-    // count of kets of a Q-descending list with qb * q >= thr
-    auto prefix = [](const std::vector<double>& q, double qb, double thr) {
-      int lo = 0, hi = (int)q.size();
-      while (lo < hi) {
-        const int mid = (lo + hi) / 2;
-        if (qb * q[mid] >= thr) lo = mid + 1;
-        else hi = mid;
-      }
-      return lo;
-    };
+    return lo;
+  };
+  auto build_part = [&](int q, int i) {
+    Part& P = parts[(size_t)q * ni + i];
+    const int X = pclass(qc[q].la, qc[q].lb), Y = pclass(qc[q].lc, qc[q].ld);
     // units of one bra over its rows [r0, r1) of list k: up to kUnitQuartets
     // consecutive quartets across its rows (all ket primitive counts)
     auto add_units = [&](int k, int r0, const std::vector<int>& kn, int bnprim) {
-      auto& L = W.ul[k];
-      const int r1 = (int)L.rows.size();
+      auto& rows = P.urows[k];
+      const int r1 = (int)rows.size();
       int rr = r0, off = 0;
       while (rr < r1) {
         WorkItem u{rr, off, 0, 0};
         double cost = 0.0;
         while (u.count < kUnitQuartets && rr < r1) {
-          const int t = std::min(L.rows[rr].nket - off, kUnitQuartets - u.count);
+          const int t = std::min(rows[rr].nket - off, kUnitQuartets - u.count);
           u.count += t;
           cost += double(t) * bnprim * kn[rr - r0];
           off += t;
-          if (off == L.rows[rr].nket) {
+          if (off == rows[rr].nket) {
             ++rr;
             off = 0;
           }
         }
-        utmp[k].push_back({u, cost});
+        P.utmp[k].push_back({u, cost});
       }
     };
-    for (int i = 0; i < c->ninst; ++i) {
-      // rows of this instance grouped by (bra, ket) primitive counts
-      std::vector<std::pair<std::pair<int, int>, std::vector<WorkRow>>> groups;
-      for (const Sub& bs : subs[i][X])
-        for (size_t r = 0; r < bs.ids.size(); ++r) {
-          const int bra = bs.ids[r];
-          const double qb = bs.q[r];
-          const int sb = sub_of[bra];
-          const auto& kv = subs[i][Y];
-          int ur0[3];
-          std::vector<int> ur_nprim[3];
-          for (int k = 0; k < 3; ++k) ur0[k] = (int)W.ul[k].rows.size();
-          for (int t = 0; t < (int)kv.size(); ++t) {
-            const Sub& ks = kv[t];
-            int lim = tau > 0.0 ? prefix(ks.q, qb, tau) : (int)ks.q.size();
-            if (X == Y) {
-              if (t > sb) lim = 0;
-              else if (t == sb) lim = std::min(lim, (int)r + 1);
-            }
-            if (lim == 0) continue;
-            const int n64 = std::min(lim, prefix(ks.q, qb, split));
-            const std::pair<int, int> key(bs.nprim, ks.nprim);
-            size_t g = 0;
-            while (g < groups.size() && groups[g].first != key) ++g;
-            if (g == groups.size()) groups.push_back({key, {}});
-            groups[g].second.push_back(WorkRow{bra, ks.ket_off, lim, 0});
-            W.ul[0].rows.push_back(WorkRow{bra, ks.ket_off, lim, 0});
-            ur_nprim[0].push_back(ks.nprim);
-            if (n64 > 0) {
-              W.ul[1].rows.push_back(WorkRow{bra, ks.ket_off, n64, 0});
-              ur_nprim[1].push_back(ks.nprim);
-            }
-            if (lim > n64) {
-              W.ul[2].rows.push_back(WorkRow{bra, ks.ket_off + n64, lim - n64, 0});
-              ur_nprim[2].push_back(ks.nprim);
-            }
-            W.nquart32 += lim - n64;
-            W.inst_quart32[i] += lim - n64;
-            W.nquart += lim;
-            W.nprimq += double(lim) * bs.nprim * ks.nprim;
-            W.inst_quart[i] += lim;
-            W.inst_primq[i] += double(lim) * bs.nprim * ks.nprim;
-          }
-          for (int k = 0; k < 3; ++k) add_units(k, ur0[k], ur_nprim[k], bs.nprim);
+    std::vector<int> ur_nprim[3];
+    // rows of this instance grouped by (bra, ket) primitive counts
+    std::vector<std::pair<std::pair<int, int>, std::vector<WorkRow>>> groups;
+    for (const Sub& bs : subs[i][X])
+      for (size_t r = 0; r < bs.ids.size(); ++r) {
+        const int bra = bs.ids[r];
+        const double qb = bs.q[r];
+        const int sb = sub_of[bra];
+        const auto& kv = subs[i][Y];
+        int ur0[3];
+        for (int k = 0; k < 3; ++k) {
+          ur0[k] = (int)P.urows[k].size();
+          ur_nprim[k].clear();
         }
-      // tile every group with items of up to 64 quartets (one per lane)
-      for (auto& gr : groups) {
-        const int r0 = (int)W.rows.size();
-        W.rows.insert(W.rows.end(), gr.second.begin(), gr.second.end());
-        const int r1 = (int)W.rows.size();
-        const double cost = double(gr.first.first) * gr.first.second;
-        int r = r0, off = 0;
-        while (r < r1) {
-          WorkItem w{r, off, 0, 0};
-          while (w.count < kWave && r < r1) {
-            const int t = std::min(W.rows[r].nket - off, kWave - w.count);
-            w.count += t;
-            off += t;
-            if (off == W.rows[r].nket) {
-              ++r;
-              off = 0;
-            }
+        for (int t = 0; t < (int)kv.size(); ++t) {
+          const Sub& ks = kv[t];
+          int lim = tau > 0.0 ? prefix(ks.q, qb, tau) : (int)ks.q.size();
+          if (X == Y) {
+            if (t > sb) lim = 0;
+            else if (t == sb) lim = std::min(lim, (int)r + 1);
           }
-          tmp.push_back({w, cost});
+          if (lim == 0) continue;
+          const int n64 = std::min(lim, prefix(ks.q, qb, split));
+          const std::pair<int, int> key(bs.nprim, ks.nprim);
+          size_t g = 0;
+          while (g < groups.size() && groups[g].first != key) ++g;
+          if (g == groups.size()) groups.push_back({key, {}});
+          groups[g].second.push_back(WorkRow{bra, ks.ket_off, lim, 0});
+          P.urows[0].push_back(WorkRow{bra, ks.ket_off, lim, 0});
+          ur_nprim[0].push_back(ks.nprim);
+          if (n64 > 0) {
+            P.urows[1].push_back(WorkRow{bra, ks.ket_off, n64, 0});
+            ur_nprim[1].push_back(ks.nprim);
+          }
+          if (lim > n64) {
+            P.urows[2].push_back(WorkRow{bra, ks.ket_off + n64, lim - n64, 0});
+            ur_nprim[2].push_back(ks.nprim);
+          }
+          P.nquart32 += lim - n64;
+          P.nquart += lim;
+          P.nprimq += double(lim) * bs.nprim * ks.nprim;
         }
+        for (int k = 0; k < 3; ++k) add_units(k, ur0[k], ur_nprim[k], bs.nprim);
+      }
+    // tile every group with items of up to 64 quartets (one per lane)
+    for (auto& gr : groups) {
+      const int r0 = (int)P.rows.size();
+      P.rows.insert(P.rows.end(), gr.second.begin(), gr.second.end());
+      const int r1 = (int)P.rows.size();
+      const double cost = double(gr.first.first) * gr.first.second;
+      int r = r0, off = 0;
+      while (r < r1) {
+        WorkItem w{r, off, 0, 0};
+        while (w.count < kWave && r < r1) {
+          const int t = std::min(P.rows[r].nket - off, kWave - w.count);
+          w.count += t;
+          off += t;
+          if (off == P.rows[r].nket) {
+            ++r;
+            off = 0;
+          }
+        }
+        P.tmp.push_back({w, cost});
       }
     }
-    // most expensive contraction groups first
-    std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; });
-    W.items.resize(tmp.size());
-    for (size_t k = 0; k < tmp.size(); ++k) W.items[k] = tmp[k].w;
-    for (int k = 0; k < 3; ++k) {
-      auto& ut = utmp[k];
-      std::stable_sort(ut.begin(), ut.end(), [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; });
-      W.ul[k].units.resize(ut.size());
-      for (size_t j = 0; j < ut.size(); ++j) W.ul[k].units[j] = ut[j].w;
+  };
+  auto merge_class = [&](int q) {
+    auto& W = c->work[q];
+    W.nquart = W.nprimq = W.nquart32 = 0;
+    W.inst_quart.assign(ni, 0.0);
+    W.inst_primq.assign(ni, 0.0);
+    W.inst_quart32.assign(ni, 0.0);
+    std::vector<Tmp> tmp, utmp[3];
+    W.rows.clear();
+    for (auto& L : W.ul) L.rows.clear();
+    {
+      size_t nr = 0, nt = 0, nur[3] = {0, 0, 0}, nut[3] = {0, 0, 0};
+      for (int i = 0; i < ni; ++i) {
+        const Part& P = parts[(size_t)q * ni + i];
+        nr += P.rows.size();
+        nt += P.tmp.size();
+        for (int k = 0; k < 3; ++k) {
+          nur[k] += P.urows[k].size();
+          nut[k] += P.utmp[k].size();
+        }
+      }
+      W.rows.reserve(nr);
+      tmp.reserve(nt);
+      for (int k = 0; k < 3; ++k) {
+        W.ul[k].rows.reserve(nur[k]);
+        utmp[k].reserve(nut[k]);
+      }
     }
+    for (int i = 0; i < ni; ++i) {
+      Part& P = parts[(size_t)q * ni + i];
+      const int r0 = (int)W.rows.size();
+      W.rows.insert(W.rows.end(), P.rows.begin(), P.rows.end());
+      for (Tmp t : P.tmp) {
+        t.w.row += r0;
+        tmp.push_back(t);
+      }
+      for (int k = 0; k < 3; ++k) {
+        const int u0 = (int)W.ul[k].rows.size();
+        W.ul[k].rows.insert(W.ul[k].rows.end(), P.urows[k].begin(), P.urows[k].end());
+        for (Tmp t : P.utmp[k]) {
+          t.w.row += u0;
+          utmp[k].push_back(t);
+        }
+      }
+      W.nquart += P.nquart;
+      W.nprimq += P.nprimq;
+      W.nquart32 += P.nquart32;
+      W.inst_quart[i] = P.nquart;
+      W.inst_primq[i] = P.nprimq;
+      W.inst_quart32[i] = P.nquart32;
+      P = Part();   // release the part
+    }
+    // most expensive first, by counting sorts (stable).  An item's cost is
+    // the product of its bra and ket primitive counts, an integer: exact
+    // order.  A unit's cost is a sum over its rows; units are ordered by
+    // eighths of an octave of it (the order only schedules the work).
+    auto counting = [](const std::vector<Tmp>& v, std::vector<WorkItem>& out, auto&& key, int nkey) {
+      std::vector<int> start(nkey + 1, 0);
+      for (const Tmp& t : v) ++start[key(t.cost) + 1];
+      for (int b = 0; b < nkey; ++b) start[b + 1] += start[b];
+      out.resize(v.size());
+      for (const Tmp& t : v) out[start[key(t.cost)]++] = t.w;
+    };
+    // item keys: 4096 - cost (primitive counts per shell pair stay below 64);
+    // unit keys: 320 - eighths of octaves (costs stay below 2^40)
+    counting(tmp, W.items, [](double cst) { return 4096 - std::min((int)cst, 4096); }, 4097);
+    for (int k = 0; k < 3; ++k)
+      counting(utmp[k], W.ul[k].units, [](double cst) {
+        const int b = cst > 1.0 ? (int)(8.0 * std::log2(cst)) : 0;
+        return 320 - std::min(b, 320);
+      }, 321);
     W.lds_ok = sizeof(double) * (size_t)unit_lds_doubles(qc[q].la, qc[q].lb, c->max_n,
                                                           c->max_prims) <= c->max_lds_bytes;
   };
-  {
-    std::atomic<int> next{0};
-    std::vector<std::exception_ptr> err(kNumQuartetClasses);
-    auto worker = [&] {
-      for (int q; (q = next++) < kNumQuartetClasses;) {
-        try {
-          build_class(q);
-        } catch (...) {
-          err[q] = std::current_exception();
-        }
-      }
-    };
-    const int nth = std::max(1, std::min<int>(8, (int)std::thread::hardware_concurrency()));
-    std::vector<std::thread> pool;
-    for (int t = 1; t < nth; ++t) pool.emplace_back(worker);
-    worker();
-    for (auto& th : pool) th.join();
-    for (auto& e : err)
-      if (e) std::rethrow_exception(e);
-  }
+  // host threads: first every (class, instance) part, then every class's merge
+  // parts interleaved over classes, so that the large classes spread over the threads
+  const double t_parts = now_ms();
+  run_tasks(kNumQuartetClasses * ni, [&](int t) { build_part(t % kNumQuartetClasses, t / kNumQuartetClasses); });
+  const double t_merge = now_ms();
+  run_tasks(kNumQuartetClasses, [&](int q) { merge_class(q); });
+  c->t_work_phase_ms[0] += t_parts - t_start;
+  c->t_work_phase_ms[1] += t_merge - t_parts;
+  c->t_work_phase_ms[2] += now_ms() - t_merge;
   c->max_ncd = 0;
   for (int pid : c->kets) {
     const ShellPair& pr = c->pairs[pid];
@@ -867,6 +945,7 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
   }
   c->host_tau = tau;
   c->host_split = split;
+  c->t_work_host_ms += now_ms() - t_start;
 }
 
 // Device part: uploads, the ket-order primitive copy and the ket-position
@@ -2005,6 +2084,8 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
       W.launches = W.grad_launches = 0;
     }
     c->t_fock_ms = c->t_scf_ms = c->t_grad_ms = c->t_setup_ms = c->t_fock_gpu_ms = c->t_work_ms = 0;
+    c->t_work_host_ms = 0;
+    c->t_work_phase_ms[0] = c->t_work_phase_ms[1] = c->t_work_phase_ms[2] = 0;
     c->fock_builds = c->scf_iters = 0;
     c->sp2_calls = c->sp2_steps = c->sp2_fallbacks = 0;
   });
@@ -2020,6 +2101,8 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
       << ", \"t_fock_ms\": " << c->t_fock_ms << ", \"t_scf_ms\": " << c->t_scf_ms
       << ", \"t_grad_ms\": " << c->t_grad_ms << ", \"t_setup_ms\": " << c->t_setup_ms
       << ", \"t_fock_gpu_ms\": " << c->t_fock_gpu_ms << ", \"t_work_ms\": " << c->t_work_ms
+      << ", \"t_work_host_ms\": " << c->t_work_host_ms << ", \"t_work_phase_ms\": ["
+      << c->t_work_phase_ms[0] << ", " << c->t_work_phase_ms[1] << ", " << c->t_work_phase_ms[2] << "]"
       << ", \"sp2_calls\": " << c->sp2_calls << ", \"sp2_steps\": " << c->sp2_steps
       << ", \"sp2_fallbacks\": " << c->sp2_fallbacks
       << ", \"classes\": {";
