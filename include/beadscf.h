@@ -80,10 +80,17 @@ typedef struct {
   int density;         /* bscf_density: how each iteration's density is formed;
                           both give the projector on the lowest N/2 levels of
                           the extrapolated Fock matrix (Section 2, SCF step)   */
+  int incremental;     /* 1: iterations after the first build J and K from the
+                          density change, skipping quartets whose Schwarz bound
+                          times max |dP| is below schwarz_tol (the integral
+                          cutoff applied to the change, Section 3.1), with a
+                          full build every 12 iterations; 0: every iteration a
+                          full build                                            */
 } bscf_scf_opts;
 
 /* Fill opts with defaults: e_tol 1e-8, comm_tol 1e-6, schwarz_tol 1e-12,
- * fp32_split_tol 1e-4, max_iter 100, diis_size 8, FP64, core guess, SP2. */
+ * fp32_split_tol 1e-4, max_iter 100, diis_size 8, FP64, core guess, SP2,
+ * incremental builds. */
 bscf_status bscf_default_opts(bscf_scf_opts* opts);
 
 /* Create a context on HIP device `hip_device`; `hip_stream` may be NULL (the

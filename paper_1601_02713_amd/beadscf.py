@@ -32,7 +32,8 @@ class ScfOpts(ctypes.Structure):
                 ("schwarz_tol", ctypes.c_double), ("fp32_split_tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("diis_size", ctypes.c_int),
                 ("precision", ctypes.c_int), ("guess", ctypes.c_int),
-                ("deterministic", ctypes.c_int), ("density", ctypes.c_int)]
+                ("deterministic", ctypes.c_int), ("density", ctypes.c_int),
+                ("incremental", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p

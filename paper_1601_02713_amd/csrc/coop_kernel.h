@@ -166,6 +166,8 @@ __global__ __launch_bounds__(CP::NT) void coop_fock_kernel(FockArgs a) {
               sd = a.shells[ket.b];
   const int inst = sa.inst;
   if (!a.active[inst]) return;
+  // incremental build: quartets below the density-weighted bound do nothing
+  if (a.dpmax && a.Q[bid] * a.Q[kid] * fmin(a.dpmax[inst], 1.0) < a.tau) return;
   const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
   const double CD[3] = {sc_.x - sd.x, sc_.y - sd.y, sc_.z - sd.z};
   coop_primitives<CP>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,

@@ -57,6 +57,11 @@ constexpr int kMaxLaneScratch = 2048;
 // idempotency error Tr X - Tr X^2 = sum_k l_k (1 - l_k) below which a replica's
 // projector counts as converged (two more steps then square the residual
 // occupation error away).
+// Incremental Fock builds: a full build at the first SCF iteration and every
+// kFullEvery iterations, which bounds the accumulated effect of the skipped
+// quartets.
+constexpr int kFullEvery = 12;
+
 constexpr int kSp2MaxSteps = 100;
 constexpr double kSp2Tol = 1e-11;
 
@@ -318,6 +323,7 @@ struct bscf_ctx {
       std::vector<WorkRow> rows;
       DevBuf<WorkItem> d_units;
       DevBuf<WorkRow> d_rows;
+      DevBuf<int> d_keep;   // kets per row that an incremental build keeps
     } ul[3];
     double nquart32 = 0;                 // quartets of the FP32 list
     std::vector<double> inst_quart32;    // per instance
@@ -361,6 +367,11 @@ struct bscf_ctx {
   std::vector<int> task_first, task_count;  // per pair class ranges into task arrays
   // matrices
   DevBuf<double> S, T, V, H, X, F, J, K, P, Pnew, W, tmp1, tmp2, err, Fbar, C, Cacc, eig, eigE;
+  DevBuf<double> Pprev, dP, d_dpmax;   // incremental builds: last build's P, its change, max |dP|
+  // work kept by incremental builds, [quartets, primitive quartets, FP32
+  // quartets][class][instance], accumulated on the device until read
+  DevBuf<double> d_kept;
+  long long inc_builds = 0;
   DevBuf<double> Fhist, Ehist, diisB, diisC;
   DevBuf<int> diis_count, diis_head, d_info;
   // SP2 purification: per-step (Tr X, Tr X^2) of every instance, Gershgorin
@@ -962,6 +973,7 @@ void build_work_device(bscf_ctx* c) {
     for (auto& L : W.ul) {
       L.d_units.upload(L.units, c->stream);
       L.d_rows.upload(L.rows, c->stream);
+      L.d_keep.resize(L.rows.size());
     }
   }
   c->d_kets.upload(c->kets, c->stream);
@@ -994,6 +1006,24 @@ void ensure_work(bscf_ctx* c, double tau, double split, bool split_matters) {
     build_work_host(c, tau, split);
   build_work_device(c);
   c->t_work_ms += now_ms() - t0;
+}
+
+// Add the work that incremental builds kept (counted on the device) to the
+// statistics and clear the device counts.
+void collect_kept(bscf_ctx* c) {
+  if (c->d_kept.n == 0) return;
+  std::vector<double> h(c->d_kept.n);
+  HIPCHK(hipMemcpyAsync(h.data(), c->d_kept.p, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+  sync(c);
+  const int ni = c->ninst;
+  for (int q = 0; q < kNumQuartetClasses; ++q)
+    for (int i = 0; i < ni; ++i) {
+      c->work[q].done_quart += h[(size_t)q * ni + i];
+      c->work[q].done_primq += h[(size_t)(kNumQuartetClasses + q) * ni + i];
+      c->work[q].done_quart32 += h[(size_t)(2 * kNumQuartetClasses + q) * ni + i];
+    }
+  launch_fill(c->d_kept.p, (long long)c->d_kept.n, 0.0, c->stream);
 }
 
 // Start a profiled interval on stream s (returns its index) / end it.
@@ -1058,6 +1088,10 @@ FockArgs fock_args(bscf_ctx* c, double* J, double* K, const int* active) {
   a.boys64 = c->d_boys64.p;
   a.boys32 = c->d_boys32.p;
   a.active = active;
+  a.ukeep = nullptr;
+  a.Q = c->d_Q.p;
+  a.dpmax = nullptr;
+  a.tau = 0.0;
   return a;
 }
 
@@ -1069,6 +1103,7 @@ void set_class(FockArgs& a, const bscf_ctx::ClassWork& W, int k) {
   a.units = W.ul[k].d_units.p;
   a.nunits = (int)W.ul[k].units.size();
   a.urows = W.ul[k].d_rows.p;
+  a.ukeep = W.ul[k].d_keep.p;
 }
 
 // Lane-kernel launches of class q: every quartet in FP64, or in MIXED mode
@@ -1148,13 +1183,48 @@ void autotune_fock(bscf_ctx* c, int pcol) {
   c->fock_tuned[pcol] = true;
 }
 
-void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
+// One Fock build.  Full: J and K from P over every listed quartet.
+// Incremental (Almlof's direct SCF): J and K keep the last build's values and
+// gain the contributions of dP = P - Pprev, from the quartets with
+// Q_ab Q_cd min(max|dP|, 1) >= tau; J and K are linear in the density, so
+// only the skipped quartets (each bounded by tau) differ from a full build.
+void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool incremental = false) {
   ensure_work(c, tau, c->split_tol, precision == BSCF_MIXED);
   if (!c->fock_tuned[precision == BSCF_MIXED ? 1 : 0]) autotune_fock(c, precision == BSCF_MIXED ? 1 : 0);
   const double t0 = now_ms();
-  launch_fill(c->J.p, c->mtot, 0.0, c->stream);
-  launch_fill(c->K.p, c->mtot, 0.0, c->stream);
   FockArgs a = fock_args(c, c->J.p, c->K.p, masked ? c->d_active.p : c->d_all_active.p);
+  const BatchInfo bset = c->batch(masked);
+  if (incremental) {
+    launch_density_change(bset, c->max_n, c->P.p, c->Pprev.p, c->dP.p, c->d_dpmax.p, c->stream);
+    // kept kets per row for the lane kernels, and the kept work of every
+    // class counted on the device (the statistics read it later)
+    const int pc = precision == BSCF_MIXED ? 1 : 0;
+    const int ni = c->ninst;
+    for (int q = 0; q < kNumQuartetClasses; ++q) {
+      auto& W = c->work[q];
+      if (W.items.empty()) continue;
+      double* cq = c->d_kept.p + (size_t)q * ni;
+      double* cpq = c->d_kept.p + (size_t)(kNumQuartetClasses + q) * ni;
+      double* c32 = c->d_kept.p + (size_t)(2 * kNumQuartetClasses + q) * ni;
+      if (c->fock_variant[pc][q]) {
+        launch_row_keep(W.d_rows.p, (int)W.rows.size(), c->d_kets.p, c->d_pairs.p, c->d_shells.p,
+                        c->d_Q.p, c->d_dpmax.p, a.active, tau, ni, nullptr, cq, cpq, nullptr,
+                        c->stream);
+      } else {
+        for (int k = (pc ? 1 : 0); k <= (pc ? 2 : 0); ++k)
+          launch_row_keep(W.ul[k].d_rows.p, (int)W.ul[k].rows.size(), c->d_kets.p, c->d_pairs.p,
+                          c->d_shells.p, c->d_Q.p, c->d_dpmax.p, a.active, tau, ni,
+                          W.ul[k].d_keep.p, cq, cpq, k == 2 ? c32 : nullptr, c->stream);
+      }
+    }
+    a.P = c->dP.p;
+    a.dpmax = c->d_dpmax.p;
+    a.tau = tau;
+    c->inc_builds++;
+  } else {
+    launch_fill(c->J.p, c->mtot, 0.0, c->stream);
+    launch_fill(c->K.p, c->mtot, 0.0, c->stream);
+  }
   const KetPosArgs kp = ketpos_args(c);
   const QuartetClass* qc = quartet_classes();
   // class kernels run concurrently on the auxiliary streams (J and K are
@@ -1163,7 +1233,7 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
   // private scratch stay on the context stream: the runtime reserves scratch
   // per hardware queue for full occupancy.
   const int pbuild = c->profiling ? prof_begin(c, 0, 2, c->stream) : -1;
-  launch_gather_pk(kp, c->max_ncd, c->P.p, c->d_Pk.p, c->stream);
+  launch_gather_pk(kp, c->max_ncd, a.P, c->d_Pk.p, c->stream);
   HIPCHK(hipEventRecord(c->ev_fork, c->stream));
   for (int k = 0; k < bscf_ctx::kAux; ++k) HIPCHK(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
   int slot = 0;
@@ -1186,12 +1256,13 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
         launch(c->private_bytes[q][fp32], run);
       });
     }
-    for (int i = 0; i < c->ninst; ++i)
-      if (!masked || c->h_active[i]) {
-        W.done_quart += W.inst_quart[i];
-        W.done_primq += W.inst_primq[i];
-        if (precision == BSCF_MIXED && !c->fock_variant[pcol][q]) W.done_quart32 += W.inst_quart32[i];
-      }
+    if (!incremental)   // (an incremental build counts its kept work on the device)
+      for (int i = 0; i < c->ninst; ++i)
+        if (!masked || c->h_active[i]) {
+          W.done_quart += W.inst_quart[i];
+          W.done_primq += W.inst_primq[i];
+          if (precision == BSCF_MIXED && !c->fock_variant[pcol][q]) W.done_quart32 += W.inst_quart32[i];
+        }
     W.launches++;
   }
   for (int k = 0; k < bscf_ctx::kAux; ++k) {
@@ -1205,6 +1276,7 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked) {
   BatchInfo b = c->batch(masked);
   launch_fock_assemble(b, c->max_n, c->H.p, c->J.p, c->K.p, c->P.p, c->d_Enuc.p, c->F.p, c->d_E.p,
                        c->stream);
+  launch_scale_copy(bset, c->max_n, c->P.p, c->Pprev.p, 1.0, 0, c->stream);   // next build's reference
   c->fock_builds++;
   c->t_fock_ms += now_ms() - t0;
 }
@@ -1233,6 +1305,7 @@ bscf_status bscf_default_opts(bscf_scf_opts* o) {
   o->guess = BSCF_GUESS_CORE;
   o->deterministic = 0;
   o->density = BSCF_DENSITY_SP2;
+  o->incremental = 1;
   return BSCF_OK;
 }
 
@@ -1449,8 +1522,11 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     const size_t mt = (size_t)c->mtot;
     for (DevBuf<double>* m : {&c->S, &c->T, &c->V, &c->H, &c->X, &c->F, &c->J, &c->K, &c->P,
                               &c->Pnew, &c->W, &c->tmp1, &c->tmp2, &c->err, &c->Fbar, &c->C,
-                              &c->Cacc, &c->eig, &c->eigE})
+                              &c->Cacc, &c->eig, &c->eigE, &c->Pprev, &c->dP})
       m->resize(mt);
+    c->d_dpmax.resize((size_t)n_inst * (1 + (size_t)((c->max_n + 31) / 32) * ((c->max_n + 31) / 32)));
+    c->d_kept.resize((size_t)3 * kNumQuartetClasses * n_inst);
+    launch_fill(c->d_kept.p, (long long)c->d_kept.n, 0.0, s);
     c->Fhist.resize(mt * 8);
     c->Ehist.resize(mt * 8);
     c->diisB.resize((size_t)n_inst * 64);
@@ -1757,7 +1833,7 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     BatchInfo bm = c->batch(true);
     int it = 0;
     for (; it < o.max_iter; ++it) {
-      fock_build(c, o.schwarz_tol, o.precision, true);
+      fock_build(c, o.schwarz_tol, o.precision, true, o.incremental && it % kFullEvery != 0);
       // M = F P S, e = X (M - M^T) X
       gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->F.p, c->P.p, 0.0,
            c->tmp1.p);
@@ -2079,6 +2155,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
     need(c != nullptr, BSCF_E_INVALID, "NULL context");
     join_work(c);
     prof_collect(c);
+    collect_kept(c);
     for (auto& W : c->work) {
       W.done_quart = W.done_primq = W.kernel_ms = W.grad_ms = W.done_quart32 = 0;
       W.launches = W.grad_launches = 0;
@@ -2088,6 +2165,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
     c->t_work_phase_ms[0] = c->t_work_phase_ms[1] = c->t_work_phase_ms[2] = 0;
     c->fock_builds = c->scf_iters = 0;
     c->sp2_calls = c->sp2_steps = c->sp2_fallbacks = 0;
+    c->inc_builds = 0;
   });
 }
 
@@ -2096,6 +2174,7 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
     need(c && buf && len > 0, BSCF_E_INVALID, "bad arguments");
     join_work(c);
     prof_collect(c);
+    collect_kept(c);
     std::ostringstream s;
     s << "{\"fock_builds\": " << c->fock_builds << ", \"scf_iterations\": " << c->scf_iters
       << ", \"t_fock_ms\": " << c->t_fock_ms << ", \"t_scf_ms\": " << c->t_scf_ms
@@ -2104,7 +2183,7 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
       << ", \"t_work_host_ms\": " << c->t_work_host_ms << ", \"t_work_phase_ms\": ["
       << c->t_work_phase_ms[0] << ", " << c->t_work_phase_ms[1] << ", " << c->t_work_phase_ms[2] << "]"
       << ", \"sp2_calls\": " << c->sp2_calls << ", \"sp2_steps\": " << c->sp2_steps
-      << ", \"sp2_fallbacks\": " << c->sp2_fallbacks
+      << ", \"sp2_fallbacks\": " << c->sp2_fallbacks << ", \"incremental_builds\": " << c->inc_builds
       << ", \"classes\": {";
     const QuartetClass* qc = quartet_classes();
     for (int q = 0; q < kNumQuartetClasses; ++q) {

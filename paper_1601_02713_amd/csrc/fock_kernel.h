@@ -57,7 +57,52 @@ struct FockArgs {
   const double* boys64;
   const float* boys32;
   const int* active;       // per instance: nonzero while its SCF runs
+  // Incremental build (dpmax != nullptr): P is the density change since the
+  // last full build and a quartet contributes only when
+  // Q_ab Q_cd min(dpmax[inst], 1) >= tau; ukeep[r] is the number of kets of
+  // unit row r that pass (the rows' kets run in descending Q, so they are a
+  // prefix).  Full build: dpmax == nullptr, every listed quartet contributes.
+  const int* ukeep;
+  const double* Q;         // Schwarz bound per shell pair
+  const double* dpmax;     // per instance max |dP|
+  double tau;
 };
+
+// Quartets of unit u that pass an incremental build's test: the kept kets of
+// each row the unit covers are a prefix of the row
+__device__ __forceinline__ int unit_kept(const WorkItem& u, const WorkRow* __restrict__ rows,
+                                         const int* __restrict__ keep) {
+  int rem = u.count, rr = u.row, off = u.off, kept = 0;
+  while (rem > 0) {
+    const int take = min(rows[rr].nket - off, rem);
+    kept += max(0, min(keep[rr] - off, take));
+    rem -= take;
+    ++rr;
+    off = 0;
+  }
+  return kept;
+}
+
+// Row rr and position k0 in it of kept quartet t (t < unit_kept) of unit u
+__device__ __forceinline__ void unit_kept_quartet(const WorkItem& u,
+                                                  const WorkRow* __restrict__ rows,
+                                                  const int* __restrict__ keep, int t, int& rr,
+                                                  int& k0) {
+  int rem = u.count, off = u.off;
+  rr = u.row;
+  for (;;) {
+    const int take = min(rows[rr].nket - off, rem);
+    const int kc = max(0, min(keep[rr] - off, take));
+    if (t < kc) {
+      k0 = off + t;
+      return;
+    }
+    t -= kc;
+    rem -= take;
+    ++rr;
+    off = 0;
+  }
+}
 
 struct SchwarzArgs {
   const int* pair_ids;     // pairs of one class
@@ -175,6 +220,10 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
   const Shell sa = a.shells[bra.a], sb = a.shells[bra.b];
   const int inst = sa.inst;
   if (!a.active[inst]) return;
+  // incremental build: a unit whose quartets all fall below the bound does nothing
+  const bool screen = a.dpmax != nullptr;
+  const int total = screen ? unit_kept(u, a.urows, a.ukeep) : u.count;
+  if (total == 0) return;
   const long long mo = a.moff[inst];
   const int n = a.nbf[inst];
   const int m0 = sa.bf, n0 = sb.bf;
@@ -202,15 +251,21 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
       jab[i][j] = 0.0;
     }
   const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
-  for (int c0 = 0; c0 < u.count; c0 += kWave) {
+  for (int c0 = 0; c0 < total; c0 += kWave) {
     const int t = c0 + lane;
-    const bool valid = t < u.count;
-    int rr = u.row, k0 = u.off + (valid ? t : 0);
-    int nk = a.urows[rr].nket;
-    while (k0 >= nk) {
-      k0 -= nk;
-      ++rr;
-      nk = a.urows[rr].nket;
+    const bool valid = t < total;
+    int rr, k0;
+    if (screen) {
+      unit_kept_quartet(u, a.urows, a.ukeep, valid ? t : 0, rr, k0);
+    } else {
+      rr = u.row;
+      k0 = u.off + (valid ? t : 0);
+      int nk = a.urows[rr].nket;
+      while (k0 >= nk) {
+        k0 -= nk;
+        ++rr;
+        nk = a.urows[rr].nket;
+      }
     }
     const int pos = a.urows[rr].ket0 + k0;
     const int kid = a.kets[pos];

@@ -74,4 +74,64 @@ void launch_jk_finalize(const KetPosArgs& a, int max_ncd, double* Jk, double* J,
                      max_ncd, Jk, J);
 }
 
+// Kets of each work row that pass an incremental build's test
+// Q_ab Q_cd min(dpmax[inst], 1) >= tau: the row's kets run in descending
+// Schwarz bound, so the count is a binary search.  One thread per row; rows of
+// instances that are not active are left alone.  When keep is given the count
+// goes there; when cq is given the kept quartets and primitive quartets (and,
+// with c32, quartets again) are added to cq[inst], cpq[inst] (c32[inst]).
+__global__ void row_keep_kernel(const WorkRow* __restrict__ rows, int nrows,
+                                const int* __restrict__ kets, const ShellPair* __restrict__ pairs,
+                                const Shell* __restrict__ shells, const double* __restrict__ Q,
+                                const double* __restrict__ dpmax, const int* __restrict__ active,
+                                double tau, int ninst, int* __restrict__ keep, double* cq,
+                                double* cpq, double* c32) {
+  extern __shared__ double part[];   // [2 or 3][ninst] when counting
+  const int nc = c32 ? 3 : 2;
+  if (cq) {
+    for (int k = threadIdx.x; k < nc * ninst; k += blockDim.x) part[k] = 0.0;
+    __syncthreads();
+  }
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrows) {
+    const WorkRow w = rows[r];
+    const ShellPair bra = pairs[w.bra];
+    const int inst = shells[bra.a].inst;
+    if (active[inst]) {
+      const double qd = Q[w.bra] * fmin(dpmax[inst], 1.0);
+      int lo = 0, hi = w.nket;
+      while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (qd * Q[kets[w.ket0 + mid]] >= tau) lo = mid + 1;
+        else hi = mid;
+      }
+      if (keep) keep[r] = lo;
+      if (cq && lo > 0) {
+        const int knp = pairs[kets[w.ket0]].nprim;   // one primitive count per row
+        atomicAdd(&part[inst], double(lo));
+        atomicAdd(&part[ninst + inst], double(lo) * bra.nprim * knp);
+        if (c32) atomicAdd(&part[2 * ninst + inst], double(lo));
+      }
+    }
+  }
+  if (cq) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < ninst; k += blockDim.x) {
+      if (part[k] != 0.0) atomicAdd(&cq[k], part[k]);
+      if (part[ninst + k] != 0.0) atomicAdd(&cpq[k], part[ninst + k]);
+      if (c32 && part[2 * ninst + k] != 0.0) atomicAdd(&c32[k], part[2 * ninst + k]);
+    }
+  }
+}
+
+void launch_row_keep(const WorkRow* rows, int nrows, const int* kets, const ShellPair* pairs,
+                     const Shell* shells, const double* Q, const double* dpmax, const int* active,
+                     double tau, int ninst, int* keep, double* cq, double* cpq, double* c32,
+                     hipStream_t s) {
+  if (nrows == 0) return;
+  const size_t lds = cq ? sizeof(double) * (c32 ? 3 : 2) * ninst : 0;
+  hipLaunchKernelGGL(row_keep_kernel, dim3((nrows + 255) / 256), dim3(256), lds, s, rows, nrows,
+                     kets, pairs, shells, Q, dpmax, active, tau, ninst, keep, cq, cpq, c32);
+}
+
 }  // namespace bscf

@@ -55,6 +55,14 @@ struct Grad1EArgs {
 
 void launch_prim_pairs(const PrimPairSetupArgs& a, hipStream_t s);
 void launch_onee(int la, int lb, const OneEArgs& a, hipStream_t s);
+// keep[r] = kets of work row r with Q_ab Q_cd min(dpmax[inst], 1) >= tau for
+// the rows of active instances (keep may be NULL); with cq, the kept
+// quartets, primitive quartets (and, with c32, quartets again) are added per
+// instance to cq, cpq (c32) (jk.hip)
+void launch_row_keep(const WorkRow* rows, int nrows, const int* kets, const ShellPair* pairs,
+                     const Shell* shells, const double* Q, const double* dpmax, const int* active,
+                     double tau, int ninst, int* keep, double* cq, double* cpq, double* c32,
+                     hipStream_t s);
 void launch_grad1e(int la, int lb, const Grad1EArgs& a, hipStream_t s);
 
 // ---- ket-list-position buffers of the Fock build (jk.hip) ----
@@ -135,6 +143,10 @@ void launch_sp2_init(const BatchInfo& b, int max_n, const double* F, const doubl
 void launch_sp2_step(const BatchInfo& b, int max_n, const int* nocc, const double* X, double* Xn,
                      const double* st_in, double* st_out, hipStream_t s);
 int sp2_tiles(int max_n);
+// dP = P - Pprev and dpmax[i] = max |dP| of instance i (the instances of b);
+// dpmax needs room for ninst + ninst * ceil(max_n/32)^2 doubles (scf.hip)
+void launch_density_change(const BatchInfo& b, int max_n, const double* P, const double* Pprev,
+                           double* dP, double* dpmax, hipStream_t s);
 // P_new -> P for active instances
 void launch_commit(const BatchInfo& b, int max_n, const double* Pnew, double* P, hipStream_t s);
 // nuclear repulsion energy and gradient per instance

@@ -118,6 +118,49 @@ __global__ void antisym_kernel(BatchInfo b, int max_n, const double* A, double* 
     tmax[((long long)inst * ntm + bi) * ntm + bj] = nan_max(nan_max(wm[0], wm[1]), nan_max(wm[2], wm[3]));
 }
 
+// dP = P - Pprev per 32 x 32 tile, and the largest |dP| of each tile to
+// tmax[inst][bi][bj] (tile grid of max_n), for the instances of b
+__global__ void dp_kernel(BatchInfo b, int max_n, const double* P, const double* Pprev,
+                          double* dP, double* tmax) {
+  __shared__ double wm[4];
+  const int inst = blockIdx.z;
+  if (b.active && !b.active[inst]) return;
+  const int n = b.nbf[inst];
+  const int nt = ntiles_1d(n), ntm = ntiles_1d(max_n);
+  const int bi = blockIdx.x, bj = blockIdx.y;
+  if (bi >= nt || bj >= nt) return;
+  const long long o = b.moff[inst];
+  double m = 0.0;
+  for (int r = threadIdx.y; r < kTile; r += blockDim.y) {
+    const int i = bi * kTile + r, j = bj * kTile + threadIdx.x;
+    if (i < n && j < n) {
+      const long long e = o + (long long)i * n + j;
+      const double d = P[e] - Pprev[e];
+      dP[e] = d;
+      m = nan_max(m, fabs(d));
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) m = nan_max(m, __shfl_xor(m, off, 64));
+  const int tid = threadIdx.y * kTile + threadIdx.x;
+  if ((tid & 63) == 0) wm[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0)
+    tmax[((long long)inst * ntm + bi) * ntm + bj] = nan_max(nan_max(wm[0], wm[1]), nan_max(wm[2], wm[3]));
+}
+
+// out[i] = the largest of instance i's tile maxima (one wavefront per instance)
+__global__ __launch_bounds__(64) void tile_max_kernel(BatchInfo b, int max_n, const double* tmax,
+                                                      double* out) {
+  const int i = blockIdx.x;
+  if (b.active && !b.active[i]) return;
+  const int nt = ntiles_1d(b.nbf[i]), ntm = ntiles_1d(max_n);
+  double m = 0.0;
+  for (int t = threadIdx.x; t < nt * nt; t += 64)
+    m = nan_max(m, tmax[((long long)i * ntm + t / nt) * ntm + t % nt]);
+  for (int off = 32; off > 0; off >>= 1) m = nan_max(m, __shfl_xor(m, off, 64));
+  if (threadIdx.x == 0) out[i] = m;
+}
+
 // DIIS: copy F, e into the slot head[inst]
 __global__ void diis_copy_kernel(DiisArgs d, const double* F, const double* e) {
   const int inst = blockIdx.y;
@@ -585,6 +628,15 @@ void launch_antisym(const BatchInfo& b, int max_n, const double* A, double* out,
   const int nt = ntiles_1d(max_n);
   hipLaunchKernelGGL(antisym_kernel, dim3(nt, nt, b.ninst), dim3(kTile, 8), 0, s, b, max_n, A, out,
                      emax + b.ninst);
+}
+
+void launch_density_change(const BatchInfo& b, int max_n, const double* P, const double* Pprev,
+                           double* dP, double* dpmax, hipStream_t s) {
+  const int nt = ntiles_1d(max_n);
+  hipLaunchKernelGGL(dp_kernel, dim3(nt, nt, b.ninst), dim3(kTile, 8), 0, s, b, max_n, P, Pprev, dP,
+                     dpmax + b.ninst);
+  hipLaunchKernelGGL(tile_max_kernel, dim3(b.ninst), dim3(64), 0, s, b, max_n, dpmax + b.ninst,
+                     dpmax);
 }
 
 void launch_diis_store(const DiisArgs& d, int max_n, const double* F, const double* e,
