@@ -79,7 +79,8 @@ def measured_traffic(kernel):
 def guess_study(w, n_steps, dt_fs=0.25, temperature=300.0):
     """Ring-polymer MD on the workload's beads: the previous-step guess run
     integrates n_steps; the learned-guess run replays the same geometries,
-    trains after every step from step 1 and predicts from step 3."""
+    trains after every step from step 1 (5 full-batch Adam steps) and predicts
+    from step 3."""
     import numpy as np
     import inputs
     from paper_1601_02713_amd import beadscf, md
@@ -93,7 +94,7 @@ def guess_study(w, n_steps, dt_fs=0.25, temperature=300.0):
         poly = md.RingPolymer(z, xb.copy(), v, temperature)
         ref, traj = md.run(e1, poly, n_steps, dt_fs, guess="previous", opts=opts, basis=basis)
         lrn, _ = md.run(e2, poly, n_steps, dt_fs, guess="learned", opts=opts, geometries=traj,
-                        train_from=1, train_steps=30, predict_from=3, basis=basis)
+                        train_from=1, train_steps=5, predict_from=3, basis=basis)
     finally:
         e1.close()
         e2.close()

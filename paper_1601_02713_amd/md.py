@@ -64,7 +64,7 @@ class RingPolymer:
 
 
 def run(engine: beadscf.Engine, poly: RingPolymer, n_steps: int, dt_fs: float, guess: str = "previous",
-        train_from: int = 1, train_steps: int = 30, predict_from: int = 3, opts=None,
+        train_from: int = 1, train_steps: int = 5, predict_from: int = 3, opts=None,
         geometries=None, basis=None):
     """Propagate n_steps; returns the per-step records and the geometries.
 
