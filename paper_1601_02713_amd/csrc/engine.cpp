@@ -263,9 +263,11 @@ struct bscf_ctx {
   int grad_variant[kNumQuartetClasses] = {};
   bool fock_tuned[2] = {false, false};
   bool grad_tuned = false;
-  float tune_ms[2][kNumQuartetClasses][2] = {};
+  // fock_variant[precision][class]: 0 lane (MIXED: the mixed form), 1 cooperative,
+  // 2 (MIXED only) the FP64 lane form; tune_ms holds their times
+  float tune_ms[2][kNumQuartetClasses][3] = {};
   float tune_grad_ms[kNumQuartetClasses][2] = {};
-  // per-lane private (scratch) bytes of every class kernel: [class][fp64, fp32, grad].
+  // per-lane private (scratch) bytes of every class kernel: [class][fp64, mixed, grad].
   // The runtime reserves (and keeps) scratch per hardware queue for full
   // occupancy, so every kernel that uses scratch (class kernels, one-electron
   // and Schwarz kernels) runs on the context's own stream; only scratch-free
@@ -829,7 +831,7 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
           while (g < groups.size() && groups[g].first != key) ++g;
           if (g == groups.size()) groups.push_back({key, {}});
           groups[g].second.push_back(WorkRow{bra, ks.ket_off, lim, 0});
-          P.urows[0].push_back(WorkRow{bra, ks.ket_off, lim, 0});
+          P.urows[0].push_back(WorkRow{bra, ks.ket_off, lim, n64});   // pad: FP64 prefix
           ur_nprim[0].push_back(ks.nprim);
           if (n64 > 0) {
             P.urows[1].push_back(WorkRow{bra, ks.ket_off, n64, 0});
@@ -1106,25 +1108,20 @@ void set_class(FockArgs& a, const bscf_ctx::ClassWork& W, int k) {
   a.ukeep = W.ul[k].d_keep.p;
 }
 
-// Lane-kernel launches of class q: every quartet in FP64, or in MIXED mode
-// the quartets above the split in FP64 and the rest in FP32.
+// Lane-kernel launch of class q: mode 0 every quartet in FP64, mode 2 the
+// quartets above the split in FP64 and the rest in FP32, in one launch.
 template <class Launch>
-void lane_launches(bscf_ctx* c, FockArgs& a, int q, int precision, Launch&& launch) {
+void lane_launches(bscf_ctx* c, FockArgs& a, int q, int mode, Launch&& launch) {
   const QuartetClass* qc = quartet_classes();
   const auto& W = c->work[q];
-  if (precision != BSCF_MIXED) {
-    set_class(a, W, 0);
-    launch(0, [&](hipStream_t s) { qc[q].fock(a, 0, s); });
-  } else {
-    if (!W.ul[1].units.empty()) {
-      set_class(a, W, 1);
-      launch(0, [&](hipStream_t s) { qc[q].fock(a, 0, s); });
-    }
-    if (!W.ul[2].units.empty()) {
-      set_class(a, W, 2);
-      launch(1, [&](hipStream_t s) { qc[q].fock(a, 1, s); });
-    }
-  }
+  set_class(a, W, 0);
+  if (mode == 2) launch(1, [&](hipStream_t s) { qc[q].fock(a, 2, s); });
+  else launch(0, [&](hipStream_t s) { qc[q].fock(a, 0, s); });
+}
+
+// lane mode of class q under the chosen variant
+int lane_mode(bscf_ctx* c, int precision, int q) {
+  return (precision == BSCF_MIXED && c->fock_variant[1][q] == 0) ? 2 : 0;
 }
 
 KetPosArgs ketpos_args(bscf_ctx* c) {
@@ -1162,18 +1159,24 @@ void autotune_fock(bscf_ctx* c, int pcol) {
     if (env && !strcmp(env, "lane")) { c->fock_variant[pcol][q] = 0; continue; }
     if (env && !strcmp(env, "coop")) { c->fock_variant[pcol][q] = 1; continue; }
     set_class(a, W, 0);
-    for (int v = 0; v < 2; ++v) {
+    // variants: 0 the lane form of this precision, 1 cooperative, and in
+    // MIXED mode 2 the FP64 lane form (FP32 integrals do not pay everywhere)
+    const int nv = pcol ? 3 : 2;
+    for (int v = 0; v < nv; ++v) {
       for (int rep = 0; rep < 2; ++rep) {
         HIPCHK(hipEventRecord(e0, c->stream));
-        if (v) qc[q].coop_fock(a, c->stream);
-        else lane_launches(c, a, q, pcol ? BSCF_MIXED : BSCF_FP64,
+        if (v == 1) qc[q].coop_fock(a, c->stream);
+        else lane_launches(c, a, q, (pcol && v == 0) ? 2 : 0,
                            [&](int, auto&& run) { run(c->stream); });
         HIPCHK(hipEventRecord(e1, c->stream));
       }
       HIPCHK(hipEventSynchronize(e1));
       HIPCHK(hipEventElapsedTime(&c->tune_ms[pcol][q][v], e0, e1));
     }
-    c->fock_variant[pcol][q] = c->tune_ms[pcol][q][1] < c->tune_ms[pcol][q][0] ? 1 : 0;
+    int best = 0;
+    for (int v = 1; v < nv; ++v)
+      if (c->tune_ms[pcol][q][v] < c->tune_ms[pcol][q][best]) best = v;
+    c->fock_variant[pcol][q] = best;
   }
   // the lane runs left ket-side sums in Jk: fold them into the throwaway J
   launch_jk_finalize(kp, c->max_ncd, c->d_Jk.p, c->tmp1.p, c->stream);
@@ -1206,15 +1209,14 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
       double* cq = c->d_kept.p + (size_t)q * ni;
       double* cpq = c->d_kept.p + (size_t)(kNumQuartetClasses + q) * ni;
       double* c32 = c->d_kept.p + (size_t)(2 * kNumQuartetClasses + q) * ni;
-      if (c->fock_variant[pc][q]) {
+      if (c->fock_variant[pc][q] == 1) {
         launch_row_keep(W.d_rows.p, (int)W.rows.size(), c->d_kets.p, c->d_pairs.p, c->d_shells.p,
                         c->d_Q.p, c->d_dpmax.p, a.active, tau, ni, nullptr, cq, cpq, nullptr,
                         c->stream);
       } else {
-        for (int k = (pc ? 1 : 0); k <= (pc ? 2 : 0); ++k)
-          launch_row_keep(W.ul[k].d_rows.p, (int)W.ul[k].rows.size(), c->d_kets.p, c->d_pairs.p,
-                          c->d_shells.p, c->d_Q.p, c->d_dpmax.p, a.active, tau, ni,
-                          W.ul[k].d_keep.p, cq, cpq, k == 2 ? c32 : nullptr, c->stream);
+        launch_row_keep(W.ul[0].d_rows.p, (int)W.ul[0].rows.size(), c->d_kets.p, c->d_pairs.p,
+                        c->d_shells.p, c->d_Q.p, c->d_dpmax.p, a.active, tau, ni, W.ul[0].d_keep.p,
+                        cq, cpq, lane_mode(c, precision, q) == 2 ? c32 : nullptr, c->stream);
       }
     }
     a.P = c->dP.p;
@@ -1248,12 +1250,12 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
       run(s);
       if (pk >= 0) prof_end(c, pk, s);
     };
-    if (c->fock_variant[pcol][q]) {
+    if (c->fock_variant[pcol][q] == 1) {
       set_class(a, W, 0);
       launch(c->coop_bytes[q][0], [&](hipStream_t s) { qc[q].coop_fock(a, s); });
     } else {
-      lane_launches(c, a, q, precision, [&](int fp32, auto&& run) {
-        launch(c->private_bytes[q][fp32], run);
+      lane_launches(c, a, q, lane_mode(c, precision, q), [&](int k, auto&& run) {
+        launch(c->private_bytes[q][k], run);
       });
     }
     if (!incremental)   // (an incremental build counts its kept work on the device)
@@ -1261,7 +1263,7 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
         if (!masked || c->h_active[i]) {
           W.done_quart += W.inst_quart[i];
           W.done_primq += W.inst_primq[i];
-          if (precision == BSCF_MIXED && !c->fock_variant[pcol][q]) W.done_quart32 += W.inst_quart32[i];
+          if (lane_mode(c, precision, q) == 2) W.done_quart32 += W.inst_quart32[i];
         }
     W.launches++;
   }
@@ -1338,7 +1340,7 @@ bscf_status bscf_create(int hip_device, void* hip_stream, bscf_ctx** out) {
       const QuartetClass* qc = quartet_classes();
       for (int q = 0; q < kNumQuartetClasses; ++q) {
         c->private_bytes[q][0] = qc[q].fock ? qc[q].fock_private_bytes(0) : 0;
-        c->private_bytes[q][1] = qc[q].fock ? qc[q].fock_private_bytes(1) : 0;
+        c->private_bytes[q][1] = qc[q].fock ? qc[q].fock_private_bytes(2) : 0;   // mixed form
         c->private_bytes[q][2] = qc[q].grad ? qc[q].grad_private_bytes() : 0;
         c->coop_bytes[q][0] = qc[q].coop_private_bytes(0);
         c->coop_bytes[q][1] = qc[q].coop_private_bytes(1);
@@ -2203,7 +2205,8 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
         << ", " << c->private_bytes[q][2] << "], \"variant\": [" << c->fock_variant[0][q] << ", "
         << c->fock_variant[1][q] << ", " << c->grad_variant[q] << "], \"tune_ms\": ["
         << c->tune_ms[0][q][0] << ", " << c->tune_ms[0][q][1] << ", " << c->tune_grad_ms[q][0]
-        << ", " << c->tune_grad_ms[q][1] << "]}";
+        << ", " << c->tune_grad_ms[q][1] << "], \"tune_ms_mixed\": [" << c->tune_ms[1][q][0] << ", "
+        << c->tune_ms[1][q][1] << ", " << c->tune_ms[1][q][2] << "]}";
     }
     s << "}}";
     const std::string str = s.str();

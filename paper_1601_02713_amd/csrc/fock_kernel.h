@@ -68,42 +68,6 @@ struct FockArgs {
   double tau;
 };
 
-// Quartets of unit u that pass an incremental build's test: the kept kets of
-// each row the unit covers are a prefix of the row
-__device__ __forceinline__ int unit_kept(const WorkItem& u, const WorkRow* __restrict__ rows,
-                                         const int* __restrict__ keep) {
-  int rem = u.count, rr = u.row, off = u.off, kept = 0;
-  while (rem > 0) {
-    const int take = min(rows[rr].nket - off, rem);
-    kept += max(0, min(keep[rr] - off, take));
-    rem -= take;
-    ++rr;
-    off = 0;
-  }
-  return kept;
-}
-
-// Row rr and position k0 in it of kept quartet t (t < unit_kept) of unit u
-__device__ __forceinline__ void unit_kept_quartet(const WorkItem& u,
-                                                  const WorkRow* __restrict__ rows,
-                                                  const int* __restrict__ keep, int t, int& rr,
-                                                  int& k0) {
-  int rem = u.count, off = u.off;
-  rr = u.row;
-  for (;;) {
-    const int take = min(rows[rr].nket - off, rem);
-    const int kc = max(0, min(keep[rr] - off, take));
-    if (t < kc) {
-      k0 = off + t;
-      return;
-    }
-    t -= kc;
-    rem -= take;
-    ++rr;
-    off = 0;
-  }
-}
-
 struct SchwarzArgs {
   const int* pair_ids;     // pairs of one class
   int npairs;
@@ -208,7 +172,61 @@ __host__ __device__ constexpr int unit_lds_doubles(int la, int lb, int nmax, int
   return 2 * (ncart(la) + ncart(lb)) * nmax + 12 * max_prims;
 }
 
-template <class CL, typename R>
+// Quartets of unit u selected by sel (0: the kept ones of every row;
+// 1: those in each row's FP64 prefix, row.pad kets long; 2: the rest), with
+// keep (incremental builds) bounding each row's kept prefix when given
+__device__ __forceinline__ void unit_sel_range(const WorkRow& w, const int* keep, int rr, int sel,
+                                               int& lo, int& hi) {
+  hi = keep ? keep[rr] : w.nket;
+  lo = 0;
+  if (sel == 1) hi = min(hi, w.pad);
+  else if (sel == 2) lo = w.pad;
+}
+
+__device__ __forceinline__ int unit_sel_count(const WorkItem& u, const WorkRow* __restrict__ rows,
+                                              const int* keep, int sel) {
+  int rem = u.count, rr = u.row, off = u.off, cnt = 0;
+  while (rem > 0) {
+    const WorkRow w = rows[rr];
+    const int take = min(w.nket - off, rem);
+    int lo, hi;
+    unit_sel_range(w, keep, rr, sel, lo, hi);
+    cnt += max(0, min(off + take, hi) - max(off, lo));
+    rem -= take;
+    ++rr;
+    off = 0;
+  }
+  return cnt;
+}
+
+// Row rr and position k0 of selected quartet t (t < unit_sel_count) of unit u
+__device__ __forceinline__ void unit_sel_quartet(const WorkItem& u,
+                                                 const WorkRow* __restrict__ rows,
+                                                 const int* keep, int sel, int t, int& rr,
+                                                 int& k0) {
+  int rem = u.count, off = u.off;
+  rr = u.row;
+  for (;;) {
+    const WorkRow w = rows[rr];
+    const int take = min(w.nket - off, rem);
+    int lo, hi;
+    unit_sel_range(w, keep, rr, sel, lo, hi);
+    const int b = max(off, lo), c = max(0, min(off + take, hi) - b);
+    if (t < c) {
+      k0 = b + t;
+      return;
+    }
+    t -= c;
+    rem -= take;
+    ++rr;
+    off = 0;
+  }
+}
+
+// MIX (with R = double): the mixed-precision form in one launch: the unit's
+// quartets in its rows' FP64 prefixes first, with FP64 integrals, then the rest
+// with FP32 integrals, over one set of LDS rows and one flush.
+template <class CL, typename R, bool MIX = false>
 __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
   constexpr int NA = ncart(CL::LA), NB = ncart(CL::LB), NC = ncart(CL::LC), ND = ncart(CL::LD);
   constexpr int NR = NA + NB;
@@ -222,8 +240,8 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
   if (!a.active[inst]) return;
   // incremental build: a unit whose quartets all fall below the bound does nothing
   const bool screen = a.dpmax != nullptr;
-  const int total = screen ? unit_kept(u, a.urows, a.ukeep) : u.count;
-  if (total == 0) return;
+  const int* keep = screen ? a.ukeep : nullptr;
+  if (screen && unit_sel_count(u, a.urows, keep, 0) == 0) return;
   const long long mo = a.moff[inst];
   const int n = a.nbf[inst];
   const int m0 = sa.bf, n0 = sb.bf;
@@ -251,12 +269,16 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
       jab[i][j] = 0.0;
     }
   const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
+  // one pass over the quartets of selection sel with integrals of precision RP
+  auto pass = [&](auto prec, int sel) {
+  using RP = decltype(prec);
+  const int total = (screen || sel != 0) ? unit_sel_count(u, a.urows, keep, sel) : u.count;
   for (int c0 = 0; c0 < total; c0 += kWave) {
     const int t = c0 + lane;
     const bool valid = t < total;
     int rr, k0;
-    if (screen) {
-      unit_kept_quartet(u, a.urows, a.ukeep, valid ? t : 0, rr, k0);
+    if (screen || sel != 0) {
+      unit_sel_quartet(u, a.urows, keep, sel, valid ? t : 0, rr, k0);
     } else {
       rr = u.row;
       k0 = u.off + (valid ? t : 0);
@@ -273,9 +295,9 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
     const Shell sc = a.shells[ket.a], sd = a.shells[ket.b];
     const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
     const int2 kp = a.kpos[pos];
-    R v[CL::NOUT];
-    eri_block<CL, R>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64, a.boys32,
-                     v);
+    RP v[CL::NOUT];
+    eri_block<CL, RP>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64, a.boys32,
+                      v);
     const double g = ((bra.a == bra.b) ? 1.0 : 2.0) * ((ket.a == ket.b) ? 1.0 : 2.0) *
                      ((kid == bid) ? 1.0 : 2.0);
     const double fj = valid ? 0.5 * g : 0.0;
@@ -345,6 +367,13 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
         for (int l = 0; l < ND; ++l) atomicAdd(&Kacc[(NA + j) * n + s0 + l], fk * kbd[j][l]);
       }
     }
+  }
+  };
+  if constexpr (MIX) {
+    pass(double(0), 1);
+    pass(float(0), 2);
+  } else {
+    pass(R(0), 0);
   }
   __syncthreads();
   double* K = a.K + mo;

@@ -534,16 +534,19 @@ def main(outdir):
             write_if_changed(os.path.join(outdir, f"eri_{tag}.h"), "\n".join(hdr))
             tu = [f"// generated by gen_eri.py: kernels of class ({la}{lb}|{lc}{ld})",
                   '#include "fock_kernel.h"', f'#include "eri_{tag}.h"', "namespace bscf {",
-                  f"void launch_fock_{tag}(const FockArgs& a, int fp32, hipStream_t s) {{",
+                  f"// mode 0: FP64; 1: FP32; 2: mixed (each row's FP64 prefix in FP64, the rest in FP32)",
+                  f"void launch_fock_{tag}(const FockArgs& a, int mode, hipStream_t s) {{",
                   "  if (a.nunits == 0) return;",
                   f"  const size_t lds = sizeof(double) * unit_lds_doubles({la}, {lb}, a.nmax, a.max_prims);",
-                  f"  if (fp32) hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, float>), dim3(a.nunits), dim3(64), lds, s, a);",
+                  f"  if (mode == 2) hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, double, true>), dim3(a.nunits), dim3(64), lds, s, a);",
+                  f"  else if (mode == 1) hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, float>), dim3(a.nunits), dim3(64), lds, s, a);",
                   f"  else hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, double>), dim3(a.nunits), dim3(64), lds, s, a);",
                   "}",
-                  f"int fock_private_bytes_{tag}(int fp32) {{",
+                  f"int fock_private_bytes_{tag}(int mode) {{",
                   "  hipFuncAttributes at{};",
-                  f"  const void* f = fp32 ? reinterpret_cast<const void*>(&fock_unit_kernel<Cls{tag}, float>)",
-                  f"                       : reinterpret_cast<const void*>(&fock_unit_kernel<Cls{tag}, double>);",
+                  f"  const void* f = mode == 2 ? reinterpret_cast<const void*>(&fock_unit_kernel<Cls{tag}, double, true>)",
+                  f"                : mode == 1 ? reinterpret_cast<const void*>(&fock_unit_kernel<Cls{tag}, float>)",
+                  f"                            : reinterpret_cast<const void*>(&fock_unit_kernel<Cls{tag}, double>);",
                   "  if (hipFuncGetAttributes(&at, f) != hipSuccess) return -1;",
                   "  return (int)at.localSizeBytes;",
                   "}",

@@ -79,7 +79,8 @@ void launch_jk_finalize(const KetPosArgs& a, int max_ncd, double* Jk, double* J,
 // Schwarz bound, so the count is a binary search.  One thread per row; rows of
 // instances that are not active are left alone.  When keep is given the count
 // goes there; when cq is given the kept quartets and primitive quartets (and,
-// with c32, quartets again) are added to cq[inst], cpq[inst] (c32[inst]).
+// with c32, the kept quartets past the row's FP64 prefix of w.pad kets) are
+// added to cq[inst], cpq[inst] (c32[inst]).
 __global__ void row_keep_kernel(const WorkRow* __restrict__ rows, int nrows,
                                 const int* __restrict__ kets, const ShellPair* __restrict__ pairs,
                                 const Shell* __restrict__ shells, const double* __restrict__ Q,
@@ -110,7 +111,7 @@ __global__ void row_keep_kernel(const WorkRow* __restrict__ rows, int nrows,
         const int knp = pairs[kets[w.ket0]].nprim;   // one primitive count per row
         atomicAdd(&part[inst], double(lo));
         atomicAdd(&part[ninst + inst], double(lo) * bra.nprim * knp);
-        if (c32) atomicAdd(&part[2 * ninst + inst], double(lo));
+        if (c32) atomicAdd(&part[2 * ninst + inst], double(max(0, lo - w.pad)));
       }
     }
   }

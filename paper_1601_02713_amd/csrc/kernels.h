@@ -57,8 +57,8 @@ void launch_prim_pairs(const PrimPairSetupArgs& a, hipStream_t s);
 void launch_onee(int la, int lb, const OneEArgs& a, hipStream_t s);
 // keep[r] = kets of work row r with Q_ab Q_cd min(dpmax[inst], 1) >= tau for
 // the rows of active instances (keep may be NULL); with cq, the kept
-// quartets, primitive quartets (and, with c32, quartets again) are added per
-// instance to cq, cpq (c32) (jk.hip)
+// quartets, primitive quartets (and, with c32, kept quartets past each row's
+// FP64 prefix, row.pad) are added per instance to cq, cpq (c32) (jk.hip)
 void launch_row_keep(const WorkRow* rows, int nrows, const int* kets, const ShellPair* pairs,
                      const Shell* shells, const double* Q, const double* dpmax, const int* active,
                      double tau, int ninst, int* keep, double* cq, double* cpq, double* c32,
