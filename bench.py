@@ -202,9 +202,9 @@ def main():
                  for k, v in cls.items() if v["launches"]}
     d = cls[dom]
     ach = d["done_flops"] / (d["kernel_ms"] * 1e-3) / 1e12 if d["kernel_ms"] > 0 else 0.0
-    dom_kernel = {"lane": f"fock_unit_kernel<Cls{dom}, double>" if fvar == 0
+    dom_kernel = {"lane": f"fock_unit_kernel<Cls{dom}, double, false>" if fvar == 0
                   else f"fock_unit_kernel<Cls{dom}, double, true>",
-                  "lane-fp64": f"fock_unit_kernel<Cls{dom}, double>",
+                  "lane-fp64": f"fock_unit_kernel<Cls{dom}, double, false>",
                   "coop": f"coop_fock_kernel<CoopE{dom}>"}[per_class[dom]["kernel"]]
     n_inst = len(xs)
     out = {
