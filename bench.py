@@ -236,6 +236,8 @@ def main():
                                "t_work_host_ms")},
         "density": {"method": "sp2", "calls_per_step": st_json["sp2_calls"] / args.steps,
                     "projection_steps_per_call": st_json["sp2_steps"] / max(st_json["sp2_calls"], 1),
+                    "projection_steps_needed_per_call":
+                        st_json["sp2_steps_needed"] / max(st_json["sp2_calls"], 1),
                     "fallbacks": st_json["sp2_fallbacks"]},
         "roofline": {"bound": "alu",
                      "kernel": dom_kernel,

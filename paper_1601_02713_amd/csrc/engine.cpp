@@ -53,17 +53,22 @@ constexpr int kUnitQuartets = 256;
 // cooperatively), which bounds every queue's reservation to about 1 GiB.
 constexpr int kMaxLaneScratch = 2048;
 
-// SP2 purification: at most this many projection steps per density, and the
-// idempotency error Tr X - Tr X^2 = sum_k l_k (1 - l_k) below which a replica's
-// projector counts as converged (two more steps then square the residual
-// occupation error away).
 // Incremental Fock builds: a full build at the first SCF iteration and every
 // kFullEvery iterations, which bounds the accumulated effect of the skipped
 // quartets.
 constexpr int kFullEvery = 12;
 
+// SP2 purification: at most kSp2MaxSteps projection steps per density; a
+// replica's projector counts as converged once the idempotency error
+// Tr X - Tr X^2 = sum_k l_k (1 - l_k) is below kSp2Tol and Tr X is N/2 within
+// kSp2TraceTol (two more steps then square the residual occupation error
+// away).  A call launches the step count the last call needed plus
+// kSp2Margin before it looks at the result; steps past a replica's need are
+// copies.
 constexpr int kSp2MaxSteps = 100;
 constexpr double kSp2Tol = 1e-11;
+constexpr double kSp2TraceTol = 1e-6;
+constexpr int kSp2Margin = 4;
 
 thread_local std::string g_err;
 
@@ -112,6 +117,33 @@ struct DevBuf {
   void upload(const std::vector<T>& v, hipStream_t s) {
     resize(v.size());
     if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+};
+
+// Pinned host memory (hipHostMalloc) for the small device-to-host reads the
+// SCF loop waits on.
+template <typename T>
+struct PinBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  PinBuf() = default;
+  PinBuf(const PinBuf&) = delete;
+  PinBuf& operator=(const PinBuf&) = delete;
+  ~PinBuf() { release(); }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void resize(size_t m) {
+    if (m <= n && p) return;
+    release();
+    if (m == 0) m = 1;
+    if (hipHostMalloc((void**)&p, m * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      throw Error(BSCF_E_NOMEM, "hipHostMalloc of " + std::to_string(m * sizeof(T)) + " bytes failed");
+    }
+    n = m;
   }
 };
 
@@ -318,16 +350,16 @@ struct bscf_ctx {
     std::vector<WorkRow> rows;
     DevBuf<WorkItem> d_items;
     DevBuf<WorkRow> d_rows;
-    // unit lists: kUnitsAll every screened quartet; kUnits64 / kUnits32 the
-    // quartets with Q_ab Q_cd at or above / below the FP32 split of MIXED mode
+    // per-bra units over every screened quartet; each row's pad is its FP64
+    // prefix, the kets with Q_ab Q_cd at or above the FP32 split of MIXED mode
     struct UnitList {
       std::vector<WorkItem> units;
       std::vector<WorkRow> rows;
       DevBuf<WorkItem> d_units;
       DevBuf<WorkRow> d_rows;
       DevBuf<int> d_keep;   // kets per row that an incremental build keeps
-    } ul[3];
-    double nquart32 = 0;                 // quartets of the FP32 list
+    } ul;
+    double nquart32 = 0;                 // quartets below the FP32 split
     std::vector<double> inst_quart32;    // per instance
     double done_quart32 = 0;
     bool lds_ok = true;   // the lane kernel's LDS rows fit one workgroup
@@ -377,12 +409,22 @@ struct bscf_ctx {
   DevBuf<double> Fhist, Ehist, diisB, diisC;
   DevBuf<int> diis_count, diis_head, d_info;
   // SP2 purification: per-step (Tr X, Tr X^2) of every instance, Gershgorin
-  // bounds, and the orbital-commit mask; sp2_pred is the step count the last
-  // call needed (the next call runs that many before its first check)
+  // bounds, the first converged step of every instance (two alternating
+  // arrays of ninst), and the orbital-commit mask.  sp2_pred[0] is the step
+  // count the last core guess needed; sp2_pred[1 + it] that of SCF iteration
+  // it (the need falls over an SCF run, and runs of one batch repeat the
+  // pattern); iterations past the table use its last entry
+  static constexpr int kSp2PredIters = 64;
   DevBuf<double> d_sp2, d_sp2b;
-  DevBuf<int> d_omask;
-  int sp2_pred = 24;
-  long long sp2_calls = 0, sp2_steps = 0, sp2_fallbacks = 0;
+  DevBuf<int> d_sp2c, d_omask;
+  int sp2_pred[1 + kSp2PredIters] = {};
+  long long sp2_calls = 0, sp2_steps = 0, sp2_needed = 0, sp2_fallbacks = 0;
+  // what the SCF loop reads once per iteration: [ninst] active flags, then
+  // [ninst] SP2 first converged steps; packed on the device, then one copy
+  DevBuf<int> d_pin;
+  PinBuf<int> h_pin;
+  DevBuf<double> d_wmin;    // smallest overlap eigenvalue per instance
+  PinBuf<double> h_wmin;
   bool have_C = false;
   std::vector<int> h_active;   // host copy of the active flags
   bool profiling = false;
@@ -477,17 +519,17 @@ void build_orthogonaliser(bscf_ctx* c) {
   const long long mt = c->mtot;
   HIPCHK(hipMemcpyAsync(c->eig.p, c->S.p, mt * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   syevd(c, c->eig.p, c->tmp2.p);
-  // smallest eigenvalue check
-  std::vector<double> wmin(c->ninst);
-  for (int i = 0; i < c->ninst; ++i)
-    HIPCHK(hipMemcpyAsync(&wmin[i], c->tmp2.p + c->moff[i], sizeof(double), hipMemcpyDeviceToHost,
-                          c->stream));
+  // smallest eigenvalue check (gathered on the device, one read)
+  BatchInfo b = c->batch(false);
+  hipLaunchKernelGGL(min_eig_kernel, dim3((c->ninst + 63) / 64), dim3(64), 0, c->stream, b,
+                     c->tmp2.p, c->d_wmin.p);
+  HIPCHK(hipMemcpyAsync(c->h_wmin.p, c->d_wmin.p, c->ninst * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
   sync(c);
   for (int i = 0; i < c->ninst; ++i)
-    need(wmin[i] > 1e-7, BSCF_E_UNSUPPORTED,
+    need(c->h_wmin.p[i] > 1e-7, BSCF_E_UNSUPPORTED,
          "overlap matrix of instance " + std::to_string(i) + " is near-singular (min eigenvalue " +
-             std::to_string(wmin[i]) + ")");
-  BatchInfo b = c->batch(false);
+             std::to_string(c->h_wmin.p[i]) + ")");
   const long long nn = (long long)c->max_n * c->max_n;
   const unsigned gx = (unsigned)std::min<long long>((nn + 255) / 256, 1024);
   hipLaunchKernelGGL(scale_cols_kernel, dim3(gx, c->ninst), dim3(256), 0, c->stream, b, c->eig.p,
@@ -527,76 +569,119 @@ void density_from_orbitals(bscf_ctx* c, double* Pout) {
   }
 }
 
-// SP2 on F' (in eig) for the instances with act[i] set (the device mask b.active
-// matches): X_k alternates between tmp1 and tmp2, each step one fused
-// product-and-update launch; then P = 2 X X_k X.  False when some of them has
-// not converged after kSp2MaxSteps steps (no gap).
-bool density_sp2(bscf_ctx* c, const BatchInfo& b, const std::vector<int>& act, double* Pout) {
-  const hipStream_t st = c->stream;
-  const int ni = c->ninst;
-  const int ntm = sp2_tiles(c->max_n);
-  const long long row = 2LL * ni * ntm;   // statistics of one step
-  double* stats = c->d_sp2.p;
+// SP2 on F' (in eig) for the instances of the device mask of b.  X_k
+// alternates between tmp1 and tmp2, each step one fused product-and-update
+// launch that also decides, per instance, when the projection is finished
+// (launch_sp2_step); the first converged step of instance i after k steps is
+// at d_sp2c[(k & 1) * ninst + i].
+void sp2_start(bscf_ctx* c, const BatchInfo& b) {
+  launch_sp2_bounds(b, c->max_n, c->eig.p, c->d_sp2b.p, c->stream);
+  launch_sp2_init(b, c->max_n, c->eig.p, c->d_sp2b.p, c->tmp1.p, c->d_sp2.p, c->d_sp2c.p,
+                  c->stream);
+}
+
+// steps k0 .. k1 - 1
+void sp2_steps(bscf_ctx* c, const BatchInfo& b, int k0, int k1) {
+  const long long row = 2LL * c->ninst * sp2_tiles(c->max_n);   // statistics of one step
   double* buf[2] = {c->tmp1.p, c->tmp2.p};
-  launch_sp2_bounds(b, c->max_n, c->eig.p, c->d_sp2b.p, st);
-  launch_sp2_init(b, c->max_n, c->eig.p, c->d_sp2b.p, buf[0], stats, st);
-  int k = 0;
-  auto step = [&] {
-    launch_sp2_step(b, c->max_n, c->d_nocc.p, buf[k & 1], buf[(k + 1) & 1], stats + k * row,
-                    stats + (k + 1) * row, st);
-    ++k;
-  };
-  int target = std::min(std::max(c->sp2_pred, 1), kSp2MaxSteps);
-  std::vector<double> h;
-  for (;;) {
-    while (k < target) step();
-    h.resize((size_t)(k + 1) * row);
-    HIPCHK(hipMemcpyAsync(h.data(), stats, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    sync(c);
-    // first converged step of every replica taking part
-    int kc = 0;
-    bool all = true;
-    for (int i = 0; i < ni && all; ++i) {
-      if (!act[i]) continue;
-      const int nt = (c->nbf[i] + 31) / 32;
-      int j = 0;
-      for (; j <= k; ++j) {
-        double tr = 0.0, t2 = 0.0;
-        const double* r = h.data() + (size_t)j * row + (size_t)i * ntm * 2;
-        for (int t = 0; t < nt * nt; ++t) {
-          tr += r[2 * t];
-          t2 += r[2 * t + 1];
-        }
-        if (tr - t2 < kSp2Tol && std::fabs(tr - c->nocc[i]) < 1e-6) break;
-      }
-      if (j > k) all = false;
-      else kc = std::max(kc, j);
-    }
-    if (all) {
-      c->sp2_pred = kc + 2;
-      while (k < std::min(kc + 2, kSp2MaxSteps)) step();   // stats rows stay within the buffer
-      break;
-    }
-    if (k >= kSp2MaxSteps) return false;
-    target = std::min(k + 4, kSp2MaxSteps);
-  }
-  c->sp2_calls++;
-  c->sp2_steps += k;
-  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->X.p, buf[k & 1], 0.0,
-       c->eig.p);
+  for (int k = k0; k < k1; ++k)
+    launch_sp2_step(b, c->max_n, c->d_nocc.p, buf[k & 1], buf[(k + 1) & 1], c->d_sp2.p + k * row,
+                    c->d_sp2.p + (k + 1) * row, k, kSp2Tol, kSp2TraceTol,
+                    c->d_sp2c.p + (k & 1) * c->ninst, c->d_sp2c.p + ((k + 1) & 1) * c->ninst,
+                    c->stream);
+}
+
+// P = 2 X X_k X into Pout
+void sp2_project(bscf_ctx* c, int k, double* Pout) {
+  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->X.p,
+       (k & 1) ? c->tmp2.p : c->tmp1.p, 0.0, c->eig.p);
   gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 2.0, c->eig.p, c->X.p, 0.0,
        Pout);
+}
+
+// Step predictor index: the core guess, or SCF iteration it.
+int sp2_slot(int it) { return it < 0 ? 0 : 1 + std::min(it, bscf_ctx::kSp2PredIters - 1); }
+
+// Launch a whole SP2 density without waiting: the step count predicted by
+// sp2_pred[which] (or, where that has no record yet, by the previous slot)
+// plus a margin, then the projector into Pout.  Returns the steps launched.
+int sp2_launch(bscf_ctx* c, const BatchInfo& b, int which, double* Pout) {
+  int pred = 0;
+  for (int w = which; w >= 0 && pred == 0; --w) pred = c->sp2_pred[w];
+  if (pred == 0) pred = 48;
+  const int k = std::min(pred + kSp2Margin, kSp2MaxSteps);
+  sp2_start(c, b);
+  sp2_steps(c, b, 0, k);
+  sp2_project(c, k, Pout);
+  return k;
+}
+
+// Queue the read of the first converged steps after k steps into h_pin[ninst..].
+void sp2_read(bscf_ctx* c, int k) {
+  HIPCHK(hipMemcpyAsync(c->h_pin.p + c->ninst, c->d_sp2c.p + (k & 1) * c->ninst,
+                        c->ninst * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+}
+
+// After sp2_read(c, k) and a synchronisation: true when every instance of
+// act finished within k steps (then sp2_pred[which] becomes the largest need).
+bool sp2_finished(bscf_ctx* c, const std::vector<int>& act, int k, int which) {
+  const int* first = c->h_pin.p + c->ninst;
+  int need = 0;
+  for (int i = 0; i < c->ninst; ++i) {
+    if (!act[i]) continue;
+    if (first[i] < 0 || first[i] + 2 > k) return false;
+    need = std::max(need, first[i] + 2);
+  }
+  if (need > 0) {
+    c->sp2_pred[which] = need;
+    c->sp2_needed += need;
+  }
   return true;
 }
 
-// density of the extrapolated Fock matrix Fb for the replicas with act[i]
-// (device mask of b): SP2 by default, the eigenvector route on request or when
-// SP2 finds no gap
+// Continue a projection that has not finished after k steps, in batches of a
+// quarter of the steps so far (at least 4) with a check after each; on
+// success the projector goes to Pout.  False when some instance of act has
+// not converged after kSp2MaxSteps (no gap).  k is updated to the steps
+// launched.
+bool sp2_extend(bscf_ctx* c, const BatchInfo& b, const std::vector<int>& act, int which, int& k,
+                double* Pout) {
+  while (k < kSp2MaxSteps) {
+    const int k1 = std::min(k + std::max(4, k / 4), kSp2MaxSteps);
+    sp2_steps(c, b, k, k1);
+    k = k1;
+    sp2_read(c, k);
+    sync(c);
+    if (sp2_finished(c, act, k, which)) {
+      sp2_project(c, k, Pout);
+      return true;
+    }
+  }
+  return false;
+}
+
+// SP2 density of the instances with act[i] set (the device mask of b
+// matches), waiting for the result; which selects the step predictor.  False
+// when some has not converged after kSp2MaxSteps steps.
+bool density_sp2(bscf_ctx* c, const BatchInfo& b, const std::vector<int>& act, int which,
+                 double* Pout) {
+  int k = sp2_launch(c, b, which, Pout);
+  sp2_read(c, k);
+  sync(c);
+  const bool ok = sp2_finished(c, act, k, which) || sp2_extend(c, b, act, which, k, Pout);
+  c->sp2_calls++;
+  c->sp2_steps += k;
+  return ok;
+}
+
+// density of the Fock matrix Fb (the core Hamiltonian of a guess) for the
+// replicas with act[i] (device mask of b): SP2 by default, the eigenvector
+// route on request or when SP2 finds no gap
 void density_from_fock(bscf_ctx* c, const double* Fb, const BatchInfo& b,
                        const std::vector<int>& act, int method, double* Pout) {
   if (method == BSCF_DENSITY_SP2) {
     ortho_fock(c, Fb);
-    if (density_sp2(c, b, act, Pout)) return;
+    if (density_sp2(c, b, act, sp2_slot(-1), Pout)) return;
     c->sp2_fallbacks++;
   }
   orbitals_from_fock(c, Fb);
@@ -762,8 +847,8 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
   struct Part {
     std::vector<WorkRow> rows;     // item rows (grouped by primitive counts)
     std::vector<Tmp> tmp;          // 64-quartet items over them
-    std::vector<WorkRow> urows[3];
-    std::vector<Tmp> utmp[3];      // per-bra units of the three unit lists
+    std::vector<WorkRow> urows;
+    std::vector<Tmp> utmp;         // per-bra units over urows
     double nquart = 0, nprimq = 0, nquart32 = 0;
   };
   const int ni = c->ninst;
@@ -781,10 +866,10 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
   auto build_part = [&](int q, int i) {
     Part& P = parts[(size_t)q * ni + i];
     const int X = pclass(qc[q].la, qc[q].lb), Y = pclass(qc[q].lc, qc[q].ld);
-    // units of one bra over its rows [r0, r1) of list k: up to kUnitQuartets
+    // units of one bra over its unit rows [r0, r1): up to kUnitQuartets
     // consecutive quartets across its rows (all ket primitive counts)
-    auto add_units = [&](int k, int r0, const std::vector<int>& kn, int bnprim) {
-      auto& rows = P.urows[k];
+    auto add_units = [&](int r0, const std::vector<int>& kn, int bnprim) {
+      auto& rows = P.urows;
       const int r1 = (int)rows.size();
       int rr = r0, off = 0;
       while (rr < r1) {
@@ -800,10 +885,10 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
             off = 0;
           }
         }
-        P.utmp[k].push_back({u, cost});
+        P.utmp.push_back({u, cost});
       }
     };
-    std::vector<int> ur_nprim[3];
+    std::vector<int> ur_nprim;
     // rows of this instance grouped by (bra, ket) primitive counts
     std::vector<std::pair<std::pair<int, int>, std::vector<WorkRow>>> groups;
     for (const Sub& bs : subs[i][X])
@@ -812,11 +897,8 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
         const double qb = bs.q[r];
         const int sb = sub_of[bra];
         const auto& kv = subs[i][Y];
-        int ur0[3];
-        for (int k = 0; k < 3; ++k) {
-          ur0[k] = (int)P.urows[k].size();
-          ur_nprim[k].clear();
-        }
+        const int ur0 = (int)P.urows.size();
+        ur_nprim.clear();
         for (int t = 0; t < (int)kv.size(); ++t) {
           const Sub& ks = kv[t];
           int lim = tau > 0.0 ? prefix(ks.q, qb, tau) : (int)ks.q.size();
@@ -831,21 +913,13 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
           while (g < groups.size() && groups[g].first != key) ++g;
           if (g == groups.size()) groups.push_back({key, {}});
           groups[g].second.push_back(WorkRow{bra, ks.ket_off, lim, 0});
-          P.urows[0].push_back(WorkRow{bra, ks.ket_off, lim, n64});   // pad: FP64 prefix
-          ur_nprim[0].push_back(ks.nprim);
-          if (n64 > 0) {
-            P.urows[1].push_back(WorkRow{bra, ks.ket_off, n64, 0});
-            ur_nprim[1].push_back(ks.nprim);
-          }
-          if (lim > n64) {
-            P.urows[2].push_back(WorkRow{bra, ks.ket_off + n64, lim - n64, 0});
-            ur_nprim[2].push_back(ks.nprim);
-          }
+          P.urows.push_back(WorkRow{bra, ks.ket_off, lim, n64});   // pad: FP64 prefix
+          ur_nprim.push_back(ks.nprim);
           P.nquart32 += lim - n64;
           P.nquart += lim;
           P.nprimq += double(lim) * bs.nprim * ks.nprim;
         }
-        for (int k = 0; k < 3; ++k) add_units(k, ur0[k], ur_nprim[k], bs.nprim);
+        add_units(ur0, ur_nprim, bs.nprim);
       }
     // tile every group with items of up to 64 quartets (one per lane)
     for (auto& gr : groups) {
@@ -875,26 +949,22 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
     W.inst_quart.assign(ni, 0.0);
     W.inst_primq.assign(ni, 0.0);
     W.inst_quart32.assign(ni, 0.0);
-    std::vector<Tmp> tmp, utmp[3];
+    std::vector<Tmp> tmp, utmp;
     W.rows.clear();
-    for (auto& L : W.ul) L.rows.clear();
+    W.ul.rows.clear();
     {
-      size_t nr = 0, nt = 0, nur[3] = {0, 0, 0}, nut[3] = {0, 0, 0};
+      size_t nr = 0, nt = 0, nur = 0, nut = 0;
       for (int i = 0; i < ni; ++i) {
         const Part& P = parts[(size_t)q * ni + i];
         nr += P.rows.size();
         nt += P.tmp.size();
-        for (int k = 0; k < 3; ++k) {
-          nur[k] += P.urows[k].size();
-          nut[k] += P.utmp[k].size();
-        }
+        nur += P.urows.size();
+        nut += P.utmp.size();
       }
       W.rows.reserve(nr);
       tmp.reserve(nt);
-      for (int k = 0; k < 3; ++k) {
-        W.ul[k].rows.reserve(nur[k]);
-        utmp[k].reserve(nut[k]);
-      }
+      W.ul.rows.reserve(nur);
+      utmp.reserve(nut);
     }
     for (int i = 0; i < ni; ++i) {
       Part& P = parts[(size_t)q * ni + i];
@@ -904,13 +974,11 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
         t.w.row += r0;
         tmp.push_back(t);
       }
-      for (int k = 0; k < 3; ++k) {
-        const int u0 = (int)W.ul[k].rows.size();
-        W.ul[k].rows.insert(W.ul[k].rows.end(), P.urows[k].begin(), P.urows[k].end());
-        for (Tmp t : P.utmp[k]) {
-          t.w.row += u0;
-          utmp[k].push_back(t);
-        }
+      const int u0 = (int)W.ul.rows.size();
+      W.ul.rows.insert(W.ul.rows.end(), P.urows.begin(), P.urows.end());
+      for (Tmp t : P.utmp) {
+        t.w.row += u0;
+        utmp.push_back(t);
       }
       W.nquart += P.nquart;
       W.nprimq += P.nprimq;
@@ -934,11 +1002,10 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
     // item keys: 4096 - cost (primitive counts per shell pair stay below 64);
     // unit keys: 320 - eighths of octaves (costs stay below 2^40)
     counting(tmp, W.items, [](double cst) { return 4096 - std::min((int)cst, 4096); }, 4097);
-    for (int k = 0; k < 3; ++k)
-      counting(utmp[k], W.ul[k].units, [](double cst) {
-        const int b = cst > 1.0 ? (int)(8.0 * std::log2(cst)) : 0;
-        return 320 - std::min(b, 320);
-      }, 321);
+    counting(utmp, W.ul.units, [](double cst) {
+      const int b = cst > 1.0 ? (int)(8.0 * std::log2(cst)) : 0;
+      return 320 - std::min(b, 320);
+    }, 321);
     W.lds_ok = sizeof(double) * (size_t)unit_lds_doubles(qc[q].la, qc[q].lb, c->max_n,
                                                           c->max_prims) <= c->max_lds_bytes;
   };
@@ -972,11 +1039,9 @@ void build_work_device(bscf_ctx* c) {
     auto& W = c->work[q];
     W.d_items.upload(W.items, c->stream);
     W.d_rows.upload(W.rows, c->stream);
-    for (auto& L : W.ul) {
-      L.d_units.upload(L.units, c->stream);
-      L.d_rows.upload(L.rows, c->stream);
-      L.d_keep.resize(L.rows.size());
-    }
+    W.ul.d_units.upload(W.ul.units, c->stream);
+    W.ul.d_rows.upload(W.ul.rows, c->stream);
+    W.ul.d_keep.resize(W.ul.rows.size());
   }
   c->d_kets.upload(c->kets, c->stream);
   // ket-position buffers; Jk is kept zero between builds by jk_finalize
@@ -1097,15 +1162,15 @@ FockArgs fock_args(bscf_ctx* c, double* J, double* K, const int* active) {
   return a;
 }
 
-// Point a at the 64-quartet items of class W and at its unit list k.
-void set_class(FockArgs& a, const bscf_ctx::ClassWork& W, int k) {
+// Point a at the 64-quartet items and the units of class W.
+void set_class(FockArgs& a, const bscf_ctx::ClassWork& W) {
   a.items = W.d_items.p;
   a.nitems = (int)W.items.size();
   a.rows = W.d_rows.p;
-  a.units = W.ul[k].d_units.p;
-  a.nunits = (int)W.ul[k].units.size();
-  a.urows = W.ul[k].d_rows.p;
-  a.ukeep = W.ul[k].d_keep.p;
+  a.units = W.ul.d_units.p;
+  a.nunits = (int)W.ul.units.size();
+  a.urows = W.ul.d_rows.p;
+  a.ukeep = W.ul.d_keep.p;
 }
 
 // Lane-kernel launch of class q: mode 0 every quartet in FP64, mode 2 the
@@ -1114,7 +1179,7 @@ template <class Launch>
 void lane_launches(bscf_ctx* c, FockArgs& a, int q, int mode, Launch&& launch) {
   const QuartetClass* qc = quartet_classes();
   const auto& W = c->work[q];
-  set_class(a, W, 0);
+  set_class(a, W);
   if (mode == 2) launch(1, [&](hipStream_t s) { qc[q].fock(a, 2, s); });
   else launch(0, [&](hipStream_t s) { qc[q].fock(a, 0, s); });
 }
@@ -1158,7 +1223,7 @@ void autotune_fock(bscf_ctx* c, int pcol) {
     if (W.items.empty()) continue;
     if (env && !strcmp(env, "lane")) { c->fock_variant[pcol][q] = 0; continue; }
     if (env && !strcmp(env, "coop")) { c->fock_variant[pcol][q] = 1; continue; }
-    set_class(a, W, 0);
+    set_class(a, W);
     // variants: 0 the lane form of this precision, 1 cooperative, and in
     // MIXED mode 2 the FP64 lane form (FP32 integrals do not pay everywhere)
     const int nv = pcol ? 3 : 2;
@@ -1201,24 +1266,33 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
     launch_density_change(bset, c->max_n, c->P.p, c->Pprev.p, c->dP.p, c->d_dpmax.p, c->stream);
     // kept kets per row for the lane kernels, and the kept work of every
     // class counted on the device (the statistics read it later)
+    // (one launch for all classes)
     const int pc = precision == BSCF_MIXED ? 1 : 0;
     const int ni = c->ninst;
+    RowKeepClass rk[kNumQuartetClasses];
+    int nrk = 0;
     for (int q = 0; q < kNumQuartetClasses; ++q) {
       auto& W = c->work[q];
       if (W.items.empty()) continue;
-      double* cq = c->d_kept.p + (size_t)q * ni;
-      double* cpq = c->d_kept.p + (size_t)(kNumQuartetClasses + q) * ni;
-      double* c32 = c->d_kept.p + (size_t)(2 * kNumQuartetClasses + q) * ni;
-      if (c->fock_variant[pc][q] == 1) {
-        launch_row_keep(W.d_rows.p, (int)W.rows.size(), c->d_kets.p, c->d_pairs.p, c->d_shells.p,
-                        c->d_Q.p, c->d_dpmax.p, a.active, tau, ni, nullptr, cq, cpq, nullptr,
-                        c->stream);
+      RowKeepClass& r = rk[nrk++];
+      r.cq = c->d_kept.p + (size_t)q * ni;
+      r.cpq = c->d_kept.p + (size_t)(kNumQuartetClasses + q) * ni;
+      r.block0 = 0;
+      if (c->fock_variant[pc][q] == 1) {   // cooperative: counts over the item rows
+        r.rows = W.d_rows.p;
+        r.nrows = (int)W.rows.size();
+        r.keep = nullptr;
+        r.c32 = nullptr;
       } else {
-        launch_row_keep(W.ul[0].d_rows.p, (int)W.ul[0].rows.size(), c->d_kets.p, c->d_pairs.p,
-                        c->d_shells.p, c->d_Q.p, c->d_dpmax.p, a.active, tau, ni, W.ul[0].d_keep.p,
-                        cq, cpq, lane_mode(c, precision, q) == 2 ? c32 : nullptr, c->stream);
+        r.rows = W.ul.d_rows.p;
+        r.nrows = (int)W.ul.rows.size();
+        r.keep = W.ul.d_keep.p;
+        r.c32 = lane_mode(c, precision, q) == 2
+                    ? c->d_kept.p + (size_t)(2 * kNumQuartetClasses + q) * ni : nullptr;
       }
     }
+    launch_row_keep(rk, nrk, c->d_kets.p, c->d_pairs.p, c->d_shells.p, c->d_Q.p, c->d_dpmax.p,
+                    a.active, tau, ni, c->stream);
     a.P = c->dP.p;
     a.dpmax = c->d_dpmax.p;
     a.tau = tau;
@@ -1229,15 +1303,19 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
   }
   const KetPosArgs kp = ketpos_args(c);
   const QuartetClass* qc = quartet_classes();
-  // class kernels run concurrently on the auxiliary streams (J and K are
-  // accumulated with atomics, so their order does not matter); heavy classes
-  // are issued first because they are latency-bound.  Kernels that need
-  // private scratch stay on the context stream: the runtime reserves scratch
-  // per hardware queue for full occupancy.
+  // class kernels run concurrently on the context stream and three auxiliary
+  // streams, one per hardware queue (J and K are accumulated with atomics, so
+  // their order does not matter); heavy classes are issued first because they
+  // are latency-bound, and the first goes to the context stream, which needs
+  // no cross-stream wait to start.  Kernels that need private scratch stay on
+  // the context stream: the runtime reserves scratch per hardware queue for
+  // full occupancy.
+  constexpr int kRing = 4;
+  const hipStream_t ring[kRing] = {c->stream, c->aux[0], c->aux[1], c->aux[2]};
   const int pbuild = c->profiling ? prof_begin(c, 0, 2, c->stream) : -1;
   launch_gather_pk(kp, c->max_ncd, a.P, c->d_Pk.p, c->stream);
   HIPCHK(hipEventRecord(c->ev_fork, c->stream));
-  for (int k = 0; k < bscf_ctx::kAux; ++k) HIPCHK(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
+  for (int k = 1; k < kRing; ++k) HIPCHK(hipStreamWaitEvent(ring[k], c->ev_fork, 0));
   int slot = 0;
   const int pcol = precision == BSCF_MIXED ? 1 : 0;
   for (int q = kNumQuartetClasses - 1; q >= 0; --q) {
@@ -1245,13 +1323,13 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
     if (W.items.empty()) continue;
     // one launch: kernels with private scratch go to the context stream
     auto launch = [&](int pbytes, auto&& run) {
-      const hipStream_t s = pbytes != 0 ? c->stream : c->aux[slot++ % bscf_ctx::kAux];
+      const hipStream_t s = pbytes != 0 ? c->stream : ring[slot++ % kRing];
       const int pk = c->profiling ? prof_begin(c, q, 0, s) : -1;
       run(s);
       if (pk >= 0) prof_end(c, pk, s);
     };
     if (c->fock_variant[pcol][q] == 1) {
-      set_class(a, W, 0);
+      set_class(a, W);
       launch(c->coop_bytes[q][0], [&](hipStream_t s) { qc[q].coop_fock(a, s); });
     } else {
       lane_launches(c, a, q, lane_mode(c, precision, q), [&](int k, auto&& run) {
@@ -1267,8 +1345,8 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
         }
     W.launches++;
   }
-  for (int k = 0; k < bscf_ctx::kAux; ++k) {
-    HIPCHK(hipEventRecord(c->ev_join[k], c->aux[k]));
+  for (int k = 1; k < kRing; ++k) {
+    HIPCHK(hipEventRecord(c->ev_join[k], ring[k]));
     HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join[k], 0));
   }
   launch_jk_finalize(kp, c->max_ncd, c->d_Jk.p, c->J.p, c->stream);
@@ -1534,6 +1612,11 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->diisB.resize((size_t)n_inst * 64);
     c->d_sp2.resize((size_t)(kSp2MaxSteps + 1) * 2 * n_inst * sp2_tiles(c->max_n));
     c->d_sp2b.resize((size_t)2 * n_inst * c->max_n);
+    c->d_sp2c.resize((size_t)2 * n_inst);
+    c->d_pin.resize((size_t)2 * n_inst);
+    c->d_wmin.resize(n_inst);
+    c->h_wmin.resize(n_inst);
+    c->h_pin.resize((size_t)2 * n_inst);
     c->d_omask.resize(n_inst);
     c->diisC.resize((size_t)n_inst * 8);
     c->diis_count.resize(n_inst);
@@ -1849,17 +1932,47 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
       launch_convergence(ni, c->max_n, c->d_nbf.p, c->d_E.p, c->d_Eprev.p, c->d_emax.p, o.e_tol,
                          o.comm_tol, it,
                          c->d_active.p, c->d_conv_iter.p, c->d_status.p, st);
-      HIPCHK(hipMemcpyAsync(flags.data(), c->d_active.p, ni * sizeof(int), hipMemcpyDeviceToHost, st));
+      // The next density is launched before the host knows which replicas
+      // converged: DIIS, SP2 and the commit follow the device's active flags,
+      // so a finished replica is left alone and a finished batch costs only
+      // these masked launches.  One synchronisation per iteration then reads
+      // the flags and whether every SP2 projection finished.
+      launch_diis_store(d, c->max_n, c->F.p, c->err.p, st);
+      launch_diis_extrapolate(d, c->max_n, c->Fbar.p, st);
+      int k = -1;
+      if (o.density == BSCF_DENSITY_SP2) {
+        ortho_fock(c, c->Fbar.p);
+        k = sp2_launch(c, bm, sp2_slot(it), c->Pnew.p);
+      } else {
+        orbitals_from_fock(c, c->Fbar.p);
+        density_from_orbitals(c, c->Pnew.p);
+      }
+      launch_commit(bm, c->max_n, c->Pnew.p, c->P.p, st);
+      launch_concat_ints(c->d_active.p, ni, k >= 0 ? c->d_sp2c.p + (k & 1) * ni : nullptr,
+                         k >= 0 ? ni : 0, c->d_pin.p, st);
+      HIPCHK(hipMemcpyAsync(c->h_pin.p, c->d_pin.p, (k >= 0 ? 2 : 1) * ni * sizeof(int),
+                            hipMemcpyDeviceToHost, st));
       sync(c);
+      std::copy(c->h_pin.p, c->h_pin.p + ni, flags.begin());
       c->scf_iters++;
       c->h_active = flags;
       bool any = false;
       for (int i = 0; i < ni; ++i) any |= flags[i] != 0;
       if (!any) break;
-      launch_diis_store(d, c->max_n, c->F.p, c->err.p, st);
-      launch_diis_extrapolate(d, c->max_n, c->Fbar.p, st);
-      density_from_fock(c, c->Fbar.p, bm, flags, o.density, c->Pnew.p);
-      launch_commit(bm, c->max_n, c->Pnew.p, c->P.p, st);
+      if (k >= 0) {
+        // a projection still short of its need is finished here, or falls
+        // back to the eigenvector route when it has no gap
+        if (!sp2_finished(c, flags, k, sp2_slot(it))) {
+          if (!sp2_extend(c, bm, flags, sp2_slot(it), k, c->Pnew.p)) {
+            c->sp2_fallbacks++;
+            orbitals_from_fock(c, c->Fbar.p);
+            density_from_orbitals(c, c->Pnew.p);
+          }
+          launch_commit(bm, c->max_n, c->Pnew.p, c->P.p, st);
+        }
+        c->sp2_calls++;
+        c->sp2_steps += k;
+      }
       for (int i = 0; i < ni; ++i) updates[i] += flags[i] != 0;
     }
     // orbitals for the next call's previous-step guess, once per call: those
@@ -1967,9 +2080,9 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
       g.items = W.d_items.p;
       g.nitems = (int)W.items.size();
       g.rows = W.d_rows.p;
-      g.units = W.ul[0].d_units.p;
-      g.nunits = (int)W.ul[0].units.size();
-      g.urows = W.ul[0].d_rows.p;
+      g.units = W.ul.d_units.p;
+      g.nunits = (int)W.ul.units.size();
+      g.urows = W.ul.d_rows.p;
     };
     const QuartetClass* qc = quartet_classes();
     if (!c->grad_tuned) {
@@ -2166,7 +2279,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
     c->t_work_host_ms = 0;
     c->t_work_phase_ms[0] = c->t_work_phase_ms[1] = c->t_work_phase_ms[2] = 0;
     c->fock_builds = c->scf_iters = 0;
-    c->sp2_calls = c->sp2_steps = c->sp2_fallbacks = 0;
+    c->sp2_calls = c->sp2_steps = c->sp2_needed = c->sp2_fallbacks = 0;
     c->inc_builds = 0;
   });
 }
@@ -2185,6 +2298,7 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
       << ", \"t_work_host_ms\": " << c->t_work_host_ms << ", \"t_work_phase_ms\": ["
       << c->t_work_phase_ms[0] << ", " << c->t_work_phase_ms[1] << ", " << c->t_work_phase_ms[2] << "]"
       << ", \"sp2_calls\": " << c->sp2_calls << ", \"sp2_steps\": " << c->sp2_steps
+      << ", \"sp2_steps_needed\": " << c->sp2_needed
       << ", \"sp2_fallbacks\": " << c->sp2_fallbacks << ", \"incremental_builds\": " << c->inc_builds
       << ", \"classes\": {";
     const QuartetClass* qc = quartet_classes();

@@ -76,26 +76,26 @@ void launch_jk_finalize(const KetPosArgs& a, int max_ncd, double* Jk, double* J,
 
 // Kets of each work row that pass an incremental build's test
 // Q_ab Q_cd min(dpmax[inst], 1) >= tau: the row's kets run in descending
-// Schwarz bound, so the count is a binary search.  One thread per row; rows of
-// instances that are not active are left alone.  When keep is given the count
-// goes there; when cq is given the kept quartets and primitive quartets (and,
-// with c32, the kept quartets past the row's FP64 prefix of w.pad kets) are
-// added to cq[inst], cpq[inst] (c32[inst]).
-__global__ void row_keep_kernel(const WorkRow* __restrict__ rows, int nrows,
-                                const int* __restrict__ kets, const ShellPair* __restrict__ pairs,
+// Schwarz bound, so the count is a binary search.  One thread per row, the
+// rows of every class in one launch (set.cls[c] owns the blocks from its
+// block0 on); rows of instances that are not active are left alone.  When
+// keep is given the count goes there; the kept quartets and primitive
+// quartets (and, with c32, the kept quartets past the row's FP64 prefix of
+// w.pad kets) are added to cq[inst], cpq[inst] (c32[inst]).
+__global__ void row_keep_kernel(RowKeepSet set, const int* __restrict__ kets,
+                                const ShellPair* __restrict__ pairs,
                                 const Shell* __restrict__ shells, const double* __restrict__ Q,
                                 const double* __restrict__ dpmax, const int* __restrict__ active,
-                                double tau, int ninst, int* __restrict__ keep, double* cq,
-                                double* cpq, double* c32) {
-  extern __shared__ double part[];   // [2 or 3][ninst] when counting
-  const int nc = c32 ? 3 : 2;
-  if (cq) {
-    for (int k = threadIdx.x; k < nc * ninst; k += blockDim.x) part[k] = 0.0;
-    __syncthreads();
-  }
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < nrows) {
-    const WorkRow w = rows[r];
+                                double tau, int ninst) {
+  extern __shared__ double part[];   // [3][ninst]
+  int ci = 0;
+  while (ci + 1 < set.nclass && (int)blockIdx.x >= set.cls[ci + 1].block0) ++ci;
+  const RowKeepClass& C = set.cls[ci];
+  for (int k = threadIdx.x; k < 3 * ninst; k += blockDim.x) part[k] = 0.0;
+  __syncthreads();
+  const int r = ((int)blockIdx.x - C.block0) * blockDim.x + threadIdx.x;
+  if (r < C.nrows) {
+    const WorkRow w = C.rows[r];
     const ShellPair bra = pairs[w.bra];
     const int inst = shells[bra.a].inst;
     if (active[inst]) {
@@ -106,33 +106,41 @@ __global__ void row_keep_kernel(const WorkRow* __restrict__ rows, int nrows,
         if (qd * Q[kets[w.ket0 + mid]] >= tau) lo = mid + 1;
         else hi = mid;
       }
-      if (keep) keep[r] = lo;
-      if (cq && lo > 0) {
+      if (C.keep) C.keep[r] = lo;
+      if (lo > 0) {
         const int knp = pairs[kets[w.ket0]].nprim;   // one primitive count per row
         atomicAdd(&part[inst], double(lo));
         atomicAdd(&part[ninst + inst], double(lo) * bra.nprim * knp);
-        if (c32) atomicAdd(&part[2 * ninst + inst], double(max(0, lo - w.pad)));
+        if (C.c32) atomicAdd(&part[2 * ninst + inst], double(max(0, lo - w.pad)));
       }
     }
   }
-  if (cq) {
-    __syncthreads();
-    for (int k = threadIdx.x; k < ninst; k += blockDim.x) {
-      if (part[k] != 0.0) atomicAdd(&cq[k], part[k]);
-      if (part[ninst + k] != 0.0) atomicAdd(&cpq[k], part[ninst + k]);
-      if (c32 && part[2 * ninst + k] != 0.0) atomicAdd(&c32[k], part[2 * ninst + k]);
-    }
+  __syncthreads();
+  for (int k = threadIdx.x; k < ninst; k += blockDim.x) {
+    if (part[k] != 0.0) atomicAdd(&C.cq[k], part[k]);
+    if (part[ninst + k] != 0.0) atomicAdd(&C.cpq[k], part[ninst + k]);
+    if (C.c32 && part[2 * ninst + k] != 0.0) atomicAdd(&C.c32[k], part[2 * ninst + k]);
   }
 }
 
-void launch_row_keep(const WorkRow* rows, int nrows, const int* kets, const ShellPair* pairs,
+void launch_row_keep(const RowKeepClass* cls, int ncls, const int* kets, const ShellPair* pairs,
                      const Shell* shells, const double* Q, const double* dpmax, const int* active,
-                     double tau, int ninst, int* keep, double* cq, double* cpq, double* c32,
-                     hipStream_t s) {
-  if (nrows == 0) return;
-  const size_t lds = cq ? sizeof(double) * (c32 ? 3 : 2) * ninst : 0;
-  hipLaunchKernelGGL(row_keep_kernel, dim3((nrows + 255) / 256), dim3(256), lds, s, rows, nrows,
-                     kets, pairs, shells, Q, dpmax, active, tau, ninst, keep, cq, cpq, c32);
+                     double tau, int ninst, hipStream_t s) {
+  for (int c0 = 0; c0 < ncls; c0 += kRowKeepMaxClasses) {
+    RowKeepSet set;
+    set.nclass = 0;
+    int blocks = 0;
+    for (int c = c0; c < std::min(ncls, c0 + kRowKeepMaxClasses); ++c) {
+      if (cls[c].nrows <= 0) continue;
+      RowKeepClass& d = set.cls[set.nclass++];
+      d = cls[c];
+      d.block0 = blocks;
+      blocks += (cls[c].nrows + 255) / 256;
+    }
+    if (blocks == 0) continue;
+    hipLaunchKernelGGL(row_keep_kernel, dim3(blocks), dim3(256), sizeof(double) * 3 * ninst, s, set,
+                       kets, pairs, shells, Q, dpmax, active, tau, ninst);
+  }
 }
 
 }  // namespace bscf

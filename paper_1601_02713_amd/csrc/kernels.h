@@ -55,14 +55,30 @@ struct Grad1EArgs {
 
 void launch_prim_pairs(const PrimPairSetupArgs& a, hipStream_t s);
 void launch_onee(int la, int lb, const OneEArgs& a, hipStream_t s);
+// The work rows of one quartet class for launch_row_keep: keep (may be NULL)
+// receives per row the kets that pass; cq, cpq (and c32, may be NULL) receive
+// per instance the kept quartets, primitive quartets (and kept quartets past
+// each row's FP64 prefix, row.pad).  block0 is set by the launcher.
+struct RowKeepClass {
+  const WorkRow* rows;
+  int nrows;
+  int block0;
+  int* keep;
+  double* cq;
+  double* cpq;
+  double* c32;
+};
+constexpr int kRowKeepMaxClasses = 24;
+struct RowKeepSet {
+  int nclass;
+  RowKeepClass cls[kRowKeepMaxClasses];
+};
 // keep[r] = kets of work row r with Q_ab Q_cd min(dpmax[inst], 1) >= tau for
-// the rows of active instances (keep may be NULL); with cq, the kept
-// quartets, primitive quartets (and, with c32, kept quartets past each row's
-// FP64 prefix, row.pad) are added per instance to cq, cpq (c32) (jk.hip)
-void launch_row_keep(const WorkRow* rows, int nrows, const int* kets, const ShellPair* pairs,
+// the rows of active instances, with the counts added to cq, cpq (c32), for
+// ncls classes in one launch per kRowKeepMaxClasses (jk.hip)
+void launch_row_keep(const RowKeepClass* cls, int ncls, const int* kets, const ShellPair* pairs,
                      const Shell* shells, const double* Q, const double* dpmax, const int* active,
-                     double tau, int ninst, int* keep, double* cq, double* cpq, double* c32,
-                     hipStream_t s);
+                     double tau, int ninst, hipStream_t s);
 void launch_grad1e(int la, int lb, const Grad1EArgs& a, hipStream_t s);
 
 // ---- ket-list-position buffers of the Fock build (jk.hip) ----
@@ -131,22 +147,31 @@ void launch_convergence(int ninst, int max_n, const int* nbf, const double* E, d
 // SP2 purification (scf.hip).  launch_sp2_bounds: Gershgorin intervals of
 // the rows of each instance's F' (bounds[inst][row] = (lo, hi), room for
 // ninst * max_n pairs).  launch_sp2_init: X = (hi I - (F' + F'^T)/2)/(hi - lo)
-// over their union.  launch_sp2_step: Xn = X^2 or 2X - X^2, as the trace rule
-// on st_in (the statistics of X) decides; X and Xn must not overlap.  Both
-// store, per 32 x 32 tile of the result, its (Tr, Tr^2) partial at
-// st[(inst * sp2_tiles(max_n) + tile) * 2]; the sum over an instance's tiles
-// is its (Tr X, Tr X^2).  Instances masked out by b.active are skipped.
+// over their union, and conv[inst] = -1.  launch_sp2_step (step k): Xn = X^2
+// or 2X - X^2, as the trace rule on st_in (the statistics of X) decides; X and
+// Xn must not overlap.  Both store, per 32 x 32 tile of the result, its
+// (Tr, Tr^2) partial at st[(inst * sp2_tiles(max_n) + tile) * 2]; the sum over
+// an instance's tiles is its (Tr X, Tr X^2).  conv_out[inst] = the first step
+// j <= k whose X_j met Tr X - Tr X^2 < idem_tol and |Tr X - nocc| < trace_tol
+// (-1 if none), given conv_in from step k - 1 (from init for k = 0); an
+// instance with j + 2 <= k is finished and Xn = X.  conv_in and conv_out must
+// be distinct arrays of ninst ints.  Instances masked out by b.active are
+// skipped.
 void launch_sp2_bounds(const BatchInfo& b, int max_n, const double* F, double* bounds,
                        hipStream_t s);
 void launch_sp2_init(const BatchInfo& b, int max_n, const double* F, const double* bounds,
-                     double* X, double* st, hipStream_t s);
+                     double* X, double* st, int* conv, hipStream_t s);
 void launch_sp2_step(const BatchInfo& b, int max_n, const int* nocc, const double* X, double* Xn,
-                     const double* st_in, double* st_out, hipStream_t s);
+                     const double* st_in, double* st_out, int step, double idem_tol,
+                     double trace_tol, const int* conv_in, int* conv_out, hipStream_t s);
 int sp2_tiles(int max_n);
 // dP = P - Pprev and dpmax[i] = max |dP| of instance i (the instances of b);
 // dpmax needs room for ninst + ninst * ceil(max_n/32)^2 doubles (scf.hip)
 void launch_density_change(const BatchInfo& b, int max_n, const double* P, const double* Pprev,
                            double* dP, double* dpmax, hipStream_t s);
+// out[0, na) = a and out[na, na + nb) = b (int arrays; one copy to the host
+// then reads both)
+void launch_concat_ints(const int* a, int na, const int* b, int nb, int* out, hipStream_t s);
 // P_new -> P for active instances
 void launch_commit(const BatchInfo& b, int max_n, const double* Pnew, double* P, hipStream_t s);
 // nuclear repulsion energy and gradient per instance

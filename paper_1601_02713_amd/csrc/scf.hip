@@ -344,6 +344,13 @@ __global__ __launch_bounds__(64) void convergence_kernel(int ninst, int max_n, c
   Eprev[i] = e;
 }
 
+// out[0, na) = a, out[na, na + nb) = b
+__global__ void concat_ints_kernel(const int* a, int na, const int* b, int nb, int* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < na) out[t] = a[t];
+  else if (t < na + nb) out[t] = b[t - na];
+}
+
 __global__ void commit_kernel(BatchInfo b, const double* Pnew, double* P) {
   const int inst = blockIdx.y;
   if (!b.active[inst]) return;
@@ -468,15 +475,17 @@ __device__ void sp2_store_stats(double a, double q, double* st, double* sh) {
 // X_0 = (hi I - (F' + F'^T)/2) / (hi - lo) over the union of the rows'
 // Gershgorin intervals; the symmetrised start keeps every later X exactly
 // symmetric.  Grid (tile of the 32 x 32 tiling, instance); each tile stores its
-// (Tr, Tr^2) partial at st[inst][tile].
+// (Tr, Tr^2) partial at st[inst][tile]; conv[inst] = -1 (not converged).
 __global__ __launch_bounds__(256) void sp2_init_kernel(BatchInfo b, int max_n, const double* F,
-                                                       const double* rowb, double* X, double* st) {
+                                                       const double* rowb, double* X, double* st,
+                                                       int* conv) {
   __shared__ double sh[8];
   const int inst = blockIdx.y;
   if (b.active && !b.active[inst]) return;
   const int n = b.nbf[inst], nt = ntiles_1d(n), ntm = ntiles_1d(max_n);
   const int tile = blockIdx.x;
   if (tile >= nt * nt) return;
+  if (tile == 0 && threadIdx.x == 0) conv[inst] = -1;
   const long long o = b.moff[inst];
   double lo = INFINITY, hi = -INFINITY;
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
@@ -520,10 +529,21 @@ __global__ __launch_bounds__(256) void sp2_init_kernel(BatchInfo b, int max_n, c
 // next chunk loaded into registers while the current one is multiplied.  The
 // epilogue writes Xn = Y or 2X - Y by the trace rule on the previous
 // statistics and stores this tile's (Tr, Tr^2) partial of Xn.
+//
+// Stopping is decided here, per instance: conv_in[inst] is the first step
+// whose X met Tr X - Tr X^2 < idem_tol and |Tr X - N| < trace_tol (-1 while
+// none has); this step's X is tested when none has, and the result goes to
+// conv_out[inst].  Two steps after that first step the instance is finished:
+// Xn = X and its statistics are carried forward unchanged, so steps launched
+// beyond the need are cheap copies.  conv_in and conv_out are different
+// arrays (the caller alternates them), so no block reads what another block
+// of the same launch writes.
 constexpr int kSp2K = 96;
 __global__ __launch_bounds__(256) void sp2_gemm_kernel(BatchInfo b, int max_n, const int* nocc,
                                                        const double* X, double* Xn,
-                                                       const double* st_in, double* st_out) {
+                                                       const double* st_in, double* st_out,
+                                                       int step, double idem_tol, double trace_tol,
+                                                       const int* conv_in, int* conv_out) {
   constexpr int kPer = kSp2K * kTile / 256;   // panel elements per thread and chunk
   __shared__ double sh[8];
   __shared__ double As[kSp2K][kTile], Bs[kSp2K][kTile];
@@ -559,6 +579,18 @@ __global__ __launch_bounds__(256) void sp2_gemm_kernel(BatchInfo b, int max_n, c
   double tr, t2;
   sp2_stats(st_in + (long long)inst * ntm * ntm * 2, nt * nt, tr, t2, sh);
   const double N = nocc[inst];
+  int first = conv_in[inst];
+  if (first < 0 && tr - t2 < idem_tol && fabs(tr - N) < trace_tol) first = step;
+  if (tile == 0 && threadIdx.x == 0) conv_out[inst] = first;
+  if (first >= 0 && step >= first + 2) {   // finished: carry X forward (block-uniform)
+    for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+      const int i = ti0 + e / kTile, j = tj0 + e % kTile;
+      if (i < n && j < n) Xn[o + (long long)i * n + j] = X[o + (long long)i * n + j];
+    }
+    const long long so = ((long long)inst * ntm * ntm + tile) * 2;
+    if (threadIdx.x < 2) st_out[so + threadIdx.x] = st_in[so + threadIdx.x];
+    return;
+  }
   const bool square = fabs(t2 - N) < fabs(2.0 * tr - t2 - N);
   v4d acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < n; k0 += kSp2K) {
@@ -662,6 +694,12 @@ void launch_convergence(int ninst, int max_n, const int* nbf, const double* E, d
                      emax + ninst, emax, etol, ctol, iter, active, conv_iter, status);
 }
 
+void launch_concat_ints(const int* a, int na, const int* b, int nb, int* out, hipStream_t s) {
+  const int n = na + nb;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(concat_ints_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a, na, b, nb, out);
+}
+
 void launch_commit(const BatchInfo& b, int max_n, const double* Pnew, double* P, hipStream_t s) {
   const long long nn = (long long)max_n * max_n;
   const unsigned gx = (unsigned)std::min<long long>((nn + 255) / 256, 1024);
@@ -675,17 +713,18 @@ void launch_sp2_bounds(const BatchInfo& b, int max_n, const double* F, double* b
 }
 
 void launch_sp2_init(const BatchInfo& b, int max_n, const double* F, const double* bounds,
-                     double* X, double* st, hipStream_t s) {
+                     double* X, double* st, int* conv, hipStream_t s) {
   const int nt = ntiles_1d(max_n);
   hipLaunchKernelGGL(sp2_init_kernel, dim3(nt * nt, b.ninst), dim3(256), 0, s, b, max_n, F, bounds,
-                     X, st);
+                     X, st, conv);
 }
 
 void launch_sp2_step(const BatchInfo& b, int max_n, const int* nocc, const double* X, double* Xn,
-                     const double* st_in, double* st_out, hipStream_t s) {
+                     const double* st_in, double* st_out, int step, double idem_tol,
+                     double trace_tol, const int* conv_in, int* conv_out, hipStream_t s) {
   const int nt = ntiles_1d(max_n);
   hipLaunchKernelGGL(sp2_gemm_kernel, dim3(nt * nt, b.ninst), dim3(256), 0, s, b, max_n, nocc, X,
-                     Xn, st_in, st_out);
+                     Xn, st_in, st_out, step, idem_tol, trace_tol, conv_in, conv_out);
 }
 
 int sp2_tiles(int max_n) { return ntiles_1d(max_n) * ntiles_1d(max_n); }
