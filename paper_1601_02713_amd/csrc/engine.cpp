@@ -299,6 +299,7 @@ struct bscf_ctx {
   // 2 (MIXED only) the FP64 lane form; tune_ms holds their times
   float tune_ms[2][kNumQuartetClasses][3] = {};
   float tune_grad_ms[kNumQuartetClasses][2] = {};
+  float tune_grad1e_ms[kNumPairClasses] = {};   // one-electron gradient kernels alone
   // per-lane private (scratch) bytes of every class kernel: [class][fp64, mixed, grad].
   // The runtime reserves (and keeps) scratch per hardware queue for full
   // occupancy, so every kernel that uses scratch (class kernels, one-electron
@@ -2026,11 +2027,11 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
     launch_fill(c->d_grad.p, 3LL * c->total_atoms, 0.0, st);
     launch_nuclear(c->ninst, c->d_natoms.p, c->d_atom_off.p, c->d_xyz.p, c->d_Zd.p, c->d_Enuc.p,
                    c->d_grad.p, 1, st);
+    // one-electron gradient arguments per pair class (launched below with the
+    // two-electron classes)
+    Grad1EArgs g1[kNumPairClasses];
     for (int pc = 0; pc < kNumPairClasses; ++pc) {
-      if (c->task_count[pc] == 0) continue;
-      const int la = pc == 0 ? 0 : (pc < 3 ? 1 : 2);
-      const int lb = pc - la * (la + 1) / 2;
-      Grad1EArgs g;
+      Grad1EArgs& g = g1[pc];
       g.ntasks = c->task_count[pc];
       g.task_a = c->d_task_a.p + c->task_first[pc];
       g.task_b = c->d_task_b.p + c->task_first[pc];
@@ -2048,8 +2049,11 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
       g.W = c->W.p;
       g.active = c->d_all_active.p;
       g.grad = c->d_grad.p;
-      launch_grad1e(la, lb, g, st);
     }
+    auto pc_l = [](int pc, int& la, int& lb) {
+      la = pc == 0 ? 0 : (pc < 3 ? 1 : 2);
+      lb = pc - la * (la + 1) / 2;
+    };
     // two-electron part over the same screened work lists
     GradArgs ga;
     ga.items = nullptr;
@@ -2086,59 +2090,109 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
     };
     const QuartetClass* qc = quartet_classes();
     if (!c->grad_tuned) {
-      // time both gradient variants where both exist (into a throwaway buffer)
+      // time both gradient variants where both exist, and every kernel that
+      // the gradient launches alone (into a throwaway buffer): the choice
+      // of variant and the stream schedule below use these times
       const char* env = getenv("BSCF_VARIANT");
       GradArgs gt = ga;
       gt.grad = c->tmp1.p;
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
+      auto time_alone = [&](auto&& run) {
+        HIPCHK(hipEventRecord(e0, st));
+        run();
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        return ms;
+      };
       for (int q = 0; q < kNumQuartetClasses; ++q) {
         auto& W = c->work[q];
+        c->tune_grad_ms[q][0] = c->tune_grad_ms[q][1] = 0.0f;
+        if (W.items.empty()) continue;
+        set_gclass(gt, W);
         const bool lds_ok = sizeof(double) * (size_t)grad_unit_lds_doubles(
                                 qc[q].la, qc[q].lb, c->max_n, c->max_atoms, c->max_prims) <=
                             c->max_lds_bytes;
-        if (!qc[q].grad || !lds_ok || c->private_bytes[q][2] > kMaxLaneScratch) {
-          c->grad_variant[q] = 1;
-          continue;
-        }
-        if (W.items.empty()) continue;
-        if (env && !strcmp(env, "lane")) { c->grad_variant[q] = 0; continue; }
-        if (env && !strcmp(env, "coop")) { c->grad_variant[q] = 1; continue; }
-        set_gclass(gt, W);
-        for (int v = 0; v < 2; ++v) {
-          HIPCHK(hipEventRecord(e0, st));
-          if (v) qc[q].coop_grad(gt, st);
-          else qc[q].grad(gt, st);
-          HIPCHK(hipEventRecord(e1, st));
-          HIPCHK(hipEventSynchronize(e1));
-          HIPCHK(hipEventElapsedTime(&c->tune_grad_ms[q][v], e0, e1));
-        }
-        c->grad_variant[q] = c->tune_grad_ms[q][1] < c->tune_grad_ms[q][0] ? 1 : 0;
+        const bool lane_ok = qc[q].grad && lds_ok && c->private_bytes[q][2] <= kMaxLaneScratch;
+        if (lane_ok && !(env && !strcmp(env, "coop")))
+          c->tune_grad_ms[q][0] = time_alone([&] { qc[q].grad(gt, st); });
+        if (!lane_ok || !(env && !strcmp(env, "lane")))
+          c->tune_grad_ms[q][1] = time_alone([&] { qc[q].coop_grad(gt, st); });
+        if (!lane_ok) c->grad_variant[q] = 1;
+        else if (env && !strcmp(env, "lane")) c->grad_variant[q] = 0;
+        else if (env && !strcmp(env, "coop")) c->grad_variant[q] = 1;
+        else c->grad_variant[q] = c->tune_grad_ms[q][1] < c->tune_grad_ms[q][0] ? 1 : 0;
+      }
+      for (int pc = 0; pc < kNumPairClasses; ++pc) {
+        c->tune_grad1e_ms[pc] = 0.0f;
+        if (g1[pc].ntasks == 0) continue;
+        Grad1EArgs g = g1[pc];
+        g.grad = c->tmp1.p;
+        int la, lb;
+        pc_l(pc, la, lb);
+        c->tune_grad1e_ms[pc] = time_alone([&] { launch_grad1e(la, lb, g, st); });
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       c->grad_tuned = true;
     }
-    HIPCHK(hipEventRecord(c->ev_fork, st));
-    for (int k = 0; k < bscf_ctx::kAux; ++k) HIPCHK(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
-    int slot = 0;
-    for (int q = kNumQuartetClasses - 1; q >= 0; --q) {
-      auto& W = c->work[q];
-      if (W.items.empty()) continue;
-      set_gclass(ga, W);
+    // Every class kernel and one-electron kernel is independent (the force
+    // accumulates with atomics): longest first, each onto the stream with the
+    // least time queued so far (the context stream and the auxiliary ones),
+    // from the times alone above.  Kernels with private scratch stay on the
+    // context stream: the runtime reserves scratch per hardware queue.
+    struct Job {
+      float ms;
+      int q;    // quartet class, or -1 - pair class for a one-electron kernel
+      int pbytes;
+    };
+    std::vector<Job> jobs;
+    for (int q = 0; q < kNumQuartetClasses; ++q) {
+      if (c->work[q].items.empty()) continue;
       const int var = c->grad_variant[q];
-      const int pbytes = var ? c->coop_bytes[q][1] : c->private_bytes[q][2];
-      const hipStream_t s = pbytes != 0 ? st : c->aux[slot++ % bscf_ctx::kAux];
-      const int pk = c->profiling ? prof_begin(c, q, 1, s) : -1;
-      if (var) qc[q].coop_grad(ga, s);
-      else qc[q].grad(ga, s);
-      if (pk >= 0) prof_end(c, pk, s);
-      W.grad_launches++;
+      jobs.push_back({c->tune_grad_ms[q][var], q,
+                      var ? c->coop_bytes[q][1] : c->private_bytes[q][2]});
     }
-    for (int k = 0; k < bscf_ctx::kAux; ++k) {
-      HIPCHK(hipEventRecord(c->ev_join[k], c->aux[k]));
-      HIPCHK(hipStreamWaitEvent(st, c->ev_join[k], 0));
+    for (int pc = 0; pc < kNumPairClasses; ++pc)
+      if (g1[pc].ntasks > 0) jobs.push_back({c->tune_grad1e_ms[pc], -1 - pc, 0});
+    std::stable_sort(jobs.begin(), jobs.end(), [](const Job& x, const Job& y) { return x.ms > y.ms; });
+    constexpr int kNs = 1 + bscf_ctx::kAux;
+    const hipStream_t ring[kNs] = {st, c->aux[0], c->aux[1], c->aux[2], c->aux[3]};
+    float load[kNs] = {};
+    bool used[kNs] = {true};
+    HIPCHK(hipEventRecord(c->ev_fork, st));
+    for (const Job& j : jobs) {
+      int k = 0;
+      if (j.pbytes == 0)
+        for (int t = 1; t < kNs; ++t)
+          if (load[t] < load[k]) k = t;
+      load[k] += j.ms;
+      if (!used[k]) {
+        HIPCHK(hipStreamWaitEvent(ring[k], c->ev_fork, 0));
+        used[k] = true;
+      }
+      const hipStream_t s = ring[k];
+      if (j.q >= 0) {
+        auto& W = c->work[j.q];
+        set_gclass(ga, W);
+        const int pk = c->profiling ? prof_begin(c, j.q, 1, s) : -1;
+        if (c->grad_variant[j.q]) qc[j.q].coop_grad(ga, s);
+        else qc[j.q].grad(ga, s);
+        if (pk >= 0) prof_end(c, pk, s);
+        W.grad_launches++;
+      } else {
+        int la, lb;
+        pc_l(-1 - j.q, la, lb);
+        launch_grad1e(la, lb, g1[-1 - j.q], s);
+      }
+    }
+    for (int k = 1; k < kNs; ++k) {
+      if (!used[k]) continue;
+      HIPCHK(hipEventRecord(c->ev_join[k - 1], ring[k]));
+      HIPCHK(hipStreamWaitEvent(st, c->ev_join[k - 1], 0));
     }
     HIPCHK(hipGetLastError());
     std::vector<double> g(3 * c->total_atoms);
