@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--split", type=float, default=1e-4,
                     help="mixed precision: quartets with Q_ab Q_cd below this run in FP32")
+    ap.add_argument("--graph", type=int, choices=[0, 1], default=1,
+                    help="replay each SCF iteration's steps after the Fock build from a HIP graph")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--guess-steps", type=int, default=8,
@@ -157,7 +159,7 @@ def main():
     prec = beadscf.BSCF_MIXED if args.precision == "mixed" else beadscf.BSCF_FP64
     opts = beadscf.default_opts(e_tol=w["e_tol"], comm_tol=w["comm_tol"], schwarz_tol=1e-12,
                                 precision=prec, guess=beadscf.GUESS_CORE, max_iter=60,
-                                fp32_split_tol=args.split)
+                                fp32_split_tol=args.split, graph=args.graph)
 
     def step():
         eng.set_geometries(xs)
@@ -222,7 +224,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["label"], "instances": n_inst, "basis_functions": eng.nbf[0],
                    "scf_e_tol": w["e_tol"], "scf_comm_tol": w["comm_tol"],
-                   "schwarz_tol": 1e-12, "guess": "core"},
+                   "schwarz_tol": 1e-12, "guess": "core", "graph": bool(args.graph)},
         "bead_scf_steps_per_s": iters / wall,
         "bead_energy_force_per_s": n_inst * args.steps / wall,
         "scf_iterations_per_bead": iters / (n_inst * args.steps),

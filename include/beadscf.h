@@ -86,11 +86,18 @@ typedef struct {
                           cutoff applied to the change, Section 3.1), with a
                           full build every 12 iterations; 0: every iteration a
                           full build                                            */
+  int graph;           /* 1 (with BSCF_DENSITY_SP2): each iteration's steps
+                          after its Fock build (commutator error, convergence
+                          test, DIIS, SP2 density and its commit) replay a HIP
+                          graph that the context captures once per SP2 step
+                          count and keeps until the batch changes; the same
+                          kernels as with 0, where they are launched one by
+                          one                                                   */
 } bscf_scf_opts;
 
 /* Fill opts with defaults: e_tol 1e-8, comm_tol 1e-6, schwarz_tol 1e-12,
  * fp32_split_tol 1e-4, max_iter 100, diis_size 8, FP64, core guess, SP2,
- * incremental builds. */
+ * incremental builds, graph replay. */
 bscf_status bscf_default_opts(bscf_scf_opts* opts);
 
 /* Create a context on HIP device `hip_device`; `hip_stream` may be NULL (the

@@ -33,7 +33,7 @@ class ScfOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("diis_size", ctypes.c_int),
                 ("precision", ctypes.c_int), ("guess", ctypes.c_int),
                 ("deterministic", ctypes.c_int), ("density", ctypes.c_int),
-                ("incremental", ctypes.c_int)]
+                ("incremental", ctypes.c_int), ("graph", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p

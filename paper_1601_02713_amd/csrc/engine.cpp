@@ -28,6 +28,7 @@
 #include <string>
 #include <future>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/beadscf.h"
@@ -426,6 +427,15 @@ struct bscf_ctx {
   PinBuf<int> h_pin;
   DevBuf<double> d_wmin;    // smallest overlap eigenvalue per instance
   PinBuf<double> h_wmin;
+  // captured density halves of an SCF iteration, by (SP2 steps, e_tol,
+  // comm_tol, DIIS size); they hold device addresses of this context's
+  // buffers, so every change of the batch drops them
+  std::map<std::tuple<int, double, double, int>, hipGraphExec_t> graphs;
+  long long graph_launches = 0, graph_captures = 0;
+  void drop_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    graphs.clear();
+  }
   bool have_C = false;
   std::vector<int> h_active;   // host copy of the active flags
   bool profiling = false;
@@ -603,18 +613,21 @@ void sp2_project(bscf_ctx* c, int k, double* Pout) {
 // Step predictor index: the core guess, or SCF iteration it.
 int sp2_slot(int it) { return it < 0 ? 0 : 1 + std::min(it, bscf_ctx::kSp2PredIters - 1); }
 
-// Launch a whole SP2 density without waiting: the step count predicted by
-// sp2_pred[which] (or, where that has no record yet, by the previous slot)
-// plus a margin, then the projector into Pout.  Returns the steps launched.
-int sp2_launch(bscf_ctx* c, const BatchInfo& b, int which, double* Pout) {
+// Steps to launch ahead for predictor slot which: its last need (or, where
+// that has no record yet, that of an earlier slot) plus a margin.
+int sp2_target(bscf_ctx* c, int which) {
   int pred = 0;
   for (int w = which; w >= 0 && pred == 0; --w) pred = c->sp2_pred[w];
   if (pred == 0) pred = 48;
-  const int k = std::min(pred + kSp2Margin, kSp2MaxSteps);
+  return std::min(pred + kSp2Margin, kSp2MaxSteps);
+}
+
+// Launch a whole SP2 density of k steps without waiting, then the projector
+// into Pout.
+void sp2_launch(bscf_ctx* c, const BatchInfo& b, int k, double* Pout) {
   sp2_start(c, b);
   sp2_steps(c, b, 0, k);
   sp2_project(c, k, Pout);
-  return k;
 }
 
 // Queue the read of the first converged steps after k steps into h_pin[ninst..].
@@ -666,7 +679,8 @@ bool sp2_extend(bscf_ctx* c, const BatchInfo& b, const std::vector<int>& act, in
 // when some has not converged after kSp2MaxSteps steps.
 bool density_sp2(bscf_ctx* c, const BatchInfo& b, const std::vector<int>& act, int which,
                  double* Pout) {
-  int k = sp2_launch(c, b, which, Pout);
+  int k = sp2_target(c, which);
+  sp2_launch(c, b, k, Pout);
   sp2_read(c, k);
   sync(c);
   const bool ok = sp2_finished(c, act, k, which) || sp2_extend(c, b, act, which, k, Pout);
@@ -687,6 +701,72 @@ void density_from_fock(bscf_ctx* c, const double* Fb, const BatchInfo& b,
   }
   orbitals_from_fock(c, Fb);
   density_from_orbitals(c, Pout);
+}
+
+// The steps of one SCF iteration after its Fock build: the commutator error
+// e = X (FPS - SPF) X, the convergence test, DIIS, the density of the
+// extrapolated F (SP2 with k steps, or the eigenvector route when k < 0) and
+// its commit, and the packing of what the host reads afterwards.  DIIS, the
+// density and the commit follow the device's active flags, so this runs
+// before the host knows which replicas the test has just finished.  Every
+// launch argument is a buffer of the context or a value fixed for the SCF
+// call, so with SP2 the sequence is the same for every iteration of k steps.
+void density_half(bscf_ctx* c, const bscf_scf_opts& o, const DiisArgs& d, const BatchInfo& bm,
+                  int k) {
+  const hipStream_t st = c->stream;
+  const int ni = c->ninst;
+  // M = F P S, e = X (M - M^T) X
+  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->F.p, c->P.p, 0.0,
+       c->tmp1.p);
+  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->tmp1.p, c->S.p, 0.0,
+       c->tmp2.p);
+  launch_antisym(c->batch(false), c->max_n, c->tmp2.p, c->tmp1.p, c->d_emax.p, st);
+  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->X.p, c->tmp1.p, 0.0,
+       c->tmp2.p);
+  gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->tmp2.p, c->X.p, 0.0,
+       c->err.p);
+  launch_convergence(ni, c->max_n, c->d_nbf.p, c->d_E.p, c->d_Eprev.p, c->d_emax.p, o.e_tol,
+                     o.comm_tol, c->d_active.p, c->d_conv_iter.p, c->d_status.p, st);
+  launch_diis_store(d, c->max_n, c->F.p, c->err.p, st);
+  launch_diis_extrapolate(d, c->max_n, c->Fbar.p, st);
+  if (k >= 0) {
+    ortho_fock(c, c->Fbar.p);
+    sp2_launch(c, bm, k, c->Pnew.p);
+  } else {
+    orbitals_from_fock(c, c->Fbar.p);
+    density_from_orbitals(c, c->Pnew.p);
+  }
+  launch_commit(bm, c->max_n, c->Pnew.p, c->P.p, st);
+  launch_concat_ints(c->d_active.p, ni, k >= 0 ? c->d_sp2c.p + (k & 1) * ni : nullptr,
+                     k >= 0 ? ni : 0, c->d_pin.p, st);
+}
+
+// density_half with SP2 of k steps as one launch of a HIP graph, captured
+// from the same calls the first time this (k, tolerances, DIIS size) occurs.
+void density_half_graph(bscf_ctx* c, const bscf_scf_opts& o, const DiisArgs& d,
+                        const BatchInfo& bm, int k) {
+  const auto key = std::make_tuple(k, o.e_tol, o.comm_tol, o.diis_size);
+  auto g = c->graphs.find(key);
+  if (g == c->graphs.end()) {
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipGraph_t graph = nullptr;
+    try {
+      density_half(c, o, d, bm, k);
+    } catch (...) {
+      (void)hipStreamEndCapture(c->stream, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(c->stream, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t r = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(r);
+    g = c->graphs.emplace(key, exec).first;
+    c->graph_captures++;
+  }
+  HIPCHK(hipGraphLaunch(g->second, c->stream));
+  c->graph_launches++;
 }
 
 void build_shell_topology(bscf_ctx* c) {
@@ -1387,6 +1467,7 @@ bscf_status bscf_default_opts(bscf_scf_opts* o) {
   o->deterministic = 0;
   o->density = BSCF_DENSITY_SP2;
   o->incremental = 1;
+  o->graph = 1;
   return BSCF_OK;
 }
 
@@ -1459,6 +1540,7 @@ bscf_status bscf_destroy(bscf_ctx* c) {
     (void)hipEventDestroy(r.e1);
   }
   for (hipEvent_t e : c->prof_free) (void)hipEventDestroy(e);
+  c->drop_graphs();
   if (c->blas) rocblas_destroy_handle(c->blas);
   for (int k = 0; k < bscf_ctx::kAux; ++k) {
     if (c->aux[k]) (void)hipStreamSynchronize(c->aux[k]);
@@ -1477,6 +1559,9 @@ bscf_status bscf_load_basis(bscf_ctx* c, const char* json) {
   return guard([&] {
     need(c && json, BSCF_E_INVALID, "NULL argument");
     join_work(c);
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->drop_graphs();
     JParser p{json};
     JVal root = p.parse();
     const JVal* el = root.get("elements");
@@ -1514,6 +1599,8 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     need(!c->basis.empty(), BSCF_E_INVALID, "load a basis first");
     HIPCHK(hipSetDevice(c->device));
     join_work(c);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->drop_graphs();   // they hold addresses of buffers about to be resized
     c->ninst = n_inst;
     c->natoms.assign(n_atoms, n_atoms + n_inst);
     c->atom_off.assign(n_inst, 0);
@@ -1920,37 +2007,13 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     int it = 0;
     for (; it < o.max_iter; ++it) {
       fock_build(c, o.schwarz_tol, o.precision, true, o.incremental && it % kFullEvery != 0);
-      // M = F P S, e = X (M - M^T) X
-      gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->F.p, c->P.p, 0.0,
-           c->tmp1.p);
-      gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->tmp1.p, c->S.p,
-           0.0, c->tmp2.p);
-      launch_antisym(c->batch(false), c->max_n, c->tmp2.p, c->tmp1.p, c->d_emax.p, st);
-      gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->X.p, c->tmp1.p,
-           0.0, c->tmp2.p);
-      gemm(c, rocblas_operation_none, rocblas_operation_none, -1, -1, -1, 1.0, c->tmp2.p, c->X.p,
-           0.0, c->err.p);
-      launch_convergence(ni, c->max_n, c->d_nbf.p, c->d_E.p, c->d_Eprev.p, c->d_emax.p, o.e_tol,
-                         o.comm_tol, it,
-                         c->d_active.p, c->d_conv_iter.p, c->d_status.p, st);
-      // The next density is launched before the host knows which replicas
-      // converged: DIIS, SP2 and the commit follow the device's active flags,
-      // so a finished replica is left alone and a finished batch costs only
-      // these masked launches.  One synchronisation per iteration then reads
-      // the flags and whether every SP2 projection finished.
-      launch_diis_store(d, c->max_n, c->F.p, c->err.p, st);
-      launch_diis_extrapolate(d, c->max_n, c->Fbar.p, st);
-      int k = -1;
-      if (o.density == BSCF_DENSITY_SP2) {
-        ortho_fock(c, c->Fbar.p);
-        k = sp2_launch(c, bm, sp2_slot(it), c->Pnew.p);
-      } else {
-        orbitals_from_fock(c, c->Fbar.p);
-        density_from_orbitals(c, c->Pnew.p);
-      }
-      launch_commit(bm, c->max_n, c->Pnew.p, c->P.p, st);
-      launch_concat_ints(c->d_active.p, ni, k >= 0 ? c->d_sp2c.p + (k & 1) * ni : nullptr,
-                         k >= 0 ? ni : 0, c->d_pin.p, st);
+      // the rest of the iteration goes out before the host knows which
+      // replicas this iteration finishes (density_half); one synchronisation
+      // per iteration then reads the active flags and whether every SP2
+      // projection finished
+      const int k = o.density == BSCF_DENSITY_SP2 ? sp2_target(c, sp2_slot(it)) : -1;
+      if (k >= 0 && o.graph) density_half_graph(c, o, d, bm, k);
+      else density_half(c, o, d, bm, k);
       HIPCHK(hipMemcpyAsync(c->h_pin.p, c->d_pin.p, (k >= 0 ? 2 : 1) * ni * sizeof(int),
                             hipMemcpyDeviceToHost, st));
       sync(c);
@@ -1963,8 +2026,9 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
       if (k >= 0) {
         // a projection still short of its need is finished here, or falls
         // back to the eigenvector route when it has no gap
-        if (!sp2_finished(c, flags, k, sp2_slot(it))) {
-          if (!sp2_extend(c, bm, flags, sp2_slot(it), k, c->Pnew.p)) {
+        int ks = k;
+        if (!sp2_finished(c, flags, ks, sp2_slot(it))) {
+          if (!sp2_extend(c, bm, flags, sp2_slot(it), ks, c->Pnew.p)) {
             c->sp2_fallbacks++;
             orbitals_from_fock(c, c->Fbar.p);
             density_from_orbitals(c, c->Pnew.p);
@@ -1972,7 +2036,7 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
           launch_commit(bm, c->max_n, c->Pnew.p, c->P.p, st);
         }
         c->sp2_calls++;
-        c->sp2_steps += k;
+        c->sp2_steps += ks;
       }
       for (int i = 0; i < ni; ++i) updates[i] += flags[i] != 0;
     }
@@ -2335,6 +2399,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
     c->fock_builds = c->scf_iters = 0;
     c->sp2_calls = c->sp2_steps = c->sp2_needed = c->sp2_fallbacks = 0;
     c->inc_builds = 0;
+    c->graph_launches = c->graph_captures = 0;
   });
 }
 
@@ -2354,6 +2419,7 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
       << ", \"sp2_calls\": " << c->sp2_calls << ", \"sp2_steps\": " << c->sp2_steps
       << ", \"sp2_steps_needed\": " << c->sp2_needed
       << ", \"sp2_fallbacks\": " << c->sp2_fallbacks << ", \"incremental_builds\": " << c->inc_builds
+      << ", \"graph_launches\": " << c->graph_launches << ", \"graph_captures\": " << c->graph_captures
       << ", \"classes\": {";
     const QuartetClass* qc = quartet_classes();
     for (int q = 0; q < kNumQuartetClasses; ++q) {

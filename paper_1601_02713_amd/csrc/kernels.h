@@ -139,11 +139,14 @@ struct DiisArgs {
 void launch_diis_store(const DiisArgs& d, int max_n, const double* F, const double* e,
                        hipStream_t s);
 void launch_diis_extrapolate(const DiisArgs& d, int max_n, double* Fbar, hipStream_t s);
-// convergence flags: emax[i] = max |A - A^T| from launch_antisym's tile
-// maxima; conv[i] = |E - Eprev| < etol && emax < ctol (only active)
+// convergence flags of the active instances: emax[i] = max |A - A^T| from
+// launch_antisym's tile maxima; niter[i] += 1; instance i converges (leaves
+// the active set) when it has a previous energy and |E - Eprev| < etol and
+// emax < ctol.  No host value changes between iterations, so the launch can
+// be replayed from a graph.
 void launch_convergence(int ninst, int max_n, const int* nbf, const double* E, double* Eprev,
-                        double* emax, double etol, double ctol, int iter, int* active,
-                        int* conv_iter, int* status, hipStream_t s);
+                        double* emax, double etol, double ctol, int* active, int* niter,
+                        int* status, hipStream_t s);
 // SP2 purification (scf.hip).  launch_sp2_bounds: Gershgorin intervals of
 // the rows of each instance's F' (bounds[inst][row] = (lo, hi), room for
 // ninst * max_n pairs).  launch_sp2_init: X = (hi I - (F' + F'^T)/2)/(hi - lo)

@@ -315,11 +315,13 @@ __global__ void diis_combine_kernel(DiisArgs d, double* Fbar) {
   }
 }
 
+// niter[i] counts the iterations instance i has taken (it stops when the
+// instance leaves the active set, so it ends as the iteration count).
 __global__ __launch_bounds__(64) void convergence_kernel(int ninst, int max_n, const int* nbf,
                                                         const double* E, double* Eprev,
                                                         const double* tmax, double* emax,
-                                                        double etol, double ctol, int iter,
-                                                        int* active, int* conv_iter, int* status) {
+                                                        double etol, double ctol, int* active,
+                                                        int* niter, int* status) {
   const int i = blockIdx.x;
   if (!active[i]) return;
   const int nt = ntiles_1d(nbf[i]), ntm = ntiles_1d(max_n);
@@ -329,17 +331,17 @@ __global__ __launch_bounds__(64) void convergence_kernel(int ninst, int max_n, c
   for (int off = 32; off > 0; off >>= 1) em = nan_max(em, __shfl_xor(em, off, 64));
   if (threadIdx.x != 0) return;
   emax[i] = em;
+  const int iter = niter[i];
+  niter[i] = iter + 1;
   const double e = E[i];
   if (!isfinite(e) || !isfinite(em)) {
     active[i] = 0;
     status[i] |= 2;
-    conv_iter[i] = iter + 1;
     return;
   }
   if (iter > 0 && fabs(e - Eprev[i]) < etol && em < ctol) {
     active[i] = 0;
     status[i] &= ~1;
-    conv_iter[i] = iter + 1;
   }
   Eprev[i] = e;
 }
@@ -688,10 +690,10 @@ void launch_diis_extrapolate(const DiisArgs& d, int max_n, double* Fbar, hipStre
 }
 
 void launch_convergence(int ninst, int max_n, const int* nbf, const double* E, double* Eprev,
-                        double* emax, double etol, double ctol, int iter, int* active,
-                        int* conv_iter, int* status, hipStream_t s) {
+                        double* emax, double etol, double ctol, int* active, int* niter,
+                        int* status, hipStream_t s) {
   hipLaunchKernelGGL(convergence_kernel, dim3(ninst), dim3(64), 0, s, ninst, max_n, nbf, E, Eprev,
-                     emax + ninst, emax, etol, ctol, iter, active, conv_iter, status);
+                     emax + ninst, emax, etol, ctol, active, niter, status);
 }
 
 void launch_concat_ints(const int* a, int na, const int* b, int nb, int* out, hipStream_t s) {

@@ -293,3 +293,39 @@ def test_incremental_builds_agree(eng, b631gs):
         assert np.abs(F0[k] - F1[k]).max() < 1e-7
     r = oracle.scf(oracle.build_basis(b631gs, *inst[0]), 1e-10, 1e-8)
     assert abs(E1[0] - r["E"]) < 1e-8
+
+
+def test_graph_replay_matches_eager(eng):
+    """The steps of each SCF iteration after the Fock build replayed from a
+    captured HIP graph give what the same launches one by one give: four
+    (H2O)3 beads, a core-guess SCF and then, at displaced geometries, a
+    previous-step-guess SCF (so one graph is replayed across iterations and
+    calls, with eager Fock builds and host synchronisations between the
+    replays).  Energies within 1e-10 Eh, densities and forces within 1e-8,
+    equal iteration counts, and every iteration one graph launch."""
+    z, x = inputs.water_cluster(3, 17)
+    bx = inputs.beads(z, x, 4, 17)
+    by = inputs.beads(z, x, 4, 18)
+    out = {}
+    for graph in (0, 1):
+        _setup(eng, "6-31g*", [(z, bx[k]) for k in range(4)])
+        eng.reset_stats()
+        res = []
+        for geoms, guess in ((None, 0), (by, 1)):
+            if geoms is not None:
+                eng.set_geometries([geoms[k] for k in range(4)])
+            E, it, st = eng.run_scf(e_tol=1e-10, comm_tol=1e-8, graph=graph, guess=guess)
+            assert (st == 0).all()
+            res.append((E, it, [eng.density(k) for k in range(4)], eng.forces()))
+        s = eng.stats()
+        out[graph] = (res, s["graph_launches"], s["graph_captures"], s["scf_iterations"])
+    (r0, l0, c0, n0), (r1, l1, c1, n1) = out[0], out[1]
+    print("graph launches", l1, "captures", c1, "iterations", n1)
+    assert l0 == 0 and c0 == 0
+    assert l1 == n1 and 1 <= c1 < l1
+    for (E0, it0, P0, F0), (E1, it1, P1, F1) in zip(r0, r1):
+        assert (it0 == it1).all()
+        assert np.abs(E0 - E1).max() < 1e-10
+        for k in range(4):
+            assert np.abs(P0[k] - P1[k]).max() < 1e-8
+            assert np.abs(F0[k] - F1[k]).max() < 1e-8
