@@ -236,6 +236,7 @@ def main():
         "phase_ms_per_step": {k: st_json[k] / args.steps for k in
                               ("t_setup_ms", "t_scf_ms", "t_grad_ms", "t_fock_ms", "t_work_ms",
                                "t_work_host_ms")},
+        "work_list_host_phases_ms_per_step": [v / args.steps for v in st_json["t_work_phase_ms"]],
         "density": {"method": "sp2", "calls_per_step": st_json["sp2_calls"] / args.steps,
                     "projection_steps_per_call": st_json["sp2_steps"] / max(st_json["sp2_calls"], 1),
                     "projection_steps_needed_per_call":

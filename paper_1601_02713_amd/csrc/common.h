@@ -17,6 +17,11 @@ constexpr double kBoysTmax = 40.0;  // asymptotic branch at and above
 constexpr int kBoysCols = 24;       // F_0..F_22 and exp(-T_k) in column 23
 constexpr int kBoysExpCol = 23;
 constexpr int kWave = 64;
+// XCDs of an MI355X.  The dispatcher deals the workgroups of a launch to
+// them in turn by linear id, and each XCD has its own L2, so launches that
+// want an instance's data to stay in one L2 place its blocks at ids
+// congruent modulo kXcds.
+constexpr int kXcds = 8;
 
 // Primitive pair of a contracted shell pair (a, b) with la >= lb.
 struct PrimPair {

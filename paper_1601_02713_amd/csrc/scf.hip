@@ -427,6 +427,20 @@ __global__ void sp2_bounds_kernel(BatchInfo b, int max_n, const double* F, doubl
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// Per-instance tile grids launched one-dimensional over xcd_grid(ninst, T)
+// blocks: block L runs on XCD L % kXcds, and instance i's T tiles all take
+// blocks on XCD i % kXcds, so they share that XCD's L2.  False for the
+// padding blocks past the last instance.
+__device__ inline bool xcd_tile(int ninst, int T, int& inst, int& tile) {
+  const int L = blockIdx.x, x = L % kXcds, j = L / kXcds;
+  inst = x + kXcds * (j / T);
+  tile = j % T;
+  return inst < ninst;
+}
+inline unsigned xcd_grid(int ninst, int T) {
+  return (unsigned)(kXcds * ((ninst + kXcds - 1) / kXcds) * T);
+}
+
 // sum of the per-tile partial (Tr, Tr^2) rows of one instance (a block-wide
 // call; the result is valid in every thread)
 __device__ void sp2_stats(const double* st, int nt2, double& tr, double& t2, double* sh) {
@@ -476,16 +490,17 @@ __device__ void sp2_store_stats(double a, double q, double* st, double* sh) {
 
 // X_0 = (hi I - (F' + F'^T)/2) / (hi - lo) over the union of the rows'
 // Gershgorin intervals; the symmetrised start keeps every later X exactly
-// symmetric.  Grid (tile of the 32 x 32 tiling, instance); each tile stores its
+// symmetric.  One block per (instance, 32 x 32 tile), placed by xcd_tile; each tile stores its
 // (Tr, Tr^2) partial at st[inst][tile]; conv[inst] = -1 (not converged).
 __global__ __launch_bounds__(256) void sp2_init_kernel(BatchInfo b, int max_n, const double* F,
                                                        const double* rowb, double* X, double* st,
                                                        int* conv) {
   __shared__ double sh[8];
-  const int inst = blockIdx.y;
+  const int ntm = ntiles_1d(max_n);
+  int inst, tile;
+  if (!xcd_tile(b.ninst, ntm * ntm, inst, tile)) return;
   if (b.active && !b.active[inst]) return;
-  const int n = b.nbf[inst], nt = ntiles_1d(n), ntm = ntiles_1d(max_n);
-  const int tile = blockIdx.x;
+  const int n = b.nbf[inst], nt = ntiles_1d(n);
   if (tile >= nt * nt) return;
   if (tile == 0 && threadIdx.x == 0) conv[inst] = -1;
   const long long o = b.moff[inst];
@@ -549,10 +564,11 @@ __global__ __launch_bounds__(256) void sp2_gemm_kernel(BatchInfo b, int max_n, c
   constexpr int kPer = kSp2K * kTile / 256;   // panel elements per thread and chunk
   __shared__ double sh[8];
   __shared__ double As[kSp2K][kTile], Bs[kSp2K][kTile];
-  const int inst = blockIdx.y;
+  const int ntm = ntiles_1d(max_n);
+  int inst, tile;
+  if (!xcd_tile(b.ninst, ntm * ntm, inst, tile)) return;
   if (b.active && !b.active[inst]) return;
-  const int n = b.nbf[inst], nt = ntiles_1d(n), ntm = ntiles_1d(max_n);
-  const int tile = blockIdx.x;
+  const int n = b.nbf[inst], nt = ntiles_1d(n);
   if (tile >= nt * nt) return;
   const long long o = b.moff[inst];
   const int ti0 = (tile / nt) * kTile, tj0 = (tile % nt) * kTile;
@@ -717,16 +733,16 @@ void launch_sp2_bounds(const BatchInfo& b, int max_n, const double* F, double* b
 void launch_sp2_init(const BatchInfo& b, int max_n, const double* F, const double* bounds,
                      double* X, double* st, int* conv, hipStream_t s) {
   const int nt = ntiles_1d(max_n);
-  hipLaunchKernelGGL(sp2_init_kernel, dim3(nt * nt, b.ninst), dim3(256), 0, s, b, max_n, F, bounds,
-                     X, st, conv);
+  hipLaunchKernelGGL(sp2_init_kernel, dim3(xcd_grid(b.ninst, nt * nt)), dim3(256), 0, s, b, max_n,
+                     F, bounds, X, st, conv);
 }
 
 void launch_sp2_step(const BatchInfo& b, int max_n, const int* nocc, const double* X, double* Xn,
                      const double* st_in, double* st_out, int step, double idem_tol,
                      double trace_tol, const int* conv_in, int* conv_out, hipStream_t s) {
   const int nt = ntiles_1d(max_n);
-  hipLaunchKernelGGL(sp2_gemm_kernel, dim3(nt * nt, b.ninst), dim3(256), 0, s, b, max_n, nocc, X,
-                     Xn, st_in, st_out, step, idem_tol, trace_tol, conv_in, conv_out);
+  hipLaunchKernelGGL(sp2_gemm_kernel, dim3(xcd_grid(b.ninst, nt * nt)), dim3(256), 0, s, b, max_n,
+                     nocc, X, Xn, st_in, st_out, step, idem_tol, trace_tol, conv_in, conv_out);
 }
 
 int sp2_tiles(int max_n) { return ntiles_1d(max_n) * ntiles_1d(max_n); }

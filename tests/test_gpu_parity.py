@@ -329,3 +329,37 @@ def test_graph_replay_matches_eager(eng):
         for k in range(4):
             assert np.abs(P0[k] - P1[k]).max() < 1e-8
             assert np.abs(F0[k] - F1[k]).max() < 1e-8
+
+
+def test_full_size_bead_batch(eng, b631gs):
+    """The benchmark's batch at full size, in its launch configuration: 16
+    beads of (H2O)8 in 6-31G* (152 functions), FP64, core guess, SCF to
+    1e-8 Eh with incremental builds and graph replay.  Every bead converges
+    with Tr(PS) = 80 electrons and zero net force; on sampled beads the
+    oracle's Fock matrix and energy at the GPU's converged density agree with
+    the GPU's within 1e-9 and 1e-8 Eh, and on one of them the oracle's
+    gradient at that density and Fock matrix with the GPU's forces within
+    1e-7 Eh/bohr."""
+    w = inputs.workload("w8_beads")
+    inst = w["instances"]
+    assert len(inst) == 16
+    _setup(eng, w["basis"], inst)
+    E, it, st = eng.run_scf(e_tol=w["e_tol"], comm_tol=w["comm_tol"], max_iter=60)
+    assert (st == 0).all(), st
+    F = eng.forces()
+    Ps = [eng.density(k) for k in range(16)]
+    Fg, Eg = eng.build_fock(Ps)
+    for k in range(16):
+        S, _, _ = oracle.one_electron(oracle.build_basis(b631gs, *inst[k]))
+        assert abs(np.sum(Ps[k] * S) - 80.0) < 1e-8
+        assert np.abs(F[k].sum(axis=0)).max() < 1e-8
+        assert abs(Eg[k] - E[k]) < 1e-8
+    for k in (0, 11):
+        b = oracle.build_basis(b631gs, *inst[k])
+        S, T, V = oracle.one_electron(b)
+        Fo, Eo = oracle.fock_energy(b, T + V, Ps[k])
+        assert np.abs(Fg[k] - Fo).max() < 1e-9
+        assert abs(E[k] - Eo) < 1e-8
+        if k == 11:   # (the oracle's gradient takes about 10 s at this size)
+            g = oracle.gradient(b, Ps[k], Fo)
+            assert np.abs(F[k] + g).max() < 1e-7
