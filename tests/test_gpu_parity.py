@@ -54,6 +54,15 @@ def test_device_boys_against_mpmath(eng):
                         mpmath.gammainc(m + mpmath.mpf(1) / 2, 0, tt) / (2 * tt ** (m + mpmath.mpf(1) / 2)))
             assert abs(F64[i, m] - ref) <= 2e-14 * ref, (t, m, F64[i, m], ref)
             assert abs(F32[i, m] - ref) <= 2e-6 * ref, (t, m, F32[i, m], ref)
+    # F_0 alone (the body the classes with total angular momentum 0 use),
+    # around the grid points and the large-T branch
+    T0 = np.concatenate([T, [1e-6, 0.005, 0.009999, 0.01, 0.010001, 0.02, 1.0, 12.5]])
+    F0 = eng.boys(0, T0, 0)
+    for i, t in enumerate(T0):
+        tt = mpmath.mpf(float(t))
+        ref = float(1 if tt == 0 else
+                    mpmath.gammainc(mpmath.mpf(1) / 2, 0, tt) / (2 * tt ** (mpmath.mpf(1) / 2)))
+        assert abs(F0[i, 0] - ref) <= 2e-14 * ref, (t, F0[i, 0], ref)
 
 
 @pytest.mark.parametrize("case,basis", [("h2o_sto3g", "sto-3g"), ("h2o_sto3g", "6-31g*")])
