@@ -146,12 +146,23 @@ __device__ __forceinline__ int2 block_rc(int t, int m0, int n0, int l0, int s0) 
   return make_int2(n0 + t / ND, s0 + t % ND);
 }
 
-// Quartet of block b of a cooperative launch (one quartet per block).
-__device__ __forceinline__ bool coop_quartet(const WorkItem* items, const WorkRow* rows,
-                                             const int* kets, int b, int& bid, int& kid) {
-  const WorkItem it = items[b >> 6];
+// Quartet of block b of a cooperative launch (one quartet per block, over
+// coop_blocks(nitems) blocks).  Block b runs on XCD b % kXcds; that XCD's
+// blocks take the items at positions congruent to it modulo kXcds in order,
+// 64 blocks (one per quartet) per item.  False for blocks past the items
+// and for lanes past an item's quartets.
+__device__ __forceinline__ bool coop_quartet(const WorkItem* items, int nitems,
+                                             const WorkRow* rows, const int* kets, int b,
+                                             int& bid, int& kid) {
+  const int x = b % kXcds, j = b / kXcds;
+  const int pos = x + kXcds * (j >> 6);
+  if (pos >= nitems) return false;
+  const WorkItem it = items[pos];
   bool single;
-  return lane_quartet(it, rows, kets, b & (kWave - 1), bid, kid, single);
+  return lane_quartet(it, rows, kets, j & (kWave - 1), bid, kid, single);
+}
+__host__ __device__ inline unsigned coop_blocks(int nitems) {
+  return (unsigned)(kXcds * ((nitems + kXcds - 1) / kXcds) * kWave);
 }
 
 template <class CP>
@@ -160,7 +171,7 @@ __global__ __launch_bounds__(CP::NT) void coop_fock_kernel(FockArgs a) {
   __shared__ double slots[CP::NSLOT];
   __shared__ double sc[kNumSel];
   int bid, kid;
-  if (!coop_quartet(a.items, a.rows, a.kets, blockIdx.x, bid, kid)) return;
+  if (!coop_quartet(a.items, a.nitems, a.rows, a.kets, blockIdx.x, bid, kid)) return;
   const ShellPair bra = a.pairs[bid], ket = a.pairs[kid];
   const Shell sa = a.shells[bra.a], sb = a.shells[bra.b], sc_ = a.shells[ket.a],
               sd = a.shells[ket.b];
@@ -263,7 +274,7 @@ __global__ __launch_bounds__(CP::NT) void coop_grad_kernel(GradArgs a) {
   __shared__ double ctab[CP::NCTAB];
   __shared__ double red[NW][9];
   int bid, kid;
-  if (!coop_quartet(a.items, a.rows, a.kets, blockIdx.x, bid, kid)) return;
+  if (!coop_quartet(a.items, a.nitems, a.rows, a.kets, blockIdx.x, bid, kid)) return;
   const ShellPair bra = a.pairs[bid], ket = a.pairs[kid];
   const Shell sa = a.shells[bra.a], sb = a.shells[bra.b], sc_ = a.shells[ket.a],
               sd = a.shells[ket.b];

@@ -922,7 +922,7 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
   struct Tmp {
     WorkItem w;
     double cost;
-    int inst;   // (units only) instance of the unit's rows
+    int inst;   // instance of the rows
   };
   // The lists of one (class, instance), row indices local to the part; the
   // class's lists are the parts in instance order.
@@ -1021,7 +1021,7 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
             off = 0;
           }
         }
-        P.tmp.push_back({w, cost});
+        P.tmp.push_back({w, cost, i});
       }
     }
   };
@@ -1074,64 +1074,58 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
     // the product of its bra and ket primitive counts, an integer: exact
     // order.  A unit's cost is a sum over its rows; units are ordered by
     // eighths of an octave of it (the order only schedules the work).
-    auto counting = [](const std::vector<Tmp>& v, std::vector<WorkItem>& out, auto&& key, int nkey) {
-      std::vector<int> start(nkey + 1, 0);
-      for (const Tmp& t : v) ++start[key(t.cost) + 1];
-      for (int b = 0; b < nkey; ++b) start[b + 1] += start[b];
-      out.resize(v.size());
-      for (const Tmp& t : v) out[start[key(t.cost)]++] = t.w;
-    };
-    // item keys: 4096 - cost (primitive counts per shell pair stay below 64);
-    // unit keys: 320 - eighths of octaves (costs stay below 2^40)
-    counting(tmp, W.items, [](double cst) { return 4096 - std::min((int)cst, 4096); }, 4097);
-    {
-      // units by cost; with kXcds or more instances then dealt so that the
-      // unit at position L (the block of that linear id) belongs to an
-      // instance i with i % kXcds == L % kXcds: each XCD works on its own
-      // instances and keeps their ket data in its L2.  Each XCD's units stay
-      // in cost order; once one XCD's run out, the rest follow in cost order.
-      constexpr int nk = 321;
-      auto key = [](double cst) {
-        const int b = cst > 1.0 ? (int)(8.0 * std::log2(cst)) : 0;
-        return 320 - std::min(b, 320);
-      };
+    // Items and units go most expensive first.  With kXcds or more instances
+    // they are then dealt so that the one at launch position L belongs to an
+    // instance i with i % kXcds == L % kXcds: the dispatcher deals workgroups
+    // to the XCDs in turn, so each XCD works on its own instances and keeps
+    // their ket data in its L2 (a cooperative launch runs the 64 quartets of
+    // the item at position p on XCD p % kXcds).  Each XCD's share stays in
+    // cost order; once one XCD's share runs out, the rest follow in cost
+    // order.  Both orders are counting sorts (stable).
+    auto deal = [&](const std::vector<Tmp>& v, std::vector<WorkItem>& out, auto&& key, int nk) {
       const int nx = ni >= kXcds ? kXcds : 1;
       auto xkey = [&](const Tmp& t) { return (nx > 1 ? t.inst % kXcds : 0) * nk + key(t.cost); };
-      // one counting sort by (XCD, cost key): XCD x's units, in cost order,
-      // end up in sorted[begin[x], begin[x + 1])
+      // one counting sort by (XCD, cost key): XCD x's share, in cost order,
+      // ends up in sorted[begin[x], begin[x + 1])
       std::vector<int> start(nx * nk + 1, 0);
-      for (const Tmp& t : utmp) ++start[xkey(t) + 1];
+      for (const Tmp& t : v) ++start[xkey(t) + 1];
       for (int b = 0; b < nx * nk; ++b) start[b + 1] += start[b];
       std::vector<int> begin(nx + 1);
       for (int x = 0; x <= nx; ++x) begin[x] = start[x * nk];
-      std::vector<WorkItem> sorted(utmp.size());
-      std::vector<short> skey(nx > 1 ? utmp.size() : 0);
-      for (const Tmp& t : utmp) {
+      std::vector<WorkItem> sorted(v.size());
+      std::vector<int> skey(nx > 1 ? v.size() : 0);
+      for (const Tmp& t : v) {
         const int k = xkey(t), pos = start[k]++;
         sorted[pos] = t.w;
-        if (nx > 1) skey[pos] = (short)(k % nk);
+        if (nx > 1) skey[pos] = k % nk;
       }
-      auto& out = W.ul.units;
       if (nx == 1) {
         out.swap(sorted);
-      } else {
-        out.clear();
-        out.reserve(sorted.size());
-        int take = begin[1] - begin[0];
-        for (int x = 1; x < nx; ++x) take = std::min(take, begin[x + 1] - begin[x]);
-        for (int r = 0; r < take; ++r)
-          for (int x = 0; x < nx; ++x) out.push_back(sorted[begin[x] + r]);
-        // the rest by cost key (a counting sort over what is left)
-        std::vector<int> rs(nk + 1, 0);
-        for (int x = 0; x < nx; ++x)
-          for (int p = begin[x] + take; p < begin[x + 1]; ++p) ++rs[skey[p] + 1];
-        for (int b = 0; b < nk; ++b) rs[b + 1] += rs[b];
-        const size_t base = out.size();
-        out.resize(sorted.size());
-        for (int x = 0; x < nx; ++x)
-          for (int p = begin[x] + take; p < begin[x + 1]; ++p) out[base + rs[skey[p]]++] = sorted[p];
+        return;
       }
-    }
+      out.clear();
+      out.reserve(sorted.size());
+      int take = begin[1] - begin[0];
+      for (int x = 1; x < nx; ++x) take = std::min(take, begin[x + 1] - begin[x]);
+      for (int r = 0; r < take; ++r)
+        for (int x = 0; x < nx; ++x) out.push_back(sorted[begin[x] + r]);
+      // the rest by cost key (a counting sort over what is left)
+      std::vector<int> rs(nk + 1, 0);
+      for (int x = 0; x < nx; ++x)
+        for (int p = begin[x] + take; p < begin[x + 1]; ++p) ++rs[skey[p] + 1];
+      for (int b = 0; b < nk; ++b) rs[b + 1] += rs[b];
+      const size_t base = out.size();
+      out.resize(sorted.size());
+      for (int x = 0; x < nx; ++x)
+        for (int p = begin[x] + take; p < begin[x + 1]; ++p) out[base + rs[skey[p]]++] = sorted[p];
+    };
+    // item keys: 4096 - cost (primitive counts per shell pair stay below 64);
+    // unit keys: 320 - eighths of octaves (costs stay below 2^40)
+    deal(tmp, W.items, [](double cst) { return 4096 - std::min((int)cst, 4096); }, 4097);
+    deal(utmp, W.ul.units, [](double cst) {
+      const int b = cst > 1.0 ? (int)(8.0 * std::log2(cst)) : 0;
+      return 320 - std::min(b, 320);
+    }, 321);
     W.lds_ok = sizeof(double) * (size_t)unit_lds_doubles(qc[q].la, qc[q].lb, c->max_n,
                                                           c->max_prims) <= c->max_lds_bytes;
   };

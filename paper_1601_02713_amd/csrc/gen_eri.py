@@ -469,11 +469,11 @@ def coop_tu(la, lb, lc, ld):
              "}  // namespace",
              f"void launch_coop_fock_{tag}(const FockArgs& a, hipStream_t s) {{",
              "  if (a.nitems == 0) return;",
-             f"  hipLaunchKernelGGL((coop_fock_kernel<CoopE{tag}>), dim3(a.nitems * 64), dim3(CoopE{tag}::NT), 0, s, a);",
+             f"  hipLaunchKernelGGL((coop_fock_kernel<CoopE{tag}>), dim3(coop_blocks(a.nitems)), dim3(CoopE{tag}::NT), 0, s, a);",
              "}",
              f"void launch_coop_grad_{tag}(const GradArgs& a, hipStream_t s) {{",
              "  if (a.nitems == 0) return;",
-             f"  hipLaunchKernelGGL((coop_grad_kernel<CoopG{tag}>), dim3(a.nitems * 64), dim3(CoopG{tag}::NT), 0, s, a);",
+             f"  hipLaunchKernelGGL((coop_grad_kernel<CoopG{tag}>), dim3(coop_blocks(a.nitems)), dim3(CoopG{tag}::NT), 0, s, a);",
              "}",
              f"void launch_coop_tensor_{tag}(const TensorArgs& a, hipStream_t s) {{",
              "  if (a.nquart == 0) return;",
