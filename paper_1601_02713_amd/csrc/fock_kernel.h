@@ -92,8 +92,8 @@ struct TensorArgs {        // full ERI tensor of one instance (test path)
 // Contracted (ab|cd) block of class CL for one quartet, in type R.  Classes
 // with total angular momentum >= 6 keep one out-of-line copy shared by all
 // kernels of the class (bounded code size and compile time).
-template <class CL, typename R>
-__device__ __forceinline__ void eri_block_body(const PrimPair* __restrict__ bp, int nb,
+template <class CL, typename R, int BW = 12>
+__device__ __forceinline__ void eri_block_body(const double* __restrict__ bp, int nb,
                                           const PrimPair* __restrict__ kp, int nk, int ks,
                                           const double AB[3], const double CD[3],
                                           const double* __restrict__ tab64,
@@ -107,7 +107,14 @@ __device__ __forceinline__ void eri_block_body(const PrimPair* __restrict__ bp, 
   for (int j = 0; j < nk; ++j) {
     const PrimPair Q = kp[j * ks];
     for (int i = 0; i < nb; ++i) {
-      const PrimPair B = bp[i];
+      PrimPair B;
+      if constexpr (BW == 12) {
+        B = reinterpret_cast<const PrimPair*>(bp)[i];
+      } else {   // the compact (ss|ss) records {p, Px, Py, Pz, C}
+        static_assert(BW == 5 && L == 0, "compact bra records carry F_0 data only");
+        const double* r = bp + BW * i;
+        B = PrimPair{r[0], r[1], r[2], r[3], 0.0, 0.0, 0.0, r[4], 0.0, 0.0, 0.0, 0.0};
+      }
       const double pq = B.p + Q.p;
       const double rpq = rsqrt(pq);
       const double oopq = rpq * rpq;
@@ -141,11 +148,14 @@ __device__ __noinline__ void eri_block_outline(const PrimPair* __restrict__ bp, 
                                                const double* AB, const double* CD,
                                                const double* __restrict__ tab64,
                                                const float* __restrict__ tab32, R* out) {
-  eri_block_body<CL, R>(bp, nb, kp, nk, ks, AB, CD, tab64, tab32, out);
+  eri_block_body<CL, R>(reinterpret_cast<const double*>(bp), nb, kp, nk, ks, AB, CD, tab64, tab32,
+                        out);
 }
 
-// ket primitive j of the quartet is kp[j * ks]
-template <class CL, typename R>
+// ket primitive j of the quartet is kp[j * ks]; the bra's primitives are
+// PrimPair records, or with BW = 5 (class (ss|ss) only) the compact records
+// {p, Px, Py, Pz, C} of 5 doubles each
+template <class CL, typename R, int BW = 12>
 __device__ __forceinline__ void eri_block(const PrimPair* __restrict__ bp, int nb,
                                           const PrimPair* __restrict__ kp, int nk, int ks,
                                           const double AB[3], const double CD[3],
@@ -154,7 +164,8 @@ __device__ __forceinline__ void eri_block(const PrimPair* __restrict__ bp, int n
   if constexpr (CL::LA + CL::LB + CL::LC + CL::LD >= 6) {
     eri_block_outline<CL, R>(bp, nb, kp, nk, ks, AB, CD, tab64, tab32, out);
   } else {
-    eri_block_body<CL, R>(bp, nb, kp, nk, ks, AB, CD, tab64, tab32, out);
+    eri_block_body<CL, R, BW>(reinterpret_cast<const double*>(bp), nb, kp, nk, ks, AB, CD, tab64,
+                              tab32, out);
   }
 }
 
@@ -167,9 +178,11 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 // LDS footprint of the unit kernel of a class: K accumulators and P rows of the
 // bra shells, (NA + NB) rows of nmax doubles each, and the bra's primitive
-// pairs (at most max_prims records of 12 doubles).
+// pairs (at most max_prims records of 12 doubles; of 5 for an (ss) bra, whose
+// only class (ss|ss) needs p, P and C).  The footprint bounds the blocks per
+// CU, so it is kept small.
 __host__ __device__ constexpr int unit_lds_doubles(int la, int lb, int nmax, int max_prims) {
-  return 2 * (ncart(la) + ncart(lb)) * nmax + 12 * max_prims;
+  return 2 * (ncart(la) + ncart(lb)) * nmax + (la + lb == 0 ? 5 : 12) * max_prims;
 }
 
 // Quartets of unit u selected by sel (0: the kept ones of every row;
@@ -247,7 +260,9 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
   const int m0 = sa.bf, n0 = sb.bf;
   double* Kacc = lds;           // row r: K row of bf m0 + r (r < NA) or n0 + r - NA
   double* Prow = lds + NR * n;  // the same rows of P
-  PrimPair* Bp = reinterpret_cast<PrimPair*>(lds + 2 * NR * a.nmax);   // the bra's primitives
+  // the bra's primitives: whole records, or for an (ss) bra {p, Px, Py, Pz, C}
+  constexpr int BW = CL::LA + CL::LB == 0 ? 5 : 12;
+  PrimPair* Bp = reinterpret_cast<PrimPair*>(lds + 2 * NR * a.nmax);
   for (int t = lane; t < NR * n; t += kWave) {
     const int r = t / n, col = t - r * n;
     const int bf = r < NA ? m0 + r : n0 + (r - NA);
@@ -257,7 +272,14 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
   {
     const double* src = reinterpret_cast<const double*>(a.prims + bra.prim0);
     double* dst = reinterpret_cast<double*>(Bp);
-    for (int t = lane; t < 12 * bra.nprim; t += kWave) dst[t] = src[t];
+    for (int t = lane; t < BW * bra.nprim; t += kWave) {
+      if constexpr (BW == 12) {
+        dst[t] = src[t];
+      } else {
+        const int i = t / BW, f = t - i * BW;   // fields p, Px, Py, Pz, then C (field 7)
+        dst[t] = src[12 * i + (f < 4 ? f : 7)];
+      }
+    }
   }
   __syncthreads();
   double Pab[NA][NB], jab[NA][NB];
@@ -296,8 +318,8 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
     const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
     const int2 kp = a.kpos[pos];
     RP v[CL::NOUT];
-    eri_block<CL, RP>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64, a.boys32,
-                      v);
+    eri_block<CL, RP, BW>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64,
+                          a.boys32, v);
     const double g = ((bra.a == bra.b) ? 1.0 : 2.0) * ((ket.a == ket.b) ? 1.0 : 2.0) *
                      ((kid == bid) ? 1.0 : 2.0);
     const double fj = valid ? 0.5 * g : 0.0;
