@@ -51,8 +51,9 @@ constexpr int kUnitQuartets = 256;
 // 256 CUs) and keeps the reservation while the process lives; several
 // contexts in one process reach several queues.  Lane kernels that spill more
 // than this many bytes per lane are never launched (their class runs
-// cooperatively), which bounds every queue's reservation to about 1 GiB.
-constexpr int kMaxLaneScratch = 2048;
+// cooperatively), which bounds every queue's reservation to about 2 GiB of
+// the 288 GB; below it the autotuner times both forms and keeps the faster.
+constexpr int kMaxLaneScratch = 4096;
 
 // Incremental Fock builds: a full build at the first SCF iteration and every
 // kFullEvery iterations, which bounds the accumulated effect of the skipped
@@ -352,6 +353,7 @@ struct bscf_ctx {
     std::vector<WorkRow> rows;
     DevBuf<WorkItem> d_items;
     DevBuf<WorkRow> d_rows;
+    int max_prims = 1;   // largest primitive count of the class's bra pairs (sizes unit LDS)
     // per-bra units over every screened quartet; each row's pad is its FP64
     // prefix, the kets with Q_ab Q_cd at or above the FP32 split of MIXED mode
     struct UnitList {
@@ -383,6 +385,7 @@ struct bscf_ctx {
   DevBuf<int> d_kmap;          // source primitive pair of each kprims record
   DevBuf<int2> d_kpos;         // per position: first record, stride
   int max_prims = 1;
+  int max_prims_pc[kNumPairClasses] = {};   // the same per pair class
   int max_ncd = 0;
   size_t max_lds_bytes = 65536;
 
@@ -903,6 +906,7 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
     std::vector<int2> kpos(c->kets.size());
     std::vector<int> kmap;
     c->max_prims = 1;
+    std::fill(c->max_prims_pc, c->max_prims_pc + kNumPairClasses, 1);
     for (int i = 0; i < c->ninst; ++i)
       for (int pc = 0; pc < NPC; ++pc)
         for (const Sub& sb : subs[i][pc]) {
@@ -914,6 +918,7 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
             for (int j = 0; j < pr.nprim; ++j) kmap[kp0 + (size_t)j * ns + r] = pr.prim0 + j;
           }
           c->max_prims = std::max(c->max_prims, sb.nprim);
+          c->max_prims_pc[pc] = std::max(c->max_prims_pc[pc], sb.nprim);
         }
     c->h_kpos.swap(kpos);
     c->h_kmap.swap(kmap);
@@ -1126,8 +1131,9 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
       const int b = cst > 1.0 ? (int)(8.0 * std::log2(cst)) : 0;
       return 320 - std::min(b, 320);
     }, 321);
+    W.max_prims = c->max_prims_pc[pclass(qc[q].la, qc[q].lb)];
     W.lds_ok = sizeof(double) * (size_t)unit_lds_doubles(qc[q].la, qc[q].lb, c->max_n,
-                                                          c->max_prims) <= c->max_lds_bytes;
+                                                          W.max_prims) <= c->max_lds_bytes;
   };
   // host threads: first every (class, instance) part, then every class's merge
   // parts interleaved over classes, so that the large classes spread over the threads
@@ -1291,6 +1297,7 @@ void set_class(FockArgs& a, const bscf_ctx::ClassWork& W) {
   a.nunits = (int)W.ul.units.size();
   a.urows = W.ul.d_rows.p;
   a.ukeep = W.ul.d_keep.p;
+  a.max_prims = W.max_prims;
 }
 
 // Lane-kernel launch of class q: mode 0 every quartet in FP64, mode 2 the
@@ -1335,19 +1342,17 @@ void autotune_fock(bscf_ctx* c, int pcol) {
   HIPCHK(hipEventCreate(&e1));
   for (int q = 0; q < kNumQuartetClasses; ++q) {
     auto& W = c->work[q];
-    if (!qc[q].fock || !W.lds_ok || c->private_bytes[q][0] > kMaxLaneScratch ||
-        (pcol && c->private_bytes[q][1] > kMaxLaneScratch)) {
-      c->fock_variant[pcol][q] = 1;
-      continue;
-    }
+    for (float& t : c->tune_ms[pcol][q]) t = 0.0f;
+    const bool lane_ok = qc[q].fock && W.lds_ok && c->private_bytes[q][0] <= kMaxLaneScratch &&
+                         !(pcol && c->private_bytes[q][1] > kMaxLaneScratch);
+    if (!lane_ok) c->fock_variant[pcol][q] = 1;
     if (W.items.empty()) continue;
-    if (env && !strcmp(env, "lane")) { c->fock_variant[pcol][q] = 0; continue; }
-    if (env && !strcmp(env, "coop")) { c->fock_variant[pcol][q] = 1; continue; }
     set_class(a, W);
     // variants: 0 the lane form of this precision, 1 cooperative, and in
-    // MIXED mode 2 the FP64 lane form (FP32 integrals do not pay everywhere)
-    const int nv = pcol ? 3 : 2;
-    for (int v = 0; v < nv; ++v) {
+    // MIXED mode 2 the FP64 lane form (FP32 integrals do not pay everywhere);
+    // each timed alone (second of two runs), the chosen one at least, since
+    // the build's stream schedule uses its time
+    auto time_variant = [&](int v) {
       for (int rep = 0; rep < 2; ++rep) {
         HIPCHK(hipEventRecord(e0, c->stream));
         if (v == 1) qc[q].coop_fock(a, c->stream);
@@ -1357,7 +1362,18 @@ void autotune_fock(bscf_ctx* c, int pcol) {
       }
       HIPCHK(hipEventSynchronize(e1));
       HIPCHK(hipEventElapsedTime(&c->tune_ms[pcol][q][v], e0, e1));
+    };
+    int forced = -1;
+    if (!lane_ok) forced = 1;
+    else if (env && !strcmp(env, "lane")) forced = 0;
+    else if (env && !strcmp(env, "coop")) forced = 1;
+    if (forced >= 0) {
+      c->fock_variant[pcol][q] = forced;
+      time_variant(forced);
+      continue;
     }
+    const int nv = pcol ? 3 : 2;
+    for (int v = 0; v < nv; ++v) time_variant(v);
     int best = 0;
     for (int v = 1; v < nv; ++v)
       if (c->tune_ms[pcol][q][v] < c->tune_ms[pcol][q][best]) best = v;
@@ -1425,25 +1441,37 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
   const QuartetClass* qc = quartet_classes();
   // class kernels run concurrently on the context stream and three auxiliary
   // streams, one per hardware queue (J and K are accumulated with atomics, so
-  // their order does not matter); heavy classes are issued first because they
-  // are latency-bound, and the first goes to the context stream, which needs
-  // no cross-stream wait to start.  Kernels that need private scratch stay on
-  // the context stream: the runtime reserves scratch per hardware queue for
-  // full occupancy.
+  // their order does not matter): the longest first, each onto the stream with
+  // the least time queued, so the first goes to the context stream, which
+  // needs no cross-stream wait to start.  Kernels that need private scratch
+  // stay on the context stream: the runtime reserves scratch per hardware
+  // queue for full occupancy.
   constexpr int kRing = 4;
   const hipStream_t ring[kRing] = {c->stream, c->aux[0], c->aux[1], c->aux[2]};
   const int pbuild = c->profiling ? prof_begin(c, 0, 2, c->stream) : -1;
   launch_gather_pk(kp, c->max_ncd, a.P, c->d_Pk.p, c->stream);
   HIPCHK(hipEventRecord(c->ev_fork, c->stream));
   for (int k = 1; k < kRing; ++k) HIPCHK(hipStreamWaitEvent(ring[k], c->ev_fork, 0));
-  int slot = 0;
   const int pcol = precision == BSCF_MIXED ? 1 : 0;
-  for (int q = kNumQuartetClasses - 1; q >= 0; --q) {
+  // classes longest first (by the chosen kernel's time alone), each onto the
+  // stream with the least time queued
+  int order[kNumQuartetClasses];
+  for (int q = 0; q < kNumQuartetClasses; ++q) order[q] = kNumQuartetClasses - 1 - q;
+  auto alone = [&](int q) { return c->tune_ms[pcol][q][c->fock_variant[pcol][q]]; };
+  std::stable_sort(order, order + kNumQuartetClasses,
+                   [&](int x, int y) { return alone(x) > alone(y); });
+  float load[kRing] = {};
+  for (int q : order) {
     auto& W = c->work[q];
     if (W.items.empty()) continue;
     // one launch: kernels with private scratch go to the context stream
     auto launch = [&](int pbytes, auto&& run) {
-      const hipStream_t s = pbytes != 0 ? c->stream : ring[slot++ % kRing];
+      int k = 0;
+      if (pbytes == 0)
+        for (int t = 1; t < kRing; ++t)
+          if (load[t] < load[k]) k = t;
+      load[k] += alone(q);
+      const hipStream_t s = ring[k];
       const int pk = c->profiling ? prof_begin(c, q, 0, s) : -1;
       run(s);
       if (pk >= 0) prof_end(c, pk, s);
@@ -2190,6 +2218,7 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
       g.units = W.ul.d_units.p;
       g.nunits = (int)W.ul.units.size();
       g.urows = W.ul.d_rows.p;
+      g.max_prims = W.max_prims;
     };
     const QuartetClass* qc = quartet_classes();
     if (!c->grad_tuned) {
@@ -2217,7 +2246,7 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
         if (W.items.empty()) continue;
         set_gclass(gt, W);
         const bool lds_ok = sizeof(double) * (size_t)grad_unit_lds_doubles(
-                                qc[q].la, qc[q].lb, c->max_n, c->max_atoms, c->max_prims) <=
+                                qc[q].la, qc[q].lb, c->max_n, c->max_atoms, W.max_prims) <=
                             c->max_lds_bytes;
         const bool lane_ok = qc[q].grad && lds_ok && c->private_bytes[q][2] <= kMaxLaneScratch;
         if (lane_ok && !(env && !strcmp(env, "coop")))
