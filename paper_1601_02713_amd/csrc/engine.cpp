@@ -1493,9 +1493,9 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
         }
     W.launches++;
   }
-  for (int k = 1; k < kRing; ++k) {
-    HIPCHK(hipEventRecord(c->ev_join[k], ring[k]));
-    HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join[k], 0));
+  for (int k = 1; k < kRing; ++k) {   // ring[k] is aux[k - 1]
+    HIPCHK(hipEventRecord(c->ev_join[k - 1], ring[k]));
+    HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join[k - 1], 0));
   }
   launch_jk_finalize(kp, c->max_ncd, c->d_Jk.p, c->J.p, c->stream);
   HIPCHK(hipGetLastError());
