@@ -2291,8 +2291,8 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
     for (int pc = 0; pc < kNumPairClasses; ++pc)
       if (g1[pc].ntasks > 0) jobs.push_back({c->tune_grad1e_ms[pc], -1 - pc, 0});
     std::stable_sort(jobs.begin(), jobs.end(), [](const Job& x, const Job& y) { return x.ms > y.ms; });
-    constexpr int kNs = 1 + bscf_ctx::kAux;
-    const hipStream_t ring[kNs] = {st, c->aux[0], c->aux[1], c->aux[2], c->aux[3]};
+    constexpr int kNs = 4;   // one stream per hardware queue (five measured slower)
+    const hipStream_t ring[kNs] = {st, c->aux[0], c->aux[1], c->aux[2]};
     float load[kNs] = {};
     bool used[kNs] = {true};
     HIPCHK(hipEventRecord(c->ev_fork, st));
