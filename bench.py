@@ -114,6 +114,51 @@ def guess_study(w, n_steps, dt_fs=0.25, temperature=300.0):
     }
 
 
+def per_instance_study(w, n, opts):
+    """The first n instances of the workload through one batched engine, then
+    each through an engine of its own (one launch sequence per instance), both
+    warmed up first so that autotuning stays out of the timing: setup, SCF and
+    forces per pass, wall clock."""
+    import numpy as np
+    import inputs
+    from paper_1601_02713_amd import beadscf
+
+    inst = w["instances"][:n]
+    basis = inputs.load_basis(w["basis"])
+
+    def engine(group):
+        e = beadscf.Engine(0)
+        e.load_basis(basis)
+        e.set_instances([z for z, _ in group])
+        return e
+
+    def run(e, group):
+        e.set_geometries([x for _, x in group])
+        E, it, st = e.run_scf(opts)
+        e.forces()
+        return E, it
+
+    eb = engine(inst)
+    run(eb, inst)
+    t0 = time.perf_counter()
+    Eb, itb = run(eb, inst)
+    t_batched = time.perf_counter() - t0
+    eb.close()
+    t_single, dE, its = 0.0, 0.0, []
+    for k, one in enumerate(inst):
+        e = engine([one])
+        run(e, [one])
+        t0 = time.perf_counter()
+        E1, it1 = run(e, [one])
+        t_single += time.perf_counter() - t0
+        e.close()
+        dE = max(dE, abs(float(E1[0]) - float(Eb[k])))
+        its.append(int(it1[0]))
+    return {"instances": n, "batched_ms": t_batched * 1e3, "per_instance_ms": t_single * 1e3,
+            "speedup": t_single / t_batched, "max_abs_dE_Eh": dE,
+            "scf_iterations_batched": [int(v) for v in itb], "scf_iterations_single": its}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +170,8 @@ def main():
                     help="mixed precision: quartets with Q_ab Q_cd below this run in FP32")
     ap.add_argument("--graph", type=int, choices=[0, 1], default=1,
                     help="replay each SCF iteration's steps after the Fock build from a HIP graph")
+    ap.add_argument("--per-instance", type=int, default=0, metavar="N",
+                    help="also time the first N instances batched against one engine each")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--guess-steps", type=int, default=8,
@@ -268,6 +315,8 @@ def main():
             "max_abs_dE_vs_fp64_Eh": float(dE.max()), "max_abs_dF_vs_fp64_Eh_per_bohr": float(dF.max()),
             "per_bead_abs_dE_Eh": [float(v) for v in dE],
             "per_bead_max_abs_dF_Eh_per_bohr": [float(v) for v in dF]}
+    if args.per_instance > 0:
+        out["per_instance"] = per_instance_study(w, args.per_instance, opts)
     if args.guess_steps > 0:
         eng.close()
         out["learned_guess"] = guess_study(w, args.guess_steps)
