@@ -92,9 +92,14 @@ def guess_study(w, n_steps, dt_fs=0.25, temperature=300.0):
     e1, e2 = beadscf.Engine(0), beadscf.Engine(0)
     try:
         poly = md.RingPolymer(z, xb.copy(), v, temperature)
-        ref, traj = md.run(e1, poly, n_steps, dt_fs, guess="previous", opts=opts, basis=basis)
+        def log(kind):
+            return lambda r: print(f"[guess study] {kind} guess: MD step {r.step} done",
+                                   file=sys.stderr, flush=True)
+        ref, traj = md.run(e1, poly, n_steps, dt_fs, guess="previous", opts=opts, basis=basis,
+                           log=log("previous-step"))
         lrn, _ = md.run(e2, poly, n_steps, dt_fs, guess="learned", opts=opts, geometries=traj,
-                        train_from=1, train_steps=5, predict_from=3, basis=basis)
+                        train_from=1, train_steps=5, predict_from=3, basis=basis,
+                        log=log("learned"))
     finally:
         e1.close()
         e2.close()
@@ -154,6 +159,7 @@ def per_instance_study(w, n, opts):
         e.close()
         dE = max(dE, abs(float(E1[0]) - float(Eb[k])))
         its.append(int(it1[0]))
+        print(f"[per-instance] instance {k} done", file=sys.stderr, flush=True)
     return {"instances": n, "batched_ms": t_batched * 1e3, "per_instance_ms": t_single * 1e3,
             "speedup": t_single / t_batched, "max_abs_dE_Eh": dE,
             "scf_iterations_batched": [int(v) for v in itb], "scf_iterations_single": its}
@@ -214,15 +220,17 @@ def main():
         F = eng.forces()
         return E, it, st, F
 
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
         step()
+        print(f"[bench] warm-up step {k} done", file=sys.stderr, flush=True)
     eng.reset_stats()
     eng.set_profiling(True)
     iters = 0
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         E, it, st, F = step()
         iters += int(np.sum(it))
+        print(f"[bench] timed step {k} done", file=sys.stderr, flush=True)
     t1 = time.perf_counter()
     eng.set_profiling(False)
     st_json = eng.stats()

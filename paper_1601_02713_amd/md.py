@@ -65,7 +65,7 @@ class RingPolymer:
 
 def run(engine: beadscf.Engine, poly: RingPolymer, n_steps: int, dt_fs: float, guess: str = "previous",
         train_from: int = 1, train_steps: int = 5, predict_from: int = 3, opts=None,
-        geometries=None, basis=None):
+        geometries=None, basis=None, log=None):
     """Propagate n_steps; returns the per-step records and the geometries.
 
     guess: "core" (every step from the core Hamiltonian), "previous" (the
@@ -108,6 +108,8 @@ def run(engine: beadscf.Engine, poly: RingPolymer, n_steps: int, dt_fs: float, g
             rec.train_loss = engine.guess_train(train_steps)
             rec.train_ms = (time.perf_counter() - t3) * 1e3
         records.append(rec)
+        if log is not None:
+            log(rec)
         if geometries is not None:
             continue
         # velocity Verlet: finish the previous step's kick with the new
