@@ -196,7 +196,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "layout is a design note, not part of this build", file=sys.stderr)
+              "layout is a design note and is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -3,8 +3,8 @@
 The network kernels (MFMA GEMMs, loss gradient, ReLU masks, bias sums, Adam)
 against the NumPy FP64 oracle of oracle/mlp.py on the same FP32-rounded
 parameters and rows; then the in-run use on a ring-polymer trajectory: the
-converged energies are those of the previous-step guess (the converged SCF is
-the judge) while the learned guess needs fewer SCF iterations, and sabotaged
+converged energies are those of the previous-step guess (the converged SCF
+decides) while the learned guess needs fewer SCF iterations, and sabotaged
 weights are caught by the fallback.
 """
 
