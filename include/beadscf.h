@@ -114,7 +114,11 @@ bscf_status bscf_load_basis(bscf_ctx* ctx, const char* basis_json);
  * charges Z_concat (concatenated over instances) and total charges charge[i]
  * (may be NULL for neutral).  Allocates all per-instance device storage.
  * BSCF_E_UNSUPPORTED for an element missing from the basis or an odd number
- * of electrons. */
+ * of electrons, BSCF_E_INVALID for an instance without atoms; arguments are
+ * checked before anything changes, so after either the previous instance set
+ * and geometry stay usable.  After a device error (BSCF_E_DEVICE,
+ * BSCF_E_NOMEM) the context holds no instance set until a call succeeds.
+ * A successful call discards the geometry: set it again before computing. */
 bscf_status bscf_set_instances(bscf_ctx* ctx, int n_inst, const int* n_atoms,
                                const int* Z_concat, const int* charge);
 

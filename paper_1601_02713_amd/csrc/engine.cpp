@@ -1664,18 +1664,51 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
   return guard([&] {
     need(c && n_inst > 0 && n_atoms && Z, BSCF_E_INVALID, "bad arguments");
     need(!c->basis.empty(), BSCF_E_INVALID, "load a basis first");
+    // every argument is checked before the context changes, so a rejected
+    // call leaves the previous instance set (and geometry) in place
+    std::vector<int> ne_of(n_inst), nb_of(n_inst);
+    int tot = 0;
+    for (int i = 0; i < n_inst; ++i) {
+      need(n_atoms[i] > 0, BSCF_E_INVALID, "instance without atoms");
+      int ne = -(charge ? charge[i] : 0), nb = 0;
+      for (int a = 0; a < n_atoms[i]; ++a) {
+        const int z = Z[tot + a];
+        auto it = c->basis.find(z);
+        need(it != c->basis.end(), BSCF_E_UNSUPPORTED,
+             "element Z=" + std::to_string(z) + " not in basis");
+        ne += z;
+        for (auto& s : it->second) nb += ncart(s.l);
+      }
+      need(ne > 0 && ne % 2 == 0, BSCF_E_UNSUPPORTED,
+           "instance " + std::to_string(i) + ": closed-shell RHF needs an even electron count");
+      need(ne / 2 <= nb, BSCF_E_UNSUPPORTED, "more occupied orbitals than basis functions");
+      ne_of[i] = ne;
+      nb_of[i] = nb;
+      tot += n_atoms[i];
+    }
     HIPCHK(hipSetDevice(c->device));
     join_work(c);
     HIPCHK(hipStreamSynchronize(c->stream));
     c->drop_graphs();   // they hold addresses of buffers about to be resized
+    // a device failure below leaves no instance set rather than host tables
+    // that no longer match the device buffers
+    struct Undo {
+      bscf_ctx* c;
+      bool done = false;
+      ~Undo() {
+        if (!done) {
+          c->ninst = 0;
+          c->have_geom = c->have_scf = c->have_C = false;
+        }
+      }
+    } undo{c};
+    c->have_geom = c->have_scf = c->have_C = false;
     c->ninst = n_inst;
     c->natoms.assign(n_atoms, n_atoms + n_inst);
     c->atom_off.assign(n_inst, 0);
-    int tot = 0;
-    for (int i = 0; i < n_inst; ++i) {
-      need(n_atoms[i] > 0, BSCF_E_INVALID, "instance without atoms");
-      c->atom_off[i] = tot;
-      tot += n_atoms[i];
+    for (int i = 0, off = 0; i < n_inst; ++i) {
+      c->atom_off[i] = off;
+      off += n_atoms[i];
     }
     c->total_atoms = tot;
     c->Zs.assign(Z, Z + tot);
@@ -1688,20 +1721,9 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->max_n = 0;
     c->max_atoms = 0;
     for (int i = 0; i < n_inst; ++i) {
-      int ne = -c->charge[i], nb = 0;
-      for (int a = 0; a < n_atoms[i]; ++a) {
-        const int z = c->Zs[c->atom_off[i] + a];
-        auto it = c->basis.find(z);
-        need(it != c->basis.end(), BSCF_E_UNSUPPORTED,
-             "element Z=" + std::to_string(z) + " not in basis");
-        ne += z;
-        for (auto& s : it->second) nb += ncart(s.l);
-      }
-      need(ne > 0 && ne % 2 == 0, BSCF_E_UNSUPPORTED,
-           "instance " + std::to_string(i) + ": closed-shell RHF needs an even electron count");
-      need(ne / 2 <= nb, BSCF_E_UNSUPPORTED, "more occupied orbitals than basis functions");
+      const int nb = nb_of[i];
       c->nbf[i] = nb;
-      c->nocc[i] = ne / 2;
+      c->nocc[i] = ne_of[i] / 2;
       c->moff[i] = c->mtot;
       c->mtot += (long long)nb * nb;
       c->max_n = std::max(c->max_n, nb);
@@ -1789,6 +1811,7 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->fock_tuned[0] = c->fock_tuned[1] = c->grad_tuned = false;
     c->guess.reset_batch(c->ninst);
     sync(c);
+    undo.done = true;
   });
 }
 
@@ -1796,12 +1819,13 @@ bscf_status bscf_set_geometries(bscf_ctx* c, const double* xyz) {
   return guard([&] {
     need(c && xyz, BSCF_E_INVALID, "NULL argument");
     need(c->ninst > 0, BSCF_E_INVALID, "set instances first");
+    // checked first: a rejected geometry leaves the current one in place
+    for (int k = 0; k < 3 * c->total_atoms; ++k)
+      need(std::isfinite(xyz[k]), BSCF_E_INVALID, "non-finite coordinate");
     HIPCHK(hipSetDevice(c->device));
     join_work(c);
     c->work_tau = c->host_tau = -1.0;
     const double t0 = now_ms();
-    for (int k = 0; k < 3 * c->total_atoms; ++k)
-      need(std::isfinite(xyz[k]), BSCF_E_INVALID, "non-finite coordinate");
     c->xyz.assign(xyz, xyz + 3 * c->total_atoms);
     for (Shell& s : c->shells) {
       s.x = xyz[3 * s.atom];
