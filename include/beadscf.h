@@ -130,7 +130,10 @@ bscf_status bscf_set_geometries(bscf_ctx* ctx, const double* xyz_bohr_concat);
 /* One Fock build at given densities: P (all instances concatenated, each
  * n_i x n_i) -> F = H + J - K/2 and E[i] = Tr[P(H+F)]/2 + E_nuc.  With
  * device_ptrs, P and F are device pointers and E may be NULL.  schwarz_tol as
- * in the options (<= 0: no screening); precision a bscf_precision. */
+ * in the options (<= 0: no screening); precision a bscf_precision.  The
+ * given densities replace the SCF's: bscf_forces then answers BSCF_E_STATE
+ * until the next bscf_run_scf (the same holds for bscf_build_jk and
+ * bscf_set_density). */
 bscf_status bscf_build_fock(bscf_ctx* ctx, const double* P, double* F, double* E,
                             double schwarz_tol, int precision, int device_ptrs);
 
@@ -147,7 +150,8 @@ bscf_status bscf_run_scf(bscf_ctx* ctx, const bscf_scf_opts* opts, double* E, in
 
 /* Forces F = -dE/dR [sum n_atoms][3] (Eh/bohr, host) at the densities of the
  * last bscf_run_scf (Pople et al. 1979 gradient with W = P F P / 2).
- * BSCF_E_STATE if no SCF has run at the current geometry. */
+ * BSCF_E_STATE if no SCF has run at the current geometry or its densities
+ * were replaced since. */
 bscf_status bscf_forces(bscf_ctx* ctx, double* F);
 
 /* Density of instance `inst` after the last SCF (n_i x n_i), host or device. */

@@ -1905,6 +1905,7 @@ bscf_status bscf_build_jk(bscf_ctx* c, const double* P, double* J, double* K, do
     require_geom(c);
     HIPCHK(hipSetDevice(c->device));
     const auto kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    c->have_scf = false;   // the SCF density is replaced: forces need a new SCF
     HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double), kind, c->stream));
     fock_build(c, tau, precision, false);
     // symmetrised J, K
@@ -1928,6 +1929,7 @@ bscf_status bscf_build_fock(bscf_ctx* c, const double* P, double* F, double* E, 
     require_geom(c);
     HIPCHK(hipSetDevice(c->device));
     const auto kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    c->have_scf = false;   // the SCF density is replaced: forces need a new SCF
     HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double), kind, c->stream));
     fock_build(c, tau, precision, false);
     const auto back = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -1941,6 +1943,7 @@ bscf_status bscf_set_density(bscf_ctx* c, const double* P, int device_ptrs) {
   return guard([&] {
     need(c && P, BSCF_E_INVALID, "NULL argument");
     need(c->ninst > 0, BSCF_E_INVALID, "set instances first");
+    c->have_scf = false;   // the SCF density is replaced: forces need a new SCF
     HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double),
                           device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
     sync(c);

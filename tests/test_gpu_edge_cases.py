@@ -108,6 +108,14 @@ def test_rejected_calls_leave_the_context_usable(eng, beadscf, b631gs):
     E1, _, st = eng.run_scf(e_tol=1e-11, comm_tol=1e-9)
     assert st[0] == 0 and abs(E1[0] - E0[0]) < 1e-10
 
+    # a Fock build at a caller's density replaces the SCF's: no forces until
+    # the next SCF, which gives them back
+    P = eng.density(0)
+    eng.build_fock([0.5 * P])
+    rejected(-4, eng.forces)
+    eng.run_scf(e_tol=1e-11, comm_tol=1e-9)
+    assert np.abs(eng.forces()[0] - F0).max() < 1e-9
+
     # a new instance set discards the geometry and the converged state
     eng.set_instances([np.array([8, 1, 1])])
     rejected(-4, eng.forces)
