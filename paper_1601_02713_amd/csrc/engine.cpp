@@ -2050,6 +2050,7 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     need(o.density == BSCF_DENSITY_SP2 || o.density == BSCF_DENSITY_EIG, BSCF_E_INVALID,
          "density must be BSCF_DENSITY_SP2 or BSCF_DENSITY_EIG");
     c->split_tol = o.fp32_split_tol;
+    c->have_scf = false;   // set again once every instance has its density
     const double t0 = now_ms();
     const hipStream_t st = c->stream;
     const int ni = c->ninst;
