@@ -154,7 +154,9 @@ bscf_status bscf_run_scf(bscf_ctx* ctx, const bscf_scf_opts* opts, double* E, in
  * were replaced since. */
 bscf_status bscf_forces(bscf_ctx* ctx, double* F);
 
-/* Density of instance `inst` after the last SCF (n_i x n_i), host or device. */
+/* Density of instance `inst` after the last SCF (n_i x n_i), host or device;
+ * the last density given to the batch (bscf_set_density, a Fock build) if
+ * that came later, and zero before the first of these. */
 bscf_status bscf_get_density(bscf_ctx* ctx, int inst, double* P, int device_ptr);
 /* Set the density of every instance (concatenated), used by BSCF_GUESS_USER. */
 bscf_status bscf_set_density(bscf_ctx* ctx, const double* P, int device_ptrs);

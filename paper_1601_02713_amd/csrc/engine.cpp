@@ -1781,6 +1781,9 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
                               &c->Pnew, &c->W, &c->tmp1, &c->tmp2, &c->err, &c->Fbar, &c->C,
                               &c->Cacc, &c->eig, &c->eigE, &c->Pprev, &c->dP})
       m->resize(mt);
+    // a new batch has zero density until an SCF, a Fock build or
+    // bscf_set_density gives it one (a user guess never starts from garbage)
+    launch_fill(c->P.p, (long long)mt, 0.0, s);
     c->d_dpmax.resize((size_t)n_inst * (1 + (size_t)((c->max_n + 31) / 32) * ((c->max_n + 31) / 32)));
     c->d_kept.resize((size_t)3 * kNumQuartetClasses * n_inst);
     launch_fill(c->d_kept.p, (long long)c->d_kept.n, 0.0, s);

@@ -116,8 +116,10 @@ def test_rejected_calls_leave_the_context_usable(eng, beadscf, b631gs):
     eng.run_scf(e_tol=1e-11, comm_tol=1e-9)
     assert np.abs(eng.forces()[0] - F0).max() < 1e-9
 
-    # a new instance set discards the geometry and the converged state
+    # a new instance set discards the geometry and the converged state, and
+    # its density is zero until one is computed or given
     eng.set_instances([np.array([8, 1, 1])])
+    assert not eng.density(0).any()
     rejected(-4, eng.forces)
     rejected(-1, eng.run_scf)
     eng.set_geometries([np.asarray(inst[0][1], float)])
