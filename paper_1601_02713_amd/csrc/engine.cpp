@@ -402,6 +402,7 @@ struct bscf_ctx {
   DevBuf<int> d_nocc, d_nbf, d_natoms, d_atom_off, d_active, d_all_active, d_conv_iter, d_status;
   DevBuf<long long> d_moff;
   DevBuf<double> d_xyz, d_Zd, d_Enuc, d_E, d_Eprev, d_emax, d_grad;
+  DevBuf<double> d_grad_tune;   // [3 total_atoms]: the gradient kernels' timing pass writes here
   DevBuf<int> d_task_a, d_task_b;  // 1e tasks: pair shells
   std::vector<int> task_first, task_count;  // per pair class ranges into task arrays
   // matrices
@@ -1806,6 +1807,7 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->d_Eprev.resize(n_inst);
     c->d_emax.resize((size_t)n_inst * (1 + (size_t)((c->max_n + 31) / 32) * ((c->max_n + 31) / 32)));
     c->d_grad.resize((size_t)tot * 3);
+    c->d_grad_tune.resize((size_t)tot * 3);
     c->d_xyz.resize((size_t)tot * 3);
     c->have_geom = false;
     c->have_scf = false;
@@ -1825,6 +1827,10 @@ bscf_status bscf_set_geometries(bscf_ctx* c, const double* xyz) {
     // checked first: a rejected geometry leaves the current one in place
     for (int k = 0; k < 3 * c->total_atoms; ++k)
       need(std::isfinite(xyz[k]), BSCF_E_INVALID, "non-finite coordinate");
+    // from here on the context holds neither a geometry nor an SCF until the
+    // call has finished: a device error part-way through cannot leave the
+    // previous densities paired with the new coordinates
+    c->have_geom = c->have_scf = false;
     HIPCHK(hipSetDevice(c->device));
     join_work(c);
     c->work_tau = c->host_tau = -1.0;
@@ -2257,8 +2263,11 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
       // the gradient launches alone (into a throwaway buffer): the choice
       // of variant and the stream schedule below use these times
       const char* env = getenv("BSCF_VARIANT");
+      // the kernels add into grad[3 * atom + d] of every atom of the batch
+      need(c->d_grad_tune.n >= (size_t)3 * c->total_atoms, BSCF_E_STATE,
+           "gradient timing buffer smaller than the batch");
       GradArgs gt = ga;
-      gt.grad = c->tmp1.p;
+      gt.grad = c->d_grad_tune.p;
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
@@ -2293,7 +2302,7 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
         c->tune_grad1e_ms[pc] = 0.0f;
         if (g1[pc].ntasks == 0) continue;
         Grad1EArgs g = g1[pc];
-        g.grad = c->tmp1.p;
+        g.grad = c->d_grad_tune.p;
         int la, lb;
         pc_l(pc, la, lb);
         c->tune_grad1e_ms[pc] = time_alone([&] { launch_grad1e(la, lb, g, st); });

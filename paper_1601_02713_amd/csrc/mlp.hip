@@ -728,11 +728,22 @@ void Guess::save(const std::string& path) {
 }
 
 void Guess::load(const std::string& path) {
+  // the whole file is read and checked into host vectors before the model
+  // changes, so a bad or truncated file leaves the current model in place
   std::ifstream f(path, std::ios::binary);
   if (!f) throw std::runtime_error("learned guess: cannot read " + path);
   int head[5];
   f.read(reinterpret_cast<char*>(head), sizeof(head));
-  if (!f || head[0] != 0x42534347 || head[1] <= 0 || head[2] <= 0 || head[4] < 0 || head[4] > 128)
+  // widths as ensure_model makes them (dout = bmax^2, din = element pairs +
+  // geometric features + two blocks), or those of a network fixed by
+  // configure() alone (no element types, bmax 0, 0 < dout <= din)
+  const int nt = head[4];
+  const bool sized = nt > 0 && nt <= 128 && head[3] > 0 && head[3] <= 64 &&
+                     head[2] == head[3] * head[3] &&
+                     head[1] == nt * (nt + 1) / 2 + kGeoFeatures + 2 * head[3] * head[3];
+  const bool bare = nt == 0 && head[3] == 0 && head[2] > 0 && head[2] <= head[1] &&
+                    head[1] <= (1 << 20);
+  if (!f || head[0] != 0x42534347 || !(sized || bare))
     throw std::runtime_error("learned guess: not a model file");
   std::vector<int> types(head[4]);
   f.read(reinterpret_cast<char*>(types.data()), types.size() * sizeof(int));
@@ -740,13 +751,15 @@ void Guess::load(const std::string& path) {
   long steps;
   f.read(reinterpret_cast<char*>(&scale), sizeof(float));
   f.read(reinterpret_cast<char*>(&steps), sizeof(long));
-  configure(head[1], head[2], 2000u);
-  const long n = nparams();
+  const long n = (long)head[1] * kHidden + kHidden + (long)kHidden * kHidden + kHidden +
+                 (long)kHidden * head[2] + head[2];
   std::vector<float> th(n), m(n), v(n);
   f.read(reinterpret_cast<char*>(th.data()), n * sizeof(float));
   f.read(reinterpret_cast<char*>(m.data()), n * sizeof(float));
   f.read(reinterpret_cast<char*>(v.data()), n * sizeof(float));
   if (!f) throw std::runtime_error("learned guess: truncated model file");
+  if (!std::isfinite(scale) || steps < 0) throw std::runtime_error("learned guess: not a model file");
+  configure(head[1], head[2], 2000u);
   chk(hipMemcpy(theta_.p, th.data(), n * sizeof(float), hipMemcpyHostToDevice), "load");
   chk(hipMemcpy(m_.p, m.data(), n * sizeof(float), hipMemcpyHostToDevice), "load");
   chk(hipMemcpy(v_.p, v.data(), n * sizeof(float), hipMemcpyHostToDevice), "load");

@@ -125,3 +125,23 @@ def test_rejected_calls_leave_the_context_usable(eng, beadscf, b631gs):
     eng.set_geometries([np.asarray(inst[0][1], float)])
     E2, _, st = eng.run_scf(e_tol=1e-11, comm_tol=1e-9)
     assert st[0] == 0 and abs(E2[0] - E0[0]) < 1e-10
+
+
+@pytest.mark.parametrize("z,x,q", [
+    ([1, 1], [[0.0, 0.0, 0.0], [0.1, -0.05, 1.4]], 0),    # H2: 4 matrix elements, 6 force components
+    ([1], [[0.3, -0.2, 0.1]], -1),                         # H-: 1 matrix element, 3 force components
+])
+def test_batches_with_fewer_matrix_elements_than_force_components(eng, sto3g, z, x, q):
+    # In STO-3G these batches hold fewer density-matrix elements than force
+    # components; the first forces call of a batch also times every gradient
+    # kernel alone, into a buffer of the batch's force components.
+    _setup(eng, sto3g, [(z, x)], [q])
+    E, _, st = eng.run_scf(e_tol=1e-11, comm_tol=1e-9)
+    assert st[0] == 0
+    F = eng.forces()[0]
+    b = oracle.build_basis(sto3g, np.asarray(z), np.asarray(x, float))
+    r = oracle.scf(b, 1e-11, 1e-9, charge=q)
+    g = oracle.gradient(b, r["P"], r["F"])
+    assert abs(E[0] - r["E"]) < 1e-9
+    assert np.abs(F + g).max() < 1e-8, (F, -g)
+    assert np.abs(F.sum(axis=0)).max() < 1e-10

@@ -162,3 +162,36 @@ def test_sabotaged_network_falls_back(beadscf, eng):
         e2.close()
     assert (st & beadscf.STATUS_FALLBACK).all()
     assert np.abs(E - ref[3].energies).max() < 1e-8
+
+
+def test_model_file_round_trip_and_refusals(beadscf, eng, tmp_path):
+    """A saved network loads into another context with the same parameters
+    and outputs; a truncated or foreign file is refused and leaves the loaded
+    network as it was."""
+    rng = np.random.default_rng([2000, 11])
+    din, dout = 33, 7
+    eng.guess_configure(din, dout)
+    th = _theta(rng, din, dout)
+    eng.guess_set_params(th)
+    X, T, M = _rows(rng, 20, din, dout)
+    Y0, _, _ = eng.guess_eval(X, T, M)
+    path = str(tmp_path / "model.bin")
+    eng.guess_save(path)
+    e2 = beadscf.Engine(0)
+    try:
+        e2.guess_load(path)
+        assert e2.guess_dims()[:2] == (din, dout)
+        assert np.array_equal(e2.guess_params(), th)
+        Y1, _, _ = e2.guess_eval(X, T, M)
+        assert np.array_equal(Y0, Y1)
+        raw = open(path, "rb").read()
+        cut = str(tmp_path / "cut.bin")
+        open(cut, "wb").write(raw[:len(raw) // 2])
+        junk = str(tmp_path / "junk.bin")
+        open(junk, "wb").write(b"\0" * 64)
+        for bad in (cut, junk, str(tmp_path / "missing.bin")):
+            with pytest.raises(beadscf.BscfError):
+                e2.guess_load(bad)
+            assert np.array_equal(e2.guess_params(), th)
+    finally:
+        e2.close()
