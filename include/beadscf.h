@@ -154,6 +154,18 @@ bscf_status bscf_run_scf(bscf_ctx* ctx, const bscf_scf_opts* opts, double* E, in
  * were replaced since. */
 bscf_status bscf_forces(bscf_ctx* ctx, double* F);
 
+/* Forces F = -dE/dR [sum n_atoms][3] (Eh/bohr, host) of the same gradient
+ * expression as bscf_forces (Pople et al. 1979; the analytic BO force of each
+ * replica, Section 2), evaluated at caller densities P and Fock matrices F
+ * (all instances concatenated, each n_i x n_i, symmetric; W = P F P / 2)
+ * instead of those of an SCF.  Two-electron terms use the screened work lists
+ * of the current geometry at Schwarz cutoff schwarz_tol (<= 0: no screening).
+ * With device_ptrs, P and F are device pointers; Fout is host memory.  The
+ * given densities replace the SCF's, as with bscf_build_fock.  For checking
+ * the gradient kernels at densities that do not come from this library. */
+bscf_status bscf_forces_at(bscf_ctx* ctx, const double* P, const double* F, double* Fout,
+                           double schwarz_tol, int device_ptrs);
+
 /* Density of instance `inst` after the last SCF (n_i x n_i), host or device;
  * the last density given to the batch (bscf_set_density, a Fock build) if
  * that came later, and zero before the first of these. */

@@ -25,6 +25,7 @@ from .rhf import (  # noqa: F401
     eri_quartet,
     schwarz,
     jk,
+    jk_pairs,
     nuclear_repulsion,
     scf,
     gradient,

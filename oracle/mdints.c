@@ -486,14 +486,28 @@ long or_jk(int nsh, int nbf, const int *l, const int *atom, const int *nprim, co
 }
 
 /* Two-electron gradient: g[atom][3] += 1/2 sum (mn|ls)^x [P_mn P_ls - 1/2 P_ml P_ns]
- * over all ordered index quartets, with the same Schwarz rule as or_jk. */
-long or_grad_2e(int nsh, int nbf, const int *l, const int *atom, const int *nprim,
-                const int *pofs, const int *bf, const double *exps, const double *coefs,
-                const double *xyz, int natom, const double *Q, double tau, const double *P,
-                double *g) {
+ * over all ordered index quartets, with the same Schwarz rule as or_jk.
+ * With amask != NULL only the atoms with amask[atom] != 0 are accumulated
+ * (the others stay 0), and quartets with no shell on such an atom are skipped. */
+static long grad_2e(int nsh, int nbf, const int *l, const int *atom, const int *nprim,
+                    const int *pofs, const int *bf, const double *exps, const double *coefs,
+                    const double *xyz, int natom, const double *Q, double tau, const double *P,
+                    const int *amask, double *g) {
   basis_t bs = {nsh, nbf, l, atom, nprim, pofs, bf, exps, coefs, xyz};
   int *lst;
   int nq = canonical_list(nsh, Q, tau, &lst);
+  if (amask) { /* keep the quartets that touch a selected atom */
+    int m = 0;
+    for (int q = 0; q < nq; ++q) {
+      int hit = 0;
+      for (int k = 0; k < 4; ++k) hit |= amask[atom[lst[4 * q + k]]] != 0;
+      if (hit) {
+        for (int k = 0; k < 4; ++k) lst[4 * m + k] = lst[4 * q + k];
+        ++m;
+      }
+    }
+    nq = m;
+  }
   size_t n = nbf;
   memset(g, 0, sizeof(double) * 3 * natom);
 #pragma omp parallel
@@ -523,9 +537,11 @@ long or_grad_2e(int nsh, int nbf, const int *l, const int *atom, const int *npri
                 gam += 0.5 * (P[mu * n + nu] * P[la * n + si] - 0.5 * P[mu * n + la] * P[nu * n + si]);
               }
               /* every permutation has the same centre derivatives (same centres) */
-              for (int cen = 0; cen < 4; ++cen)
+              for (int cen = 0; cen < 4; ++cen) {
+                if (amask && !amask[at[cen]]) continue;
                 for (int dir = 0; dir < 3; ++dir)
                   gt[3 * at[cen] + dir] += gam * der[(cen * 3 + dir) * nblk + e];
+              }
             }
     }
 #pragma omp critical
@@ -536,16 +552,37 @@ long or_grad_2e(int nsh, int nbf, const int *l, const int *atom, const int *npri
   return nq;
 }
 
-/* One-electron gradient: g[atom][3] = sum P_mn dH_mn/dX - sum W_mn dS_mn/dX,
- * with the Hellmann-Feynman operator term of every nucleus. */
-void or_grad_1e(int nsh, int nbf, const int *l, const int *atom, const int *nprim,
+long or_grad_2e(int nsh, int nbf, const int *l, const int *atom, const int *nprim,
                 const int *pofs, const int *bf, const double *exps, const double *coefs,
-                int natom, const double *xyz, const int *Z, const double *P, const double *W,
+                const double *xyz, int natom, const double *Q, double tau, const double *P,
                 double *g) {
+  return grad_2e(nsh, nbf, l, atom, nprim, pofs, bf, exps, coefs, xyz, natom, Q, tau, P, NULL, g);
+}
+
+long or_grad_2e_atoms(int nsh, int nbf, const int *l, const int *atom, const int *nprim,
+                      const int *pofs, const int *bf, const double *exps, const double *coefs,
+                      const double *xyz, int natom, const double *Q, double tau, const double *P,
+                      const int *amask, double *g) {
+  return grad_2e(nsh, nbf, l, atom, nprim, pofs, bf, exps, coefs, xyz, natom, Q, tau, P, amask, g);
+}
+
+/* One-electron gradient: g[atom][3] = sum P_mn dH_mn/dX - sum W_mn dS_mn/dX,
+ * with the Hellmann-Feynman operator term of every nucleus.  With amask !=
+ * NULL only the atoms with amask[atom] != 0 are accumulated (the others stay
+ * 0): the bra and ket terms of the shells on them and their operator terms. */
+static void grad_1e(int nsh, int nbf, const int *l, const int *atom, const int *nprim,
+                    const int *pofs, const int *bf, const double *exps, const double *coefs,
+                    int natom, const double *xyz, const int *Z, const double *P, const double *W,
+                    const int *amask, double *g) {
   size_t n = nbf;
   memset(g, 0, sizeof(double) * 3 * natom);
+#pragma omp parallel
+  {
+  double *gt = calloc(3 * natom, sizeof(double));
+#pragma omp for schedule(dynamic)
   for (int a = 0; a < nsh; ++a)
     for (int b = 0; b < nsh; ++b) {
+      const int bra_on = !amask || amask[atom[a]], ket_on = !amask || amask[atom[b]];
       const double *A = xyz + 3 * atom[a], *B = xyz + 3 * atom[b];
       for (int ka = 0; ka < nprim[a]; ++ka)
         for (int kb = 0; kb < nprim[b]; ++kb) {
@@ -563,6 +600,7 @@ void or_grad_1e(int nsh, int nbf, const int *l, const int *atom, const int *npri
               double pmn = P[mu * n + nu], wmn = W[mu * n + nu];
               for (int dir = 0; dir < 3; ++dir) {
                 /* derivative with respect to the bra centre (atom of shell a) */
+                if (bra_on) {
                 int up[3] = {ia[0], ia[1], ia[2]}, dn[3] = {ia[0], ia[1], ia[2]};
                 up[dir] += 1; dn[dir] -= 1;
                 double dS = 2 * al * prim_S(&pe, up, ib) - ia[dir] * prim_S(&pe, dn, ib);
@@ -573,24 +611,102 @@ void or_grad_1e(int nsh, int nbf, const int *l, const int *atom, const int *npri
                   if (ia[dir] > 0) v -= ia[dir] * prim_V(&pe, dn, ib, xyz + 3 * c, -1);
                   dV -= Z[c] * v;
                 }
-                g[3 * atom[a] + dir] += f * (pmn * (dT + dV) - wmn * dS);
+                gt[3 * atom[a] + dir] += f * (pmn * (dT + dV) - wmn * dS);
+                }
                 /* derivative with respect to the ket centre (atom of shell b) */
+                if (ket_on) {
                 int up2[3] = {ib[0], ib[1], ib[2]}, dn2[3] = {ib[0], ib[1], ib[2]};
                 up2[dir] += 1; dn2[dir] -= 1;
-                dS = 2 * be * prim_S(&pe, ia, up2) - ib[dir] * prim_S(&pe, ia, dn2);
-                dT = 2 * be * prim_T(&pe, ia, up2, be) - ib[dir] * prim_T(&pe, ia, dn2, be);
-                dV = 0.0;
+                double dS = 2 * be * prim_S(&pe, ia, up2) - ib[dir] * prim_S(&pe, ia, dn2);
+                double dT = 2 * be * prim_T(&pe, ia, up2, be) - ib[dir] * prim_T(&pe, ia, dn2, be);
+                double dV = 0.0;
                 for (int c = 0; c < natom; ++c) {
                   double v = 2 * be * prim_V(&pe, ia, up2, xyz + 3 * c, -1);
                   if (ib[dir] > 0) v -= ib[dir] * prim_V(&pe, ia, dn2, xyz + 3 * c, -1);
                   dV -= Z[c] * v;
                 }
-                g[3 * atom[b] + dir] += f * (pmn * (dT + dV) - wmn * dS);
+                gt[3 * atom[b] + dir] += f * (pmn * (dT + dV) - wmn * dS);
+                }
                 /* operator centre of every nucleus c */
                 for (int c = 0; c < natom; ++c)
-                  g[3 * c + dir] += f * pmn * (-Z[c]) * prim_V(&pe, ia, ib, xyz + 3 * c, dir);
+                  if (!amask || amask[c])
+                    gt[3 * c + dir] += f * pmn * (-Z[c]) * prim_V(&pe, ia, ib, xyz + 3 * c, dir);
               }
             }
         }
     }
+#pragma omp critical
+  for (int i = 0; i < 3 * natom; ++i) g[i] += gt[i];
+  free(gt);
+  }
+}
+
+void or_grad_1e(int nsh, int nbf, const int *l, const int *atom, const int *nprim,
+                const int *pofs, const int *bf, const double *exps, const double *coefs,
+                int natom, const double *xyz, const int *Z, const double *P, const double *W,
+                double *g) {
+  grad_1e(nsh, nbf, l, atom, nprim, pofs, bf, exps, coefs, natom, xyz, Z, P, W, NULL, g);
+}
+
+void or_grad_1e_atoms(int nsh, int nbf, const int *l, const int *atom, const int *nprim,
+                      const int *pofs, const int *bf, const double *exps, const double *coefs,
+                      int natom, const double *xyz, const int *Z, const double *P,
+                      const double *W, const int *amask, double *g) {
+  grad_1e(nsh, nbf, l, atom, nprim, pofs, bf, exps, coefs, natom, xyz, Z, P, W, amask, g);
+}
+
+/* J and K blocks of selected shell pairs, by direct summation over every
+ * ordered ket shell pair (no permutational symmetry):
+ *   J_mn = sum_{c,d} sum_{l in c, s in d} (mn|ls) P_ls,  included when
+ *          Q_ab Q_cd >= tau,
+ *   K_mn = sum_{c,d} sum_{l in c, s in d} (ml|ns) P_ls,  included when
+ *          Q_ac Q_bd >= tau,
+ * for m in shell pa[i], n in shell pb[i]; the same Schwarz rule as or_jk
+ * (the rule of the canonical quartet each term belongs to).  Only the
+ * elements of the selected blocks of J and K (n x n) are written. */
+void or_jk_pairs(int nsh, int nbf, const int *l, const int *atom, const int *nprim,
+                 const int *pofs, const int *bf, const double *exps, const double *coefs,
+                 const double *xyz, const double *Q, double tau, const double *P, int npairs,
+                 const int *pa, const int *pb, double *J, double *K) {
+  basis_t bs = {nsh, nbf, l, atom, nprim, pofs, bf, exps, coefs, xyz};
+  size_t n = nbf;
+  for (int i = 0; i < npairs; ++i) {
+    const int a = pa[i], b = pb[i], na = ncart(l[a]), nb = ncart(l[b]);
+    double Jb[36] = {0}, Kb[36] = {0};
+#pragma omp parallel
+    {
+      double Jt[36] = {0}, Kt[36] = {0};
+      double blk[6 * 6 * 6 * 6];
+#pragma omp for schedule(dynamic)
+      for (int c = 0; c < nsh; ++c)
+        for (int d = 0; d < nsh; ++d) {
+          const int nc = ncart(l[c]), nd = ncart(l[d]);
+          if (tau <= 0.0 || Q[a * nsh + b] * Q[c * nsh + d] >= tau) {
+            shell_quartet(&bs, a, b, c, d, blk, NULL);
+            for (int u = 0; u < na; ++u)
+              for (int v = 0; v < nb; ++v)
+                for (int x = 0; x < nc; ++x)
+                  for (int y = 0; y < nd; ++y)
+                    Jt[u * nb + v] += blk[((u * nb + v) * nc + x) * nd + y] *
+                                      P[(bf[c] + x) * n + bf[d] + y];
+          }
+          if (tau <= 0.0 || Q[a * nsh + c] * Q[b * nsh + d] >= tau) {
+            shell_quartet(&bs, a, c, b, d, blk, NULL);
+            for (int u = 0; u < na; ++u)
+              for (int x = 0; x < nc; ++x)
+                for (int v = 0; v < nb; ++v)
+                  for (int y = 0; y < nd; ++y)
+                    Kt[u * nb + v] += blk[((u * nc + x) * nb + v) * nd + y] *
+                                      P[(bf[c] + x) * n + bf[d] + y];
+          }
+        }
+#pragma omp critical
+      for (int k = 0; k < na * nb; ++k) { Jb[k] += Jt[k]; Kb[k] += Kt[k]; }
+    }
+    for (int u = 0; u < na; ++u)
+      for (int v = 0; v < nb; ++v) {
+        J[(bf[a] + u) * n + bf[b] + v] = Jb[u * nb + v];
+        K[(bf[a] + u) * n + bf[b] + v] = Kb[u * nb + v];
+      }
+  }
 }

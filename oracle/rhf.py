@@ -50,6 +50,7 @@ def _c():
         _lib = ctypes.CDLL(_LIB)
         _lib.or_jk.restype = ctypes.c_long
         _lib.or_grad_2e.restype = ctypes.c_long
+        _lib.or_grad_2e_atoms.restype = ctypes.c_long
     return _lib
 
 
@@ -113,6 +114,23 @@ def jk(b, P, tau: float = 1e-12, Q=None):
     nq = _c().or_jk(*_bargs(b), _p(b["xyz"]), _p(np.ascontiguousarray(Q)),
                     ctypes.c_double(tau), _p(P), _p(J), _p(K))
     return J, K, int(nq)
+
+
+def jk_pairs(b, P, pairs, tau: float = 1e-12, Q=None):
+    """J and K blocks of the shell pairs (a, b) in ``pairs`` by direct
+    summation over every ket shell pair, each term screened by the Schwarz
+    rule of its canonical quartet (as in ``jk``).  Returns n x n arrays J, K
+    holding those blocks, NaN elsewhere."""
+    n = b["nbf"]
+    if Q is None:
+        Q = schwarz(b)
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    pa = np.ascontiguousarray([int(a) for a, _ in pairs], dtype=np.int32)
+    pb = np.ascontiguousarray([int(c) for _, c in pairs], dtype=np.int32)
+    J, K = np.full((n, n), np.nan), np.full((n, n), np.nan)
+    _c().or_jk_pairs(*_bargs(b), _p(b["xyz"]), _p(np.ascontiguousarray(Q)), ctypes.c_double(tau),
+                     _p(P), ctypes.c_int(len(pa)), _p(pa), _p(pb), _p(J), _p(K))
+    return J, K
 
 
 def nuclear_repulsion(Z, xyz) -> float:
@@ -223,17 +241,28 @@ def scf(b, e_tol=1e-8, comm_tol=1e-6, max_iter=100, guess=None, tau=1e-12, diis_
                 Q=Q)
 
 
-def gradient(b, P, F, tau=1e-12, Q=None):
-    """dE/dR [natom,3] at density P with Fock matrix F (W = P F P / 2)."""
+def gradient(b, P, F, tau=1e-12, Q=None, atoms=None):
+    """dE/dR [natom,3] at density P with Fock matrix F (W = P F P / 2).
+    With ``atoms`` (indices) only those rows are computed; the others are NaN."""
     nat = len(b["Z"])
     P = np.ascontiguousarray(P, dtype=np.float64)
     W = np.ascontiguousarray(0.5 * P @ F @ P)
     Zi = np.ascontiguousarray(b["Z"], dtype=np.int32)
-    g1 = np.zeros((nat, 3))
-    _c().or_grad_1e(*_bargs(b), ctypes.c_int(nat), _p(b["xyz"]), _p(Zi), _p(P), _p(W), _p(g1))
     if Q is None:
         Q = schwarz(b)
-    g2 = np.zeros((nat, 3))
-    _c().or_grad_2e(*_bargs(b), _p(b["xyz"]), ctypes.c_int(nat), _p(np.ascontiguousarray(Q)),
-                    ctypes.c_double(tau), _p(P), _p(g2))
-    return g1 + g2 + nuclear_repulsion_gradient(b["Z"], b["xyz"])
+    Q = np.ascontiguousarray(Q)
+    g1, g2 = np.zeros((nat, 3)), np.zeros((nat, 3))
+    if atoms is None:
+        _c().or_grad_1e(*_bargs(b), ctypes.c_int(nat), _p(b["xyz"]), _p(Zi), _p(P), _p(W), _p(g1))
+        _c().or_grad_2e(*_bargs(b), _p(b["xyz"]), ctypes.c_int(nat), _p(Q), ctypes.c_double(tau),
+                        _p(P), _p(g2))
+        return g1 + g2 + nuclear_repulsion_gradient(b["Z"], b["xyz"])
+    mask = np.zeros(nat, np.int32)
+    mask[np.asarray(atoms, int)] = 1
+    _c().or_grad_1e_atoms(*_bargs(b), ctypes.c_int(nat), _p(b["xyz"]), _p(Zi), _p(P), _p(W),
+                          _p(mask), _p(g1))
+    _c().or_grad_2e_atoms(*_bargs(b), _p(b["xyz"]), ctypes.c_int(nat), _p(Q), ctypes.c_double(tau),
+                          _p(P), _p(mask), _p(g2))
+    g = g1 + g2 + nuclear_repulsion_gradient(b["Z"], b["xyz"])
+    g[mask == 0] = np.nan
+    return g

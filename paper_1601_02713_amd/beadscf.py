@@ -50,6 +50,7 @@ _SIGS = {
     "bscf_build_jk": [_vp, _vp, _vp, _vp, _d, _i, _i],
     "bscf_run_scf": [_vp, ctypes.POINTER(ScfOpts), _vp, _vp, _vp],
     "bscf_forces": [_vp, _vp],
+    "bscf_forces_at": [_vp, _vp, _vp, _vp, _d, _i],
     "bscf_get_density": [_vp, _i, _vp, _i],
     "bscf_set_density": [_vp, _vp, _i],
     "bscf_get_one_electron": [_vp, _i, _vp, _vp],
@@ -154,7 +155,10 @@ class Engine:
         _chk(_lib.bscf_set_geometries(self._h, _ptr(x)))
 
     def _cat(self, mats):
-        return np.ascontiguousarray(np.concatenate([np.asarray(m, float).ravel() for m in mats]))
+        mats = [np.asarray(m, float) for m in mats]
+        if [m.shape for m in mats] != [(n, n) for n in self.nbf]:
+            raise ValueError(f"expected matrices of shapes {[(n, n) for n in self.nbf]}")
+        return np.ascontiguousarray(np.concatenate([m.ravel() for m in mats]))
 
     def _split(self, flat):
         out, o = [], 0
@@ -191,6 +195,17 @@ class Engine:
         out, o = [], 0
         for n in self.natoms:
             out.append(F[o:o + n].copy())
+            o += n
+        return out
+
+    def forces_at(self, Ps, Fs, schwarz_tol=1e-12):
+        """-dE/dR per instance at caller densities and Fock matrices."""
+        P, Fm = self._cat(Ps), self._cat(Fs)
+        G = np.empty((int(self.natoms.sum()), 3))
+        _chk(_lib.bscf_forces_at(self._h, _ptr(P), _ptr(Fm), _ptr(G), schwarz_tol, 0))
+        out, o = [], 0
+        for n in self.natoms:
+            out.append(G[o:o + n].copy())
             o += n
         return out
 

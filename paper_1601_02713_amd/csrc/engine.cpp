@@ -2180,11 +2180,10 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
   });
 }
 
-bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
-  return guard([&] {
-    need(c && Fout, BSCF_E_INVALID, "NULL argument");
-    need(c->have_scf, BSCF_E_STATE, "forces need an SCF at the current geometry");
-    HIPCHK(hipSetDevice(c->device));
+namespace {
+// -dE/dR of every instance at the densities c->P and Fock matrices c->F
+// (W = P F P / 2) into Fout [total_atoms][3] (host)
+void forces_impl(bscf_ctx* c, double* Fout) {
     const double t0 = now_ms();
     const hipStream_t st = c->stream;
     // W = P F P / 2
@@ -2372,6 +2371,32 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
     sync(c);
     for (size_t k = 0; k < g.size(); ++k) Fout[k] = -g[k];
     c->t_grad_ms += now_ms() - t0;
+}
+}  // namespace
+
+bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
+  return guard([&] {
+    need(c && Fout, BSCF_E_INVALID, "NULL argument");
+    need(c->have_scf, BSCF_E_STATE, "forces need an SCF at the current geometry");
+    HIPCHK(hipSetDevice(c->device));
+    forces_impl(c, Fout);
+  });
+}
+
+bscf_status bscf_forces_at(bscf_ctx* c, const double* P, const double* F, double* Fout,
+                           double tau, int device_ptrs) {
+  return guard([&] {
+    need(c && P && F && Fout, BSCF_E_INVALID, "NULL argument");
+    need(std::isfinite(tau), BSCF_E_INVALID, "bad Schwarz cutoff");
+    require_geom(c);
+    HIPCHK(hipSetDevice(c->device));
+    // the screened work lists of the current geometry at this cutoff
+    ensure_work(c, tau, c->split_tol, false);
+    c->have_scf = false;   // the SCF density is replaced: forces need a new SCF
+    const auto kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double), kind, c->stream));
+    HIPCHK(hipMemcpyAsync(c->F.p, F, c->mtot * sizeof(double), kind, c->stream));
+    forces_impl(c, Fout);
   });
 }
 
@@ -2595,7 +2620,7 @@ bscf_status bscf_guess_configure(bscf_ctx* c, int din, int dout, unsigned seed) 
   return guard([&] {
     need(c != nullptr && din > 0 && dout > 0, BSCF_E_INVALID, "bad arguments");
     HIPCHK(hipSetDevice(c->device));
-    c->guess.configure(din, dout, seed);
+    c->guess.configure_detached(din, dout, seed);
   });
 }
 

@@ -84,6 +84,10 @@ class Guess {
   // Direct use of the network (tests): fixed dimensions, parameter access,
   // evaluation and full-batch training on caller rows (host arrays).
   void configure(int din, int dout, unsigned seed);
+  // configure() for a network that belongs to no batch: no element types, no
+  // block size and no recorded steps, so the in-run guess sizes a new model
+  // from its batch before using one
+  void configure_detached(int din, int dout, unsigned seed);
   int din() const { return din_; }
   int dout() const { return dout_; }
   long nparams() const;

@@ -353,6 +353,14 @@ void Guess::configure(int din, int dout, unsigned seed) {
   work_rows_ = 0;
 }
 
+void Guess::configure_detached(int din, int dout, unsigned seed) {
+  configure(din, dout, seed);
+  types_.clear();
+  bmax_ = 0;
+  scale_ = 0.f;
+  replay_next_ = replay_count_ = 0;
+}
+
 void Guess::set_params(const float* h, long n, hipStream_t s) {
   if (n != nparams()) throw std::runtime_error("learned guess: parameter count mismatch");
   chk(hipMemcpyAsync(theta_.p, h, n * sizeof(float), hipMemcpyHostToDevice, s), "set params");

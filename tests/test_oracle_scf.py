@@ -108,3 +108,51 @@ def test_gradient_net_force_torque_and_rotation(sto3g):
     r2 = oracle.scf(b2, 1e-11, 1e-9)
     g2 = oracle.gradient(b2, r2["P"], r2["F"])
     assert np.abs(g2 - g @ R.T).max() < 1e-8
+
+
+@pytest.mark.parametrize("tau", [0.0, 1e-12, 1e-6])
+def test_jk_pairs_against_full_tensor_and_canonical_build(b631gs, tau):
+    """The sampled-block J/K (direct sums over every ket pair) equal the
+    einsum over the full ERI tensor at tau = 0 and the canonical-quartet build
+    at the same Schwarz cutoff, for every shell pair of (H2O)2, diagonal and
+    off-diagonal, in both orders."""
+    z, x = inputs.workload("w2")["instances"][0]
+    b = oracle.build_basis(b631gs, z, x)
+    P = _rand_density(b["nbf"], np.random.default_rng(17))
+    Q = oracle.schwarz(b)
+    ns = b["nsh"]
+    pairs = [(a, c) for a in range(ns) for c in range(ns)]
+    Jp, Kp = oracle.jk_pairs(b, P, pairs, tau, Q)
+    assert not np.isnan(Jp).any() and not np.isnan(Kp).any()
+    J, K, _ = oracle.jk(b, P, tau, Q)
+    assert np.abs(Jp - J).max() < 1e-12 and np.abs(Kp - K).max() < 1e-12
+    if tau == 0.0:
+        g = oracle.eri_tensor(b)
+        assert np.abs(Jp - np.einsum("ijkl,kl->ij", g, P)).max() < 1e-12
+        assert np.abs(Kp - np.einsum("ikjl,kl->ij", g, P)).max() < 1e-12
+    # a subset fills only its own blocks
+    Js, Ks = oracle.jk_pairs(b, P, [(3, 0), (5, 5)], tau, Q)
+    bf, l = b["bf"], b["l"]
+    nc = lambda s: (int(l[s]) + 1) * (int(l[s]) + 2) // 2
+    for a, c in [(3, 0), (5, 5)]:
+        blk = np.s_[bf[a]:bf[a] + nc(a), bf[c]:bf[c] + nc(c)]
+        # (threads add their partial sums in any order: equal to rounding)
+        assert np.abs(Js[blk] - Jp[blk]).max() < 1e-14 and np.abs(Ks[blk] - Kp[blk]).max() < 1e-14
+    assert np.isnan(Js).sum() == b["nbf"] ** 2 - nc(3) * nc(0) - nc(5) ** 2
+
+
+def test_gradient_of_selected_atoms_equals_full_gradient_rows(b631gs):
+    """The atom-restricted gradient (quartets touching the selected atoms,
+    their one-electron and operator terms) reproduces those rows of the full
+    gradient at an arbitrary density and Fock matrix, and leaves the rest NaN."""
+    z, x = inputs.water_cluster(2, 5)
+    b = oracle.build_basis(b631gs, z, x)
+    rng = np.random.default_rng(23)
+    P = _rand_density(b["nbf"], rng)
+    F = _rand_density(b["nbf"], rng)
+    g = oracle.gradient(b, P, F)
+    for atoms in ([1], [0, 4], [5, 2, 3]):
+        ga = oracle.gradient(b, P, F, atoms=atoms)
+        assert np.abs(ga[atoms] - g[atoms]).max() < 1e-11, atoms
+        others = [k for k in range(len(z)) if k not in atoms]
+        assert np.isnan(ga[others]).all()
