@@ -166,6 +166,61 @@ bscf_status bscf_forces(bscf_ctx* ctx, double* F);
 bscf_status bscf_forces_at(bscf_ctx* ctx, const double* P, const double* F, double* Fout,
                            double schwarz_tol, int device_ptrs);
 
+/* Ring-polymer (path-integral) molecular dynamics on the device.  The
+ * paper's replica layer moves every replica between force calls from its BO
+ * force (Section 2; its PIMD of water clusters, Section 3.1, counts time per
+ * step as the figure of merit, Fig. 3).  Here the batch's instances are the
+ * beads of one ring polymer (copies of one system, at most 64) and the
+ * position and momentum update runs on the device in normal-mode
+ * coordinates: a step of length dt is O B A B O with the PILE-L Langevin
+ * thermostat (Ceriotti, Parrinello, Markland and Manolopoulos 2010) on every
+ * normal mode (O), half kicks by the forces (B) and the exact free
+ * ring-polymer motion (A).  Convention: physical masses, bead potential V/P,
+ * spring frequency w_P = sqrt(P) k_B T / hbar, sampling at T.  The thermostat
+ * draws its Gaussian deviates from Philox4x32-10 (Salmon et al. 2011) with
+ * the Box-Muller transform, from counters fixed by (seed, step, half-step,
+ * mode, atom, xyz), so runs repeat exactly. */
+typedef struct {
+  double dt;               /* time step, atomic time units (1 fs = 41.341373336)   */
+  double temperature;      /* K: the ensemble's, and the spring frequency's        */
+  int thermostat;          /* 0: none (NVE); 1: PILE-L                             */
+  double tau_centroid;     /* 1/gamma of the centroid mode, atomic time units;
+                              <= 0: the centroid is not thermostatted              */
+  double friction_scale;   /* lambda in gamma_k = 2 lambda w_k of the internal
+                              modes, w_k = 2 w_P sin(k pi / P); 1 = critical       */
+  unsigned long long seed; /* key of the thermostat's random stream                */
+} bscf_pimd_opts;
+
+/* Defaults: dt 0.25 fs, 300 K, PILE-L, tau_centroid 100 fs, lambda 1, seed 0. */
+bscf_status bscf_pimd_default_opts(bscf_pimd_opts* opts);
+/* Start a ring polymer at the current geometry (bscf_set_geometries; bead j
+ * = instance j) with masses[n_atoms] (electron masses) and momenta p0
+ * [P][n_atoms][3] (host; NULL: zero).  BSCF_E_INVALID unless every instance
+ * is a copy of instance 0's composition; BSCF_E_UNSUPPORTED above 64 beads.
+ * A new batch (bscf_set_instances) ends the ring polymer. */
+bscf_status bscf_pimd_init(bscf_ctx* ctx, const bscf_pimd_opts* opts, const double* masses,
+                           const double* p0);
+/* One step with this context as the force provider: at the first step (or
+ * after the positions changed) SCF and forces at the current positions, then
+ * O B A, the geometry set from the new positions, the SCF of every bead with
+ * opts (E, n_iter, status as bscf_run_scf, host, may be NULL), the forces,
+ * and B O.  Learned-guess training, if wanted, is the caller's between
+ * steps (bscf_guess_train). */
+bscf_status bscf_pimd_step(bscf_ctx* ctx, const bscf_scf_opts* opts, double* E, int* n_iter,
+                           int* status);
+/* The two halves of a step with the caller's forces instead (for other
+ * force providers and tests): begin = O B A with forces [P][n_atoms][3]
+ * (Eh/bohr, host; -dV/dq of each bead, not divided by P) at the current
+ * positions; end = B O with the forces at the new positions.  NULL forces
+ * take the context's own, which exist only within bscf_pimd_step
+ * (BSCF_E_STATE otherwise).  The context's geometry is not changed. */
+bscf_status bscf_pimd_begin(bscf_ctx* ctx, const double* forces);
+bscf_status bscf_pimd_end(bscf_ctx* ctx, const double* forces);
+/* Positions x and momenta p [P][n_atoms][3] (host, may be NULL) and obs[3]
+ * (may be NULL): kinetic energy sum |p|^2/2m, spring energy
+ * sum m w_P^2 |q_j - q_{j+1}|^2 / 2 (Eh), and the number of steps taken. */
+bscf_status bscf_pimd_state(bscf_ctx* ctx, double* x, double* p, double* obs);
+
 /* Density of instance `inst` after the last SCF (n_i x n_i), host or device;
  * the last density given to the batch (bscf_set_density, a Fock build) if
  * that came later, and zero before the first of these. */

@@ -82,6 +82,35 @@ _lib.bscf_boys_table_entry.restype = ctypes.c_double
 _lib.bscf_boys_table_entry.argtypes = [_i, _i]
 
 
+class PimdOpts(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("temperature", ctypes.c_double),
+                ("thermostat", ctypes.c_int), ("tau_centroid", ctypes.c_double),
+                ("friction_scale", ctypes.c_double), ("seed", ctypes.c_ulonglong)]
+
+
+_SIGS.update({
+    "bscf_pimd_default_opts": [ctypes.POINTER(PimdOpts)],
+    "bscf_pimd_init": [_vp, ctypes.POINTER(PimdOpts), _vp, _vp],
+    "bscf_pimd_step": [_vp, ctypes.POINTER(ScfOpts), _vp, _vp, _vp],
+    "bscf_pimd_begin": [_vp, _vp],
+    "bscf_pimd_end": [_vp, _vp],
+    "bscf_pimd_state": [_vp, _vp, _vp, _vp],
+})
+for _name in ("bscf_pimd_default_opts", "bscf_pimd_init", "bscf_pimd_step", "bscf_pimd_begin",
+              "bscf_pimd_end", "bscf_pimd_state"):
+    _f = getattr(_lib, _name)
+    _f.argtypes = _SIGS[_name]
+    _f.restype = ctypes.c_int
+
+
+def pimd_default_opts(**kw) -> PimdOpts:
+    o = PimdOpts()
+    _chk(_lib.bscf_pimd_default_opts(ctypes.byref(o)))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
 class BscfError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"beadscf error {code}: {msg}")
@@ -208,6 +237,48 @@ class Engine:
             out.append(G[o:o + n].copy())
             o += n
         return out
+
+    # ---- ring polymer (the batch's instances are its beads)
+    def pimd_init(self, masses, p0=None, opts: PimdOpts | None = None, **kw):
+        o = opts or pimd_default_opts(**kw)
+        m = np.ascontiguousarray(np.asarray(masses, float))
+        p = None if p0 is None else np.ascontiguousarray(np.asarray(p0, float))
+        if p is not None and p.size != 3 * int(self.natoms.sum()):
+            raise ValueError("p0 must hold [P][n_atoms][3] momenta")
+        if m.size != int(self.natoms[0]):
+            raise ValueError("one mass per atom of a bead")
+        _chk(_lib.bscf_pimd_init(self._h, ctypes.byref(o), _ptr(m), _ptr(p) if p is not None else None))
+
+    def pimd_step(self, opts: ScfOpts | None = None, **kw):
+        o = opts or default_opts(**kw)
+        E = np.empty(self.n_inst)
+        it = np.empty(self.n_inst, np.int32)
+        st = np.empty(self.n_inst, np.int32)
+        _chk(_lib.bscf_pimd_step(self._h, ctypes.byref(o), _ptr(E), _ptr(it), _ptr(st)))
+        return E, it, st
+
+    def _pimd_forces(self, F):
+        if F is None:
+            return None
+        F = np.ascontiguousarray(np.asarray(F, float))
+        if F.size != 3 * int(self.natoms.sum()):
+            raise ValueError("forces must be [P][n_atoms][3]")
+        return F
+
+    def pimd_begin(self, F=None):
+        F = self._pimd_forces(F)
+        _chk(_lib.bscf_pimd_begin(self._h, _ptr(F) if F is not None else None))
+
+    def pimd_end(self, F=None):
+        F = self._pimd_forces(F)
+        _chk(_lib.bscf_pimd_end(self._h, _ptr(F) if F is not None else None))
+
+    def pimd_state(self):
+        """(x, p [P, N, 3], kinetic, spring, steps)."""
+        P, N = self.n_inst, int(self.natoms[0])
+        x, p, obs = np.empty((P, N, 3)), np.empty((P, N, 3)), np.empty(3)
+        _chk(_lib.bscf_pimd_state(self._h, _ptr(x), _ptr(p), _ptr(obs)))
+        return x, p, float(obs[0]), float(obs[1]), int(obs[2])
 
     def density(self, i):
         n = self.nbf[i]

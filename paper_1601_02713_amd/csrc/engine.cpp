@@ -37,6 +37,7 @@
 #include "kernels.h"
 #include "grad.h"
 #include "mlp.h"
+#include "pimd.h"
 
 using namespace bscf;
 
@@ -450,6 +451,18 @@ struct bscf_ctx {
   std::vector<int> last_iters;
 
   mlp::Guess guess;
+
+  // ring-polymer integrator over the batch's instances (its beads); state on
+  // the device between steps
+  struct Pimd {
+    bool on = false;
+    int P = 0, N = 0;
+    bscf_pimd_opts o{};
+    uint64_t step = 0;
+    bool synced = false;       // the context's geometry is the integrator's positions
+    bool have_force = false;   // d_grad holds the gradient at the current positions
+    DevBuf<double> x, p, C, w, c1, c2, mass, sig, F;
+  } md;
 
   BatchInfo batch(bool masked) const {
     BatchInfo b;
@@ -1815,6 +1828,7 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->work_tau = c->host_tau = -1.0;
     c->fock_tuned[0] = c->fock_tuned[1] = c->grad_tuned = false;
     c->guess.reset_batch(c->ninst);
+    c->md.on = c->md.synced = c->md.have_force = false;
     sync(c);
     undo.done = true;
   });
@@ -1831,6 +1845,7 @@ bscf_status bscf_set_geometries(bscf_ctx* c, const double* xyz) {
     // call has finished: a device error part-way through cannot leave the
     // previous densities paired with the new coordinates
     c->have_geom = c->have_scf = false;
+    c->md.synced = c->md.have_force = false;
     HIPCHK(hipSetDevice(c->device));
     join_work(c);
     c->work_tau = c->host_tau = -1.0;
@@ -2370,6 +2385,7 @@ void forces_impl(bscf_ctx* c, double* Fout) {
     HIPCHK(hipMemcpyAsync(g.data(), c->d_grad.p, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     sync(c);
     for (size_t k = 0; k < g.size(); ++k) Fout[k] = -g[k];
+    if (c->md.on && c->md.synced) c->md.have_force = true;
     c->t_grad_ms += now_ms() - t0;
 }
 }  // namespace
@@ -2397,6 +2413,236 @@ bscf_status bscf_forces_at(bscf_ctx* c, const double* P, const double* F, double
     HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double), kind, c->stream));
     HIPCHK(hipMemcpyAsync(c->F.p, F, c->mtot * sizeof(double), kind, c->stream));
     forces_impl(c, Fout);
+  });
+}
+
+// ------------------------------------------------------------ ring polymer
+
+namespace {
+constexpr double kKbHartreePerK = 3.166811563e-6;   // CODATA 2018
+
+PimdArgs pimd_args(bscf_ctx* c) {
+  auto& m = c->md;
+  PimdArgs a;
+  a.P = m.P;
+  a.ncol = 3 * m.N;
+  a.dt = m.o.dt;
+  a.x = m.x.p;
+  a.p = m.p.p;
+  a.C = m.C.p;
+  a.w = m.w.p;
+  a.c1 = m.c1.p;
+  a.c2 = m.c2.p;
+  a.mass = m.mass.p;
+  a.sig = m.sig.p;
+  a.seed = m.o.seed;
+  return a;
+}
+
+// forces of a half-step: the caller's [P][N][3] (host), or the context's
+// last gradient at the current positions (sign -1)
+const double* pimd_forces(bscf_ctx* c, const double* F, double& sign) {
+  auto& m = c->md;
+  if (F) {
+    const size_t n = (size_t)m.P * 3 * m.N;
+    for (size_t k = 0; k < n; ++k) need(std::isfinite(F[k]), BSCF_E_INVALID, "non-finite force");
+    m.F.resize(n);
+    HIPCHK(hipMemcpyAsync(m.F.p, F, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    sign = 1.0;
+    return m.F.p;
+  }
+  need(m.have_force, BSCF_E_STATE, "no forces at the current ring-polymer positions");
+  sign = -1.0;
+  return c->d_grad.p;
+}
+
+void pimd_begin_impl(bscf_ctx* c, const double* F) {
+  auto& m = c->md;
+  double sign = 1.0;
+  const double* f = pimd_forces(c, F, sign);
+  const PimdArgs a = pimd_args(c);
+  launch_pimd_ob(a, f, sign, m.o.thermostat, 2 * m.step, 0, c->stream);
+  launch_pimd_a(a, c->stream);
+  HIPCHK(hipGetLastError());
+  m.synced = m.have_force = false;
+}
+
+void pimd_end_impl(bscf_ctx* c, const double* F) {
+  auto& m = c->md;
+  double sign = 1.0;
+  const double* f = pimd_forces(c, F, sign);
+  launch_pimd_ob(pimd_args(c), f, sign, m.o.thermostat, 2 * m.step + 1, 1, c->stream);
+  HIPCHK(hipGetLastError());
+  ++m.step;
+}
+
+void check_status(bscf_status rc) {
+  if (rc != BSCF_OK) throw Error(rc, g_err);
+}
+
+// the context's geometry from the integrator's positions, then SCF and forces
+void pimd_forces_here(bscf_ctx* c, const bscf_scf_opts* o, double* E, int* it, int* st) {
+  auto& m = c->md;
+  std::vector<double> x((size_t)m.P * 3 * m.N), F(x.size());
+  HIPCHK(hipMemcpyAsync(x.data(), m.x.p, x.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  check_status(bscf_set_geometries(c, x.data()));
+  m.synced = true;
+  check_status(bscf_run_scf(c, o, E, it, st));
+  forces_impl(c, F.data());
+}
+}  // namespace
+
+bscf_status bscf_pimd_default_opts(bscf_pimd_opts* o) {
+  if (!o) return BSCF_E_INVALID;
+  o->dt = 0.25 * 41.341373336;
+  o->temperature = 300.0;
+  o->thermostat = 1;
+  o->tau_centroid = 100.0 * 41.341373336;
+  o->friction_scale = 1.0;
+  o->seed = 0;
+  return BSCF_OK;
+}
+
+bscf_status bscf_pimd_init(bscf_ctx* c, const bscf_pimd_opts* opts, const double* masses,
+                           const double* p0) {
+  return guard([&] {
+    need(c && opts && masses, BSCF_E_INVALID, "NULL argument");
+    require_geom(c);
+    const bscf_pimd_opts o = *opts;
+    need(std::isfinite(o.dt) && o.dt > 0.0, BSCF_E_INVALID, "dt must be positive");
+    need(std::isfinite(o.temperature) && o.temperature > 0.0, BSCF_E_INVALID,
+         "temperature must be positive");
+    need(o.thermostat == 0 || o.thermostat == 1, BSCF_E_INVALID, "thermostat must be 0 or 1");
+    need(std::isfinite(o.friction_scale) && o.friction_scale > 0.0, BSCF_E_INVALID,
+         "friction_scale must be positive");
+    need(std::isfinite(o.tau_centroid), BSCF_E_INVALID, "bad tau_centroid");
+    const int P = c->ninst, N = c->natoms[0];
+    need(P <= kPimdMaxBeads, BSCF_E_UNSUPPORTED,
+         "at most " + std::to_string(kPimdMaxBeads) + " beads");
+    for (int i = 0; i < P; ++i) {
+      need(c->natoms[i] == N, BSCF_E_INVALID, "beads must be copies of one system");
+      for (int a = 0; a < N; ++a)
+        need(c->Zs[c->atom_off[i] + a] == c->Zs[a], BSCF_E_INVALID, "beads must be copies of one system");
+    }
+    for (int a = 0; a < N; ++a)
+      need(std::isfinite(masses[a]) && masses[a] > 0.0, BSCF_E_INVALID, "masses must be positive");
+    const size_t n = (size_t)P * 3 * N;
+    if (p0)
+      for (size_t k = 0; k < n; ++k) need(std::isfinite(p0[k]), BSCF_E_INVALID, "non-finite momentum");
+    HIPCHK(hipSetDevice(c->device));
+    // normal modes of the cyclic chain, their frequencies and the O-step
+    // factors (host, FP64)
+    const double kT = kKbHartreePerK * o.temperature;
+    const double wp = std::sqrt((double)P) * kT;
+    std::vector<double> C((size_t)P * P), w(P), c1(P), c2(P), sig(N), mass(masses, masses + N);
+    for (int j = 0; j < P; ++j)
+      for (int k = 0; k < P; ++k) {
+        double v;
+        if (k == 0) v = 1.0 / std::sqrt((double)P);
+        else if (2 * k < P) v = std::sqrt(2.0 / P) * std::cos(2.0 * M_PI * j * k / P);
+        else if (2 * k == P) v = (j % 2 ? -1.0 : 1.0) / std::sqrt((double)P);
+        else v = std::sqrt(2.0 / P) * std::sin(2.0 * M_PI * j * k / P);
+        C[(size_t)j * P + k] = v;
+      }
+    for (int k = 0; k < P; ++k) {
+      w[k] = 2.0 * wp * std::sin(k * M_PI / P);
+      const double gam = k == 0 ? (o.tau_centroid > 0.0 ? 1.0 / o.tau_centroid : 0.0)
+                                : 2.0 * o.friction_scale * w[k];
+      c1[k] = std::exp(-0.5 * gam * o.dt);
+      c2[k] = std::sqrt(1.0 - c1[k] * c1[k]);
+    }
+    for (int a = 0; a < N; ++a) sig[a] = std::sqrt(mass[a] * kT);
+    auto& m = c->md;
+    m.on = false;
+    const hipStream_t s = c->stream;
+    m.C.upload(C, s);
+    m.w.upload(w, s);
+    m.c1.upload(c1, s);
+    m.c2.upload(c2, s);
+    m.sig.upload(sig, s);
+    m.mass.upload(mass, s);
+    m.x.upload(c->xyz, s);
+    std::vector<double> pv(n, 0.0);
+    if (p0) pv.assign(p0, p0 + n);
+    m.p.upload(pv, s);
+    m.F.resize(n);
+    sync(c);
+    m.P = P;
+    m.N = N;
+    m.o = o;
+    m.step = 0;
+    m.on = true;
+    m.synced = true;
+    m.have_force = false;
+  });
+}
+
+bscf_status bscf_pimd_begin(bscf_ctx* c, const double* forces) {
+  return guard([&] {
+    need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    need(c->md.on, BSCF_E_STATE, "no ring polymer: call bscf_pimd_init");
+    HIPCHK(hipSetDevice(c->device));
+    pimd_begin_impl(c, forces);
+    sync(c);
+  });
+}
+
+bscf_status bscf_pimd_end(bscf_ctx* c, const double* forces) {
+  return guard([&] {
+    need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    need(c->md.on, BSCF_E_STATE, "no ring polymer: call bscf_pimd_init");
+    HIPCHK(hipSetDevice(c->device));
+    pimd_end_impl(c, forces);
+    sync(c);
+  });
+}
+
+bscf_status bscf_pimd_step(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int* n_iter,
+                           int* status) {
+  return guard([&] {
+    need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    need(c->md.on, BSCF_E_STATE, "no ring polymer: call bscf_pimd_init");
+    HIPCHK(hipSetDevice(c->device));
+    if (!c->md.have_force) pimd_forces_here(c, opts, nullptr, nullptr, nullptr);
+    pimd_begin_impl(c, nullptr);
+    pimd_forces_here(c, opts, E, n_iter, status);
+    pimd_end_impl(c, nullptr);
+    sync(c);
+  });
+}
+
+bscf_status bscf_pimd_state(bscf_ctx* c, double* x, double* p, double* obs) {
+  return guard([&] {
+    need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    need(c->md.on, BSCF_E_STATE, "no ring polymer: call bscf_pimd_init");
+    HIPCHK(hipSetDevice(c->device));
+    auto& m = c->md;
+    const size_t n = (size_t)m.P * 3 * m.N;
+    std::vector<double> hx(n), hp(n);
+    HIPCHK(hipMemcpyAsync(hx.data(), m.x.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(hp.data(), m.p.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    if (x) std::copy(hx.begin(), hx.end(), x);
+    if (p) std::copy(hp.begin(), hp.end(), p);
+    if (obs) {
+      std::vector<double> mass(m.N);
+      HIPCHK(hipMemcpy(mass.data(), m.mass.p, m.N * sizeof(double), hipMemcpyDeviceToHost));
+      const double wp = std::sqrt((double)m.P) * kKbHartreePerK * m.o.temperature;
+      double ke = 0.0, sp = 0.0;
+      for (int j = 0; j < m.P; ++j)
+        for (int a = 0; a < m.N; ++a)
+          for (int d = 0; d < 3; ++d) {
+            const size_t i = ((size_t)j * m.N + a) * 3 + d;
+            const size_t i1 = ((size_t)((j + 1) % m.P) * m.N + a) * 3 + d;
+            ke += hp[i] * hp[i] / (2.0 * mass[a]);
+            const double dx = hx[i] - hx[i1];
+            sp += 0.5 * mass[a] * wp * wp * dx * dx;
+          }
+      obs[0] = ke;
+      obs[1] = sp;
+      obs[2] = (double)m.step;
+    }
   });
 }
 

@@ -110,6 +110,7 @@ class Guess {
   void build_rows(const Batch& b);
   void features(const Batch& b, float* X);   // device rows of the current row list
   void forward(int rows, const float* X, hipStream_t s);
+  void forward_into(int rows, const float* X, float* h1, float* h2, float* y, hipStream_t s);
   float backward(int rows, const float* X, const float* T, const float* M, double cnt,
                  hipStream_t s);
   void adam(float lr, hipStream_t s);

@@ -390,17 +390,23 @@ void Guess::alloc_work(int rows) {
 
 void Guess::forward(int rows, const float* X, hipStream_t s) {
   alloc_work(rows);
+  forward_into(rows, X, h1_.p, h2_.p, y_.p, s);
+}
+
+// the three layers and the residual connection into caller buffers
+// (h1, h2: rows x kHidden; y: rows x dout); kernel launches only
+void Guess::forward_into(int rows, const float* X, float* h1, float* h2, float* y, hipStream_t s) {
   const float* W1 = theta_.p;
   const float* b1 = W1 + (long)din_ * kHidden;
   const float* W2 = b1 + kHidden;
   const float* b2 = W2 + (long)kHidden * kHidden;
   const float* W3 = b2 + kHidden;
   const float* b3 = W3 + (long)kHidden * dout_;
-  gemm(false, false, rows, kHidden, din_, X, din_, W1, kHidden, h1_.p, kHidden, b1, true, s);
-  gemm(false, false, rows, kHidden, kHidden, h1_.p, kHidden, W2, kHidden, h2_.p, kHidden, b2, true, s);
-  gemm(false, false, rows, dout_, kHidden, h2_.p, kHidden, W3, dout_, y_.p, dout_, b3, false, s);
+  gemm(false, false, rows, kHidden, din_, X, din_, W1, kHidden, h1, kHidden, b1, true, s);
+  gemm(false, false, rows, kHidden, kHidden, h1, kHidden, W2, kHidden, h2, kHidden, b2, true, s);
+  gemm(false, false, rows, dout_, kHidden, h2, kHidden, W3, dout_, y, dout_, b3, false, s);
   const long ny = (long)rows * dout_;
-  hipLaunchKernelGGL(skip_kernel, grid1d(ny), dim3(256), 0, s, ny, din_, dout_, X, y_.p);
+  hipLaunchKernelGGL(skip_kernel, grid1d(ny), dim3(256), 0, s, ny, din_, dout_, X, y);
 }
 
 // gradient of the loss of the last forward pass into grad_; returns the loss
