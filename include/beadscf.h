@@ -307,6 +307,22 @@ bscf_status bscf_guess_eval(bscf_ctx* ctx, int rows, const float* X, const float
 bscf_status bscf_guess_fit(bscf_ctx* ctx, int rows, const float* X, const float* T,
                            const float* mask, int steps, float lr, float* loss);
 
+/* Allocation-free evaluation of the guess network, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The same result as bscf_guess_eval
+ * without targets: Y = net(X) for `rows` input rows.  X (rows x din) and Y
+ * (rows x dout) are FP32 row-major HIP device pointers on the context's
+ * device; the work is enqueued on the context's stream and the call returns
+ * without synchronising.  It allocates nothing: the hidden activations go to
+ * one fixed array per GPU of 2 x BSCF_NOALLOC_MAX_ROWS x 256 floats (16 MiB),
+ * set up by bscf_create and held until the process ends.  rows must be
+ * 1..BSCF_NOALLOC_MAX_ROWS (BSCF_E_INVALID otherwise); BSCF_E_STATE without a
+ * configured network.  Every call on one GPU uses that GPU's array, so calls
+ * that overlap on one GPU (other contexts or streams) race; calls ordered on
+ * one stream do not. */
+#define BSCF_NOALLOC_MAX_ROWS 8192
+bscf_status bscf_guess_eval_noalloc(bscf_ctx* ctx, int rows, const float* X, float* Y);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* bscf_last_error(void);
 

@@ -71,6 +71,7 @@ _SIGS = {
     "bscf_guess_get_params": [_vp, _vp, ctypes.c_long],
     "bscf_guess_eval": [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp],
     "bscf_guess_fit": [_vp, _i, _vp, _vp, _vp, _i, ctypes.c_float, _vp],
+    "bscf_guess_eval_noalloc": [_vp, _i, _vp, _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -359,6 +360,11 @@ class Engine:
     def guess_set_params(self, p):
         p = np.ascontiguousarray(np.asarray(p, np.float32))
         _chk(_lib.bscf_guess_set_params(self._h, _ptr(p), p.size))
+
+    def guess_eval_noalloc(self, rows, x_dev_ptr, y_dev_ptr):
+        """Allocation-free evaluation on device buffers (addresses as ints),
+        enqueued on the context's stream without synchronising."""
+        _chk(_lib.bscf_guess_eval_noalloc(self._h, rows, _vp(x_dev_ptr), _vp(y_dev_ptr)))
 
     def guess_eval(self, X, T=None, mask=None):
         """(Y, gradient, loss) of the network on host rows; gradient and loss

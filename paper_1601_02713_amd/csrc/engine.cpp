@@ -1594,6 +1594,7 @@ bscf_status bscf_create(int hip_device, void* hip_stream, bscf_ctx** out) {
         c->grad_variant[q] = qc[q].grad && c->private_bytes[q][2] <= kMaxLaneScratch ? 0 : 1;
       }
     }
+    mlp::init_noalloc_scratch(hip_device);
     BLASCHK(rocblas_create_handle(&c->blas));
     BLASCHK(rocblas_set_stream(c->blas, c->stream));
     std::vector<double> tab(kBoysRows * kBoysCols);
@@ -2905,6 +2906,17 @@ bscf_status bscf_guess_eval(bscf_ctx* c, int rows, const float* X, const float* 
     need(c->guess.din() > 0, BSCF_E_STATE, "network not configured");
     HIPCHK(hipSetDevice(c->device));
     c->guess.eval_rows(rows, X, T, mask, Y, grad, loss, c->stream);
+  });
+}
+
+bscf_status bscf_guess_eval_noalloc(bscf_ctx* c, int rows, const float* X, float* Y) {
+  return guard([&] {
+    need(c && X && Y, BSCF_E_INVALID, "NULL argument");
+    need(rows > 0 && rows <= mlp::kNoAllocRows, BSCF_E_INVALID,
+         "rows must be 1.." + std::to_string(mlp::kNoAllocRows) + " for the allocation-free evaluation");
+    need(c->guess.din() > 0, BSCF_E_STATE, "network not configured");
+    HIPCHK(hipSetDevice(c->device));
+    c->guess.eval_noalloc(c->device, rows, X, Y, c->stream);
   });
 }
 

@@ -62,6 +62,13 @@ struct Buf {
   void resize(size_t m);   // contents undefined after growth
 };
 
+// Largest row count of the allocation-free evaluation (its hidden activations
+// sit in a fixed per-GPU array of 2 x kNoAllocRows x kHidden floats, 16 MiB).
+constexpr int kNoAllocRows = 8192;
+// Finds the device address of that array on `device` (which must be current)
+// once per device; called by context creation.
+void init_noalloc_scratch(int device);
+
 class Guess {
  public:
   ~Guess();
@@ -101,6 +108,11 @@ class Guess {
   // moments; loss before the last step.
   float fit_rows(int rows, const float* X, const float* T, const float* M, int steps, float lr,
                  hipStream_t s);
+  // Y = net(X) for device rows X (rows x din) into device Y (rows x dout),
+  // enqueued on s with no allocation and no synchronisation; the activations
+  // go to the per-GPU array of init_noalloc_scratch (calls that overlap on one
+  // GPU race on it).
+  void eval_noalloc(int device, int rows, const float* X, float* Y, hipStream_t s);
 
  private:
   struct Row {

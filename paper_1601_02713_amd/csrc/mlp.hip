@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <map>
+#include <mutex>
 #include <random>
 #include <stdexcept>
 
@@ -407,6 +409,48 @@ void Guess::forward_into(int rows, const float* X, float* h1, float* h2, float* 
   gemm(false, false, rows, dout_, kHidden, h2, kHidden, W3, dout_, y, dout_, b3, false, s);
   const long ny = (long)rows * dout_;
   hipLaunchKernelGGL(skip_kernel, grid1d(ny), dim3(256), 0, s, ny, din_, dout_, X, y);
+}
+
+// ------------------------------------------------- allocation-free evaluation
+
+namespace {
+// Hidden activations of the allocation-free forward pass: h1 then h2, each
+// kNoAllocRows x kHidden floats.  One copy per GPU, held until the process
+// ends.  Host code never passes this name to a kernel: it uses the device
+// address found by hipGetSymbolAddress, kept per device below.
+__device__ __align__(256) float scratch[2 * (size_t)kNoAllocRows * kHidden];
+
+std::mutex g_scratch_mu;
+std::map<int, float*> g_scratch_ptr;   // device ordinal -> address of its copy of scratch
+}  // namespace
+
+void init_noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr.count(device)) return;
+  int cur = -1;
+  chk(hipGetDevice(&cur), "current device");
+  if (cur != device) throw std::runtime_error("init_noalloc_scratch: device not current");
+  void* p = nullptr;
+  chk(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "address of the allocation-free scratch");
+  if (p == nullptr) throw std::runtime_error("allocation-free scratch has no device address");
+  g_scratch_ptr[device] = static_cast<float*>(p);
+}
+
+void Guess::eval_noalloc(int device, int rows, const float* X, float* Y, hipStream_t s) {
+  if (din_ == 0) throw std::runtime_error("learned guess: network not configured");
+  if (rows <= 0 || rows > kNoAllocRows)
+    throw std::runtime_error("learned guess: the allocation-free evaluation takes 1.." +
+                             std::to_string(kNoAllocRows) + " rows, not " + std::to_string(rows));
+  float* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it == g_scratch_ptr.end())
+      throw std::runtime_error("allocation-free scratch not set up on this device");
+    base = it->second;
+  }
+  forward_into(rows, X, base, base + (size_t)kNoAllocRows * kHidden, Y, s);
+  chk(hipGetLastError(), "allocation-free forward launch");
 }
 
 // gradient of the loss of the last forward pass into grad_; returns the loss
