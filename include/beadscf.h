@@ -76,7 +76,12 @@ typedef struct {
   int diis_size;       /* Pulay DIIS subspace (<= 8)                            */
   int precision;       /* bscf_precision                                        */
   int guess;           /* bscf_guess                                            */
-  int deterministic;   /* reserved: 0                                           */
+  int deterministic;   /* 1: J and K of every Fock build accumulate in exact
+                          fixed point (a 128-bit integer with 80 fractional
+                          bits per element) instead of FP64 atomics, so they do
+                          not depend on the order in which workgroups finish
+                          (bitwise equal from run to run at equal densities);
+                          0: FP64 atomics (faster; equal to rounding)        */
   int density;         /* bscf_density: how each iteration's density is formed;
                           both give the projector on the lowest N/2 levels of
                           the extrapolated Fock matrix (Section 2, SCF step)   */
@@ -105,12 +110,17 @@ bscf_status bscf_default_opts(bscf_scf_opts* opts);
 bscf_status bscf_create(int hip_device, void* hip_stream, bscf_ctx** out);
 bscf_status bscf_destroy(bscf_ctx* ctx);
 
-/* Basis set as JSON text: {"elements": {"H": {"Z": 1, "shells": [{"l": 0,
+/* Gaussian basis set of the electronic-structure layer (the paper's runs use
+ * 6-31G*, Section 3.1; here with Cartesian d functions).
+ * Basis set as JSON text: {"elements": {"H": {"Z": 1, "shells": [{"l": 0,
  * "exponents": [...], "coefficients": [...]}, ...]}, ...}}; s, p, d shells
  * (SP shells given as separate s and p shells).  Copied. */
 bscf_status bscf_load_basis(bscf_ctx* ctx, const char* basis_json);
 
-/* Batch composition: n_inst instances; n_atoms[i] atoms each with nuclear
+/* The set of n replicas whose BO energies and forces every step needs
+ * (Section 2: the PIMD layer generates n nuclear configurations; Section 3.2:
+ * the images of a string).
+ * Batch composition: n_inst instances; n_atoms[i] atoms each with nuclear
  * charges Z_concat (concatenated over instances) and total charges charge[i]
  * (may be NULL for neutral).  Allocates all per-instance device storage.
  * BSCF_E_UNSUPPORTED for an element missing from the basis or an odd number
@@ -122,12 +132,19 @@ bscf_status bscf_load_basis(bscf_ctx* ctx, const char* basis_json);
 bscf_status bscf_set_instances(bscf_ctx* ctx, int n_inst, const int* n_atoms,
                                const int* Z_concat, const int* charge);
 
-/* Nuclear positions [sum n_atoms][3] in bohr, host memory, copied.  Computes
+/* The replicas' configurations of the current step (Section 2), and with them
+ * everything that depends on geometry only: the integral screening at the
+ * paper's cutoff 1e-12 (Section 3.1) and the one-electron matrices.
+ * Nuclear positions [sum n_atoms][3] in bohr, host memory, copied.  Computes
  * the shell-pair data, Schwarz bounds, screened work lists, S, H and the
  * orthogonaliser of every instance on the device. */
 bscf_status bscf_set_geometries(bscf_ctx* ctx, const double* xyz_bohr_concat);
 
-/* One Fock build at given densities: P (all instances concatenated, each
+/* The direct-SCF Fock build of every replica (the step the paper finds to
+ * dominate at high core counts, Section 3.1, Fig. 2b): Roothaan-Hall
+ * F = H + J - K/2 (Szabo and Ostlund, Section 3.4) with Schwarz-screened
+ * two-electron integrals (cutoff of Section 3.1).
+ * One Fock build at given densities: P (all instances concatenated, each
  * n_i x n_i) -> F = H + J - K/2 and E[i] = Tr[P(H+F)]/2 + E_nuc.  With
  * device_ptrs, P and F are device pointers and E may be NULL.  schwarz_tol as
  * in the options (<= 0: no screening); precision a bscf_precision.  The
@@ -141,14 +158,21 @@ bscf_status bscf_build_fock(bscf_ctx* ctx, const double* P, double* F, double* E
 bscf_status bscf_build_jk(bscf_ctx* ctx, const double* P, double* J, double* K,
                           double schwarz_tol, int precision, int device_ptrs);
 
-/* Run the SCF of every instance (Pulay DIIS on the orthogonalised commutator;
+/* The SCF of every replica to the paper's density threshold (Section 3.1),
+ * all replicas in one batch; a replica that converges is masked out of later
+ * builds, so replicas needing different numbers of SCF cycles do not hold
+ * each other up (the imbalance of Section 3.2).
+ * Run the SCF of every instance (Pulay DIIS on the orthogonalised commutator;
  * converged when both thresholds hold).  Outputs (host, may be NULL): E[n_inst],
  * n_iter[n_inst], status[n_inst] (bscf status bits).  Non-convergence of an
  * instance is a status bit, not an error. */
 bscf_status bscf_run_scf(bscf_ctx* ctx, const bscf_scf_opts* opts, double* E, int* n_iter,
                          int* status);
 
-/* Forces F = -dE/dR [sum n_atoms][3] (Eh/bohr, host) at the densities of the
+/* The BO forces of every replica, gathered into one array (Section 2: the
+ * forces of the respective replica, summed into the zero-filled per-replica
+ * arrays; Fig. 2c).
+ * Forces F = -dE/dR [sum n_atoms][3] (Eh/bohr, host) at the densities of the
  * last bscf_run_scf (Pople et al. 1979 gradient with W = P F P / 2).
  * BSCF_E_STATE if no SCF has run at the current geometry or its densities
  * were replaced since. */
@@ -203,11 +227,12 @@ bscf_status bscf_pimd_init(bscf_ctx* ctx, const bscf_pimd_opts* opts, const doub
 /* One step with this context as the force provider: at the first step (or
  * after the positions changed) SCF and forces at the current positions, then
  * O B A, the geometry set from the new positions, the SCF of every bead with
- * opts (E, n_iter, status as bscf_run_scf, host, may be NULL), the forces,
- * and B O.  Learned-guess training, if wanted, is the caller's between
- * steps (bscf_guess_train). */
+ * opts (E, n_iter, status as bscf_run_scf, host, may be NULL), the forces
+ * (-dE/dR [P][n_atoms][3] into `forces`, host, may be NULL), and B O.
+ * Learned-guess training, if wanted, is the caller's between steps
+ * (bscf_guess_train). */
 bscf_status bscf_pimd_step(bscf_ctx* ctx, const bscf_scf_opts* opts, double* E, int* n_iter,
-                           int* status);
+                           int* status, double* forces);
 /* The two halves of a step with the caller's forces instead (for other
  * force providers and tests): begin = O B A with forces [P][n_atoms][3]
  * (Eh/bohr, host; -dV/dq of each bead, not divided by P) at the current
@@ -221,7 +246,44 @@ bscf_status bscf_pimd_end(bscf_ctx* ctx, const double* forces);
  * sum m w_P^2 |q_j - q_{j+1}|^2 / 2 (Eh), and the number of steps taken. */
 bscf_status bscf_pimd_state(bscf_ctx* ctx, double* x, double* p, double* obs);
 
-/* Density of instance `inst` after the last SCF (n_i x n_i), host or device;
+/* String method on the device.  The paper's second workload moves a
+ * reaction path of images between force calls (Section 3.2, Fig. 4: each
+ * image's BO energy and force in parallel, images needing different numbers
+ * of SCF iterations).  Here the batch's instances are the images (copies of
+ * one system, 2..2048) and the path follows the simplified string method
+ * (E, Ren and Vanden-Eijnden 2007): every movable image takes the
+ * steepest-descent step x <- x + step F, then the images are redistributed
+ * to equal arc length along the piecewise-linear path (linear
+ * interpolation; the end images keep their positions). */
+typedef struct {
+  double step;   /* steepest-descent step, bohr^2/Eh (> 0)                 */
+  int fix_ends;  /* 1: the first and last image do not move                */
+} bscf_string_opts;
+
+/* Defaults: step 0.5 bohr^2/Eh, ends free. */
+bscf_status bscf_string_default_opts(bscf_string_opts* opts);
+/* Start a string at the current geometry (image i = instance i).
+ * BSCF_E_INVALID unless every instance is a copy of instance 0's
+ * composition and there are at least two; BSCF_E_UNSUPPORTED above 2048. */
+bscf_status bscf_string_init(bscf_ctx* ctx, const bscf_string_opts* opts);
+/* One iteration with this context as the force provider: the geometry set
+ * from the images (if they moved), the SCF of every image with opts, the
+ * forces, then the evolution and redistribution on the device.  E, n_iter,
+ * status (as bscf_run_scf) and forces (-dE/dR [n][n_atoms][3]) are those of
+ * the images as evaluated, before they move (host, each may be NULL). */
+bscf_status bscf_string_step(bscf_ctx* ctx, const bscf_scf_opts* opts, double* E, int* n_iter,
+                             int* status, double* forces);
+/* The same update with the caller's forces [n][n_atoms][3] (host, Eh/bohr)
+ * at the current images, for other force providers and tests. */
+bscf_status bscf_string_evolve(bscf_ctx* ctx, const double* forces);
+/* Current images [n][n_atoms][3] (bohr) and their normalised arc positions
+ * s_i / L [n] (host, each may be NULL). */
+bscf_status bscf_string_state(bscf_ctx* ctx, double* x, double* arc);
+
+/* Each replica's converged density, kept on the device between steps (the
+ * paper keeps every replica's orbitals in memory for the next step's guess,
+ * Section 2).
+ * Density of instance `inst` after the last SCF (n_i x n_i), host or device;
  * the last density given to the batch (bscf_set_density, a Fock build) if
  * that came later, and zero before the first of these. */
 bscf_status bscf_get_density(bscf_ctx* ctx, int inst, double* P, int device_ptr);
@@ -230,7 +292,8 @@ bscf_status bscf_set_density(bscf_ctx* ctx, const double* P, int device_ptrs);
 /* One-electron matrices of instance `inst` (host buffers, may be NULL). */
 bscf_status bscf_get_one_electron(bscf_ctx* ctx, int inst, double* S, double* H);
 
-/* Full ERI tensor of instance `inst` (n^4 doubles, host), n <= 64; test use. */
+/* Full ERI tensor of instance `inst` (n^4 doubles, host), n <= 64; test use
+ * (the two-electron integrals behind the Fock build above). */
 bscf_status bscf_eri_tensor(bscf_ctx* ctx, int inst, double* out);
 /* Schwarz bounds of instance `inst` as an n_shell x n_shell matrix (host). */
 bscf_status bscf_schwarz(bscf_ctx* ctx, int inst, double* Q, int nsh);
@@ -243,13 +306,20 @@ bscf_status bscf_instance_info(bscf_ctx* ctx, int inst, int* nbf, int* nshell, i
 bscf_status bscf_work_counts(bscf_ctx* ctx, double* n_quartets, double* n_prim_quartets,
                              double* flops);
 
+/* Deterministic J and K (as bscf_scf_opts.deterministic) for every later
+ * Fock build of the context: bscf_build_fock, bscf_build_jk and every SCF
+ * (an SCF with opts.deterministic = 1 is deterministic either way). */
+bscf_status bscf_set_deterministic(bscf_ctx* ctx, int on);
+
 /* Kernel profiling: with on != 0 every Fock-build class kernel is bracketed by
  * HIP events on the context's stream; per-class times appear in the stats. */
 bscf_status bscf_set_profiling(bscf_ctx* ctx, int on);
 /* Zero the accumulated counters and timers reported by bscf_get_stats. */
 bscf_status bscf_reset_stats(bscf_ctx* ctx);
 
-/* Statistics as a JSON object: per quartet class the screened quartet and
+/* Timings behind the paper's figure of merit, time per step (Section 3.1,
+ * Fig. 3), split by phase and by integral class.
+ * Statistics as a JSON object: per quartet class the screened quartet and
  * primitive-quartet counts of the current work lists, the counts and
  * algorithmic FLOPs evaluated since the last reset (active instances only) and
  * the measured kernel time; totals of Fock builds, SCF iterations and phase

@@ -22,4 +22,5 @@ from .geometry import (  # noqa: F401
     maxwell_boltzmann,
     workload,
     h2_molecule,
+    zundel_path,
 )

@@ -118,6 +118,35 @@ def maxwell_boltzmann(Z: np.ndarray, n_beads: int, temperature: float, seed: int
     return v - vcm
 
 
+def zundel_path(n_images: int, r_oo_angstrom: float = 2.75):
+    """Proton transfer in H5O2+ (a synthetic reaction for the string method):
+    O1 at the origin, O2 on +x at r_oo; in the reactant the shared proton sits
+    0.99 Angstrom from O1 on the O-O axis, O1 carries two more H (H3O+
+    pyramid, O-H 0.98 Angstrom, 112 degrees from the axis) and O2 a water
+    (O-H 0.9572 Angstrom, H-O-H 104.52 degrees, bisector along +x).  The
+    product is the reactant mirrored through the plane x = r_oo / 2 with the
+    roles of the two waters exchanged, so the reaction is symmetric.
+    Returns (Z[7] atoms O1, O2, H*, H, H on O1, H, H on O2; images
+    [n_images, 7, 3] bohr) on the straight line from reactant to product."""
+    R = r_oo_angstrom
+    th = math.radians(112.0)
+    u = [(math.cos(th), s * math.sin(th) * math.sin(math.radians(60.0)),
+          -math.sin(th) * math.cos(math.radians(60.0))) for s in (1.0, -1.0)]
+    half = math.radians(104.52 / 2)
+    react = np.array([
+        [0.0, 0.0, 0.0], [R, 0.0, 0.0], [0.99, 0.0, 0.0],
+        [0.98 * u[0][0], 0.98 * u[0][1], 0.98 * u[0][2]],
+        [0.98 * u[1][0], 0.98 * u[1][1], 0.98 * u[1][2]],
+        [R + 0.9572 * math.cos(half), 0.9572 * math.sin(half), 0.0],
+        [R + 0.9572 * math.cos(half), -0.9572 * math.sin(half), 0.0]])
+    mirror = lambda p: np.array([R - p[0], p[1], p[2]])
+    partner = [1, 0, 2, 5, 6, 3, 4]
+    prod = np.array([mirror(react[partner[k]]) for k in range(7)])
+    t = np.linspace(0.0, 1.0, n_images)[:, None, None]
+    Z = np.array([8, 8, 1, 1, 1, 1, 1], np.int32)
+    return Z, (react[None] + t * (prod - react)[None]) * BOHR_PER_ANGSTROM
+
+
 def h2_molecule(r_bohr: float = 1.4):
     """H2 along z, used for the Szabo-Ostlund STO-3G worked example."""
     return np.array([1, 1], np.int32), np.array([[0.0, 0.0, 0.0], [0.0, 0.0, r_bohr]])

@@ -26,6 +26,7 @@ from .rhf import (  # noqa: F401
     schwarz,
     jk,
     jk_pairs,
+    jk_sample,
     nuclear_repulsion,
     scf,
     gradient,

@@ -485,6 +485,64 @@ long or_jk(int nsh, int nbf, const int *l, const int *atom, const int *nprim, co
   return nq;
 }
 
+/* Timing sample of or_jk: the same digestion over every stride-th quartet of
+ * the canonical screened list only, on nthreads threads (<= 0: the OpenMP
+ * default).  J and K receive that partial sum.  Returns the number of shell
+ * quartets evaluated. */
+long or_jk_sample(int nsh, int nbf, const int *l, const int *atom, const int *nprim,
+                  const int *pofs, const int *bf, const double *exps, const double *coefs,
+                  const double *xyz, const double *Q, double tau, const double *P, int stride,
+                  int nthreads, double *J, double *K) {
+  basis_t bs = {nsh, nbf, l, atom, nprim, pofs, bf, exps, coefs, xyz};
+  int *lst;
+  int nq = canonical_list(nsh, Q, tau, &lst);
+  if (stride < 1) stride = 1;
+  int ns = (nq + stride - 1) / stride;
+  for (int q = 0; q < ns; ++q)
+    for (int k = 0; k < 4; ++k) lst[4 * q + k] = lst[4 * (q * stride) + k];
+  size_t n = nbf;
+  memset(J, 0, sizeof(double) * n * n);
+  memset(K, 0, sizeof(double) * n * n);
+#ifdef _OPENMP
+  int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+  int nt = 1;
+  (void)nthreads;
+#endif
+#pragma omp parallel num_threads(nt)
+  {
+    double *Jt = calloc(n * n, sizeof(double)), *Kt = calloc(n * n, sizeof(double));
+    double blk[6 * 6 * 6 * 6];
+#pragma omp for schedule(dynamic, 16)
+    for (int q = 0; q < ns; ++q) {
+      int s4[4] = {lst[4 * q], lst[4 * q + 1], lst[4 * q + 2], lst[4 * q + 3]};
+      shell_quartet(&bs, s4[0], s4[1], s4[2], s4[3], blk, NULL);
+      int nc4[4], b0[4];
+      for (int k = 0; k < 4; ++k) { nc4[k] = ncart(l[s4[k]]); b0[k] = bf[s4[k]]; }
+      int which[8], np = distinct_perms(s4, which);
+      int e = 0;
+      for (int i = 0; i < nc4[0]; ++i)
+        for (int j = 0; j < nc4[1]; ++j)
+          for (int k = 0; k < nc4[2]; ++k)
+            for (int m = 0; m < nc4[3]; ++m, ++e) {
+              int g[4] = {b0[0] + i, b0[1] + j, b0[2] + k, b0[3] + m};
+              double v = blk[e];
+              for (int pp = 0; pp < np; ++pp) {
+                const int *pm = PERM8[which[pp]];
+                int mu = g[pm[0]], nu = g[pm[1]], la = g[pm[2]], si = g[pm[3]];
+                Jt[mu * n + nu] += v * P[la * n + si];
+                Kt[mu * n + la] += v * P[nu * n + si];
+              }
+            }
+    }
+#pragma omp critical
+    for (size_t i = 0; i < n * n; ++i) { J[i] += Jt[i]; K[i] += Kt[i]; }
+    free(Jt); free(Kt);
+  }
+  free(lst);
+  return ns;
+}
+
 /* Two-electron gradient: g[atom][3] += 1/2 sum (mn|ls)^x [P_mn P_ls - 1/2 P_ml P_ns]
  * over all ordered index quartets, with the same Schwarz rule as or_jk.
  * With amask != NULL only the atoms with amask[atom] != 0 are accumulated

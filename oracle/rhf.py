@@ -51,6 +51,7 @@ def _c():
         _lib.or_jk.restype = ctypes.c_long
         _lib.or_grad_2e.restype = ctypes.c_long
         _lib.or_grad_2e_atoms.restype = ctypes.c_long
+        _lib.or_jk_sample.restype = ctypes.c_long
     return _lib
 
 
@@ -113,6 +114,20 @@ def jk(b, P, tau: float = 1e-12, Q=None):
     J, K = np.zeros((n, n)), np.zeros((n, n))
     nq = _c().or_jk(*_bargs(b), _p(b["xyz"]), _p(np.ascontiguousarray(Q)),
                     ctypes.c_double(tau), _p(P), _p(J), _p(K))
+    return J, K, int(nq)
+
+
+def jk_sample(b, P, stride: int, nthreads: int = 0, tau: float = 1e-12, Q=None):
+    """Timing sample of ``jk``: every stride-th canonical screened quartet
+    only, on nthreads threads (0: the OpenMP default).  Returns (partial J,
+    partial K, quartets evaluated)."""
+    n = b["nbf"]
+    if Q is None:
+        Q = schwarz(b)
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    J, K = np.zeros((n, n)), np.zeros((n, n))
+    nq = _c().or_jk_sample(*_bargs(b), _p(b["xyz"]), _p(np.ascontiguousarray(Q)), ctypes.c_double(tau),
+                           _p(P), ctypes.c_int(stride), ctypes.c_int(nthreads), _p(J), _p(K))
     return J, K, int(nq)
 
 

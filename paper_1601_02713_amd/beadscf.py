@@ -60,6 +60,7 @@ _SIGS = {
     "bscf_work_counts": [_vp, _vp, _vp, _vp],
     "bscf_get_stats": [_vp, ctypes.c_char_p, _i],
     "bscf_set_profiling": [_vp, _i],
+    "bscf_set_deterministic": [_vp, _i],
     "bscf_reset_stats": [_vp],
     "bscf_boys": [_vp, _i, _i, _vp, _vp, _i],
     "bscf_guess_train": [_vp, _i, _vp],
@@ -92,7 +93,7 @@ class PimdOpts(ctypes.Structure):
 _SIGS.update({
     "bscf_pimd_default_opts": [ctypes.POINTER(PimdOpts)],
     "bscf_pimd_init": [_vp, ctypes.POINTER(PimdOpts), _vp, _vp],
-    "bscf_pimd_step": [_vp, ctypes.POINTER(ScfOpts), _vp, _vp, _vp],
+    "bscf_pimd_step": [_vp, ctypes.POINTER(ScfOpts), _vp, _vp, _vp, _vp],
     "bscf_pimd_begin": [_vp, _vp],
     "bscf_pimd_end": [_vp, _vp],
     "bscf_pimd_state": [_vp, _vp, _vp, _vp],
@@ -102,6 +103,32 @@ for _name in ("bscf_pimd_default_opts", "bscf_pimd_init", "bscf_pimd_step", "bsc
     _f = getattr(_lib, _name)
     _f.argtypes = _SIGS[_name]
     _f.restype = ctypes.c_int
+
+
+class StringOpts(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_double), ("fix_ends", ctypes.c_int)]
+
+
+_SIGS.update({
+    "bscf_string_default_opts": [ctypes.POINTER(StringOpts)],
+    "bscf_string_init": [_vp, ctypes.POINTER(StringOpts)],
+    "bscf_string_step": [_vp, ctypes.POINTER(ScfOpts), _vp, _vp, _vp, _vp],
+    "bscf_string_evolve": [_vp, _vp],
+    "bscf_string_state": [_vp, _vp, _vp],
+})
+for _name in ("bscf_string_default_opts", "bscf_string_init", "bscf_string_step",
+              "bscf_string_evolve", "bscf_string_state"):
+    _f = getattr(_lib, _name)
+    _f.argtypes = _SIGS[_name]
+    _f.restype = ctypes.c_int
+
+
+def string_default_opts(**kw) -> StringOpts:
+    o = StringOpts()
+    _chk(_lib.bscf_string_default_opts(ctypes.byref(o)))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
 
 
 def pimd_default_opts(**kw) -> PimdOpts:
@@ -250,13 +277,20 @@ class Engine:
             raise ValueError("one mass per atom of a bead")
         _chk(_lib.bscf_pimd_init(self._h, ctypes.byref(o), _ptr(m), _ptr(p) if p is not None else None))
 
-    def pimd_step(self, opts: ScfOpts | None = None, **kw):
+    def pimd_step(self, opts: ScfOpts | None = None, return_forces=False, **kw):
+        """One MD step; (E, iterations, status) of the new positions, and
+        with return_forces their forces per bead."""
         o = opts or default_opts(**kw)
         E = np.empty(self.n_inst)
         it = np.empty(self.n_inst, np.int32)
         st = np.empty(self.n_inst, np.int32)
-        _chk(_lib.bscf_pimd_step(self._h, ctypes.byref(o), _ptr(E), _ptr(it), _ptr(st)))
-        return E, it, st
+        F = np.empty((int(self.natoms.sum()), 3)) if return_forces else None
+        _chk(_lib.bscf_pimd_step(self._h, ctypes.byref(o), _ptr(E), _ptr(it), _ptr(st),
+                                 _ptr(F) if F is not None else None))
+        if not return_forces:
+            return E, it, st
+        n = int(self.natoms[0])
+        return E, it, st, [F[k * n:(k + 1) * n].copy() for k in range(self.n_inst)]
 
     def _pimd_forces(self, F):
         if F is None:
@@ -280,6 +314,36 @@ class Engine:
         x, p, obs = np.empty((P, N, 3)), np.empty((P, N, 3)), np.empty(3)
         _chk(_lib.bscf_pimd_state(self._h, _ptr(x), _ptr(p), _ptr(obs)))
         return x, p, float(obs[0]), float(obs[1]), int(obs[2])
+
+    # ---- string method (the batch's instances are its images)
+    def string_init(self, opts: StringOpts | None = None, **kw):
+        o = opts or string_default_opts(**kw)
+        _chk(_lib.bscf_string_init(self._h, ctypes.byref(o)))
+
+    def string_step(self, opts: ScfOpts | None = None, **kw):
+        """One iteration; (E, iterations, status, forces) of the images as
+        evaluated, before they moved."""
+        o = opts or default_opts(**kw)
+        E = np.empty(self.n_inst)
+        it = np.empty(self.n_inst, np.int32)
+        st = np.empty(self.n_inst, np.int32)
+        n = int(self.natoms[0])
+        F = np.empty((self.n_inst, n, 3))
+        _chk(_lib.bscf_string_step(self._h, ctypes.byref(o), _ptr(E), _ptr(it), _ptr(st), _ptr(F)))
+        return E, it, st, F
+
+    def string_evolve(self, F):
+        F = np.ascontiguousarray(np.asarray(F, float))
+        if F.size != 3 * int(self.natoms.sum()):
+            raise ValueError("forces must be [n][n_atoms][3]")
+        _chk(_lib.bscf_string_evolve(self._h, _ptr(F)))
+
+    def string_state(self):
+        """(images [n, N, 3], normalised arc positions [n])."""
+        x = np.empty((self.n_inst, int(self.natoms[0]), 3))
+        s = np.empty(self.n_inst)
+        _chk(_lib.bscf_string_state(self._h, _ptr(x), _ptr(s)))
+        return x, s
 
     def density(self, i):
         n = self.nbf[i]
@@ -314,6 +378,9 @@ class Engine:
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _chk(_lib.bscf_work_counts(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
+
+    def set_deterministic(self, on=True):
+        _chk(_lib.bscf_set_deterministic(self._h, 1 if on else 0))
 
     def set_profiling(self, on=True):
         _chk(_lib.bscf_set_profiling(self._h, 1 if on else 0))

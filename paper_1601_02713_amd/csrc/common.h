@@ -96,4 +96,25 @@ __device__ __forceinline__ bool lane_quartet(const WorkItem& it, const WorkRow* 
 
 __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 
+// Order-independent accumulation for the deterministic Fock build.  A value
+// is held as a signed 128-bit fixed-point number with 80 fractional bits in
+// two 64-bit words, p[0] = low word, p[1] = high word (two's complement).
+// fx_add converts v exactly (to 2^-80) and adds it with two integer atomics,
+// the carry of the low word going into the high one; integer addition is
+// associative, so the total does not depend on the order of the adds, and it
+// is the exact sum of the contributions.  |values| must stay below 2^47.
+__device__ __forceinline__ void fx_add(unsigned long long* p, double v) {
+  const double x = v * 0x1p16;
+  const double h = floor(x);
+  const unsigned long long lo = (unsigned long long)((x - h) * 0x1p64);
+  const long long hi = (long long)h;
+  const unsigned long long old = atomicAdd(p, lo);
+  const long long carry = (old + lo < old) ? 1 : 0;
+  if (hi + carry != 0) atomicAdd(p + 1, (unsigned long long)(hi + carry));
+}
+
+__device__ __forceinline__ double fx_value(const unsigned long long* p) {
+  return (double)(long long)p[1] * 0x1p-16 + (double)p[0] * 0x1p-80;
+}
+
 }  // namespace bscf

@@ -259,7 +259,12 @@ __global__ __launch_bounds__(CP::NT) void coop_fock_kernel(FockArgs a) {
       f = fk;
     }
     const int2 rc = block_rc<NA, NB, NC, ND>(t, m0, n0, l0, s0);
-    atomicAdd(t < OAC ? &J[rc.x * n + rc.y] : &K[rc.x * n + rc.y], f * acc);
+    if (a.Kfx) {
+      const long long e = mo + (long long)rc.x * n + rc.y;
+      fx_add(t < OAC ? &a.Jfx[2 * e] : &a.Kfx[2 * e], f * acc);
+    } else {
+      atomicAdd(t < OAC ? &J[rc.x * n + rc.y] : &K[rc.x * n + rc.y], f * acc);
+    }
   }
 }
 

@@ -38,6 +38,7 @@
 #include "grad.h"
 #include "mlp.h"
 #include "pimd.h"
+#include "string_method.h"
 
 using namespace bscf;
 
@@ -372,6 +373,9 @@ struct bscf_ctx {
     std::vector<double> inst_quart, inst_primq;  // per instance
     // evaluated so far (active instances only) and measured kernel time
     double done_quart = 0, done_primq = 0, kernel_ms = 0, grad_ms = 0;
+    // Schwarz-screened quartets (at the build's cutoff) of the instances each
+    // build covered, whether a full or an incremental build evaluated them
+    double screened_quart = 0;
     long launches = 0, grad_launches = 0;
   };
   ClassWork work[kNumQuartetClasses];
@@ -379,6 +383,11 @@ struct bscf_ctx {
   DevBuf<int> d_kets;
   // ket-list-position buffers: P gathered per ket pair and ket-side J
   DevBuf<double> d_Pk, d_Jk;
+  // deterministic builds: J, K and Jk in fixed point (two words per element),
+  // allocated on first use; det is the setting of bscf_set_deterministic,
+  // det_now that of the build in progress
+  DevBuf<unsigned long long> Jfx, Kfx, Jkfx;
+  bool det = false, det_now = false;
   // ket primitive pairs copied into ket-list order: within a block of
   // positions sharing a primitive count, primitive j of every position is
   // adjacent to that of the next position (coalesced lane loads)
@@ -463,6 +472,16 @@ struct bscf_ctx {
     bool have_force = false;   // d_grad holds the gradient at the current positions
     DevBuf<double> x, p, C, w, c1, c2, mass, sig, F;
   } md;
+
+  // string of images over the batch's instances; positions on the device
+  struct Str {
+    bool on = false;
+    int n = 0, N = 0;
+    bscf_string_opts o{};
+    bool synced = false;   // the context's geometry is the images' positions
+    long long iters = 0;
+    DevBuf<double> x, xt, F, arc;
+  } str;
 
   BatchInfo batch(bool masked) const {
     BatchInfo b;
@@ -1299,6 +1318,7 @@ FockArgs fock_args(bscf_ctx* c, double* J, double* K, const int* active) {
   a.Q = c->d_Q.p;
   a.dpmax = nullptr;
   a.tau = 0.0;
+  a.Jfx = a.Kfx = a.Jkfx = nullptr;
   return a;
 }
 
@@ -1412,6 +1432,21 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
   const double t0 = now_ms();
   FockArgs a = fock_args(c, c->J.p, c->K.p, masked ? c->d_active.p : c->d_all_active.p);
   const BatchInfo bset = c->batch(masked);
+  const bool det = c->det_now;
+  const long long njk = (long long)c->max_ncd * (long long)c->kets.size();
+  if (det) {
+    if (c->Jfx.n < 2 * (size_t)c->mtot || c->Kfx.n < 2 * (size_t)c->mtot ||
+        c->Jkfx.n < 2 * (size_t)std::max(njk, 1LL)) {
+      c->Jfx.resize(2 * (size_t)c->mtot);
+      c->Kfx.resize(2 * (size_t)c->mtot);
+      c->Jkfx.resize(2 * (size_t)std::max(njk, 1LL));
+      launch_fill_u64((long long)c->Jkfx.n, c->Jkfx.p, c->stream);
+      incremental = false;   // fresh accumulators: this build starts from zero
+    }
+    a.Jfx = c->Jfx.p;
+    a.Kfx = c->Kfx.p;
+    a.Jkfx = c->Jkfx.p;
+  }
   if (incremental) {
     launch_density_change(bset, c->max_n, c->P.p, c->Pprev.p, c->dP.p, c->d_dpmax.p, c->stream);
     // kept kets per row for the lane kernels, and the kept work of every
@@ -1447,6 +1482,9 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
     a.dpmax = c->d_dpmax.p;
     a.tau = tau;
     c->inc_builds++;
+  } else if (det) {
+    launch_fill_u64(2 * c->mtot, c->Jfx.p, c->stream);
+    launch_fill_u64(2 * c->mtot, c->Kfx.p, c->stream);
   } else {
     launch_fill(c->J.p, c->mtot, 0.0, c->stream);
     launch_fill(c->K.p, c->mtot, 0.0, c->stream);
@@ -1498,6 +1536,8 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
         launch(c->private_bytes[q][k], run);
       });
     }
+    for (int i = 0; i < c->ninst; ++i)
+      if (!masked || c->h_active[i]) W.screened_quart += W.inst_quart[i];
     if (!incremental)   // (an incremental build counts its kept work on the device)
       for (int i = 0; i < c->ninst; ++i)
         if (!masked || c->h_active[i]) {
@@ -1511,7 +1551,13 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
     HIPCHK(hipEventRecord(c->ev_join[k - 1], ring[k]));
     HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join[k - 1], 0));
   }
-  launch_jk_finalize(kp, c->max_ncd, c->d_Jk.p, c->J.p, c->stream);
+  if (det) {
+    launch_jk_finalize_fx(kp, c->max_ncd, c->Jkfx.p, c->Jfx.p, c->stream);
+    launch_fx_to_double(c->mtot, c->Jfx.p, c->J.p, c->stream);
+    launch_fx_to_double(c->mtot, c->Kfx.p, c->K.p, c->stream);
+  } else {
+    launch_jk_finalize(kp, c->max_ncd, c->d_Jk.p, c->J.p, c->stream);
+  }
   HIPCHK(hipGetLastError());
   if (pbuild >= 0) prof_end(c, pbuild, c->stream);
   if (c->prof_pending.size() > 8192) prof_collect(c);
@@ -1830,6 +1876,7 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->fock_tuned[0] = c->fock_tuned[1] = c->grad_tuned = false;
     c->guess.reset_batch(c->ninst);
     c->md.on = c->md.synced = c->md.have_force = false;
+    c->str.on = c->str.synced = false;
     sync(c);
     undo.done = true;
   });
@@ -1847,6 +1894,7 @@ bscf_status bscf_set_geometries(bscf_ctx* c, const double* xyz) {
     // previous densities paired with the new coordinates
     c->have_geom = c->have_scf = false;
     c->md.synced = c->md.have_force = false;
+    c->str.synced = false;
     HIPCHK(hipSetDevice(c->device));
     join_work(c);
     c->work_tau = c->host_tau = -1.0;
@@ -1932,6 +1980,7 @@ bscf_status bscf_build_jk(bscf_ctx* c, const double* P, double* J, double* K, do
     const auto kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     c->have_scf = false;   // the SCF density is replaced: forces need a new SCF
     HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double), kind, c->stream));
+    c->det_now = c->det;
     fock_build(c, tau, precision, false);
     // symmetrised J, K
     BatchInfo b = c->batch(false);
@@ -1956,6 +2005,7 @@ bscf_status bscf_build_fock(bscf_ctx* c, const double* P, double* F, double* E, 
     const auto kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     c->have_scf = false;   // the SCF density is replaced: forces need a new SCF
     HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double), kind, c->stream));
+    c->det_now = c->det;
     fock_build(c, tau, precision, false);
     const auto back = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     HIPCHK(hipMemcpyAsync(F, c->F.p, c->mtot * sizeof(double), back, c->stream));
@@ -2074,6 +2124,8 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     need(o.fp32_split_tol > 0.0, BSCF_E_INVALID, "fp32_split_tol must be positive");
     need(o.density == BSCF_DENSITY_SP2 || o.density == BSCF_DENSITY_EIG, BSCF_E_INVALID,
          "density must be BSCF_DENSITY_SP2 or BSCF_DENSITY_EIG");
+    need(o.deterministic == 0 || o.deterministic == 1, BSCF_E_INVALID, "deterministic must be 0 or 1");
+    c->det_now = o.deterministic == 1 || c->det;
     c->split_tol = o.fp32_split_tol;
     c->have_scf = false;   // set again once every instance has its density
     const double t0 = now_ms();
@@ -2482,7 +2534,8 @@ void check_status(bscf_status rc) {
 }
 
 // the context's geometry from the integrator's positions, then SCF and forces
-void pimd_forces_here(bscf_ctx* c, const bscf_scf_opts* o, double* E, int* it, int* st) {
+void pimd_forces_here(bscf_ctx* c, const bscf_scf_opts* o, double* E, int* it, int* st,
+                      double* Fout = nullptr) {
   auto& m = c->md;
   std::vector<double> x((size_t)m.P * 3 * m.N), F(x.size());
   HIPCHK(hipMemcpyAsync(x.data(), m.x.p, x.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -2491,6 +2544,7 @@ void pimd_forces_here(bscf_ctx* c, const bscf_scf_opts* o, double* E, int* it, i
   m.synced = true;
   check_status(bscf_run_scf(c, o, E, it, st));
   forces_impl(c, F.data());
+  if (Fout) std::copy(F.begin(), F.end(), Fout);
 }
 }  // namespace
 
@@ -2600,14 +2654,14 @@ bscf_status bscf_pimd_end(bscf_ctx* c, const double* forces) {
 }
 
 bscf_status bscf_pimd_step(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int* n_iter,
-                           int* status) {
+                           int* status, double* forces) {
   return guard([&] {
     need(c != nullptr, BSCF_E_INVALID, "NULL context");
     need(c->md.on, BSCF_E_STATE, "no ring polymer: call bscf_pimd_init");
     HIPCHK(hipSetDevice(c->device));
     if (!c->md.have_force) pimd_forces_here(c, opts, nullptr, nullptr, nullptr);
     pimd_begin_impl(c, nullptr);
-    pimd_forces_here(c, opts, E, n_iter, status);
+    pimd_forces_here(c, opts, E, n_iter, status, forces);
     pimd_end_impl(c, nullptr);
     sync(c);
   });
@@ -2644,6 +2698,123 @@ bscf_status bscf_pimd_state(bscf_ctx* c, double* x, double* p, double* obs) {
       obs[1] = sp;
       obs[2] = (double)m.step;
     }
+  });
+}
+
+// ------------------------------------------------------------ string method
+
+namespace {
+// all instances copies of instance 0's composition
+void require_copies(bscf_ctx* c, const char* what) {
+  const int N = c->natoms[0];
+  for (int i = 0; i < c->ninst; ++i) {
+    need(c->natoms[i] == N, BSCF_E_INVALID, what);
+    for (int a = 0; a < N; ++a)
+      need(c->Zs[c->atom_off[i] + a] == c->Zs[a], BSCF_E_INVALID, what);
+  }
+}
+
+// evolve with forces (caller's host array, or sign -1 on the context's
+// gradient), then reparametrise into the image buffer
+void string_update(bscf_ctx* c, const double* F, double sign) {
+  auto& g = c->str;
+  const int ncol = 3 * g.N;
+  launch_string_evolve(g.n, ncol, g.x.p, F, sign, g.o.step, g.o.fix_ends, c->stream);
+  launch_string_reparam(g.n, ncol, g.x.p, g.xt.p, g.arc.p, c->stream);
+  HIPCHK(hipGetLastError());
+  std::swap(g.x.p, g.xt.p);
+  g.synced = false;
+  ++g.iters;
+}
+}  // namespace
+
+bscf_status bscf_string_default_opts(bscf_string_opts* o) {
+  if (!o) return BSCF_E_INVALID;
+  o->step = 0.5;
+  o->fix_ends = 0;
+  return BSCF_OK;
+}
+
+bscf_status bscf_string_init(bscf_ctx* c, const bscf_string_opts* opts) {
+  return guard([&] {
+    need(c && opts, BSCF_E_INVALID, "NULL argument");
+    require_geom(c);
+    need(std::isfinite(opts->step) && opts->step > 0.0, BSCF_E_INVALID, "step must be positive");
+    need(opts->fix_ends == 0 || opts->fix_ends == 1, BSCF_E_INVALID, "fix_ends must be 0 or 1");
+    need(c->ninst >= 2, BSCF_E_INVALID, "a string needs at least two images");
+    need(c->ninst <= kStringMaxImages, BSCF_E_UNSUPPORTED,
+         "at most " + std::to_string(kStringMaxImages) + " images");
+    require_copies(c, "images must be copies of one system");
+    HIPCHK(hipSetDevice(c->device));
+    auto& g = c->str;
+    g.on = false;
+    const size_t n = (size_t)c->ninst * 3 * c->natoms[0];
+    g.x.upload(c->xyz, c->stream);
+    g.xt.resize(n);
+    g.F.resize(n);
+    g.arc.resize(c->ninst);
+    sync(c);
+    g.n = c->ninst;
+    g.N = c->natoms[0];
+    g.o = *opts;
+    g.iters = 0;
+    g.synced = true;
+    g.on = true;
+  });
+}
+
+bscf_status bscf_string_step(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int* n_iter,
+                             int* status, double* forces) {
+  return guard([&] {
+    need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    need(c->str.on, BSCF_E_STATE, "no string: call bscf_string_init");
+    HIPCHK(hipSetDevice(c->device));
+    auto& g = c->str;
+    std::vector<double> x((size_t)g.n * 3 * g.N);
+    if (!g.synced) {
+      HIPCHK(hipMemcpyAsync(x.data(), g.x.p, x.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+      sync(c);
+      check_status(bscf_set_geometries(c, x.data()));
+      g.synced = true;
+    }
+    check_status(bscf_run_scf(c, opts, E, n_iter, status));
+    forces_impl(c, x.data());
+    if (forces) std::copy(x.begin(), x.end(), forces);
+    string_update(c, c->d_grad.p, -1.0);
+    sync(c);
+  });
+}
+
+bscf_status bscf_string_evolve(bscf_ctx* c, const double* forces) {
+  return guard([&] {
+    need(c && forces, BSCF_E_INVALID, "NULL argument");
+    need(c->str.on, BSCF_E_STATE, "no string: call bscf_string_init");
+    HIPCHK(hipSetDevice(c->device));
+    auto& g = c->str;
+    const size_t n = (size_t)g.n * 3 * g.N;
+    for (size_t k = 0; k < n; ++k) need(std::isfinite(forces[k]), BSCF_E_INVALID, "non-finite force");
+    HIPCHK(hipMemcpyAsync(g.F.p, forces, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    string_update(c, g.F.p, 1.0);
+    sync(c);
+  });
+}
+
+bscf_status bscf_string_state(bscf_ctx* c, double* x, double* arc) {
+  return guard([&] {
+    need(c != nullptr, BSCF_E_INVALID, "NULL context");
+    need(c->str.on, BSCF_E_STATE, "no string: call bscf_string_init");
+    HIPCHK(hipSetDevice(c->device));
+    auto& g = c->str;
+    if (x)
+      HIPCHK(hipMemcpyAsync(x, g.x.p, (size_t)g.n * 3 * g.N * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+    if (arc) {   // the arc positions of the current images (the redistribution is discarded)
+      launch_string_reparam(g.n, 3 * g.N, g.x.p, g.xt.p, g.arc.p, c->stream);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(arc, g.arc.p, g.n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    sync(c);
   });
 }
 
@@ -2741,18 +2912,22 @@ bscf_status bscf_work_counts(bscf_ctx* c, double* nq, double* npq, double* flops
     for (int q = 0; q < kNumQuartetClasses; ++q) {
       a += c->work[q].nquart;
       b += c->work[q].nprimq;
-      const int L = qc[q].la + qc[q].lb + qc[q].lc + qc[q].ld;
-      (void)L;
       const int nout = ncart(qc[q].la) * ncart(qc[q].lb) * ncart(qc[q].lc) * ncart(qc[q].ld);
-      // per primitive quartet: VRR plus setup and Boys (60 + 4L FLOP);
-      // per contracted quartet: HRR + digestion (6 FMAs = 12 FLOP per integral)
-      const double boys = 60.0 + 4.0 * (qc[q].la + qc[q].lb + qc[q].lc + qc[q].ld);
-      f += c->work[q].nprimq * (qc[q].vrr_flops + boys) +
-           c->work[q].nquart * (qc[q].hrr_flops + 12.0 * nout);
+      // per primitive quartet: setup, Boys and VRR as counted from the code by
+      // the generator; per contracted quartet: HRR + digestion (6 FMAs = 12
+      // FLOP per integral)
+      f += c->work[q].nprimq * qc[q].prim_flops + c->work[q].nquart * (qc[q].hrr_flops + 12.0 * nout);
     }
     if (nq) *nq = a;
     if (npq) *npq = b;
     if (flops) *flops = f;
+  });
+}
+
+bscf_status bscf_set_deterministic(bscf_ctx* c, int on) {
+  return guard([&] {
+    need(c != nullptr && (on == 0 || on == 1), BSCF_E_INVALID, "bad arguments");
+    c->det = on == 1;
   });
 }
 
@@ -2771,6 +2946,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
     collect_kept(c);
     for (auto& W : c->work) {
       W.done_quart = W.done_primq = W.kernel_ms = W.grad_ms = W.done_quart32 = 0;
+      W.screened_quart = 0;
       W.launches = W.grad_launches = 0;
     }
     c->t_fock_ms = c->t_scf_ms = c->t_grad_ms = c->t_setup_ms = c->t_fock_gpu_ms = c->t_work_ms = 0;
@@ -2805,14 +2981,14 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
     for (int q = 0; q < kNumQuartetClasses; ++q) {
       const auto& W = c->work[q];
       const double nout = ncart(qc[q].la) * ncart(qc[q].lb) * ncart(qc[q].lc) * ncart(qc[q].ld);
-      const double boys = 60.0 + 4.0 * (qc[q].la + qc[q].lb + qc[q].lc + qc[q].ld);
-      const double flops = W.done_primq * (qc[q].vrr_flops + boys) +
-                           W.done_quart * (qc[q].hrr_flops + 12.0 * nout);
+      const double flops = W.done_primq * qc[q].prim_flops + W.done_quart * (qc[q].hrr_flops + 12.0 * nout);
       s << (q ? ", " : "") << "\"" << qc[q].la << qc[q].lb << qc[q].lc << qc[q].ld
         << "\": {\"quartets\": " << W.nquart << ", \"prim_quartets\": " << W.nprimq
         << ", \"quartets_fp32_list\": " << W.nquart32 << ", \"done_quartets_fp32\": " << W.done_quart32
         << ", \"items\": " << W.items.size() << ", \"done_quartets\": " << W.done_quart
         << ", \"done_prim_quartets\": " << W.done_primq << ", \"done_flops\": " << flops
+        << ", \"screened_quartets_built\": " << W.screened_quart
+        << ", \"prim_flops\": " << qc[q].prim_flops << ", \"hrr_flops\": " << qc[q].hrr_flops
         << ", \"kernel_ms\": " << W.kernel_ms << ", \"launches\": " << W.launches
         << ", \"grad_ms\": " << W.grad_ms << ", \"grad_launches\": " << W.grad_launches
         << ", \"private_bytes\": [" << c->private_bytes[q][0] << ", " << c->private_bytes[q][1]

@@ -66,6 +66,12 @@ struct FockArgs {
   const double* Q;         // Schwarz bound per shell pair
   const double* dpmax;     // per instance max |dP|
   double tau;
+  // Deterministic build (Kfx != nullptr): J, K and Jk accumulate in the
+  // fixed-point words of fx_add (two per element, same element order) instead
+  // of FP64 atomics on J, K and Jk.
+  unsigned long long* Jfx;
+  unsigned long long* Kfx;
+  unsigned long long* Jkfx;
 };
 
 struct SchwarzArgs {
@@ -372,8 +378,11 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
 #pragma unroll
       for (int k = 0; k < NC; ++k)
 #pragma unroll
-        for (int l = 0; l < ND; ++l)
-          atomicAdd(&a.Jk[(long long)(k * ND + l) * a.nk_total + pos], fj * jket[k][l]);
+        for (int l = 0; l < ND; ++l) {
+          const long long e = (long long)(k * ND + l) * a.nk_total + pos;
+          if (a.Jkfx) fx_add(&a.Jkfx[2 * e], fj * jket[k][l]);
+          else atomicAdd(&a.Jk[e], fj * jket[k][l]);
+        }
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
 #pragma unroll
@@ -398,22 +407,26 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
     pass(R(0), 0);
   }
   __syncthreads();
-  double* K = a.K + mo;
   for (int t = lane; t < NR * n; t += kWave) {
     const double x = Kacc[t];
     if (x != 0.0) {
       const int r = t / n, col = t - r * n;
       const int bf = r < NA ? m0 + r : n0 + (r - NA);
-      atomicAdd(&K[(long long)bf * n + col], x);
+      const long long e = mo + (long long)bf * n + col;
+      if (a.Kfx) fx_add(&a.Kfx[2 * e], x);
+      else atomicAdd(&a.K[e], x);
     }
   }
-  double* J = a.J + mo;
 #pragma unroll
   for (int i = 0; i < NA; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const double x = wave_sum(jab[i][j]);
-      if (lane == 0) atomicAdd(&J[(m0 + i) * n + n0 + j], x);
+      const long long e = mo + (long long)(m0 + i) * n + n0 + j;
+      if (lane == 0) {
+        if (a.Jfx) fx_add(&a.Jfx[2 * e], x);
+        else atomicAdd(&a.J[e], x);
+      }
     }
 }
 

@@ -495,6 +495,31 @@ def coop_tu(la, lb, lc, ld):
     return "\n".join(lines), pe, pg
 
 
+def prim_flops(L):
+    """FLOPs of one primitive quartet outside the VRR, counted from the lane
+    kernel's primitive loop (eri_block_body in fock_kernel.h) and from
+    boys_f64 (boys.h); an FMA counts two, a reciprocal square root one.
+
+    Setup (every class):
+      p + q 1; rsqrt(p + q) 1; 1/(p + q) as its square 1; rho = p q/(p + q) 2;
+      PQ 3; T = rho |PQ|^2 6; prefactor C_ab C_cd rsqrt(p + q) 2      -> 16
+    Setup of the VRR arguments (L > 0):
+      q/(p + q), p/(p + q) 2; -q/(p + q) PQ and p/(p + q) PQ 6;
+      1/(2(p + q)) 1; the two 1/(2p) q/(p + q) factors 2                -> 11
+    Boys function below T = 40 (the branch every integral of these systems
+    takes, T being far smaller):
+      grid index T/0.1 1; d = T - 0.1 k 2; 8-term Taylor of F_L, 7 x (mul +
+      FMA) 21; F_L scaled 1                                             -> 25
+      L > 0: exp(-T) from the 9-term Taylor of exp, 8 x (mul + FMA), times
+      the table's exp(-T_k) 25; 2T 1; per m < L FMA, 1/(2m+1) and the
+      scaling 4                                                         -> 26 + 4L
+    L = 0 adds acc += F_0 (1) and runs no VRR."""
+    f = 16 + 25
+    if L == 0:
+        return f + 1
+    return f + 11 + 26 + 4 * L
+
+
 def main(outdir):
     """Write the per-class headers and translation units, classes.h and
     eri_flops.json."""
@@ -509,7 +534,9 @@ def main(outdir):
         fn_h, nacc_h, fl_h, code_h = gen_hrr(la, lb, lc, ld)
         assert nacc == nacc_h
         nout = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
-        table[tag] = dict(vrr_flops_per_prim=fl_v, hrr_flops=fl_h, nacc=nacc, ncart=nout)
+        # per primitive quartet in all: setup, Boys and (L > 0) the VRR
+        table[tag] = dict(vrr_flops_per_prim=fl_v, hrr_flops=fl_h, nacc=nacc, ncart=nout,
+                          prim_flops=prim_flops(L) + (fl_v if L > 0 else 0))
         if L <= LANE_E_MAX:
             struct = f"""struct Cls{tag} {{
   static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld};
@@ -676,7 +703,8 @@ def main(outdir):
             "  void (*grad)(const GradArgs&, hipStream_t);",
             "  void (*coop_grad)(const GradArgs&, hipStream_t);",
             "  void (*tensor)(const TensorArgs&, hipStream_t);",
-            "  double vrr_flops, hrr_flops, grad_vrr_flops, grad_con_flops;",
+            "  // FLOPs per primitive quartet (setup, Boys, VRR) and per contracted quartet (HRR)",
+            "  double prim_flops, hrr_flops, grad_vrr_flops, grad_con_flops;",
             "  int (*fock_private_bytes)(int);",
             "  int (*grad_private_bytes)();",
             "  int (*coop_private_bytes)(int);",
@@ -691,7 +719,7 @@ def main(outdir):
         reg.append(f"    {{{la}, {lb}, {lc}, {ld}, {f'launch_fock_{tag}' if le else 'nullptr'}, "
                    f"launch_coop_fock_{tag}, {f'launch_grad_{tag}' if lg else 'nullptr'}, "
                    f"launch_coop_grad_{tag}, {f'launch_tensor_{tag}' if le else f'launch_coop_tensor_{tag}'}, "
-                   f"{t['vrr_flops_per_prim']}.0, {t['hrr_flops']}.0, {t['grad_vrr_flops_per_prim']}.0, "
+                   f"{t['prim_flops']}.0, {t['hrr_flops']}.0, {t['grad_vrr_flops_per_prim']}.0, "
                    f"{t['grad_contract_flops']}.0, {f'fock_private_bytes_{tag}' if le else 'nullptr'}, "
                    f"{f'grad_private_bytes_{tag}' if lg else 'nullptr'}, coop_private_bytes_{tag}}},")
     reg += ["  };", "  return t;", "}"]

@@ -5,6 +5,8 @@
 // each J element at most once and needs no atomics.
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace bscf {
 namespace {
 
@@ -45,6 +47,37 @@ __global__ __launch_bounds__(256) void jk_finalize_kernel(KetPosArgs a, int max_
   Jk[t] = 0.0;
 }
 
+// deterministic builds: the same fold in fixed point (Jfx += Jkfx with the
+// carry of the low word, then Jkfx cleared)
+__global__ __launch_bounds__(256) void jk_finalize_fx_kernel(KetPosArgs a, int max_ncd,
+                                                             unsigned long long* __restrict__ Jk,
+                                                             unsigned long long* __restrict__ J) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)max_ncd * a.nk_total) return;
+  const int e = (int)(t / a.nk_total), pos = (int)(t - (long long)e * a.nk_total);
+  const PosElem x = pos_elem(a, e, pos);
+  if (!x.ok) return;
+  const unsigned long long lo = J[2 * x.idx], add = Jk[2 * t];
+  J[2 * x.idx] = lo + add;
+  J[2 * x.idx + 1] += Jk[2 * t + 1] + (lo + add < lo ? 1ull : 0ull);
+  Jk[2 * t] = 0ull;
+  Jk[2 * t + 1] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void fx_to_double_kernel(long long n,
+                                                           const unsigned long long* __restrict__ fx,
+                                                           double* __restrict__ out) {
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (long long)gridDim.x * blockDim.x)
+    out[t] = fx_value(fx + 2 * t);
+}
+
+__global__ __launch_bounds__(256) void fill_u64_kernel(long long n, unsigned long long* __restrict__ p) {
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (long long)gridDim.x * blockDim.x)
+    p[t] = 0ull;
+}
+
 __global__ __launch_bounds__(256) void gather_prims_kernel(int n, const int* __restrict__ map,
                                                            const PrimPair* __restrict__ src,
                                                            PrimPair* __restrict__ dst) {
@@ -65,6 +98,26 @@ void launch_gather_pk(const KetPosArgs& a, int max_ncd, const double* P, double*
   if (n == 0) return;
   hipLaunchKernelGGL(gather_pk_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a,
                      max_ncd, P, Pk);
+}
+
+void launch_jk_finalize_fx(const KetPosArgs& a, int max_ncd, unsigned long long* Jk,
+                           unsigned long long* J, hipStream_t s) {
+  const long long n = (long long)max_ncd * a.nk_total;
+  if (n == 0) return;
+  hipLaunchKernelGGL(jk_finalize_fx_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a,
+                     max_ncd, Jk, J);
+}
+
+void launch_fx_to_double(long long n, const unsigned long long* fx, double* out, hipStream_t s) {
+  if (n == 0) return;
+  const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fx_to_double_kernel, dim3((unsigned)blocks), dim3(256), 0, s, n, fx, out);
+}
+
+void launch_fill_u64(long long n, unsigned long long* p, hipStream_t s) {
+  if (n == 0) return;
+  const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, n, p);
 }
 
 void launch_jk_finalize(const KetPosArgs& a, int max_ncd, double* Jk, double* J, hipStream_t s) {

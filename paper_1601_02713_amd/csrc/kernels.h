@@ -101,6 +101,12 @@ void launch_gather_pk(const KetPosArgs& a, int max_ncd, const double* P, double*
                       hipStream_t s);
 // J(c_k, d_l) += Jk[e * nk_total + pos], then Jk = 0 (ready for the next build)
 void launch_jk_finalize(const KetPosArgs& a, int max_ncd, double* Jk, double* J, hipStream_t s);
+// Deterministic builds: the fold in the fixed-point words of fx_add (common.h),
+// the conversion of n fixed-point values to FP64 and a clear of n words.
+void launch_jk_finalize_fx(const KetPosArgs& a, int max_ncd, unsigned long long* Jk,
+                           unsigned long long* J, hipStream_t s);
+void launch_fx_to_double(long long n, const unsigned long long* fx, double* out, hipStream_t s);
+void launch_fill_u64(long long n, unsigned long long* p, hipStream_t s);
 
 // ---- dense per-instance helpers (scf.hip) ----
 struct BatchInfo {

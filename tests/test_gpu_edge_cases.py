@@ -145,3 +145,24 @@ def test_batches_with_fewer_matrix_elements_than_force_components(eng, sto3g, z,
     assert abs(E[0] - r["E"]) < 1e-9
     assert np.abs(F + g).max() < 1e-8, (F, -g)
     assert np.abs(F.sum(axis=0)).max() < 1e-10
+
+
+def test_lane_kernels_over_the_scratch_bound_never_run(eng, b631gs):
+    """Every class whose lane kernel needs more private memory per lane than
+    the engine's bound (4096 bytes) runs cooperatively, for the Fock build in
+    both precisions and for the gradient."""
+    inst = inputs.workload("w3")["instances"]
+    _setup(eng, b631gs, inst)
+    eng.run_scf(e_tol=1e-9, comm_tol=1e-7)
+    eng.forces()
+    eng.run_scf(e_tol=1e-9, comm_tol=1e-7, precision=1)
+    st = eng.stats()["classes"]
+    over = 0
+    for tag, v in st.items():
+        if not v["items"]:
+            continue
+        for k in range(3):
+            if v["private_bytes"][k] > 4096:
+                over += 1
+                assert v["variant"][k] == 1, (tag, k, v["private_bytes"], v["variant"])
+    assert over >= 1   # (the (pp|pp) lane gradient is over the bound)

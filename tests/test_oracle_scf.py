@@ -156,3 +156,16 @@ def test_gradient_of_selected_atoms_equals_full_gradient_rows(b631gs):
         assert np.abs(ga[atoms] - g[atoms]).max() < 1e-11, atoms
         others = [k for k in range(len(z)) if k not in atoms]
         assert np.isnan(ga[others]).all()
+
+
+def test_jk_sample_with_stride_one_is_the_full_build(b631gs):
+    """The timing sample at stride 1 is the canonical build itself; at
+    stride s it evaluates ceil(n / s) quartets."""
+    z, x = inputs.workload("w2")["instances"][0]
+    b = oracle.build_basis(b631gs, z, x)
+    P = _rand_density(b["nbf"], np.random.default_rng(29))
+    J, K, nq = oracle.jk(b, P)
+    Js, Ks, ns = oracle.jk_sample(b, P, 1, 2)
+    assert ns == nq and np.abs(Js - J).max() < 1e-13 and np.abs(Ks - K).max() < 1e-13
+    _, _, n7 = oracle.jk_sample(b, P, 7, 1)
+    assert n7 == (nq + 6) // 7
