@@ -46,7 +46,15 @@ namespace {
 
 // quartets per lane-kernel unit: the K rows of its bra are flushed once per
 // unit, so longer units amortise the flush, shorter ones spread the work
-constexpr int kUnitQuartets = 256;
+// Quartets per lane-kernel unit: 256, doubled for every doubling of the
+// batch's largest basis beyond 152 functions (to 2048 at most), so that the
+// unit's fixed cost, loading and flushing (n_a + n_b) rows of n elements, stays
+// a like share of its integral work as n grows.
+int unit_quartets(int max_n) {
+  int u = 256;
+  for (int n = 304; n <= max_n && u < 2048; n *= 2) u *= 2;
+  return u;
+}
 
 // The HIP runtime backs a kernel's private segment with scratch reserved per
 // hardware queue for full occupancy (bytes per lane x 64 lanes x 32 waves x
@@ -302,6 +310,8 @@ struct bscf_ctx {
   // fock_variant[precision][class]: 0 lane (MIXED: the mixed form), 1 cooperative,
   // 2 (MIXED only) the FP64 lane form; tune_ms holds their times
   float tune_ms[2][kNumQuartetClasses][3] = {};
+  // threads per lane-kernel unit, [precision mode][class][variant] (see tune_ms)
+  int unit_threads[2][kNumQuartetClasses][3] = {};
   float tune_grad_ms[kNumQuartetClasses][2] = {};
   float tune_grad1e_ms[kNumPairClasses] = {};   // one-electron gradient kernels alone
   // per-lane private (scratch) bytes of every class kernel: [class][fp64, mixed, grad].
@@ -986,8 +996,9 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
   auto build_part = [&](int q, int i) {
     Part& P = parts[(size_t)q * ni + i];
     const int X = pclass(qc[q].la, qc[q].lb), Y = pclass(qc[q].lc, qc[q].ld);
-    // units of one bra over its unit rows [r0, r1): up to kUnitQuartets
+    // units of one bra over its unit rows [r0, r1): up to unit_quartets()
     // consecutive quartets across its rows (all ket primitive counts)
+    const int kUnitQuartets = unit_quartets(c->max_n);
     auto add_units = [&](int r0, const std::vector<int>& kn, int bnprim) {
       auto& rows = P.urows;
       const int r1 = (int)rows.size();
@@ -1319,6 +1330,7 @@ FockArgs fock_args(bscf_ctx* c, double* J, double* K, const int* active) {
   a.dpmax = nullptr;
   a.tau = 0.0;
   a.Jfx = a.Kfx = a.Jkfx = nullptr;
+  a.unit_threads = 64;
   return a;
 }
 
@@ -1367,6 +1379,11 @@ KetPosArgs ketpos_args(bscf_ctx* c) {
 // kernel needs more LDS than one workgroup may hold runs cooperatively.
 void autotune_fock(bscf_ctx* c, int pcol) {
   const char* env = getenv("BSCF_VARIANT");
+  // BSCF_UNIT_THREADS=64|128|256 fixes the threads of the lane units
+  const char* env_u = getenv("BSCF_UNIT_THREADS");
+  const int env_nt = env_u ? atoi(env_u) : 0;
+  need(env_nt == 0 || env_nt == 64 || env_nt == 128 || env_nt == 256, BSCF_E_INVALID,
+       "BSCF_UNIT_THREADS must be 64, 128 or 256");
   const QuartetClass* qc = quartet_classes();
   FockArgs a = fock_args(c, c->tmp1.p, c->tmp2.p, c->d_all_active.p);
   const KetPosArgs kp = ketpos_args(c);
@@ -1386,16 +1403,32 @@ void autotune_fock(bscf_ctx* c, int pcol) {
     // MIXED mode 2 the FP64 lane form (FP32 integrals do not pay everywhere);
     // each timed alone (second of two runs), the chosen one at least, since
     // the build's stream schedule uses its time
+    // lane forms also try units of one, two and four wavefronts (they share
+    // the unit's LDS rows) and keep the fastest
     auto time_variant = [&](int v) {
-      for (int rep = 0; rep < 2; ++rep) {
-        HIPCHK(hipEventRecord(e0, c->stream));
-        if (v == 1) qc[q].coop_fock(a, c->stream);
-        else lane_launches(c, a, q, (pcol && v == 0) ? 2 : 0,
-                           [&](int, auto&& run) { run(c->stream); });
-        HIPCHK(hipEventRecord(e1, c->stream));
+      float best = -1.0f;
+      c->unit_threads[pcol][q][v] = 64;
+      for (int nt : {64, 128, 256}) {
+        if (v == 1 && nt != 64) break;
+        if (env_nt > 0 && v != 1 && nt != env_nt) continue;
+        a.unit_threads = nt;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIPCHK(hipEventRecord(e0, c->stream));
+          if (v == 1) qc[q].coop_fock(a, c->stream);
+          else lane_launches(c, a, q, (pcol && v == 0) ? 2 : 0,
+                             [&](int, auto&& run) { run(c->stream); });
+          HIPCHK(hipEventRecord(e1, c->stream));
+        }
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (best < 0.0f || ms < best) {
+          best = ms;
+          if (v != 1) c->unit_threads[pcol][q][v] = nt;
+        }
       }
-      HIPCHK(hipEventSynchronize(e1));
-      HIPCHK(hipEventElapsedTime(&c->tune_ms[pcol][q][v], e0, e1));
+      c->tune_ms[pcol][q][v] = best;
+      a.unit_threads = 64;
     };
     int forced = -1;
     if (!lane_ok) forced = 1;
@@ -1532,6 +1565,7 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
       set_class(a, W);
       launch(c->coop_bytes[q][0], [&](hipStream_t s) { qc[q].coop_fock(a, s); });
     } else {
+      a.unit_threads = det ? 64 : c->unit_threads[pcol][q][c->fock_variant[pcol][q]];
       lane_launches(c, a, q, lane_mode(c, precision, q), [&](int k, auto&& run) {
         launch(c->private_bytes[q][k], run);
       });

@@ -72,6 +72,9 @@ struct FockArgs {
   unsigned long long* Jfx;
   unsigned long long* Kfx;
   unsigned long long* Jkfx;
+  // threads of a lane-kernel unit: 64, 128 or 256 (one to four wavefronts
+  // sharing the unit's LDS rows); 64 in deterministic builds
+  int unit_threads;
 };
 
 struct SchwarzArgs {
@@ -245,12 +248,16 @@ __device__ __forceinline__ void unit_sel_quartet(const WorkItem& u,
 // MIX (with R = double): the mixed-precision form in one launch: the unit's
 // quartets in its rows' FP64 prefixes first, with FP64 integrals, then the rest
 // with FP32 integrals, over one set of LDS rows and one flush.
+// A unit is one to four wavefronts (blockDim.x = a.unit_threads): they share
+// the unit's LDS rows, so at large basis sizes, where those rows bound the
+// workgroups per CU, more wavefronts per unit keep more of them resident.
 template <class CL, typename R, bool MIX = false>
-__global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
+__global__ __launch_bounds__(256) void fock_unit_kernel(FockArgs a) {
   constexpr int NA = ncart(CL::LA), NB = ncart(CL::LB), NC = ncart(CL::LC), ND = ncart(CL::LD);
   constexpr int NR = NA + NB;
   extern __shared__ double lds[];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & (kWave - 1);
   const WorkItem u = a.units[blockIdx.x];
   const int bid = a.urows[u.row].bra;
   const ShellPair bra = a.pairs[bid];
@@ -269,7 +276,7 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
   // the bra's primitives: whole records, or for an (ss) bra {p, Px, Py, Pz, C}
   constexpr int BW = CL::LA + CL::LB == 0 ? 5 : 12;
   PrimPair* Bp = reinterpret_cast<PrimPair*>(lds + 2 * NR * a.nmax);
-  for (int t = lane; t < NR * n; t += kWave) {
+  for (int t = tid; t < NR * n; t += nt) {
     const int r = t / n, col = t - r * n;
     const int bf = r < NA ? m0 + r : n0 + (r - NA);
     Kacc[t] = 0.0;
@@ -278,7 +285,7 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
   {
     const double* src = reinterpret_cast<const double*>(a.prims + bra.prim0);
     double* dst = reinterpret_cast<double*>(Bp);
-    for (int t = lane; t < BW * bra.nprim; t += kWave) {
+    for (int t = tid; t < BW * bra.nprim; t += nt) {
       if constexpr (BW == 12) {
         dst[t] = src[t];
       } else {
@@ -301,8 +308,8 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
   auto pass = [&](auto prec, int sel) {
   using RP = decltype(prec);
   const int total = (screen || sel != 0) ? unit_sel_count(u, a.urows, keep, sel) : u.count;
-  for (int c0 = 0; c0 < total; c0 += kWave) {
-    const int t = c0 + lane;
+  for (int c0 = 0; c0 < total; c0 += nt) {
+    const int t = c0 + tid;
     const bool valid = t < total;
     int rr, k0;
     if (screen || sel != 0) {
@@ -407,7 +414,7 @@ __global__ __launch_bounds__(64) void fock_unit_kernel(FockArgs a) {
     pass(R(0), 0);
   }
   __syncthreads();
-  for (int t = lane; t < NR * n; t += kWave) {
+  for (int t = tid; t < NR * n; t += nt) {
     const double x = Kacc[t];
     if (x != 0.0) {
       const int r = t / n, col = t - r * n;

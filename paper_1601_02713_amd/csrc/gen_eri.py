@@ -565,9 +565,9 @@ def main(outdir):
                   f"void launch_fock_{tag}(const FockArgs& a, int mode, hipStream_t s) {{",
                   "  if (a.nunits == 0) return;",
                   f"  const size_t lds = sizeof(double) * unit_lds_doubles({la}, {lb}, a.nmax, a.max_prims);",
-                  f"  if (mode == 2) hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, double, true>), dim3(a.nunits), dim3(64), lds, s, a);",
-                  f"  else if (mode == 1) hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, float>), dim3(a.nunits), dim3(64), lds, s, a);",
-                  f"  else hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, double>), dim3(a.nunits), dim3(64), lds, s, a);",
+                  f"  if (mode == 2) hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, double, true>), dim3(a.nunits), dim3(a.unit_threads), lds, s, a);",
+                  f"  else if (mode == 1) hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, float>), dim3(a.nunits), dim3(a.unit_threads), lds, s, a);",
+                  f"  else hipLaunchKernelGGL((fock_unit_kernel<Cls{tag}, double>), dim3(a.nunits), dim3(a.unit_threads), lds, s, a);",
                   "}",
                   f"int fock_private_bytes_{tag}(int mode) {{",
                   "  hipFuncAttributes at{};",

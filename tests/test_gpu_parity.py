@@ -384,3 +384,26 @@ def test_full_size_bead_batch(eng, b631gs):
     g = oracle.gradient(b, r["P"], r["F"])
     assert abs(E[k] - r["E"]) < 1e-8
     assert np.abs(F[k] + g).max() < 1e-7
+
+
+@pytest.mark.parametrize("threads", ["64", "128", "256"])
+def test_lane_units_of_each_width(beadscf, b631gs, threads, monkeypatch):
+    """Lane units of one, two and four wavefronts sharing their LDS rows give
+    the oracle's J and K, in FP64 and in mixed precision (all lane forms
+    forced), on a ragged batch of 3- and 2-water clusters."""
+    monkeypatch.setenv("BSCF_VARIANT", "lane")
+    monkeypatch.setenv("BSCF_UNIT_THREADS", threads)
+    e = beadscf.Engine(0)
+    try:
+        inst = inputs.workload("w3")["instances"] + inputs.workload("w2")["instances"]
+        _setup(e, "6-31g*", inst)
+        Ps = [_rand_density(n, 40 + k) for k, n in enumerate(e.nbf)]
+        Jg, Kg = e.build_jk(Ps)
+        Jm, Km = e.build_jk(Ps, precision=beadscf.BSCF_MIXED)
+        for k, (z, x) in enumerate(inst):
+            b = oracle.build_basis(b631gs, z, x)
+            J, K, _ = oracle.jk(b, Ps[k])
+            assert np.abs(Jg[k] - J).max() < 1e-11 and np.abs(Kg[k] - K).max() < 1e-11, k
+            assert np.abs(Jm[k] - J).max() < 1e-7 and np.abs(Km[k] - K).max() < 1e-7, k
+    finally:
+        e.close()
