@@ -1,0 +1,145 @@
+"""Pins of the exchange-correlation oracle (oracle/dft.py).
+
+* The grid integrates a normalised s-Gaussian density to 1 and its Slater
+  exchange energy to the closed form N^(4/3) (a/pi)^2 (3 pi / (4 a))^(3/2)
+  times -(3/4)(3/pi)^(1/3); the core-guess density of water to 10 electrons.
+* The closed-shell LYP expression equals the spin-resolved form of Miehlich
+  et al. at rho_a = rho_b (the reduction is algebra written out once).
+* VWN's leading high-density behaviour: d e_c / d ln rs -> A with
+  A = (1 - ln 2)/pi^2, the exact coefficient of the uniform electron gas.
+* The complex-step potentials agree with central differences of the
+  energy densities.
+* V_xc is the derivative of E_xc with respect to the density matrix.
+* E_xc is unchanged by a rigid translation (the grid moves with the atoms)
+  and changes by grid-sized amounts under a rotation.
+* Sanity: the B3LYP SCF of water converges, 0.2-0.6 Eh below Hartree-Fock,
+  and lands on the commonly quoted B3LYP/6-31G* energy of water at this
+  geometry, -76.4087 Eh (a recalled value, within 2e-3 Eh: a check of the
+  functional as a whole, not a pin of its digits).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from oracle import dft, rhf
+
+
+def _water(basis):
+    z, x = inputs.workload("h2o_sto3g")["instances"][0]
+    return z, x, oracle.build_basis(basis, z, x)
+
+
+def test_grid_integrates_a_gaussian_and_its_slater_exchange(b631gs):
+    z, x, _ = _water(b631gs)
+    pts, w = dft.molecular_grid(z, x)
+    a, N = 1.3, 10.0
+    r2 = np.sum((pts - x[0]) ** 2, axis=1)
+    rho = N * (a / math.pi) ** 1.5 * np.exp(-a * r2)
+    assert abs(np.sum(w * rho) - N) < 1e-5 * N
+    ex = np.sum(w * dft.e_slater(rho))
+    exact = -0.75 * (3 / math.pi) ** (1 / 3) * N ** (4 / 3) * (a / math.pi) ** 2 * (3 * math.pi / (4 * a)) ** 1.5
+    assert abs(ex - exact) < 1e-5 * abs(exact)
+
+
+def test_core_guess_density_integrates_to_ten_electrons(b631gs):
+    z, x, b = _water(b631gs)
+    S, T, V = oracle.one_electron(b)
+    X = rhf.orthogonaliser(S)
+    P, _, _ = rhf._density(X.T @ (T + V) @ X, X, 5)
+    pts, w = dft.molecular_grid(z, x)
+    phi, _ = dft.basis_values(b, pts)
+    rho = np.sum((phi @ P) * phi, axis=1)
+    assert abs(np.sum(w * rho) - 10.0) < 2e-5
+    # the basis values agree with the overlap matrix on the grid
+    Sg = phi.T @ (w[:, None] * phi)
+    assert np.abs(Sg - S).max() < 5e-5
+
+
+def test_closed_shell_lyp_is_the_spin_form_at_equal_spins():
+    rng = np.random.default_rng(3)
+    rho = 10 ** rng.uniform(-6, 2, 200)
+    sigma = rho ** (8 / 3) * 10 ** rng.uniform(-3, 1, 200)
+    got = dft.e_lyp(rho, sigma)
+    ref = dft.lyp_miehlich(rho / 2, rho / 2, sigma / 4, sigma / 4, sigma / 4)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.all(np.abs(got - ref) <= 1e-12 * np.abs(ref) + 1e-300)
+
+
+def test_vwn_high_density_coefficient():
+    A = (1 - math.log(2)) / math.pi ** 2
+    assert abs(A - 0.0310907) < 1e-7
+    for rs in (1e-6, 1e-8):
+        rho = 3 / (4 * math.pi * rs ** 3)
+        rho2 = 3 / (4 * math.pi * (rs / 2) ** 3)
+        slope = (dft.e_vwn(np.array([rho]))[0] / rho - dft.e_vwn(np.array([rho2]))[0] / rho2) / math.log(2)
+        assert abs(slope - A) < 2e-3 * A
+
+
+def test_complex_step_potentials_match_central_differences():
+    rng = np.random.default_rng(4)
+    rho = 10 ** rng.uniform(-4, 1, 50)
+    sigma = rho ** (8 / 3) * 10 ** rng.uniform(-2, 1, 50)
+    e, vr, vs = dft.potentials(rho, sigma)
+    for k in range(50):
+        h = 1e-5 * rho[k]
+        d = (dft.e_b3lyp(rho[k] + h, sigma[k]) - dft.e_b3lyp(rho[k] - h, sigma[k])) / (2 * h)
+        assert abs(d - vr[k]) < 1e-7 * max(abs(vr[k]), 1e-12), k
+        h = 1e-5 * sigma[k]
+        d = (dft.e_b3lyp(rho[k], sigma[k] + h) - dft.e_b3lyp(rho[k], sigma[k] - h)) / (2 * h)
+        assert abs(d - vs[k]) < 1e-6 * max(abs(vs[k]), 1e-12), k
+
+
+def test_vxc_is_the_density_derivative_of_exc(b631gs):
+    """Along a path of densities P(t) = 2 C(t) C(t)^T with the occupied
+    orbitals C(t) = C_occ + t C_vir R (a Gram matrix, so the density stays
+    non-negative on every grid point), dE_xc/dt = sum V_xc * dP/dt."""
+    z, x, b = _water(b631gs)
+    S, T, V = oracle.one_electron(b)
+    X = rhf.orthogonaliser(S)
+    _, C, _ = rhf._density(X.T @ (T + V) @ X, X, 5)
+    Co, Cv = C[:, :5], C[:, 5:]
+    R = np.random.default_rng(5).standard_normal((Cv.shape[1], 5)) * 0.3
+    Pt = lambda t: 2 * (Co + t * Cv @ R) @ (Co + t * Cv @ R).T
+    D = 2 * (Cv @ R @ Co.T + Co @ R.T @ Cv.T)
+    grid = dft.molecular_grid(z, x, 40, 10)
+    _, Vxc = dft.xc(b, Pt(0.0), grid)
+    h = 1e-4
+    Ep, _ = dft.xc(b, Pt(h), grid)
+    Em, _ = dft.xc(b, Pt(-h), grid)
+    assert abs((Ep - Em) / (2 * h) - np.sum(Vxc * D)) < 1e-7 * abs(np.sum(Vxc * D))
+
+
+def test_rigid_motion(b631gs):
+    z, x, b = _water(b631gs)
+    S, T, V = oracle.one_electron(b)
+    X = rhf.orthogonaliser(S)
+    P, _, _ = rhf._density(X.T @ (T + V) @ X, X, 5)
+    E0, _ = dft.xc(b, P)
+    bt = oracle.build_basis(b631gs, z, x + np.array([0.7, -1.1, 0.4]))
+    Et, _ = dft.xc(bt, P)
+    assert abs(Et - E0) < 1e-11
+    th = 0.3
+    R = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]])
+    br = oracle.build_basis(b631gs, z, x @ R.T)
+    # the density matrix of the rotated molecule is the rotated one: use the
+    # rotated molecule's own core guess
+    S, T, V = oracle.one_electron(br)
+    X = rhf.orthogonaliser(S)
+    Pr, _, _ = rhf._density(X.T @ (T + V) @ X, X, 5)
+    Er, _ = dft.xc(br, Pr)
+    assert abs(Er - E0) < 1e-4
+
+
+@pytest.mark.slow
+def test_b3lyp_scf_of_water_converges_below_hartree_fock(b631gs):
+    z, x, b = _water(b631gs)
+    r = dft.ks_scf(b, 1e-9, 1e-7)
+    assert r["converged"]
+    hf = rhf.scf(b, 1e-9, 1e-7)
+    print("B3LYP", r["E"], "HF", hf["E"])
+    assert hf["E"] - 0.6 < r["E"] < hf["E"] - 0.2
+    assert abs(r["E"] - (-76.4087)) < 2e-3
