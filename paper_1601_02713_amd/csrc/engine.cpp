@@ -313,6 +313,7 @@ struct bscf_ctx {
   // threads per lane-kernel unit, [precision mode][class][variant] (see tune_ms)
   int unit_threads[2][kNumQuartetClasses][3] = {};
   float tune_grad_ms[kNumQuartetClasses][2] = {};
+  int grad_unit_threads[kNumQuartetClasses] = {};   // threads per lane gradient unit
   float tune_grad1e_ms[kNumPairClasses] = {};   // one-electron gradient kernels alone
   // per-lane private (scratch) bytes of every class kernel: [class][fp64, mixed, grad].
   // The runtime reserves (and keeps) scratch per hardware queue for full
@@ -2348,6 +2349,7 @@ void forces_impl(bscf_ctx* c, double* Fout) {
     ga.Pk = c->d_Pk.p;
     ga.grad = c->d_grad.p;
     ga.boys64 = c->d_boys64.p;
+    ga.unit_threads = 64;
     launch_gather_pk(ketpos_args(c), c->max_ncd, c->P.p, c->d_Pk.p, st);
     auto set_gclass = [](GradArgs& g, const bscf_ctx::ClassWork& W) {
       g.items = W.d_items.p;
@@ -2364,6 +2366,10 @@ void forces_impl(bscf_ctx* c, double* Fout) {
       // the gradient launches alone (into a throwaway buffer): the choice
       // of variant and the stream schedule below use these times
       const char* env = getenv("BSCF_VARIANT");
+      const char* env_u = getenv("BSCF_UNIT_THREADS");
+      const int env_nt = env_u ? atoi(env_u) : 0;
+      need(env_nt == 0 || env_nt == 64 || env_nt == 128 || env_nt == 256, BSCF_E_INVALID,
+           "BSCF_UNIT_THREADS must be 64, 128 or 256");
       // the kernels add into grad[3 * atom + d] of every atom of the batch
       need(c->d_grad_tune.n >= (size_t)3 * c->total_atoms, BSCF_E_STATE,
            "gradient timing buffer smaller than the batch");
@@ -2390,8 +2396,22 @@ void forces_impl(bscf_ctx* c, double* Fout) {
                                 qc[q].la, qc[q].lb, c->max_n, c->max_atoms, W.max_prims) <=
                             c->max_lds_bytes;
         const bool lane_ok = qc[q].grad && lds_ok && c->private_bytes[q][2] <= kMaxLaneScratch;
-        if (lane_ok && !(env && !strcmp(env, "coop")))
-          c->tune_grad_ms[q][0] = time_alone([&] { qc[q].grad(gt, st); });
+        c->grad_unit_threads[q] = 64;
+        if (lane_ok && !(env && !strcmp(env, "coop"))) {
+          // units of one, two and four wavefronts, the fastest kept
+          float best = -1.0f;
+          for (int nt : {64, 128, 256}) {
+            if (env_nt > 0 && nt != env_nt) continue;
+            gt.unit_threads = nt;
+            const float ms = time_alone([&] { qc[q].grad(gt, st); });
+            if (best < 0.0f || ms < best) {
+              best = ms;
+              c->grad_unit_threads[q] = nt;
+            }
+          }
+          gt.unit_threads = 64;
+          c->tune_grad_ms[q][0] = best;
+        }
         if (!lane_ok || !(env && !strcmp(env, "lane")))
           c->tune_grad_ms[q][1] = time_alone([&] { qc[q].coop_grad(gt, st); });
         if (!lane_ok) c->grad_variant[q] = 1;
@@ -2452,6 +2472,7 @@ void forces_impl(bscf_ctx* c, double* Fout) {
         auto& W = c->work[j.q];
         set_gclass(ga, W);
         const int pk = c->profiling ? prof_begin(c, j.q, 1, s) : -1;
+        ga.unit_threads = c->grad_unit_threads[j.q] ? c->grad_unit_threads[j.q] : 64;
         if (c->grad_variant[j.q]) qc[j.q].coop_grad(ga, s);
         else qc[j.q].grad(ga, s);
         if (pk >= 0) prof_end(c, pk, s);

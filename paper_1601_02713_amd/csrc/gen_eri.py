@@ -655,7 +655,7 @@ def main(outdir):
               f"void launch_grad_{tag}(const GradArgs& a, hipStream_t s) {{",
               "  if (a.nunits == 0) return;",
               f"  const size_t lds = sizeof(double) * grad_unit_lds_doubles({la}, {lb}, a.nmax, a.max_atoms, a.max_prims);",
-              f"  hipLaunchKernelGGL((grad_unit_kernel<ClsG{tag}>), dim3(a.nunits), dim3(64), lds, s, a);",
+              f"  hipLaunchKernelGGL((grad_unit_kernel<ClsG{tag}>), dim3(a.nunits), dim3(a.unit_threads), lds, s, a);",
               "}",
               f"int grad_private_bytes_{tag}() {{",
               "  hipFuncAttributes at{};",

@@ -28,6 +28,7 @@ struct GradArgs {
   const double* Pk;        // P gathered by ket-list position (see FockArgs)
   double* grad;            // [total atoms][3], dE/dR accumulated
   const double* boys64;
+  int unit_threads;        // threads of a lane-kernel unit: 64, 128 or 256
 };
 
 // LDS footprint of the gradient unit kernel: P rows of the bra shells, one

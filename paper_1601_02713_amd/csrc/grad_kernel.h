@@ -167,18 +167,20 @@ __device__ __forceinline__ T gwave_sum(T v) {
   return v;
 }
 
-// One wavefront per FockUnit (a bra pair and up to a few hundred kets; see
-// fock_kernel.h).  The density factor of each quartet is built from the bra
-// shells' P rows (LDS) and the ket block of Pk; dE/dR of the bra atoms is
-// reduced across the wavefront once per unit, that of the ket atoms is
-// accumulated per atom in LDS and flushed with contiguous atomics.
+// One to four wavefronts (blockDim.x = a.unit_threads) per unit of the Fock
+// build (a bra pair and its kets; see fock_kernel.h), sharing the unit's LDS.
+// The density factor of each quartet is built from the bra shells' P rows
+// (LDS) and the ket block of Pk; dE/dR of the bra atoms is reduced across
+// each wavefront once per unit, that of the ket atoms is accumulated per atom
+// in LDS and flushed with contiguous atomics.
 template <class CG>
-__global__ __launch_bounds__(64) void grad_unit_kernel(GradArgs a) {
+__global__ __launch_bounds__(256) void grad_unit_kernel(GradArgs a) {
   constexpr int NA = ncart(CG::LA), NB = ncart(CG::LB), NC = ncart(CG::LC), ND = ncart(CG::LD);
   constexpr int NR = NA + NB;
   constexpr int NOUT = NA * NB * NC * ND;
   extern __shared__ double lds[];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & (kWave - 1);
   const WorkItem u = a.units[blockIdx.x];
   const int bid = a.urows[u.row].bra;
   const ShellPair bra = a.pairs[bid];
@@ -195,19 +197,19 @@ __global__ __launch_bounds__(64) void grad_unit_kernel(GradArgs a) {
   {
     const double* src = reinterpret_cast<const double*>(a.prims + bra.prim0);
     double* dst = reinterpret_cast<double*>(Bp);
-    for (int t = lane; t < 12 * bra.nprim; t += kWave) dst[t] = src[t];
+    for (int t = tid; t < 12 * bra.nprim; t += nt) dst[t] = src[t];
   }
-  for (int t = lane; t < NR * n; t += kWave) {
+  for (int t = tid; t < NR * n; t += nt) {
     const int r = t / n, col = t - r * n;
     const int bf = r < NA ? m0 + r : n0 + (r - NA);
     Prow[t] = a.P[mo + (long long)bf * n + col];
   }
-  for (int t = lane; t < nat3; t += kWave) Gat[t] = 0.0;
+  for (int t = tid; t < nat3; t += nt) Gat[t] = 0.0;
   __syncthreads();
   const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
   double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
-  for (int c0 = 0; c0 < u.count; c0 += kWave) {
-    const int t = c0 + lane;
+  for (int c0 = 0; c0 < u.count; c0 += nt) {
+    const int t = c0 + tid;
     const bool valid = t < u.count;
     int rr = u.row, k0 = u.off + (valid ? t : 0);
     int nk = a.urows[rr].nket;
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(64) void grad_unit_kernel(GradArgs a) {
   }
   __syncthreads();
   double* grad = a.grad + 3LL * a0;
-  for (int t = lane; t < nat3; t += kWave) {
+  for (int t = tid; t < nat3; t += nt) {
     const double x = Gat[t];
     if (x != 0.0) atomicAdd(&grad[t], x);
   }

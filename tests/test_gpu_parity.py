@@ -390,7 +390,8 @@ def test_full_size_bead_batch(eng, b631gs):
 def test_lane_units_of_each_width(beadscf, b631gs, threads, monkeypatch):
     """Lane units of one, two and four wavefronts sharing their LDS rows give
     the oracle's J and K, in FP64 and in mixed precision (all lane forms
-    forced), on a ragged batch of 3- and 2-water clusters."""
+    forced), on a ragged batch of 3- and 2-water clusters, and the oracle's
+    forces through the gradient's lane units of the same width."""
     monkeypatch.setenv("BSCF_VARIANT", "lane")
     monkeypatch.setenv("BSCF_UNIT_THREADS", threads)
     e = beadscf.Engine(0)
@@ -405,5 +406,15 @@ def test_lane_units_of_each_width(beadscf, b631gs, threads, monkeypatch):
             J, K, _ = oracle.jk(b, Ps[k])
             assert np.abs(Jg[k] - J).max() < 1e-11 and np.abs(Kg[k] - K).max() < 1e-11, k
             assert np.abs(Jm[k] - J).max() < 1e-7 and np.abs(Km[k] - K).max() < 1e-7, k
+        # the gradient's lane units of the same width
+        z, x = inputs.water_cluster(2, 13)
+        _setup(e, "6-31g*", [(z, x)])
+        E, _, st = e.run_scf(e_tol=1e-11, comm_tol=1e-9)
+        F = e.forces()[0]
+        b = oracle.build_basis(b631gs, z, x)
+        r = oracle.scf(b, 1e-11, 1e-9)
+        g = oracle.gradient(b, r["P"], r["F"])
+        assert st[0] == 0 and abs(E[0] - r["E"]) < 1e-9
+        assert np.abs(F + g).max() < 1e-8
     finally:
         e.close()
