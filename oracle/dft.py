@@ -207,12 +207,14 @@ def e_b3lyp(rho, sigma):
 
 
 def potentials(rho, sigma, func=e_b3lyp):
-    """(e, v_rho, v_sigma) by complex-step differentiation."""
+    """(e, v_rho, v_sigma) by complex-step differentiation.  The sigma step is
+    relative to max(sigma, rho^(8/3)) (the scale of sigma in the reduced
+    gradient), so it stays non-zero where sigma vanishes."""
     h = 1e-30
     e = func(rho, sigma)
     vr = np.imag(func(rho + 1j * h * rho, sigma + 0j)) / (h * rho)
-    sg = np.maximum(sigma, 1e-300)
-    vs = np.imag(func(rho + 0j, sg + 1j * h * sg)) / (h * sg)
+    hs = h * np.maximum(sigma, rho ** (8.0 / 3.0))
+    vs = np.imag(func(rho + 0j, sigma + 1j * hs)) / hs
     return e, vr, vs
 
 
