@@ -311,6 +311,42 @@ bscf_status bscf_work_counts(bscf_ctx* ctx, double* n_quartets, double* n_prim_q
  * (an SCF with opts.deterministic = 1 is deterministic either way). */
 bscf_status bscf_set_deterministic(bscf_ctx* ctx, int on);
 
+/* Exchange-correlation model of the Fock builds (the paper's runs use
+ * B3LYP, Section 3.1: B3LYP/6-31G*).
+ * BSCF_XC_NONE: Hartree-Fock, F = H + J - K/2 (the default).
+ * BSCF_XC_B3LYP: closed-shell Kohn-Sham with the B3LYP functional of
+ * Stephens, Devlin, Chabalowski and Frisch (1994): F = H + J - 0.1 K + V_xc
+ * and E = Tr[P(H + J/2 - 0.05 K)] + E_xc + E_nuc, where E_xc = 0.8 Slater +
+ * 0.72 Becke-88 correction + 0.19 VWN (RPA fit) + 0.81 LYP is integrated on
+ * a molecular grid of 60 radial x 288 angular points per atom (Becke's radial
+ * mapping, R = 1.0 bohr for H and 0.6 bohr otherwise; 12 Gauss-Legendre nodes
+ * in cos(theta) x 24 in phi; Becke's fuzzy-cell weights).  Applies to every
+ * later bscf_build_fock and bscf_run_scf of the context (bscf_build_jk still
+ * returns J and K).  B3LYP forces are not implemented: bscf_forces after a
+ * B3LYP SCF, bscf_forces_at, bscf_pimd_step and bscf_string_step answer
+ * BSCF_E_UNSUPPORTED while B3LYP is set. */
+#define BSCF_XC_NONE 0
+#define BSCF_XC_B3LYP 1
+bscf_status bscf_set_xc(bscf_ctx* ctx, int functional);
+
+/* The B3LYP exchange-correlation matrix and energy (Section 3.1's level of
+ * theory; the grid and functional of bscf_set_xc) at densities P (all
+ * instances concatenated, each n_i x n_i, symmetric): Vxc[i] (n_i x n_i) and
+ * Exc[i] per instance.  With device_ptrs all three are device pointers.  The
+ * given densities replace the SCF's, as with bscf_build_fock. */
+bscf_status bscf_xc_matrix(bscf_ctx* ctx, const double* P, double* Vxc, double* Exc,
+                           int device_ptrs);
+
+/* Number of grid points of instance `inst` (atoms x 17280). */
+bscf_status bscf_xc_grid_size(bscf_ctx* ctx, int inst, long long* npts);
+
+/* The closed-shell B3LYP energy density e(rho, sigma) (Eh/bohr^3) and its
+ * derivatives vrho = de/drho, vsigma = de/dsigma at n points on the device
+ * (rho the total density, sigma = |grad rho|^2; host arrays).  rho must be
+ * positive.  Test use. */
+bscf_status bscf_xc_functional(bscf_ctx* ctx, int n, const double* rho, const double* sigma,
+                               double* e, double* vrho, double* vsigma);
+
 /* Kernel profiling: with on != 0 every Fock-build class kernel is bracketed by
  * HIP events on the context's stream; per-class times appear in the stats. */
 bscf_status bscf_set_profiling(bscf_ctx* ctx, int on);

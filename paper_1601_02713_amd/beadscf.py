@@ -25,6 +25,7 @@ BSCF_FP64, BSCF_MIXED = 0, 1
 GUESS_CORE, GUESS_PREVIOUS, GUESS_LEARNED, GUESS_USER = 0, 1, 2, 3
 DENSITY_SP2, DENSITY_EIG = 0, 1
 STATUS_MAX_ITER, STATUS_NAN, STATUS_FALLBACK = 1, 2, 4
+XC_NONE, XC_B3LYP = 0, 1
 
 
 class ScfOpts(ctypes.Structure):
@@ -73,6 +74,10 @@ _SIGS = {
     "bscf_guess_eval": [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp],
     "bscf_guess_fit": [_vp, _i, _vp, _vp, _vp, _i, ctypes.c_float, _vp],
     "bscf_guess_eval_noalloc": [_vp, _i, _vp, _vp],
+    "bscf_set_xc": [_vp, _i],
+    "bscf_xc_matrix": [_vp, _vp, _vp, _vp, _i],
+    "bscf_xc_grid_size": [_vp, _i, _vp],
+    "bscf_xc_functional": [_vp, _i, _vp, _vp, _vp, _vp, _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -378,6 +383,34 @@ class Engine:
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _chk(_lib.bscf_work_counts(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
+
+    def set_xc(self, functional=XC_B3LYP):
+        """XC_NONE (Hartree-Fock) or XC_B3LYP for later Fock builds and SCFs."""
+        _chk(_lib.bscf_set_xc(self._h, int(functional)))
+
+    def xc_matrix(self, Ps):
+        """(V_xc per instance, E_xc [n_inst]) of B3LYP at densities Ps."""
+        P = self._cat(Ps)
+        V = np.empty_like(P)
+        E = np.empty(self.n_inst)
+        _chk(_lib.bscf_xc_matrix(self._h, _ptr(P), _ptr(V), _ptr(E), 0))
+        return self._split(V), E
+
+    def xc_grid_size(self, i):
+        n = ctypes.c_longlong()
+        _chk(_lib.bscf_xc_grid_size(self._h, i, ctypes.byref(n)))
+        return n.value
+
+    def xc_functional(self, rho, sigma):
+        """(e, v_rho, v_sigma) of the closed-shell B3LYP energy density."""
+        rho = np.ascontiguousarray(np.asarray(rho, float))
+        sigma = np.ascontiguousarray(np.asarray(sigma, float))
+        if rho.shape != sigma.shape or rho.ndim != 1:
+            raise ValueError("rho and sigma must be 1-D arrays of one length")
+        e, vr, vs = np.empty_like(rho), np.empty_like(rho), np.empty_like(rho)
+        _chk(_lib.bscf_xc_functional(self._h, len(rho), _ptr(rho), _ptr(sigma), _ptr(e), _ptr(vr),
+                                     _ptr(vs)))
+        return e, vr, vs
 
     def set_deterministic(self, on=True):
         _chk(_lib.bscf_set_deterministic(self._h, 1 if on else 0))

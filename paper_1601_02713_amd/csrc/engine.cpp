@@ -39,6 +39,7 @@
 #include "mlp.h"
 #include "pimd.h"
 #include "string_method.h"
+#include "xc.h"
 
 using namespace bscf;
 
@@ -483,6 +484,20 @@ struct bscf_ctx {
     bool have_force = false;   // d_grad holds the gradient at the current positions
     DevBuf<double> x, p, C, w, c1, c2, mass, sig, F;
   } md;
+
+  // B3LYP exchange-correlation: xc the setting of bscf_set_xc, xc_now that of
+  // the build in progress, scf_xc that of the last SCF (forces refuse it)
+  int xc = 0, xc_now = 0;
+  bool scf_xc = false;
+  struct Xcs {
+    bool tables = false;
+    bool grid_ok = false;               // the grid of the current geometry is on the device
+    std::vector<long long> pt_off;      // per instance: first grid point
+    long long npts = 0;
+    DevBuf<double> rad_r, rad_w, ang_u, ang_w, pts;
+    DevBuf<double> B, Bx, By, Bz, Z;    // chunk buffers, [n_max][kXcChunk]
+    DevBuf<double> V, exc;              // V_xc [mtot], E_xc [ninst]
+  } xcs;
 
   // string of images over the batch's instances; positions on the device
   struct Str {
@@ -1460,6 +1475,138 @@ void autotune_fock(bscf_ctx* c, int pcol) {
 // gain the contributions of dP = P - Pprev, from the quartets with
 // Q_ab Q_cd min(max|dP|, 1) >= tau; J and K are linear in the density, so
 // only the skipped quartets (each bounded by tau) differ from a full build.
+// ------------------------------------------------------------------ B3LYP
+
+constexpr int kXcChunk = 16384;   // grid points per basis-value chunk
+
+// Radial and angular tables of the grid (xc.h), once per context
+void xc_tables(bscf_ctx* c) {
+  auto& x = c->xcs;
+  if (x.tables) return;
+  std::vector<double> rr(2 * kXcRad), rw(2 * kXcRad);
+  for (int t = 0; t < 2; ++t) {
+    const double R = t == 0 ? 1.0 : 0.6;
+    for (int i = 1; i <= kXcRad; ++i) {
+      const double th = i * M_PI / (kXcRad + 1), xx = std::cos(th);
+      const double r = R * (1 + xx) / (1 - xx);
+      const double w = M_PI / (kXcRad + 1) * std::sin(th) * std::sin(th);
+      rr[t * kXcRad + i - 1] = r;
+      rw[t * kXcRad + i - 1] = w * r * r * (2 * R / ((1 - xx) * (1 - xx))) / std::sqrt(1 - xx * xx);
+    }
+  }
+  // Gauss-Legendre nodes in cos(theta) by Newton's method on P_n
+  std::vector<double> ct(kXcTheta), wt(kXcTheta);
+  for (int k = 0; k < kXcTheta; ++k) {
+    double z = std::cos(M_PI * (k + 0.75) / (kXcTheta + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int m = 2; m <= kXcTheta; ++m) {
+        const double p2 = ((2 * m - 1) * z * p1 - (m - 1) * p0) / m;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = kXcTheta * (z * p1 - p0) / (z * z - 1);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    ct[k] = z;
+    wt[k] = 2.0 / ((1 - z * z) * dp * dp);
+  }
+  std::vector<double> au(3 * kXcAng), aw(kXcAng);
+  const int nphi = 2 * kXcTheta;
+  for (int k = 0; k < kXcTheta; ++k)
+    for (int m = 0; m < nphi; ++m) {
+      const int j = k * nphi + m;
+      const double st = std::sqrt(1 - ct[k] * ct[k]), ph = 2 * M_PI * m / nphi;
+      au[3 * j] = st * std::cos(ph);
+      au[3 * j + 1] = st * std::sin(ph);
+      au[3 * j + 2] = ct[k];
+      aw[j] = wt[k] * 2 * M_PI / nphi;
+    }
+  x.rad_r.upload(rr, c->stream);
+  x.rad_w.upload(rw, c->stream);
+  x.ang_u.upload(au, c->stream);
+  x.ang_w.upload(aw, c->stream);
+  x.tables = true;
+}
+
+// the molecular grid of every instance at the current geometry
+void xc_grid(bscf_ctx* c) {
+  auto& x = c->xcs;
+  if (x.grid_ok) return;
+  xc_tables(c);
+  x.pt_off.assign(c->ninst + 1, 0);
+  for (int i = 0; i < c->ninst; ++i)
+    x.pt_off[i + 1] = x.pt_off[i] + (long long)c->natoms[i] * kXcPerAtom;
+  x.npts = x.pt_off[c->ninst];
+  x.pts.resize((size_t)4 * x.npts);
+  for (int i = 0; i < c->ninst; ++i) {
+    XcGridArgs g;
+    g.npts = (int)(x.pt_off[i + 1] - x.pt_off[i]);
+    g.natoms = c->natoms[i];
+    g.xyz = c->d_xyz.p + 3LL * c->atom_off[i];
+    g.Z = c->d_Zd.p + c->atom_off[i];
+    g.rad_r = x.rad_r.p;
+    g.rad_w = x.rad_w.p;
+    g.ang_u = x.ang_u.p;
+    g.ang_w = x.ang_w.p;
+    g.pts = x.pts.p + 4 * x.pt_off[i];
+    launch_xc_grid(g, c->stream);
+  }
+  HIPCHK(hipGetLastError());
+  x.grid_ok = true;
+}
+
+// V_xc and E_xc of every (active, if masked) instance at the densities P
+void xc_build(bscf_ctx* c, const double* P, bool masked) {
+  auto& x = c->xcs;
+  xc_grid(c);
+  const size_t chunk = (size_t)c->max_n * kXcChunk;
+  for (DevBuf<double>* b : {&x.B, &x.Bx, &x.By, &x.Bz, &x.Z}) b->resize(chunk);
+  x.V.resize(c->mtot);
+  x.exc.resize(c->ninst);
+  launch_fill(x.exc.p, c->ninst, 0.0, c->stream);
+  const hipStream_t st = c->stream;
+  for (int i = 0; i < c->ninst; ++i) {
+    if (masked && !c->h_active[i]) continue;
+    const int n = c->nbf[i];
+    double* V = x.V.p + c->moff[i];
+    const double* Pi = P + c->moff[i];
+    const long long np = x.pt_off[i + 1] - x.pt_off[i];
+    for (long long g0 = 0; g0 < np; g0 += kXcChunk) {
+      XcChunkArgs a;
+      a.g0 = (int)g0;
+      a.ng = (int)std::min<long long>(kXcChunk, np - g0);
+      a.n = n;
+      a.sh0 = c->shell_off[i];
+      a.nsh = c->nshell[i];
+      a.shells = c->d_shells.p;
+      a.sh_exp = c->d_sh_exp.p;
+      a.sh_coef = c->d_sh_coef.p;
+      a.pts = x.pts.p + 4 * x.pt_off[i];
+      a.B = x.B.p;
+      a.Bx = x.Bx.p;
+      a.By = x.By.p;
+      a.Bz = x.Bz.p;
+      a.Z = x.Z.p;
+      a.exc = x.exc.p + i;
+      launch_xc_basis(a, st);
+      // Z = B P: function-major B is the column-major ng x n matrix
+      const double one = 1.0, zero = 0.0;
+      BLASCHK(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, a.ng, n, n,
+                            &one, x.B.p, a.ng, Pi, n, &zero, x.Z.p, a.ng));
+      launch_xc_point(a, st);   // Z <- X
+      // V (column-major) += X^T B over the chunk; V + V^T at the end
+      const double beta = g0 == 0 ? 0.0 : 1.0;
+      BLASCHK(rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, n, n,
+                            a.ng, &one, x.Z.p, a.ng, x.B.p, a.ng, &beta, V, n));
+    }
+    launch_xc_symmetrize(n, V, st);
+  }
+  HIPCHK(hipGetLastError());
+}
+
 void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool incremental = false) {
   ensure_work(c, tau, c->split_tol, precision == BSCF_MIXED);
   if (!c->fock_tuned[precision == BSCF_MIXED ? 1 : 0]) autotune_fock(c, precision == BSCF_MIXED ? 1 : 0);
@@ -1597,8 +1744,14 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
   if (pbuild >= 0) prof_end(c, pbuild, c->stream);
   if (c->prof_pending.size() > 8192) prof_collect(c);
   BatchInfo b = c->batch(masked);
-  launch_fock_assemble(b, c->max_n, c->H.p, c->J.p, c->K.p, c->P.p, c->d_Enuc.p, c->F.p, c->d_E.p,
-                       c->stream);
+  if (c->xc_now) {
+    xc_build(c, c->P.p, masked);
+    launch_fock_assemble(b, c->max_n, c->H.p, c->J.p, c->K.p, c->P.p, c->d_Enuc.p, c->F.p,
+                         c->d_E.p, c->stream, kXcA0, c->xcs.V.p, c->xcs.exc.p);
+  } else {
+    launch_fock_assemble(b, c->max_n, c->H.p, c->J.p, c->K.p, c->P.p, c->d_Enuc.p, c->F.p,
+                         c->d_E.p, c->stream);
+  }
   launch_scale_copy(bset, c->max_n, c->P.p, c->Pprev.p, 1.0, 0, c->stream);   // next build's reference
   c->fock_builds++;
   c->t_fock_ms += now_ms() - t0;
@@ -1912,6 +2065,7 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->guess.reset_batch(c->ninst);
     c->md.on = c->md.synced = c->md.have_force = false;
     c->str.on = c->str.synced = false;
+    c->xcs.grid_ok = false;
     sync(c);
     undo.done = true;
   });
@@ -1930,6 +2084,7 @@ bscf_status bscf_set_geometries(bscf_ctx* c, const double* xyz) {
     c->have_geom = c->have_scf = false;
     c->md.synced = c->md.have_force = false;
     c->str.synced = false;
+    c->xcs.grid_ok = false;
     HIPCHK(hipSetDevice(c->device));
     join_work(c);
     c->work_tau = c->host_tau = -1.0;
@@ -2016,6 +2171,7 @@ bscf_status bscf_build_jk(bscf_ctx* c, const double* P, double* J, double* K, do
     c->have_scf = false;   // the SCF density is replaced: forces need a new SCF
     HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double), kind, c->stream));
     c->det_now = c->det;
+    c->xc_now = 0;
     fock_build(c, tau, precision, false);
     // symmetrised J, K
     BatchInfo b = c->batch(false);
@@ -2041,6 +2197,7 @@ bscf_status bscf_build_fock(bscf_ctx* c, const double* P, double* F, double* E, 
     c->have_scf = false;   // the SCF density is replaced: forces need a new SCF
     HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double), kind, c->stream));
     c->det_now = c->det;
+    c->xc_now = c->xc;
     fock_build(c, tau, precision, false);
     const auto back = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     HIPCHK(hipMemcpyAsync(F, c->F.p, c->mtot * sizeof(double), back, c->stream));
@@ -2161,6 +2318,8 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
          "density must be BSCF_DENSITY_SP2 or BSCF_DENSITY_EIG");
     need(o.deterministic == 0 || o.deterministic == 1, BSCF_E_INVALID, "deterministic must be 0 or 1");
     c->det_now = o.deterministic == 1 || c->det;
+    c->xc_now = c->xc;
+    c->scf_xc = c->xc != 0;
     c->split_tol = o.fp32_split_tol;
     c->have_scf = false;   // set again once every instance has its density
     const double t0 = now_ms();
@@ -2502,6 +2661,7 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
   return guard([&] {
     need(c && Fout, BSCF_E_INVALID, "NULL argument");
     need(c->have_scf, BSCF_E_STATE, "forces need an SCF at the current geometry");
+    need(!c->scf_xc, BSCF_E_UNSUPPORTED, "forces of a B3LYP SCF are not implemented");
     HIPCHK(hipSetDevice(c->device));
     forces_impl(c, Fout);
   });
@@ -2512,6 +2672,7 @@ bscf_status bscf_forces_at(bscf_ctx* c, const double* P, const double* F, double
   return guard([&] {
     need(c && P && F && Fout, BSCF_E_INVALID, "NULL argument");
     need(std::isfinite(tau), BSCF_E_INVALID, "bad Schwarz cutoff");
+    need(c->xc == 0, BSCF_E_UNSUPPORTED, "forces of B3LYP are not implemented");
     require_geom(c);
     HIPCHK(hipSetDevice(c->device));
     // the screened work lists of the current geometry at this cutoff
@@ -2713,6 +2874,7 @@ bscf_status bscf_pimd_step(bscf_ctx* c, const bscf_scf_opts* opts, double* E, in
   return guard([&] {
     need(c != nullptr, BSCF_E_INVALID, "NULL context");
     need(c->md.on, BSCF_E_STATE, "no ring polymer: call bscf_pimd_init");
+    need(c->xc == 0, BSCF_E_UNSUPPORTED, "forces of B3LYP are not implemented");
     HIPCHK(hipSetDevice(c->device));
     if (!c->md.have_force) pimd_forces_here(c, opts, nullptr, nullptr, nullptr);
     pimd_begin_impl(c, nullptr);
@@ -2823,6 +2985,7 @@ bscf_status bscf_string_step(bscf_ctx* c, const bscf_scf_opts* opts, double* E, 
   return guard([&] {
     need(c != nullptr, BSCF_E_INVALID, "NULL context");
     need(c->str.on, BSCF_E_STATE, "no string: call bscf_string_init");
+    need(c->xc == 0, BSCF_E_UNSUPPORTED, "forces of B3LYP are not implemented");
     HIPCHK(hipSetDevice(c->device));
     auto& g = c->str;
     std::vector<double> x((size_t)g.n * 3 * g.N);
@@ -2983,6 +3146,60 @@ bscf_status bscf_set_deterministic(bscf_ctx* c, int on) {
   return guard([&] {
     need(c != nullptr && (on == 0 || on == 1), BSCF_E_INVALID, "bad arguments");
     c->det = on == 1;
+  });
+}
+
+bscf_status bscf_set_xc(bscf_ctx* c, int functional) {
+  return guard([&] {
+    need(c != nullptr && (functional == BSCF_XC_NONE || functional == BSCF_XC_B3LYP),
+         BSCF_E_INVALID, "bad arguments");
+    c->xc = functional;
+  });
+}
+
+bscf_status bscf_xc_matrix(bscf_ctx* c, const double* P, double* Vxc, double* Exc,
+                           int device_ptrs) {
+  return guard([&] {
+    need(c && P && Vxc && Exc, BSCF_E_INVALID, "NULL argument");
+    require_geom(c);
+    HIPCHK(hipSetDevice(c->device));
+    const auto kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    c->have_scf = false;   // the SCF density is replaced: forces need a new SCF
+    HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double), kind, c->stream));
+    xc_build(c, c->P.p, false);
+    const auto back = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPCHK(hipMemcpyAsync(Vxc, c->xcs.V.p, c->mtot * sizeof(double), back, c->stream));
+    HIPCHK(hipMemcpyAsync(Exc, c->xcs.exc.p, c->ninst * sizeof(double), back, c->stream));
+    sync(c);
+  });
+}
+
+bscf_status bscf_xc_grid_size(bscf_ctx* c, int inst, long long* npts) {
+  return guard([&] {
+    need(c && npts, BSCF_E_INVALID, "NULL argument");
+    need(inst >= 0 && inst < c->ninst, BSCF_E_INVALID, "instance out of range");
+    *npts = (long long)c->natoms[inst] * kXcPerAtom;
+  });
+}
+
+bscf_status bscf_xc_functional(bscf_ctx* c, int n, const double* rho, const double* sigma,
+                               double* e, double* vrho, double* vsigma) {
+  return guard([&] {
+    need(c && n >= 0, BSCF_E_INVALID, "bad arguments");
+    if (n == 0) return;
+    need(rho && sigma && e && vrho && vsigma, BSCF_E_INVALID, "NULL argument");
+    HIPCHK(hipSetDevice(c->device));
+    DevBuf<double> d;
+    d.resize((size_t)5 * n);
+    const hipStream_t st = c->stream;
+    HIPCHK(hipMemcpyAsync(d.p, rho, n * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.p + n, sigma, n * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_xc_functional(n, d.p, d.p + n, d.p + 2 * n, d.p + 3 * n, d.p + 4 * n, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(e, d.p + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(vrho, d.p + 3 * n, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(vsigma, d.p + 4 * n, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(c);
   });
 }
 

@@ -117,11 +117,13 @@ struct BatchInfo {
 };
 
 void launch_fill(double* p, long long n, double v, hipStream_t s);
-// F = H + (J + J^T)/2 - (K + K^T)/4 ; E[i] = Tr[P(H+F)]/2 + Enuc[i]; instances
-// masked out by b.active (when non-NULL) keep their F and E
+// F = H + (J + J^T)/2 - kx (K + K^T)/4 (+ Vxc); E[i] = Tr[P(H+F')]/2 + Exc[i] +
+// Enuc[i] with F' = F without Vxc (Hartree-Fock: kx = 1, no Vxc, Exc);
+// instances masked out by b.active (when non-NULL) keep their F and E
 void launch_fock_assemble(const BatchInfo& b, int max_n, const double* H, const double* J,
                           const double* K, const double* P, const double* Enuc, double* F,
-                          double* E, hipStream_t s);
+                          double* E, hipStream_t s, double kx = 1.0, const double* Vxc = nullptr,
+                          const double* Exc = nullptr);
 // out = A - A^T per instance; the largest |out| of every 32 x 32 tile goes to
 // the scratch after the first ninst entries of emax (room for
 // ninst * ceil(max_n/32)^2 doubles), reduced into emax[i] by launch_convergence

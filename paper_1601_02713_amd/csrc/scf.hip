@@ -46,8 +46,12 @@ __device__ T block_sum(T v, T* sh) {
 }
 
 // grid: (max_n rows, ninst); writes row partials of Tr[P(H+F)]/2 to rowE
+// F = H + J - (kx / 2) K (+ Vxc), symmetrised; row sums of the energy
+// Tr[P (H + F')] / 2 with F' = F without Vxc, plus Exc on row 0 (kx = 1 and
+// no Vxc: Hartree-Fock; kx = exact-exchange share with Vxc, Exc: hybrid DFT)
 __global__ void fock_assemble_kernel(BatchInfo b, const double* H, const double* J,
-                                     const double* K, const double* P, double* F, double* rowE) {
+                                     const double* K, const double* P, double* F, double* rowE,
+                                     double kx, const double* Vxc, const double* Exc) {
   __shared__ double sh[8];
   const int inst = blockIdx.y, i = blockIdx.x;
   const int n = b.nbf[inst];
@@ -57,12 +61,13 @@ __global__ void fock_assemble_kernel(BatchInfo b, const double* H, const double*
   double e = 0.0;
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     const long long ij = o + (long long)i * n + j, ji = o + (long long)j * n + i;
-    const double f = H[ij] + 0.5 * (J[ij] + J[ji]) - 0.25 * (K[ij] + K[ji]);
-    F[ij] = f;
+    const double f = H[ij] + 0.5 * (J[ij] + J[ji]) - 0.25 * kx * (K[ij] + K[ji]);
+    F[ij] = Vxc ? f + Vxc[ij] : f;
     e += P[ij] * (H[ij] + f);
   }
   e = block_sum(e, sh);
-  if (threadIdx.x == 0) rowE[(long long)inst * gridDim.x + i] = 0.5 * e;
+  if (threadIdx.x == 0)
+    rowE[(long long)inst * gridDim.x + i] = 0.5 * e + ((Exc && i == 0) ? Exc[inst] : 0.0);
 }
 
 __global__ void energy_sum_kernel(int ninst, int max_n, const int* nbf, const int* active,
@@ -665,10 +670,11 @@ void launch_fill(double* p, long long n, double v, hipStream_t s) {
 // ninst + ninst*max_n doubles (first ninst are the energies).
 void launch_fock_assemble(const BatchInfo& b, int max_n, const double* H, const double* J,
                           const double* K, const double* P, const double* Enuc, double* F,
-                          double* E, hipStream_t s) {
+                          double* E, hipStream_t s, double kx, const double* Vxc,
+                          const double* Exc) {
   double* rowE = E + b.ninst;
   hipLaunchKernelGGL(fock_assemble_kernel, dim3(max_n, b.ninst), dim3(256), 0, s, b, H, J, K, P,
-                     F, rowE);
+                     F, rowE, kx, Vxc, Exc);
   hipLaunchKernelGGL(energy_sum_kernel, dim3(b.ninst), dim3(256), 0, s, b.ninst, max_n, b.nbf,
                      b.active, rowE, Enuc, E);
 }
