@@ -296,7 +296,8 @@ struct bscf_ctx {
   // the statistics are requested, so the timed work is not synchronised
   struct ProfRec {
     hipEvent_t e0, e1;
-    int q, kind;   // class index; kind: 0 Fock class kernel, 1 gradient class kernel, 2 whole build
+    int q, kind;   // class index; kind: 0 Fock class kernel, 1 gradient class kernel, 2 whole
+                   // build, 3 exchange-correlation step q (XcStep)
   };
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> prof_free;
@@ -324,6 +325,10 @@ struct bscf_ctx {
   int private_bytes[kNumQuartetClasses][3] = {};
   int coop_bytes[kNumQuartetClasses][2] = {};   // cooperative fock, gradient
   double t_fock_gpu_ms = 0, t_work_ms = 0;
+  // exchange-correlation builds: kernel time per step (HIP events, with
+  // profiling), launches, builds, grid points evaluated and GEMM FLOPs
+  double xc_ms[5] = {}, xc_points = 0, xc_gemm_flops = 0;
+  long long xc_launches[5] = {}, xc_builds = 0;
   double t_work_host_ms = 0;   // host part of the work lists, wherever it ran
   double t_work_phase_ms[3] = {0, 0, 0};   // its ket lists, parts, merges
   rocblas_handle blas = nullptr;
@@ -493,9 +498,15 @@ struct bscf_ctx {
     bool tables = false;
     bool grid_ok = false;               // the grid of the current geometry is on the device
     std::vector<long long> pt_off;      // per instance: first grid point
+    std::vector<int> npts_i;            // per instance: grid points
     long long npts = 0;
     DevBuf<double> rad_r, rad_w, ang_u, ang_w, pts;
-    DevBuf<double> B, Bx, By, Bz, Z;    // chunk buffers, [n_max][kXcChunk]
+    DevBuf<long long> d_pt_off;
+    DevBuf<int> d_npts, d_sh_off, d_nsh;
+    DevBuf<double> B, Z, part;          // chunk buffers [count][n][G], partial sums
+    DevBuf<double> Vp;                  // [count][S][n][n] slice products
+    DevBuf<double*> gp;                 // slice GEMM operands: A, B, C pointer arrays
+    std::vector<double*> hgp;
     DevBuf<double> V, exc;              // V_xc [mtot], E_xc [ninst]
   } xcs;
 
@@ -1307,7 +1318,8 @@ void prof_collect(bscf_ctx* c) {
     HIPCHK(hipEventElapsedTime(&ms, r.e0, r.e1));
     if (r.kind == 0) c->work[r.q].kernel_ms += ms;
     else if (r.kind == 1) c->work[r.q].grad_ms += ms;
-    else c->t_fock_gpu_ms += ms;
+    else if (r.kind == 2) c->t_fock_gpu_ms += ms;
+    else c->xc_ms[r.q] += ms;
     c->prof_free.push_back(r.e0);
     c->prof_free.push_back(r.e1);
   }
@@ -1477,7 +1489,17 @@ void autotune_fock(bscf_ctx* c, int pcol) {
 // only the skipped quartets (each bounded by tau) differ from a full build.
 // ------------------------------------------------------------------ B3LYP
 
-constexpr int kXcChunk = 16384;   // grid points per basis-value chunk
+// Chunk buffers hold at most this many doubles each (2 GiB): a run of
+// instances takes its grid points in chunks of G = budget / (count n),
+// a multiple of the slice width kXcSlice
+constexpr size_t kXcBudget = size_t(1) << 28;
+// V += X^T B reduces over the chunk's points; the library GEMM is slow for a
+// reduction dimension far above n, so the chunk is cut into slices of this
+// many points, one batched GEMM covers every (instance, slice) and a kernel
+// sums the slices in order
+constexpr int kXcSlice = 8192;
+// steps of an XC build as timed by the statistics
+enum XcStep { kXcBasis = 0, kXcGemm = 1, kXcPoint = 2, kXcGemmV = 3, kXcWhole = 4 };
 
 // Radial and angular tables of the grid (xc.h), once per context
 void xc_tables(bscf_ctx* c) {
@@ -1540,7 +1562,13 @@ void xc_grid(bscf_ctx* c) {
   for (int i = 0; i < c->ninst; ++i)
     x.pt_off[i + 1] = x.pt_off[i] + (long long)c->natoms[i] * kXcPerAtom;
   x.npts = x.pt_off[c->ninst];
+  x.npts_i.assign(c->ninst, 0);
+  for (int i = 0; i < c->ninst; ++i) x.npts_i[i] = (int)(x.pt_off[i + 1] - x.pt_off[i]);
   x.pts.resize((size_t)4 * x.npts);
+  x.d_pt_off.upload(x.pt_off, c->stream);
+  x.d_npts.upload(x.npts_i, c->stream);
+  x.d_sh_off.upload(c->shell_off, c->stream);
+  x.d_nsh.upload(c->nshell, c->stream);
   for (int i = 0; i < c->ninst; ++i) {
     XcGridArgs g;
     g.npts = (int)(x.pt_off[i + 1] - x.pt_off[i]);
@@ -1558,52 +1586,115 @@ void xc_grid(bscf_ctx* c) {
   x.grid_ok = true;
 }
 
-// V_xc and E_xc of every (active, if masked) instance at the densities P
+// V_xc and E_xc of every (active, if masked) instance at the densities P:
+// per run of consecutive active instances of one group (equal basis size),
+// batched over the run's instances, in chunks of grid points
 void xc_build(bscf_ctx* c, const double* P, bool masked) {
   auto& x = c->xcs;
   xc_grid(c);
-  const size_t chunk = (size_t)c->max_n * kXcChunk;
-  for (DevBuf<double>* b : {&x.B, &x.Bx, &x.By, &x.Bz, &x.Z}) b->resize(chunk);
   x.V.resize(c->mtot);
   x.exc.resize(c->ninst);
-  launch_fill(x.exc.p, c->ninst, 0.0, c->stream);
   const hipStream_t st = c->stream;
-  for (int i = 0; i < c->ninst; ++i) {
-    if (masked && !c->h_active[i]) continue;
-    const int n = c->nbf[i];
-    double* V = x.V.p + c->moff[i];
-    const double* Pi = P + c->moff[i];
-    const long long np = x.pt_off[i + 1] - x.pt_off[i];
-    for (long long g0 = 0; g0 < np; g0 += kXcChunk) {
+  const int pw = c->profiling ? prof_begin(c, kXcWhole, 3, st) : -1;
+  launch_fill(x.exc.p, c->ninst, 0.0, st);
+  // one XC step, bracketed by events when profiling
+  auto step = [&](int q, auto&& f) {
+    const int pk = c->profiling ? prof_begin(c, q, 3, st) : -1;
+    f();
+    if (pk >= 0) prof_end(c, pk, st);
+    c->xc_launches[q]++;
+  };
+  for (const Group& gr : c->groups) {
+    for (int r0 = gr.first; r0 < gr.first + gr.count;) {
+      if (masked && !c->h_active[r0]) {
+        ++r0;
+        continue;
+      }
+      int r1 = r0;
+      while (r1 < gr.first + gr.count && (!masked || c->h_active[r1])) ++r1;
+      const int count = r1 - r0, n = gr.n;
+      int np_max = 0, nsh_max = 0;
+      for (int i = r0; i < r1; ++i) {
+        np_max = std::max(np_max, x.npts_i[i]);
+        nsh_max = std::max(nsh_max, c->nshell[i]);
+      }
+      int slice = kXcSlice;
+      int cap = (int)std::min<size_t>(kXcBudget / ((size_t)count * n), 1 << 30);
+      if (const char* e = std::getenv("BSCF_XC_CHUNK")) {   // chunk width (tests)
+        cap = std::min(cap, std::atoi(e));
+        slice = std::max(256, std::min(slice, cap / 2 / 256 * 256));
+      }
+      cap = std::max(slice, cap / slice * slice);
+      const int G = std::min((np_max + slice - 1) / slice * slice, cap);
+      const int S = G / slice;
+      x.B.resize((size_t)count * n * G);
+      x.Z.resize((size_t)count * n * G);
+      x.part.resize((size_t)count * (G / 256));
+      x.Vp.resize((size_t)count * S * n * n);
+      x.hgp.resize((size_t)3 * count * S);
+      for (int i = 0; i < count; ++i)
+        for (int sl = 0; sl < S; ++sl) {
+          const size_t k = (size_t)i * S + sl, o = (size_t)i * n * G + (size_t)sl * slice;
+          x.hgp[k] = x.Z.p + o;
+          x.hgp[(size_t)count * S + k] = x.B.p + o;
+          x.hgp[(size_t)2 * count * S + k] = x.Vp.p + k * n * n;
+        }
+      x.gp.resize(x.hgp.size());
+      HIPCHK(hipMemcpyAsync(x.gp.p, x.hgp.data(), x.hgp.size() * sizeof(const double*),
+                            hipMemcpyHostToDevice, st));
       XcChunkArgs a;
-      a.g0 = (int)g0;
-      a.ng = (int)std::min<long long>(kXcChunk, np - g0);
+      a.G = G;
       a.n = n;
-      a.sh0 = c->shell_off[i];
-      a.nsh = c->nshell[i];
+      a.first = r0;
+      a.npts = x.d_npts.p;
+      a.pt_off = x.d_pt_off.p;
+      a.sh_off = x.d_sh_off.p;
+      a.nsh = x.d_nsh.p;
       a.shells = c->d_shells.p;
       a.sh_exp = c->d_sh_exp.p;
       a.sh_coef = c->d_sh_coef.p;
-      a.pts = x.pts.p + 4 * x.pt_off[i];
+      a.pts = x.pts.p;
       a.B = x.B.p;
-      a.Bx = x.Bx.p;
-      a.By = x.By.p;
-      a.Bz = x.Bz.p;
       a.Z = x.Z.p;
-      a.exc = x.exc.p + i;
-      launch_xc_basis(a, st);
-      // Z = B P: function-major B is the column-major ng x n matrix
+      a.part = x.part.p;
+      const long long sBZ = (long long)n * G, sP = (long long)n * n;
+      double* V = x.V.p + c->moff[r0];
       const double one = 1.0, zero = 0.0;
-      BLASCHK(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, a.ng, n, n,
-                            &one, x.B.p, a.ng, Pi, n, &zero, x.Z.p, a.ng));
-      launch_xc_point(a, st);   // Z <- X
-      // V (column-major) += X^T B over the chunk; V + V^T at the end
-      const double beta = g0 == 0 ? 0.0 : 1.0;
-      BLASCHK(rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, n, n,
-                            a.ng, &one, x.Z.p, a.ng, x.B.p, a.ng, &beta, V, n));
+      for (int g0 = 0; g0 < np_max; g0 += G) {
+        a.g0 = g0;
+        step(kXcBasis, [&] { launch_xc_basis(a, count, nsh_max, st); });
+        // Z = B P: each function-major B is a column-major G x n matrix
+        step(kXcGemm, [&] {
+          BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none,
+                                                rocblas_operation_none, G, n, n, &one, x.B.p, G,
+                                                sBZ, P + c->moff[r0], n, sP, &zero, x.Z.p, G, sBZ,
+                                                count));
+        });
+        step(kXcPoint, [&] {
+          launch_xc_point(a, count, st);   // Z <- X
+          launch_xc_reduce(a, count, x.exc.p, st);
+        });
+        // V (column-major) += X^T B over the chunk: one product per
+        // (instance, slice), then their sum; V + V^T at the end (a rank-2k
+        // update would do both, but the library's is far slower at k >> n)
+        step(kXcGemmV, [&] {
+          const double* const* pa = x.gp.p;
+          const double* const* pb = x.gp.p + (size_t)count * S;
+          BLASCHK(rocblas_dgemm_batched(c->blas, rocblas_operation_transpose,
+                                        rocblas_operation_none, n, n, slice, &one, pa, G, pb, G,
+                                        &zero, x.gp.p + (size_t)2 * count * S, n, count * S));
+          launch_xc_slice_sum(n, count, S, x.Vp.p, V, g0 > 0, st);
+        });
+        c->xc_gemm_flops += 4.0 * G * (double)n * n * count;
+      }
+      for (int i = r0; i < r1; ++i) c->xc_points += x.npts_i[i];
+      launch_xc_symmetrize(n, count, V, st);
+      r0 = r1;
     }
-    launch_xc_symmetrize(n, V, st);
   }
+  if (pw >= 0) prof_end(c, pw, st);
+  c->xc_launches[kXcWhole]++;
+  c->xc_builds++;
   HIPCHK(hipGetLastError());
 }
 
@@ -3228,6 +3319,12 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
     c->sp2_calls = c->sp2_steps = c->sp2_needed = c->sp2_fallbacks = 0;
     c->inc_builds = 0;
     c->graph_launches = c->graph_captures = 0;
+    for (int k = 0; k < 5; ++k) {
+      c->xc_ms[k] = 0;
+      c->xc_launches[k] = 0;
+    }
+    c->xc_builds = 0;
+    c->xc_points = c->xc_gemm_flops = 0;
   });
 }
 
@@ -3248,7 +3345,12 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
       << ", \"sp2_steps_needed\": " << c->sp2_needed
       << ", \"sp2_fallbacks\": " << c->sp2_fallbacks << ", \"incremental_builds\": " << c->inc_builds
       << ", \"graph_launches\": " << c->graph_launches << ", \"graph_captures\": " << c->graph_captures
-      << ", \"classes\": {";
+      << ", \"xc\": {\"builds\": " << c->xc_builds << ", \"points\": " << c->xc_points
+      << ", \"gemm_flops\": " << c->xc_gemm_flops << ", \"ms\": {";
+    const char* xn[5] = {"basis", "gemm", "point", "gemm_v", "build"};
+    for (int k = 0; k < 5; ++k)
+      s << (k ? ", " : "") << "\"" << xn[k] << "\": [" << c->xc_ms[k] << ", " << c->xc_launches[k] << "]";
+    s << "}}, \"classes\": {";
     const QuartetClass* qc = quartet_classes();
     for (int q = 0; q < kNumQuartetClasses; ++q) {
       const auto& W = c->work[q];

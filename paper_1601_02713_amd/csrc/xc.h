@@ -11,11 +11,13 @@
 // correction + 0.19 VWN (RPA fit) + 0.81 LYP, with 0.2 of the exact exchange;
 // closed shell, rho the total density and sigma = |grad rho|^2.
 //
-// Per instance and chunk of grid points: basis values and gradients B, Bx,
-// By, Bz, function-major [n][points] (xc_basis), Z = B P (a GEMM), density,
-// gradient and the functional per point with
-// X = w (v_rho B / 2 + 2 v_sigma grad rho . grad B) written over Z (xc_point),
-// then V += X^T B (a GEMM); V_xc = V + V^T at the end.
+// Per run of consecutive instances with equal basis size and per chunk of G
+// grid points: basis values B, function-major [inst][n][G] (xc_basis);
+// Z = B P (a strided-batched GEMM); per point the density, its gradient (basis
+// gradients recomputed on the fly, never stored) and the functional, and
+// X = w (v_rho B / 2 + 2 v_sigma grad rho . grad B) written over Z
+// (xc_point); then V = X^T B accumulated over the chunks (a batched GEMM
+// per slice of the chunk's points and their sum) and V + V^T at the end.
 #pragma once
 #include "common.h"
 
@@ -41,26 +43,34 @@ struct XcGridArgs {
 };
 
 struct XcChunkArgs {
-  int g0, ng;               // points [g0, g0 + ng) of the instance
-  int n;                    // basis functions of the instance
-  int sh0, nsh;             // its shells in the shell table
+  int G;                    // chunk width: the leading dimension of B and Z
+  int g0;                   // first point of the chunk (per instance)
+  int n;                    // basis functions of every instance of the run
+  int first;                // first instance of the run
+  const int* npts;          // [ninst] grid points per instance
+  const long long* pt_off;  // [ninst] first point of each instance in pts
+  const int* sh_off;        // [ninst] first shell of each instance
+  const int* nsh;           // [ninst] shells per instance
   const Shell* shells;
   const double* sh_exp;
   const double* sh_coef;
-  const double* pts;        // the instance's [npts][4]
-  double* B;                // [n][ng] (function-major) values
-  double* Bx;               // and gradients
-  double* By;
-  double* Bz;
-  double* Z;                // [n][ng]: B P, then (xc_point) X
-  double* exc;              // accumulates sum_g w e
+  const double* pts;        // [sum npts][4]: x, y, z, weight
+  double* B;                // [count][n][G] basis values
+  double* Z;                // [count][n][G]: B P, then (xc_point) X
+  double* part;             // [count][G / 256] partial sums of w e per block
 };
 
 void launch_xc_grid(const XcGridArgs& a, hipStream_t s);
-void launch_xc_basis(const XcChunkArgs& a, hipStream_t s);
-void launch_xc_point(const XcChunkArgs& a, hipStream_t s);
-// V (n x n, row-major) = M + M^T, in place
-void launch_xc_symmetrize(int n, double* V, hipStream_t s);
+// count instances of the run, at most max_nsh shells each
+void launch_xc_basis(const XcChunkArgs& a, int count, int max_nsh, hipStream_t s);
+void launch_xc_point(const XcChunkArgs& a, int count, hipStream_t s);
+// exc[first + i] += sum of the G / 256 partial sums of instance i, in order
+void launch_xc_reduce(const XcChunkArgs& a, int count, double* exc, hipStream_t s);
+// V[i] = (add ? V[i] : 0) + sum over s < S of Vp[i][s] (n x n each), i < count
+void launch_xc_slice_sum(int n, int count, int S, const double* Vp, double* V, bool add,
+                         hipStream_t s);
+// count n x n matrices (stride n^2): M <- M + M^T
+void launch_xc_symmetrize(int n, int count, double* V, hipStream_t s);
 // e, v_rho, v_sigma of the closed-shell B3LYP energy density at n points
 void launch_xc_functional(int n, const double* rho, const double* sigma, double* e, double* vr,
                           double* vs, hipStream_t s);

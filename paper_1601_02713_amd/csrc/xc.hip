@@ -1,6 +1,6 @@
 // Exchange-correlation quadrature kernels (see xc.h).  Basis values and the
-// GEMM operands are function-major, [n][points], so consecutive threads of a
-// point-parallel kernel touch consecutive addresses.
+// GEMM operands are function-major, [inst][n][G], so consecutive threads of a
+// point-parallel kernel touch consecutive addresses.  G is a multiple of 256.
 #include "xc.h"
 
 #include <algorithm>
@@ -123,69 +123,93 @@ __global__ void xc_grid_kernel(XcGridArgs a) {
   o[3] = w;
 }
 
-__device__ __forceinline__ double dfact(int n) {   // n!! for n in -1..3
-  return n == 3 ? 3.0 : 1.0;
-}
-
-// one thread per (point, shell): values and gradients of the shell's
-// Cartesian components (lexicographic), each normalised to unit self-overlap
-__global__ __launch_bounds__(256) void xc_basis_kernel(XcChunkArgs a) {
-  const int gl = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gl >= a.ng) return;
-  const Shell sh = a.shells[a.sh0 + blockIdx.y];
-  const double* pt = a.pts + 4LL * (a.g0 + gl);
-  const double dx = pt[0] - sh.x, dy = pt[1] - sh.y, dz = pt[2] - sh.z;
+// Values (and with Grad, gradients) of the Cartesian components of one shell
+// at displacement (dx, dy, dz) from its centre, lexicographic order, each
+// normalised to unit self-overlap: f(k, value, d/dx, d/dy, d/dz).
+template <bool Grad, class Fn>
+__device__ __forceinline__ void shell_eval(const Shell& sh, const double* __restrict__ ex,
+                                           const double* __restrict__ co, double dx, double dy,
+                                           double dz, Fn&& f) {
   const double r2 = dx * dx + dy * dy + dz * dz;
   double rad = 0.0, drad = 0.0;   // sum c e^{-a r^2} and its r^2-derivative
   for (int k = 0; k < sh.nprim; ++k) {
-    const double al = a.sh_exp[sh.prim0 + k];
-    const double e = a.sh_coef[sh.prim0 + k] * exp(-al * r2);
+    const double al = ex[sh.prim0 + k];
+    const double e = co[sh.prim0 + k] * exp(-al * r2);
     rad += e;
     drad -= al * e;
   }
-  const long long ng = a.ng;
-  int f = sh.bf;
-  const int l = sh.l;
-  for (int lx = l; lx >= 0; --lx)
-    for (int ly = l - lx; ly >= 0; --ly, ++f) {
-      const int lz = l - lx - ly;
-      const double cn = rsqrt(dfact(2 * lx - 1) * dfact(2 * ly - 1) * dfact(2 * lz - 1));
-      const double px = lx == 0 ? 1.0 : (lx == 1 ? dx : dx * dx);
-      const double py = ly == 0 ? 1.0 : (ly == 1 ? dy : dy * dy);
-      const double pz = lz == 0 ? 1.0 : (lz == 1 ? dz : dz * dz);
-      const double qx = lx == 0 ? 0.0 : (lx == 1 ? 1.0 : 2.0 * dx);   // d/dx of x^lx
-      const double qy = ly == 0 ? 0.0 : (ly == 1 ? 1.0 : 2.0 * dy);
-      const double qz = lz == 0 ? 0.0 : (lz == 1 ? 1.0 : 2.0 * dz);
-      const double ang = px * py * pz;
-      const long long o = (long long)f * ng + gl;
-      a.B[o] = cn * ang * rad;
-      a.Bx[o] = cn * (qx * py * pz * rad + ang * 2.0 * dx * drad);
-      a.By[o] = cn * (px * qy * pz * rad + ang * 2.0 * dy * drad);
-      a.Bz[o] = cn * (px * py * qz * rad + ang * 2.0 * dz * drad);
-    }
+  const double gx = 2.0 * dx * drad, gy = 2.0 * dy * drad, gz = 2.0 * dz * drad;
+  if (sh.l == 0) {
+    f(0, rad, gx, gy, gz);
+  } else if (sh.l == 1) {
+    f(0, dx * rad, rad + dx * gx, dx * gy, dx * gz);
+    f(1, dy * rad, dy * gx, rad + dy * gy, dy * gz);
+    f(2, dz * rad, dz * gx, dz * gy, rad + dz * gz);
+  } else {
+    const double r3 = 0.57735026918962576451;   // 1/sqrt(3): xx, yy, zz
+    f(0, r3 * dx * dx * rad, r3 * (2.0 * dx * rad + dx * dx * gx), r3 * dx * dx * gy,
+      r3 * dx * dx * gz);
+    f(1, dx * dy * rad, dy * rad + dx * dy * gx, dx * rad + dx * dy * gy, dx * dy * gz);
+    f(2, dx * dz * rad, dz * rad + dx * dz * gx, dx * dz * gy, dx * rad + dx * dz * gz);
+    f(3, r3 * dy * dy * rad, r3 * dy * dy * gx, r3 * (2.0 * dy * rad + dy * dy * gy),
+      r3 * dy * dy * gz);
+    f(4, dy * dz * rad, dy * dz * gx, dz * rad + dy * dz * gy, dy * rad + dy * dz * gz);
+    f(5, r3 * dz * dz * rad, r3 * dz * dz * gx, r3 * dz * dz * gy,
+      r3 * (2.0 * dz * rad + dz * dz * gz));
+  }
 }
 
-// one thread per point: rho = sum B Z, grad rho = 2 sum grad(B) Z, the
-// functional, and X = w (v_rho B / 2 + 2 v_sigma grad rho . grad B) over Z
+// one thread per (point, shell, instance of the run): the shell's basis
+// values at the point (zero past the instance's last point)
+__global__ __launch_bounds__(256) void xc_basis_kernel(XcChunkArgs a) {
+  const int gl = blockIdx.x * blockDim.x + threadIdx.x;
+  const int zi = blockIdx.z, inst = a.first + zi;
+  if ((int)blockIdx.y >= a.nsh[inst]) return;
+  const Shell sh = a.shells[a.sh_off[inst] + blockIdx.y];
+  double* Bc = a.B + ((size_t)zi * a.n + sh.bf) * a.G + gl;
+  const int p = a.g0 + gl;
+  const int nc = (sh.l + 1) * (sh.l + 2) / 2;
+  if (p >= a.npts[inst]) {
+    for (int k = 0; k < nc; ++k) Bc[(size_t)k * a.G] = 0.0;
+    return;
+  }
+  const double* pt = a.pts + 4 * (a.pt_off[inst] + p);
+  shell_eval<false>(sh, a.sh_exp, a.sh_coef, pt[0] - sh.x, pt[1] - sh.y, pt[2] - sh.z,
+                    [&](int k, double v, double, double, double) { Bc[(size_t)k * a.G] = v; });
+}
+
+// one thread per point: rho = sum B Z, grad rho = 2 sum grad(B) Z (basis
+// gradients recomputed), the functional, then
+// X = w (v_rho B / 2 + 2 v_sigma grad rho . grad B) written over Z; each
+// block's sum of w e to its partial-sum slot
 __global__ __launch_bounds__(256) void xc_point_kernel(XcChunkArgs a) {
   __shared__ double red[256];
   const int gl = blockIdx.x * blockDim.x + threadIdx.x;
+  const int zi = blockIdx.y, inst = a.first + zi;
+  const int p = a.g0 + gl;
   double ew = 0.0;
-  if (gl < a.ng) {
-    const long long ng = a.ng;
+  if (p < a.npts[inst]) {
+    const double* pt = a.pts + 4 * (a.pt_off[inst] + p);
+    const double x = pt[0], y = pt[1], z = pt[2], w = pt[3];
+    double* Zc = a.Z + (size_t)zi * a.n * a.G + gl;
+    const Shell* sh0 = a.shells + a.sh_off[inst];
+    const int nsh = a.nsh[inst];
     double rho = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int m = 0; m < a.n; ++m) {
-      const long long o = (long long)m * ng + gl;
-      const double z = a.Z[o];
-      rho += a.B[o] * z;
-      gx += a.Bx[o] * z;
-      gy += a.By[o] * z;
-      gz += a.Bz[o] * z;
+    for (int s = 0; s < nsh; ++s) {
+      const Shell sh = sh0[s];
+      double* zf = Zc + (size_t)sh.bf * a.G;
+      shell_eval<true>(sh, a.sh_exp, a.sh_coef, x - sh.x, y - sh.y, z - sh.z,
+                       [&](int k, double v, double vx, double vy, double vz) {
+                         const double zz = zf[(size_t)k * a.G];
+                         rho += v * zz;
+                         gx += vx * zz;
+                         gy += vy * zz;
+                         gz += vz * zz;
+                       });
     }
     gx *= 2.0;
     gy *= 2.0;
     gz *= 2.0;
-    const double w = a.pts[4LL * (a.g0 + gl) + 3];
     double cr = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
     if (rho > kXcRhoMin) {
       const Xc f = b3lyp(rho, gx * gx + gy * gy + gz * gz);
@@ -195,26 +219,59 @@ __global__ __launch_bounds__(256) void xc_point_kernel(XcChunkArgs a) {
       cy = 2.0 * w * f.vs * gy;
       cz = 2.0 * w * f.vs * gz;
     }
-    for (int m = 0; m < a.n; ++m) {
-      const long long o = (long long)m * ng + gl;
-      a.Z[o] = cr * a.B[o] + cx * a.Bx[o] + cy * a.By[o] + cz * a.Bz[o];
+    for (int s = 0; s < nsh; ++s) {
+      const Shell sh = sh0[s];
+      double* zf = Zc + (size_t)sh.bf * a.G;
+      shell_eval<true>(sh, a.sh_exp, a.sh_coef, x - sh.x, y - sh.y, z - sh.z,
+                       [&](int k, double v, double vx, double vy, double vz) {
+                         zf[(size_t)k * a.G] = cr * v + cx * vx + cy * vy + cz * vz;
+                       });
     }
   }
   red[threadIdx.x] = ew;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && red[0] != 0.0) atomicAdd(a.exc, red[0]);
+  if (threadIdx.x == 0) a.part[(size_t)zi * (a.G / 256) + blockIdx.x] = red[0];
 }
 
+// one block per instance: its partial sums in a fixed order
+__global__ __launch_bounds__(256) void xc_reduce_kernel(XcChunkArgs a, double* exc) {
+  __shared__ double red[256];
+  const int nb = a.G / 256;
+  const double* pp = a.part + (size_t)blockIdx.x * nb;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) s += pp[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) exc[a.first + blockIdx.x] += red[0];
+}
+
+// V[i] (+)= sum over s of Vp[i][s], s in order
+__global__ void xc_slice_sum_kernel(int n, int S, const double* Vp, double* V, int add) {
+  const size_t nn = (size_t)n * n;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  const double* src = Vp + (size_t)blockIdx.y * S * nn + e;
+  double acc = add ? V[(size_t)blockIdx.y * nn + e] : 0.0;
+  for (int s = 0; s < S; ++s) acc += src[(size_t)s * nn];
+  V[(size_t)blockIdx.y * nn + e] = acc;
+}
+
+// M <- M + M^T for each of the run's n x n matrices
 __global__ void xc_symmetrize_kernel(int n, double* V) {
   const int i = blockIdx.y, j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n || j < i) return;
-  const double s = V[(long long)i * n + j] + V[(long long)j * n + i];
-  V[(long long)i * n + j] = s;
-  V[(long long)j * n + i] = s;
+  double* M = V + (size_t)blockIdx.z * n * n;
+  const double s = M[(size_t)i * n + j] + M[(size_t)j * n + i];
+  M[(size_t)i * n + j] = s;
+  M[(size_t)j * n + i] = s;
 }
 
 __global__ void xc_functional_kernel(int n, const double* rho, const double* sigma, double* e,
@@ -234,18 +291,32 @@ void launch_xc_grid(const XcGridArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(xc_grid_kernel, dim3((a.npts + 255) / 256), dim3(256), 0, s, a);
 }
 
-void launch_xc_basis(const XcChunkArgs& a, hipStream_t s) {
-  if (a.ng == 0 || a.nsh == 0) return;
-  hipLaunchKernelGGL(xc_basis_kernel, dim3((a.ng + 255) / 256, a.nsh), dim3(256), 0, s, a);
+void launch_xc_basis(const XcChunkArgs& a, int count, int max_nsh, hipStream_t s) {
+  if (count == 0 || max_nsh == 0) return;
+  hipLaunchKernelGGL(xc_basis_kernel, dim3(a.G / 256, max_nsh, count), dim3(256), 0, s, a);
 }
 
-void launch_xc_point(const XcChunkArgs& a, hipStream_t s) {
-  if (a.ng == 0) return;
-  hipLaunchKernelGGL(xc_point_kernel, dim3((a.ng + 255) / 256), dim3(256), 0, s, a);
+void launch_xc_point(const XcChunkArgs& a, int count, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(xc_point_kernel, dim3(a.G / 256, count), dim3(256), 0, s, a);
 }
 
-void launch_xc_symmetrize(int n, double* V, hipStream_t s) {
-  hipLaunchKernelGGL(xc_symmetrize_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, n, V);
+void launch_xc_reduce(const XcChunkArgs& a, int count, double* exc, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(xc_reduce_kernel, dim3(count), dim3(256), 0, s, a, exc);
+}
+
+void launch_xc_slice_sum(int n, int count, int S, const double* Vp, double* V, bool add,
+                         hipStream_t s) {
+  if (count == 0 || n == 0) return;
+  const size_t nn = (size_t)n * n;
+  hipLaunchKernelGGL(xc_slice_sum_kernel, dim3((unsigned)((nn + 255) / 256), count), dim3(256), 0,
+                     s, n, S, Vp, V, add ? 1 : 0);
+}
+
+void launch_xc_symmetrize(int n, int count, double* V, hipStream_t s) {
+  if (count == 0 || n == 0) return;
+  hipLaunchKernelGGL(xc_symmetrize_kernel, dim3((n + 255) / 256, n, count), dim3(256), 0, s, n, V);
 }
 
 void launch_xc_functional(int n, const double* rho, const double* sigma, double* e, double* vr,

@@ -5,9 +5,10 @@ the CPU suite pins to closed forms and to the derivative identities.
 * The energy density and its two derivatives at random (rho, sigma) over
   fifteen decades (analytic derivatives on the device, complex-step ones in
   the oracle).
-* V_xc and E_xc of a ragged batch (H2, water, the water dimer; 4 to 38
-  functions, 34560 to 103680 grid points, so every instance spans several
-  point chunks and ends in a ragged one) at the oracle's core-guess density.
+* V_xc and E_xc of a ragged batch (H2, three water beads batched together,
+  the water dimer; 4 to 38 functions, 34560 to 103680 grid points) at the
+  oracle's core-guess density, with whole-instance chunks and with chunks of
+  9984 points (several per instance, the last one ragged).
 * Kohn-Sham F and E of one build, and converged B3LYP SCF energies.
 * B3LYP forces are refused, and bscf_build_jk ignores the setting.
 """
@@ -68,8 +69,15 @@ def test_functional_matches_oracle(beadscf, b631gs):
         assert err[k] < 1e-11, (name, rho[k], sigma[k], got[k], ref[k])
 
 
-def test_vxc_and_exc_match_oracle(beadscf, b631gs):
-    inst = _batch()
+@pytest.mark.parametrize("chunk", [None, 10000])
+def test_vxc_and_exc_match_oracle(beadscf, b631gs, chunk, monkeypatch):
+    """Three water beads form one batched run; with a chunk width of 9984
+    points every instance takes several chunks and ends in a ragged one."""
+    if chunk:
+        monkeypatch.setenv("BSCF_XC_CHUNK", str(chunk))
+    h2, w, d = _batch()
+    wb = inputs.beads(w[0], w[1], 3, 21)
+    inst = [h2] + [(w[0], x) for x in wb] + [d]
     e = _engine(beadscf, b631gs, inst)
     try:
         bs = [oracle.build_basis(b631gs, z, x) for z, x in inst]
