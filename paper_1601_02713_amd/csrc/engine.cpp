@@ -427,6 +427,10 @@ struct bscf_ctx {
   DevBuf<double> d_boys64;
   DevBuf<float> d_boys32;
   DevBuf<int> d_nocc, d_nbf, d_natoms, d_atom_off, d_active, d_all_active, d_conv_iter, d_status;
+  DevBuf<int> d_shell_off, d_nshell;     // per instance
+  DevBuf<long long> d_pm_off;            // per instance: offset of its shell-block max |P|
+  DevBuf<double> d_pmax;                 // [sum nsh^2] largest |P| per shell block
+  int max_nshell = 0;
   DevBuf<long long> d_moff;
   DevBuf<double> d_xyz, d_Zd, d_Enuc, d_E, d_Eprev, d_emax, d_grad;
   DevBuf<double> d_grad_tune;   // [3 total_atoms]: the gradient kernels' timing pass writes here
@@ -2085,6 +2089,20 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->d_moff.upload(c->moff, s);
     c->d_natoms.upload(c->natoms, s);
     c->d_atom_off.upload(c->atom_off, s);
+    {
+      std::vector<long long> po(c->ninst);
+      long long t = 0;
+      c->max_nshell = 0;
+      for (int i = 0; i < c->ninst; ++i) {
+        po[i] = t;
+        t += (long long)c->nshell[i] * c->nshell[i];
+        c->max_nshell = std::max(c->max_nshell, c->nshell[i]);
+      }
+      c->d_pm_off.upload(po, s);
+      c->d_pmax.resize((size_t)std::max(t, 1LL));
+      c->d_shell_off.upload(c->shell_off, s);
+      c->d_nshell.upload(c->nshell, s);
+    }
     std::vector<double> zd(c->Zs.begin(), c->Zs.end());
     c->d_Zd.upload(zd, s);
     c->d_sh_exp.upload(c->sh_exp, s);
@@ -2600,6 +2618,15 @@ void forces_impl(bscf_ctx* c, double* Fout) {
     ga.grad = c->d_grad.p;
     ga.boys64 = c->d_boys64.p;
     ga.unit_threads = 64;
+    // density-weighted screening at the lists' Schwarz cutoff
+    ga.Q = c->d_Q.p;
+    ga.Pm = c->d_pmax.p;
+    ga.pm_off = c->d_pm_off.p;
+    ga.shell_off = c->d_shell_off.p;
+    ga.nsh = c->d_nshell.p;
+    ga.tau = c->work_tau;
+    launch_shell_pmax(c->ninst, c->max_nshell, c->d_shell_off.p, c->d_nshell.p, c->d_pm_off.p,
+                      c->d_shells.p, c->d_moff.p, c->d_nbf.p, c->P.p, c->d_pmax.p, st);
     launch_gather_pk(ketpos_args(c), c->max_ncd, c->P.p, c->d_Pk.p, st);
     auto set_gclass = [](GradArgs& g, const bscf_ctx::ClassWork& W) {
       g.items = W.d_items.p;

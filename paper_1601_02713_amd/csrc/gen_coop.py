@@ -394,6 +394,24 @@ def threads_per_block(prog, grad, lds_per_cu=160 * 1024):
     return max(64, min(nt, 512, (med // 64) * 64))
 
 
+def grad_quartets_per_block(prog, budget=56 * 1024):
+    """Quartets per block of the cooperative gradient: the largest power of
+    two up to 8 whose LDS stays within `budget` bytes (table loads and the
+    per-primitive set-up are shared by the block's quartets)."""
+    per = 8 * lds_doubles(prog, True)
+    qb = 1
+    while qb < 8 and 2 * qb * per <= budget:
+        qb *= 2
+    return qb
+
+
+def grad_block_threads(prog):
+    """Threads of a cooperative gradient block: the per-quartet count times
+    the quartets per block, at most 256 (never fewer than one quartet's)."""
+    nt = threads_per_block(prog, True)
+    return max(nt, min(256, nt * grad_quartets_per_block(prog)))
+
+
 def emit_tables(name, prog, grad=False):
     """C++ constant tables of one program (namespace-scope __device__)."""
     def arr(t, nm, v):
@@ -405,6 +423,12 @@ def emit_tables(name, prog, grad=False):
             body = ", ".join(str(int(x)) for x in v)
         return f"__device__ const {t} {name}_{nm}[{max(len(v), 1)}] = {{{body or '0'}}};"
     out = [f"// cooperative tables: {prog['nslot']} LDS slots, L = {prog['L']}"]
+    # the kernels rely on these: accumulator k in slot k, at most five terms
+    # per VRR node and two per HRR node (coop_kernel.h, kVrrTerms / kHrrTerms)
+    assert list(prog["acc_slot"]) == list(range(prog["nacc"]))
+    for ph, mx in (("vrr", 5), ("hrr", 2)):
+        t0 = prog[ph][2]
+        assert all(t0[i + 1] - t0[i] <= mx for i in range(len(t0) - 1)), (ph, prog["lsh"])
     for ph in ("vrr", "hrr"):
         ls, nodes, terms = pack_phase(prog[ph])
         out += [arr("int", f"{ph}_lstart", ls), arr("unsigned long long", f"{ph}_node", nodes),

@@ -448,7 +448,9 @@ def coop_tu(la, lb, lc, ld):
             acc += [f"  __device__ static const {t}* {f}() {{ return {prefix}_{f}; }}"
                     for t, f in [("int", "con_lstart"), ("unsigned long long", "con_word"),
                                  ("double", "con_ctab")]]
-            extra = f", NCLEV = {len(p['con_lstart']) - 1}, NCTAB = {len(set(p['con_c']))}"
+            extra = (f", NCLEV = {len(p['con_lstart']) - 1}, NCTAB = {len(set(p['con_c']))}"
+                     f";\n  static constexpr int QB = {gen_coop.grad_quartets_per_block(p)}, "
+                     f"NTQ = {gen_coop.grad_block_threads(p)};   // quartets and threads per block")
         else:
             acc += [f"  __device__ static const {t}* {f}() {{ return {prefix}_{f}; }}"
                     for t, f in [("unsigned short", "out_slot"), ("double", "norm")]]
@@ -473,7 +475,7 @@ def coop_tu(la, lb, lc, ld):
              "}",
              f"void launch_coop_grad_{tag}(const GradArgs& a, hipStream_t s) {{",
              "  if (a.nitems == 0) return;",
-             f"  hipLaunchKernelGGL((coop_grad_kernel<CoopG{tag}>), dim3(coop_blocks(a.nitems)), dim3(CoopG{tag}::NT), 0, s, a);",
+             f"  hipLaunchKernelGGL((coop_grad_kernel<CoopG{tag}>), dim3(coop_blocks_q(a.nitems, CoopG{tag}::QB)), dim3(CoopG{tag}::NTQ), 0, s, a);",
              "}",
              f"void launch_coop_tensor_{tag}(const TensorArgs& a, hipStream_t s) {{",
              "  if (a.nquart == 0) return;",

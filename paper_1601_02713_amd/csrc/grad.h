@@ -29,7 +29,28 @@ struct GradArgs {
   double* grad;            // [total atoms][3], dE/dR accumulated
   const double* boys64;
   int unit_threads;        // threads of a lane-kernel unit: 64, 128 or 256
+  // density-weighted screening of the cooperative kernels: a quartet is
+  // skipped when Q_ab Q_cd (Pm_ab Pm_cd + (Pm_ac Pm_bd + Pm_ad Pm_bc) / 4) <
+  // tau, with Pm the largest |P| of each shell-pair block (tau <= 0: none)
+  const double* Q;         // Schwarz bound per shell pair
+  const double* Pm;        // per instance [nsh][nsh] at pm_off
+  const long long* pm_off;
+  const int* shell_off;    // first global shell of each instance
+  const int* nsh;          // shells per instance
+  double tau;
 };
+
+// Density-weighted bound of quartet (bid|kid) (see GradArgs).
+__device__ __forceinline__ double grad_quartet_bound(const GradArgs& a, int bid, int kid) {
+  const ShellPair bra = a.pairs[bid], ket = a.pairs[kid];
+  const int inst = a.shells[bra.a].inst;
+  const int s0 = a.shell_off[inst], ns = a.nsh[inst];
+  const double* M = a.Pm + a.pm_off[inst];
+  const int i = bra.a - s0, j = bra.b - s0, k = ket.a - s0, l = ket.b - s0;
+  const double g = M[i * ns + j] * M[k * ns + l] +
+                   0.25 * (M[i * ns + k] * M[j * ns + l] + M[i * ns + l] * M[j * ns + k]);
+  return a.Q[bid] * a.Q[kid] * g;
+}
 
 // LDS footprint of the gradient unit kernel: P rows of the bra shells, one
 // dE/dR accumulator triple per atom of the instance and the bra's primitive

@@ -225,7 +225,10 @@ __global__ __launch_bounds__(256) void grad_unit_kernel(GradArgs a) {
     const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
     const double deg = ((bra.a == bra.b) ? 1.0 : 2.0) * ((ket.a == ket.b) ? 1.0 : 2.0) *
                        ((kid == bid) ? 1.0 : 2.0);
-    const double fac = valid ? 0.5 * deg : 0.0;
+    // density-weighted screening (GradArgs): a wavefront whose quartets are
+    // all below the bound skips the integrals
+    const bool keep = valid && !(a.tau > 0.0 && grad_quartet_bound(a, bid, kid) < a.tau);
+    const double fac = keep ? 0.5 * deg : 0.0;
     const int l0 = sc.bf, s0 = sd.bf;
     // density factors of the quartet (Coulomb and exchange terms)
     auto gfill = [&](double* G) {
@@ -248,21 +251,23 @@ __global__ __launch_bounds__(256) void grad_unit_kernel(GradArgs a) {
     };
     double g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int2 kp = a.kpos[pos];
-    if constexpr (CG::LA + CG::LB + CG::LC + CG::LD >= 5) {
-      double G[NOUT];
-      gfill(G);
-      grad_block_outline<CG>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64,
-                             G, g9);
-    } else {
-      grad_block_lane<CG>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64,
-                          gfill, g9);
+    if (keep) {
+      if constexpr (CG::LA + CG::LB + CG::LC + CG::LD >= 5) {
+        double G[NOUT];
+        gfill(G);
+        grad_block_outline<CG>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64,
+                               G, g9);
+      } else {
+        grad_block_lane<CG>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64,
+                            gfill, g9);
+      }
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       gA[d] += g9[d];
       gB[d] += g9[3 + d];
     }
-    if (valid) {
+    if (keep) {
       const int ac = sc.atom - a0, ad = sd.atom - a0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {

@@ -92,6 +92,34 @@ void launch_gather_prims(int n, const int* map, const PrimPair* src, PrimPair* d
   hipLaunchKernelGGL(gather_prims_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, map, src, dst);
 }
 
+namespace {
+// largest |P| of every shell-pair block of every instance
+__global__ void shell_pmax_kernel(const int* shell_off, const int* nsh, const long long* pm_off,
+                                  const Shell* shells, const long long* moff, const int* nbf,
+                                  const double* P, double* Pm) {
+  const int inst = blockIdx.y, ns = nsh[inst];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ns * ns) return;
+  const int s = e / ns, t = e - s * ns;
+  const Shell a = shells[shell_off[inst] + s], b = shells[shell_off[inst] + t];
+  const int na = (a.l + 1) * (a.l + 2) / 2, nb = (b.l + 1) * (b.l + 2) / 2, n = nbf[inst];
+  const double* M = P + moff[inst];
+  double m = 0.0;
+  for (int i = 0; i < na; ++i)
+    for (int j = 0; j < nb; ++j) m = fmax(m, fabs(M[(long long)(a.bf + i) * n + b.bf + j]));
+  Pm[pm_off[inst] + e] = m;
+}
+}  // namespace
+
+void launch_shell_pmax(int ninst, int max_nsh, const int* shell_off, const int* nsh,
+                       const long long* pm_off, const Shell* shells, const long long* moff,
+                       const int* nbf, const double* P, double* Pm, hipStream_t s) {
+  if (ninst == 0 || max_nsh == 0) return;
+  const long long nn = (long long)max_nsh * max_nsh;
+  hipLaunchKernelGGL(shell_pmax_kernel, dim3((unsigned)((nn + 255) / 256), ninst), dim3(256), 0, s,
+                     shell_off, nsh, pm_off, shells, moff, nbf, P, Pm);
+}
+
 void launch_gather_pk(const KetPosArgs& a, int max_ncd, const double* P, double* Pk,
                       hipStream_t s) {
   const long long n = (long long)max_ncd * a.nk_total;

@@ -97,6 +97,11 @@ struct KetPosArgs {
 // dst[t] = src[map[t]] for the n primitive-pair records of the ket order
 void launch_gather_prims(int n, const int* map, const PrimPair* src, PrimPair* dst, hipStream_t s);
 // Pk[e * nk_total + pos] = P(c_k, d_l)
+// Pm[pm_off[i] + s nsh[i] + t] = max |P| over the block of local shells s, t
+// of instance i (density-weighted screening of the gradient)
+void launch_shell_pmax(int ninst, int max_nsh, const int* shell_off, const int* nsh,
+                       const long long* pm_off, const Shell* shells, const long long* moff,
+                       const int* nbf, const double* P, double* Pm, hipStream_t s);
 void launch_gather_pk(const KetPosArgs& a, int max_ncd, const double* P, double* Pk,
                       hipStream_t s);
 // J(c_k, d_l) += Jk[e * nk_total + pos], then Jk = 0 (ready for the next build)
