@@ -87,12 +87,19 @@ def cpu_baseline(w, seconds: float):
         _, _, nq = oracle.jk_sample(b, P, stride, nt, 1e-12, Q)
         return nq, time.perf_counter() - t0
 
-    nq, t = rate(4096, threads)           # probe
-    full = nq * 4096
-    stride = max(1, int(full / max(nq / t * seconds, 1.0)))
-    nq, t = rate(stride, threads)
-    s1 = max(1, int(full / max(nq / t / threads * seconds / 3, 1.0)))
-    nq1, t1 = rate(s1, 1)
+    def sized(stride, nt, target):
+        # a short probe underestimates the rate (fixed costs), so the stride
+        # is refined until the sample takes about the target time
+        nq, t = rate(stride, nt)
+        for _ in range(4):
+            if t >= 0.5 * target or stride == 1:
+                break
+            stride = max(1, int(stride * t / target))
+            nq, t = rate(stride, nt)
+        return stride, nq, t
+
+    stride, nq, t = sized(4096, threads, seconds)
+    s1, nq1, t1 = sized(stride * threads, 1, seconds / 3)
     return dict(value=nq / t, unit="screened shell-quartets/s", cores=threads, kind="oracle",
                 cpu_model=cpu_model(), one_core_value=nq1 / t1,
                 sample=f"every {stride}th quartet of the canonical Schwarz-screened list of bead 0 of "
@@ -400,11 +407,12 @@ def b3lyp_bench(args):
         eng.set_profiling(False)
         stats = eng.stats()
         nbf = eng.nbf[0]
+        npts = eng.xc_grid_size(0)
         eng.close()
-        return wall, np.array(its[args.warmup:]), Es, stats, nbf
+        return wall, np.array(its[args.warmup:]), Es, stats, nbf, npts
 
-    wall, its, Es, st, nbf = run(True)
-    wall_hf, its_hf, _, st_hf, _ = run(False)
+    wall, its, Es, st, nbf, npts = run(True)
+    wall_hf, its_hf, _, st_hf, _, _ = run(False)
     fs = fock_summary(st, prec == beadscf.BSCF_MIXED, w["label"])
     xr = xc_summary(st, nbf)
     dom = max(xr, key=lambda k: xr[k]["ms"])
@@ -418,7 +426,7 @@ def b3lyp_bench(args):
         "data": "synthetic",
         "config": {"workload": w["label"].replace("RHF", "B3LYP"), "mode": "B3LYP SCF per step",
                    "beads": P, "basis_functions": nbf, "grid": "60 radial x 288 angular per atom",
-                   "grid_points_per_bead": x["points"] / max(x["builds"], 1) / P,
+                   "grid_points_per_bead": npts,
                    "precision": args.precision, "guess": "previous-step orbitals",
                    "scf_e_tol": w["e_tol"], "scf_comm_tol": w["comm_tol"], "schwarz_tol": 1e-12},
         "bead_scf_steps_per_s": float(its.sum()) / wall,
