@@ -133,6 +133,15 @@ def measured_traffic(kernel, workload):
     return None
 
 
+def nout_of(tag):
+    """Cartesian integrals of one shell quartet of class tag ("LaLbLcLd")."""
+    n = 1
+    for ch in tag:
+        l = int(ch)
+        n *= (l + 1) * (l + 2) // 2
+    return n
+
+
 def kernel_name(dom, variant, mixed):
     if variant == "coop":
         return f"coop_fock_kernel<CoopE{dom}>"
@@ -170,8 +179,18 @@ def fock_summary(st, mixed, workload):
     avg_ms = d["kernel_ms"] / d["launches"]
     ach = d["done_flops"] / d["launches"] / (avg_ms * 1e-3) / 1e12
     kname = kernel_name(dom, per_class[dom]["kernel"], mixed)
+    # the same kernel alone: the autotuner's time of a full build and the
+    # algorithmic FLOPs of a full build of the class (the concurrent build
+    # stretches each kernel's own duration)
+    full_flops = d["prim_quartets"] * d["prim_flops"] + d["quartets"] * (
+        d["hrr_flops"] + 12.0 * nout_of(dom))
+    alone = per_class[dom]["alone_ms"]
     roof = {"bound": "alu", "kernel": kname, "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS,
             "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR_TFLOPS,
+            "alone": {"ms_full_build": alone,
+                      "achieved": full_flops / (alone * 1e-3) / 1e12 if alone else None,
+                      "frac": full_flops / (alone * 1e-3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS
+                      if alone else None},
             "traffic": measured_traffic(kname, workload), "traffic_unit": "bytes per launch",
             "launches": d["launches"], "avg_launch_ms": avg_ms,
             "flops_per_launch": d["done_flops"] / d["launches"],

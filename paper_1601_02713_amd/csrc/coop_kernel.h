@@ -204,6 +204,15 @@ __global__ __launch_bounds__(CP::NT) void coop_fock_kernel(FockArgs a) {
   if (!a.active[inst]) return;
   // incremental build: quartets below the density-weighted bound do nothing
   if (a.dpmax && a.Q[bid] * a.Q[kid] * fmin(a.dpmax[inst], 1.0) < a.tau) return;
+  // and those that the bound of their own density-change blocks drops (the
+  // kept counts, taken from the instance bound, lose them)
+  if (a.dPm && fock_block_bound(a, bid, kid) < a.tau) {
+    if (threadIdx.x == 0) {
+      atomicAdd(&a.kept_q[inst], -1.0);
+      atomicAdd(&a.kept_pq[inst], -double(bra.nprim * ket.nprim));
+    }
+    return;
+  }
   const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
   const double CD[3] = {sc_.x - sd.x, sc_.y - sd.y, sc_.z - sd.z};
   coop_primitives<CP>(a.prims + bra.prim0, bra.nprim, a.prims + ket.prim0, ket.nprim, AB, CD,

@@ -430,6 +430,7 @@ struct bscf_ctx {
   DevBuf<int> d_shell_off, d_nshell;     // per instance
   DevBuf<long long> d_pm_off;            // per instance: offset of its shell-block max |P|
   DevBuf<double> d_pmax;                 // [sum nsh^2] largest |P| per shell block
+  DevBuf<double> d_dpm;                  // the same of the density change (incremental builds)
   int max_nshell = 0;
   DevBuf<long long> d_moff;
   DevBuf<double> d_xyz, d_Zd, d_Enuc, d_E, d_Eprev, d_emax, d_grad;
@@ -1361,6 +1362,11 @@ FockArgs fock_args(bscf_ctx* c, double* J, double* K, const int* active) {
   a.Q = c->d_Q.p;
   a.dpmax = nullptr;
   a.tau = 0.0;
+  a.dPm = nullptr;
+  a.pm_off = c->d_pm_off.p;
+  a.shell_off = c->d_shell_off.p;
+  a.nsh = c->d_nshell.p;
+  a.kept_q = a.kept_pq = a.kept_32 = nullptr;
   a.Jfx = a.Kfx = a.Jkfx = nullptr;
   a.unit_threads = 64;
   return a;
@@ -1757,6 +1763,9 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
     a.P = c->dP.p;
     a.dpmax = c->d_dpmax.p;
     a.tau = tau;
+    launch_shell_pmax(c->ninst, c->max_nshell, c->d_shell_off.p, c->d_nshell.p, c->d_pm_off.p,
+                      c->d_shells.p, c->d_moff.p, c->d_nbf.p, c->dP.p, c->d_dpm.p, c->stream);
+    a.dPm = c->d_dpm.p;
     c->inc_builds++;
   } else if (det) {
     launch_fill_u64(2 * c->mtot, c->Jfx.p, c->stream);
@@ -1804,6 +1813,13 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
       run(s);
       if (pk >= 0) prof_end(c, pk, s);
     };
+    if (a.dPm) {   // this class's kept counts, lowered by what the kernels drop
+      const size_t ni = (size_t)c->ninst;
+      a.kept_q = c->d_kept.p + q * ni;
+      a.kept_pq = c->d_kept.p + (kNumQuartetClasses + q) * ni;
+      a.kept_32 = c->fock_variant[pcol][q] == 0 && lane_mode(c, precision, q) == 2
+                      ? c->d_kept.p + (2 * kNumQuartetClasses + q) * ni : nullptr;
+    }
     if (c->fock_variant[pcol][q] == 1) {
       set_class(a, W);
       launch(c->coop_bytes[q][0], [&](hipStream_t s) { qc[q].coop_fock(a, s); });
@@ -2100,6 +2116,7 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
       }
       c->d_pm_off.upload(po, s);
       c->d_pmax.resize((size_t)std::max(t, 1LL));
+      c->d_dpm.resize((size_t)std::max(t, 1LL));
       c->d_shell_off.upload(c->shell_off, s);
       c->d_nshell.upload(c->nshell, s);
     }

@@ -66,6 +66,19 @@ struct FockArgs {
   const double* Q;         // Schwarz bound per shell pair
   const double* dpmax;     // per instance max |dP|
   double tau;
+  // With dPm (incremental builds): the largest |dP| of every shell-pair block
+  // of every instance ([nsh][nsh] at pm_off); a quartet of the kept prefix is
+  // also dropped when Q_ab Q_cd min(largest |dP| of its six blocks, 1) < tau,
+  // and the class's kept counts of its instance (kept_q, kept_pq and, for the
+  // mixed lane form, kept_32, filled from the prefixes) are lowered by what
+  // the kernel drops.
+  const double* dPm;
+  const long long* pm_off;
+  const int* shell_off;
+  const int* nsh;
+  double* kept_q;
+  double* kept_pq;
+  double* kept_32;
   // Deterministic build (Kfx != nullptr): J, K and Jk accumulate in the
   // fixed-point words of fx_add (two per element, same element order) instead
   // of FP64 atomics on J, K and Jk.
@@ -176,6 +189,18 @@ __device__ __forceinline__ void eri_block(const PrimPair* __restrict__ bp, int n
     eri_block_body<CL, R, BW>(reinterpret_cast<const double*>(bp), nb, kp, nk, ks, AB, CD, tab64,
                               tab32, out);
   }
+}
+
+// Q_ab Q_cd min(largest |dP| over the quartet's six blocks, 1)
+__device__ __forceinline__ double fock_block_bound(const FockArgs& a, int bid, int kid) {
+  const ShellPair bra = a.pairs[bid], ket = a.pairs[kid];
+  const int inst = a.shells[bra.a].inst;
+  const int s0 = a.shell_off[inst], ns = a.nsh[inst];
+  const double* M = a.dPm + a.pm_off[inst];
+  const int i = bra.a - s0, j = bra.b - s0, k = ket.a - s0, l = ket.b - s0;
+  const double m = fmax(fmax(fmax(M[i * ns + j], M[k * ns + l]), fmax(M[i * ns + k], M[j * ns + l])),
+                        fmax(M[i * ns + l], M[j * ns + k]));
+  return a.Q[bid] * a.Q[kid] * fmin(m, 1.0);
 }
 
 template <typename T>
@@ -304,6 +329,7 @@ __global__ __launch_bounds__(256) void fock_unit_kernel(FockArgs a) {
       jab[i][j] = 0.0;
     }
   const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
+  double dropped[3] = {0.0, 0.0, 0.0};   // quartets, primitive quartets, FP32 quartets
   // one pass over the quartets of selection sel with integrals of precision RP
   auto pass = [&](auto prec, int sel) {
   using RP = decltype(prec);
@@ -327,6 +353,12 @@ __global__ __launch_bounds__(256) void fock_unit_kernel(FockArgs a) {
     const int pos = a.urows[rr].ket0 + k0;
     const int kid = a.kets[pos];
     const ShellPair ket = a.pairs[kid];
+    if (valid && a.dPm && fock_block_bound(a, bid, kid) < a.tau) {
+      dropped[0] += 1.0;
+      dropped[1] += double(bra.nprim * ket.nprim);
+      if (sel == 2) dropped[2] += 1.0;
+      continue;   // the lanes of this pass that keep their quartet go on
+    }
     const Shell sc = a.shells[ket.a], sd = a.shells[ket.b];
     const double CD[3] = {sc.x - sd.x, sc.y - sd.y, sc.z - sd.z};
     const int2 kp = a.kpos[pos];
@@ -412,6 +444,15 @@ __global__ __launch_bounds__(256) void fock_unit_kernel(FockArgs a) {
     pass(float(0), 2);
   } else {
     pass(R(0), 0);
+  }
+  if (a.dPm) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dropped[k] = wave_sum(dropped[k]);
+    if (lane == 0 && dropped[0] > 0.0) {
+      atomicAdd(&a.kept_q[inst], -dropped[0]);
+      atomicAdd(&a.kept_pq[inst], -dropped[1]);
+      if (a.kept_32 && dropped[2] > 0.0) atomicAdd(&a.kept_32[inst], -dropped[2]);
+    }
   }
   __syncthreads();
   for (int t = tid; t < NR * n; t += nt) {
