@@ -254,6 +254,8 @@ def md_bench(args):
             g = beadscf.GUESS_PREVIOUS
             if use_learned and step >= args.predict_from:
                 g = beadscf.GUESS_LEARNED
+            elif args.guess == "extrapolated":
+                g = beadscf.GUESS_EXTRAPOLATED
             E, it, st, F = eng.pimd_step(opts(prec, g), return_forces=True)
         tt = time.perf_counter()
         if use_learned and step >= 1:
@@ -651,7 +653,7 @@ def main():
                     help="md: w8_beads, w16_beads, w32_beads (default); scf: any named workload")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
                     help="timed path precision (md default mixed, scf default fp64)")
-    ap.add_argument("--guess", choices=["learned", "previous"], default="learned")
+    ap.add_argument("--guess", choices=["learned", "previous", "extrapolated"], default="learned")
     ap.add_argument("--split", type=float, default=1e-4,
                     help="mixed precision: quartets with Q_ab Q_cd below this run in FP32")
     ap.add_argument("--dt-fs", type=float, default=0.25)

@@ -50,7 +50,16 @@ typedef enum {
   BSCF_GUESS_CORE = 0,     /* core-Hamiltonian guess                              */
   BSCF_GUESS_PREVIOUS = 1, /* previous SCF orbitals, re-orthonormalised in new S  */
   BSCF_GUESS_LEARNED = 2,  /* density predicted by the in-run trained network     */
-  BSCF_GUESS_USER = 3      /* density set with bscf_set_density                  */
+  BSCF_GUESS_USER = 3,     /* density set with bscf_set_density                  */
+  BSCF_GUESS_EXTRAPOLATED = 4 /* the occupied orbitals of the last two SCFs of each
+                          instance extrapolated to second order in the step:
+                          C2 aligned to C1 by the orthogonal Procrustes
+                          rotation U = polar(C2^T S C1), C = 2 C1 - C2 U,
+                          re-orthonormalised in the new S (as the previous-step
+                          guess, which it falls back to after one SCF; the core
+                          guess before any).  For MD-like sequences of nearby
+                          geometries (the reuse of orbitals of Section 2,
+                          carried one order further)                          */
 } bscf_guess;
 typedef enum {
   BSCF_DENSITY_SP2 = 0, /* second-order spectral projection of X^T F X (GEMMs only);
@@ -375,8 +384,8 @@ double bscf_boys_table_entry(int m, int k);
  * pair's element types, geometry and displacement, its block of the
  * previous-step guess and of the previous step's residual; output: the
  * residual block, converged minus previous-step density), trained in-run.
- * Every converged SCF that started from the previous-step or learned guess
- * records its residual rows; run_scf with BSCF_GUESS_LEARNED applies the
+ * Every converged SCF that started from the previous-step, extrapolated or
+ * learned guess records its residual rows; run_scf with BSCF_GUESS_LEARNED applies the
  * network once it has been trained, and otherwise (no model, no previous
  * step, or a non-finite or oversized prediction) keeps the previous-step
  * guess and sets BSCF_FALLBACK_USED.  The converged result does not depend on

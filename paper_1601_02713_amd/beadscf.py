@@ -22,7 +22,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 BSCF_FP64, BSCF_MIXED = 0, 1
-GUESS_CORE, GUESS_PREVIOUS, GUESS_LEARNED, GUESS_USER = 0, 1, 2, 3
+GUESS_CORE, GUESS_PREVIOUS, GUESS_LEARNED, GUESS_USER, GUESS_EXTRAPOLATED = 0, 1, 2, 3, 4
 DENSITY_SP2, DENSITY_EIG = 0, 1
 STATUS_MAX_ITER, STATUS_NAN, STATUS_FALLBACK = 1, 2, 4
 XC_NONE, XC_B3LYP = 0, 1

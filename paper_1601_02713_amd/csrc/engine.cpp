@@ -439,6 +439,11 @@ struct bscf_ctx {
   std::vector<int> task_first, task_count;  // per pair class ranges into task arrays
   // matrices
   DevBuf<double> S, T, V, H, X, F, J, K, P, Pnew, W, tmp1, tmp2, err, Fbar, C, Cacc, eig, eigE;
+  // orbitals of the SCF before the last (extrapolated guess), its work buffers,
+  // and per instance the number of SCFs whose orbitals are stored (0, 1, 2)
+  DevBuf<double> Cprev, Cext, Mpol;
+  DevBuf<int> d_cfirst, d_c2ok;
+  std::vector<int> h_ccount;
   DevBuf<double> Pprev, dP, d_dpmax;   // incremental builds: last build's P, its change, max |dP|
   // work kept by incremental builds, [quartets, primitive quartets, FP32
   // quartets][class][instance], accumulated on the device until read
@@ -2154,7 +2159,8 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     const size_t mt = (size_t)c->mtot;
     for (DevBuf<double>* m : {&c->S, &c->T, &c->V, &c->H, &c->X, &c->F, &c->J, &c->K, &c->P,
                               &c->Pnew, &c->W, &c->tmp1, &c->tmp2, &c->err, &c->Fbar, &c->C,
-                              &c->Cacc, &c->eig, &c->eigE, &c->Pprev, &c->dP})
+                              &c->Cacc, &c->eig, &c->eigE, &c->Pprev, &c->dP, &c->Cprev,
+                              &c->Cext, &c->Mpol})
       m->resize(mt);
     // a new batch has zero density until an SCF, a Fock build or
     // bscf_set_density gives it one (a user guess never starts from garbage)
@@ -2186,6 +2192,9 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->have_geom = false;
     c->have_scf = false;
     c->have_C = false;
+    c->h_ccount.assign(n_inst, 0);
+    c->d_cfirst.resize(n_inst);
+    c->d_c2ok.resize(n_inst);
     c->work_tau = c->host_tau = -1.0;
     c->fock_tuned[0] = c->fock_tuned[1] = c->grad_tuned = false;
     c->guess.reset_batch(c->ninst);
@@ -2356,8 +2365,10 @@ __global__ void scale_cols_occ_kernel(int ninst, const long long* moff, const in
     out[o + k] = U[o + k] / sqrt(w[o + k / no]);
 }
 
-// previous-step guess: C_occ' = C_occ (C_occ^T S C_occ)^{-1/2}, P = 2 C' C'^T
-void previous_guess(bscf_ctx* c) {
+// previous-step guess: C_occ' = C_occ (C_occ^T S C_occ)^{-1/2}, P = 2 C' C'^T,
+// with C_occ the first nocc columns of Csrc (default: the last SCF's orbitals)
+void previous_guess(bscf_ctx* c, const double* Csrc = nullptr) {
+  if (!Csrc) Csrc = c->Cacc.p;
   const double one = 1.0, zero = 0.0, two = 2.0;
   for (const Group& g : c->groups) {
     const long long o = c->moff[g.first];
@@ -2365,11 +2376,11 @@ void previous_guess(bscf_ctx* c) {
     const int n = g.n, no = c->nocc[g.first];
     // tmp1 = S C_occ (n x no)
     BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none,
-                                          n, no, n, &one, c->S.p + o, n, st, c->Cacc.p + o, n, st,
+                                          n, no, n, &one, c->S.p + o, n, st, Csrc + o, n, st,
                                           &zero, c->tmp1.p + o, n, st, g.count));
     // eig = C_occ^T S C_occ (no x no, leading dim no)
     BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose,
-                                          rocblas_operation_none, no, no, n, &one, c->Cacc.p + o,
+                                          rocblas_operation_none, no, no, n, &one, Csrc + o,
                                           n, st, c->tmp1.p + o, n, st, &zero, c->eig.p + o, no, st,
                                           g.count));
     BLASCHK(rocsolver_dsyevd_strided_batched(c->blas, rocblas_evect_original, rocblas_fill_upper,
@@ -2391,13 +2402,79 @@ void previous_guess(bscf_ctx* c) {
                                           c->Fbar.p + o, no, st, g.count));
     // C' = C_occ Minv (n x no) -> tmp1
     BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none,
-                                          n, no, no, &one, c->Cacc.p + o, n, st, c->Fbar.p + o, no,
+                                          n, no, no, &one, Csrc + o, n, st, c->Fbar.p + o, no,
                                           st, &zero, c->tmp1.p + o, n, st, g.count));
     BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none,
                                           rocblas_operation_transpose, n, n, no, &two,
                                           c->tmp1.p + o, n, st, c->tmp1.p + o, n, st, &zero,
                                           c->P.p + o, n, st, g.count));
   }
+}
+
+// C2 U - 2 C1 -> -(C_ext) for the instances with two stored SCFs (c2ok), C1
+// otherwise: out = c2ok ? 2 C1 - C2U : C1 over the first nocc columns
+__global__ void extrap_kernel(int ninst, const long long* moff, const int* nbf, const int* nocc,
+                              const int* c2ok, const double* C1, const double* C2U, double* out) {
+  const int inst = blockIdx.y;
+  if (inst >= ninst) return;
+  const long long o = moff[inst], m = (long long)nbf[inst] * nocc[inst];
+  const bool ex = c2ok[inst] != 0;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < m;
+       k += (long long)gridDim.x * blockDim.x)
+    out[o + k] = ex ? 2.0 * C1[o + k] - C2U[o + k] : C1[o + k];
+}
+
+// Second-order orbital extrapolation (BSCF_GUESS_EXTRAPOLATED): align the
+// orbitals before the last (C2) to the last (C1) by the orthogonal Procrustes
+// rotation U = M (M^T M)^{-1/2}, M = C2^T S C1 (occupied columns, current S),
+// take C = 2 C1 - C2 U and re-orthonormalise it as the previous-step guess.
+void extrapolated_guess(bscf_ctx* c) {
+  const double one = 1.0, zero = 0.0;
+  for (const Group& g : c->groups) {
+    const long long o = c->moff[g.first];
+    const long long st = (long long)g.n * g.n;
+    const int n = g.n, no = c->nocc[g.first];
+    // tmp1 = S C1 (n x no); Mpol = C2^T tmp1 (no x no); eig = Mpol^T Mpol
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none,
+                                          n, no, n, &one, c->S.p + o, n, st, c->Cacc.p + o, n, st,
+                                          &zero, c->tmp1.p + o, n, st, g.count));
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose,
+                                          rocblas_operation_none, no, no, n, &one, c->Cprev.p + o,
+                                          n, st, c->tmp1.p + o, n, st, &zero, c->Mpol.p + o, no, st,
+                                          g.count));
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose,
+                                          rocblas_operation_none, no, no, no, &one, c->Mpol.p + o,
+                                          no, st, c->Mpol.p + o, no, st, &zero, c->eig.p + o, no, st,
+                                          g.count));
+    BLASCHK(rocsolver_dsyevd_strided_batched(c->blas, rocblas_evect_original, rocblas_fill_upper,
+                                             no, c->eig.p + o, no, st, c->tmp2.p + o, st,
+                                             c->eigE.p + o, st, c->d_info.p + g.first, g.count));
+  }
+  const long long nn = (long long)c->max_n * c->max_n;
+  const unsigned gx = (unsigned)std::min<long long>((nn + 255) / 256, 1024);
+  hipLaunchKernelGGL(scale_cols_occ_kernel, dim3(gx, c->ninst), dim3(256), 0, c->stream, c->ninst,
+                     c->d_moff.p, c->d_nocc.p, c->eig.p, c->tmp2.p, c->err.p);
+  for (const Group& g : c->groups) {
+    const long long o = c->moff[g.first];
+    const long long st = (long long)g.n * g.n;
+    const int n = g.n, no = c->nocc[g.first];
+    // (M^T M)^{-1/2} = (V w^-1/2) V^T -> Fbar; U = Mpol Fbar -> tmp2; C2 U -> Cext
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none,
+                                          rocblas_operation_transpose, no, no, no, &one,
+                                          c->err.p + o, no, st, c->eig.p + o, no, st, &zero,
+                                          c->Fbar.p + o, no, st, g.count));
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none,
+                                          no, no, no, &one, c->Mpol.p + o, no, st, c->Fbar.p + o,
+                                          no, st, &zero, c->tmp2.p + o, no, st, g.count));
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none,
+                                          n, no, no, &one, c->Cprev.p + o, n, st, c->tmp2.p + o,
+                                          no, st, &zero, c->Cext.p + o, n, st, g.count));
+  }
+  hipLaunchKernelGGL(extrap_kernel, dim3(gx, c->ninst), dim3(256), 0, c->stream, c->ninst,
+                     c->d_moff.p, c->d_nbf.p, c->d_nocc.p, c->d_c2ok.p, c->Cacc.p, c->Cext.p,
+                     c->Cext.p);
+  HIPCHK(hipGetLastError());
+  previous_guess(c, c->Cext.p);
 }
 
 mlp::Batch guess_batch(bscf_ctx* c) {
@@ -2418,14 +2495,21 @@ mlp::Batch guess_batch(bscf_ctx* c) {
   return b;
 }
 
-__global__ void commit_C_kernel(BatchInfo b, const double* src, double* dst) {
+// dst <- src for the active instances; the orbitals dst held move to prev
+// (or, for an instance without stored orbitals (first), src itself)
+__global__ void commit_C_kernel(BatchInfo b, const int* first, const double* src, double* dst,
+                                double* prev) {
   const int inst = blockIdx.y;
   if (!b.active[inst]) return;
   const int n = b.nbf[inst];
   const long long o = b.moff[inst], nn = (long long)n * n;
+  const bool f = first[inst] != 0;
   for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nn;
-       k += (long long)gridDim.x * blockDim.x)
+       k += (long long)gridDim.x * blockDim.x) {
+    const double old = dst[o + k];
+    prev[o + k] = f ? src[o + k] : old;
     dst[o + k] = src[o + k];
+  }
 }
 }  // namespace
 
@@ -2439,6 +2523,8 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     bscf_default_opts(&o);
     if (opts) o = *opts;
     need(o.max_iter > 0 && o.diis_size >= 1 && o.diis_size <= 8, BSCF_E_INVALID, "bad options");
+    need(o.guess >= BSCF_GUESS_CORE && o.guess <= BSCF_GUESS_EXTRAPOLATED, BSCF_E_INVALID,
+         "guess must be a bscf_guess");
     need(o.fp32_split_tol > 0.0, BSCF_E_INVALID, "fp32_split_tol must be positive");
     need(o.density == BSCF_DENSITY_SP2 || o.density == BSCF_DENSITY_EIG, BSCF_E_INVALID,
          "density must be BSCF_DENSITY_SP2 or BSCF_DENSITY_EIG");
@@ -2459,7 +2545,8 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     const mlp::Batch gb = guess_batch(c);
     // the learned guess corrects the previous-step guess; without previous
     // orbitals both fall back to the core guess
-    if ((guess == BSCF_GUESS_PREVIOUS || guess == BSCF_GUESS_LEARNED) && !c->have_C) {
+    if ((guess == BSCF_GUESS_PREVIOUS || guess == BSCF_GUESS_LEARNED ||
+         guess == BSCF_GUESS_EXTRAPOLATED) && !c->have_C) {
       if (guess == BSCF_GUESS_LEARNED) std::fill(fallback.begin(), fallback.end(), BSCF_FALLBACK_USED);
       guess = BSCF_GUESS_CORE;
     }
@@ -2467,7 +2554,17 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
       c->d_active.upload(flags, st);
       density_from_fock(c, c->H.p, c->batch(true), flags, o.density, c->P.p);
       c->guess.begin_step(gb, false);
+    } else if (guess == BSCF_GUESS_EXTRAPOLATED) {
+      // the extrapolated orbitals where two SCFs are stored (the previous
+      // step's elsewhere)
+      std::vector<int> ok(ni);
+      for (int i = 0; i < ni; ++i) ok[i] = c->h_ccount[i] >= 2 ? 1 : 0;
+      c->d_c2ok.upload(ok, st);
+      extrapolated_guess(c);
+      c->guess.begin_step(gb, true);
     } else if (guess == BSCF_GUESS_PREVIOUS || guess == BSCF_GUESS_LEARNED) {
+      // the learned guess corrects the previous-step density (its network
+      // carries last step's residual forward, which that base keeps coherent)
       previous_guess(c);
       c->guess.begin_step(gb, true);
       if (guess == BSCF_GUESS_LEARNED && !c->guess.predict(gb))
@@ -2545,7 +2642,13 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
         orbitals_from_fock(c, c->Fbar.p);
         BatchInfo bo = c->batch(false);
         bo.active = c->d_omask.p;
-        commit_C_kernel<<<dim3(1024, ni), 256, 0, st>>>(bo, c->C.p, c->Cacc.p);
+        std::vector<int> first(ni);
+        for (int i = 0; i < ni; ++i) first[i] = c->h_ccount[i] == 0 ? 1 : 0;
+        c->d_cfirst.upload(first, st);
+        commit_C_kernel<<<dim3(1024, ni), 256, 0, st>>>(bo, c->d_cfirst.p, c->C.p, c->Cacc.p,
+                                                         c->Cprev.p);
+        for (int i = 0; i < ni; ++i)
+          if (mask[i]) c->h_ccount[i] = std::min(2, c->h_ccount[i] + 1);
       }
     }
     std::vector<double> e(ni);
