@@ -358,23 +358,24 @@ def md_bench(args):
 def xc_summary(st, nbf):
     """Per-step XC kernel times and rooflines (HIP events over the timed
     region): the basis and point kernels against HBM bandwidth (algorithmic
-    bytes per grid point 8 n + 32 and 16 n + 32), the two dense products per
-    chunk (Z = B P and V += X^T B, 2 G n^2 FLOPs each per instance) against
-    the FP64 matrix peak."""
+    bytes per grid point 8 m + 32 and 16 m + 32, m the functions the point
+    takes: n in the dense form, its chunk's in the sparse one), the two
+    products per chunk (Z = B P and X^T B, 2 G m^2 FLOPs each per instance,
+    m padded to the bucket width) against the FP64 matrix peak."""
     x = st["xc"]
     pts = x["points"]
     rows = {}
-    for k, (nbytes, flops) in {"basis": (8 * nbf + 32, None), "point": (16 * nbf + 32, None),
+    for k, (nbytes, flops) in {"basis": (x["basis_bytes"], None), "point": (x["point_bytes"], None),
                                "gemm": (None, x["gemm_flops"] / 2),
                                "gemm_v": (None, x["gemm_flops"] / 2)}.items():
         ms, launches = x["ms"][k]
         if not launches or not ms:
             continue
         if nbytes is not None:
-            a = nbytes * pts / (ms * 1e-3) / 1e9
+            a = nbytes / (ms * 1e-3) / 1e9
             rows[k] = {"bound": "hbm", "achieved": a, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                        "frac": a / PEAK_HBM_GBS, "ms": ms, "launches": launches,
-                       "avg_launch_ms": ms / launches, "bytes_per_point": nbytes}
+                       "avg_launch_ms": ms / launches, "bytes_per_point": nbytes / max(pts, 1)}
         else:
             a = flops / (ms * 1e-3) / 1e12
             rows[k] = {"bound": "mfma", "achieved": a, "peak": PEAK_FP64_MATRIX_TFLOPS, "unit": "TFLOP/s",

@@ -328,6 +328,9 @@ struct bscf_ctx {
   // exchange-correlation builds: kernel time per step (HIP events, with
   // profiling), launches, builds, grid points evaluated and GEMM FLOPs
   double xc_ms[5] = {}, xc_points = 0, xc_gemm_flops = 0;
+  // algorithmic bytes of the basis and point steps: per point 8 m + 32 and
+  // 16 m + 32 with m the functions the point takes (n dense, a chunk's ns sparse)
+  double xc_basis_bytes = 0, xc_point_bytes = 0;
   long long xc_launches[5] = {}, xc_builds = 0;
   double t_work_host_ms = 0;   // host part of the work lists, wherever it ran
   double t_work_phase_ms[3] = {0, 0, 0};   // its ket lists, parts, merges
@@ -517,6 +520,26 @@ struct bscf_ctx {
     DevBuf<double> Vp;                  // [count][S][n][n] slice products
     DevBuf<double*> gp;                 // slice GEMM operands: A, B, C pointer arrays
     std::vector<double*> hgp;
+    // sparse form, per group (xc.h): chunks of kXcSparseShells radial shells
+    // of one atom and the basis shells each takes
+    struct Chunk {
+      int p0, gcnt, sh0, nsh, f0, ns;
+    };
+    // chunks of similar size share a launch, padded to W functions
+    struct Bucket {
+      int c0, nch, W, max_nsh;   // chunks [c0, c0 + nch) of the group's sorted list
+    };
+    struct GroupChunks {
+      bool sparse = false;
+      std::vector<Chunk> chunks;   // largest first
+      std::vector<Bucket> buckets;
+      int meta0 = 0;               // first chunk's entry in d_meta
+    };
+    std::vector<GroupChunks> gch;
+    std::vector<double> h_rad_r;        // [2][kXcRad] radial points (H, others)
+    DevBuf<int> d_shl, d_scbf, d_fmap;  // the chunks' shell lists, compact offsets, function maps
+    DevBuf<int> d_meta;                 // [chunk][6] of every group's sorted chunks
+    DevBuf<double> Ps, Vs;
     DevBuf<double> V, exc;              // V_xc [mtot], E_xc [ninst]
   } xcs;
 
@@ -1561,11 +1584,104 @@ void xc_tables(bscf_ctx* c) {
       au[3 * j + 2] = ct[k];
       aw[j] = wt[k] * 2 * M_PI / nphi;
     }
+  x.h_rad_r = rr;
   x.rad_r.upload(rr, c->stream);
   x.rad_w.upload(rw, c->stream);
   x.ang_u.upload(au, c->stream);
   x.ang_w.upload(aw, c->stream);
   x.tables = true;
+}
+
+// Sparse chunks of every group whose instances have the same atoms: per atom
+// and block of kXcSparseShells radial shells (points at distances r_lo..r_hi
+// from the atom), the basis shells whose values or gradients can exceed
+// kXcShellEps there in some instance of the group.  Bound at the shortest
+// distance d from the shell's centre to that spherical shell:
+// sum_k |c_k| exp(-a_k d^2) (d + 3)^l (1 + 2 a_k (d + 3)).
+void xc_chunks(bscf_ctx* c) {
+  auto& x = c->xcs;
+  x.gch.assign(c->groups.size(), {});
+  std::vector<int> shl, scbf, fmap, meta;
+  for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+    const Group& gr = c->groups[gi];
+    auto& G = x.gch[gi];
+    const int i0 = gr.first, na = c->natoms[i0];
+    bool same = true;
+    for (int i = i0 + 1; i < gr.first + gr.count && same; ++i) {
+      same = c->natoms[i] == na && c->nshell[i] == c->nshell[i0];
+      for (int a = 0; a < na && same; ++a) same = c->Zs[c->atom_off[i] + a] == c->Zs[c->atom_off[i0] + a];
+    }
+    if (!same) continue;
+    G.sparse = true;
+    const int nsh = c->nshell[i0];
+    for (int a = 0; a < na; ++a) {
+      const int tab = c->Zs[c->atom_off[i0] + a] == 1 ? 0 : 1;
+      for (int r0 = 0; r0 < kXcRad; r0 += kXcSparseShells) {
+        const int r1 = std::min(kXcRad, r0 + kXcSparseShells);
+        double rlo = 1e300, rhi = 0.0;
+        for (int r = r0; r < r1; ++r) {
+          rlo = std::min(rlo, x.h_rad_r[tab * kXcRad + r]);
+          rhi = std::max(rhi, x.h_rad_r[tab * kXcRad + r]);
+        }
+        bscf_ctx::Xcs::Chunk ch;
+        ch.p0 = a * kXcPerAtom + r0 * kXcAng;
+        ch.gcnt = (r1 - r0) * kXcAng;
+        ch.sh0 = (int)shl.size();
+        ch.f0 = (int)fmap.size();
+        int nf = 0;
+        for (int s = 0; s < nsh; ++s) {
+          bool keep = false;
+          for (int i = i0; i < gr.first + gr.count && !keep; ++i) {
+            const Shell& sh = c->shells[c->shell_off[i] + s];
+            const double* A = &c->xyz[3 * (size_t)(c->atom_off[i] + a)];
+            const double d = std::sqrt((sh.x - A[0]) * (sh.x - A[0]) + (sh.y - A[1]) * (sh.y - A[1]) +
+                                       (sh.z - A[2]) * (sh.z - A[2]));
+            const double dm = std::max(0.0, std::max(d - rhi, rlo - d)), dp = dm + 3.0;
+            double b = 0.0;
+            for (int k = 0; k < sh.nprim; ++k) {
+              const double al = c->sh_exp[sh.prim0 + k];
+              b += std::fabs(c->sh_coef[sh.prim0 + k]) * std::exp(-al * dm * dm) *
+                   (1.0 + 2.0 * al * dp);
+            }
+            b *= std::pow(dp, sh.l);
+            keep = b > kXcShellEps;
+          }
+          if (!keep) continue;
+          const Shell& sh = c->shells[c->shell_off[i0] + s];
+          shl.push_back(s);
+          scbf.push_back(nf);
+          for (int k = 0; k < ncart(sh.l); ++k) fmap.push_back(sh.bf + k);
+          nf += ncart(sh.l);
+        }
+        ch.nsh = (int)shl.size() - ch.sh0;
+        ch.ns = nf;
+        if (nf > 0) G.chunks.push_back(ch);
+      }
+    }
+    // largest first; a bucket takes the chunks down to 70% of its first one's
+    // width (padded to a multiple of 16)
+    std::stable_sort(G.chunks.begin(), G.chunks.end(),
+                     [](const bscf_ctx::Xcs::Chunk& p, const bscf_ctx::Xcs::Chunk& q) { return p.ns > q.ns; });
+    for (int k = 0; k < (int)G.chunks.size();) {
+      bscf_ctx::Xcs::Bucket b;
+      b.c0 = k;
+      b.W = (G.chunks[k].ns + 15) / 16 * 16;
+      b.max_nsh = 0;
+      do {   // the first chunk always, then those down to 70% of the width
+        b.max_nsh = std::max(b.max_nsh, G.chunks[k].nsh);
+        ++k;
+      } while (k < (int)G.chunks.size() && G.chunks[k].ns * 10 >= b.W * 7);
+      b.nch = k - b.c0;
+      G.buckets.push_back(b);
+    }
+    G.meta0 = (int)meta.size() / 6;
+    for (const auto& ch : G.chunks)
+      for (int v : {ch.p0, ch.gcnt, ch.sh0, ch.nsh, ch.f0, ch.ns}) meta.push_back(v);
+  }
+  x.d_meta.upload(meta, c->stream);
+  x.d_shl.upload(shl, c->stream);
+  x.d_scbf.upload(scbf, c->stream);
+  x.d_fmap.upload(fmap, c->stream);
 }
 
 // the molecular grid of every instance at the current geometry
@@ -1598,6 +1714,7 @@ void xc_grid(bscf_ctx* c) {
     launch_xc_grid(g, c->stream);
   }
   HIPCHK(hipGetLastError());
+  xc_chunks(c);
   x.grid_ok = true;
 }
 
@@ -1619,7 +1736,10 @@ void xc_build(bscf_ctx* c, const double* P, bool masked) {
     if (pk >= 0) prof_end(c, pk, st);
     c->xc_launches[q]++;
   };
-  for (const Group& gr : c->groups) {
+  const char* dense_env = std::getenv("BSCF_XC_DENSE");   // the dense form everywhere (tests)
+  const bool force_dense = dense_env && std::atoi(dense_env) != 0;
+  for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+    const Group& gr = c->groups[gi];
     for (int r0 = gr.first; r0 < gr.first + gr.count;) {
       if (masked && !c->h_active[r0]) {
         ++r0;
@@ -1628,6 +1748,87 @@ void xc_build(bscf_ctx* c, const double* P, bool masked) {
       int r1 = r0;
       while (r1 < gr.first + gr.count && (!masked || c->h_active[r1])) ++r1;
       const int count = r1 - r0, n = gr.n;
+      const auto& GC = x.gch[gi];
+      if (GC.sparse && !force_dense) {
+        // sparse form: per bucket of chunks, all its chunks times the run's
+        // instances in one launch of each step (xc.h)
+        const int G = kXcSparseG;
+        double* V = x.V.p + c->moff[r0];
+        launch_fill(V, (long long)count * n * n, 0.0, st);
+        XcSparseArgs a;
+        a.G = G;
+        a.count = count;
+        a.first = r0;
+        a.n = n;
+        a.sh_list = x.d_shl.p;
+        a.sh_cbf = x.d_scbf.p;
+        a.fmap = x.d_fmap.p;
+        a.sh_off = x.d_sh_off.p;
+        a.shells = c->d_shells.p;
+        a.sh_exp = c->d_sh_exp.p;
+        a.sh_coef = c->d_sh_coef.p;
+        a.pt_off = x.d_pt_off.p;
+        a.pts = x.pts.p;
+        a.moff = c->d_moff.p;
+        a.P = P;
+        a.V = x.V.p;
+        const double one = 1.0, zero = 0.0;
+        for (const auto& bk : GC.buckets) {
+          const int W = bk.W;
+          // launches of at most the buffer budget
+          const int per = std::max<int>(1, (int)(kXcBudget / ((size_t)count * W * G)));
+          for (int c0 = 0; c0 < bk.nch; c0 += per) {
+            const int nch = std::min(per, bk.nch - c0), slots = nch * count;
+            x.B.resize((size_t)slots * W * G);
+            x.Z.resize((size_t)slots * W * G);
+            x.Ps.resize((size_t)slots * W * W);
+            x.Vs.resize((size_t)slots * W * W);
+            x.part.resize((size_t)slots * (G / 256));
+            a.W = W;
+            a.nch = nch;
+            a.meta = x.d_meta.p + 6 * (GC.meta0 + bk.c0 + c0);
+            a.B = x.B.p;
+            a.Z = x.Z.p;
+            a.Ps = x.Ps.p;
+            a.Vs = x.Vs.p;
+            a.part = x.part.p;
+            const long long sBZ = (long long)W * G, sP = (long long)W * W;
+            step(kXcBasis, [&] {
+              launch_xc_sparse_basis(a, bk.max_nsh, st);
+              launch_xc_sparse_gather(a, st);
+            });
+            // Z = B Ps (column-major G x W times W x W, every slot)
+            step(kXcGemm, [&] {
+              BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none,
+                                                    rocblas_operation_none, G, W, W, &one, x.B.p,
+                                                    G, sBZ, x.Ps.p, W, sP, &zero, x.Z.p, G, sBZ,
+                                                    slots));
+            });
+            step(kXcPoint, [&] {
+              launch_xc_sparse_point(a, st);   // Z <- X
+              launch_xc_sparse_reduce(a, x.exc.p, st);
+            });
+            // Vs = X^T B, added into V through the function maps
+            step(kXcGemmV, [&] {
+              BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose,
+                                                    rocblas_operation_none, W, W, G, &one, x.Z.p,
+                                                    G, sBZ, x.B.p, G, sBZ, &zero, x.Vs.p, W, sP,
+                                                    slots));
+              launch_xc_sparse_scatter(a, st);
+            });
+            c->xc_gemm_flops += 4.0 * G * (double)W * W * slots;
+            for (int k = 0; k < nch; ++k) {
+              const auto& ch = GC.chunks[bk.c0 + c0 + k];
+              c->xc_basis_bytes += (8.0 * ch.ns + 32.0) * ch.gcnt * count;
+              c->xc_point_bytes += (16.0 * ch.ns + 32.0) * ch.gcnt * count;
+            }
+          }
+        }
+        launch_xc_symmetrize(n, count, V, st);
+        for (int i = r0; i < r1; ++i) c->xc_points += x.npts_i[i];
+        r0 = r1;
+        continue;
+      }
       int np_max = 0, nsh_max = 0;
       for (int i = r0; i < r1; ++i) {
         np_max = std::max(np_max, x.npts_i[i]);
@@ -1702,7 +1903,11 @@ void xc_build(bscf_ctx* c, const double* P, bool masked) {
         });
         c->xc_gemm_flops += 4.0 * G * (double)n * n * count;
       }
-      for (int i = r0; i < r1; ++i) c->xc_points += x.npts_i[i];
+      for (int i = r0; i < r1; ++i) {
+        c->xc_points += x.npts_i[i];
+        c->xc_basis_bytes += (8.0 * n + 32.0) * x.npts_i[i];
+        c->xc_point_bytes += (16.0 * n + 32.0) * x.npts_i[i];
+      }
       launch_xc_symmetrize(n, count, V, st);
       r0 = r1;
     }
@@ -3471,7 +3676,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
       c->xc_launches[k] = 0;
     }
     c->xc_builds = 0;
-    c->xc_points = c->xc_gemm_flops = 0;
+    c->xc_points = c->xc_gemm_flops = c->xc_basis_bytes = c->xc_point_bytes = 0;
   });
 }
 
@@ -3493,7 +3698,8 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
       << ", \"sp2_fallbacks\": " << c->sp2_fallbacks << ", \"incremental_builds\": " << c->inc_builds
       << ", \"graph_launches\": " << c->graph_launches << ", \"graph_captures\": " << c->graph_captures
       << ", \"xc\": {\"builds\": " << c->xc_builds << ", \"points\": " << c->xc_points
-      << ", \"gemm_flops\": " << c->xc_gemm_flops << ", \"ms\": {";
+      << ", \"gemm_flops\": " << c->xc_gemm_flops << ", \"basis_bytes\": " << c->xc_basis_bytes
+      << ", \"point_bytes\": " << c->xc_point_bytes << ", \"ms\": {";
     const char* xn[5] = {"basis", "gemm", "point", "gemm_v", "build"};
     for (int k = 0; k < 5; ++k)
       s << (k ? ", " : "") << "\"" << xn[k] << "\": [" << c->xc_ms[k] << ", " << c->xc_launches[k] << "]";

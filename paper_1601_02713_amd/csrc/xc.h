@@ -60,6 +60,56 @@ struct XcChunkArgs {
   double* part;             // [count][G / 256] partial sums of w e per block
 };
 
+// Sparse form (instances of one group with the same atoms, e.g. beads): the
+// grid is cut into chunks of kXcSparseShells radial shells of one atom, and a
+// chunk takes only the basis shells whose values (or gradients) can exceed
+// kXcShellEps somewhere on it (a distance bound, union over the group's
+// instances), numbered compactly: B, Z [count][ns][G], P and V through the
+// compact-to-local function map.
+constexpr int kXcSparseShells = 8;
+constexpr int kXcSparseG = kXcSparseShells * kXcAng;   // 2304 points, 9 x 256
+constexpr double kXcShellEps = 1e-14;
+
+// One launch covers nch chunks of a bucket (chunks of similar size, padded to
+// W compact functions) times the count instances of a run: slot z =
+// chunk * count + instance.  Per chunk (chunk metadata, 6 ints): first point,
+// points, first entry and length of its shell list, first entry and length of
+// its function map.
+struct XcSparseArgs {
+  int G;                    // points per chunk slot (multiple of 256)
+  int W;                    // padded compact functions per slot
+  int nch, count;           // chunks and instances of the launch
+  int first;                // first instance of the run
+  int n;                    // basis functions per instance
+  const int* meta;          // [nch][6]: p0, gcnt, sh0, nsh, f0, ns
+  const int* sh_list;       // shells (local to the instance) of all chunks
+  const int* sh_cbf;        // first compact function of each listed shell
+  const int* fmap;          // local function of each compact one, all chunks
+  const int* sh_off;        // per instance: first global shell
+  const Shell* shells;
+  const double* sh_exp;
+  const double* sh_coef;
+  const long long* pt_off;  // per instance: first grid point
+  const double* pts;
+  const long long* moff;    // per instance: matrix offset
+  const double* P;
+  double* B;                // [slot][W][G]
+  double* Z;                // [slot][W][G]: B Ps, then X
+  double* Ps;               // [slot][W][W] compact density (column-major, zero padded)
+  double* Vs;               // [slot][W][W] X^T B
+  double* V;                // V_xc (column-major per instance, + V^T at the end)
+  double* part;             // [slot][G / 256] partial sums of w e
+};
+
+// max_nsh: the longest shell list of the launch's chunks
+void launch_xc_sparse_basis(const XcSparseArgs& a, int max_nsh, hipStream_t s);
+void launch_xc_sparse_gather(const XcSparseArgs& a, hipStream_t s);
+void launch_xc_sparse_point(const XcSparseArgs& a, hipStream_t s);
+// V += Vs through the function maps (atomics: chunks of one instance overlap)
+void launch_xc_sparse_scatter(const XcSparseArgs& a, hipStream_t s);
+// exc[first + i] += the partial sums of instance i over the launch's chunks, in order
+void launch_xc_sparse_reduce(const XcSparseArgs& a, double* exc, hipStream_t s);
+
 void launch_xc_grid(const XcGridArgs& a, hipStream_t s);
 // count instances of the run, at most max_nsh shells each
 void launch_xc_basis(const XcChunkArgs& a, int count, int max_nsh, hipStream_t s);

@@ -264,6 +264,142 @@ __global__ void xc_slice_sum_kernel(int n, int S, const double* Vp, double* V, i
   V[(size_t)blockIdx.y * nn + e] = acc;
 }
 
+// ---------------------------------------------------------- sparse form
+
+struct ChunkMeta {
+  int p0, gcnt, sh0, nsh, f0, ns;
+};
+__device__ __forceinline__ ChunkMeta chunk_meta(const int* m, int c) {
+  const int* q = m + 6 * c;
+  return {q[0], q[1], q[2], q[3], q[4], q[5]};
+}
+
+// grid (G / 256, max_nsh + 1, slots): y < nsh a shell of the chunk, the last
+// y the zero padding rows [ns, W)
+__global__ __launch_bounds__(256) void xc_sparse_basis_kernel(XcSparseArgs a) {
+  const int gl = blockIdx.x * blockDim.x + threadIdx.x;
+  const int slot = blockIdx.z, c = slot / a.count, zi = slot - c * a.count, inst = a.first + zi;
+  const ChunkMeta m = chunk_meta(a.meta, c);
+  double* Bs = a.B + (size_t)slot * a.W * a.G + gl;
+  if ((int)blockIdx.y == (int)gridDim.y - 1) {
+    for (int k = m.ns; k < a.W; ++k) Bs[(size_t)k * a.G] = 0.0;
+    return;
+  }
+  if ((int)blockIdx.y >= m.nsh) return;
+  const int j = m.sh0 + blockIdx.y;
+  const Shell sh = a.shells[a.sh_off[inst] + a.sh_list[j]];
+  double* Bc = Bs + (size_t)a.sh_cbf[j] * a.G;
+  const int nc = (sh.l + 1) * (sh.l + 2) / 2;
+  if (gl >= m.gcnt) {
+    for (int k = 0; k < nc; ++k) Bc[(size_t)k * a.G] = 0.0;
+    return;
+  }
+  const double* pt = a.pts + 4 * (a.pt_off[inst] + m.p0 + gl);
+  shell_eval<false>(sh, a.sh_exp, a.sh_coef, pt[0] - sh.x, pt[1] - sh.y, pt[2] - sh.z,
+                    [&](int k, double v, double, double, double) { Bc[(size_t)k * a.G] = v; });
+}
+
+// Ps(i, j) = P(fmap[i], fmap[j]) inside the chunk's ns, zero in the padding
+__global__ void xc_sparse_gather_kernel(XcSparseArgs a) {
+  const int slot = blockIdx.y, c = slot / a.count, zi = slot - c * a.count, inst = a.first + zi;
+  const long long ww = (long long)a.W * a.W;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ww) return;
+  const ChunkMeta m = chunk_meta(a.meta, c);
+  const int j = (int)(e / a.W), i = (int)(e - (long long)j * a.W);
+  double v = 0.0;
+  if (i < m.ns && j < m.ns)
+    v = a.P[a.moff[inst] + (long long)a.fmap[m.f0 + i] * a.n + a.fmap[m.f0 + j]];
+  a.Ps[slot * ww + e] = v;
+}
+
+// as xc_point_kernel over the chunk's shells
+__global__ __launch_bounds__(256) void xc_sparse_point_kernel(XcSparseArgs a) {
+  __shared__ double red[256];
+  const int gl = blockIdx.x * blockDim.x + threadIdx.x;
+  const int slot = blockIdx.y, c = slot / a.count, zi = slot - c * a.count, inst = a.first + zi;
+  const ChunkMeta m = chunk_meta(a.meta, c);
+  double ew = 0.0;
+  if (gl < m.gcnt) {
+    const double* pt = a.pts + 4 * (a.pt_off[inst] + m.p0 + gl);
+    const double x = pt[0], y = pt[1], z = pt[2], w = pt[3];
+    double* Zc = a.Z + (size_t)slot * a.W * a.G + gl;
+    const Shell* sh0 = a.shells + a.sh_off[inst];
+    double rho = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int j = m.sh0; j < m.sh0 + m.nsh; ++j) {
+      const Shell sh = sh0[a.sh_list[j]];
+      double* zf = Zc + (size_t)a.sh_cbf[j] * a.G;
+      shell_eval<true>(sh, a.sh_exp, a.sh_coef, x - sh.x, y - sh.y, z - sh.z,
+                       [&](int k, double v, double vx, double vy, double vz) {
+                         const double zz = zf[(size_t)k * a.G];
+                         rho += v * zz;
+                         gx += vx * zz;
+                         gy += vy * zz;
+                         gz += vz * zz;
+                       });
+    }
+    gx *= 2.0;
+    gy *= 2.0;
+    gz *= 2.0;
+    double cr = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
+    if (rho > kXcRhoMin) {
+      const Xc f = b3lyp(rho, gx * gx + gy * gy + gz * gz);
+      ew = w * f.e;
+      cr = 0.5 * w * f.vr;
+      cx = 2.0 * w * f.vs * gx;
+      cy = 2.0 * w * f.vs * gy;
+      cz = 2.0 * w * f.vs * gz;
+    }
+    for (int j = m.sh0; j < m.sh0 + m.nsh; ++j) {
+      const Shell sh = sh0[a.sh_list[j]];
+      double* zf = Zc + (size_t)a.sh_cbf[j] * a.G;
+      shell_eval<true>(sh, a.sh_exp, a.sh_coef, x - sh.x, y - sh.y, z - sh.z,
+                       [&](int k, double v, double vx, double vy, double vz) {
+                         zf[(size_t)k * a.G] = cr * v + cx * vx + cy * vy + cz * vz;
+                       });
+    }
+  }
+  red[threadIdx.x] = ew;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.part[(size_t)slot * (a.G / 256) + blockIdx.x] = red[0];
+}
+
+// V(fmap[i], fmap[j]) += Vs(i, j), column-major; the chunks of one instance
+// add into the same matrix, so with atomics
+__global__ void xc_sparse_scatter_kernel(XcSparseArgs a) {
+  const int slot = blockIdx.y, c = slot / a.count, zi = slot - c * a.count, inst = a.first + zi;
+  const long long ww = (long long)a.W * a.W;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ww) return;
+  const ChunkMeta m = chunk_meta(a.meta, c);
+  const int j = (int)(e / a.W), i = (int)(e - (long long)j * a.W);
+  if (i >= m.ns || j >= m.ns) return;
+  atomicAdd(&a.V[a.moff[inst] + (long long)a.fmap[m.f0 + j] * a.n + a.fmap[m.f0 + i]],
+            a.Vs[slot * ww + e]);
+}
+
+// one block per instance: its partial sums over the launch's chunks, in order
+__global__ __launch_bounds__(256) void xc_sparse_reduce_kernel(XcSparseArgs a, double* exc) {
+  __shared__ double red[256];
+  const int nb = a.G / 256, zi = blockIdx.x;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < a.nch * nb; k += 256) {
+    const int c = k / nb, b = k - c * nb;
+    s += a.part[((size_t)c * a.count + zi) * nb + b];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) exc[a.first + zi] += red[0];
+}
+
 // M <- M + M^T for each of the run's n x n matrices
 __global__ void xc_symmetrize_kernel(int n, double* V) {
   const int i = blockIdx.y, j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -317,6 +453,40 @@ void launch_xc_slice_sum(int n, int count, int S, const double* Vp, double* V, b
 void launch_xc_symmetrize(int n, int count, double* V, hipStream_t s) {
   if (count == 0 || n == 0) return;
   hipLaunchKernelGGL(xc_symmetrize_kernel, dim3((n + 255) / 256, n, count), dim3(256), 0, s, n, V);
+}
+
+void launch_xc_sparse_basis(const XcSparseArgs& a, int max_nsh, hipStream_t s) {
+  const int slots = a.nch * a.count;
+  if (slots == 0) return;
+  hipLaunchKernelGGL(xc_sparse_basis_kernel, dim3(a.G / 256, max_nsh + 1, slots), dim3(256), 0, s,
+                     a);
+}
+
+void launch_xc_sparse_gather(const XcSparseArgs& a, hipStream_t s) {
+  const long long ww = (long long)a.W * a.W;
+  const int slots = a.nch * a.count;
+  if (slots == 0 || ww == 0) return;
+  hipLaunchKernelGGL(xc_sparse_gather_kernel, dim3((unsigned)((ww + 255) / 256), slots), dim3(256),
+                     0, s, a);
+}
+
+void launch_xc_sparse_point(const XcSparseArgs& a, hipStream_t s) {
+  const int slots = a.nch * a.count;
+  if (slots == 0) return;
+  hipLaunchKernelGGL(xc_sparse_point_kernel, dim3(a.G / 256, slots), dim3(256), 0, s, a);
+}
+
+void launch_xc_sparse_scatter(const XcSparseArgs& a, hipStream_t s) {
+  const long long ww = (long long)a.W * a.W;
+  const int slots = a.nch * a.count;
+  if (slots == 0 || ww == 0) return;
+  hipLaunchKernelGGL(xc_sparse_scatter_kernel, dim3((unsigned)((ww + 255) / 256), slots), dim3(256),
+                     0, s, a);
+}
+
+void launch_xc_sparse_reduce(const XcSparseArgs& a, double* exc, hipStream_t s) {
+  if (a.count == 0 || a.nch == 0) return;
+  hipLaunchKernelGGL(xc_sparse_reduce_kernel, dim3(a.count), dim3(256), 0, s, a, exc);
 }
 
 void launch_xc_functional(int n, const double* rho, const double* sigma, double* e, double* vr,

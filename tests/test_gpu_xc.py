@@ -7,8 +7,10 @@ the CPU suite pins to closed forms and to the derivative identities.
   the oracle).
 * V_xc and E_xc of a ragged batch (H2, three water beads batched together,
   the water dimer; 4 to 38 functions, 34560 to 103680 grid points) at the
-  oracle's core-guess density, with whole-instance chunks and with chunks of
-  9984 points (several per instance, the last one ragged).
+  oracle's core-guess density, in the sparse form (per chunk of radial
+  shells only the basis shells that matter there) and in the dense form,
+  with whole-instance chunks and with chunks of 9984 points (several per
+  instance, the last one ragged).
 * Kohn-Sham F and E of one build, and converged B3LYP SCF energies.
 * B3LYP forces are refused, and bscf_build_jk ignores the setting.
 """
@@ -69,12 +71,17 @@ def test_functional_matches_oracle(beadscf, b631gs):
         assert err[k] < 1e-11, (name, rho[k], sigma[k], got[k], ref[k])
 
 
-@pytest.mark.parametrize("chunk", [None, 10000])
-def test_vxc_and_exc_match_oracle(beadscf, b631gs, chunk, monkeypatch):
-    """Three water beads form one batched run; with a chunk width of 9984
-    points every instance takes several chunks and ends in a ragged one."""
-    if chunk:
-        monkeypatch.setenv("BSCF_XC_CHUNK", str(chunk))
+@pytest.mark.parametrize("form", ["sparse", "dense", "dense-chunked"])
+def test_vxc_and_exc_match_oracle(beadscf, b631gs, form, monkeypatch):
+    """Three water beads form one batched run.  Sparse: chunks of 8 radial
+    shells of one atom, each with the basis shells that matter there (the
+    default for instances with the same atoms).  Dense: every point takes
+    every function; with a chunk width of 9984 points every instance takes
+    several chunks and ends in a ragged one."""
+    if form != "sparse":
+        monkeypatch.setenv("BSCF_XC_DENSE", "1")
+    if form == "dense-chunked":
+        monkeypatch.setenv("BSCF_XC_CHUNK", "10000")
     h2, w, d = _batch()
     wb = inputs.beads(w[0], w[1], 3, 21)
     inst = [h2] + [(w[0], x) for x in wb] + [d]
