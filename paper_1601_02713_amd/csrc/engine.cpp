@@ -66,6 +66,15 @@ int unit_quartets(int max_n) {
 // the 288 GB; below it the autotuner times both forms and keeps the faster.
 constexpr int kMaxLaneScratch = 4096;
 
+// The bound a context applies: kMaxLaneScratch, or less when the environment
+// variable BSCF_LANE_SCRATCH_MAX asks for less (tests use it to route classes
+// whose lane kernels spill less than kMaxLaneScratch to the cooperative form).
+int lane_scratch_bound() {
+  const char* v = getenv("BSCF_LANE_SCRATCH_MAX");
+  if (!v || !*v) return kMaxLaneScratch;
+  return std::max(0, std::min(kMaxLaneScratch, atoi(v)));
+}
+
 // Incremental Fock builds: a full build at the first SCF iteration and every
 // kFullEvery iterations, which bounds the accumulated effect of the skipped
 // quartets.
@@ -323,6 +332,7 @@ struct bscf_ctx {
   // and Schwarz kernels) runs on the context's own stream; only scratch-free
   // class kernels overlap on the auxiliary streams.
   int private_bytes[kNumQuartetClasses][3] = {};
+  int lane_scratch_max = lane_scratch_bound();   // lane kernels above it never run
   int coop_bytes[kNumQuartetClasses][2] = {};   // cooperative fock, gradient
   double t_fock_gpu_ms = 0, t_work_ms = 0;
   // exchange-correlation builds: kernel time per step (HIP events, with
@@ -1460,8 +1470,8 @@ void autotune_fock(bscf_ctx* c, int pcol) {
   for (int q = 0; q < kNumQuartetClasses; ++q) {
     auto& W = c->work[q];
     for (float& t : c->tune_ms[pcol][q]) t = 0.0f;
-    const bool lane_ok = qc[q].fock && W.lds_ok && c->private_bytes[q][0] <= kMaxLaneScratch &&
-                         !(pcol && c->private_bytes[q][1] > kMaxLaneScratch);
+    const bool lane_ok = qc[q].fock && W.lds_ok && c->private_bytes[q][0] <= c->lane_scratch_max &&
+                         !(pcol && c->private_bytes[q][1] > c->lane_scratch_max);
     if (!lane_ok) c->fock_variant[pcol][q] = 1;
     if (W.items.empty()) continue;
     set_class(a, W);
@@ -2144,9 +2154,9 @@ bscf_status bscf_create(int hip_device, void* hip_stream, bscf_ctx** out) {
           need(c->private_bytes[q][k] >= 0, BSCF_E_DEVICE, "hipFuncGetAttributes failed");
         for (int k = 0; k < 2; ++k)
           need(c->coop_bytes[q][k] >= 0, BSCF_E_DEVICE, "hipFuncGetAttributes failed");
-        c->fock_variant[0][q] = qc[q].fock && c->private_bytes[q][0] <= kMaxLaneScratch ? 0 : 1;
-        c->fock_variant[1][q] = qc[q].fock && c->private_bytes[q][1] <= kMaxLaneScratch ? 0 : 1;
-        c->grad_variant[q] = qc[q].grad && c->private_bytes[q][2] <= kMaxLaneScratch ? 0 : 1;
+        c->fock_variant[0][q] = qc[q].fock && c->private_bytes[q][0] <= c->lane_scratch_max ? 0 : 1;
+        c->fock_variant[1][q] = qc[q].fock && c->private_bytes[q][1] <= c->lane_scratch_max ? 0 : 1;
+        c->grad_variant[q] = qc[q].grad && c->private_bytes[q][2] <= c->lane_scratch_max ? 0 : 1;
       }
     }
     mlp::init_noalloc_scratch(hip_device);
@@ -2997,7 +3007,7 @@ void forces_impl(bscf_ctx* c, double* Fout) {
         const bool lds_ok = sizeof(double) * (size_t)grad_unit_lds_doubles(
                                 qc[q].la, qc[q].lb, c->max_n, c->max_atoms, W.max_prims) <=
                             c->max_lds_bytes;
-        const bool lane_ok = qc[q].grad && lds_ok && c->private_bytes[q][2] <= kMaxLaneScratch;
+        const bool lane_ok = qc[q].grad && lds_ok && c->private_bytes[q][2] <= c->lane_scratch_max;
         c->grad_unit_threads[q] = 64;
         if (lane_ok && !(env && !strcmp(env, "coop"))) {
           // units of one, two and four wavefronts, the fastest kept

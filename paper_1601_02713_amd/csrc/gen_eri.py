@@ -426,8 +426,9 @@ def quartet_classes():
 
 
 LANE_E_MAX = 5   # one-lane-per-quartet Fock kernels up to this total L
-LANE_G_MAX = 4   # one-lane-per-quartet gradient kernels up to this total L
+LANE_G_MAX = 5   # one-lane-per-quartet gradient kernels up to this total L
 SPLIT_GRAD_ACC = 120   # lane gradient classes with more accumulators run one pass per centre
+SUB_GRAD_ACC = 128     # ... and split each centre's pass into parts of at most this many
 
 
 def coop_tu(la, lb, lc, ld):
@@ -606,6 +607,8 @@ def main(outdir):
         szs = ", ".join(f"N{s} = {sizes.get(s, 1)}" for s in allsets)
         arg = ", ".join(s for s in names)
         split = sum(sizes.values()) > SPLIT_GRAD_ACC
+        per_pass = max(sizes.get(f"R{X}", 0) + sizes.get(f"L{X}", 0) for X in "ABC")
+        nsub = -(-per_pass // SUB_GRAD_ACC) if split else 1
         def cargs(X):   # the per-centre functions' set arguments: S1 = raised, S2 = lowered
             return "S1" + (", S2" if f"L{X}" in names else "")
         vx = "\n".join(
@@ -618,6 +621,7 @@ def main(outdir):
   static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld};
   static constexpr bool PRIM = false;
   static constexpr bool SPLIT = {'true' if split else 'false'};   // one pass per centre
+  static constexpr int NSUB = {nsub};   // sub-passes per centre pass
   static constexpr int {szs};
   // centre X (0 = A, 1 = B, 2 = C): S1 = its raised set, S2 = its lowered set (if any)
   template <int X, typename R>

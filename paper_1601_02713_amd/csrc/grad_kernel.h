@@ -21,7 +21,12 @@ namespace bscf {
 // One centre's pass of a class whose six contracted sets do not fit a lane's
 // registers at once: the primitive loop again, accumulating only the raised
 // and lowered sets of centre X (0 = A, 1 = B, 2 = C), then their contraction.
-template <class CG, int X, class GF>
+// With CG::NSUB > 1 the pass is split further: sub-pass SUB keeps the SUB-th
+// of NSUB contiguous ranges of the centre's sets (raised, then lowered) and
+// drops the rest before the contraction, so the compiler removes their
+// recurrence work and accumulators from this sub-pass; the contraction is
+// linear in the sets, so the sub-passes' sums add up to the centre's.
+template <class CG, int X, int SUB, class GF>
 __device__ __forceinline__ void grad_centre_pass(const PrimPair* __restrict__ bp, int nb,
                                                  const PrimPair* __restrict__ kp, int nk, int ks,
                                                  const double* AB, const double* CD,
@@ -55,9 +60,36 @@ __device__ __forceinline__ void grad_centre_pass(const PrimPair* __restrict__ bp
                               2.0 * Q.alpha, S1, S2);
     }
   }
+  if constexpr (CG::NSUB > 1) {
+    constexpr int lo = SUB * (N1 + N2) / CG::NSUB, hi = (SUB + 1) * (N1 + N2) / CG::NSUB;
+#pragma unroll
+    for (int k = 0; k < N1; ++k)
+      if (k < lo || k >= hi) S1[k] = 0;
+#pragma unroll
+    for (int k = 0; k < N2; ++k)
+      if (N1 + k < lo || N1 + k >= hi) S2[k] = 0;
+  }
   double G[ncart(CG::LA) * ncart(CG::LB) * ncart(CG::LC) * ncart(CG::LD)];
   gfill(G);
   CG::template conx<X, R>(S1, S2, AB[0], AB[1], AB[2], CD[0], CD[1], CD[2], G, g9);
+  // The force sums are needed here, in this pass.  Otherwise the compiler
+  // sinks the contraction below the later passes' primitive loops (its
+  // results are only used at the end), which keeps this pass's accumulators
+  // live across those loops: several KB of scratch per lane for the classes
+  // with d functions.
+#pragma unroll
+  for (int k = 0; k < 9; ++k) asm volatile("" : "+v"(g9[k]));
+}
+
+template <class CG, int X, int SUB, class GF>
+__device__ __forceinline__ void grad_centre_subpasses(const PrimPair* __restrict__ bp, int nb,
+                                                      const PrimPair* __restrict__ kp, int nk,
+                                                      int ks, const double* AB, const double* CD,
+                                                      const double* __restrict__ tab64,
+                                                      const GF& gfill, double* g9) {
+  grad_centre_pass<CG, X, SUB>(bp, nb, kp, nk, ks, AB, CD, tab64, gfill, g9);
+  if constexpr (SUB + 1 < CG::NSUB)
+    grad_centre_subpasses<CG, X, SUB + 1>(bp, nb, kp, nk, ks, AB, CD, tab64, gfill, g9);
 }
 
 // Contracted-set forms (lane kernels): gfill(G) writes the quartet's density
@@ -73,9 +105,9 @@ __device__ __forceinline__ void grad_block_lane(const PrimPair* __restrict__ bp,
   using R = double;
   static_assert(!CG::PRIM, "lane gradient classes contract their sets");
   if constexpr (CG::SPLIT) {
-    grad_centre_pass<CG, 0>(bp, nb, kp, nk, ks, AB, CD, tab64, gfill, g9);
-    grad_centre_pass<CG, 1>(bp, nb, kp, nk, ks, AB, CD, tab64, gfill, g9);
-    grad_centre_pass<CG, 2>(bp, nb, kp, nk, ks, AB, CD, tab64, gfill, g9);
+    grad_centre_subpasses<CG, 0, 0>(bp, nb, kp, nk, ks, AB, CD, tab64, gfill, g9);
+    grad_centre_subpasses<CG, 1, 0>(bp, nb, kp, nk, ks, AB, CD, tab64, gfill, g9);
+    grad_centre_subpasses<CG, 2, 0>(bp, nb, kp, nk, ks, AB, CD, tab64, gfill, g9);
   } else {
     R RA[CG::NRA], RB[CG::NRB], RC[CG::NRC], LA[CG::NLA], LB[CG::NLB], LC[CG::NLC];
 #pragma unroll
@@ -115,51 +147,6 @@ __device__ __forceinline__ void grad_block_lane(const PrimPair* __restrict__ bp,
   }
 }
 
-template <class CG>
-__device__ __forceinline__ void grad_block_body(const PrimPair* __restrict__ bp, int nb,
-                                                const PrimPair* __restrict__ kp, int nk, int ks,
-                                                const double* AB, const double* CD,
-                                                const double* __restrict__ tab64,
-                                                const double* __restrict__ G, double* g9) {
-  constexpr int L = CG::LA + CG::LB + CG::LC + CG::LD + 1;
-  using R = double;
-  if constexpr (!CG::PRIM) {
-    grad_block_lane<CG>(bp, nb, kp, nk, ks, AB, CD, tab64, [&](double* Gd) {
-      for (int k = 0; k < ncart(CG::LA) * ncart(CG::LB) * ncart(CG::LC) * ncart(CG::LD); ++k)
-        Gd[k] = G[k];
-    }, g9);
-  } else {
-    for (int j = 0; j < nk; ++j) {
-      const PrimPair Q = kp[j * ks];
-      for (int i = 0; i < nb; ++i) {
-        const PrimPair B = bp[i];
-        const double pq = B.p + Q.p;
-        const double rpq = rsqrt(pq);
-        const double oopq = rpq * rpq;
-        const double rho = B.p * Q.p * oopq;
-        const double PQx = B.Px - Q.Px, PQy = B.Py - Q.Py, PQz = B.Pz - Q.Pz;
-        const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
-        R F[L + 1];
-        boys_f64<L>(T, B.C * Q.C * rpq, tab64, F);
-        const double qf = Q.p * oopq, pf = B.p * oopq;
-        CG::template prim<R>(F, B.PAx, B.PAy, B.PAz, -qf * PQx, -qf * PQy, -qf * PQz, Q.PAx,
-                             Q.PAy, Q.PAz, pf * PQx, pf * PQy, pf * PQz, B.oo2p, Q.oo2p,
-                             0.5 * oopq, B.oo2p * qf, Q.oo2p * pf, 2.0 * B.alpha, 2.0 * B.beta,
-                             2.0 * Q.alpha, AB[0], AB[1], AB[2], CD[0], CD[1], CD[2], G, g9);
-      }
-    }
-  }
-}
-
-template <class CG>
-__device__ __noinline__ void grad_block_outline(const PrimPair* __restrict__ bp, int nb,
-                                                const PrimPair* __restrict__ kp, int nk, int ks,
-                                                const double* AB, const double* CD,
-                                                const double* __restrict__ tab64,
-                                                const double* __restrict__ G, double* g9) {
-  grad_block_body<CG>(bp, nb, kp, nk, ks, AB, CD, tab64, G, g9);
-}
-
 template <typename T>
 __device__ __forceinline__ T gwave_sum(T v) {
 #pragma unroll
@@ -177,7 +164,6 @@ template <class CG>
 __global__ __launch_bounds__(256) void grad_unit_kernel(GradArgs a) {
   constexpr int NA = ncart(CG::LA), NB = ncart(CG::LB), NC = ncart(CG::LC), ND = ncart(CG::LD);
   constexpr int NR = NA + NB;
-  constexpr int NOUT = NA * NB * NC * ND;
   extern __shared__ double lds[];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & (kWave - 1);
@@ -251,17 +237,9 @@ __global__ __launch_bounds__(256) void grad_unit_kernel(GradArgs a) {
     };
     double g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int2 kp = a.kpos[pos];
-    if (keep) {
-      if constexpr (CG::LA + CG::LB + CG::LC + CG::LD >= 5) {
-        double G[NOUT];
-        gfill(G);
-        grad_block_outline<CG>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64,
-                               G, g9);
-      } else {
-        grad_block_lane<CG>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64,
-                            gfill, g9);
-      }
-    }
+    if (keep)
+      grad_block_lane<CG>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64,
+                          gfill, g9);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       gA[d] += g9[d];

@@ -147,22 +147,40 @@ def test_batches_with_fewer_matrix_elements_than_force_components(eng, sto3g, z,
     assert np.abs(F.sum(axis=0)).max() < 1e-10
 
 
-def test_lane_kernels_over_the_scratch_bound_never_run(eng, b631gs):
+def test_lane_kernels_over_the_scratch_bound_never_run(beadscf, eng, b631gs, monkeypatch):
     """Every class whose lane kernel needs more private memory per lane than
-    the engine's bound (4096 bytes) runs cooperatively, for the Fock build in
-    both precisions and for the gradient."""
+    the context's bound (4096 bytes, or less through BSCF_LANE_SCRATCH_MAX)
+    runs cooperatively, for the Fock build in both precisions and for the
+    gradient.  No lane kernel of the library is over 4096 bytes, so a bound
+    of 1024 bytes routes some classes (among them the (pp|pp) and (dp|ds)
+    gradients) to the cooperative form; the forces stay those of the
+    default routing."""
     inst = inputs.workload("w3")["instances"]
-    _setup(eng, b631gs, inst)
-    eng.run_scf(e_tol=1e-9, comm_tol=1e-7)
-    eng.forces()
-    eng.run_scf(e_tol=1e-9, comm_tol=1e-7, precision=1)
-    st = eng.stats()["classes"]
-    over = 0
-    for tag, v in st.items():
-        if not v["items"]:
-            continue
-        for k in range(3):
-            if v["private_bytes"][k] > 4096:
-                over += 1
-                assert v["variant"][k] == 1, (tag, k, v["private_bytes"], v["variant"])
-    assert over >= 1   # (the (pp|pp) lane gradient is over the bound)
+
+    def run(e):
+        _setup(e, b631gs, inst)
+        e.run_scf(e_tol=1e-9, comm_tol=1e-7)
+        F = e.forces()
+        e.run_scf(e_tol=1e-9, comm_tol=1e-7, precision=1)
+        return F, e.stats()["classes"]
+
+    F0, st0 = run(eng)
+    monkeypatch.setenv("BSCF_LANE_SCRATCH_MAX", "1024")
+    e1 = beadscf.Engine(0)
+    try:
+        F1, st1 = run(e1)
+    finally:
+        e1.close()
+    for bound, st in ((4096, st0), (1024, st1)):
+        over = 0
+        for tag, v in st.items():
+            if not v["items"]:
+                continue
+            for k in range(3):
+                if v["private_bytes"][k] > bound:
+                    over += 1
+                    assert v["variant"][k] == 1, (bound, tag, k, v["private_bytes"], v["variant"])
+        if bound == 1024:
+            assert over >= 1
+    for a, b in zip(F0, F1):
+        assert np.abs(a - b).max() < 1e-10

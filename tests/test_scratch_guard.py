@@ -35,9 +35,12 @@ def test_scratch_bound_and_unconditional_kernels():
     kmax = int(re.search(r"constexpr int kMaxLaneScratch = (\d+);", src).group(1))
     # the reservation of one hardware queue at full occupancy stays within 2 GiB
     assert kmax * 64 * 32 * 256 <= 2 ** 31
-    # every lane-form selection tests the bound: Fock (FP64 and mixed) and
-    # gradient at context creation, the Fock autotuner and the gradient's
-    assert len(re.findall(r"private_bytes\[q\]\[[0-2]\] <= kMaxLaneScratch", src)) >= 5
+    # every lane-form selection tests the context's bound: Fock (FP64 and
+    # mixed) and gradient at context creation, the Fock autotuner and the
+    # gradient's; the environment can only lower that bound
+    assert len(re.findall(r"private_bytes\[q\]\[[0-2]\] <= c->lane_scratch_max", src)) >= 5
+    assert "int lane_scratch_max = lane_scratch_bound();" in src
+    assert "std::min(kMaxLaneScratch, atoi(v))" in src
     recs = _records()
     if not recs:
         pytest.skip("no resource records: build the library first")
