@@ -77,16 +77,22 @@ def angular_grid(n_th: int):
     return u, w
 
 
+def _norm(v, axis=-1):
+    """Euclidean length, written out so that complex coordinates (the
+    complex-step derivatives below) pass through analytically."""
+    return np.sqrt(np.sum(v * v, axis=axis))
+
+
 def becke_weights(points, xyz, owner):
     """Becke partition weight of each point's own atom."""
     nat = len(xyz)
-    d = np.linalg.norm(points[:, None, :] - xyz[None, :, :], axis=2)    # [npt, nat]
-    P = np.ones((len(points), nat))
+    d = _norm(points[:, None, :] - xyz[None, :, :], axis=2)    # [npt, nat]
+    P = np.ones((len(points), nat), dtype=d.dtype)
     for A in range(nat):
         for B in range(nat):
             if A == B:
                 continue
-            mu = (d[:, A] - d[:, B]) / np.linalg.norm(xyz[A] - xyz[B])
+            mu = (d[:, A] - d[:, B]) / _norm(xyz[A] - xyz[B])
             for _ in range(3):
                 mu = 1.5 * mu - 0.5 * mu ** 3
             P[:, A] *= 0.5 * (1 - mu)
@@ -95,7 +101,8 @@ def becke_weights(points, xyz, owner):
 
 def molecular_grid(Z, xyz, n_rad=60, n_th=12):
     """Points [npt, 3] and weights [npt] of the molecular grid."""
-    xyz = np.asarray(xyz, float)
+    xyz = np.asarray(xyz)
+    xyz = xyz.astype(np.result_type(xyz, float))
     u, wa = angular_grid(n_th)
     pts, wts, own = [], [], []
     for A, z in enumerate(Z):
@@ -120,15 +127,16 @@ def _dfact(n):
 def basis_values(b, points):
     """phi [npt, nbf] and grad phi [3, npt, nbf] of the oracle basis."""
     npt = len(points)
-    phi = np.zeros((npt, b["nbf"]))
-    dphi = np.zeros((3, npt, b["nbf"]))
+    dt = np.result_type(points, b["xyz"], float)   # complex for complex-step derivatives
+    phi = np.zeros((npt, b["nbf"]), dtype=dt)
+    dphi = np.zeros((3, npt, b["nbf"]), dtype=dt)
     for s in range(b["nsh"]):
         l, A = int(b["l"][s]), b["xyz"][int(b["atom"][s])]
         p0, nprim, f0 = int(b["pofs"][s]), int(b["nprim"][s]), int(b["bf"][s])
         d = points - A[None, :]
         r2 = np.sum(d * d, axis=1)
-        rad = np.zeros(npt)
-        drad = np.zeros(npt)        # d(rad)/d(r^2)
+        rad = np.zeros(npt, dtype=dt)
+        drad = np.zeros(npt, dtype=dt)        # d(rad)/d(r^2)
         for k in range(nprim):
             a, cf = b["exps"][p0 + k], b["coefs"][p0 + k]
             e = cf * np.exp(-a * r2)
@@ -290,3 +298,46 @@ def ks_scf(b, e_tol=1e-8, comm_tol=1e-6, max_iter=100, n_rad=60, n_th=12, charge
             break
         P, _, _ = rhf._density(X.T @ Fbar @ X, X, nocc)
     return dict(E=E, P=P, F=F, n_iter=max_iter, converged=False)
+
+
+# ------------------------------------------------------------------- forces
+
+def xc_energy(b, P, grid, func=e_b3lyp):
+    """E_xc = sum_g w_g e(rho_g, sigma_g) at density P on the given grid.  Real
+    or complex: with complex atom positions (and the grid built from them) the
+    imaginary part carries the complex-step derivative."""
+    pts, w = grid
+    phi, dphi = basis_values(b, pts)
+    Zm = phi @ P
+    rho = np.sum(phi * Zm, axis=1)
+    grad = 2.0 * np.einsum("xgm,gm->gx", dphi, Zm)
+    sigma = np.sum(grad * grad, axis=1)
+    keep = np.real(rho) > RHO_MIN
+    return np.sum(w[keep] * func(rho[keep], sigma[keep]))
+
+
+def xc_gradient(b, P, n_rad=60, n_th=12, func=e_b3lyp, h=1e-20):
+    """dE_xc/dR [natom, 3] at fixed density P: the derivative of the quadrature
+    energy itself, with the grid points moving with their atoms, the Becke
+    weights and the basis functions following the nuclei.  Each coordinate by
+    one complex-step evaluation (Squire and Trapp 1998), exact to rounding."""
+    xyz = np.asarray(b["xyz"], float)
+    nat = len(xyz)
+    g = np.zeros((nat, 3))
+    for A in range(nat):
+        for i in range(3):
+            xc_ = xyz.astype(complex)
+            xc_[A, i] += 1j * h
+            bc = dict(b, xyz=xc_)
+            E = xc_energy(bc, P, molecular_grid(b["Z"], xc_, n_rad, n_th), func)
+            g[A, i] = np.imag(E) / h
+    return g
+
+
+def ks_gradient(b, P, F, tau=1e-12, Q=None, n_rad=60, n_th=12):
+    """dE/dR of B3LYP at density P with Kohn-Sham Fock matrix F: the one-
+    electron, nuclear and two-electron terms of rhf.gradient with the exact
+    exchange scaled by a0 (the Pulay term W = P F P / 2 from the Kohn-Sham F),
+    plus the exchange-correlation term at fixed P."""
+    return (rhf.gradient(b, P, F, tau, Q, kx=A0_EXACT)
+            + xc_gradient(b, P, n_rad, n_th))

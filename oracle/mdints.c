@@ -543,14 +543,15 @@ long or_jk_sample(int nsh, int nbf, const int *l, const int *atom, const int *np
   return ns;
 }
 
-/* Two-electron gradient: g[atom][3] += 1/2 sum (mn|ls)^x [P_mn P_ls - 1/2 P_ml P_ns]
- * over all ordered index quartets, with the same Schwarz rule as or_jk.
+/* Two-electron gradient: g[atom][3] += 1/2 sum (mn|ls)^x [P_mn P_ls - kx/2 P_ml P_ns]
+ * over all ordered index quartets, with the same Schwarz rule as or_jk; kx is
+ * the share of exact exchange (1 for Hartree-Fock, 0.2 in B3LYP).
  * With amask != NULL only the atoms with amask[atom] != 0 are accumulated
  * (the others stay 0), and quartets with no shell on such an atom are skipped. */
 static long grad_2e(int nsh, int nbf, const int *l, const int *atom, const int *nprim,
                     const int *pofs, const int *bf, const double *exps, const double *coefs,
                     const double *xyz, int natom, const double *Q, double tau, const double *P,
-                    const int *amask, double *g) {
+                    double kx, const int *amask, double *g) {
   basis_t bs = {nsh, nbf, l, atom, nprim, pofs, bf, exps, coefs, xyz};
   int *lst;
   int nq = canonical_list(nsh, Q, tau, &lst);
@@ -592,7 +593,7 @@ static long grad_2e(int nsh, int nbf, const int *l, const int *atom, const int *
               for (int pp = 0; pp < np; ++pp) {
                 const int *pm = PERM8[which[pp]];
                 int mu = gi[pm[0]], nu = gi[pm[1]], la = gi[pm[2]], si = gi[pm[3]];
-                gam += 0.5 * (P[mu * n + nu] * P[la * n + si] - 0.5 * P[mu * n + la] * P[nu * n + si]);
+                gam += 0.5 * (P[mu * n + nu] * P[la * n + si] - 0.5 * kx * P[mu * n + la] * P[nu * n + si]);
               }
               /* every permutation has the same centre derivatives (same centres) */
               for (int cen = 0; cen < 4; ++cen) {
@@ -614,14 +615,21 @@ long or_grad_2e(int nsh, int nbf, const int *l, const int *atom, const int *npri
                 const int *pofs, const int *bf, const double *exps, const double *coefs,
                 const double *xyz, int natom, const double *Q, double tau, const double *P,
                 double *g) {
-  return grad_2e(nsh, nbf, l, atom, nprim, pofs, bf, exps, coefs, xyz, natom, Q, tau, P, NULL, g);
+  return grad_2e(nsh, nbf, l, atom, nprim, pofs, bf, exps, coefs, xyz, natom, Q, tau, P, 1.0, NULL, g);
+}
+
+long or_grad_2e_kx(int nsh, int nbf, const int *l, const int *atom, const int *nprim,
+                   const int *pofs, const int *bf, const double *exps, const double *coefs,
+                   const double *xyz, int natom, const double *Q, double tau, const double *P,
+                   double kx, double *g) {
+  return grad_2e(nsh, nbf, l, atom, nprim, pofs, bf, exps, coefs, xyz, natom, Q, tau, P, kx, NULL, g);
 }
 
 long or_grad_2e_atoms(int nsh, int nbf, const int *l, const int *atom, const int *nprim,
                       const int *pofs, const int *bf, const double *exps, const double *coefs,
                       const double *xyz, int natom, const double *Q, double tau, const double *P,
                       const int *amask, double *g) {
-  return grad_2e(nsh, nbf, l, atom, nprim, pofs, bf, exps, coefs, xyz, natom, Q, tau, P, amask, g);
+  return grad_2e(nsh, nbf, l, atom, nprim, pofs, bf, exps, coefs, xyz, natom, Q, tau, P, 1.0, amask, g);
 }
 
 /* One-electron gradient: g[atom][3] = sum P_mn dH_mn/dX - sum W_mn dS_mn/dX,

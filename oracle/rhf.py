@@ -51,6 +51,7 @@ def _c():
         _lib.or_jk.restype = ctypes.c_long
         _lib.or_grad_2e.restype = ctypes.c_long
         _lib.or_grad_2e_atoms.restype = ctypes.c_long
+        _lib.or_grad_2e_kx.restype = ctypes.c_long
         _lib.or_jk_sample.restype = ctypes.c_long
     return _lib
 
@@ -256,9 +257,11 @@ def scf(b, e_tol=1e-8, comm_tol=1e-6, max_iter=100, guess=None, tau=1e-12, diis_
                 Q=Q)
 
 
-def gradient(b, P, F, tau=1e-12, Q=None, atoms=None):
+def gradient(b, P, F, tau=1e-12, Q=None, atoms=None, kx=1.0):
     """dE/dR [natom,3] at density P with Fock matrix F (W = P F P / 2).
-    With ``atoms`` (indices) only those rows are computed; the others are NaN."""
+    With ``atoms`` (indices) only those rows are computed; the others are NaN.
+    ``kx`` is the share of exact exchange in the two-electron term (1 for
+    Hartree-Fock; with kx != 1 every atom is computed)."""
     nat = len(b["Z"])
     P = np.ascontiguousarray(P, dtype=np.float64)
     W = np.ascontiguousarray(0.5 * P @ F @ P)
@@ -267,10 +270,10 @@ def gradient(b, P, F, tau=1e-12, Q=None, atoms=None):
         Q = schwarz(b)
     Q = np.ascontiguousarray(Q)
     g1, g2 = np.zeros((nat, 3)), np.zeros((nat, 3))
-    if atoms is None:
+    if atoms is None or kx != 1.0:
         _c().or_grad_1e(*_bargs(b), ctypes.c_int(nat), _p(b["xyz"]), _p(Zi), _p(P), _p(W), _p(g1))
-        _c().or_grad_2e(*_bargs(b), _p(b["xyz"]), ctypes.c_int(nat), _p(Q), ctypes.c_double(tau),
-                        _p(P), _p(g2))
+        _c().or_grad_2e_kx(*_bargs(b), _p(b["xyz"]), ctypes.c_int(nat), _p(Q),
+                           ctypes.c_double(tau), _p(P), ctypes.c_double(kx), _p(g2))
         return g1 + g2 + nuclear_repulsion_gradient(b["Z"], b["xyz"])
     mask = np.zeros(nat, np.int32)
     mask[np.asarray(atoms, int)] = 1

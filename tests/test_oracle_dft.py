@@ -12,6 +12,11 @@
 * V_xc is the derivative of E_xc with respect to the density matrix.
 * E_xc is unchanged by a rigid translation (the grid moves with the atoms)
   and changes by grid-sized amounts under a rotation.
+* The exchange-correlation gradient at fixed density (complex step through
+  grid, weights, basis and functional) agrees with central differences of
+  E_xc and sums to zero over the atoms; the whole B3LYP gradient (exchange
+  share 0.2 in the two-electron term, the Pulay term from the Kohn-Sham F)
+  agrees with central differences of the converged SCF energy.
 * Sanity: the B3LYP SCF of water converges, 0.2-0.6 Eh below Hartree-Fock,
   and lands on the commonly quoted B3LYP/6-31G* energy of water at this
   geometry, -76.4087 Eh (a recalled value, within 2e-3 Eh: a check of the
@@ -143,3 +148,41 @@ def test_b3lyp_scf_of_water_converges_below_hartree_fock(b631gs):
     print("B3LYP", r["E"], "HF", hf["E"])
     assert hf["E"] - 0.6 < r["E"] < hf["E"] - 0.2
     assert abs(r["E"] - (-76.4087)) < 2e-3
+
+
+def test_xc_gradient_matches_differences_of_exc(sto3g):
+    z, x, b = _water(sto3g)
+    r = dft.ks_scf(b, 1e-10, 1e-8)
+    g = dft.xc_gradient(b, r["P"])
+    # translation: the grid and the weights move with the atoms
+    assert np.abs(g.sum(axis=0)).max() < 1e-12
+    h = 1e-4
+    for A, i in [(0, 0), (1, 2), (2, 1)]:
+        e = []
+        for sgn in (1, -1):
+            xp = np.array(x, float)
+            xp[A, i] += sgn * h
+            e.append(dft.xc_energy(dict(b, xyz=xp), r["P"], dft.molecular_grid(z, xp)))
+        assert abs((e[0] - e[1]) / (2 * h) - g[A, i]) < 5e-9, (A, i)
+
+
+def test_b3lyp_gradient_matches_differences_of_the_scf_energy(sto3g):
+    z, x, b = _water(sto3g)
+    r = dft.ks_scf(b, 1e-13, 1e-11)
+    assert r["converged"]
+    g = dft.ks_gradient(b, r["P"], r["F"])
+    assert np.abs(g.sum(axis=0)).max() < 1e-10
+    h = 1e-4
+    for A, i in [(0, 0), (1, 2), (2, 1)]:
+        e = []
+        for sgn in (1, -1):
+            xp = np.array(x, float)
+            xp[A, i] += sgn * h
+            rp = dft.ks_scf(oracle.build_basis(sto3g, z, xp), 1e-13, 1e-11)
+            assert rp["converged"]
+            e.append(rp["E"])
+        assert abs((e[0] - e[1]) / (2 * h) - g[A, i]) < 1e-8, (A, i)
+    # the exact-exchange share matters at this level: Hartree-Fock's
+    # two-electron term (share 1) moves the gradient far beyond the bound
+    g1 = rhf.gradient(b, r["P"], r["F"]) + dft.xc_gradient(b, r["P"])
+    assert np.abs(g1 - g).max() > 1e-3
