@@ -182,7 +182,8 @@ bscf_status bscf_run_scf(bscf_ctx* ctx, const bscf_scf_opts* opts, double* E, in
  * forces of the respective replica, summed into the zero-filled per-replica
  * arrays; Fig. 2c).
  * Forces F = -dE/dR [sum n_atoms][3] (Eh/bohr, host) at the densities of the
- * last bscf_run_scf (Pople et al. 1979 gradient with W = P F P / 2).
+ * last bscf_run_scf (Pople et al. 1979 gradient with W = P F P / 2; for a
+ * B3LYP SCF the Kohn-Sham gradient described at bscf_set_xc).
  * BSCF_E_STATE if no SCF has run at the current geometry or its densities
  * were replaced since. */
 bscf_status bscf_forces(bscf_ctx* ctx, double* F);
@@ -331,9 +332,14 @@ bscf_status bscf_set_deterministic(bscf_ctx* ctx, int on);
  * mapping, R = 1.0 bohr for H and 0.6 bohr otherwise; 12 Gauss-Legendre nodes
  * in cos(theta) x 24 in phi; Becke's fuzzy-cell weights).  Applies to every
  * later bscf_build_fock and bscf_run_scf of the context (bscf_build_jk still
- * returns J and K).  B3LYP forces are not implemented: bscf_forces after a
- * B3LYP SCF, bscf_forces_at, bscf_pimd_step and bscf_string_step answer
- * BSCF_E_UNSUPPORTED while B3LYP is set. */
+ * returns J and K).  Forces of a B3LYP SCF (bscf_forces, bscf_pimd_step,
+ * bscf_string_step; bscf_forces_at while B3LYP is set) are the analytic
+ * gradient of that discrete energy: the two-electron term with the exchange
+ * scaled by 0.2, W = P F P / 2 from the Kohn-Sham F, and the derivative of
+ * E_xc at fixed density with the grid points moving with their atoms,
+ * Becke's weight derivatives included.  They need every group of equal basis
+ * size to hold instances with the same atoms in the same order (beads,
+ * images); otherwise BSCF_E_UNSUPPORTED. */
 #define BSCF_XC_NONE 0
 #define BSCF_XC_B3LYP 1
 bscf_status bscf_set_xc(bscf_ctx* ctx, int functional);

@@ -419,7 +419,7 @@ __global__ __launch_bounds__(CP::NTQ) void coop_grad_kernel(GradArgs a) {
       const int mu = sa.bf + i, nu = sb.bf + j, la = sc_.bf + k, si = sd.bf + l;
       v = 0.5 * deg *
           (P[mu * n + nu] * P[la * n + si] -
-           0.25 * (P[mu * n + la] * P[nu * n + si] + P[mu * n + si] * P[nu * n + la]));
+           0.25 * a.kx * (P[mu * n + la] * P[nu * n + si] + P[mu * n + si] * P[nu * n + la]));
     }
     G[q][r] = v;
   }

@@ -337,11 +337,11 @@ struct bscf_ctx {
   double t_fock_gpu_ms = 0, t_work_ms = 0;
   // exchange-correlation builds: kernel time per step (HIP events, with
   // profiling), launches, builds, grid points evaluated and GEMM FLOPs
-  double xc_ms[5] = {}, xc_points = 0, xc_gemm_flops = 0;
+  double xc_ms[7] = {}, xc_points = 0, xc_gemm_flops = 0;
   // algorithmic bytes of the basis and point steps: per point 8 m + 32 and
   // 16 m + 32 with m the functions the point takes (n dense, a chunk's ns sparse)
   double xc_basis_bytes = 0, xc_point_bytes = 0;
-  long long xc_launches[5] = {}, xc_builds = 0;
+  long long xc_launches[7] = {}, xc_builds = 0;
   double t_work_host_ms = 0;   // host part of the work lists, wherever it ran
   double t_work_phase_ms[3] = {0, 0, 0};   // its ket lists, parts, merges
   rocblas_handle blas = nullptr;
@@ -514,7 +514,7 @@ struct bscf_ctx {
   } md;
 
   // B3LYP exchange-correlation: xc the setting of bscf_set_xc, xc_now that of
-  // the build in progress, scf_xc that of the last SCF (forces refuse it)
+  // the build in progress, scf_xc that of the last SCF (its forces add the XC term)
   int xc = 0, xc_now = 0;
   bool scf_xc = false;
   struct Xcs {
@@ -551,6 +551,8 @@ struct bscf_ctx {
     DevBuf<int> d_meta;                 // [chunk][6] of every group's sorted chunks
     DevBuf<double> Ps, Vs;
     DevBuf<double> V, exc;              // V_xc [mtot], E_xc [ninst]
+    // gradient (xc.h): Y = D Ps per slot, the point factors, e per grid point
+    DevBuf<double> Yg, gf, eg;
   } xcs;
 
   // string of images over the batch's instances; positions on the device
@@ -1547,7 +1549,9 @@ constexpr size_t kXcBudget = size_t(1) << 28;
 // sums the slices in order
 constexpr int kXcSlice = 8192;
 // steps of an XC build as timed by the statistics
-enum XcStep { kXcBasis = 0, kXcGemm = 1, kXcPoint = 2, kXcGemmV = 3, kXcWhole = 4 };
+// steps of the XC build, then the XC gradient's basis-function and weight terms
+enum XcStep { kXcBasis = 0, kXcGemm = 1, kXcPoint = 2, kXcGemmV = 3, kXcWhole = 4, kXcGradOrb = 5,
+              kXcGradWeight = 6 };
 
 // Radial and angular tables of the grid (xc.h), once per context
 void xc_tables(bscf_ctx* c) {
@@ -1925,6 +1929,101 @@ void xc_build(bscf_ctx* c, const double* P, bool masked) {
   if (pw >= 0) prof_end(c, pw, st);
   c->xc_launches[kXcWhole]++;
   c->xc_builds++;
+  HIPCHK(hipGetLastError());
+}
+
+// dE_xc/dR at the densities P of every instance, added into grad ([total
+// atoms][3]): the basis-function term per bucket of the sparse chunks, then
+// the Becke-weight term per instance (xc.h).  Needs the sparse form in every
+// group (instances of a group with the same atoms).
+void xc_gradient(bscf_ctx* c, const double* P, double* grad) {
+  auto& x = c->xcs;
+  xc_grid(c);
+  for (const auto& GC : x.gch)
+    need(GC.sparse, BSCF_E_UNSUPPORTED,
+         "B3LYP forces need the instances of each basis-size group to have the same atoms");
+  // the weight-derivative kernel keeps [natoms][64 + 3] doubles in LDS
+  need(sizeof(double) * (64 + 3) * (size_t)c->max_atoms <= 65536, BSCF_E_UNSUPPORTED,
+       "B3LYP forces are limited to 122 atoms per instance");
+  const hipStream_t st = c->stream;
+  x.eg.resize((size_t)x.npts);
+  const int p1 = c->profiling ? prof_begin(c, kXcGradOrb, 3, st) : -1;
+  launch_fill(x.eg.p, x.npts, 0.0, st);
+  const double one = 1.0, zero = 0.0;
+  const int G = kXcSparseG;
+  for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+    const Group& gr = c->groups[gi];
+    const auto& GC = x.gch[gi];
+    const int count = gr.count, n = gr.n;
+    XcSparseArgs a;
+    a.G = G;
+    a.count = count;
+    a.first = gr.first;
+    a.n = n;
+    a.sh_list = x.d_shl.p;
+    a.sh_cbf = x.d_scbf.p;
+    a.fmap = x.d_fmap.p;
+    a.sh_off = x.d_sh_off.p;
+    a.shells = c->d_shells.p;
+    a.sh_exp = c->d_sh_exp.p;
+    a.sh_coef = c->d_sh_coef.p;
+    a.pt_off = x.d_pt_off.p;
+    a.pts = x.pts.p;
+    a.moff = c->d_moff.p;
+    a.P = P;
+    a.V = nullptr;
+    for (const auto& bk : GC.buckets) {
+      const int W = bk.W;
+      const int per = std::max<int>(1, (int)(kXcBudget / ((size_t)count * W * G)));
+      for (int c0 = 0; c0 < bk.nch; c0 += per) {
+        const int nch = std::min(per, bk.nch - c0), slots = nch * count;
+        x.B.resize((size_t)slots * W * G);
+        x.Z.resize((size_t)slots * W * G);
+        x.Yg.resize((size_t)slots * W * G);
+        x.Ps.resize((size_t)slots * W * W);
+        x.gf.resize((size_t)slots * 5 * G);
+        a.W = W;
+        a.nch = nch;
+        a.meta = x.d_meta.p + 6 * (GC.meta0 + bk.c0 + c0);
+        a.B = x.B.p;
+        a.Z = x.Z.p;
+        a.Ps = x.Ps.p;
+        a.Vs = nullptr;
+        a.part = nullptr;
+        const long long sBZ = (long long)W * G, sP = (long long)W * W;
+        launch_xc_sparse_basis(a, bk.max_nsh, st);
+        launch_xc_sparse_gather(a, st);
+        // Z = B Ps
+        BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none,
+                                              rocblas_operation_none, G, W, W, &one, x.B.p, G,
+                                              sBZ, x.Ps.p, W, sP, &zero, x.Z.p, G, sBZ, slots));
+        launch_xc_sparse_gpoint(a, x.gf.p, x.eg.p, st);   // B <- D
+        // Y = D Ps
+        BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none,
+                                              rocblas_operation_none, G, W, W, &one, x.B.p, G,
+                                              sBZ, x.Ps.p, W, sP, &zero, x.Yg.p, G, sBZ, slots));
+        launch_xc_sparse_force(a, bk.max_nsh, x.gf.p, x.Yg.p, c->d_atom_off.p, grad, st);
+      }
+    }
+  }
+  if (p1 >= 0) prof_end(c, p1, st);
+  c->xc_launches[kXcGradOrb]++;
+  const int p2 = c->profiling ? prof_begin(c, kXcGradWeight, 3, st) : -1;
+  for (int i = 0; i < c->ninst; ++i) {
+    XcGridArgs g;
+    g.npts = x.npts_i[i];
+    g.natoms = c->natoms[i];
+    g.xyz = c->d_xyz.p + 3LL * c->atom_off[i];
+    g.Z = c->d_Zd.p + c->atom_off[i];
+    g.rad_r = x.rad_r.p;
+    g.rad_w = x.rad_w.p;
+    g.ang_u = x.ang_u.p;
+    g.ang_w = x.ang_w.p;
+    g.pts = nullptr;
+    launch_xc_weight_grad(g, x.eg.p + x.pt_off[i], grad + 3LL * c->atom_off[i], st);
+  }
+  if (p2 >= 0) prof_end(c, p2, st);
+  c->xc_launches[kXcGradWeight]++;
   HIPCHK(hipGetLastError());
 }
 
@@ -2889,7 +2988,9 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
 namespace {
 // -dE/dR of every instance at the densities c->P and Fock matrices c->F
 // (W = P F P / 2) into Fout [total_atoms][3] (host)
-void forces_impl(bscf_ctx* c, double* Fout) {
+// with_xc: B3LYP forces (exact exchange scaled by the hybrid's share, plus
+// the exchange-correlation term); W comes from the Kohn-Sham F then
+void forces_impl(bscf_ctx* c, double* Fout, bool with_xc = false) {
     const double t0 = now_ms();
     const hipStream_t st = c->stream;
     // W = P F P / 2
@@ -2960,6 +3061,7 @@ void forces_impl(bscf_ctx* c, double* Fout) {
     ga.shell_off = c->d_shell_off.p;
     ga.nsh = c->d_nshell.p;
     ga.tau = c->work_tau;
+    ga.kx = with_xc ? kXcA0 : 1.0;
     launch_shell_pmax(c->ninst, c->max_nshell, c->d_shell_off.p, c->d_nshell.p, c->d_pm_off.p,
                       c->d_shells.p, c->d_moff.p, c->d_nbf.p, c->P.p, c->d_pmax.p, st);
     launch_gather_pk(ketpos_args(c), c->max_ncd, c->P.p, c->d_Pk.p, st);
@@ -3101,6 +3203,7 @@ void forces_impl(bscf_ctx* c, double* Fout) {
       HIPCHK(hipStreamWaitEvent(st, c->ev_join[k - 1], 0));
     }
     HIPCHK(hipGetLastError());
+    if (with_xc) xc_gradient(c, c->P.p, c->d_grad.p);
     std::vector<double> g(3 * c->total_atoms);
     HIPCHK(hipMemcpyAsync(g.data(), c->d_grad.p, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     sync(c);
@@ -3114,9 +3217,8 @@ bscf_status bscf_forces(bscf_ctx* c, double* Fout) {
   return guard([&] {
     need(c && Fout, BSCF_E_INVALID, "NULL argument");
     need(c->have_scf, BSCF_E_STATE, "forces need an SCF at the current geometry");
-    need(!c->scf_xc, BSCF_E_UNSUPPORTED, "forces of a B3LYP SCF are not implemented");
     HIPCHK(hipSetDevice(c->device));
-    forces_impl(c, Fout);
+    forces_impl(c, Fout, c->scf_xc);
   });
 }
 
@@ -3125,7 +3227,6 @@ bscf_status bscf_forces_at(bscf_ctx* c, const double* P, const double* F, double
   return guard([&] {
     need(c && P && F && Fout, BSCF_E_INVALID, "NULL argument");
     need(std::isfinite(tau), BSCF_E_INVALID, "bad Schwarz cutoff");
-    need(c->xc == 0, BSCF_E_UNSUPPORTED, "forces of B3LYP are not implemented");
     require_geom(c);
     HIPCHK(hipSetDevice(c->device));
     // the screened work lists of the current geometry at this cutoff
@@ -3134,7 +3235,7 @@ bscf_status bscf_forces_at(bscf_ctx* c, const double* P, const double* F, double
     const auto kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIPCHK(hipMemcpyAsync(c->P.p, P, c->mtot * sizeof(double), kind, c->stream));
     HIPCHK(hipMemcpyAsync(c->F.p, F, c->mtot * sizeof(double), kind, c->stream));
-    forces_impl(c, Fout);
+    forces_impl(c, Fout, c->xc != 0);
   });
 }
 
@@ -3212,7 +3313,7 @@ void pimd_forces_here(bscf_ctx* c, const bscf_scf_opts* o, double* E, int* it, i
   check_status(bscf_set_geometries(c, x.data()));
   m.synced = true;
   check_status(bscf_run_scf(c, o, E, it, st));
-  forces_impl(c, F.data());
+  forces_impl(c, F.data(), c->scf_xc);
   if (Fout) std::copy(F.begin(), F.end(), Fout);
 }
 }  // namespace
@@ -3327,7 +3428,6 @@ bscf_status bscf_pimd_step(bscf_ctx* c, const bscf_scf_opts* opts, double* E, in
   return guard([&] {
     need(c != nullptr, BSCF_E_INVALID, "NULL context");
     need(c->md.on, BSCF_E_STATE, "no ring polymer: call bscf_pimd_init");
-    need(c->xc == 0, BSCF_E_UNSUPPORTED, "forces of B3LYP are not implemented");
     HIPCHK(hipSetDevice(c->device));
     if (!c->md.have_force) pimd_forces_here(c, opts, nullptr, nullptr, nullptr);
     pimd_begin_impl(c, nullptr);
@@ -3438,7 +3538,6 @@ bscf_status bscf_string_step(bscf_ctx* c, const bscf_scf_opts* opts, double* E, 
   return guard([&] {
     need(c != nullptr, BSCF_E_INVALID, "NULL context");
     need(c->str.on, BSCF_E_STATE, "no string: call bscf_string_init");
-    need(c->xc == 0, BSCF_E_UNSUPPORTED, "forces of B3LYP are not implemented");
     HIPCHK(hipSetDevice(c->device));
     auto& g = c->str;
     std::vector<double> x((size_t)g.n * 3 * g.N);
@@ -3450,7 +3549,7 @@ bscf_status bscf_string_step(bscf_ctx* c, const bscf_scf_opts* opts, double* E, 
       g.synced = true;
     }
     check_status(bscf_run_scf(c, opts, E, n_iter, status));
-    forces_impl(c, x.data());
+    forces_impl(c, x.data(), c->scf_xc);
     if (forces) std::copy(x.begin(), x.end(), forces);
     string_update(c, c->d_grad.p, -1.0);
     sync(c);
@@ -3681,7 +3780,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
     c->sp2_calls = c->sp2_steps = c->sp2_needed = c->sp2_fallbacks = 0;
     c->inc_builds = 0;
     c->graph_launches = c->graph_captures = 0;
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 7; ++k) {
       c->xc_ms[k] = 0;
       c->xc_launches[k] = 0;
     }
@@ -3710,8 +3809,9 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
       << ", \"xc\": {\"builds\": " << c->xc_builds << ", \"points\": " << c->xc_points
       << ", \"gemm_flops\": " << c->xc_gemm_flops << ", \"basis_bytes\": " << c->xc_basis_bytes
       << ", \"point_bytes\": " << c->xc_point_bytes << ", \"ms\": {";
-    const char* xn[5] = {"basis", "gemm", "point", "gemm_v", "build"};
-    for (int k = 0; k < 5; ++k)
+    const char* xn[7] = {"basis", "gemm", "point", "gemm_v", "build", "grad_basis_term",
+                         "grad_weight_term"};
+    for (int k = 0; k < 7; ++k)
       s << (k ? ", " : "") << "\"" << xn[k] << "\": [" << c->xc_ms[k] << ", " << c->xc_launches[k] << "]";
     s << "}}, \"classes\": {";
     const QuartetClass* qc = quartet_classes();

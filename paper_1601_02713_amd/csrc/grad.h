@@ -38,6 +38,9 @@ struct GradArgs {
   const int* shell_off;    // first global shell of each instance
   const int* nsh;          // shells per instance
   double tau;
+  // share of exact exchange in the density factor: 1 for Hartree-Fock, 0.2
+  // for B3LYP (the bound above stays an upper bound for kx <= 1)
+  double kx;
 };
 
 // Density-weighted bound of quartet (bid|kid) (see GradArgs).

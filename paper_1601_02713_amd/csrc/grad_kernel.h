@@ -215,6 +215,7 @@ __global__ __launch_bounds__(256) void grad_unit_kernel(GradArgs a) {
     // all below the bound skips the integrals
     const bool keep = valid && !(a.tau > 0.0 && grad_quartet_bound(a, bid, kid) < a.tau);
     const double fac = keep ? 0.5 * deg : 0.0;
+    const double qx = 0.25 * a.kx;
     const int l0 = sc.bf, s0 = sd.bf;
     // density factors of the quartet (Coulomb and exchange terms)
     auto gfill = [&](double* G) {
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(256) void grad_unit_kernel(GradArgs a) {
               const double pac = Prow[i * n + l0 + k], pbd = Prow[(NA + j) * n + s0 + l];
               const double pad = Prow[i * n + s0 + l], pbc = Prow[(NA + j) * n + l0 + k];
               G[((i * NB + j) * NC + k) * ND + l] =
-                  fac * (pab * pcd - 0.25 * (pac * pbd + pad * pbc));
+                  fac * (pab * pcd - qx * (pac * pbd + pad * pbc));
             }
         }
     };

@@ -110,6 +110,30 @@ void launch_xc_sparse_scatter(const XcSparseArgs& a, hipStream_t s);
 // exc[first + i] += the partial sums of instance i over the launch's chunks, in order
 void launch_xc_sparse_reduce(const XcSparseArgs& a, double* exc, hipStream_t s);
 
+// Nuclear gradient of E_xc at fixed density (closed shell, sparse form).  Per
+// point of a chunk of atom B, for every atom A != B (point held fixed):
+//   d(w e)/dR_A = w_rad w_ang e dW_B/dR_A
+//                 + w [v_rho drho/dR_A + v_sigma dsigma/dR_A],
+//   drho/dR_A   = -2 sum_{m on A} grad phi_m Z_m,
+//   dsigma/dR_A = -4 sum_{m on A} [(H_m grad rho) Z_m + grad phi_m Y_m],
+// Z_m = sum_n P_mn phi_n, Y_m = sum_n P_mn (grad rho . grad phi_n), H_m the
+// Hessian of phi_m, W_B the Becke weight; atom B takes minus the sum over
+// A != B (each point's term is unchanged by a rigid translation, the point
+// moving with its atom).
+//
+// xc_sparse_gpoint: per point rho, grad rho and the functional; writes
+// D_m = grad rho . grad phi_m over B (the compact functions), the factors
+// gf[slot][5][G] = {w v_rho, w v_sigma, grad rho} and e per grid point into
+// eg (zero where rho is below kXcRhoMin).  Then Y = D Ps (a batched GEMM).
+void launch_xc_sparse_gpoint(const XcSparseArgs& a, double* gf, double* eg, hipStream_t s);
+// xc_sparse_force: the basis-function term, one thread per (point, shell),
+// summed per block and shell into grad[3 * atom] (dE/dR) with atomics
+void launch_xc_sparse_force(const XcSparseArgs& a, int max_nsh, const double* gf,
+                            const double* Y, const int* atom_off, double* grad, hipStream_t s);
+// xc_weight_grad: the Becke-weight term of one instance's points (the grid
+// arguments of the instance; eg its energy densities; grad its atoms' rows)
+void launch_xc_weight_grad(const XcGridArgs& a, const double* eg, double* grad, hipStream_t s);
+
 void launch_xc_grid(const XcGridArgs& a, hipStream_t s);
 // count instances of the run, at most max_nsh shells each
 void launch_xc_basis(const XcChunkArgs& a, int count, int max_nsh, hipStream_t s);

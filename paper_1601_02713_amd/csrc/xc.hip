@@ -159,6 +159,73 @@ __device__ __forceinline__ void shell_eval(const Shell& sh, const double* __rest
   }
 }
 
+// Values, gradients and Hessians (xx, xy, xz, yy, yz, zz) of the Cartesian
+// components of one shell, same order and normalisation as shell_eval:
+// f(k, v, g[3], h[6]).  Each component is s x^a y^b z^c R(r^2) with
+// R = sum c e^{-alpha r^2}: d_i R = 2 x_i R', d_i d_j R = 2 delta_ij R' +
+// 4 x_i x_j R''.
+struct Mono {
+  double v, d, dd;   // x^a and its first two derivatives
+};
+__device__ __forceinline__ Mono mono(int a, double x) {
+  if (a == 0) return {1.0, 0.0, 0.0};
+  if (a == 1) return {x, 1.0, 0.0};
+  return {x * x, 2.0 * x, 2.0};
+}
+template <class Fn>
+__device__ __forceinline__ void shell_eval_h(const Shell& sh, const double* __restrict__ ex,
+                                             const double* __restrict__ co, double dx, double dy,
+                                             double dz, Fn&& f) {
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  double R = 0.0, R1 = 0.0, R2 = 0.0;
+  for (int k = 0; k < sh.nprim; ++k) {
+    const double al = ex[sh.prim0 + k];
+    const double e = co[sh.prim0 + k] * exp(-al * r2);
+    R += e;
+    R1 -= al * e;
+    R2 += al * al * e;
+  }
+  const double d[3] = {dx, dy, dz};
+  double Rg[3], Rh[6];
+  {
+    int q = 0;
+    for (int i = 0; i < 3; ++i) {
+      Rg[i] = 2.0 * d[i] * R1;
+      for (int j = i; j < 3; ++j, ++q) Rh[q] = (i == j ? 2.0 * R1 : 0.0) + 4.0 * d[i] * d[j] * R2;
+    }
+  }
+  auto comp = [&](int k, int a, int b, int c, double sc) {
+    const Mono X = mono(a, dx), Y = mono(b, dy), Z = mono(c, dz);
+    const double A = X.v * Y.v * Z.v;
+    const double Ag[3] = {X.d * Y.v * Z.v, X.v * Y.d * Z.v, X.v * Y.v * Z.d};
+    const double Ah[6] = {X.dd * Y.v * Z.v, X.d * Y.d * Z.v, X.d * Y.v * Z.d,
+                          X.v * Y.dd * Z.v, X.v * Y.d * Z.d, X.v * Y.v * Z.dd};
+    double g[3], h[6];
+    int q = 0;
+    for (int i = 0; i < 3; ++i) {
+      g[i] = sc * (Ag[i] * R + A * Rg[i]);
+      for (int j = i; j < 3; ++j, ++q)
+        h[q] = sc * (Ah[q] * R + Ag[i] * Rg[j] + Ag[j] * Rg[i] + A * Rh[q]);
+    }
+    f(k, sc * A * R, g, h);
+  };
+  if (sh.l == 0) {
+    comp(0, 0, 0, 0, 1.0);
+  } else if (sh.l == 1) {
+    comp(0, 1, 0, 0, 1.0);
+    comp(1, 0, 1, 0, 1.0);
+    comp(2, 0, 0, 1, 1.0);
+  } else {
+    const double r3 = 0.57735026918962576451;   // 1/sqrt(3): xx, yy, zz
+    comp(0, 2, 0, 0, r3);
+    comp(1, 1, 1, 0, 1.0);
+    comp(2, 1, 0, 1, 1.0);
+    comp(3, 0, 2, 0, r3);
+    comp(4, 0, 1, 1, 1.0);
+    comp(5, 0, 0, 2, r3);
+  }
+}
+
 // one thread per (point, shell, instance of the run): the shell's basis
 // values at the point (zero past the instance's last point)
 __global__ __launch_bounds__(256) void xc_basis_kernel(XcChunkArgs a) {
@@ -400,6 +467,224 @@ __global__ __launch_bounds__(256) void xc_sparse_reduce_kernel(XcSparseArgs a, d
   if (threadIdx.x == 0) exc[a.first + zi] += red[0];
 }
 
+// ---------------------------------------------------------- gradient
+
+// as xc_sparse_point_kernel up to the functional; then D over B, the point
+// factors and the energy density (xc.h)
+__global__ __launch_bounds__(256) void xc_sparse_gpoint_kernel(XcSparseArgs a, double* gf,
+                                                               double* eg) {
+  const int gl = blockIdx.x * blockDim.x + threadIdx.x;
+  const int slot = blockIdx.y, c = slot / a.count, zi = slot - c * a.count, inst = a.first + zi;
+  const ChunkMeta m = chunk_meta(a.meta, c);
+  double* f = gf + (size_t)slot * 5 * a.G + gl;
+  if (gl >= m.gcnt) {
+    for (int k = 0; k < 5; ++k) f[(size_t)k * a.G] = 0.0;
+    return;
+  }
+  const long long gp = a.pt_off[inst] + m.p0 + gl;
+  const double* pt = a.pts + 4 * gp;
+  const double x = pt[0], y = pt[1], z = pt[2], w = pt[3];
+  const double* Zc = a.Z + (size_t)slot * a.W * a.G + gl;
+  double* Dc = a.B + (size_t)slot * a.W * a.G + gl;
+  const Shell* sh0 = a.shells + a.sh_off[inst];
+  double rho = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int j = m.sh0; j < m.sh0 + m.nsh; ++j) {
+    const Shell sh = sh0[a.sh_list[j]];
+    const double* zf = Zc + (size_t)a.sh_cbf[j] * a.G;
+    shell_eval<true>(sh, a.sh_exp, a.sh_coef, x - sh.x, y - sh.y, z - sh.z,
+                     [&](int k, double v, double vx, double vy, double vz) {
+                       const double zz = zf[(size_t)k * a.G];
+                       rho += v * zz;
+                       gx += vx * zz;
+                       gy += vy * zz;
+                       gz += vz * zz;
+                     });
+  }
+  gx *= 2.0;
+  gy *= 2.0;
+  gz *= 2.0;
+  double cr = 0.0, cs = 0.0, e = 0.0;
+  if (rho > kXcRhoMin) {
+    const Xc fx = b3lyp(rho, gx * gx + gy * gy + gz * gz);
+    cr = w * fx.vr;
+    cs = w * fx.vs;
+    e = fx.e;
+  }
+  f[0] = cr;
+  f[(size_t)a.G] = cs;
+  f[(size_t)2 * a.G] = gx;
+  f[(size_t)3 * a.G] = gy;
+  f[(size_t)4 * a.G] = gz;
+  eg[gp] = e;
+  for (int j = m.sh0; j < m.sh0 + m.nsh; ++j) {
+    const Shell sh = sh0[a.sh_list[j]];
+    double* df = Dc + (size_t)a.sh_cbf[j] * a.G;
+    shell_eval<true>(sh, a.sh_exp, a.sh_coef, x - sh.x, y - sh.y, z - sh.z,
+                     [&](int k, double, double vx, double vy, double vz) {
+                       df[(size_t)k * a.G] = gx * vx + gy * vy + gz * vz;
+                     });
+  }
+}
+
+// grid (G / 256, max_nsh, slots): y a shell of the chunk
+__global__ __launch_bounds__(256) void xc_sparse_force_kernel(XcSparseArgs a, const double* gf,
+                                                              const double* Y,
+                                                              const int* atom_off, double* grad) {
+  __shared__ double red[3][256];
+  const int gl = blockIdx.x * blockDim.x + threadIdx.x;
+  const int slot = blockIdx.z, c = slot / a.count, zi = slot - c * a.count, inst = a.first + zi;
+  const ChunkMeta m = chunk_meta(a.meta, c);
+  if ((int)blockIdx.y >= m.nsh) return;   // the whole block
+  const int j = m.sh0 + blockIdx.y;
+  const Shell sh = a.shells[a.sh_off[inst] + a.sh_list[j]];
+  const int own = atom_off[inst] + m.p0 / kXcPerAtom;   // the chunk's atom
+  if (sh.atom == own) return;             // no net term (translation)
+  double t[3] = {0.0, 0.0, 0.0};
+  if (gl < m.gcnt) {
+    const double* f = gf + (size_t)slot * 5 * a.G + gl;
+    const double cr = f[0], cs = f[(size_t)a.G];
+    if (cr != 0.0 || cs != 0.0) {
+      const double g[3] = {f[(size_t)2 * a.G], f[(size_t)3 * a.G], f[(size_t)4 * a.G]};
+      const double* pt = a.pts + 4 * (a.pt_off[inst] + m.p0 + gl);
+      const size_t o = (size_t)slot * a.W * a.G + (size_t)a.sh_cbf[j] * a.G + gl;
+      const double* zf = a.Z + o;
+      const double* yf = Y + o;
+      shell_eval_h(sh, a.sh_exp, a.sh_coef, pt[0] - sh.x, pt[1] - sh.y, pt[2] - sh.z,
+                   [&](int k, double, const double* dv, const double* h) {
+                     const double zz = zf[(size_t)k * a.G], yy = yf[(size_t)k * a.G];
+                     const double hg[3] = {h[0] * g[0] + h[1] * g[1] + h[2] * g[2],
+                                           h[1] * g[0] + h[3] * g[1] + h[4] * g[2],
+                                           h[2] * g[0] + h[4] * g[1] + h[5] * g[2]};
+                     for (int i = 0; i < 3; ++i)
+                       t[i] += -2.0 * cr * dv[i] * zz - 4.0 * cs * (hg[i] * zz + dv[i] * yy);
+                   });
+    }
+  }
+  for (int i = 0; i < 3; ++i) red[i][threadIdx.x] = t[i];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int i = 0; i < 3; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) {
+    const double v = red[threadIdx.x][0];
+    if (v != 0.0) {
+      atomicAdd(&grad[3 * sh.atom + threadIdx.x], v);
+      atomicAdd(&grad[3 * own + threadIdx.x], -v);
+    }
+  }
+}
+
+// Becke's s(mu) = (1 - p(p(p(mu)))) / 2 and s'/s (zero where s vanishes: mu
+// = 1, where s' vanishes too)
+__device__ __forceinline__ void becke_s(double mu, double& s, double& t) {
+  const double p1 = 1.5 * mu - 0.5 * mu * mu * mu;
+  const double p2 = 1.5 * p1 - 0.5 * p1 * p1 * p1;
+  const double p3 = 1.5 * p2 - 0.5 * p2 * p2 * p2;
+  s = 0.5 * (1.0 - p3);
+  const double ds = -0.5 * 1.5 * (1.0 - p2 * p2) * 1.5 * (1.0 - p1 * p1) * 1.5 * (1.0 - mu * mu);
+  t = s > 0.0 ? ds / s : 0.0;
+}
+
+// one thread per point of the instance (blocks of 64); dynamic LDS: the cell
+// functions P_C of the block's points [natoms][64] and the block's gradient
+// sums [natoms][3]
+__global__ __launch_bounds__(64) void xc_weight_grad_kernel(XcGridArgs a, const double* eg,
+                                                            double* grad) {
+  extern __shared__ double lds[];
+  const int na = a.natoms;
+  double* Pc = lds;              // [C][64]
+  double* Gs = lds + 64 * na;    // [A][3]
+  for (int t = threadIdx.x; t < 3 * na; t += 64) Gs[t] = 0.0;
+  __syncthreads();
+  const int p = blockIdx.x * 64 + threadIdx.x;
+  const double* R = a.xyz;
+  double e = 0.0;
+  if (p < a.npts) e = eg[p];
+  if (e != 0.0) {
+    const int B = p / kXcPerAtom, k = p - B * kXcPerAtom;
+    const int i = k / kXcAng, jj = k - i * kXcAng;
+    const int tab = a.Z[B] == 1.0 ? 0 : 1;
+    const double r = a.rad_r[tab * kXcRad + i];
+    const double x = R[3 * B] + r * a.ang_u[3 * jj];
+    const double y = R[3 * B + 1] + r * a.ang_u[3 * jj + 1];
+    const double z = R[3 * B + 2] + r * a.ang_u[3 * jj + 2];
+    const double wra = a.rad_w[tab * kXcRad + i] * a.ang_w[jj];
+    auto dist = [&](int C) {
+      const double dx = x - R[3 * C], dy = y - R[3 * C + 1], dz = z - R[3 * C + 2];
+      return sqrt(dx * dx + dy * dy + dz * dz);
+    };
+    auto sep = [&](int C, int D) {
+      const double dx = R[3 * C] - R[3 * D], dy = R[3 * C + 1] - R[3 * D + 1],
+                   dz = R[3 * C + 2] - R[3 * D + 2];
+      return sqrt(dx * dx + dy * dy + dz * dz);
+    };
+    double Zs = 0.0;
+    for (int C = 0; C < na; ++C) {
+      const double rC = dist(C);
+      double PC = 1.0;
+      for (int D = 0; D < na && PC > 0.0; ++D) {
+        if (D == C) continue;
+        double s, t;
+        becke_s((rC - dist(D)) / sep(C, D), s, t);
+        PC *= s;
+      }
+      Pc[C * 64 + threadIdx.x] = PC;
+      Zs += PC;
+    }
+    const double PB = Pc[B * 64 + threadIdx.x];
+    if (Zs > 0.0 && PB > 0.0) {
+      const double WB = PB / Zs, fac = wra * e / Zs;
+      double gB[3] = {0.0, 0.0, 0.0};
+      for (int A = 0; A < na; ++A) {
+        if (A == B) continue;
+        const double rA = dist(A);
+        const double eA[3] = {(x - R[3 * A]) / rA, (y - R[3 * A + 1]) / rA,
+                              (z - R[3 * A + 2]) / rA};
+        // S_A = sum_C dP_C/dR_A; dPB = dP_B/dR_A
+        double S[3] = {0.0, 0.0, 0.0}, dPB[3] = {0.0, 0.0, 0.0}, uA[3] = {0.0, 0.0, 0.0};
+        const double PA = Pc[A * 64 + threadIdx.x];
+        for (int C = 0; C < na; ++C) {
+          if (C == A) continue;
+          const double RCA = sep(C, A), rC = dist(C);
+          const double muCA = (rC - rA) / RCA;
+          const double dv[3] = {R[3 * C] - R[3 * A], R[3 * C + 1] - R[3 * A + 1],
+                                R[3 * C + 2] - R[3 * A + 2]};
+          const double PC = Pc[C * 64 + threadIdx.x];
+          if (PC > 0.0) {
+            // dmu_CA/dR_A = e_A / R_CA + mu_CA (R_C - R_A) / R_CA^2
+            double s, t;
+            becke_s(muCA, s, t);
+            for (int d = 0; d < 3; ++d) {
+              const double v = PC * t * (eA[d] / RCA + muCA * dv[d] / (RCA * RCA));
+              S[d] += v;
+              if (C == B) dPB[d] = v;
+            }
+          }
+          if (PA > 0.0) {
+            // mu_AC = -mu_CA; dmu_AC/dR_A = -e_A / R_AC + mu_CA (R_A - R_C) / R_AC^2
+            double s, t;
+            becke_s(-muCA, s, t);
+            for (int d = 0; d < 3; ++d) uA[d] += t * (-eA[d] / RCA - muCA * dv[d] / (RCA * RCA));
+          }
+        }
+        for (int d = 0; d < 3; ++d) {
+          const double v = fac * (dPB[d] - WB * (S[d] + PA * uA[d]));
+          atomicAdd(&Gs[3 * A + d], v);
+          gB[d] -= v;
+        }
+      }
+      for (int d = 0; d < 3; ++d) atomicAdd(&Gs[3 * B + d], gB[d]);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 3 * na; t += 64) {
+    const double v = Gs[t];
+    if (v != 0.0) atomicAdd(&grad[t], v);
+  }
+}
+
 // M <- M + M^T for each of the run's n x n matrices
 __global__ void xc_symmetrize_kernel(int n, double* V) {
   const int i = blockIdx.y, j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -487,6 +772,26 @@ void launch_xc_sparse_scatter(const XcSparseArgs& a, hipStream_t s) {
 void launch_xc_sparse_reduce(const XcSparseArgs& a, double* exc, hipStream_t s) {
   if (a.count == 0 || a.nch == 0) return;
   hipLaunchKernelGGL(xc_sparse_reduce_kernel, dim3(a.count), dim3(256), 0, s, a, exc);
+}
+
+void launch_xc_sparse_gpoint(const XcSparseArgs& a, double* gf, double* eg, hipStream_t s) {
+  if (a.nch * a.count == 0) return;
+  hipLaunchKernelGGL(xc_sparse_gpoint_kernel, dim3(a.G / 256, a.nch * a.count), dim3(256), 0, s,
+                     a, gf, eg);
+}
+
+void launch_xc_sparse_force(const XcSparseArgs& a, int max_nsh, const double* gf,
+                            const double* Y, const int* atom_off, double* grad, hipStream_t s) {
+  if (a.nch * a.count == 0 || max_nsh == 0) return;
+  hipLaunchKernelGGL(xc_sparse_force_kernel, dim3(a.G / 256, max_nsh, a.nch * a.count),
+                     dim3(256), 0, s, a, gf, Y, atom_off, grad);
+}
+
+void launch_xc_weight_grad(const XcGridArgs& a, const double* eg, double* grad, hipStream_t s) {
+  if (a.npts == 0) return;
+  const size_t lds = sizeof(double) * (64 + 3) * (size_t)a.natoms;
+  hipLaunchKernelGGL(xc_weight_grad_kernel, dim3((a.npts + 63) / 64), dim3(64), lds, s, a, eg,
+                     grad);
 }
 
 void launch_xc_functional(int n, const double* rho, const double* sigma, double* e, double* vr,

@@ -12,7 +12,11 @@ the CPU suite pins to closed forms and to the derivative identities.
   with whole-instance chunks and with chunks of 9984 points (several per
   instance, the last one ragged).
 * Kohn-Sham F and E of one build, and converged B3LYP SCF energies.
-* B3LYP forces are refused, and bscf_build_jk ignores the setting.
+* B3LYP forces at the oracle's converged densities and Kohn-Sham Fock
+  matrices against the oracle's gradient (itself pinned to differences of
+  the SCF energy); the forces of the device's own B3LYP SCF; a group whose
+  instances differ in their atoms is refused (the sparse chunks the gradient
+  runs on need the same atoms).  bscf_build_jk ignores the setting.
 """
 
 import numpy as np
@@ -146,22 +150,46 @@ def test_b3lyp_scf_energies_match_oracle(beadscf, b631gs):
         assert abs(E[k] - r["E"]) < 1e-7, (k, E[k], r["E"])
 
 
-def test_b3lyp_forces_are_refused(beadscf, b631gs):
-    inst = _batch()[1:2]
+def test_b3lyp_forces_match_oracle(beadscf, b631gs):
+    inst = _batch()
+    bs = [oracle.build_basis(b631gs, z, x) for z, x in inst]
+    refs = [dft.ks_scf(b, 1e-10, 1e-8) for b in bs]
+    assert all(r["converged"] for r in refs)
     e = _engine(beadscf, b631gs, inst)
     try:
         e.set_xc(beadscf.XC_B3LYP)
-        e.run_scf()
+        Fa = e.forces_at([r["P"] for r in refs], [r["F"] for r in refs])
+        E, it, st = e.run_scf(e_tol=1e-10, comm_tol=1e-8)
+        Fs = e.forces()
+        # forces belong to the SCF that was run: switching the setting after
+        # it changes nothing
+        e.set_xc(beadscf.XC_NONE)
+        Fs2 = e.forces()
+    finally:
+        e.close()
+    assert np.all(st == 0), st
+    for k, (b, r) in enumerate(zip(bs, refs)):
+        g = dft.ks_gradient(b, r["P"], r["F"])
+        assert np.abs(Fa[k] + g).max() < 1e-9, (k, np.abs(Fa[k] + g).max())
+        assert np.abs(Fa[k].sum(axis=0)).max() < 1e-10
+        # the device's own SCF: the same forces to the SCF's convergence
+        assert np.abs(Fs[k] + g).max() < 1e-5, k
+        assert np.abs(Fs2[k] - Fs[k]).max() < 1e-12, k
+
+
+def test_b3lyp_forces_need_like_atoms_in_a_group(beadscf, b631gs):
+    zw, xw = inputs.workload("h2o_sto3g")["instances"][0]
+    order = [1, 0, 2]    # the same water with its atoms in another order
+    inst = [(zw, xw), (zw[order], xw[order])]
+    e = _engine(beadscf, b631gs, inst)
+    try:
+        e.set_xc(beadscf.XC_B3LYP)
+        E, it, st = e.run_scf(e_tol=1e-9, comm_tol=1e-7)
+        assert np.all(st == 0)
+        assert abs(E[0] - E[1]) < 1e-8
         with pytest.raises(beadscf.BscfError) as ei:
             e.forces()
         assert ei.value.code == -2
-        # switching back does not make the B3LYP densities' forces valid
-        e.set_xc(beadscf.XC_NONE)
-        with pytest.raises(beadscf.BscfError):
-            e.forces()
-        e.run_scf()
-        F = e.forces()
-        assert np.all(np.isfinite(np.concatenate([f.ravel() for f in F])))
         with pytest.raises(beadscf.BscfError):
             e.set_xc(2)
     finally:
