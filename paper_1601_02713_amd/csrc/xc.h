@@ -40,6 +40,7 @@ struct XcGridArgs {
   const double* ang_u;      // [kXcAng][3]
   const double* ang_w;      // [kXcAng]
   double* pts;              // [npts][4]: x, y, z, weight (Becke weight included)
+  const double* inv_sep;    // [natoms][natoms] 1/|R_A - R_B| (weight gradient only)
 };
 
 struct XcChunkArgs {

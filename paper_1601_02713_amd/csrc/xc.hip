@@ -588,14 +588,20 @@ __device__ __forceinline__ void becke_s(double mu, double& s, double& t) {
 }
 
 // one thread per point of the instance (blocks of 64); dynamic LDS: the cell
-// functions P_C of the block's points [natoms][64] and the block's gradient
-// sums [natoms][3]
+// functions P_C and the distances r_C of the block's points [natoms][64] each
+// and the block's gradient sums [natoms][3].  A cell function below kCellTiny is taken as zero here
+// (its terms, bounded by it times |s'| <= 2.1, are far below rounding of the
+// others), so per point only the pairs that touch a cell of the point do the
+// work.
+constexpr double kCellTiny = 1e-30;
 __global__ __launch_bounds__(64) void xc_weight_grad_kernel(XcGridArgs a, const double* eg,
                                                             double* grad) {
   extern __shared__ double lds[];
   const int na = a.natoms;
   double* Pc = lds;              // [C][64]
-  double* Gs = lds + 64 * na;    // [A][3]
+  double* Rc = lds + 64 * na;    // [C][64]
+  double* Gs = lds + 128 * na;   // [A][3]
+  const double* iR = a.inv_sep;  // [C][D]
   for (int t = threadIdx.x; t < 3 * na; t += 64) Gs[t] = 0.0;
   __syncthreads();
   const int p = blockIdx.x * 64 + threadIdx.x;
@@ -611,25 +617,23 @@ __global__ __launch_bounds__(64) void xc_weight_grad_kernel(XcGridArgs a, const 
     const double y = R[3 * B + 1] + r * a.ang_u[3 * jj + 1];
     const double z = R[3 * B + 2] + r * a.ang_u[3 * jj + 2];
     const double wra = a.rad_w[tab * kXcRad + i] * a.ang_w[jj];
-    auto dist = [&](int C) {
+    for (int C = 0; C < na; ++C) {
       const double dx = x - R[3 * C], dy = y - R[3 * C + 1], dz = z - R[3 * C + 2];
-      return sqrt(dx * dx + dy * dy + dz * dz);
-    };
-    auto sep = [&](int C, int D) {
-      const double dx = R[3 * C] - R[3 * D], dy = R[3 * C + 1] - R[3 * D + 1],
-                   dz = R[3 * C + 2] - R[3 * D + 2];
-      return sqrt(dx * dx + dy * dy + dz * dz);
-    };
+      Rc[C * 64 + threadIdx.x] = sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    auto dist = [&](int C) { return Rc[C * 64 + threadIdx.x]; };
     double Zs = 0.0;
     for (int C = 0; C < na; ++C) {
       const double rC = dist(C);
       double PC = 1.0;
-      for (int D = 0; D < na && PC > 0.0; ++D) {
+      for (int D = 0; D < na && PC >= kCellTiny; ++D) {
         if (D == C) continue;
-        double s, t;
-        becke_s((rC - dist(D)) / sep(C, D), s, t);
-        PC *= s;
+        const double mu = (rC - dist(D)) * iR[C * na + D];
+        const double p1 = 1.5 * mu - 0.5 * mu * mu * mu;
+        const double p2 = 1.5 * p1 - 0.5 * p1 * p1 * p1;
+        PC *= 0.5 * (1.0 - (1.5 * p2 - 0.5 * p2 * p2 * p2));
       }
+      if (PC < kCellTiny) PC = 0.0;
       Pc[C * 64 + threadIdx.x] = PC;
       Zs += PC;
     }
@@ -639,39 +643,40 @@ __global__ __launch_bounds__(64) void xc_weight_grad_kernel(XcGridArgs a, const 
       double gB[3] = {0.0, 0.0, 0.0};
       for (int A = 0; A < na; ++A) {
         if (A == B) continue;
-        const double rA = dist(A);
-        const double eA[3] = {(x - R[3 * A]) / rA, (y - R[3 * A + 1]) / rA,
-                              (z - R[3 * A + 2]) / rA};
-        // S_A = sum_C dP_C/dR_A; dPB = dP_B/dR_A
+        const double rA = dist(A), irA = 1.0 / rA;
+        const double eA[3] = {(x - R[3 * A]) * irA, (y - R[3 * A + 1]) * irA,
+                              (z - R[3 * A + 2]) * irA};
+        // S = sum_{C != A} dP_C/dR_A, dPB = dP_B/dR_A, uA = dP_A/dR_A / P_A
         double S[3] = {0.0, 0.0, 0.0}, dPB[3] = {0.0, 0.0, 0.0}, uA[3] = {0.0, 0.0, 0.0};
         const double PA = Pc[A * 64 + threadIdx.x];
         for (int C = 0; C < na; ++C) {
           if (C == A) continue;
-          const double RCA = sep(C, A), rC = dist(C);
-          const double muCA = (rC - rA) / RCA;
+          const double PC = Pc[C * 64 + threadIdx.x];
+          if (PC == 0.0 && PA == 0.0) continue;
+          const double iRCA = iR[C * na + A], rC = dist(C);
+          const double muCA = (rC - rA) * iRCA;
           const double dv[3] = {R[3 * C] - R[3 * A], R[3 * C + 1] - R[3 * A + 1],
                                 R[3 * C + 2] - R[3 * A + 2]};
-          const double PC = Pc[C * 64 + threadIdx.x];
-          if (PC > 0.0) {
+          if (PC != 0.0) {
             // dmu_CA/dR_A = e_A / R_CA + mu_CA (R_C - R_A) / R_CA^2
             double s, t;
             becke_s(muCA, s, t);
             for (int d = 0; d < 3; ++d) {
-              const double v = PC * t * (eA[d] / RCA + muCA * dv[d] / (RCA * RCA));
+              const double v = PC * t * (eA[d] * iRCA + muCA * dv[d] * iRCA * iRCA);
               S[d] += v;
               if (C == B) dPB[d] = v;
             }
           }
-          if (PA > 0.0) {
+          if (PA != 0.0) {
             // mu_AC = -mu_CA; dmu_AC/dR_A = -e_A / R_AC + mu_CA (R_A - R_C) / R_AC^2
             double s, t;
             becke_s(-muCA, s, t);
-            for (int d = 0; d < 3; ++d) uA[d] += t * (-eA[d] / RCA - muCA * dv[d] / (RCA * RCA));
+            for (int d = 0; d < 3; ++d) uA[d] += t * (-eA[d] * iRCA - muCA * dv[d] * iRCA * iRCA);
           }
         }
         for (int d = 0; d < 3; ++d) {
           const double v = fac * (dPB[d] - WB * (S[d] + PA * uA[d]));
-          atomicAdd(&Gs[3 * A + d], v);
+          if (v != 0.0) atomicAdd(&Gs[3 * A + d], v);
           gB[d] -= v;
         }
       }
@@ -789,7 +794,7 @@ void launch_xc_sparse_force(const XcSparseArgs& a, int max_nsh, const double* gf
 
 void launch_xc_weight_grad(const XcGridArgs& a, const double* eg, double* grad, hipStream_t s) {
   if (a.npts == 0) return;
-  const size_t lds = sizeof(double) * (64 + 3) * (size_t)a.natoms;
+  const size_t lds = sizeof(double) * (128 + 3) * (size_t)a.natoms;
   hipLaunchKernelGGL(xc_weight_grad_kernel, dim3((a.npts + 63) / 64), dim3(64), lds, s, a, eg,
                      grad);
 }

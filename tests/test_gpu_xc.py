@@ -17,6 +17,9 @@ the CPU suite pins to closed forms and to the derivative identities.
   the SCF energy); the forces of the device's own B3LYP SCF; a group whose
   instances differ in their atoms is refused (the sparse chunks the gradient
   runs on need the same atoms).  bscf_build_jk ignores the setting.
+* Ring-polymer NVE at B3LYP (water, 4 beads): the ring-polymer Hamiltonian
+  stays within the second-order fluctuation of the integrator and does not
+  drift, so the forces are those of the energy the SCF converges.
 """
 
 import numpy as np
@@ -194,3 +197,34 @@ def test_b3lyp_forces_need_like_atoms_in_a_group(beadscf, b631gs):
             e.set_xc(2)
     finally:
         e.close()
+
+
+def test_b3lyp_nve_conserves_the_ring_polymer_hamiltonian(beadscf, sto3g):
+    AMU, KB, FS = 1822.888486209, 3.166811563e-6, 41.341373336
+    mass = {1: 1.008 * AMU, 8: 15.999 * AMU}
+    P, T, n = 4, 300.0, 16
+    z, x = inputs.workload("h2o_sto3g")["instances"][0]
+    xb = inputs.beads(z, x, P, 7)
+    m = np.array([mass[int(v)] for v in z])
+    p0 = inputs.maxwell_boltzmann(z, P, T, 7) * m[None, :, None]
+    e = beadscf.Engine(0)
+    try:
+        e.load_basis(sto3g)
+        e.set_instances([z] * P)
+        e.set_geometries(list(xb))
+        e.set_xc(beadscf.XC_B3LYP)
+        e.pimd_init(m, p0, beadscf.pimd_default_opts(dt=0.25 * FS, temperature=T, thermostat=0))
+        so = beadscf.default_opts(e_tol=1e-12, comm_tol=1e-10, guess=beadscf.GUESS_PREVIOUS)
+        H = []
+        for _ in range(n):
+            E, _, st = e.pimd_step(so)
+            assert (st == 0).all()
+            _, _, ke, sp, _ = e.pimd_state()
+            H.append(ke + sp + E.sum() / P)
+    finally:
+        e.close()
+    H = np.array(H)
+    ke0 = 1.5 * P * len(z) * KB * T
+    print("H fluctuation", np.ptp(H), "kinetic scale", ke0)
+    assert np.ptp(H) < 2.5e-3 * ke0
+    assert abs(H[-4:].mean() - H[:4].mean()) < 2.5e-3 * ke0
