@@ -552,7 +552,9 @@ struct bscf_ctx {
     DevBuf<double> Ps, Vs;
     DevBuf<double> V, exc;              // V_xc [mtot], E_xc [ninst]
     // gradient (xc.h): Y = D Ps per slot, the point factors, e per grid point
-    DevBuf<double> Yg, gf, eg, isep;
+    DevBuf<double> Yg, gf, eg;
+    DevBuf<double> isep;                // per instance [natoms][natoms] 1/|R_A - R_B|
+    std::vector<long long> isep_off;
   } xcs;
 
   // string of images over the batch's instances; positions on the device
@@ -1714,6 +1716,26 @@ void xc_grid(bscf_ctx* c) {
   x.d_npts.upload(x.npts_i, c->stream);
   x.d_sh_off.upload(c->shell_off, c->stream);
   x.d_nsh.upload(c->nshell, c->stream);
+  // the grid kernel keeps each point's atom distances in LDS
+  need(sizeof(double) * 64 * (size_t)c->max_atoms <= (size_t)c->max_lds_bytes, BSCF_E_UNSUPPORTED,
+       "B3LYP grid: too many atoms per instance for the LDS");
+  // 1/|R_A - R_B| of every instance's atom pairs (grid weights and their gradient)
+  x.isep_off.assign(c->ninst + 1, 0);
+  for (int i = 0; i < c->ninst; ++i)
+    x.isep_off[i + 1] = x.isep_off[i] + (long long)c->natoms[i] * c->natoms[i];
+  std::vector<double> isep(x.isep_off[c->ninst], 0.0);
+  for (int i = 0; i < c->ninst; ++i) {
+    const int na = c->natoms[i];
+    const double* X = &c->xyz[3 * (size_t)c->atom_off[i]];
+    for (int A = 0; A < na; ++A)
+      for (int B = 0; B < na; ++B)
+        if (A != B)
+          isep[x.isep_off[i] + (long long)A * na + B] =
+              1.0 / std::sqrt((X[3 * A] - X[3 * B]) * (X[3 * A] - X[3 * B]) +
+                              (X[3 * A + 1] - X[3 * B + 1]) * (X[3 * A + 1] - X[3 * B + 1]) +
+                              (X[3 * A + 2] - X[3 * B + 2]) * (X[3 * A + 2] - X[3 * B + 2]));
+  }
+  x.isep.upload(isep, c->stream);
   for (int i = 0; i < c->ninst; ++i) {
     XcGridArgs g;
     g.npts = (int)(x.pt_off[i + 1] - x.pt_off[i]);
@@ -1725,7 +1747,7 @@ void xc_grid(bscf_ctx* c) {
     g.ang_u = x.ang_u.p;
     g.ang_w = x.ang_w.p;
     g.pts = x.pts.p + 4 * x.pt_off[i];
-    g.inv_sep = nullptr;
+    g.inv_sep = x.isep.p + x.isep_off[i];
     launch_xc_grid(g, c->stream);
   }
   HIPCHK(hipGetLastError());
@@ -2009,22 +2031,6 @@ void xc_gradient(bscf_ctx* c, const double* P, double* grad) {
   }
   if (p1 >= 0) prof_end(c, p1, st);
   c->xc_launches[kXcGradOrb]++;
-  // 1/|R_A - R_B| of every instance's atom pairs
-  std::vector<long long> isoff(c->ninst + 1, 0);
-  for (int i = 0; i < c->ninst; ++i) isoff[i + 1] = isoff[i] + (long long)c->natoms[i] * c->natoms[i];
-  std::vector<double> isep(isoff[c->ninst], 0.0);
-  for (int i = 0; i < c->ninst; ++i) {
-    const int na = c->natoms[i];
-    const double* X = &c->xyz[3 * (size_t)c->atom_off[i]];
-    for (int A = 0; A < na; ++A)
-      for (int B = 0; B < na; ++B)
-        if (A != B)
-          isep[isoff[i] + (long long)A * na + B] =
-              1.0 / std::sqrt((X[3 * A] - X[3 * B]) * (X[3 * A] - X[3 * B]) +
-                              (X[3 * A + 1] - X[3 * B + 1]) * (X[3 * A + 1] - X[3 * B + 1]) +
-                              (X[3 * A + 2] - X[3 * B + 2]) * (X[3 * A + 2] - X[3 * B + 2]));
-  }
-  x.isep.upload(isep, st);
   const int p2 = c->profiling ? prof_begin(c, kXcGradWeight, 3, st) : -1;
   for (int i = 0; i < c->ninst; ++i) {
     XcGridArgs g;
@@ -2037,7 +2043,7 @@ void xc_gradient(bscf_ctx* c, const double* P, double* grad) {
     g.ang_u = x.ang_u.p;
     g.ang_w = x.ang_w.p;
     g.pts = nullptr;
-    g.inv_sep = x.isep.p + isoff[i];
+    g.inv_sep = x.isep.p + x.isep_off[i];
     launch_xc_weight_grad(g, x.eg.p + x.pt_off[i], grad + 3LL * c->atom_off[i], st);
   }
   if (p2 >= 0) prof_end(c, p2, st);

@@ -86,7 +86,11 @@ __device__ __forceinline__ Xc b3lyp(double rho, double sigma) {
 
 // ------------------------------------------------------------------- kernels
 
-__global__ void xc_grid_kernel(XcGridArgs a) {
+// one thread per point (blocks of 64); dynamic LDS: the point's distance to
+// every atom [natoms][64]
+__global__ __launch_bounds__(64) void xc_grid_kernel(XcGridArgs a) {
+  extern __shared__ double lds[];
+  double* Rc = lds;   // [C][64]
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.npts) return;
   const int A = p / kXcPerAtom, k = p - A * kXcPerAtom;
@@ -96,19 +100,19 @@ __global__ void xc_grid_kernel(XcGridArgs a) {
   const double x = a.xyz[3 * A] + r * a.ang_u[3 * j];
   const double y = a.xyz[3 * A + 1] + r * a.ang_u[3 * j + 1];
   const double z = a.xyz[3 * A + 2] + r * a.ang_u[3 * j + 2];
+  const int na = a.natoms;
+  for (int C = 0; C < na; ++C) {
+    const double dx = x - a.xyz[3 * C], dy = y - a.xyz[3 * C + 1], dz = z - a.xyz[3 * C + 2];
+    Rc[C * 64 + threadIdx.x] = sqrt(dx * dx + dy * dy + dz * dz);
+  }
   // Becke cell function of every atom at the point; the owner's share
   double own = 0.0, tot = 0.0;
-  for (int B = 0; B < a.natoms; ++B) {
-    const double dxB = x - a.xyz[3 * B], dyB = y - a.xyz[3 * B + 1], dzB = z - a.xyz[3 * B + 2];
-    const double rB = sqrt(dxB * dxB + dyB * dyB + dzB * dzB);
+  for (int B = 0; B < na; ++B) {
+    const double rB = Rc[B * 64 + threadIdx.x];
     double PB = 1.0;
-    for (int C = 0; C < a.natoms && PB > 0.0; ++C) {
+    for (int C = 0; C < na && PB > 0.0; ++C) {
       if (C == B) continue;
-      const double dxC = x - a.xyz[3 * C], dyC = y - a.xyz[3 * C + 1], dzC = z - a.xyz[3 * C + 2];
-      const double rC = sqrt(dxC * dxC + dyC * dyC + dzC * dzC);
-      const double ex = a.xyz[3 * B] - a.xyz[3 * C], ey = a.xyz[3 * B + 1] - a.xyz[3 * C + 1],
-                   ez = a.xyz[3 * B + 2] - a.xyz[3 * C + 2];
-      double mu = (rB - rC) / sqrt(ex * ex + ey * ey + ez * ez);
+      double mu = (rB - Rc[C * 64 + threadIdx.x]) * a.inv_sep[B * na + C];
       for (int it = 0; it < 3; ++it) mu = 1.5 * mu - 0.5 * mu * mu * mu;
       PB *= 0.5 * (1.0 - mu);
     }
@@ -714,7 +718,8 @@ __global__ void xc_functional_kernel(int n, const double* rho, const double* sig
 
 void launch_xc_grid(const XcGridArgs& a, hipStream_t s) {
   if (a.npts == 0) return;
-  hipLaunchKernelGGL(xc_grid_kernel, dim3((a.npts + 255) / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(xc_grid_kernel, dim3((a.npts + 63) / 64), dim3(64),
+                     sizeof(double) * 64 * (size_t)a.natoms, s, a);
 }
 
 void launch_xc_basis(const XcChunkArgs& a, int count, int max_nsh, hipStream_t s) {

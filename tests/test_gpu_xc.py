@@ -17,6 +17,9 @@ the CPU suite pins to closed forms and to the derivative identities.
   the SCF energy); the forces of the device's own B3LYP SCF; a group whose
   instances differ in their atoms is refused (the sparse chunks the gradient
   runs on need the same atoms).  bscf_build_jk ignores the setting.
+* At the MD workload's size ((H2O)8 in 6-31G*, two beads), where the
+  oracle's complex-step gradient is too slow: the B3LYP forces are minus
+  the central differences of the device's own converged B3LYP energies.
 * Ring-polymer NVE at B3LYP (water, 4 beads): the ring-polymer Hamiltonian
   stays within the second-order fluctuation of the integrator and does not
   drift, so the forces are those of the energy the SCF converges.
@@ -228,3 +231,35 @@ def test_b3lyp_nve_conserves_the_ring_polymer_hamiltonian(beadscf, sto3g):
     print("H fluctuation", np.ptp(H), "kinetic scale", ke0)
     assert np.ptp(H) < 2.5e-3 * ke0
     assert abs(H[-4:].mean() - H[:4].mean()) < 2.5e-3 * ke0
+
+
+def test_b3lyp_forces_are_the_energy_gradient_at_full_size(beadscf, b631gs):
+    w = inputs.workload("w8_beads", n_beads=2)
+    z = w["instances"][0][0]
+    xs = [x for _, x in w["instances"]]
+    e = _engine(beadscf, b631gs, w["instances"])
+    h = 1e-3
+    coords = [(0, 0, 0), (1, 4, 2), (0, 13, 1)]   # (bead, atom, axis)
+    try:
+        e.set_xc(beadscf.XC_B3LYP)
+        so = dict(e_tol=1e-11, comm_tol=1e-9)
+        E0, _, st = e.run_scf(**so)
+        assert np.all(st == 0)
+        F = e.forces()
+        fd = []
+        for b, at, ax in coords:
+            Es = []
+            for sgn in (1, -1):
+                xp = [x.copy() for x in xs]
+                xp[b][at, ax] += sgn * h
+                e.set_geometries(xp)
+                E, _, st = e.run_scf(**so)
+                assert np.all(st == 0)
+                Es.append(E[b])
+            fd.append(-(Es[0] - Es[1]) / (2 * h))
+    finally:
+        e.close()
+    for k in range(2):
+        assert np.abs(F[k].sum(axis=0)).max() < 1e-9
+    for (b, at, ax), f in zip(coords, fd):
+        assert abs(F[b][at, ax] - f) < 2e-6, (b, at, ax, F[b][at, ax], f)
