@@ -533,7 +533,7 @@ struct bscf_ctx {
     // sparse form, per group (xc.h): chunks of kXcSparseShells radial shells
     // of one atom and the basis shells each takes
     struct Chunk {
-      int p0, gcnt, sh0, nsh, f0, ns;
+      int p0, gcnt, sh0, nsh, f0, ns, sec;
     };
     // chunks of similar size share a launch, padded to W functions
     struct Bucket {
@@ -548,7 +548,9 @@ struct bscf_ctx {
     std::vector<GroupChunks> gch;
     std::vector<double> h_rad_r;        // [2][kXcRad] radial points (H, others)
     DevBuf<int> d_shl, d_scbf, d_fmap;  // the chunks' shell lists, compact offsets, function maps
-    DevBuf<int> d_meta;                 // [chunk][6] of every group's sorted chunks
+    DevBuf<int> d_meta;                 // [chunk][kXcMeta] of every group's sorted chunks
+    DevBuf<int> d_sec_ang;              // [kXcSectors][kXcSectorAng] angular nodes per sector
+    std::vector<double> h_ang_u;        // [kXcAng][3] directions (host copy)
     DevBuf<double> Ps, Vs;
     DevBuf<double> V, exc;              // V_xc [mtot], E_xc [ninst]
     // gradient (xc.h): Y = D Ps per slot, the point factors, e per grid point
@@ -1601,6 +1603,19 @@ void xc_tables(bscf_ctx* c) {
       aw[j] = wt[k] * 2 * M_PI / nphi;
     }
   x.h_rad_r = rr;
+  x.h_ang_u = au;
+  // sectors: cos(theta) >= 0 or < 0 (the first or last kXcTheta / 2 nodes,
+  // in decreasing cos(theta)) times sin(phi) >= 0 or < 0 (phi below or from pi)
+  std::vector<int> sec(kXcAng);
+  {
+    int fill[kXcSectors] = {};
+    for (int k = 0; k < kXcTheta; ++k)
+      for (int m = 0; m < nphi; ++m) {
+        const int sc = (k >= kXcTheta / 2 ? 2 : 0) + (m >= nphi / 2 ? 1 : 0);
+        sec[sc * kXcSectorAng + fill[sc]++] = k * nphi + m;
+      }
+  }
+  x.d_sec_ang.upload(sec, c->stream);
   x.rad_r.upload(rr, c->stream);
   x.rad_w.upload(rw, c->stream);
   x.ang_u.upload(au, c->stream);
@@ -1608,12 +1623,17 @@ void xc_tables(bscf_ctx* c) {
   x.tables = true;
 }
 
-// Sparse chunks of every group whose instances have the same atoms: per atom
-// and block of kXcSparseShells radial shells (points at distances r_lo..r_hi
-// from the atom), the basis shells whose values or gradients can exceed
-// kXcShellEps there in some instance of the group.  Bound at the shortest
-// distance d from the shell's centre to that spherical shell:
-// sum_k |c_k| exp(-a_k d^2) (d + 3)^l (1 + 2 a_k (d + 3)).
+// Sparse chunks of every group whose instances have the same atoms: per atom,
+// block of kXcSparseShells radial shells (points at distances r_lo..r_hi from
+// the atom) and angular sector, the basis shells whose values or gradients can
+// exceed kXcShellEps there in some instance of the group.  Bound at a lower
+// bound d of the distance from the shell's centre to the chunk's points:
+// sum_k |c_k| exp(-a_k d^2) (d + 3)^l (1 + 2 a_k (d + 3)).  With v the shell
+// centre relative to the atom, D = |v| and c >= the largest u . v / D over
+// the sector's directions u, every point r u of the chunk has |r u - v|^2 >=
+// r^2 - 2 r D c + D^2, least at r = clamp(D c, r_lo, r_hi).  A sector is the
+// convex cone s_z u_z >= 0, s_y u_y >= 0, so c = |(v_x, max(s_y v_y, 0),
+// max(s_z v_z, 0))| / D (the norm of v's projection onto the cone).
 void xc_chunks(bscf_ctx* c) {
   auto& x = c->xcs;
   x.gch.assign(c->groups.size(), {});
@@ -1630,10 +1650,36 @@ void xc_chunks(bscf_ctx* c) {
     if (!same) continue;
     G.sparse = true;
     const int nsh = c->nshell[i0];
+    // per shell the distance beyond which the bound stays below kXcShellEps:
+    // the bound, a sum of e^{-a d^2} times polynomials in d, decreases past
+    // its maxima (at d of a bohr or two), far before it reaches 1e-14, so the
+    // last point of a 0.05-bohr scan where it is still above, plus one step
+    std::vector<double> rcut(nsh, 0.0);
+    for (int s = 0; s < nsh; ++s) {
+      const Shell& sh = c->shells[c->shell_off[i0] + s];
+      auto bound = [&](double d) {
+        const double dp = d + 3.0;
+        double b = 0.0;
+        for (int k = 0; k < sh.nprim; ++k) {
+          const double al = c->sh_exp[sh.prim0 + k];
+          b += std::fabs(c->sh_coef[sh.prim0 + k]) * std::exp(-al * d * d) * (1.0 + 2.0 * al * dp);
+        }
+        return b * std::pow(dp, sh.l);
+      };
+      double last = -1.0;
+      for (double d = 0.0; d < 400.0; d += 0.05) {
+        const double b = bound(d);
+        if (b > kXcShellEps) last = d;
+        else if (last >= 0.0 && b < 1e-6 * kXcShellEps) break;
+      }
+      rcut[s] = last < 0.0 ? -1.0 : last + 0.05;
+    }
     for (int a = 0; a < na; ++a) {
       const int tab = c->Zs[c->atom_off[i0] + a] == 1 ? 0 : 1;
-      for (int r0 = 0; r0 < kXcRad; r0 += kXcSparseShells) {
+      for (int r0 = 0; r0 < kXcRad; r0 += kXcSparseShells)
+      for (int sc = 0; sc < kXcSectors; ++sc) {
         const int r1 = std::min(kXcRad, r0 + kXcSparseShells);
+        const double sy = (sc & 1) ? -1.0 : 1.0, sz = (sc & 2) ? -1.0 : 1.0;
         double rlo = 1e300, rhi = 0.0;
         for (int r = r0; r < r1; ++r) {
           rlo = std::min(rlo, x.h_rad_r[tab * kXcRad + r]);
@@ -1641,26 +1687,26 @@ void xc_chunks(bscf_ctx* c) {
         }
         bscf_ctx::Xcs::Chunk ch;
         ch.p0 = a * kXcPerAtom + r0 * kXcAng;
-        ch.gcnt = (r1 - r0) * kXcAng;
+        ch.gcnt = (r1 - r0) * kXcSectorAng;
         ch.sh0 = (int)shl.size();
         ch.f0 = (int)fmap.size();
+        ch.sec = sc;
         int nf = 0;
         for (int s = 0; s < nsh; ++s) {
           bool keep = false;
           for (int i = i0; i < gr.first + gr.count && !keep; ++i) {
             const Shell& sh = c->shells[c->shell_off[i] + s];
             const double* A = &c->xyz[3 * (size_t)(c->atom_off[i] + a)];
-            const double d = std::sqrt((sh.x - A[0]) * (sh.x - A[0]) + (sh.y - A[1]) * (sh.y - A[1]) +
-                                       (sh.z - A[2]) * (sh.z - A[2]));
-            const double dm = std::max(0.0, std::max(d - rhi, rlo - d)), dp = dm + 3.0;
-            double b = 0.0;
-            for (int k = 0; k < sh.nprim; ++k) {
-              const double al = c->sh_exp[sh.prim0 + k];
-              b += std::fabs(c->sh_coef[sh.prim0 + k]) * std::exp(-al * dm * dm) *
-                   (1.0 + 2.0 * al * dp);
+            const double vx = sh.x - A[0], vy = sh.y - A[1], vz = sh.z - A[2];
+            const double d = std::sqrt(vx * vx + vy * vy + vz * vz);
+            double dm = rlo;   // the shell sits on the atom
+            if (d > 0.0) {
+              const double py = std::max(sy * vy, 0.0), pz = std::max(sz * vz, 0.0);
+              const double cmax = std::min(1.0, std::sqrt(vx * vx + py * py + pz * pz) / d);
+              const double rs = std::min(rhi, std::max(rlo, d * cmax));
+              dm = std::sqrt(std::max(0.0, rs * rs - 2.0 * rs * d * cmax + d * d));
             }
-            b *= std::pow(dp, sh.l);
-            keep = b > kXcShellEps;
+            keep = dm <= rcut[s];
           }
           if (!keep) continue;
           const Shell& sh = c->shells[c->shell_off[i0] + s];
@@ -1674,8 +1720,9 @@ void xc_chunks(bscf_ctx* c) {
         if (nf > 0) G.chunks.push_back(ch);
       }
     }
-    // largest first; a bucket takes the chunks down to 70% of its first one's
-    // width (padded to a multiple of 16)
+    // largest first; a bucket takes the chunks whose width padded to a
+    // multiple of 16 is at least 70% of its first one's (so the narrowest
+    // chunks, all padded to 16, share one bucket)
     std::stable_sort(G.chunks.begin(), G.chunks.end(),
                      [](const bscf_ctx::Xcs::Chunk& p, const bscf_ctx::Xcs::Chunk& q) { return p.ns > q.ns; });
     for (int k = 0; k < (int)G.chunks.size();) {
@@ -1686,13 +1733,13 @@ void xc_chunks(bscf_ctx* c) {
       do {   // the first chunk always, then those down to 70% of the width
         b.max_nsh = std::max(b.max_nsh, G.chunks[k].nsh);
         ++k;
-      } while (k < (int)G.chunks.size() && G.chunks[k].ns * 10 >= b.W * 7);
+      } while (k < (int)G.chunks.size() && (G.chunks[k].ns + 15) / 16 * 16 * 10 >= b.W * 7);
       b.nch = k - b.c0;
       G.buckets.push_back(b);
     }
-    G.meta0 = (int)meta.size() / 6;
+    G.meta0 = (int)meta.size() / kXcMeta;
     for (const auto& ch : G.chunks)
-      for (int v : {ch.p0, ch.gcnt, ch.sh0, ch.nsh, ch.f0, ch.ns}) meta.push_back(v);
+      for (int v : {ch.p0, ch.gcnt, ch.sh0, ch.nsh, ch.f0, ch.ns, ch.sec}) meta.push_back(v);
   }
   x.d_meta.upload(meta, c->stream);
   x.d_shl.upload(shl, c->stream);
@@ -1798,6 +1845,7 @@ void xc_build(bscf_ctx* c, const double* P, bool masked) {
         a.first = r0;
         a.n = n;
         a.sh_list = x.d_shl.p;
+        a.sec_ang = x.d_sec_ang.p;
         a.sh_cbf = x.d_scbf.p;
         a.fmap = x.d_fmap.p;
         a.sh_off = x.d_sh_off.p;
@@ -1820,10 +1868,10 @@ void xc_build(bscf_ctx* c, const double* P, bool masked) {
             x.Z.resize((size_t)slots * W * G);
             x.Ps.resize((size_t)slots * W * W);
             x.Vs.resize((size_t)slots * W * W);
-            x.part.resize((size_t)slots * (G / 256));
+            x.part.resize((size_t)slots * (G / kXcSB));
             a.W = W;
             a.nch = nch;
-            a.meta = x.d_meta.p + 6 * (GC.meta0 + bk.c0 + c0);
+            a.meta = x.d_meta.p + kXcMeta * (GC.meta0 + bk.c0 + c0);
             a.B = x.B.p;
             a.Z = x.Z.p;
             a.Ps = x.Ps.p;
@@ -1984,6 +2032,7 @@ void xc_gradient(bscf_ctx* c, const double* P, double* grad) {
     a.first = gr.first;
     a.n = n;
     a.sh_list = x.d_shl.p;
+    a.sec_ang = x.d_sec_ang.p;
     a.sh_cbf = x.d_scbf.p;
     a.fmap = x.d_fmap.p;
     a.sh_off = x.d_sh_off.p;
@@ -2007,7 +2056,7 @@ void xc_gradient(bscf_ctx* c, const double* P, double* grad) {
         x.gf.resize((size_t)slots * 5 * G);
         a.W = W;
         a.nch = nch;
-        a.meta = x.d_meta.p + 6 * (GC.meta0 + bk.c0 + c0);
+        a.meta = x.d_meta.p + kXcMeta * (GC.meta0 + bk.c0 + c0);
         a.B = x.B.p;
         a.Z = x.Z.p;
         a.Ps = x.Ps.p;

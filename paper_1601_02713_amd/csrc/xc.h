@@ -62,27 +62,36 @@ struct XcChunkArgs {
 };
 
 // Sparse form (instances of one group with the same atoms, e.g. beads): the
-// grid is cut into chunks of kXcSparseShells radial shells of one atom, and a
-// chunk takes only the basis shells whose values (or gradients) can exceed
+// grid is cut into chunks of kXcSparseShells radial shells of one atom times
+// one of kXcSectors angular sectors (cos(theta) >= 0 or < 0 times
+// sin(phi) >= 0 or < 0: 6 x 12 of the 12 x 24 product nodes), and a chunk
+// takes only the basis shells whose values (or gradients) can exceed
 // kXcShellEps somewhere on it (a distance bound, union over the group's
 // instances), numbered compactly: B, Z [count][ns][G], P and V through the
-// compact-to-local function map.
+// compact-to-local function map.  The sparse kernels run blocks of kXcSB
+// threads (G is a multiple of it).
 constexpr int kXcSparseShells = 8;
-constexpr int kXcSparseG = kXcSparseShells * kXcAng;   // 2304 points, 9 x 256
+constexpr int kXcSectors = 4;
+constexpr int kXcSectorAng = kXcAng / kXcSectors;               // 72
+constexpr int kXcSparseG = kXcSparseShells * kXcSectorAng;      // 576 points, 9 x 64
+constexpr int kXcSB = 64;
 constexpr double kXcShellEps = 1e-14;
 
 // One launch covers nch chunks of a bucket (chunks of similar size, padded to
 // W compact functions) times the count instances of a run: slot z =
-// chunk * count + instance.  Per chunk (chunk metadata, 6 ints): first point,
+// chunk * count + instance.  Per chunk (chunk metadata, kXcMeta ints): first
+// point of its radial block (atom * kXcPerAtom + first shell * kXcAng),
 // points, first entry and length of its shell list, first entry and length of
-// its function map.
+// its function map, sector.  Point g of a chunk is radial row g / kXcSectorAng
+// of the block at angular node sec_ang[sector][g % kXcSectorAng].
 struct XcSparseArgs {
-  int G;                    // points per chunk slot (multiple of 256)
+  int G;                    // points per chunk slot (multiple of kXcSB)
   int W;                    // padded compact functions per slot
   int nch, count;           // chunks and instances of the launch
   int first;                // first instance of the run
   int n;                    // basis functions per instance
-  const int* meta;          // [nch][6]: p0, gcnt, sh0, nsh, f0, ns
+  const int* meta;          // [nch][kXcMeta]: p0, gcnt, sh0, nsh, f0, ns, sector
+  const int* sec_ang;       // [kXcSectors][kXcSectorAng] angular nodes of each sector
   const int* sh_list;       // shells (local to the instance) of all chunks
   const int* sh_cbf;        // first compact function of each listed shell
   const int* fmap;          // local function of each compact one, all chunks
@@ -99,8 +108,9 @@ struct XcSparseArgs {
   double* Ps;               // [slot][W][W] compact density (column-major, zero padded)
   double* Vs;               // [slot][W][W] X^T B
   double* V;                // V_xc (column-major per instance, + V^T at the end)
-  double* part;             // [slot][G / 256] partial sums of w e
+  double* part;             // [slot][G / kXcSB] partial sums of w e
 };
+constexpr int kXcMeta = 7;
 
 // max_nsh: the longest shell list of the launch's chunks
 void launch_xc_sparse_basis(const XcSparseArgs& a, int max_nsh, hipStream_t s);

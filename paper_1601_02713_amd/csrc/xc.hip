@@ -338,16 +338,21 @@ __global__ void xc_slice_sum_kernel(int n, int S, const double* Vp, double* V, i
 // ---------------------------------------------------------- sparse form
 
 struct ChunkMeta {
-  int p0, gcnt, sh0, nsh, f0, ns;
+  int p0, gcnt, sh0, nsh, f0, ns, sec;
 };
 __device__ __forceinline__ ChunkMeta chunk_meta(const int* m, int c) {
-  const int* q = m + 6 * c;
-  return {q[0], q[1], q[2], q[3], q[4], q[5]};
+  const int* q = m + kXcMeta * c;
+  return {q[0], q[1], q[2], q[3], q[4], q[5], q[6]};
+}
+// grid point (within the instance) of point g of the chunk
+__device__ __forceinline__ int chunk_point(const XcSparseArgs& a, const ChunkMeta& m, int g) {
+  const int row = g / kXcSectorAng;
+  return m.p0 + row * kXcAng + a.sec_ang[m.sec * kXcSectorAng + (g - row * kXcSectorAng)];
 }
 
-// grid (G / 256, max_nsh + 1, slots): y < nsh a shell of the chunk, the last
-// y the zero padding rows [ns, W)
-__global__ __launch_bounds__(256) void xc_sparse_basis_kernel(XcSparseArgs a) {
+// grid (G / kXcSB, max_nsh + 1, slots): y < nsh a shell of the chunk, the
+// last y the zero padding rows [ns, W)
+__global__ __launch_bounds__(kXcSB) void xc_sparse_basis_kernel(XcSparseArgs a) {
   const int gl = blockIdx.x * blockDim.x + threadIdx.x;
   const int slot = blockIdx.z, c = slot / a.count, zi = slot - c * a.count, inst = a.first + zi;
   const ChunkMeta m = chunk_meta(a.meta, c);
@@ -365,7 +370,7 @@ __global__ __launch_bounds__(256) void xc_sparse_basis_kernel(XcSparseArgs a) {
     for (int k = 0; k < nc; ++k) Bc[(size_t)k * a.G] = 0.0;
     return;
   }
-  const double* pt = a.pts + 4 * (a.pt_off[inst] + m.p0 + gl);
+  const double* pt = a.pts + 4 * (a.pt_off[inst] + chunk_point(a, m, gl));
   shell_eval<false>(sh, a.sh_exp, a.sh_coef, pt[0] - sh.x, pt[1] - sh.y, pt[2] - sh.z,
                     [&](int k, double v, double, double, double) { Bc[(size_t)k * a.G] = v; });
 }
@@ -385,14 +390,14 @@ __global__ void xc_sparse_gather_kernel(XcSparseArgs a) {
 }
 
 // as xc_point_kernel over the chunk's shells
-__global__ __launch_bounds__(256) void xc_sparse_point_kernel(XcSparseArgs a) {
-  __shared__ double red[256];
+__global__ __launch_bounds__(kXcSB) void xc_sparse_point_kernel(XcSparseArgs a) {
+  __shared__ double red[kXcSB];
   const int gl = blockIdx.x * blockDim.x + threadIdx.x;
   const int slot = blockIdx.y, c = slot / a.count, zi = slot - c * a.count, inst = a.first + zi;
   const ChunkMeta m = chunk_meta(a.meta, c);
   double ew = 0.0;
   if (gl < m.gcnt) {
-    const double* pt = a.pts + 4 * (a.pt_off[inst] + m.p0 + gl);
+    const double* pt = a.pts + 4 * (a.pt_off[inst] + chunk_point(a, m, gl));
     const double x = pt[0], y = pt[1], z = pt[2], w = pt[3];
     double* Zc = a.Z + (size_t)slot * a.W * a.G + gl;
     const Shell* sh0 = a.shells + a.sh_off[inst];
@@ -432,11 +437,11 @@ __global__ __launch_bounds__(256) void xc_sparse_point_kernel(XcSparseArgs a) {
   }
   red[threadIdx.x] = ew;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
+  for (int st = kXcSB / 2; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) a.part[(size_t)slot * (a.G / 256) + blockIdx.x] = red[0];
+  if (threadIdx.x == 0) a.part[(size_t)slot * (a.G / kXcSB) + blockIdx.x] = red[0];
 }
 
 // V(fmap[i], fmap[j]) += Vs(i, j), column-major; the chunks of one instance
@@ -456,7 +461,7 @@ __global__ void xc_sparse_scatter_kernel(XcSparseArgs a) {
 // one block per instance: its partial sums over the launch's chunks, in order
 __global__ __launch_bounds__(256) void xc_sparse_reduce_kernel(XcSparseArgs a, double* exc) {
   __shared__ double red[256];
-  const int nb = a.G / 256, zi = blockIdx.x;
+  const int nb = a.G / kXcSB, zi = blockIdx.x;
   double s = 0.0;
   for (int k = threadIdx.x; k < a.nch * nb; k += 256) {
     const int c = k / nb, b = k - c * nb;
@@ -475,7 +480,7 @@ __global__ __launch_bounds__(256) void xc_sparse_reduce_kernel(XcSparseArgs a, d
 
 // as xc_sparse_point_kernel up to the functional; then D over B, the point
 // factors and the energy density (xc.h)
-__global__ __launch_bounds__(256) void xc_sparse_gpoint_kernel(XcSparseArgs a, double* gf,
+__global__ __launch_bounds__(kXcSB) void xc_sparse_gpoint_kernel(XcSparseArgs a, double* gf,
                                                                double* eg) {
   const int gl = blockIdx.x * blockDim.x + threadIdx.x;
   const int slot = blockIdx.y, c = slot / a.count, zi = slot - c * a.count, inst = a.first + zi;
@@ -485,7 +490,7 @@ __global__ __launch_bounds__(256) void xc_sparse_gpoint_kernel(XcSparseArgs a, d
     for (int k = 0; k < 5; ++k) f[(size_t)k * a.G] = 0.0;
     return;
   }
-  const long long gp = a.pt_off[inst] + m.p0 + gl;
+  const long long gp = a.pt_off[inst] + chunk_point(a, m, gl);
   const double* pt = a.pts + 4 * gp;
   const double x = pt[0], y = pt[1], z = pt[2], w = pt[3];
   const double* Zc = a.Z + (size_t)slot * a.W * a.G + gl;
@@ -530,11 +535,12 @@ __global__ __launch_bounds__(256) void xc_sparse_gpoint_kernel(XcSparseArgs a, d
   }
 }
 
-// grid (G / 256, max_nsh, slots): y a shell of the chunk
-__global__ __launch_bounds__(256) void xc_sparse_force_kernel(XcSparseArgs a, const double* gf,
-                                                              const double* Y,
-                                                              const int* atom_off, double* grad) {
-  __shared__ double red[3][256];
+// grid (G / kXcSB, max_nsh, slots): y a shell of the chunk
+__global__ __launch_bounds__(kXcSB) void xc_sparse_force_kernel(XcSparseArgs a, const double* gf,
+                                                                const double* Y,
+                                                                const int* atom_off,
+                                                                double* grad) {
+  __shared__ double red[3][kXcSB];
   const int gl = blockIdx.x * blockDim.x + threadIdx.x;
   const int slot = blockIdx.z, c = slot / a.count, zi = slot - c * a.count, inst = a.first + zi;
   const ChunkMeta m = chunk_meta(a.meta, c);
@@ -549,7 +555,7 @@ __global__ __launch_bounds__(256) void xc_sparse_force_kernel(XcSparseArgs a, co
     const double cr = f[0], cs = f[(size_t)a.G];
     if (cr != 0.0 || cs != 0.0) {
       const double g[3] = {f[(size_t)2 * a.G], f[(size_t)3 * a.G], f[(size_t)4 * a.G]};
-      const double* pt = a.pts + 4 * (a.pt_off[inst] + m.p0 + gl);
+      const double* pt = a.pts + 4 * (a.pt_off[inst] + chunk_point(a, m, gl));
       const size_t o = (size_t)slot * a.W * a.G + (size_t)a.sh_cbf[j] * a.G + gl;
       const double* zf = a.Z + o;
       const double* yf = Y + o;
@@ -566,7 +572,7 @@ __global__ __launch_bounds__(256) void xc_sparse_force_kernel(XcSparseArgs a, co
   }
   for (int i = 0; i < 3; ++i) red[i][threadIdx.x] = t[i];
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
+  for (int st = kXcSB / 2; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st)
       for (int i = 0; i < 3; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + st];
     __syncthreads();
@@ -753,7 +759,7 @@ void launch_xc_symmetrize(int n, int count, double* V, hipStream_t s) {
 void launch_xc_sparse_basis(const XcSparseArgs& a, int max_nsh, hipStream_t s) {
   const int slots = a.nch * a.count;
   if (slots == 0) return;
-  hipLaunchKernelGGL(xc_sparse_basis_kernel, dim3(a.G / 256, max_nsh + 1, slots), dim3(256), 0, s,
+  hipLaunchKernelGGL(xc_sparse_basis_kernel, dim3(a.G / kXcSB, max_nsh + 1, slots), dim3(kXcSB), 0, s,
                      a);
 }
 
@@ -768,7 +774,7 @@ void launch_xc_sparse_gather(const XcSparseArgs& a, hipStream_t s) {
 void launch_xc_sparse_point(const XcSparseArgs& a, hipStream_t s) {
   const int slots = a.nch * a.count;
   if (slots == 0) return;
-  hipLaunchKernelGGL(xc_sparse_point_kernel, dim3(a.G / 256, slots), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(xc_sparse_point_kernel, dim3(a.G / kXcSB, slots), dim3(kXcSB), 0, s, a);
 }
 
 void launch_xc_sparse_scatter(const XcSparseArgs& a, hipStream_t s) {
@@ -786,15 +792,15 @@ void launch_xc_sparse_reduce(const XcSparseArgs& a, double* exc, hipStream_t s) 
 
 void launch_xc_sparse_gpoint(const XcSparseArgs& a, double* gf, double* eg, hipStream_t s) {
   if (a.nch * a.count == 0) return;
-  hipLaunchKernelGGL(xc_sparse_gpoint_kernel, dim3(a.G / 256, a.nch * a.count), dim3(256), 0, s,
+  hipLaunchKernelGGL(xc_sparse_gpoint_kernel, dim3(a.G / kXcSB, a.nch * a.count), dim3(kXcSB), 0, s,
                      a, gf, eg);
 }
 
 void launch_xc_sparse_force(const XcSparseArgs& a, int max_nsh, const double* gf,
                             const double* Y, const int* atom_off, double* grad, hipStream_t s) {
   if (a.nch * a.count == 0 || max_nsh == 0) return;
-  hipLaunchKernelGGL(xc_sparse_force_kernel, dim3(a.G / 256, max_nsh, a.nch * a.count),
-                     dim3(256), 0, s, a, gf, Y, atom_off, grad);
+  hipLaunchKernelGGL(xc_sparse_force_kernel, dim3(a.G / kXcSB, max_nsh, a.nch * a.count),
+                     dim3(kXcSB), 0, s, a, gf, Y, atom_off, grad);
 }
 
 void launch_xc_weight_grad(const XcGridArgs& a, const double* eg, double* grad, hipStream_t s) {

@@ -10,7 +10,7 @@ oracle/string_method.py (the simplified string method in code of its own).
   mirror that exchanges reactant and product, so the energy profile of the
   evolving string stays symmetric while the interior relaxes; the images stay
   equally spaced in arc length.  Images need different SCF iteration counts,
-  which the batch absorbs.
+  which the batch absorbs.  The same at B3LYP (its forces and grid).
 * Refusals: one image, images of different systems, an update before init.
 """
 
@@ -95,11 +95,14 @@ def test_scf_driven_iterations_match_oracle(beadscf, sto3g):
     assert np.abs(xg - x).max() < 1e-8
 
 
-def test_symmetric_proton_transfer_path(beadscf, b631gs):
+@pytest.mark.parametrize("xc", ["hf", "b3lyp"])
+def test_symmetric_proton_transfer_path(beadscf, b631gs, xc):
     n = 9
     z, x0 = inputs.zundel_path(n)
     e = _engine(beadscf, b631gs, z, x0)
     try:
+        if xc == "b3lyp":   # the grid is symmetric under the mirror x -> R - x too
+            e.set_xc(beadscf.XC_B3LYP)
         e.string_init(step=0.5, fix_ends=1)
         so = beadscf.default_opts(e_tol=1e-10, comm_tol=1e-8, guess=beadscf.GUESS_PREVIOUS)
         E0 = None
