@@ -8,7 +8,8 @@ the CPU suite pins to closed forms and to the derivative identities.
 * V_xc and E_xc of a ragged batch (H2, three water beads batched together,
   the water dimer; 4 to 38 functions, 34560 to 103680 grid points) at the
   oracle's core-guess density, in the sparse form (per chunk of radial
-  shells only the basis shells that matter there) and in the dense form,
+  shells and angular sector only the basis shells that matter there) and in
+  the dense form,
   with whole-instance chunks and with chunks of 9984 points (several per
   instance, the last one ragged).
 * Kohn-Sham F and E of one build, and converged B3LYP SCF energies.
@@ -84,8 +85,8 @@ def test_functional_matches_oracle(beadscf, b631gs):
 @pytest.mark.parametrize("form", ["sparse", "dense", "dense-chunked"])
 def test_vxc_and_exc_match_oracle(beadscf, b631gs, form, monkeypatch):
     """Three water beads form one batched run.  Sparse: chunks of 8 radial
-    shells of one atom, each with the basis shells that matter there (the
-    default for instances with the same atoms).  Dense: every point takes
+    shells of one atom times an angular sector, each with the basis shells
+    that matter there (the default for instances with the same atoms).  Dense: every point takes
     every function; with a chunk width of 9984 points every instance takes
     several chunks and ends in a ragged one."""
     if form != "sparse":
