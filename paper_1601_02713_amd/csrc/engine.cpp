@@ -77,8 +77,15 @@ int lane_scratch_bound() {
 
 // Incremental Fock builds: a full build at the first SCF iteration and every
 // kFullEvery iterations, which bounds the accumulated effect of the skipped
-// quartets.
+// quartets.  Their sum (each below the cutoff, over millions of quartets in
+// a large instance) also puts a floor under the commutator error, near 1e-8
+// for 608 functions: once an instance within kStallNear times comm_tol has
+// not brought its error below kStallRatio of its value two iterations back
+// (at least two iterations after a full build), the rest of the SCF call
+// builds in full.
 constexpr int kFullEvery = 12;
+constexpr double kStallNear = 100.0;
+constexpr double kStallRatio = 0.8;
 
 // SP2 purification: at most kSp2MaxSteps projection steps per density; a
 // replica's projector counts as converged once the idempotency error
@@ -479,6 +486,7 @@ struct bscf_ctx {
   // [ninst] SP2 first converged steps; packed on the device, then one copy
   DevBuf<int> d_pin;
   PinBuf<int> h_pin;
+  PinBuf<double> h_emax;   // the commutator errors of the last iteration
   DevBuf<double> d_wmin;    // smallest overlap eigenvalue per instance
   PinBuf<double> h_wmin;
   // captured density halves of an SCF iteration, by (SP2 steps, e_tol,
@@ -2565,6 +2573,7 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->d_wmin.resize(n_inst);
     c->h_wmin.resize(n_inst);
     c->h_pin.resize((size_t)2 * n_inst);
+    c->h_emax.resize(n_inst);
     c->d_omask.resize(n_inst);
     c->diisC.resize((size_t)n_inst * 8);
     c->diis_count.resize(n_inst);
@@ -2981,8 +2990,14 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     d.coef = c->diisC.p;
     BatchInfo bm = c->batch(true);
     int it = 0;
+    int since_full = 0;          // incremental builds since the last full one
+    bool stalled = false;        // full builds from here on
+    std::vector<double> err_hist[3];
+    for (auto& h : err_hist) h.assign(ni, 0.0);
     for (; it < o.max_iter; ++it) {
-      fock_build(c, o.schwarz_tol, o.precision, true, o.incremental && it % kFullEvery != 0);
+      const bool full = it == 0 || since_full + 1 >= kFullEvery || stalled;
+      fock_build(c, o.schwarz_tol, o.precision, true, o.incremental && !full);
+      since_full = full ? 0 : since_full + 1;
       // the rest of the iteration goes out before the host knows which
       // replicas this iteration finishes (density_half); one synchronisation
       // per iteration then reads the active flags and whether every SP2
@@ -2992,7 +3007,27 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
       else density_half(c, o, d, bm, k);
       HIPCHK(hipMemcpyAsync(c->h_pin.p, c->d_pin.p, (k >= 0 ? 2 : 1) * ni * sizeof(int),
                             hipMemcpyDeviceToHost, st));
+      if (o.incremental)
+        HIPCHK(hipMemcpyAsync(c->h_emax.p, c->d_emax.p, ni * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
       sync(c);
+      if (o.incremental) {
+        std::swap(err_hist[0], err_hist[1]);
+        std::swap(err_hist[1], err_hist[2]);
+        for (int i = 0; i < ni && !stalled; ++i) {
+          // instances active in this iteration and not finished by it (the
+          // others' errors are stale or no longer matter)
+          if (!(flags[i] && c->h_pin.p[i])) {
+            err_hist[2][i] = 0.0;
+            continue;
+          }
+          const double e = c->h_emax.p[i];
+          err_hist[2][i] = e;
+          if (it >= 2 && since_full >= 2 && e < kStallNear * o.comm_tol &&
+              e >= kStallRatio * err_hist[0][i] && err_hist[0][i] > 0.0)
+            stalled = true;
+        }
+      }
       std::copy(c->h_pin.p, c->h_pin.p + ni, flags.begin());
       c->scf_iters++;
       c->h_active = flags;
