@@ -171,6 +171,15 @@ def fock_summary(st, mixed, workload):
             "fp32_quartet_share": v["done_quartets_fp32"] / max(v["done_quartets"], 1),
             "grad_kernel": "lane" if v["variant"][2] == 0 else "coop",
             "grad_ms_per_launch": v["grad_ms"] / max(v["grad_launches"], 1),
+            # the gradient's algorithmic FLOPs (setup, Boys to L + 1, raised and
+            # lowered VRR per evaluated primitive quartet, contraction per
+            # evaluated quartet, counted on the device) per forces call, and
+            # their rate in the concurrent schedule and alone
+            "grad_flops_per_call": v["grad_flops"] / max(v["grad_launches"], 1),
+            "grad_tflops": v["grad_flops"] / (v["grad_ms"] * 1e-3) / 1e12 if v["grad_ms"] else None,
+            "grad_alone_tflops": (v["grad_flops"] / max(v["grad_launches"], 1)
+                                  / (v["tune_ms"][2 + v["variant"][2]] * 1e-3) / 1e12
+                                  if v["tune_ms"][2 + v["variant"][2]] else None),
             # the autotuner's timing of the chosen kernels, each alone on the GPU
             "alone_ms": (v["tune_ms_mixed"][v["variant"][1]] if mixed else v["tune_ms"][v["variant"][0]]),
             "grad_alone_ms": v["tune_ms"][2 + v["variant"][2]]}

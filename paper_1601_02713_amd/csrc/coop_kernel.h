@@ -401,6 +401,16 @@ __global__ __launch_bounds__(CP::NTQ) void coop_grad_kernel(GradArgs a) {
     np = max(np, qnp[q]);
     any |= qv[q];
   }
+  if (a.gstat && tid == 0 && any) {
+    double nq = 0.0, npq = 0.0;
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      nq += qv[q];
+      npq += qnp[q];
+    }
+    atomicAdd(&a.gstat[0], nq);
+    atomicAdd(&a.gstat[1], npq);
+  }
   if (!any) return;
   // density factors of every quartet (zero for an empty one)
   for (int e = tid; e < QB * NOUT; e += NT) {

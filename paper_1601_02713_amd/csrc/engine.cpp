@@ -410,6 +410,7 @@ struct bscf_ctx {
     std::vector<double> inst_quart, inst_primq;  // per instance
     // evaluated so far (active instances only) and measured kernel time
     double done_quart = 0, done_primq = 0, kernel_ms = 0, grad_ms = 0;
+    double grad_quart = 0, grad_primq = 0;   // evaluated by the gradient (device counts)
     // Schwarz-screened quartets (at the build's cutoff) of the instances each
     // build covered, whether a full or an incremental build evaluated them
     double screened_quart = 0;
@@ -464,6 +465,7 @@ struct bscf_ctx {
   DevBuf<double> Cprev, Cext, Mpol;
   DevBuf<int> d_cfirst, d_c2ok;
   std::vector<int> h_ccount;
+  DevBuf<double> d_gstat;   // [class][2] gradient work of one forces call
   DevBuf<double> Pprev, dP, d_dpmax;   // incremental builds: last build's P, its change, max |dP|
   // work kept by incremental builds, [quartets, primitive quartets, FP32
   // quartets][class][instance], accumulated on the device until read
@@ -3170,6 +3172,9 @@ void forces_impl(bscf_ctx* c, double* Fout, bool with_xc = false) {
     ga.nsh = c->d_nshell.p;
     ga.tau = c->work_tau;
     ga.kx = with_xc ? kXcA0 : 1.0;
+    c->d_gstat.resize((size_t)2 * kNumQuartetClasses);
+    launch_fill(c->d_gstat.p, 2LL * kNumQuartetClasses, 0.0, st);
+    ga.gstat = nullptr;
     launch_shell_pmax(c->ninst, c->max_nshell, c->d_shell_off.p, c->d_nshell.p, c->d_pm_off.p,
                       c->d_shells.p, c->d_moff.p, c->d_nbf.p, c->P.p, c->d_pmax.p, st);
     launch_gather_pk(ketpos_args(c), c->max_ncd, c->P.p, c->d_Pk.p, st);
@@ -3197,6 +3202,7 @@ void forces_impl(bscf_ctx* c, double* Fout, bool with_xc = false) {
            "gradient timing buffer smaller than the batch");
       GradArgs gt = ga;
       gt.grad = c->d_grad_tune.p;
+      gt.gstat = nullptr;
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
@@ -3295,8 +3301,10 @@ void forces_impl(bscf_ctx* c, double* Fout, bool with_xc = false) {
         set_gclass(ga, W);
         const int pk = c->profiling ? prof_begin(c, j.q, 1, s) : -1;
         ga.unit_threads = c->grad_unit_threads[j.q] ? c->grad_unit_threads[j.q] : 64;
+        ga.gstat = c->d_gstat.p + 2 * j.q;
         if (c->grad_variant[j.q]) qc[j.q].coop_grad(ga, s);
         else qc[j.q].grad(ga, s);
+        ga.gstat = nullptr;
         if (pk >= 0) prof_end(c, pk, s);
         W.grad_launches++;
       } else {
@@ -3312,9 +3320,15 @@ void forces_impl(bscf_ctx* c, double* Fout, bool with_xc = false) {
     }
     HIPCHK(hipGetLastError());
     if (with_xc) xc_gradient(c, c->P.p, c->d_grad.p);
-    std::vector<double> g(3 * c->total_atoms);
+    std::vector<double> g(3 * c->total_atoms), gs(2 * kNumQuartetClasses);
     HIPCHK(hipMemcpyAsync(g.data(), c->d_grad.p, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(gs.data(), c->d_gstat.p, gs.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          st));
     sync(c);
+    for (int q = 0; q < kNumQuartetClasses; ++q) {
+      c->work[q].grad_quart += gs[2 * q];
+      c->work[q].grad_primq += gs[2 * q + 1];
+    }
     for (size_t k = 0; k < g.size(); ++k) Fout[k] = -g[k];
     if (c->md.on && c->md.synced) c->md.have_force = true;
     c->t_grad_ms += now_ms() - t0;
@@ -3878,6 +3892,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
     collect_kept(c);
     for (auto& W : c->work) {
       W.done_quart = W.done_primq = W.kernel_ms = W.grad_ms = W.done_quart32 = 0;
+      W.grad_quart = W.grad_primq = 0;
       W.screened_quart = 0;
       W.launches = W.grad_launches = 0;
     }
@@ -3936,6 +3951,9 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
         << ", \"prim_flops\": " << qc[q].prim_flops << ", \"hrr_flops\": " << qc[q].hrr_flops
         << ", \"kernel_ms\": " << W.kernel_ms << ", \"launches\": " << W.launches
         << ", \"grad_ms\": " << W.grad_ms << ", \"grad_launches\": " << W.grad_launches
+        << ", \"grad_quartets\": " << W.grad_quart << ", \"grad_prim_quartets\": " << W.grad_primq
+        << ", \"grad_flops\": "
+        << W.grad_primq * qc[q].grad_prim_flops + W.grad_quart * qc[q].grad_con_flops
         << ", \"private_bytes\": [" << c->private_bytes[q][0] << ", " << c->private_bytes[q][1]
         << ", " << c->private_bytes[q][2] << "], \"variant\": [" << c->fock_variant[0][q] << ", "
         << c->fock_variant[1][q] << ", " << c->grad_variant[q] << "], \"tune_ms\": ["

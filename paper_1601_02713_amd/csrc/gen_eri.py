@@ -599,6 +599,8 @@ def main(outdir):
         tag = f"{la}{lb}{lc}{ld}"
         sets, sizes, gfl, cfl, code = gen_grad(la, lb, lc, ld)
         table[tag]["grad_vrr_flops_per_prim"] = gfl
+        # per primitive quartet in all: setup and Boys to L + 1, the raised and lowered VRR
+        table[tag]["grad_prim_flops"] = prim_flops(la + lb + lc + ld + 1) + gfl
         table[tag]["grad_contract_flops"] = cfl
         if la + lb + lc + ld > LANE_G_MAX:
             continue
@@ -709,8 +711,9 @@ def main(outdir):
             "  void (*grad)(const GradArgs&, hipStream_t);",
             "  void (*coop_grad)(const GradArgs&, hipStream_t);",
             "  void (*tensor)(const TensorArgs&, hipStream_t);",
-            "  // FLOPs per primitive quartet (setup, Boys, VRR) and per contracted quartet (HRR)",
-            "  double prim_flops, hrr_flops, grad_vrr_flops, grad_con_flops;",
+            "  // FLOPs per primitive quartet (setup, Boys, VRR) and per contracted quartet (HRR),",
+            "  // of the Fock build and of the gradient (its contraction with the density factors)",
+            "  double prim_flops, hrr_flops, grad_prim_flops, grad_con_flops;",
             "  int (*fock_private_bytes)(int);",
             "  int (*grad_private_bytes)();",
             "  int (*coop_private_bytes)(int);",
@@ -725,7 +728,7 @@ def main(outdir):
         reg.append(f"    {{{la}, {lb}, {lc}, {ld}, {f'launch_fock_{tag}' if le else 'nullptr'}, "
                    f"launch_coop_fock_{tag}, {f'launch_grad_{tag}' if lg else 'nullptr'}, "
                    f"launch_coop_grad_{tag}, {f'launch_tensor_{tag}' if le else f'launch_coop_tensor_{tag}'}, "
-                   f"{t['prim_flops']}.0, {t['hrr_flops']}.0, {t['grad_vrr_flops_per_prim']}.0, "
+                   f"{t['prim_flops']}.0, {t['hrr_flops']}.0, {t['grad_prim_flops']}.0, "
                    f"{t['grad_contract_flops']}.0, {f'fock_private_bytes_{tag}' if le else 'nullptr'}, "
                    f"{f'grad_private_bytes_{tag}' if lg else 'nullptr'}, coop_private_bytes_{tag}}},")
     reg += ["  };", "  return t;", "}"]

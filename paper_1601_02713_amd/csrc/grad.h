@@ -41,6 +41,9 @@ struct GradArgs {
   // share of exact exchange in the density factor: 1 for Hartree-Fock, 0.2
   // for B3LYP (the bound above stays an upper bound for kx <= 1)
   double kx;
+  // with gstat: the class's evaluated (not skipped) quartets and primitive
+  // quartets are added into gstat[0] and gstat[1]
+  double* gstat;
 };
 
 // Density-weighted bound of quartet (bid|kid) (see GradArgs).

@@ -194,6 +194,7 @@ __global__ __launch_bounds__(256) void grad_unit_kernel(GradArgs a) {
   __syncthreads();
   const double AB[3] = {sa.x - sb.x, sa.y - sb.y, sa.z - sb.z};
   double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
+  double nkeep = 0.0, nkeep_p = 0.0;   // evaluated quartets and primitive quartets
   for (int c0 = 0; c0 < u.count; c0 += nt) {
     const int t = c0 + tid;
     const bool valid = t < u.count;
@@ -238,9 +239,12 @@ __global__ __launch_bounds__(256) void grad_unit_kernel(GradArgs a) {
     };
     double g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int2 kp = a.kpos[pos];
-    if (keep)
+    if (keep) {
       grad_block_lane<CG>(Bp, bra.nprim, a.kprims + kp.x, ket.nprim, kp.y, AB, CD, a.boys64,
                           gfill, g9);
+      nkeep += 1.0;
+      nkeep_p += double(bra.nprim * ket.nprim);
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       gA[d] += g9[d];
@@ -267,6 +271,13 @@ __global__ __launch_bounds__(256) void grad_unit_kernel(GradArgs a) {
     if (lane == 0) {
       atomicAdd(&a.grad[3 * sa.atom + d], x);
       atomicAdd(&a.grad[3 * sb.atom + d], y);
+    }
+  }
+  if (a.gstat) {
+    const double q = gwave_sum(nkeep), pq = gwave_sum(nkeep_p);
+    if (lane == 0 && q > 0.0) {
+      atomicAdd(&a.gstat[0], q);
+      atomicAdd(&a.gstat[1], pq);
     }
   }
 }
