@@ -14,6 +14,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <exception>
 #include <chrono>
@@ -457,6 +458,7 @@ struct bscf_ctx {
   DevBuf<double> d_xyz, d_Zd, d_Enuc, d_E, d_Eprev, d_emax, d_grad;
   DevBuf<double> d_grad_tune;   // [3 total_atoms]: the gradient kernels' timing pass writes here
   DevBuf<int> d_task_a, d_task_b;  // 1e tasks: pair shells
+  std::vector<double> pair_rcut;    // per pair of c->pairs: distance beyond which it is negligible
   std::vector<int> task_first, task_count;  // per pair class ranges into task arrays
   // matrices
   DevBuf<double> S, T, V, H, X, F, J, K, P, Pnew, W, tmp1, tmp2, err, Fbar, C, Cacc, eig, eigE;
@@ -2533,20 +2535,10 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->d_pair_ids.clear();
     c->d_pair_ids.resize(kNumPairClasses);
     for (int pc = 0; pc < kNumPairClasses; ++pc) c->d_pair_ids[pc].upload(c->pairs_by_class[pc], s);
-    // 1e task arrays: pairs grouped by pair class
-    std::vector<int> ta, tb;
+    // 1e task arrays: built per geometry (one_e_tasks)
     c->task_first.assign(kNumPairClasses, 0);
     c->task_count.assign(kNumPairClasses, 0);
-    for (int pc = 0; pc < kNumPairClasses; ++pc) {
-      c->task_first[pc] = (int)ta.size();
-      for (int pid : c->pairs_by_class[pc]) {
-        ta.push_back(c->pairs[pid].a);
-        tb.push_back(c->pairs[pid].b);
-      }
-      c->task_count[pc] = (int)ta.size() - c->task_first[pc];
-    }
-    c->d_task_a.upload(ta, s);
-    c->d_task_b.upload(tb, s);
+    c->pair_rcut.clear();
     std::vector<int> ones(n_inst, 1), zeros(n_inst, 0);
     c->d_active.upload(ones, s);
     c->d_all_active.upload(ones, s);
@@ -2604,6 +2596,90 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
   });
 }
 
+// The one-electron tasks of the current geometry: the shell pairs, grouped by
+// pair class, whose centres lie within the pair's cutoff distance.  Past it
+// every integral of the pair and its centre derivatives (S, T, V for every
+// nucleus, their gradient) is below 1e-20: for R = |A - B| the bound
+// sum_kl |c_k c_l| e^{-mu_kl R^2} (1 + R)^(la + lb + 2) (1 + 2 a_k)(1 + 2 b_l)
+// max((pi/p)^1.5, 2 pi/p Z_max N_atoms) (mu = a b / p, p = a + b) covers the
+// Gaussian products, the polynomial factors and the derivative factors; the
+// cutoff is found once per pair by a 0.05-bohr scan of the bound's tail.
+void one_e_tasks(bscf_ctx* c, hipStream_t s) {
+  const size_t np = c->pairs.size();
+  if (c->pair_rcut.size() != np) {
+    c->pair_rcut.assign(np, 0.0);
+    // shell types by their exact contents (l, exponents, coefficients)
+    std::map<std::vector<double>, int> types;
+    std::vector<int> type(c->shells.size());
+    for (size_t k = 0; k < c->shells.size(); ++k) {
+      const Shell& S = c->shells[k];
+      std::vector<double> v{(double)S.l};
+      for (int i = 0; i < S.nprim; ++i) {
+        v.push_back(c->sh_exp[S.prim0 + i]);
+        v.push_back(c->sh_coef[S.prim0 + i]);
+      }
+      type[k] = types.emplace(v, (int)types.size()).first->second;
+    }
+    std::vector<double> zn(c->ninst, 1.0);   // Z_max N_atoms per instance
+    for (int i = 0; i < c->ninst; ++i) {
+      double zmax = 1.0;
+      for (int t = 0; t < c->natoms[i]; ++t) zmax = std::max(zmax, (double)c->Zs[c->atom_off[i] + t]);
+      zn[i] = zmax * c->natoms[i];
+    }
+    std::map<std::array<double, 3>, double> cache;   // by (type a, type b, Z_max N_atoms)
+    for (size_t k = 0; k < np; ++k) {
+      const Shell& A = c->shells[c->pairs[k].a];
+      const Shell& B = c->shells[c->pairs[k].b];
+      const double zna = zn[A.inst];
+      const std::array<double, 3> key = {(double)type[c->pairs[k].a], (double)type[c->pairs[k].b],
+                                         zna};
+      auto it = cache.find(key);
+      if (it != cache.end()) {
+        c->pair_rcut[k] = it->second;
+        continue;
+      }
+      auto bound = [&](double R) {
+        double b = 0.0;
+        for (int i = 0; i < A.nprim; ++i)
+          for (int j = 0; j < B.nprim; ++j) {
+            const double al = c->sh_exp[A.prim0 + i], be = c->sh_exp[B.prim0 + j];
+            const double p = al + be, mu = al * be / p;
+            const double pre = std::max(std::pow(M_PI / p, 1.5), 2.0 * M_PI / p * zna);
+            b += std::fabs(c->sh_coef[A.prim0 + i] * c->sh_coef[B.prim0 + j]) *
+                 std::exp(-mu * R * R) * (1.0 + 2.0 * al) * (1.0 + 2.0 * be) * pre;
+          }
+        return b * std::pow(1.0 + R, A.l + B.l + 2);
+      };
+      double last = 0.0;
+      for (double R = 0.0; R < 400.0; R += 0.05) {
+        const double b = bound(R);
+        if (b > 1e-20) last = R;
+        else if (b < 1e-26) break;
+      }
+      c->pair_rcut[k] = last + 0.05;
+      cache.emplace(key, last + 0.05);
+    }
+  }
+  std::vector<int> ta, tb;
+  ta.reserve(np);
+  tb.reserve(np);
+  for (int pc = 0; pc < kNumPairClasses; ++pc) {
+    c->task_first[pc] = (int)ta.size();
+    for (int pid : c->pairs_by_class[pc]) {
+      const Shell& A = c->shells[c->pairs[pid].a];
+      const Shell& B = c->shells[c->pairs[pid].b];
+      const double dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
+      const double rc = c->pair_rcut[pid];
+      if (dx * dx + dy * dy + dz * dz > rc * rc) continue;
+      ta.push_back(c->pairs[pid].a);
+      tb.push_back(c->pairs[pid].b);
+    }
+    c->task_count[pc] = (int)ta.size() - c->task_first[pc];
+  }
+  c->d_task_a.upload(ta, s);
+  c->d_task_b.upload(tb, s);
+}
+
 bscf_status bscf_set_geometries(bscf_ctx* c, const double* xyz) {
   return guard([&] {
     need(c && xyz, BSCF_E_INVALID, "NULL argument");
@@ -2645,7 +2721,11 @@ bscf_status bscf_set_geometries(bscf_ctx* c, const double* xyz) {
       const int lb = pc - la * (la + 1) / 2;
       schwarz_launcher(la, lb)(sa, st);
     }
-    // one-electron matrices
+    // one-electron matrices over the pairs that are not negligible at this
+    // geometry (the others stay zero)
+    one_e_tasks(c, st);
+    launch_fill(c->S.p, c->mtot, 0.0, st);
+    launch_fill(c->T.p, c->mtot, 0.0, st);
     launch_fill(c->V.p, c->mtot, 0.0, st);
     for (int pc = 0; pc < kNumPairClasses; ++pc) {
       if (c->task_count[pc] == 0) continue;
