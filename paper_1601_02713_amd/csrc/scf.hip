@@ -575,8 +575,16 @@ __global__ __launch_bounds__(256) void sp2_gemm_kernel(BatchInfo b, int max_n, c
   if (b.active && !b.active[inst]) return;
   const int n = b.nbf[inst], nt = ntiles_1d(n);
   if (tile >= nt * nt) return;
+  // X and X^2 are symmetric: the tiles above the diagonal are computed and
+  // also written transposed; a tile below it only clears its statistics
+  const int ti = tile / nt, tj = tile % nt;
+  if (ti > tj) {
+    if (threadIdx.x < 2) st_out[((long long)inst * ntm * ntm + tile) * 2 + threadIdx.x] = 0.0;
+    return;
+  }
+  const bool mirror = ti != tj;
   const long long o = b.moff[inst];
-  const int ti0 = (tile / nt) * kTile, tj0 = (tile % nt) * kTile;
+  const int ti0 = ti * kTile, tj0 = tj * kTile;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i0 = ti0 + (wave >> 1) * 16, j0 = tj0 + (wave & 1) * 16;
   const int c = lane & 15, kq = lane >> 4;
@@ -608,7 +616,10 @@ __global__ __launch_bounds__(256) void sp2_gemm_kernel(BatchInfo b, int max_n, c
   if (first >= 0 && step >= first + 2) {   // finished: carry X forward (block-uniform)
     for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
       const int i = ti0 + e / kTile, j = tj0 + e % kTile;
-      if (i < n && j < n) Xn[o + (long long)i * n + j] = X[o + (long long)i * n + j];
+      if (i < n && j < n) {
+        Xn[o + (long long)i * n + j] = X[o + (long long)i * n + j];
+        if (mirror) Xn[o + (long long)j * n + i] = X[o + (long long)j * n + i];
+      }
     }
     const long long so = ((long long)inst * ntm * ntm + tile) * 2;
     if (threadIdx.x < 2) st_out[so + threadIdx.x] = st_in[so + threadIdx.x];
@@ -650,11 +661,13 @@ __global__ __launch_bounds__(256) void sp2_gemm_kernel(BatchInfo b, int max_n, c
       const double y = acc[r];
       const double x = square ? y : 2.0 * xold[r] - y;
       Xn[o + (long long)i * n + j] = x;
+      if (mirror) Xn[o + (long long)j * n + i] = x;
       fs += x * x;
       if (i == j) ts += x;
     }
   }
-  sp2_store_stats(ts, fs, st_out + ((long long)inst * ntm * ntm + tile) * 2, sh);
+  // an off-diagonal tile stands for its mirror too in sum X_ij^2
+  sp2_store_stats(ts, mirror ? 2.0 * fs : fs, st_out + ((long long)inst * ntm * ntm + tile) * 2, sh);
 }
 
 }  // namespace
