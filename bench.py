@@ -340,8 +340,14 @@ def md_bench(args):
         "training_ms_per_step": float(np.mean(train_ms[k0:])),
         "fock": {k: v for k, v in head.items() if k not in ("roofline",)},
         "roofline": head["roofline"],
+        # t_work_ms: the SCF's wait for the screened work lists and their
+        # upload; t_work_host_ms: the host build of the lists (on worker
+        # threads, behind the geometry's device set-up)
         "phase_ms_per_step": {k: sh[k] / args.steps for k in
-                              ("t_setup_ms", "t_scf_ms", "t_grad_ms", "t_fock_ms", "t_work_ms")},
+                              ("t_setup_ms", "t_scf_ms", "t_grad_ms", "t_fock_ms", "t_work_ms",
+                               "t_work_host_ms")},
+        # the host build's phases: ket lists, per (class, instance) parts, merges
+        "work_host_phases_ms_per_step": [v / args.steps for v in sh["t_work_phase_ms"]],
         "plain_fp64_gpu": {
             "steps": nb, "guess": "previous-step orbitals",
             "screened_quartets_per_s": base["screened_quartets_per_s"],

@@ -351,6 +351,7 @@ struct bscf_ctx {
   double xc_basis_bytes = 0, xc_point_bytes = 0;
   long long xc_launches[7] = {}, xc_builds = 0;
   double t_work_host_ms = 0;   // host part of the work lists, wherever it ran
+  bool items_all = false;      // build every class's cooperative items (see build_work_host)
   double t_work_phase_ms[3] = {0, 0, 0};   // its ket lists, parts, merges
   rocblas_handle blas = nullptr;
 
@@ -412,6 +413,8 @@ struct bscf_ctx {
     // evaluated so far (active instances only) and measured kernel time
     double done_quart = 0, done_primq = 0, kernel_ms = 0, grad_ms = 0;
     double grad_quart = 0, grad_primq = 0;   // evaluated by the gradient (device counts)
+    bool has_work = false;       // any screened quartet in the batch
+    bool items_skipped = false;  // the cooperative items were not built (see build_work_host)
     // Schwarz-screened quartets (at the build's cutoff) of the instances each
     // build covered, whether a full or an incremental build evaluated them
     double screened_quart = 0;
@@ -960,6 +963,17 @@ void build_shell_topology(bscf_ctx* c) {
   }
 }
 
+// Host threads for the work lists: OMP_NUM_THREADS when set (the CPU share
+// the process is meant to use), else the hardware's, at most 16.
+int host_threads() {
+  int n = (int)std::thread::hardware_concurrency();
+  if (const char* v = std::getenv("OMP_NUM_THREADS")) {
+    const int e = std::atoi(v);
+    if (e > 0) n = e;
+  }
+  return std::max(1, std::min(16, n));
+}
+
 // Work lists for the Fock build (see file comment).
 // Host part of the work lists (no HIP calls, no device buffers): it may run
 // on a worker thread while the context's stream computes something else.
@@ -979,7 +993,7 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
         }
       }
     };
-    const int nth = std::max(1, std::min<int>(8, (int)std::thread::hardware_concurrency()));
+    const int nth = host_threads();
     std::vector<std::thread> pool;
     for (int t = 1; t < nth; ++t) pool.emplace_back(worker);
     worker();
@@ -1081,6 +1095,17 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
     }
     return lo;
   };
+  // A class whose tuned Fock kernels (every precision tuned so far) and
+  // gradient kernel are lane forms never launches a cooperative kernel in
+  // this context, so its 64-quartet items (the bulk of the merge for the
+  // light classes) are not built; tuning a further precision first rebuilds
+  // the lists with every class's items (items_all).
+  std::vector<char> skip_items(kNumQuartetClasses, 0);
+  if (!c->items_all && c->grad_tuned && (c->fock_tuned[0] || c->fock_tuned[1]))
+    for (int q = 0; q < kNumQuartetClasses; ++q)
+      skip_items[q] = c->grad_variant[q] == 0 &&
+                      (!c->fock_tuned[0] || c->fock_variant[0][q] != 1) &&
+                      (!c->fock_tuned[1] || c->fock_variant[1][q] != 1);
   auto build_part = [&](int q, int i) {
     Part& P = parts[(size_t)q * ni + i];
     const int X = pclass(qc[q].la, qc[q].lb), Y = pclass(qc[q].lc, qc[q].ld);
@@ -1141,6 +1166,7 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
         add_units(ur0, ur_nprim, bs.nprim);
       }
     // tile every group with items of up to 64 quartets (one per lane)
+    if (skip_items[q]) return;
     for (auto& gr : groups) {
       const int r0 = (int)P.rows.size();
       P.rows.insert(P.rows.end(), gr.second.begin(), gr.second.end());
@@ -1263,6 +1289,8 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
       const int b = cst > 1.0 ? (int)(8.0 * std::log2(cst)) : 0;
       return 320 - std::min(b, 320);
     }, 321);
+    W.has_work = W.nquart > 0;
+    W.items_skipped = skip_items[q] != 0;
     W.max_prims = c->max_prims_pc[pclass(qc[q].la, qc[q].lb)];
     W.lds_ok = sizeof(double) * (size_t)unit_lds_doubles(qc[q].la, qc[q].lb, c->max_n,
                                                           W.max_prims) <= c->max_lds_bytes;
@@ -1491,7 +1519,7 @@ void autotune_fock(bscf_ctx* c, int pcol) {
     const bool lane_ok = qc[q].fock && W.lds_ok && c->private_bytes[q][0] <= c->lane_scratch_max &&
                          !(pcol && c->private_bytes[q][1] > c->lane_scratch_max);
     if (!lane_ok) c->fock_variant[pcol][q] = 1;
-    if (W.items.empty()) continue;
+    if (!W.has_work) continue;
     set_class(a, W);
     // variants: 0 the lane form of this precision, 1 cooperative, and in
     // MIXED mode 2 the FP64 lane form (FP32 integrals do not pay everywhere);
@@ -2114,7 +2142,17 @@ void xc_gradient(bscf_ctx* c, const double* P, double* grad) {
 
 void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool incremental = false) {
   ensure_work(c, tau, c->split_tol, precision == BSCF_MIXED);
-  if (!c->fock_tuned[precision == BSCF_MIXED ? 1 : 0]) autotune_fock(c, precision == BSCF_MIXED ? 1 : 0);
+  if (!c->fock_tuned[precision == BSCF_MIXED ? 1 : 0]) {
+    // the autotuner times the cooperative forms too: lists with every item
+    bool skipped = false;
+    for (int q = 0; q < kNumQuartetClasses; ++q) skipped |= c->work[q].items_skipped;
+    if (skipped) {
+      c->items_all = true;
+      build_work_host(c, tau, c->split_tol);
+      build_work_device(c);
+    }
+    autotune_fock(c, precision == BSCF_MIXED ? 1 : 0);
+  }
   const double t0 = now_ms();
   FockArgs a = fock_args(c, c->J.p, c->K.p, masked ? c->d_active.p : c->d_all_active.p);
   const BatchInfo bset = c->batch(masked);
@@ -2144,7 +2182,7 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
     int nrk = 0;
     for (int q = 0; q < kNumQuartetClasses; ++q) {
       auto& W = c->work[q];
-      if (W.items.empty()) continue;
+      if (!W.has_work) continue;
       RowKeepClass& r = rk[nrk++];
       r.cq = c->d_kept.p + (size_t)q * ni;
       r.cpq = c->d_kept.p + (size_t)(kNumQuartetClasses + q) * ni;
@@ -2204,7 +2242,7 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
   float load[kRing] = {};
   for (int q : order) {
     auto& W = c->work[q];
-    if (W.items.empty()) continue;
+    if (!W.has_work) continue;
     // one launch: kernels with private scratch go to the context stream
     auto launch = [&](int pbytes, auto&& run) {
       int k = 0;
@@ -2587,6 +2625,7 @@ bscf_status bscf_set_instances(bscf_ctx* c, int n_inst, const int* n_atoms, cons
     c->d_c2ok.resize(n_inst);
     c->work_tau = c->host_tau = -1.0;
     c->fock_tuned[0] = c->fock_tuned[1] = c->grad_tuned = false;
+    c->items_all = false;
     c->guess.reset_batch(c->ninst);
     c->md.on = c->md.synced = c->md.have_force = false;
     c->str.on = c->str.synced = false;
@@ -3298,7 +3337,7 @@ void forces_impl(bscf_ctx* c, double* Fout, bool with_xc = false) {
       for (int q = 0; q < kNumQuartetClasses; ++q) {
         auto& W = c->work[q];
         c->tune_grad_ms[q][0] = c->tune_grad_ms[q][1] = 0.0f;
-        if (W.items.empty()) continue;
+        if (!W.has_work) continue;
         set_gclass(gt, W);
         const bool lds_ok = sizeof(double) * (size_t)grad_unit_lds_doubles(
                                 qc[q].la, qc[q].lb, c->max_n, c->max_atoms, W.max_prims) <=
@@ -3352,7 +3391,7 @@ void forces_impl(bscf_ctx* c, double* Fout, bool with_xc = false) {
     };
     std::vector<Job> jobs;
     for (int q = 0; q < kNumQuartetClasses; ++q) {
-      if (c->work[q].items.empty()) continue;
+      if (!c->work[q].has_work) continue;
       const int var = c->grad_variant[q];
       jobs.push_back({c->tune_grad_ms[q][var], q,
                       var ? c->coop_bytes[q][1] : c->private_bytes[q][2]});
