@@ -256,6 +256,37 @@ bscf_status bscf_pimd_end(bscf_ctx* ctx, const double* forces);
  * sum m w_P^2 |q_j - q_{j+1}|^2 / 2 (Eh), and the number of steps taken. */
 bscf_status bscf_pimd_state(bscf_ctx* ctx, double* x, double* p, double* obs);
 
+/* Checkpoint and resume of a run between steps.  The paper carries each
+ * bead's molecular orbitals from one MD step to the next as the next SCF's
+ * starting point (Section 2); a checkpoint writes that carried state, and
+ * the ring polymer's, to a file so that a new process continues the run.
+ *
+ * bscf_checkpoint_save writes (binary, this library's own little-endian
+ * format, version 1) the batch's composition, charges and basis sizes, the
+ * geometry, the density and the orbitals of the last two SCFs of every
+ * instance (the previous-step and extrapolated guesses), the ring polymer if
+ * one is running (options, masses, positions, momenta, step count, and the
+ * gradient at the current positions when it is held), and the learned
+ * guess's network with its Adam moments.  It needs a geometry
+ * (BSCF_E_STATE) and a writable path (BSCF_E_INVALID).
+ *
+ * bscf_checkpoint_load restores that state into a context whose batch was
+ * set with the same composition, charges and basis (bscf_set_instances;
+ * BSCF_E_INVALID otherwise, and for a missing, foreign or truncated file,
+ * all checked before the context changes): it sets the geometry
+ * (bscf_set_geometries), the carried density and orbitals, the ring polymer
+ * at its saved step and the network.  The next bscf_pimd_step then takes
+ * the same thermostat draws (counters by step) and, with the saved
+ * gradient, no extra SCF.  Not saved: the learned guess's recorded training
+ * steps and last residual (training resumes from the next recorded step),
+ * the autotuner's choices (retuned in the new process) and the string
+ * method's state; the SCF density has to be recomputed before bscf_forces.
+ * With the FP64 path and the previous-step or extrapolated guess the
+ * resumed step repeats the uninterrupted one to the rounding of the atomic
+ * accumulations (bitwise in the deterministic J/K mode's Fock builds). */
+bscf_status bscf_checkpoint_save(bscf_ctx* ctx, const char* path);
+bscf_status bscf_checkpoint_load(bscf_ctx* ctx, const char* path);
+
 /* String method on the device.  The paper's second workload moves a
  * reaction path of images between force calls (Section 3.2, Fig. 4: each
  * image's BO energy and force in parallel, images needing different numbers

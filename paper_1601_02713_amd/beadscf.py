@@ -65,6 +65,8 @@ _SIGS = {
     "bscf_reset_stats": [_vp],
     "bscf_boys": [_vp, _i, _i, _vp, _vp, _i],
     "bscf_guess_train": [_vp, _i, _vp],
+    "bscf_checkpoint_save": [_vp, ctypes.c_char_p],
+    "bscf_checkpoint_load": [_vp, ctypes.c_char_p],
     "bscf_guess_save": [_vp, ctypes.c_char_p],
     "bscf_guess_load": [_vp, ctypes.c_char_p],
     "bscf_guess_configure": [_vp, _i, _i, ctypes.c_uint],
@@ -319,6 +321,13 @@ class Engine:
         x, p, obs = np.empty((P, N, 3)), np.empty((P, N, 3)), np.empty(3)
         _chk(_lib.bscf_pimd_state(self._h, _ptr(x), _ptr(p), _ptr(obs)))
         return x, p, float(obs[0]), float(obs[1]), int(obs[2])
+
+    # ---- checkpoint / resume between steps
+    def checkpoint_save(self, path):
+        _chk(_lib.bscf_checkpoint_save(self._h, str(path).encode()))
+
+    def checkpoint_load(self, path):
+        _chk(_lib.bscf_checkpoint_load(self._h, str(path).encode()))
 
     # ---- string method (the batch's instances are its images)
     def string_init(self, opts: StringOpts | None = None, **kw):

@@ -17,6 +17,7 @@
 #include <array>
 #include <atomic>
 #include <exception>
+#include <fstream>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -4186,6 +4187,179 @@ bscf_status bscf_guess_fit(bscf_ctx* c, int rows, const float* X, const float* T
     HIPCHK(hipSetDevice(c->device));
     const float l = c->guess.fit_rows(rows, X, T, mask, steps, lr, c->stream);
     if (loss) *loss = l;
+  });
+}
+
+}  // extern "C"
+
+namespace {
+constexpr int kCkptMagic = 0x4B435342;   // "BSCK"
+constexpr int kCkptVersion = 1;
+
+template <typename T>
+void put(std::ostream& f, const T& v) {
+  f.write(reinterpret_cast<const char*>(&v), sizeof(T));
+}
+template <typename T>
+void put(std::ostream& f, const std::vector<T>& v) {
+  f.write(reinterpret_cast<const char*>(v.data()), v.size() * sizeof(T));
+}
+template <typename T>
+T get(std::istream& f) {
+  T v{};
+  f.read(reinterpret_cast<char*>(&v), sizeof(T));
+  need(bool(f), BSCF_E_INVALID, "checkpoint: truncated file");
+  return v;
+}
+template <typename T>
+std::vector<T> get(std::istream& f, size_t n) {
+  std::vector<T> v(n);
+  f.read(reinterpret_cast<char*>(v.data()), n * sizeof(T));
+  need(bool(f), BSCF_E_INVALID, "checkpoint: truncated file");
+  return v;
+}
+template <typename T>
+std::vector<T> fetch(bscf_ctx* c, const T* d, size_t n) {
+  std::vector<T> h(n);
+  if (n) HIPCHK(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+  return h;
+}
+}  // namespace
+
+extern "C" {
+
+bscf_status bscf_checkpoint_save(bscf_ctx* c, const char* path) {
+  return guard([&] {
+    need(c && path, BSCF_E_INVALID, "NULL argument");
+    require_geom(c);
+    HIPCHK(hipSetDevice(c->device));
+    const int ni = c->ninst, na = c->total_atoms;
+    const size_t mt = (size_t)c->mtot;
+    const auto P = fetch(c, c->P.p, mt), C1 = fetch(c, c->Cacc.p, mt), C2 = fetch(c, c->Cprev.p, mt);
+    auto& m = c->md;
+    const size_t nx = (size_t)m.P * 3 * m.N;
+    std::vector<double> mx, mp, mmass, grad;
+    if (m.on) {
+      mx = fetch(c, m.x.p, nx);
+      mp = fetch(c, m.p.p, nx);
+      mmass = fetch(c, m.mass.p, (size_t)m.N);
+      if (m.have_force) grad = fetch(c, c->d_grad.p, (size_t)3 * na);
+    }
+    sync(c);
+    std::ofstream f(path, std::ios::binary);
+    need(bool(f), BSCF_E_INVALID, std::string("checkpoint: cannot write ") + path);
+    put(f, kCkptMagic);
+    put(f, kCkptVersion);
+    put(f, ni);
+    put(f, na);
+    put(f, c->mtot);
+    put(f, c->natoms);
+    put(f, c->Zs);
+    put(f, c->charge);
+    put(f, c->nbf);
+    put(f, c->xyz);
+    put(f, (int)c->have_C);
+    put(f, c->h_ccount);
+    put(f, P);
+    put(f, C1);
+    put(f, C2);
+    put(f, (int)m.on);
+    if (m.on) {
+      put(f, m.o.dt);
+      put(f, m.o.temperature);
+      put(f, m.o.thermostat);
+      put(f, m.o.tau_centroid);
+      put(f, m.o.friction_scale);
+      put(f, m.o.seed);
+      put(f, m.P);
+      put(f, m.N);
+      put(f, m.step);
+      put(f, (int)m.synced);
+      put(f, (int)m.have_force);
+      put(f, mmass);
+      put(f, mx);
+      put(f, mp);
+      if (m.have_force) put(f, grad);
+    }
+    const int net = c->guess.din() > 0 ? 1 : 0;
+    put(f, net);
+    if (net) c->guess.save(f);
+    f.flush();
+    need(bool(f), BSCF_E_INVALID, std::string("checkpoint: write failed: ") + path);
+  });
+}
+
+bscf_status bscf_checkpoint_load(bscf_ctx* c, const char* path) {
+  return guard([&] {
+    need(c && path, BSCF_E_INVALID, "NULL argument");
+    need(c->ninst > 0, BSCF_E_INVALID, "set instances first");
+    std::ifstream f(path, std::ios::binary);
+    need(bool(f), BSCF_E_INVALID, std::string("checkpoint: cannot read ") + path);
+    // everything is read and checked on the host before the context changes
+    need(get<int>(f) == kCkptMagic && get<int>(f) == kCkptVersion, BSCF_E_INVALID,
+         "checkpoint: not a checkpoint file of this version");
+    const int ni = get<int>(f), na = get<int>(f);
+    const long long mtot = get<long long>(f);
+    need(ni == c->ninst && na == c->total_atoms && mtot == c->mtot, BSCF_E_INVALID,
+         "checkpoint: a different batch");
+    need(get<int>(f, ni) == c->natoms && get<int>(f, na) == c->Zs &&
+             get<int>(f, ni) == c->charge && get<int>(f, ni) == c->nbf,
+         BSCF_E_INVALID, "checkpoint: a different batch or basis");
+    const auto xyz = get<double>(f, (size_t)3 * na);
+    const int have_C = get<int>(f);
+    const auto ccount = get<int>(f, ni);
+    const size_t mt = (size_t)mtot;
+    const auto P = get<double>(f, mt), C1 = get<double>(f, mt), C2 = get<double>(f, mt);
+    const int md_on = get<int>(f);
+    bscf_pimd_opts o{};
+    int mP = 0, mN = 0, synced = 0, have_force = 0;
+    uint64_t step = 0;
+    std::vector<double> mmass, mx, mp, grad;
+    if (md_on) {
+      o.dt = get<double>(f);
+      o.temperature = get<double>(f);
+      o.thermostat = get<int>(f);
+      o.tau_centroid = get<double>(f);
+      o.friction_scale = get<double>(f);
+      o.seed = get<unsigned long long>(f);
+      mP = get<int>(f);
+      mN = get<int>(f);
+      step = get<uint64_t>(f);
+      synced = get<int>(f);
+      have_force = get<int>(f);
+      need(mP == ni && mN == c->natoms[0], BSCF_E_INVALID, "checkpoint: a different ring polymer");
+      const size_t nx = (size_t)mP * 3 * mN;
+      mmass = get<double>(f, (size_t)mN);
+      mx = get<double>(f, nx);
+      mp = get<double>(f, nx);
+      if (have_force) grad = get<double>(f, (size_t)3 * na);
+    }
+    const int net = get<int>(f);
+    mlp::Guess::Saved model;
+    if (net) model = mlp::Guess::read(f);
+    need(bool(f), BSCF_E_INVALID, "checkpoint: truncated file");
+    // geometry (and with it S, H, the Schwarz bounds and the work lists), the
+    // carried densities and orbitals, then the ring polymer at its saved
+    // step, then the network
+    check_status(bscf_set_geometries(c, xyz.data()));
+    HIPCHK(hipSetDevice(c->device));
+    const hipStream_t s = c->stream;
+    c->P.upload(P, s);
+    c->Cacc.upload(C1, s);
+    c->Cprev.upload(C2, s);
+    c->h_ccount = ccount;
+    c->have_C = have_C != 0;
+    if (md_on) {
+      check_status(bscf_pimd_init(c, &o, mmass.data(), mp.data()));
+      auto& m = c->md;
+      m.x.upload(mx, s);
+      m.step = step;
+      m.synced = synced != 0;
+      if (have_force) c->d_grad.upload(grad, s);
+      m.have_force = have_force != 0;
+    }
+    if (net) c->guess.apply(model);
+    sync(c);
   });
 }
 

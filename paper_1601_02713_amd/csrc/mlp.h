@@ -22,6 +22,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <iosfwd>
 #include <string>
 #include <vector>
 
@@ -87,6 +88,18 @@ class Guess {
   bool trained() const { return adam_steps_ > 0; }
   void save(const std::string& path);
   void load(const std::string& path);
+  // The same model record inside a larger file: read() checks it into host
+  // memory without touching the model, apply() installs it.
+  struct Saved {
+    int din = 0, dout = 0, bmax = 0;
+    std::vector<int> types;
+    float scale = 0.f;
+    long adam_steps = 0;
+    std::vector<float> theta, m, v;
+  };
+  void save(std::ostream& f);
+  static Saved read(std::istream& f);
+  void apply(const Saved& r);
 
   // Direct use of the network (tests): fixed dimensions, parameter access,
   // evaluation and full-batch training on caller rows (host arrays).

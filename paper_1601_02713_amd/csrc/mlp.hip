@@ -767,13 +767,18 @@ float Guess::train(int steps, hipStream_t s) {
 // file: magic, din, dout, bmax, ntypes, types, scale, adam steps, theta, m, v
 void Guess::save(const std::string& path) {
   if (din_ == 0) throw std::runtime_error("learned guess: nothing to save");
+  std::ofstream f(path, std::ios::binary);
+  if (!f) throw std::runtime_error("learned guess: cannot write " + path);
+  save(f);
+}
+
+void Guess::save(std::ostream& f) {
+  if (din_ == 0) throw std::runtime_error("learned guess: nothing to save");
   const long n = nparams();
   std::vector<float> th(n), m(n), v(n);
   chk(hipMemcpy(th.data(), theta_.p, n * sizeof(float), hipMemcpyDeviceToHost), "save");
   chk(hipMemcpy(m.data(), m_.p, n * sizeof(float), hipMemcpyDeviceToHost), "save");
   chk(hipMemcpy(v.data(), v_.p, n * sizeof(float), hipMemcpyDeviceToHost), "save");
-  std::ofstream f(path, std::ios::binary);
-  if (!f) throw std::runtime_error("learned guess: cannot write " + path);
   const int head[5] = {0x42534347, din_, dout_, bmax_, (int)types_.size()};
   f.write(reinterpret_cast<const char*>(head), sizeof(head));
   f.write(reinterpret_cast<const char*>(types_.data()), types_.size() * sizeof(int));
@@ -786,10 +791,15 @@ void Guess::save(const std::string& path) {
 }
 
 void Guess::load(const std::string& path) {
-  // the whole file is read and checked into host vectors before the model
-  // changes, so a bad or truncated file leaves the current model in place
   std::ifstream f(path, std::ios::binary);
   if (!f) throw std::runtime_error("learned guess: cannot read " + path);
+  const Saved m = read(f);
+  apply(m);
+}
+
+Guess::Saved Guess::read(std::istream& f) {
+  // the whole model is read and checked into host vectors before anything
+  // changes, so a bad or truncated file leaves the current model in place
   int head[5];
   f.read(reinterpret_cast<char*>(head), sizeof(head));
   // widths as ensure_model makes them (dout = bmax^2, din = element pairs +
@@ -817,14 +827,29 @@ void Guess::load(const std::string& path) {
   f.read(reinterpret_cast<char*>(v.data()), n * sizeof(float));
   if (!f) throw std::runtime_error("learned guess: truncated model file");
   if (!std::isfinite(scale) || steps < 0) throw std::runtime_error("learned guess: not a model file");
-  configure(head[1], head[2], 2000u);
-  chk(hipMemcpy(theta_.p, th.data(), n * sizeof(float), hipMemcpyHostToDevice), "load");
-  chk(hipMemcpy(m_.p, m.data(), n * sizeof(float), hipMemcpyHostToDevice), "load");
-  chk(hipMemcpy(v_.p, v.data(), n * sizeof(float), hipMemcpyHostToDevice), "load");
-  bmax_ = head[3];
-  types_ = types;
-  scale_ = scale;
-  adam_steps_ = steps;
+  Saved r;
+  r.din = head[1];
+  r.dout = head[2];
+  r.bmax = head[3];
+  r.types = std::move(types);
+  r.scale = scale;
+  r.adam_steps = steps;
+  r.theta = std::move(th);
+  r.m = std::move(m);
+  r.v = std::move(v);
+  return r;
+}
+
+void Guess::apply(const Saved& r) {
+  const long n = (long)r.theta.size();
+  configure(r.din, r.dout, 2000u);
+  chk(hipMemcpy(theta_.p, r.theta.data(), n * sizeof(float), hipMemcpyHostToDevice), "load");
+  chk(hipMemcpy(m_.p, r.m.data(), n * sizeof(float), hipMemcpyHostToDevice), "load");
+  chk(hipMemcpy(v_.p, r.v.data(), n * sizeof(float), hipMemcpyHostToDevice), "load");
+  bmax_ = r.bmax;
+  types_ = r.types;
+  scale_ = r.scale;
+  adam_steps_ = r.adam_steps;
 }
 
 }  // namespace mlp
