@@ -103,5 +103,42 @@ def build(force: bool = False, jobs: int | None = None, verbose: bool = True) ->
     return LIB
 
 
+# Host sanitizer variant (a test build, not the product): the host side of
+# engine.cpp instrumented with AddressSanitizer and UndefinedBehaviorSanitizer,
+# device code unchanged, linked with the other objects into
+# _san/libbeadscf_san.so, plus the C-ABI driver tests/native/engine_san_main.c
+# (the sanitizer runtimes come with the executable).
+SAN_DIR = os.path.join(HERE, "_san")
+SAN_FLAGS = ["-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=undefined",
+             "-fno-omit-frame-pointer", "-g"]
+
+
+def build_host_sanitized() -> str:
+    build(verbose=False)
+    os.makedirs(SAN_DIR, exist_ok=True)
+    eng = os.path.join(CSRC, "engine.cpp")
+    obj = os.path.join(SAN_DIR, "engine.cpp.o")
+    host_only = [a for f in SAN_FLAGS for a in ("-Xarch_host", f)]
+    subprocess.check_call(["hipcc"] + HIPFLAGS + host_only + ["-x", "hip", "-c", eng, "-o", obj])
+    objs = [o if os.path.basename(o) != "engine.cpp.o" else obj
+            for o in (os.path.join(OBJ, os.path.basename(s) + ".o") for s in _sources())]
+    lib = os.path.join(SAN_DIR, "libbeadscf_san.so")
+    subprocess.check_call(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", lib] + objs + [
+        "-L", os.path.join(ROCM, "lib"), "-lrocsolver", "-lrocblas", "-lamdhip64",
+        f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}"])
+    exe = os.path.join(SAN_DIR, "engine_san")
+    root = os.path.dirname(HERE)
+    clangxx = os.path.join(ROCM, "lib", "llvm", "bin", "clang++")
+    subprocess.check_call([clangxx] + SAN_FLAGS + [
+        "-I", os.path.join(root, "include"), "-x", "c",
+        os.path.join(root, "tests", "native", "engine_san_main.c"),
+        "-L", SAN_DIR, "-lbeadscf_san", "-Wl,-rpath,$ORIGIN", "-o", exe])
+    print(f"built {exe}")
+    return exe
+
+
 if __name__ == "__main__":
-    build(force="--force" in sys.argv)
+    if "--host-sanitize" in sys.argv:
+        build_host_sanitized()
+    else:
+        build(force="--force" in sys.argv)
