@@ -239,7 +239,7 @@ def md_bench(args):
     def opts(precision, guess):
         return beadscf.default_opts(e_tol=w["e_tol"], comm_tol=w["comm_tol"], schwarz_tol=1e-12,
                                     precision=precision, guess=guess, max_iter=60,
-                                    fp32_split_tol=args.split)
+                                    fp32_split_tol=args.split, graph=args.graph)
 
     # ---- the timed path: integrate, mixed precision, learned guess
     eng = beadscf.Engine(0)
@@ -422,7 +422,7 @@ def b3lyp_bench(args):
     def opts(guess):
         return beadscf.default_opts(e_tol=w["e_tol"], comm_tol=w["comm_tol"], schwarz_tol=1e-12,
                                     precision=prec, guess=guess, max_iter=60,
-                                    fp32_split_tol=args.split)
+                                    fp32_split_tol=args.split, graph=args.graph)
 
     def run(xc):
         name = "B3LYP" if xc else "Hartree-Fock"
@@ -659,7 +659,7 @@ def scf_bench(args):
         "config": {"workload": w["label"], "mode": "setup + SCF + forces of a fixed batch",
                    "instances": n, "basis_functions": eng.nbf[0], "precision": args.precision,
                    "scf_e_tol": w["e_tol"], "scf_comm_tol": w["comm_tol"], "schwarz_tol": 1e-12,
-                   "guess": "core", "graph": bool(args.graph)},
+                   "guess": "core", "graph": args.graph},
         "bead_scf_steps_per_s": iters / wall,
         "bead_energy_force_per_s": n * args.steps / wall,
         "scf_iterations_per_bead": iters / (n * args.steps),
@@ -698,7 +698,7 @@ def main():
     ap.add_argument("--predict-from", type=int, default=3)
     ap.add_argument("--baseline-steps", type=int, default=0,
                     help="timed steps of the plain FP64 leg (default: as many as the timed path)")
-    ap.add_argument("--graph", type=int, choices=[0, 1], default=1)
+    ap.add_argument("--graph", type=int, choices=[0, 1, 2], default=1)
     ap.add_argument("--per-instance", type=int, default=0, metavar="N")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -106,7 +106,12 @@ typedef struct {
                           graph that the context captures once per SP2 step
                           count and keeps until the batch changes; the same
                           kernels as with 0, where they are launched one by
-                          one                                                   */
+                          one; 2: as 1, and each Fock build's J and K
+                          accumulation (density change, screening counts,
+                          the class kernels on their four streams, the
+                          final fold) replays a graph as well, captured once
+                          per kind of build until the work lists or the
+                          tuning change (a new geometry: new captures)        */
 } bscf_scf_opts;
 
 /* Fill opts with defaults: e_tol 1e-8, comm_tol 1e-6, schwarz_tol 1e-12,

@@ -505,6 +505,18 @@ struct bscf_ctx {
   void drop_graphs() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     graphs.clear();
+    drop_fock_graphs();
+  }
+  // J and K accumulation of Fock builds captured as graphs (bscf_scf_opts
+  // graph 2), per (precision, masked, incremental, deterministic, tau); they
+  // hold the addresses and launch shapes of the work lists and the tuned
+  // kernels, so every change of those drops them
+  std::map<std::tuple<int, int, int, int, double>, hipGraphExec_t> fock_graphs;
+  int graph_fock = 0;
+  long long fock_graph_launches = 0, fock_graph_captures = 0;
+  void drop_fock_graphs() {
+    for (auto& g : fock_graphs) (void)hipGraphExecDestroy(g.second);
+    fock_graphs.clear();
   }
   bool have_C = false;
   std::vector<int> h_active;   // host copy of the active flags
@@ -1318,6 +1330,7 @@ void build_work_host(bscf_ctx* c, double tau, double split) {
 // Device part: uploads, the ket-order primitive copy and the ket-position
 // buffers of the lists that build_work_host made.
 void build_work_device(bscf_ctx* c) {
+  c->drop_fock_graphs();   // they hold the lists' addresses and sizes
   c->d_kpos.upload(c->h_kpos, c->stream);
   c->d_kmap.upload(c->h_kmap, c->stream);
   c->d_kprims.resize(c->h_kmap.size());
@@ -1501,6 +1514,7 @@ KetPosArgs ketpos_args(bscf_ctx* c) {
 // the faster; BSCF_VARIANT=lane|coop forces a choice.  A class whose lane
 // kernel needs more LDS than one workgroup may hold runs cooperatively.
 void autotune_fock(bscf_ctx* c, int pcol) {
+  c->drop_fock_graphs();   // they hold the tuned kernels and launch shapes
   const char* env = getenv("BSCF_VARIANT");
   // BSCF_UNIT_THREADS=64|128|256 fixes the threads of the lane units
   const char* env_u = getenv("BSCF_UNIT_THREADS");
@@ -2167,11 +2181,17 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
       c->Jkfx.resize(2 * (size_t)std::max(njk, 1LL));
       launch_fill_u64((long long)c->Jkfx.n, c->Jkfx.p, c->stream);
       incremental = false;   // fresh accumulators: this build starts from zero
+      c->drop_fock_graphs();
     }
     a.Jfx = c->Jfx.p;
     a.Kfx = c->Kfx.p;
     a.Jkfx = c->Jkfx.p;
   }
+  const int pcol = precision == BSCF_MIXED ? 1 : 0;
+  auto alone = [&](int q) { return c->tune_ms[pcol][q][c->fock_variant[pcol][q]]; };
+  // every launch of the J and K accumulation, in stream order (captured into
+  // a graph or run directly)
+  auto enqueue = [&]() {
   if (incremental) {
     launch_density_change(bset, c->max_n, c->P.p, c->Pprev.p, c->dP.p, c->d_dpmax.p, c->stream);
     // kept kets per row for the lane kernels, and the kept work of every
@@ -2209,7 +2229,6 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
     launch_shell_pmax(c->ninst, c->max_nshell, c->d_shell_off.p, c->d_nshell.p, c->d_pm_off.p,
                       c->d_shells.p, c->d_moff.p, c->d_nbf.p, c->dP.p, c->d_dpm.p, c->stream);
     a.dPm = c->d_dpm.p;
-    c->inc_builds++;
   } else if (det) {
     launch_fill_u64(2 * c->mtot, c->Jfx.p, c->stream);
     launch_fill_u64(2 * c->mtot, c->Kfx.p, c->stream);
@@ -2232,12 +2251,10 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
   launch_gather_pk(kp, c->max_ncd, a.P, c->d_Pk.p, c->stream);
   HIPCHK(hipEventRecord(c->ev_fork, c->stream));
   for (int k = 1; k < kRing; ++k) HIPCHK(hipStreamWaitEvent(ring[k], c->ev_fork, 0));
-  const int pcol = precision == BSCF_MIXED ? 1 : 0;
   // classes longest first (by the chosen kernel's time alone), each onto the
   // stream with the least time queued
   int order[kNumQuartetClasses];
   for (int q = 0; q < kNumQuartetClasses; ++q) order[q] = kNumQuartetClasses - 1 - q;
-  auto alone = [&](int q) { return c->tune_ms[pcol][q][c->fock_variant[pcol][q]]; };
   std::stable_sort(order, order + kNumQuartetClasses,
                    [&](int x, int y) { return alone(x) > alone(y); });
   float load[kRing] = {};
@@ -2272,16 +2289,6 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
         launch(c->private_bytes[q][k], run);
       });
     }
-    for (int i = 0; i < c->ninst; ++i)
-      if (!masked || c->h_active[i]) W.screened_quart += W.inst_quart[i];
-    if (!incremental)   // (an incremental build counts its kept work on the device)
-      for (int i = 0; i < c->ninst; ++i)
-        if (!masked || c->h_active[i]) {
-          W.done_quart += W.inst_quart[i];
-          W.done_primq += W.inst_primq[i];
-          if (lane_mode(c, precision, q) == 2) W.done_quart32 += W.inst_quart32[i];
-        }
-    W.launches++;
   }
   for (int k = 1; k < kRing; ++k) {   // ring[k] is aux[k - 1]
     HIPCHK(hipEventRecord(c->ev_join[k - 1], ring[k]));
@@ -2294,8 +2301,51 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
   } else {
     launch_jk_finalize(kp, c->max_ncd, c->d_Jk.p, c->J.p, c->stream);
   }
-  HIPCHK(hipGetLastError());
   if (pbuild >= 0) prof_end(c, pbuild, c->stream);
+  };
+  if (c->graph_fock && !c->profiling) {
+    const auto key = std::make_tuple(pcol, masked ? 1 : 0, incremental ? 1 : 0, det ? 1 : 0, tau);
+    auto g = c->fock_graphs.find(key);
+    if (g == c->fock_graphs.end()) {
+      HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      hipGraph_t graph = nullptr;
+      try {
+        enqueue();
+      } catch (...) {
+        (void)hipStreamEndCapture(c->stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(c->stream, &graph));
+      hipGraphExec_t exec = nullptr;
+      const hipError_t r = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIPCHK(r);
+      g = c->fock_graphs.emplace(key, exec).first;
+      c->fock_graph_captures++;
+    }
+    HIPCHK(hipGraphLaunch(g->second, c->stream));
+    c->fock_graph_launches++;
+  } else {
+    enqueue();
+  }
+  HIPCHK(hipGetLastError());
+  // work counts (an incremental build counts its kept work on the device)
+  if (incremental) c->inc_builds++;
+  for (int q = 0; q < kNumQuartetClasses; ++q) {
+    auto& W = c->work[q];
+    if (!W.has_work) continue;
+    for (int i = 0; i < c->ninst; ++i)
+      if (!masked || c->h_active[i]) W.screened_quart += W.inst_quart[i];
+    if (!incremental)
+      for (int i = 0; i < c->ninst; ++i)
+        if (!masked || c->h_active[i]) {
+          W.done_quart += W.inst_quart[i];
+          W.done_primq += W.inst_primq[i];
+          if (lane_mode(c, precision, q) == 2) W.done_quart32 += W.inst_quart32[i];
+        }
+    W.launches++;
+  }
   if (c->prof_pending.size() > 8192) prof_collect(c);
   BatchInfo b = c->batch(masked);
   if (c->xc_now) {
@@ -3047,6 +3097,13 @@ bscf_status bscf_run_scf(bscf_ctx* c, const bscf_scf_opts* opts, double* E, int*
     need(o.density == BSCF_DENSITY_SP2 || o.density == BSCF_DENSITY_EIG, BSCF_E_INVALID,
          "density must be BSCF_DENSITY_SP2 or BSCF_DENSITY_EIG");
     need(o.deterministic == 0 || o.deterministic == 1, BSCF_E_INVALID, "deterministic must be 0 or 1");
+    need(o.graph >= 0 && o.graph <= 2, BSCF_E_INVALID, "graph must be 0, 1 or 2");
+    // graph 2: this call's Fock builds replay captured J and K launches
+    struct FockGraphs {
+      bscf_ctx* c;
+      ~FockGraphs() { c->graph_fock = 0; }
+    } fg{c};
+    c->graph_fock = o.graph == 2 ? 1 : 0;
     c->det_now = o.deterministic == 1 || c->det;
     c->xc_now = c->xc;
     c->scf_xc = c->xc != 0;
@@ -4023,6 +4080,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
     c->sp2_calls = c->sp2_steps = c->sp2_needed = c->sp2_fallbacks = 0;
     c->inc_builds = 0;
     c->graph_launches = c->graph_captures = 0;
+    c->fock_graph_launches = c->fock_graph_captures = 0;
     for (int k = 0; k < 7; ++k) {
       c->xc_ms[k] = 0;
       c->xc_launches[k] = 0;
@@ -4049,6 +4107,8 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
       << ", \"sp2_steps_needed\": " << c->sp2_needed
       << ", \"sp2_fallbacks\": " << c->sp2_fallbacks << ", \"incremental_builds\": " << c->inc_builds
       << ", \"graph_launches\": " << c->graph_launches << ", \"graph_captures\": " << c->graph_captures
+      << ", \"fock_graph_launches\": " << c->fock_graph_launches
+      << ", \"fock_graph_captures\": " << c->fock_graph_captures
       << ", \"xc\": {\"builds\": " << c->xc_builds << ", \"points\": " << c->xc_points
       << ", \"gemm_flops\": " << c->xc_gemm_flops << ", \"basis_bytes\": " << c->xc_basis_bytes
       << ", \"point_bytes\": " << c->xc_point_bytes << ", \"ms\": {";

@@ -340,6 +340,54 @@ def test_graph_replay_matches_eager(eng):
             assert np.abs(F0[k] - F1[k]).max() < 1e-8
 
 
+@pytest.mark.parametrize("mode", ["fp64_deterministic", "mixed"])
+def test_fock_build_graph_matches_eager(eng, beadscf, mode, monkeypatch):
+    """Fock builds whose J and K launches replay captured graphs (graph 2)
+    against the same launches one by one (graph 1): four (H2O)3 beads, a
+    core-guess SCF and then a previous-step-guess SCF at displaced
+    geometries, so full and incremental builds are each captured once per
+    geometry and replayed across iterations, with eager work and host
+    synchronisations between the replays.  Both runs agree to rounding (the
+    energy sums and SP2 traces use atomics in both, so not bitwise even
+    with deterministic J and K): energies within 1e-11 Eh, densities within
+    1e-9, in FP64 with deterministic J and K (kernel forms fixed) and in
+    mixed precision (tuned forms)."""
+    det = mode == "fp64_deterministic"
+    if det:
+        monkeypatch.setenv("BSCF_VARIANT", "coop")
+    prec = 0 if det else 1
+    z, x = inputs.water_cluster(3, 19)
+    bx = inputs.beads(z, x, 4, 19)
+    by = inputs.beads(z, x, 4, 20)
+    out = {}
+    for graph in (1, 2):
+        _setup(eng, "6-31g*", [(z, bx[k]) for k in range(4)])
+        eng.reset_stats()
+        res = []
+        for geoms, guess in ((None, 0), (by, 1)):
+            if geoms is not None:
+                eng.set_geometries([geoms[k] for k in range(4)])
+            E, it, st = eng.run_scf(e_tol=1e-10, comm_tol=1e-8, graph=graph, guess=guess,
+                                    precision=prec, deterministic=int(det))
+            assert (st == 0).all()
+            res.append((E, it, [eng.density(k) for k in range(4)]))
+        s = eng.stats()
+        out[graph] = (res, s["fock_graph_launches"], s["fock_graph_captures"], s["fock_builds"])
+    (r1, l1, c1, _), (r2, l2, c2, n2) = out[1], out[2]
+    print("fock graph launches", l2, "captures", c2, "builds", n2)
+    assert l1 == 0 and c1 == 0
+    assert l2 == n2 and 2 <= c2 < l2
+    for (E1, it1, P1), (E2, it2, P2) in zip(r1, r2):
+        print("max dE", np.abs(E1 - E2).max(),
+              "max dP", max(np.abs(P1[k] - P2[k]).max() for k in range(4)))
+        assert (it1 == it2).all()
+        assert np.abs(E1 - E2).max() < 1e-11
+        for k in range(4):
+            assert np.abs(P1[k] - P2[k]).max() < 1e-9
+    with pytest.raises(beadscf.BscfError):
+        eng.run_scf(graph=3)
+
+
 def test_full_size_bead_batch(eng, b631gs):
     """The benchmark's batch at full size, in its launch configuration: 16
     beads of (H2O)8 in 6-31G* (152 functions), FP64, core guess, SCF to
