@@ -513,7 +513,7 @@ struct bscf_ctx {
   // kernels, so every change of those drops them
   std::map<std::tuple<int, int, int, int, double>, hipGraphExec_t> fock_graphs;
   int graph_fock = 0;
-  long long fock_graph_launches = 0, fock_graph_captures = 0;
+  long long fock_graph_launches = 0, fock_graph_captures = 0, graph_memset_nodes = 0;
   void drop_fock_graphs() {
     for (auto& g : fock_graphs) (void)hipGraphExecDestroy(g.second);
     fock_graphs.clear();
@@ -891,6 +891,22 @@ void density_half(bscf_ctx* c, const bscf_scf_opts& o, const DiisArgs& d, const 
                      k >= 0 ? ni : 0, c->d_pin.p, st);
 }
 
+// memset nodes of a captured graph (library calls can record them; the
+// statistics report them so that tests can insist on none)
+int memset_nodes(hipGraph_t g) {
+  size_t n = 0;
+  HIPCHK(hipGraphGetNodes(g, nullptr, &n));
+  std::vector<hipGraphNode_t> nodes(n);
+  if (n) HIPCHK(hipGraphGetNodes(g, nodes.data(), &n));
+  int k = 0;
+  for (hipGraphNode_t v : nodes) {
+    hipGraphNodeType t;
+    HIPCHK(hipGraphNodeGetType(v, &t));
+    if (t == hipGraphNodeTypeMemset) ++k;
+  }
+  return k;
+}
+
 // density_half with SP2 of k steps as one launch of a HIP graph, captured
 // from the same calls the first time this (k, tolerances, DIIS size) occurs.
 void density_half_graph(bscf_ctx* c, const bscf_scf_opts& o, const DiisArgs& d,
@@ -908,6 +924,7 @@ void density_half_graph(bscf_ctx* c, const bscf_scf_opts& o, const DiisArgs& d,
       throw;
     }
     HIPCHK(hipStreamEndCapture(c->stream, &graph));
+    c->graph_memset_nodes += memset_nodes(graph);
     hipGraphExec_t exec = nullptr;
     const hipError_t r = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
@@ -2317,6 +2334,7 @@ void fock_build(bscf_ctx* c, double tau, int precision, bool masked, bool increm
         throw;
       }
       HIPCHK(hipStreamEndCapture(c->stream, &graph));
+      c->graph_memset_nodes += memset_nodes(graph);
       hipGraphExec_t exec = nullptr;
       const hipError_t r = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
@@ -4080,7 +4098,7 @@ bscf_status bscf_reset_stats(bscf_ctx* c) {
     c->sp2_calls = c->sp2_steps = c->sp2_needed = c->sp2_fallbacks = 0;
     c->inc_builds = 0;
     c->graph_launches = c->graph_captures = 0;
-    c->fock_graph_launches = c->fock_graph_captures = 0;
+    c->fock_graph_launches = c->fock_graph_captures = c->graph_memset_nodes = 0;
     for (int k = 0; k < 7; ++k) {
       c->xc_ms[k] = 0;
       c->xc_launches[k] = 0;
@@ -4109,6 +4127,7 @@ bscf_status bscf_get_stats(bscf_ctx* c, char* buf, int len) {
       << ", \"graph_launches\": " << c->graph_launches << ", \"graph_captures\": " << c->graph_captures
       << ", \"fock_graph_launches\": " << c->fock_graph_launches
       << ", \"fock_graph_captures\": " << c->fock_graph_captures
+      << ", \"graph_memset_nodes\": " << c->graph_memset_nodes
       << ", \"xc\": {\"builds\": " << c->xc_builds << ", \"points\": " << c->xc_points
       << ", \"gemm_flops\": " << c->xc_gemm_flops << ", \"basis_bytes\": " << c->xc_basis_bytes
       << ", \"point_bytes\": " << c->xc_point_bytes << ", \"ms\": {";

@@ -327,6 +327,7 @@ def test_graph_replay_matches_eager(eng):
             assert (st == 0).all()
             res.append((E, it, [eng.density(k) for k in range(4)], eng.forces()))
         s = eng.stats()
+        assert s["graph_memset_nodes"] == 0   # fills are kernels, also inside the libraries
         out[graph] = (res, s["graph_launches"], s["graph_captures"], s["scf_iterations"])
     (r0, l0, c0, n0), (r1, l1, c1, n1) = out[0], out[1]
     print("graph launches", l1, "captures", c1, "iterations", n1)
@@ -372,6 +373,7 @@ def test_fock_build_graph_matches_eager(eng, beadscf, mode, monkeypatch):
             assert (st == 0).all()
             res.append((E, it, [eng.density(k) for k in range(4)]))
         s = eng.stats()
+        assert s["graph_memset_nodes"] == 0
         out[graph] = (res, s["fock_graph_launches"], s["fock_graph_captures"], s["fock_builds"])
     (r1, l1, c1, _), (r2, l2, c2, n2) = out[1], out[2]
     print("fock graph launches", l2, "captures", c2, "builds", n2)
