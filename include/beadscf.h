@@ -267,12 +267,13 @@ bscf_status bscf_pimd_state(bscf_ctx* ctx, double* x, double* p, double* obs);
  * the ring polymer's, to a file so that a new process continues the run.
  *
  * bscf_checkpoint_save writes (binary, this library's own little-endian
- * format, version 1) the batch's composition, charges and basis sizes, the
+ * format, version 2) the batch's composition, charges and basis sizes, the
  * geometry, the density and the orbitals of the last two SCFs of every
  * instance (the previous-step and extrapolated guesses), the ring polymer if
  * one is running (options, masses, positions, momenta, step count, and the
  * gradient at the current positions when it is held), and the learned
- * guess's network with its Adam moments.  It needs a geometry
+ * guess's network with its Adam moments, its last residual, the previous
+ * geometry and its replay buffer of recorded steps.  It needs a geometry
  * (BSCF_E_STATE) and a writable path (BSCF_E_INVALID).
  *
  * bscf_checkpoint_load restores that state into a context whose batch was
@@ -282,10 +283,10 @@ bscf_status bscf_pimd_state(bscf_ctx* ctx, double* x, double* p, double* obs);
  * (bscf_set_geometries), the carried density and orbitals, the ring polymer
  * at its saved step and the network.  The next bscf_pimd_step then takes
  * the same thermostat draws (counters by step) and, with the saved
- * gradient, no extra SCF.  Not saved: the learned guess's recorded training
- * steps and last residual (training resumes from the next recorded step),
- * the autotuner's choices (retuned in the new process) and the string
- * method's state; the SCF density has to be recomputed before bscf_forces.
+ * gradient, no extra SCF; the learned guess predicts and trains as it
+ * would have.  Not saved: the autotuner's choices (retuned in the new
+ * process) and the string method's state; the SCF density has to be
+ * recomputed before bscf_forces.
  * With the FP64 path and the previous-step or extrapolated guess the
  * resumed step repeats the uninterrupted one to the rounding of the atomic
  * accumulations (bitwise in the deterministic J/K mode's Fock builds). */

@@ -4273,7 +4273,7 @@ bscf_status bscf_guess_fit(bscf_ctx* c, int rows, const float* X, const float* T
 
 namespace {
 constexpr int kCkptMagic = 0x4B435342;   // "BSCK"
-constexpr int kCkptVersion = 1;
+constexpr int kCkptVersion = 2;
 
 template <typename T>
 void put(std::ostream& f, const T& v) {
@@ -4362,7 +4362,10 @@ bscf_status bscf_checkpoint_save(bscf_ctx* c, const char* path) {
     }
     const int net = c->guess.din() > 0 ? 1 : 0;
     put(f, net);
-    if (net) c->guess.save(f);
+    if (net) {
+      c->guess.save(f);
+      c->guess.save_run(f, c->mtot);
+    }
     f.flush();
     need(bool(f), BSCF_E_INVALID, std::string("checkpoint: write failed: ") + path);
   });
@@ -4415,7 +4418,13 @@ bscf_status bscf_checkpoint_load(bscf_ctx* c, const char* path) {
     }
     const int net = get<int>(f);
     mlp::Guess::Saved model;
-    if (net) model = mlp::Guess::read(f);
+    mlp::Guess::RunState run;
+    if (net) {
+      model = mlp::Guess::read(f);
+      run = mlp::Guess::read_run(f, model.din, model.dout);
+      need(!run.have_prev || (long long)run.rprev.size() == c->mtot, BSCF_E_INVALID,
+           "checkpoint: a different batch");
+    }
     need(bool(f), BSCF_E_INVALID, "checkpoint: truncated file");
     // geometry (and with it S, H, the Schwarz bounds and the work lists), the
     // carried densities and orbitals, then the ring polymer at its saved
@@ -4437,7 +4446,10 @@ bscf_status bscf_checkpoint_load(bscf_ctx* c, const char* path) {
       if (have_force) c->d_grad.upload(grad, s);
       m.have_force = have_force != 0;
     }
-    if (net) c->guess.apply(model);
+    if (net) {
+      c->guess.apply(model);
+      c->guess.apply_run(run, c->mtot);
+    }
     sync(c);
   });
 }

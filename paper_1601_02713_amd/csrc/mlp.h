@@ -100,6 +100,20 @@ class Guess {
   void save(std::ostream& f);
   static Saved read(std::istream& f);
   void apply(const Saved& r);
+  // The run state a resumed run needs to predict and train as the
+  // uninterrupted one: the last residual, the previous geometry and the
+  // replay buffer (host copies; apply_run after apply, on a batch of mtot).
+  struct RunState {
+    int have_prev = 0;
+    std::vector<double> rprev, xyz_prev;
+    int next = 0, count = 0;
+    std::vector<int> rows;
+    std::vector<double> cnt;
+    std::vector<std::vector<float>> X, T, M;
+  };
+  void save_run(std::ostream& f, long long mtot);
+  static RunState read_run(std::istream& f, int din, int dout);
+  void apply_run(const RunState& r, long long mtot);
 
   // Direct use of the network (tests): fixed dimensions, parameter access,
   // evaluation and full-batch training on caller rows (host arrays).

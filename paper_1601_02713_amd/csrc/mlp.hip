@@ -790,6 +790,102 @@ void Guess::save(std::ostream& f) {
   if (!f) throw std::runtime_error("learned guess: write failed");
 }
 
+// run state: have_prev, mtot, rprev [mtot if have_prev], n_xyz, xyz_prev,
+// next, count, then per replay step rows, cnt, X [rows din], T, M [rows dout]
+void Guess::save_run(std::ostream& f, long long mtot) {
+  auto put = [&](const void* p, size_t n) { f.write(reinterpret_cast<const char*>(p), n); };
+  const int hp = have_prev_ && rprev_.n >= (size_t)mtot ? 1 : 0;
+  put(&hp, sizeof(int));
+  put(&mtot, sizeof(long long));
+  if (hp) {
+    std::vector<double> r(mtot);
+    chk(hipMemcpy(r.data(), rprev_.p, mtot * sizeof(double), hipMemcpyDeviceToHost), "save");
+    put(r.data(), r.size() * sizeof(double));
+  }
+  const long long nx = (long long)xyz_prev_.size();
+  put(&nx, sizeof(long long));
+  put(xyz_prev_.data(), nx * sizeof(double));
+  put(&replay_next_, sizeof(int));
+  put(&replay_count_, sizeof(int));
+  for (int k = 0; k < replay_count_; ++k) {
+    const Step& st = replay_[k];
+    put(&st.rows, sizeof(int));
+    put(&st.cnt, sizeof(double));
+    std::vector<float> X((size_t)st.rows * din_), T((size_t)st.rows * dout_), M(T.size());
+    chk(hipMemcpy(X.data(), st.X.p, X.size() * sizeof(float), hipMemcpyDeviceToHost), "save");
+    chk(hipMemcpy(T.data(), st.T.p, T.size() * sizeof(float), hipMemcpyDeviceToHost), "save");
+    chk(hipMemcpy(M.data(), st.M.p, M.size() * sizeof(float), hipMemcpyDeviceToHost), "save");
+    put(X.data(), X.size() * sizeof(float));
+    put(T.data(), T.size() * sizeof(float));
+    put(M.data(), M.size() * sizeof(float));
+  }
+}
+
+Guess::RunState Guess::read_run(std::istream& f, int din, int dout) {
+  auto get = [&](void* p, size_t n) {
+    f.read(reinterpret_cast<char*>(p), n);
+    if (!f) throw std::runtime_error("learned guess: truncated run state");
+  };
+  RunState r;
+  long long mtot = 0, nx = 0;
+  get(&r.have_prev, sizeof(int));
+  get(&mtot, sizeof(long long));
+  if (mtot < 0 || mtot > (1LL << 34)) throw std::runtime_error("learned guess: bad run state");
+  if (r.have_prev) {
+    r.rprev.resize(mtot);
+    get(r.rprev.data(), mtot * sizeof(double));
+  }
+  get(&nx, sizeof(long long));
+  if (nx < 0 || nx > (1LL << 24)) throw std::runtime_error("learned guess: bad run state");
+  r.xyz_prev.resize(nx);
+  get(r.xyz_prev.data(), nx * sizeof(double));
+  get(&r.next, sizeof(int));
+  get(&r.count, sizeof(int));
+  if (r.count < 0 || r.count > kReplaySteps || r.next < 0 || r.next >= kReplaySteps)
+    throw std::runtime_error("learned guess: bad run state");
+  for (int k = 0; k < r.count; ++k) {
+    int rows = 0;
+    double cnt = 0.0;
+    get(&rows, sizeof(int));
+    get(&cnt, sizeof(double));
+    if (rows < 0 || rows > (1 << 24)) throw std::runtime_error("learned guess: bad run state");
+    r.rows.push_back(rows);
+    r.cnt.push_back(cnt);
+    r.X.emplace_back((size_t)rows * din);
+    r.T.emplace_back((size_t)rows * dout);
+    r.M.emplace_back((size_t)rows * dout);
+    get(r.X.back().data(), r.X.back().size() * sizeof(float));
+    get(r.T.back().data(), r.T.back().size() * sizeof(float));
+    get(r.M.back().data(), r.M.back().size() * sizeof(float));
+  }
+  return r;
+}
+
+void Guess::apply_run(const RunState& r, long long mtot) {
+  if (r.have_prev && (long long)r.rprev.size() != mtot)
+    throw std::runtime_error("learned guess: run state of another batch");
+  have_prev_ = r.have_prev != 0;
+  if (have_prev_) {
+    rprev_.resize(mtot);
+    r_.resize(mtot);
+    chk(hipMemcpy(rprev_.p, r.rprev.data(), mtot * sizeof(double), hipMemcpyHostToDevice), "load");
+  }
+  xyz_prev_ = r.xyz_prev;
+  for (int k = 0; k < r.count; ++k) {
+    Step& st = replay_[k];
+    st.rows = r.rows[k];
+    st.cnt = r.cnt[k];
+    st.X.resize(r.X[k].size());
+    st.T.resize(r.T[k].size());
+    st.M.resize(r.M[k].size());
+    chk(hipMemcpy(st.X.p, r.X[k].data(), r.X[k].size() * sizeof(float), hipMemcpyHostToDevice), "load");
+    chk(hipMemcpy(st.T.p, r.T[k].data(), r.T[k].size() * sizeof(float), hipMemcpyHostToDevice), "load");
+    chk(hipMemcpy(st.M.p, r.M[k].data(), r.M[k].size() * sizeof(float), hipMemcpyHostToDevice), "load");
+  }
+  replay_next_ = r.next;
+  replay_count_ = r.count;
+}
+
 void Guess::load(const std::string& path) {
   std::ifstream f(path, std::ios::binary);
   if (!f) throw std::runtime_error("learned guess: cannot read " + path);

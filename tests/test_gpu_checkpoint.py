@@ -152,3 +152,45 @@ def test_rejected_files_leave_the_context_unchanged(beadscf, b631gs, tmp_path):
             o.checkpoint_load(path)
     finally:
         o.close()
+
+
+def test_resume_with_the_learned_guess(beadscf, b631gs, tmp_path):
+    """The headline's guess: the network, its Adam moments, its last
+    residual and its replay buffer come back, so the resumed step predicts
+    from the same model and needs the same iterations, and training after it
+    continues from the same buffer."""
+    P, T = 4, 300.0
+    z, x = inputs.water_cluster(2, 24)
+    xb = inputs.beads(z, x, P, 24)
+    m = np.array([MASS[int(v)] for v in z])
+    so = beadscf.default_opts(e_tol=1e-10, comm_tol=1e-8, guess=beadscf.GUESS_LEARNED)
+    path = str(tmp_path / "learned.ckpt")
+    e = _setup(beadscf, b631gs, z, xb)
+    try:
+        e.pimd_init(m, None, beadscf.pimd_default_opts(dt=0.5 * FS, temperature=T, seed=8))
+        for _ in range(4):
+            e.pimd_step(so)
+            e.guess_train(30)
+        theta = e.guess_params()
+        e.checkpoint_save(path)
+        E5, it5, st5 = e.pimd_step(so)
+        l5 = e.guess_train(30)
+        theta5 = e.guess_params()
+    finally:
+        e.close()
+    assert ((st5 & 1) == 0).all() and not (st5 & 4).any()   # converged, the network was used
+
+    r = _setup(beadscf, b631gs, z, xb)
+    try:
+        r.checkpoint_load(path)
+        assert np.array_equal(r.guess_params(), theta)
+        E, it, st = r.pimd_step(so)
+        l = r.guess_train(30)
+        th = r.guess_params()
+    finally:
+        r.close()
+    assert not (st & 4).any()
+    assert np.array_equal(it, it5)
+    assert np.abs(E - E5).max() < 1e-10
+    assert abs(l - l5) <= 1e-4 * abs(l5)
+    assert np.abs(th - theta5).max() <= 1e-4 * np.abs(theta5).max()
